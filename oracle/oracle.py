@@ -1,0 +1,297 @@
+"""ctypes binding of the FP64 oracle (liborace.so built from rbo.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the package's smoke() check
+and bench.py's cpu_baseline leg; never by the product path.
+
+All arrays handed to the oracle are float64 copies of the float32 inputs
+(exact widening) or int32/uint8/uint32 index arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "rbo.c")
+
+COLD, PREV, LEARNED = 0, 1, 2
+PGS, JACOBI = 0, 1
+F_NONFINITE, F_CAPACITY, F_NOT_CONVERGED, F_FELLBACK = 1, 2, 4, 8
+
+# physics constants of the step (readings; the paper gives none)
+DEFAULTS = dict(margin=0.02, baumgarte=0.2, slop=0.005, rest_thresh=0.5,
+                ground_friction=0.5, ground_restitution=0.0,
+                gravity=(0.0, 0.0, -9.81), link_len=(0.10, 0.30, 0.10, 0.30, 0.10, 0.20, 0.10),
+                arm_radius=0.05)
+
+
+def build(force: bool = False) -> str:
+    """Compile rbo.c with gcc into liboracle.so next to it."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-Wall",
+               "-o", LIB + ".tmp", SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_P = C.POINTER
+_d = C.c_double
+
+
+class Model(C.Structure):
+    _fields_ = [("n_scenes", C.c_int), ("body_offset", _P(C.c_int32)), ("shape", _P(C.c_uint8)),
+                ("motion", _P(C.c_uint8)), ("param", _P(_d)), ("mass", _P(_d)),
+                ("friction", _P(_d)), ("restitution", _P(_d)), ("arm", C.c_int),
+                ("arm_base", _P(_d)), ("link_len", _d * 7), ("arm_radius", _d),
+                ("gravity", _d * 3), ("margin", _d), ("baumgarte", _d), ("slop", _d),
+                ("rest_thresh", _d), ("ground_friction", _d), ("ground_restitution", _d)]
+
+
+class Cache(C.Structure):
+    _fields_ = [("cap", C.c_int), ("count", _P(C.c_int32)), ("key", _P(C.c_uint32)),
+                ("lam", _P(_d))]
+
+
+class Mlp(C.Structure):
+    _fields_ = [("w1", _P(_d)), ("b1", _P(_d)), ("w2", _P(_d)), ("b2", _P(_d)),
+                ("w3", _P(_d)), ("b3", _P(_d)), ("mean", _P(_d)), ("std", _P(_d)),
+                ("bf16", C.c_int)]
+
+
+class Out(C.Structure):
+    _fields_ = [("max_pairs", C.c_int), ("max_contacts", C.c_int),
+                ("n_pairs", _P(C.c_int32)), ("pair_key", _P(C.c_uint32)),
+                ("n_contacts", _P(C.c_int32)), ("c_key", _P(C.c_uint32)),
+                ("c_normal", _P(_d)), ("c_point", _P(_d)), ("c_phi", _P(_d)),
+                ("c_lambda", _P(_d)), ("c_colour", _P(C.c_int32)), ("c_feat", _P(_d)),
+                ("n_colours", _P(C.c_int32)), ("sweeps", _P(C.c_int32)),
+                ("residual", _P(_d)), ("arm_force", _P(_d)), ("flags", _P(C.c_int32)),
+                ("ambiguous", _P(C.c_int32))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = build()
+        L = C.CDLL(path)
+        L.ora_step.argtypes = [_P(Model), _P(_d), _P(_d), _P(_d), _P(Cache), _P(_d), _d, C.c_int,
+                               _d, C.c_int, C.c_int, _P(Mlp), _P(Out), C.c_int, C.c_int]
+        L.ora_step.restype = C.c_int
+        L.ora_arm_pose.argtypes = [_P(Model), _P(_d), _P(_d)]
+        L.ora_collide.argtypes = [C.c_int, _P(_d), _P(_d), C.c_int, _P(_d), _P(_d), C.c_int, _d,
+                                  _P(C.c_int), _P(_d), _P(_d), _P(_d), _P(C.c_int)]
+        L.ora_collide.restype = C.c_int
+        L.ora_pairs.argtypes = [_P(Model), _P(_d), C.c_int, _P(C.c_uint32), C.c_int]
+        L.ora_pairs.restype = C.c_int
+        L.ora_mlp_forward.argtypes = [_P(Mlp), _P(_d), C.c_int, _P(_d)]
+        L.ora_mlp_loss_grad.argtypes = [_P(Mlp), _P(_d), _P(_d), C.c_int] + [_P(_d)] * 6
+        L.ora_mlp_loss_grad.restype = _d
+        L.ora_bf16.argtypes = [_d]
+        L.ora_bf16.restype = _d
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(_P(ct)) if a is not None else None
+
+
+class OracleSim:
+    """Batched FP64 simulation state driven by the oracle.
+
+    ``batch`` is a packed scene batch (float32 arrays); everything is widened
+    to float64 once.  ``cache_cap`` bounds the stored contacts per scene."""
+
+    def __init__(self, batch, cache_cap: int = 4096, **consts):
+        c = dict(DEFAULTS)
+        c.update(consts)
+        self.consts = c
+        b = batch
+        self.S = b.n_scenes
+        self.off = np.ascontiguousarray(b.body_offset, np.int32)
+        self.shape = np.ascontiguousarray(b.shape, np.uint8)
+        self.motion = np.ascontiguousarray(b.motion, np.uint8)
+        self.param = np.ascontiguousarray(b.param, np.float64).reshape(-1)
+        self.mass = np.ascontiguousarray(b.mass, np.float64)
+        self.friction = np.ascontiguousarray(b.friction, np.float64)
+        self.restitution = np.ascontiguousarray(b.restitution, np.float64)
+        self.arm = bool(b.arm)
+        self.arm_base = np.ascontiguousarray(b.arm_base, np.float64).reshape(-1)
+        self.pose = np.ascontiguousarray(b.pose, np.float64).reshape(-1).copy()
+        self.vel = np.ascontiguousarray(b.vel, np.float64).reshape(-1).copy()
+        self.theta = np.ascontiguousarray(b.arm_theta, np.float64).reshape(-1).copy()
+        self.m = Model()
+        self.m.n_scenes = self.S
+        self.m.body_offset = _ptr(self.off, C.c_int32)
+        self.m.shape = _ptr(self.shape, C.c_uint8)
+        self.m.motion = _ptr(self.motion, C.c_uint8)
+        self.m.param = _ptr(self.param, _d)
+        self.m.mass = _ptr(self.mass, _d)
+        self.m.friction = _ptr(self.friction, _d)
+        self.m.restitution = _ptr(self.restitution, _d)
+        self.m.arm = int(self.arm)
+        self.m.arm_base = _ptr(self.arm_base, _d)
+        for i in range(7):
+            self.m.link_len[i] = c["link_len"][i]
+        self.m.arm_radius = c["arm_radius"]
+        for i in range(3):
+            self.m.gravity[i] = c["gravity"][i]
+        for k in ("margin", "baumgarte", "slop", "rest_thresh", "ground_friction",
+                  "ground_restitution"):
+            setattr(self.m, k, c[k])
+        self.cache_cap = cache_cap
+        self.c_count = np.zeros(self.S, np.int32)
+        self.c_key = np.zeros(self.S * cache_cap, np.uint32)
+        self.c_lam = np.zeros(self.S * cache_cap * 4, np.float64)
+        self.cache = Cache(cache_cap, _ptr(self.c_count, C.c_int32), _ptr(self.c_key, C.c_uint32),
+                           _ptr(self.c_lam, _d))
+        if self.arm:
+            lib().ora_arm_pose(C.byref(self.m), _ptr(self.pose, _d), _ptr(self.theta, _d))
+        self._mlp_keep = None
+
+    # ---------------------------------------------------------------- state
+    def set_state(self, pose, vel, theta=None, cache=None):
+        """Overwrite the state with (float32) arrays, widened exactly."""
+        self.pose[:] = np.asarray(pose, np.float64).reshape(-1)
+        self.vel[:] = np.asarray(vel, np.float64).reshape(-1)
+        if theta is not None:
+            self.theta[:] = np.asarray(theta, np.float64).reshape(-1)
+        if cache is not None:
+            cnt, key, lam = cache
+            self.c_count[:] = cnt
+            self.c_key[:] = 0
+            self.c_lam[:] = 0
+            kk = self.c_key.reshape(self.S, -1)
+            ll = self.c_lam.reshape(self.S, -1, 4)
+            kk[:, :key.shape[1]] = key
+            ll[:, :lam.shape[1]] = lam
+
+    def set_theta(self, theta):
+        """Set the arm joint angles (float64) and recompute the arm link poses."""
+        self.theta[:] = np.asarray(theta, np.float64).reshape(-1)
+        lib().ora_arm_pose(C.byref(self.m), _ptr(self.pose, _d), _ptr(self.theta, _d))
+
+    def state32(self):
+        return (self.pose.reshape(-1, 7).astype(np.float32), self.vel.reshape(-1, 6).astype(np.float32),
+                self.theta.reshape(-1, 7).astype(np.float32))
+
+    def cache_arrays(self):
+        return (self.c_count.copy(), self.c_key.reshape(self.S, -1).copy(),
+                self.c_lam.reshape(self.S, -1, 4).copy())
+
+    def set_mlp(self, params: dict, bf16: bool = False):
+        keep = {k: np.ascontiguousarray(np.asarray(params[k], np.float64).reshape(-1))
+                for k in ("w1", "b1", "w2", "b2", "w3", "b3", "mean", "std")}
+        self._mlp_keep = keep
+        self.mlp = Mlp(*[_ptr(keep[k], _d) for k in ("w1", "b1", "w2", "b2", "w3", "b3", "mean", "std")],
+                       int(bf16))
+
+    # ---------------------------------------------------------------- step
+    def step(self, actions=None, dt=1.0 / 120.0, iters=10, tol=0.0, warm=COLD, solver=PGS,
+             scenes=None, outputs=True, max_pairs=8192, max_contacts=8192, use_cache=True):
+        s0, s1 = (0, self.S) if scenes is None else scenes
+        out = None
+        res = None
+        if outputs:
+            S = self.S
+            res = dict(
+                n_pairs=np.zeros(S, np.int32), pair_key=np.zeros(S * max_pairs, np.uint32),
+                n_contacts=np.zeros(S, np.int32), c_key=np.zeros(S * max_contacts, np.uint32),
+                c_normal=np.zeros(S * max_contacts * 3), c_point=np.zeros(S * max_contacts * 3),
+                c_phi=np.zeros(S * max_contacts), c_lambda=np.zeros(S * max_contacts * 3),
+                c_colour=np.zeros(S * max_contacts, np.int32),
+                c_feat=np.zeros(S * max_contacts * 16),
+                n_colours=np.zeros(S, np.int32), sweeps=np.zeros(S, np.int32),
+                residual=np.zeros(S), arm_force=np.zeros(S), flags=np.zeros(S, np.int32),
+                ambiguous=np.zeros(S, np.int32))
+            out = Out()
+            out.max_pairs = max_pairs
+            out.max_contacts = max_contacts
+            for k, v in res.items():
+                ct = {np.dtype(np.int32): C.c_int32, np.dtype(np.uint32): C.c_uint32,
+                      np.dtype(np.float64): _d}[v.dtype]
+                setattr(out, k, _ptr(v, ct))
+        act = None
+        if actions is not None:
+            act = np.ascontiguousarray(np.asarray(actions, np.float64).reshape(-1))
+        mlp = C.byref(self.mlp) if warm == LEARNED else None
+        rc = lib().ora_step(C.byref(self.m), _ptr(self.pose, _d), _ptr(self.vel, _d),
+                            _ptr(self.theta, _d), C.byref(self.cache) if use_cache else None,
+                            _ptr(act, _d) if act is not None else None, dt, int(iters), float(tol),
+                            int(warm), int(solver), mlp, C.byref(out) if out is not None else None,
+                            s0, s1)
+        if rc != 0:
+            raise ValueError("oracle rejected the step arguments")
+        if res is None:
+            return None
+        mp, mc = max_pairs, max_contacts
+        res["pair_key"] = res["pair_key"].reshape(self.S, mp)
+        res["c_key"] = res["c_key"].reshape(self.S, mc)
+        res["c_normal"] = res["c_normal"].reshape(self.S, mc, 3)
+        res["c_point"] = res["c_point"].reshape(self.S, mc, 3)
+        res["c_phi"] = res["c_phi"].reshape(self.S, mc)
+        res["c_lambda"] = res["c_lambda"].reshape(self.S, mc, 3)
+        res["c_colour"] = res["c_colour"].reshape(self.S, mc)
+        res["c_feat"] = res["c_feat"].reshape(self.S, mc, 16)
+        return res
+
+
+def collide(shape_a, param_a, pose_a, shape_b=None, param_b=None, pose_b=None, margin=0.02):
+    """Contacts of one pair (b = ground when shape_b is None).  Returns a list
+    of (feature, normal[3], point[3], phi) and the ambiguity count."""
+    L = lib()
+    pa = np.ascontiguousarray(param_a, np.float64)
+    xa = np.ascontiguousarray(pose_a, np.float64)
+    ground = shape_b is None
+    pb = np.ascontiguousarray(param_b if not ground else np.zeros(3), np.float64)
+    xb = np.ascontiguousarray(pose_b if not ground else [0, 0, 0, 1, 0, 0, 0], np.float64)
+    f = np.zeros(4, np.int32)
+    n = np.zeros(12)
+    p = np.zeros(12)
+    ph = np.zeros(4)
+    amb = C.c_int(0)
+    k = L.ora_collide(int(shape_a), _ptr(pa, _d), _ptr(xa, _d), int(shape_b or 0), _ptr(pb, _d),
+                      _ptr(xb, _d), int(ground), float(margin), f.ctypes.data_as(_P(C.c_int)),
+                      _ptr(n, _d), _ptr(p, _d), _ptr(ph, _d), C.byref(amb))
+    return [(int(f[i]), n[3 * i:3 * i + 3].copy(), p[3 * i:3 * i + 3].copy(), float(ph[i]))
+            for i in range(k)], amb.value
+
+
+def bf16(x: float) -> float:
+    return lib().ora_bf16(float(x))
+
+
+def mlp_struct(params: dict, bf16: bool = False):
+    keep = {k: np.ascontiguousarray(np.asarray(params[k], np.float64).reshape(-1))
+            for k in ("w1", "b1", "w2", "b2", "w3", "b3", "mean", "std")}
+    s = Mlp(*[_ptr(keep[k], _d) for k in ("w1", "b1", "w2", "b2", "w3", "b3", "mean", "std")],
+            int(bf16))
+    return s, keep
+
+
+def mlp_forward(params: dict, x, bf16: bool = False):
+    s, keep = mlp_struct(params, bf16)
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.zeros((x.shape[0], 3))
+    lib().ora_mlp_forward(C.byref(s), _ptr(x, _d), x.shape[0], _ptr(y, _d))
+    return y
+
+
+def mlp_loss_grad(params: dict, x, t, bf16: bool = False):
+    s, keep = mlp_struct(params, bf16)
+    x = np.ascontiguousarray(x, np.float64)
+    t = np.ascontiguousarray(t, np.float64)
+    g = dict(w1=np.zeros(64 * 16), b1=np.zeros(64), w2=np.zeros(64 * 64), b2=np.zeros(64),
+             w3=np.zeros(3 * 64), b3=np.zeros(3))
+    loss = lib().ora_mlp_loss_grad(C.byref(s), _ptr(x, _d), _ptr(t, _d), x.shape[0],
+                                   *[_ptr(g[k], _d) for k in ("w1", "b1", "w2", "b2", "w3", "b3")])
+    g = {k: v.reshape(np.shape(params[k])) for k, v in g.items()}
+    return loss, g

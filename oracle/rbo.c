@@ -1,0 +1,1427 @@
+/*
+ * rbo.c -- FP64 CPU oracle of the batched rigid-body step.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by tests/, smoke() and bench.py's
+ * cpu_baseline leg.  Nothing of the product path calls it.  It shares no
+ * code with the HIP path.
+ *
+ * Paper anchors (Habitat 2.0): the physics engine maps (s_t, a_t) -> s_{t+1}
+ * (Sec. 2); rigid bodies carry mass, friction and restitution and simplified
+ * collision proxies such as boxes (Sec. 3; Sec. 4.3); base-constrained parts
+ * are static (Sec. 4.1); the robot is the only non-gravity force source
+ * (Sec. 4.1); physics runs at 1/120 s (Sec. 4.4); the arm has 7 DoF (Sec. 5);
+ * the per-step collision force in newtons is what tasks consume (Sec. 5 and
+ * the Pick reward in the appendix).  The paper gives no engine algorithm; each
+ * function below states the textbook method or the reading it follows.
+ *
+ * Everything is written as plain loops in the step's order, in double
+ * precision, per scene.  Decisions that a float32 implementation could take
+ * differently (a comparison whose two sides are within the tie band) are
+ * counted in `ambiguous` so that parity tests can skip those scenes.
+ */
+#include "rbo.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PAIR_GROUND 0xFFFFu
+#define KEY_GROUND 0xFFFu
+#define BAND 1e-5       /* tie band for decisions on lengths (m) */
+#define BAND_DIM 1e-5   /* tie band for dimensionless decisions */
+#define SIN_PAR 1e-3    /* "parallel" threshold: sine of 1 mrad (approx.) */
+#define MAXCOL 256
+#define CLIP_ON 1e-4  /* clip vertices within this distance of a plane lie on it (m) */
+
+/* ------------------------------------------------------------------ vectors */
+typedef struct { double x, y, z; } V;
+static V mk(double x, double y, double z) { V r; r.x = x; r.y = y; r.z = z; return r; }
+static V add(V a, V b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static V sub(V a, V b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static V scl(V a, double s) { return mk(a.x * s, a.y * s, a.z * s); }
+static double dot(V a, V b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static V cross(V a, V b) { return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
+static double len2(V a) { return dot(a, a); }
+static double clampd(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
+static double comp(V a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+static void setc(V *a, int i, double s) { if (i == 0) a->x = s; else if (i == 1) a->y = s; else a->z = s; }
+static V unit(int i) { return mk(i == 0, i == 1, i == 2); }
+
+typedef struct { double m[3][3]; } M3;
+/* Rotation matrix of the quaternion (w, x, y, z), Hamilton convention. */
+static M3 quat_R(const double *q) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    M3 R;
+    R.m[0][0] = 1 - 2 * (y * y + z * z); R.m[0][1] = 2 * (x * y - w * z);     R.m[0][2] = 2 * (x * z + w * y);
+    R.m[1][0] = 2 * (x * y + w * z);     R.m[1][1] = 1 - 2 * (x * x + z * z); R.m[1][2] = 2 * (y * z - w * x);
+    R.m[2][0] = 2 * (x * z - w * y);     R.m[2][1] = 2 * (y * z + w * x);     R.m[2][2] = 1 - 2 * (x * x + y * y);
+    return R;
+}
+static V Rv(const M3 *R, V a) {
+    return mk(R->m[0][0] * a.x + R->m[0][1] * a.y + R->m[0][2] * a.z,
+              R->m[1][0] * a.x + R->m[1][1] * a.y + R->m[1][2] * a.z,
+              R->m[2][0] * a.x + R->m[2][1] * a.y + R->m[2][2] * a.z);
+}
+static V RTv(const M3 *R, V a) {
+    return mk(R->m[0][0] * a.x + R->m[1][0] * a.y + R->m[2][0] * a.z,
+              R->m[0][1] * a.x + R->m[1][1] * a.y + R->m[2][1] * a.z,
+              R->m[0][2] * a.x + R->m[1][2] * a.y + R->m[2][2] * a.z);
+}
+static V col(const M3 *R, int j) { return mk(R->m[0][j], R->m[1][j], R->m[2][j]); }
+static void quat_mul(const double *a, const double *b, double *o) {
+    double w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    double x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    double y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    double z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+    o[0] = w; o[1] = x; o[2] = y; o[3] = z;
+}
+
+/* ------------------------------------------------------------------ bodies */
+typedef struct {
+    int shape, motion;
+    V x; double q[4]; M3 R;
+    double prm[3];
+    V v, w;
+    double im;          /* inverse mass (0 unless dynamic) */
+    M3 Iw;              /* world inverse inertia (0 unless dynamic) */
+    double mu, e;
+    V lo, hi;           /* fattened AABB */
+    int ncon;           /* contacts touching this body (Jacobi) */
+} Body;
+
+/* Principal moments of a solid body of uniform density. */
+static void body_inertia(int shape, const double *p, double m, double I[3]) {
+    if (shape == ORA_SPHERE) {
+        I[0] = I[1] = I[2] = 0.4 * m * p[0] * p[0];
+    } else if (shape == ORA_BOX) {
+        double x2 = p[0] * p[0], y2 = p[1] * p[1], z2 = p[2] * p[2];
+        I[0] = m / 3.0 * (y2 + z2);
+        I[1] = m / 3.0 * (x2 + z2);
+        I[2] = m / 3.0 * (x2 + y2);
+    } else {
+        /* cylinder of length 2h plus two hemispherical caps; mass split by
+         * volume; caps by the parallel-axis theorem (cap centroid 3r/8 from
+         * its flat face). */
+        double r = p[0], h = p[1];
+        double vc = 2.0 * M_PI * r * r * h, vs = 4.0 / 3.0 * M_PI * r * r * r;
+        double mc = m * vc / (vc + vs), ms = m - mc;
+        I[2] = mc * r * r / 2.0 + 0.4 * ms * r * r;
+        I[0] = I[1] = mc * (r * r / 4.0 + h * h / 3.0) + ms * (0.4 * r * r + h * h + 0.75 * h * r);
+    }
+}
+
+static void body_aabb(Body *b, double margin) {
+    if (b->shape == ORA_SPHERE) {
+        double e = b->prm[0] + margin;
+        b->lo = sub(b->x, mk(e, e, e));
+        b->hi = add(b->x, mk(e, e, e));
+    } else if (b->shape == ORA_BOX) {
+        V e;
+        e.x = fabs(b->R.m[0][0]) * b->prm[0] + fabs(b->R.m[0][1]) * b->prm[1] + fabs(b->R.m[0][2]) * b->prm[2] + margin;
+        e.y = fabs(b->R.m[1][0]) * b->prm[0] + fabs(b->R.m[1][1]) * b->prm[1] + fabs(b->R.m[1][2]) * b->prm[2] + margin;
+        e.z = fabs(b->R.m[2][0]) * b->prm[0] + fabs(b->R.m[2][1]) * b->prm[1] + fabs(b->R.m[2][2]) * b->prm[2] + margin;
+        b->lo = sub(b->x, e);
+        b->hi = add(b->x, e);
+    } else {
+        V ax = scl(col(&b->R, 2), b->prm[1]);
+        V e0 = sub(b->x, ax), e1 = add(b->x, ax);
+        double r = b->prm[0] + margin;
+        b->lo = mk(fmin(e0.x, e1.x) - r, fmin(e0.y, e1.y) - r, fmin(e0.z, e1.z) - r);
+        b->hi = mk(fmax(e0.x, e1.x) + r, fmax(e0.y, e1.y) + r, fmax(e0.z, e1.z) + r);
+    }
+}
+
+/* -------------------------------------------------------------- narrowphase
+ * Conventions: routines return contacts whose normal points from the SECOND
+ * argument to the FIRST; phi is the signed separation along n (negative =
+ * penetration); p is the midpoint of the two surface witness points; f is a
+ * feature id.  A contact is kept iff phi <= margin. */
+typedef struct { int shape; V x; M3 R; double prm[3]; } Geom;
+typedef struct { int f; V n, p; double phi; } PC;
+
+static int keep(double phi, double margin, int *amb) {
+    if (fabs(phi - margin) < BAND) (*amb)++;
+    return phi <= margin;
+}
+
+/* Two spheres: distance of the centres minus the radii. */
+static PC sphere_sphere(V ca, double ra, V cb, double rb, int f) {
+    PC c;
+    V d = sub(ca, cb);
+    double L = sqrt(len2(d));
+    c.n = L < 1e-9 ? mk(0, 0, 1) : scl(d, 1.0 / L);
+    c.phi = L - ra - rb;
+    c.p = scl(add(sub(ca, scl(c.n, ra)), add(cb, scl(c.n, rb))), 0.5);
+    c.f = f;
+    return c;
+}
+
+/* Sphere (first) against a box (second): closest point by clamping in the
+ * box frame; a centre inside the box leaves through the face of least
+ * penetration (ties: lower axis, then the + face). */
+static int sphere_box(const Geom *S, const Geom *B, double margin, PC *out, int *amb) {
+    double r = S->prm[0];
+    const double *h = B->prm;
+    V l = RTv(&B->R, sub(S->x, B->x));
+    int inside = fabs(l.x) <= h[0] && fabs(l.y) <= h[1] && fabs(l.z) <= h[2];
+    V nl, q = l;
+    double phi;
+    if (!inside) {
+        q = mk(clampd(l.x, -h[0], h[0]), clampd(l.y, -h[1], h[1]), clampd(l.z, -h[2], h[2]));
+        V d = sub(l, q);
+        double L = sqrt(len2(d));
+        nl = scl(d, 1.0 / L);
+        phi = L - r;
+    } else {
+        double pen[3];
+        int a = 0;
+        for (int i = 0; i < 3; i++) pen[i] = h[i] - fabs(comp(l, i));
+        for (int i = 1; i < 3; i++) if (pen[i] < pen[a]) a = i;
+        for (int i = 0; i < 3; i++) if (i != a && fabs(pen[i] - pen[a]) < BAND) (*amb)++;
+        double la = comp(l, a);
+        if (fabs(la) < BAND) (*amb)++;
+        double s = la >= 0 ? 1.0 : -1.0;
+        nl = scl(unit(a), s);
+        setc(&q, a, s * h[a]);
+        phi = -pen[a] - r;
+    }
+    PC c;
+    c.n = Rv(&B->R, nl);
+    V wb = add(B->x, Rv(&B->R, q));
+    V wa = sub(S->x, scl(c.n, r));
+    c.p = scl(add(wa, wb), 0.5);
+    c.phi = phi;
+    c.f = 0;
+    if (!keep(phi, margin, amb)) return 0;
+    out[0] = c;
+    return 1;
+}
+
+static void capsule_seg(const Geom *C, V *p0, V *d) {
+    V ax = scl(col(&C->R, 2), C->prm[1]);
+    *p0 = sub(C->x, ax);
+    *d = scl(ax, 2.0);
+}
+
+/* Sphere (first) against a capsule (second): closest point of the core
+ * segment to the centre, then sphere-sphere. */
+static int sphere_capsule(const Geom *S, const Geom *C, double margin, PC *out, int *amb) {
+    V p0, d;
+    capsule_seg(C, &p0, &d);
+    double t = clampd(dot(sub(S->x, p0), d) / len2(d), 0.0, 1.0);
+    PC c = sphere_sphere(S->x, S->prm[0], add(p0, scl(d, t)), C->prm[0], 0);
+    if (!keep(c.phi, margin, amb)) return 0;
+    out[0] = c;
+    return 1;
+}
+
+/* Capsule against capsule.  Closest points of the two core segments
+ * (Ericson 2005, Sec. 5.1.9); nearly parallel segments whose projections
+ * overlap give two contacts at the ends of the overlap interval. */
+static int capsule_capsule(const Geom *A, const Geom *B, double margin, PC *out, int *amb) {
+    V pa, da, pb, db;
+    capsule_seg(A, &pa, &da);
+    capsule_seg(B, &pb, &db);
+    double ra = A->prm[0], rb = B->prm[0];
+    double aa = len2(da), ee = len2(db);
+    double cr2 = len2(cross(da, db));
+    double thr = 1e-6 * aa * ee;
+    if (fabs(cr2 - thr) < 1e-2 * thr) (*amb)++;
+    int n = 0;
+    if (cr2 <= thr) {
+        double s0 = dot(sub(pb, pa), da) / aa;
+        double s1 = dot(sub(add(pb, db), pa), da) / aa;
+        double lo = fmax(0.0, fmin(s0, s1)), hi = fmin(1.0, fmax(s0, s1));
+        if (fabs(hi - lo) * sqrt(aa) < BAND) (*amb)++;
+        if (lo <= hi) {
+            double ss[2] = {lo, hi};
+            for (int k = 0; k < 2; k++) {
+                if (k == 1 && !(hi > lo)) break;
+                V P = add(pa, scl(da, ss[k]));
+                double t = clampd(dot(sub(P, pb), db) / ee, 0.0, 1.0);
+                PC c = sphere_sphere(P, ra, add(pb, scl(db, t)), rb, k);
+                if (keep(c.phi, margin, amb)) out[n++] = c;
+            }
+            return n;
+        }
+    }
+    V r = sub(pa, pb);
+    double b = dot(da, db), c = dot(da, r), f = dot(db, r);
+    double den = aa * ee - b * b;
+    double s = den != 0.0 ? clampd((b * f - c * ee) / den, 0.0, 1.0) : 0.0;
+    double t = (b * s + f) / ee;
+    if (t < 0.0) { t = 0.0; s = clampd(-c / aa, 0.0, 1.0); }
+    else if (t > 1.0) { t = 1.0; s = clampd((b - c) / aa, 0.0, 1.0); }
+    PC cc = sphere_sphere(add(pa, scl(da, s)), ra, add(pb, scl(db, t)), rb, 0);
+    if (keep(cc.phi, margin, amb)) out[n++] = cc;
+    return n;
+}
+
+/* Squared distance of a box-local point to the box. */
+static double box_d2(V l, const double *h) {
+    double g = 0;
+    for (int a = 0; a < 3; a++) {
+        double x = fabs(comp(l, a)) - h[a];
+        if (x > 0) g += x * x;
+    }
+    return g;
+}
+
+/* Clip the segment l(t) = p0 + t d, t in [0, 1], to the slabs |l_b| <= h_b
+ * for the two axes b != a.  Returns 0 if the interval is empty. */
+static int clip_face(V p0, V d, const double *h, int a, double *t0, double *t1) {
+    double lo = 0.0, hi = 1.0;
+    for (int b = 0; b < 3; b++) {
+        if (b == a) continue;
+        double pb = comp(p0, b), db = comp(d, b);
+        if (db == 0.0) {
+            if (fabs(pb) > h[b]) return 0;
+            continue;
+        }
+        double ta = (-h[b] - pb) / db, tb = (h[b] - pb) / db;
+        if (ta > tb) { double x = ta; ta = tb; tb = x; }
+        if (ta > lo) lo = ta;
+        if (tb < hi) hi = tb;
+    }
+    *t0 = lo; *t1 = hi;
+    return lo <= hi;
+}
+
+/* One contact of a capsule core point l (box-local) against box face a on
+ * side s: normal s*e_a, depth from the face plane. */
+static PC cap_face_contact(V l, int a, double s, const double *h, double r, int f) {
+    PC c;
+    c.n = scl(unit(a), s);
+    c.phi = s * comp(l, a) - h[a] - r;
+    V q = l;
+    setc(&q, a, s * h[a]);
+    V wc = sub(l, scl(c.n, r));
+    c.p = scl(add(q, wc), 0.5);
+    c.f = f;
+    return c;
+}
+
+/* Capsule (first) against a box (second), in the box frame.
+ * 1. Closest point of the core segment to the box: the squared distance
+ *    g(t) is convex and piecewise quadratic in t; evaluate the ends, the slab
+ *    crossings and every piece's vertex; smallest g wins (ties: smaller t).
+ * 2. Separated core, closest point in a face region and the segment within
+ *    ~1 mrad of parallel to that face: two contacts at the ends of the
+ *    segment clipped to the face rectangle (f = 0, 1).
+ * 3. Separated core otherwise: one contact at the closest points (f = 2).
+ * 4. Core touching the box: leave through the face needing the least
+ *    translation (ties: lower axis, + side first); contacts at the ends of
+ *    the segment clipped to that face (f = 0, 1), else at the deeper
+ *    endpoint (f = 3). */
+static int capsule_box(const Geom *C, const Geom *B, double margin, PC *out, int *amb) {
+    double r = C->prm[0];
+    const double *h = B->prm;
+    V P0, D;
+    capsule_seg(C, &P0, &D);
+    V p0 = RTv(&B->R, sub(P0, B->x));
+    V d = RTv(&B->R, D);
+    double dl = sqrt(len2(d));
+    double ts[16];
+    int nt = 0;
+    ts[nt++] = 0.0; ts[nt++] = 1.0;
+    for (int a = 0; a < 3; a++) {
+        double da = comp(d, a);
+        if (da == 0.0) continue;
+        for (int sg = -1; sg <= 1; sg += 2) {
+            double t = (sg * h[a] - comp(p0, a)) / da;
+            if (t > 0.0 && t < 1.0) ts[nt++] = t;
+        }
+    }
+    for (int i = 1; i < nt; i++)            /* insertion sort */
+        for (int j = i; j > 0 && ts[j] < ts[j - 1]; j--) { double x = ts[j]; ts[j] = ts[j - 1]; ts[j - 1] = x; }
+    double cand[16];
+    double curv[16];
+    int nc = 0;
+    for (int i = 0; i < nt; i++) { cand[nc] = ts[i]; curv[nc] = -1; nc++; }
+    for (int i = 0; i + 1 < nt; i++) {
+        double tl = ts[i], th = ts[i + 1];
+        if (!(th > tl)) continue;
+        double tm = 0.5 * (tl + th), num = 0, den = 0;
+        for (int a = 0; a < 3; a++) {
+            double la = comp(p0, a) + tm * comp(d, a), ca;
+            if (la > h[a]) ca = h[a];
+            else if (la < -h[a]) ca = -h[a];
+            else continue;
+            num += comp(d, a) * (ca - comp(p0, a));
+            den += comp(d, a) * comp(d, a);
+        }
+        double tv = den > 0 ? clampd(num / den, tl, th) : tl;
+        cand[nc] = tv; curv[nc] = den; nc++;
+    }
+    int bi = 0;
+    double bg = box_d2(add(p0, scl(d, cand[0])), h);
+    for (int i = 1; i < nc; i++) {
+        double g = box_d2(add(p0, scl(d, cand[i])), h);
+        if (g < bg || (g == bg && cand[i] < cand[bi])) { bg = g; bi = i; }
+    }
+    double t = cand[bi];
+    V l = add(p0, scl(d, t));
+    int n = 0;
+    PC loc[4];
+    if (bg > 0.0) {
+        double dist = sqrt(bg);
+        if (dist < BAND) (*amb)++;
+        int ncl = 0, a = -1;
+        for (int k = 0; k < 3; k++) if (fabs(comp(l, k)) > h[k]) { ncl++; a = k; }
+        int done = 0;
+        if (ncl == 1) {
+            double sa = comp(l, a) > 0 ? 1.0 : -1.0;
+            double thr = SIN_PAR * dl;
+            if (fabs(fabs(comp(d, a)) - thr) < 1e-2 * thr) (*amb)++;
+            if (fabs(comp(d, a)) <= thr) {
+                for (int k = 0; k < 3; k++)
+                    if (k != a && fabs(h[k] - fabs(comp(l, k))) < BAND) (*amb)++;
+                double t0, t1;
+                int ok = clip_face(p0, d, h, a, &t0, &t1);
+                if (ok && fabs(t1 - t0) * dl < BAND) (*amb)++;
+                if (ok) {
+                    loc[n++] = cap_face_contact(add(p0, scl(d, t0)), a, sa, h, r, 0);
+                    if (t1 > t0) loc[n++] = cap_face_contact(add(p0, scl(d, t1)), a, sa, h, r, 1);
+                    done = 1;
+                }
+            }
+        }
+        if (!done) {
+            if (curv[bi] >= 0 && curv[bi] < 1e-4 * dl * dl) (*amb)++;
+            V q = mk(clampd(l.x, -h[0], h[0]), clampd(l.y, -h[1], h[1]), clampd(l.z, -h[2], h[2]));
+            PC c;
+            c.n = scl(sub(l, q), 1.0 / dist);
+            c.phi = dist - r;
+            c.p = scl(add(q, sub(l, scl(c.n, r))), 0.5);
+            c.f = 2;
+            loc[n++] = c;
+        }
+    } else {
+        double p1a[3], best = INFINITY, second = INFINITY;
+        int ba = 0;
+        double bs = 1.0;
+        V p1 = add(p0, d);
+        for (int a = 0; a < 3; a++) p1a[a] = comp(p1, a);
+        for (int a = 0; a < 3; a++) {
+            for (int sg = 1; sg >= -1; sg -= 2) {
+                double ex = h[a] - fmin(sg * comp(p0, a), sg * p1a[a]);
+                if (ex < best) { second = best; best = ex; ba = a; bs = sg; }
+                else if (ex < second) second = ex;
+            }
+        }
+        if (second - best < BAND) (*amb)++;
+        double t0, t1;
+        int ok = clip_face(p0, d, h, ba, &t0, &t1);
+        if (ok && fabs(t1 - t0) * dl < BAND) (*amb)++;
+        if (ok) {
+            loc[n++] = cap_face_contact(add(p0, scl(d, t0)), ba, bs, h, r, 0);
+            if (t1 > t0) loc[n++] = cap_face_contact(add(p0, scl(d, t1)), ba, bs, h, r, 1);
+        } else {
+            double e0 = bs * comp(p0, ba), e1 = bs * p1a[ba];
+            if (fabs(e0 - e1) < BAND) (*amb)++;
+            V pe = e0 <= e1 ? p0 : p1;
+            loc[n++] = cap_face_contact(pe, ba, bs, h, r, 3);
+        }
+    }
+    int m = 0;
+    for (int k = 0; k < n; k++) {
+        if (!keep(loc[k].phi, margin, amb)) continue;
+        PC c = loc[k];
+        c.n = Rv(&B->R, loc[k].n);
+        c.p = add(B->x, Rv(&B->R, loc[k].p));
+        out[m++] = c;
+    }
+    return m;
+}
+
+/* Box against box: separating-axis test over the 15 axes (Gottschalk et al.
+ * 1996), face axes preferred over edge axes and the first box's faces over
+ * the second's unless clearly better; face contact = incident face clipped
+ * against the reference face's side planes (Sutherland-Hodgman 1974) and
+ * reduced to at most 4 points; edge contact = closest points of two edges. */
+static int box_box(const Geom *A, const Geom *B, double margin, PC *out, int *amb) {
+    V a[3], b[3];
+    for (int i = 0; i < 3; i++) { a[i] = col(&A->R, i); b[i] = col(&B->R, i); }
+    const double *ha = A->prm, *hb = B->prm;
+    V D = sub(A->x, B->x);
+    double s[15], sg[15];
+    int valid[15];
+    V u[15];
+    for (int k = 0; k < 15; k++) {
+        double ra, rb;
+        valid[k] = 1;
+        if (k < 3) {
+            u[k] = a[k];
+            ra = ha[k];
+            rb = hb[0] * fabs(dot(b[0], u[k])) + hb[1] * fabs(dot(b[1], u[k])) + hb[2] * fabs(dot(b[2], u[k]));
+        } else if (k < 6) {
+            u[k] = b[k - 3];
+            rb = hb[k - 3];
+            ra = ha[0] * fabs(dot(a[0], u[k])) + ha[1] * fabs(dot(a[1], u[k])) + ha[2] * fabs(dot(a[2], u[k]));
+        } else {
+            int i = (k - 6) / 3, j = (k - 6) % 3;
+            V c = cross(a[i], b[j]);
+            double L2 = len2(c);
+            if (fabs(L2 - 1e-12) < 1e-13) (*amb)++;
+            if (L2 < 1e-12) { valid[k] = 0; s[k] = -INFINITY; sg[k] = 1; continue; }
+            u[k] = scl(c, 1.0 / sqrt(L2));
+            ra = ha[0] * fabs(dot(a[0], u[k])) + ha[1] * fabs(dot(a[1], u[k])) + ha[2] * fabs(dot(a[2], u[k]));
+            rb = hb[0] * fabs(dot(b[0], u[k])) + hb[1] * fabs(dot(b[1], u[k])) + hb[2] * fabs(dot(b[2], u[k]));
+        }
+        double dd = dot(D, u[k]);
+        s[k] = fabs(dd) - ra - rb;
+        sg[k] = dd >= 0 ? 1.0 : -1.0;
+    }
+    double smax = -INFINITY;
+    for (int k = 0; k < 15; k++) if (valid[k] && s[k] > smax) smax = s[k];
+    if (fabs(smax - margin) < BAND) (*amb)++;
+    if (smax > margin) return 0;
+
+    /* argmax within a group, ties to the lower index; near-ties are ambiguous */
+    int fa = 0, fb = 3, e = -1;
+    for (int k = 1; k < 3; k++) if (s[k] > s[fa]) fa = k;
+    for (int k = 4; k < 6; k++) if (s[k] > s[fb]) fb = k;
+    for (int k = 6; k < 15; k++) if (valid[k] && (e < 0 || s[k] > s[e])) e = k;
+    double hmax = 0;
+    for (int i = 0; i < 3; i++) { hmax = fmax(hmax, ha[i]); hmax = fmax(hmax, hb[i]); }
+    int face = fa;
+    double thr = 0.95 * s[fa] + 0.01 * hmax;
+    if (fabs(s[fb] - thr) < BAND) (*amb)++;
+    if (s[fb] > thr) face = fb;
+    int edge = 0;
+    if (e >= 0) {
+        double thr2 = 0.95 * s[face] + 0.01 * hmax;
+        if (fabs(s[e] - thr2) < BAND) (*amb)++;
+        edge = s[e] > thr2;
+    }
+    /* near-ties inside a group matter only for the group that is used */
+    if (edge) {
+        for (int k = 6; k < 15; k++) if (valid[k] && k != e && fabs(s[k] - s[e]) < BAND) (*amb)++;
+    } else if (face == fa) {
+        for (int k = 0; k < 3; k++) if (k != fa && fabs(s[k] - s[fa]) < BAND) (*amb)++;
+    } else {
+        for (int k = 3; k < 6; k++) if (k != fb && fabs(s[k] - s[fb]) < BAND) (*amb)++;
+    }
+
+    if (edge) {
+        int i = (e - 6) / 3, j = (e - 6) % 3;
+        V N = scl(u[e], sg[e]);
+        if (fabs(dot(D, u[e])) < BAND) (*amb)++;
+        V pa = A->x, pb = B->x;
+        for (int m = 0; m < 3; m++) {
+            if (m != i) {
+                double c = dot(N, a[m]);
+                if (fabs(c) < BAND_DIM) (*amb)++;
+                pa = add(pa, scl(a[m], c > 0 ? -ha[m] : ha[m]));
+            }
+            if (m != j) {
+                double c = dot(N, b[m]);
+                if (fabs(c) < BAND_DIM) (*amb)++;
+                pb = add(pb, scl(b[m], c > 0 ? hb[m] : -hb[m]));
+            }
+        }
+        V w = sub(pa, pb);
+        double bb = dot(a[i], b[j]), dd = dot(a[i], w), ee = dot(b[j], w);
+        double den = 1.0 - bb * bb;
+        double ta = (bb * ee - dd) / den;
+        double tb = ee + ta * bb;
+        ta = clampd(ta, -ha[i], ha[i]);
+        tb = clampd(tb, -hb[j], hb[j]);
+        V PA = add(pa, scl(a[i], ta)), PB = add(pb, scl(b[j], tb));
+        PC c;
+        c.n = N;
+        c.phi = dot(sub(PA, PB), N);
+        c.p = scl(add(PA, PB), 0.5);
+        c.f = 0x80 | (e - 6);
+        if (!keep(c.phi, margin, amb)) return 0;
+        out[0] = c;
+        return 1;
+    }
+
+    /* face contact */
+    V N = scl(u[face], sg[face]);               /* from B to A */
+    if (fabs(dot(D, u[face])) < BAND) (*amb)++;
+    const Geom *ref, *inc;
+    int ax, refb;
+    V nout;
+    if (face < 3) { ref = A; inc = B; ax = face; nout = scl(N, -1.0); refb = 0; }
+    else { ref = B; inc = A; ax = face - 3; nout = N; refb = 1; }
+    V rc[3], ic[3];
+    for (int k = 0; k < 3; k++) { rc[k] = col(&ref->R, k); ic[k] = col(&inc->R, k); }
+    const double *hr = ref->prm, *hi = inc->prm;
+    int side = dot(nout, rc[ax]) > 0 ? 0 : 1;
+    int refface = ax * 2 + side;
+    V cref = add(ref->x, scl(nout, hr[ax]));
+    /* incident face: most anti-parallel to nout */
+    int j = 0;
+    double best = fabs(dot(ic[0], nout));
+    for (int k = 1; k < 3; k++) { double c = fabs(dot(ic[k], nout)); if (c > best) { best = c; j = k; } }
+    for (int k = 0; k < 3; k++) if (k != j && fabs(fabs(dot(ic[k], nout)) - best) < BAND_DIM) (*amb)++;
+    double si = dot(ic[j], nout) > 0 ? -1.0 : 1.0;
+    int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+    V fc = add(inc->x, scl(ic[j], si * hi[j]));
+    V e1 = scl(ic[j1], hi[j1]), e2 = scl(ic[j2], hi[j2]);
+    V poly[8], tmp[8];
+    int np = 4;
+    poly[0] = add(add(fc, e1), e2);
+    poly[1] = add(sub(fc, e1), e2);
+    poly[2] = sub(sub(fc, e1), e2);
+    poly[3] = sub(add(fc, e1), e2);
+    int r1 = (ax + 1) % 3, r2 = (ax + 2) % 3;
+    int paxis[4] = {r1, r1, r2, r2};
+    double psign[4] = {1.0, -1.0, 1.0, -1.0};
+    for (int pl = 0; pl < 4 && np > 0; pl++) {
+        V pn = scl(rc[paxis[pl]], psign[pl]);
+        double off = hr[paxis[pl]];
+        int no = 0;
+        V prev = poly[np - 1];
+        double dp = dot(sub(prev, ref->x), pn) - off;
+        for (int k = 0; k < np; k++) {
+            V cur = poly[k];
+            double dc = dot(sub(cur, ref->x), pn) - off;
+            if (fabs(fabs(dc) - CLIP_ON) < BAND) (*amb)++;
+            /* three states: inside (< -on), on the plane (|d| <= on), outside;
+             * a vertex on the plane is kept and never spawns an intersection */
+            int ci = dc < -CLIP_ON ? -1 : (dc > CLIP_ON ? 1 : 0);
+            int pi = dp < -CLIP_ON ? -1 : (dp > CLIP_ON ? 1 : 0);
+            if (pi * ci < 0 && no < 8) tmp[no++] = add(prev, scl(sub(cur, prev), dp / (dp - dc)));
+            if (ci <= 0 && no < 8) tmp[no++] = cur;
+            prev = cur; dp = dc;
+        }
+        np = no;
+        for (int k = 0; k < np; k++) poly[k] = tmp[k];
+    }
+    int idx[8], nk = 0;
+    double ph[8];
+    for (int k = 0; k < np; k++) {
+        ph[k] = dot(sub(poly[k], cref), nout);
+        if (keep(ph[k], margin, amb)) idx[nk++] = k;
+    }
+    int sel[8], ns = 0;
+    if (nk <= 4) {
+        for (int k = 0; k < nk; k++) sel[ns++] = idx[k];
+    } else {
+        /* first kept point; farthest from it; largest triangle; largest quad
+         * (a flat face contact has all depths equal, so depth is no anchor) */
+        int used[8] = {0};
+        int i1 = idx[0];
+        used[i1] = 1;
+        int i2 = -1;
+        double bd = -1;
+        for (int k = 0; k < nk; k++) {
+            int q = idx[k];
+            if (used[q]) continue;
+            double dd = sqrt(len2(sub(poly[q], poly[i1])));
+            if (dd > bd) { bd = dd; i2 = q; }
+        }
+        for (int k = 0; k < nk; k++) {
+            int q = idx[k];
+            if (used[q] || q == i2) continue;
+            if (fabs(sqrt(len2(sub(poly[q], poly[i1]))) - bd) < BAND) (*amb)++;
+        }
+        used[i2] = 1;
+        V e12 = sub(poly[i2], poly[i1]);
+        double l12 = sqrt(len2(e12));
+        int i3 = -1;
+        double ba = -1;
+        for (int k = 0; k < nk; k++) {
+            int q = idx[k];
+            if (used[q]) continue;
+            double ar = sqrt(len2(cross(e12, sub(poly[q], poly[i1]))));
+            if (ar > ba) { ba = ar; i3 = q; }
+        }
+        for (int k = 0; k < nk; k++) {
+            int q = idx[k];
+            if (used[q] || q == i3) continue;
+            if (fabs(sqrt(len2(cross(e12, sub(poly[q], poly[i1])))) - ba) < BAND * l12) (*amb)++;
+        }
+        used[i3] = 1;
+        V e23 = sub(poly[i3], poly[i2]), e31 = sub(poly[i1], poly[i3]);
+        double per = l12 + sqrt(len2(e23)) + sqrt(len2(e31));
+        int i4 = -1;
+        double bq = -1;
+        double sc[8];
+        for (int k = 0; k < nk; k++) {
+            int q = idx[k];
+            if (used[q]) continue;
+            sc[q] = sqrt(len2(cross(e12, sub(poly[q], poly[i1])))) +
+                    sqrt(len2(cross(e23, sub(poly[q], poly[i2])))) +
+                    sqrt(len2(cross(e31, sub(poly[q], poly[i3]))));
+            if (sc[q] > bq) { bq = sc[q]; i4 = q; }
+        }
+        for (int k = 0; k < nk; k++) {
+            int q = idx[k];
+            if (used[q] || q == i4) continue;
+            if (fabs(sc[q] - bq) < BAND * per) (*amb)++;
+        }
+        used[i4] = 1;
+        for (int k = 0; k < np; k++) if (used[k]) sel[ns++] = k;
+    }
+    for (int k = 0; k < ns; k++) {
+        int q = sel[k];
+        PC c;
+        c.n = N;
+        c.phi = ph[q];
+        c.p = sub(poly[q], scl(nout, 0.5 * ph[q]));
+        c.f = refb | (refface << 1) | (q << 4);
+        out[k] = c;
+    }
+    return ns;
+}
+
+/* Ground plane z = 0 (second) against a body (first). */
+static int ground_contacts(const Geom *A, double margin, PC *out, int *amb) {
+    int n = 0;
+    V up = mk(0, 0, 1);
+    if (A->shape == ORA_SPHERE) {
+        PC c;
+        c.n = up;
+        c.phi = A->x.z - A->prm[0];
+        c.p = mk(A->x.x, A->x.y, 0.5 * (A->x.z - A->prm[0]));
+        c.f = 0;
+        if (keep(c.phi, margin, amb)) out[n++] = c;
+    } else if (A->shape == ORA_CAPSULE) {
+        V p0, d;
+        capsule_seg(A, &p0, &d);
+        for (int k = 0; k < 2; k++) {
+            V e = k == 0 ? p0 : add(p0, d);
+            PC c;
+            c.n = up;
+            c.phi = e.z - A->prm[0];
+            c.p = mk(e.x, e.y, 0.5 * (e.z - A->prm[0]));
+            c.f = k;
+            if (keep(c.phi, margin, amb)) out[n++] = c;
+        }
+    } else {
+        /* corners with depth <= margin; at most the 4 deepest (ties: lower
+         * corner index); reported in corner order */
+        V cn[8];
+        double ph[8];
+        int id[8], m = 0;
+        for (int k = 0; k < 8; k++) {
+            V off = mk((k & 1) ? A->prm[0] : -A->prm[0], (k & 2) ? A->prm[1] : -A->prm[1],
+                       (k & 4) ? A->prm[2] : -A->prm[2]);
+            cn[k] = add(A->x, Rv(&A->R, off));
+            ph[k] = cn[k].z;
+            if (keep(ph[k], margin, amb)) id[m++] = k;
+        }
+        if (m > 4) {
+            int ord[8];
+            for (int k = 0; k < m; k++) ord[k] = id[k];
+            for (int i = 1; i < m; i++)
+                for (int j = i; j > 0 && (ph[ord[j]] < ph[ord[j - 1]] ||
+                                          (ph[ord[j]] == ph[ord[j - 1]] && ord[j] < ord[j - 1])); j--) {
+                    int x = ord[j]; ord[j] = ord[j - 1]; ord[j - 1] = x;
+                }
+            if (fabs(ph[ord[3]] - ph[ord[4]]) < BAND) (*amb)++;
+            int keepk[8] = {0};
+            for (int k = 0; k < 4; k++) keepk[ord[k]] = 1;
+            m = 0;
+            for (int k = 0; k < 8; k++) if (keepk[k]) id[m++] = k;
+        }
+        for (int k = 0; k < m; k++) {
+            V c0 = cn[id[k]];
+            PC c;
+            c.n = up;
+            c.phi = ph[id[k]];
+            c.p = mk(c0.x, c0.y, 0.5 * c0.z);
+            c.f = id[k];
+            out[n++] = c;
+        }
+    }
+    return n;
+}
+
+/* Contacts of the pair (A, B) with the normal from B to A. */
+static int collide(const Geom *A, const Geom *B, double margin, PC *out, int *amb) {
+    int ta = A->shape, tb = B->shape, n = 0, flip = 0;
+    if (ta == ORA_SPHERE && tb == ORA_SPHERE) {
+        PC c = sphere_sphere(A->x, A->prm[0], B->x, B->prm[0], 0);
+        if (keep(c.phi, margin, amb)) out[n++] = c;
+    } else if (ta == ORA_SPHERE && tb == ORA_BOX) n = sphere_box(A, B, margin, out, amb);
+    else if (ta == ORA_BOX && tb == ORA_SPHERE) { n = sphere_box(B, A, margin, out, amb); flip = 1; }
+    else if (ta == ORA_SPHERE && tb == ORA_CAPSULE) n = sphere_capsule(A, B, margin, out, amb);
+    else if (ta == ORA_CAPSULE && tb == ORA_SPHERE) { n = sphere_capsule(B, A, margin, out, amb); flip = 1; }
+    else if (ta == ORA_CAPSULE && tb == ORA_BOX) n = capsule_box(A, B, margin, out, amb);
+    else if (ta == ORA_BOX && tb == ORA_CAPSULE) { n = capsule_box(B, A, margin, out, amb); flip = 1; }
+    else if (ta == ORA_BOX && tb == ORA_BOX) n = box_box(A, B, margin, out, amb);
+    else n = capsule_capsule(A, B, margin, out, amb);
+    if (flip)
+        for (int k = 0; k < n; k++) out[k].n = scl(out[k].n, -1.0);
+    return n;
+}
+
+static Geom geom_of(int shape, const double *prm, const double *pose) {
+    Geom g;
+    g.shape = shape;
+    g.x = mk(pose[0], pose[1], pose[2]);
+    g.R = quat_R(pose + 3);
+    for (int i = 0; i < 3; i++) g.prm[i] = prm[i];
+    return g;
+}
+
+int ora_collide(int shape_a, const double *param_a, const double *pose_a,
+                int shape_b, const double *param_b, const double *pose_b,
+                int ground, double margin, int *feature, double *normal,
+                double *point, double *phi, int *ambiguous) {
+    Geom A = geom_of(shape_a, param_a, pose_a);
+    PC c[4];
+    int amb = 0, n;
+    if (ground) n = ground_contacts(&A, margin, c, &amb);
+    else {
+        Geom B = geom_of(shape_b, param_b, pose_b);
+        n = collide(&A, &B, margin, c, &amb);
+    }
+    for (int k = 0; k < n; k++) {
+        feature[k] = c[k].f;
+        normal[3 * k] = c[k].n.x; normal[3 * k + 1] = c[k].n.y; normal[3 * k + 2] = c[k].n.z;
+        point[3 * k] = c[k].p.x; point[3 * k + 1] = c[k].p.y; point[3 * k + 2] = c[k].p.z;
+        phi[k] = c[k].phi;
+    }
+    if (ambiguous) *ambiguous = amb;
+    return n;
+}
+
+/* ---------------------------------------------------------------- arm */
+/* Forward kinematics of the 7-joint chain: joint axes z, y, z, y, z, y, z in
+ * each parent frame; link k is a capsule whose core runs from joint k to
+ * joint k+1 along its local z.  Writes link centres/orientations, and the
+ * world joint origins and axes. */
+static void arm_fk(const ora_model *m, const double *base, const double *th,
+                   double lpose[7][7], V o[7], V ax[7]) {
+    double q[4] = {1, 0, 0, 0};
+    V p = mk(base[0], base[1], base[2]);
+    for (int k = 0; k < 7; k++) {
+        double hq[4] = {cos(0.5 * th[k]), 0, 0, 0};
+        if (k % 2 == 0) hq[3] = sin(0.5 * th[k]); else hq[2] = sin(0.5 * th[k]);
+        double qk[4];
+        quat_mul(q, hq, qk);
+        M3 R = quat_R(qk);
+        V zl = col(&R, 2);
+        ax[k] = k % 2 == 0 ? zl : col(&R, 1);
+        o[k] = p;
+        V c = add(p, scl(zl, 0.5 * m->link_len[k]));
+        lpose[k][0] = c.x; lpose[k][1] = c.y; lpose[k][2] = c.z;
+        for (int i = 0; i < 4; i++) { lpose[k][3 + i] = qk[i]; q[i] = qk[i]; }
+        p = add(p, scl(zl, m->link_len[k]));
+    }
+}
+
+int ora_arm_pose(const ora_model *m, double *pose, const double *theta) {
+    if (!m->arm) return 0;
+    for (int s = 0; s < m->n_scenes; s++) {
+        int b1 = m->body_offset[s + 1];
+        double lp[7][7];
+        V o[7], ax[7];
+        arm_fk(m, m->arm_base + 3 * s, theta + 7 * s, lp, o, ax);
+        for (int k = 0; k < 7; k++) memcpy(pose + 7 * (b1 - 7 + k), lp[k], 7 * sizeof(double));
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------- pairs */
+static int is_dyn(const Body *b) { return b->motion == ORA_DYNAMIC; }
+
+/* Brute-force pair set: every i < j with at least one dynamic body whose
+ * closed AABBs overlap on x, y and z, then (i, ground) for dynamic i whose
+ * AABB reaches z <= 0; lexicographic order. */
+static int brute_pairs(const Body *B, int n, uint32_t *keys, int cap, int *amb) {
+    int np = 0;
+    for (int i = 0; i < n; i++) {
+        for (int j = i + 1; j < n; j++) {
+            if (!is_dyn(&B[i]) && !is_dyn(&B[j])) continue;
+            double sl = INFINITY;
+            for (int a = 0; a < 3; a++) {
+                double s1 = comp(B[i].hi, a) - comp(B[j].lo, a);
+                double s2 = comp(B[j].hi, a) - comp(B[i].lo, a);
+                sl = fmin(sl, fmin(s1, s2));
+            }
+            if (fabs(sl) < BAND) (*amb)++;
+            if (sl >= 0) {
+                if (np < cap) keys[np] = ((uint32_t)i << 16) | (uint32_t)j;
+                np++;
+            }
+        }
+        if (is_dyn(&B[i])) {
+            if (fabs(B[i].lo.z) < BAND) (*amb)++;
+            if (B[i].lo.z <= 0) {
+                if (np < cap) keys[np] = ((uint32_t)i << 16) | PAIR_GROUND;
+                np++;
+            }
+        }
+    }
+    return np;
+}
+
+/* ---------------------------------------------------------------- scene setup */
+static void load_bodies(const ora_model *m, const double *pose, const double *vel, int s, Body *B) {
+    int b0 = m->body_offset[s], n = m->body_offset[s + 1] - b0;
+    for (int k = 0; k < n; k++) {
+        int g = b0 + k;
+        Body *b = &B[k];
+        b->shape = m->shape[g];
+        b->motion = m->motion[g];
+        b->x = mk(pose[7 * g], pose[7 * g + 1], pose[7 * g + 2]);
+        for (int i = 0; i < 4; i++) b->q[i] = pose[7 * g + 3 + i];
+        b->R = quat_R(b->q);
+        for (int i = 0; i < 3; i++) b->prm[i] = m->param[3 * g + i];
+        b->v = mk(vel[6 * g], vel[6 * g + 1], vel[6 * g + 2]);
+        b->w = mk(vel[6 * g + 3], vel[6 * g + 4], vel[6 * g + 5]);
+        b->mu = m->friction[g];
+        b->e = m->restitution[g];
+        memset(&b->Iw, 0, sizeof(M3));
+        b->im = 0;
+        b->ncon = 0;
+        if (b->motion == ORA_DYNAMIC) {
+            double I[3];
+            body_inertia(b->shape, b->prm, m->mass[g], I);
+            b->im = 1.0 / m->mass[g];
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    double sum = 0;
+                    for (int k2 = 0; k2 < 3; k2++) sum += b->R.m[i][k2] * b->R.m[j][k2] / I[k2];
+                    b->Iw.m[i][j] = sum;
+                }
+        } else if (b->motion == ORA_STATIC) {
+            b->v = mk(0, 0, 0);
+            b->w = mk(0, 0, 0);
+        }
+    }
+}
+
+/* ---------------------------------------------------------------- solver */
+typedef struct {
+    int a, b;               /* local body indices, b = -1 for the ground */
+    uint32_t key;
+    V n, t1, t2, p, ra, rb;
+    double phi, mu, e, bias;
+    double m[3], k[3];      /* effective mass and its inverse per row n, t1, t2 */
+    double lam[3];
+    double feat[16];
+    int colour, matched;
+} Con;
+
+/* Orthonormal tangents from a unit normal (Duff et al. 2017, "Building an
+ * Orthonormal Basis, Revisited"). */
+static void tangents(V n, V *t1, V *t2) {
+    double sgn = copysign(1.0, n.z);
+    double a = -1.0 / (sgn + n.z);
+    double b = n.x * n.y * a;
+    *t1 = mk(1.0 + sgn * n.x * n.x * a, sgn * b, -sgn * n.x);
+    *t2 = mk(b, sgn + n.y * n.y * a, -n.y);
+}
+
+static V bvel(const Body *B, int i, V r) {
+    if (i < 0) return mk(0, 0, 0);
+    return add(B[i].v, cross(B[i].w, r));
+}
+
+static V Mv(const M3 *M, V a) { return Rv(M, a); }
+
+static double row_k(const Body *B, const Con *c, V d) {
+    double k = 0;
+    V ca = cross(c->ra, d);
+    k += B[c->a].im + dot(ca, Mv(&B[c->a].Iw, ca));
+    if (c->b >= 0) {
+        V cb = cross(c->rb, d);
+        k += B[c->b].im + dot(cb, Mv(&B[c->b].Iw, cb));
+    }
+    return k;
+}
+
+/* Apply the impulse P (from B onto A; -P onto B) at the contact. */
+static void apply(Body *B, const Con *c, V P) {
+    Body *A = &B[c->a];
+    if (A->motion == ORA_DYNAMIC) {
+        A->v = add(A->v, scl(P, A->im));
+        A->w = add(A->w, Mv(&A->Iw, cross(c->ra, P)));
+    }
+    if (c->b >= 0) {
+        Body *Bb = &B[c->b];
+        if (Bb->motion == ORA_DYNAMIC) {
+            Bb->v = sub(Bb->v, scl(P, Bb->im));
+            Bb->w = sub(Bb->w, Mv(&Bb->Iw, cross(c->rb, P)));
+        }
+    }
+}
+
+static V vrel(const Body *B, const Con *c) {
+    return sub(bvel(B, c->a, c->ra), bvel(B, c->b, c->rb));
+}
+
+/* Projection of the friction impulse onto the disk of radius mu*lambda_n. */
+static void proj_disk(double *l1, double *l2, double lim) {
+    double L = sqrt(*l1 * *l1 + *l2 * *l2);
+    if (L > lim) {
+        if (L > 0) { double f = lim / L; *l1 *= f; *l2 *= f; }
+        else { *l1 = 0; *l2 = 0; }
+    }
+}
+
+static void project(Con *c) {
+    if (c->lam[0] < 0) c->lam[0] = 0;
+    proj_disk(&c->lam[1], &c->lam[2], c->mu * c->lam[0]);
+}
+
+/* One projected Gauss-Seidel sweep in colour-major order.  Rows of one
+ * contact: the normal row, then both friction rows from the velocities that
+ * follow the normal update.  Returns the sweep residual max |dlambda|*k. */
+static double pgs_sweep(Body *B, Con *C, const int *order, int nc) {
+    double R = 0;
+    for (int q = 0; q < nc; q++) {
+        Con *c = &C[order[q]];
+        V vr = vrel(B, c);
+        double u = dot(c->n, vr);
+        double ln = fmax(0.0, c->lam[0] + c->m[0] * (c->bias - u));
+        double dn = ln - c->lam[0];
+        c->lam[0] = ln;
+        apply(B, c, scl(c->n, dn));
+        vr = vrel(B, c);
+        double l1 = c->lam[1] - c->m[1] * dot(c->t1, vr);
+        double l2 = c->lam[2] - c->m[2] * dot(c->t2, vr);
+        proj_disk(&l1, &l2, c->mu * ln);
+        double d1 = l1 - c->lam[1], d2 = l2 - c->lam[2];
+        c->lam[1] = l1; c->lam[2] = l2;
+        apply(B, c, add(scl(c->t1, d1), scl(c->t2, d2)));
+        R = fmax(R, fabs(dn) * c->k[0]);
+        R = fmax(R, fabs(d1) * c->k[1]);
+        R = fmax(R, fabs(d2) * c->k[2]);
+    }
+    return R;
+}
+
+/* One Jacobi sweep: every row reads the velocities of the start of the
+ * sweep; each increment is divided by max(n_A, n_B) (contacts per dynamic
+ * body), projected, then all impulses are applied. */
+static double jacobi_sweep(Body *B, int nb, Con *C, const int *order, int nc) {
+    V *v0 = malloc(sizeof(V) * nb * 2);
+    for (int i = 0; i < nb; i++) { v0[2 * i] = B[i].v; v0[2 * i + 1] = B[i].w; }
+    double R = 0;
+    double *dl = malloc(sizeof(double) * 3 * (nc ? nc : 1));
+    for (int q = 0; q < nc; q++) {
+        Con *c = &C[order[q]];
+        V va = add(v0[2 * c->a], cross(v0[2 * c->a + 1], c->ra));
+        V vb = c->b >= 0 ? add(v0[2 * c->b], cross(v0[2 * c->b + 1], c->rb)) : mk(0, 0, 0);
+        V vr = sub(va, vb);
+        int na = B[c->a].motion == ORA_DYNAMIC ? B[c->a].ncon : 0;
+        int nbb = (c->b >= 0 && B[c->b].motion == ORA_DYNAMIC) ? B[c->b].ncon : 0;
+        double sc = 1.0 / (double)(na > nbb ? na : nbb);
+        double ln = fmax(0.0, c->lam[0] + sc * c->m[0] * (c->bias - dot(c->n, vr)));
+        double l1 = c->lam[1] - sc * c->m[1] * dot(c->t1, vr);
+        double l2 = c->lam[2] - sc * c->m[2] * dot(c->t2, vr);
+        proj_disk(&l1, &l2, c->mu * ln);
+        dl[3 * q] = ln - c->lam[0];
+        dl[3 * q + 1] = l1 - c->lam[1];
+        dl[3 * q + 2] = l2 - c->lam[2];
+        c->lam[0] = ln; c->lam[1] = l1; c->lam[2] = l2;
+    }
+    for (int q = 0; q < nc; q++) {
+        Con *c = &C[order[q]];
+        apply(B, c, scl(c->n, dl[3 * q]));
+        apply(B, c, add(scl(c->t1, dl[3 * q + 1]), scl(c->t2, dl[3 * q + 2])));
+        R = fmax(R, fabs(dl[3 * q]) * c->k[0]);
+        R = fmax(R, fabs(dl[3 * q + 1]) * c->k[1]);
+        R = fmax(R, fabs(dl[3 * q + 2]) * c->k[2]);
+    }
+    free(dl);
+    free(v0);
+    return R;
+}
+
+/* ---------------------------------------------------------------- MLP */
+double ora_bf16(double x) {
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return x;      /* inf / nan unchanged */
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    u &= 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static double qz(const ora_mlp *net, double x) { return net->bf16 ? ora_bf16(x) : x; }
+
+/* Forward pass of one row; keeps the layer activations for backward. */
+static void mlp_row(const ora_mlp *net, const double *x, double *z0, double *a1, double *a2, double *y) {
+    for (int i = 0; i < 16; i++) {
+        double sd = net->std[i] > 1e-6 ? net->std[i] : 1e-6;
+        z0[i] = qz(net, (x[i] - net->mean[i]) / sd);
+    }
+    for (int o = 0; o < 64; o++) {
+        double s = 0;
+        for (int i = 0; i < 16; i++) s += qz(net, net->w1[16 * o + i]) * z0[i];
+        s += net->b1[o];
+        a1[o] = s > 0 ? s : 0;
+    }
+    for (int o = 0; o < 64; o++) a1[o] = qz(net, a1[o]);
+    for (int o = 0; o < 64; o++) {
+        double s = 0;
+        for (int i = 0; i < 64; i++) s += qz(net, net->w2[64 * o + i]) * a1[i];
+        s += net->b2[o];
+        a2[o] = s > 0 ? s : 0;
+    }
+    for (int o = 0; o < 64; o++) a2[o] = qz(net, a2[o]);
+    for (int o = 0; o < 3; o++) {
+        double s = 0;
+        for (int i = 0; i < 64; i++) s += qz(net, net->w3[64 * o + i]) * a2[i];
+        y[o] = s + net->b3[o];
+    }
+}
+
+void ora_mlp_forward(const ora_mlp *net, const double *x, int n, double *y) {
+    double z0[16], a1[64], a2[64];
+    for (int r = 0; r < n; r++) mlp_row(net, x + 16 * r, z0, a1, a2, y + 3 * r);
+}
+
+double ora_mlp_loss_grad(const ora_mlp *net, const double *x, const double *t, int n,
+                         double *gw1, double *gb1, double *gw2, double *gb2,
+                         double *gw3, double *gb3) {
+    memset(gw1, 0, sizeof(double) * 64 * 16); memset(gb1, 0, sizeof(double) * 64);
+    memset(gw2, 0, sizeof(double) * 64 * 64); memset(gb2, 0, sizeof(double) * 64);
+    memset(gw3, 0, sizeof(double) * 3 * 64);  memset(gb3, 0, sizeof(double) * 3);
+    double loss = 0, z0[16], a1[64], a2[64], y[3], dy[3], d2[64], d1[64];
+    double inv = 1.0 / (3.0 * n);
+    for (int r = 0; r < n; r++) {
+        mlp_row(net, x + 16 * r, z0, a1, a2, y);
+        for (int o = 0; o < 3; o++) {
+            double e = y[o] - t[3 * r + o];
+            loss += e * e * inv;
+            dy[o] = 2.0 * e * inv;
+            gb3[o] += dy[o];
+            for (int i = 0; i < 64; i++) gw3[64 * o + i] += dy[o] * a2[i];
+        }
+        for (int i = 0; i < 64; i++) {
+            double s = 0;
+            for (int o = 0; o < 3; o++) s += qz(net, net->w3[64 * o + i]) * dy[o];
+            d2[i] = a2[i] > 0 ? s : 0;
+        }
+        for (int o = 0; o < 64; o++) {
+            gb2[o] += d2[o];
+            for (int i = 0; i < 64; i++) gw2[64 * o + i] += d2[o] * a1[i];
+        }
+        for (int i = 0; i < 64; i++) {
+            double s = 0;
+            for (int o = 0; o < 64; o++) s += qz(net, net->w2[64 * o + i]) * d2[o];
+            d1[i] = a1[i] > 0 ? s : 0;
+        }
+        for (int o = 0; o < 64; o++) {
+            gb1[o] += d1[o];
+            for (int i = 0; i < 16; i++) gw1[16 * o + i] += d1[o] * z0[i];
+        }
+    }
+    return loss;
+}
+
+/* ---------------------------------------------------------------- step */
+
+static int lookup(const ora_cache *cache, int s, uint32_t key) {
+    if (!cache) return -1;
+    const uint32_t *k = cache->key + (size_t)s * cache->cap;
+    int lo = 0, hi = cache->count[s] - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) / 2;
+        if (k[mid] == key) return mid;
+        if (k[mid] < key) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+static int finite3(V a) { return isfinite(a.x) && isfinite(a.y) && isfinite(a.z); }
+
+static int solve(Body *B, int nb, Con *C, const int *order, int nc, int iters, double tol,
+                 int solver, double *res) {
+    int sw = 0;
+    double R = 0;
+    for (int it = 0; it < iters; it++) {
+        R = solver == ORA_JACOBI ? jacobi_sweep(B, nb, C, order, nc) : pgs_sweep(B, C, order, nc);
+        sw++;
+        if (tol > 0 && R <= tol) break;
+    }
+    *res = R;
+    return sw;
+}
+
+static void warm_apply(Body *B, Con *C, const int *order, int nc) {
+    for (int q = 0; q < nc; q++) {
+        Con *c = &C[order[q]];
+        project(c);
+        apply(B, c, add(scl(c->n, c->lam[0]), add(scl(c->t1, c->lam[1]), scl(c->t2, c->lam[2]))));
+    }
+}
+
+static void step_scene(const ora_model *m, double *pose, double *vel, double *theta,
+                       ora_cache *cache, const double *actions, double dt, int iters,
+                       double tol, int warm, int solver, const ora_mlp *mlp, ora_out *out, int s) {
+    int b0 = m->body_offset[s], nb = m->body_offset[s + 1] - b0;
+    int flags = 0, amb = 0;
+    double margin = m->margin;
+    V g = mk(m->gravity[0], m->gravity[1], m->gravity[2]);
+    double gmag = sqrt(len2(g));
+
+    /* 1. arm: poses at theta_t, link velocities from the joint velocities */
+    double thd[7] = {0};
+    V ao[7], aax[7];
+    if (m->arm) {
+        double lp[7][7];
+        if (actions) for (int k = 0; k < 7; k++) thd[k] = actions[7 * s + k];
+        arm_fk(m, m->arm_base + 3 * s, theta + 7 * s, lp, ao, aax);
+        for (int k = 0; k < 7; k++) {
+            int gi = b0 + nb - 7 + k;
+            memcpy(pose + 7 * gi, lp[k], 7 * sizeof(double));
+            V c = mk(lp[k][0], lp[k][1], lp[k][2]);
+            V w = mk(0, 0, 0), v = mk(0, 0, 0);
+            for (int j = 0; j <= k; j++) {
+                w = add(w, scl(aax[j], thd[j]));
+                v = add(v, scl(cross(aax[j], sub(c, ao[j])), thd[j]));
+            }
+            vel[6 * gi] = v.x; vel[6 * gi + 1] = v.y; vel[6 * gi + 2] = v.z;
+            vel[6 * gi + 3] = w.x; vel[6 * gi + 4] = w.y; vel[6 * gi + 5] = w.z;
+        }
+    }
+    Body *B = malloc(sizeof(Body) * (nb ? nb : 1));
+    load_bodies(m, pose, vel, s, B);
+
+    /* 2. velocity integration (no gyroscopic term) */
+    for (int i = 0; i < nb; i++)
+        if (B[i].motion == ORA_DYNAMIC) B[i].v = add(B[i].v, scl(g, dt));
+
+    /* 3. AABBs; 4. pairs */
+    for (int i = 0; i < nb; i++) body_aabb(&B[i], margin);
+    int maxp = nb * (nb + 1) / 2 + 1;
+    uint32_t *pk = malloc(sizeof(uint32_t) * maxp);
+    int np = brute_pairs(B, nb, pk, maxp, &amb);
+
+    /* 5. narrowphase in canonical pair order; 6. contact list */
+    int capc = 4 * np + 1;
+    Con *C = calloc(capc, sizeof(Con));
+    int nc = 0;
+    for (int q = 0; q < np; q++) {
+        int a = pk[q] >> 16, b = pk[q] & 0xFFFF;
+        int ground = b == PAIR_GROUND;
+        Geom GA, GB;
+        GA.shape = B[a].shape; GA.x = B[a].x; GA.R = B[a].R;
+        memcpy(GA.prm, B[a].prm, sizeof GA.prm);
+        PC pc[4];
+        int k;
+        if (ground) k = ground_contacts(&GA, margin, pc, &amb);
+        else {
+            GB.shape = B[b].shape; GB.x = B[b].x; GB.R = B[b].R;
+            memcpy(GB.prm, B[b].prm, sizeof GB.prm);
+            k = collide(&GA, &GB, margin, pc, &amb);
+        }
+        for (int i = 0; i < k; i++) {
+            Con *c = &C[nc++];
+            c->a = a;
+            c->b = ground ? -1 : b;
+            c->key = ((uint32_t)a << 20) | ((uint32_t)(ground ? KEY_GROUND : b) << 8) | (uint32_t)pc[i].f;
+            c->n = pc[i].n; c->p = pc[i].p; c->phi = pc[i].phi;
+        }
+    }
+
+    /* 7. setup */
+    for (int q = 0; q < nc; q++) {
+        Con *c = &C[q];
+        Body *A = &B[c->a];
+        double mub = c->b >= 0 ? B[c->b].mu : m->ground_friction;
+        double eb = c->b >= 0 ? B[c->b].e : m->ground_restitution;
+        c->mu = sqrt(A->mu * mub);
+        c->e = fmax(A->e, eb);
+        c->ra = sub(c->p, A->x);
+        c->rb = c->b >= 0 ? sub(c->p, B[c->b].x) : mk(0, 0, 0);
+        tangents(c->n, &c->t1, &c->t2);
+        c->k[0] = row_k(B, c, c->n);
+        c->k[1] = row_k(B, c, c->t1);
+        c->k[2] = row_k(B, c, c->t2);
+        for (int r = 0; r < 3; r++) c->m[r] = 1.0 / c->k[r];
+        V vr = vrel(B, c);
+        double u0 = dot(c->n, vr);
+        if (c->phi > 0) c->bias = -c->phi / dt;
+        else c->bias = m->baumgarte / dt * fmax(0.0, -c->phi - m->slop);
+        if (c->e > 0 && u0 < -m->rest_thresh) c->bias = fmax(c->bias, -c->e * u0);
+        /* previous impulse (friction re-projected on the new tangents) */
+        int hit = lookup(cache, s, c->key);
+        double lp[3] = {0, 0, 0};
+        if (hit >= 0) {
+            const double *L = cache->lam + 4 * ((size_t)s * cache->cap + hit);
+            V F = mk(L[1], L[2], L[3]);
+            lp[0] = L[0]; lp[1] = dot(F, c->t1); lp[2] = dot(F, c->t2);
+        }
+        c->matched = hit >= 0;
+        double *f = c->feat;
+        f[0] = u0; f[1] = dot(c->t1, vr); f[2] = dot(c->t2, vr);
+        f[3] = -c->phi;
+        f[4] = A->im; f[5] = c->b >= 0 ? B[c->b].im : 0;
+        V can = cross(c->ra, c->n);
+        f[6] = dot(can, Mv(&A->Iw, can));
+        if (c->b >= 0) { V cbn = cross(c->rb, c->n); f[7] = dot(cbn, Mv(&B[c->b].Iw, cbn)); }
+        else f[7] = 0;
+        f[8] = lp[0]; f[9] = lp[1]; f[10] = lp[2];
+        f[11] = c->n.x; f[12] = c->n.y; f[13] = c->n.z;
+        f[14] = c->mu; f[15] = c->matched ? 1.0 : 0.0;
+        c->lam[0] = c->lam[1] = c->lam[2] = 0;
+        if (warm == ORA_PREV) { c->lam[0] = lp[0]; c->lam[1] = lp[1]; c->lam[2] = lp[2]; }
+        else if (warm == ORA_LEARNED && mlp) {
+            double y[3];
+            ora_mlp_forward(mlp, f, 1, y);
+            double sc = gmag * dt * c->m[0];
+            for (int r = 0; r < 3; r++) c->lam[r] = y[r] * sc;
+        }
+    }
+
+    /* 9. colouring: first fit in canonical order; only dynamic bodies conflict */
+    uint64_t *used = calloc((size_t)(nb ? nb : 1) * (MAXCOL / 64), sizeof(uint64_t));
+    int ncol = 0;
+    for (int q = 0; q < nc; q++) {
+        Con *c = &C[q];
+        int ids[2] = {c->a, c->b};
+        uint64_t mask[MAXCOL / 64] = {0};
+        for (int t = 0; t < 2; t++) {
+            int i = ids[t];
+            if (i < 0 || B[i].motion != ORA_DYNAMIC) continue;
+            for (int w = 0; w < MAXCOL / 64; w++) mask[w] |= used[(size_t)i * (MAXCOL / 64) + w];
+        }
+        int col_ = -1;
+        for (int k = 0; k < MAXCOL; k++) if (!((mask[k / 64] >> (k % 64)) & 1)) { col_ = k; break; }
+        if (col_ < 0) { flags |= ORA_F_CAPACITY; col_ = MAXCOL - 1; }
+        c->colour = col_;
+        if (col_ + 1 > ncol) ncol = col_ + 1;
+        for (int t = 0; t < 2; t++) {
+            int i = ids[t];
+            if (i < 0 || B[i].motion != ORA_DYNAMIC) continue;
+            used[(size_t)i * (MAXCOL / 64) + col_ / 64] |= 1ull << (col_ % 64);
+            B[i].ncon++;
+        }
+    }
+    free(used);
+    int *order = malloc(sizeof(int) * (nc ? nc : 1));
+    {
+        int w = 0;
+        for (int k = 0; k < ncol; k++)
+            for (int q = 0; q < nc; q++) if (C[q].colour == k) order[w++] = q;
+    }
+
+    /* 8. initial impulses, 10. sweeps */
+    V *vsave = malloc(sizeof(V) * 2 * (nb ? nb : 1));
+    for (int i = 0; i < nb; i++) { vsave[2 * i] = B[i].v; vsave[2 * i + 1] = B[i].w; }
+    warm_apply(B, C, order, nc);
+    double R = 0;
+    int sweeps = solve(B, nb, C, order, nc, iters, tol, solver, &R);
+    if (tol > 0 && R > tol) {
+        if (warm == ORA_LEARNED) {
+            flags |= ORA_F_FELLBACK;
+            for (int i = 0; i < nb; i++) { B[i].v = vsave[2 * i]; B[i].w = vsave[2 * i + 1]; }
+            for (int q = 0; q < nc; q++) C[q].lam[0] = C[q].lam[1] = C[q].lam[2] = 0;
+            sweeps = solve(B, nb, C, order, nc, iters, tol, solver, &R);
+            if (R > tol) flags |= ORA_F_NOT_CONVERGED;
+        } else {
+            flags |= ORA_F_NOT_CONVERGED;
+        }
+    }
+    free(vsave);
+
+    /* 11. position integration; arm joint update */
+    for (int i = 0; i < nb; i++) {
+        Body *b = &B[i];
+        if (b->motion != ORA_DYNAMIC) continue;
+        b->x = add(b->x, scl(b->v, dt));
+        double wq[4] = {0, b->w.x, b->w.y, b->w.z}, dq[4];
+        quat_mul(wq, b->q, dq);
+        double q2[4], L = 0;
+        for (int k = 0; k < 4; k++) { q2[k] = b->q[k] + 0.5 * dt * dq[k]; L += q2[k] * q2[k]; }
+        L = sqrt(L);
+        for (int k = 0; k < 4; k++) b->q[k] = q2[k] / L;
+        int gi = b0 + i;
+        pose[7 * gi] = b->x.x; pose[7 * gi + 1] = b->x.y; pose[7 * gi + 2] = b->x.z;
+        for (int k = 0; k < 4; k++) pose[7 * gi + 3 + k] = b->q[k];
+        vel[6 * gi] = b->v.x; vel[6 * gi + 1] = b->v.y; vel[6 * gi + 2] = b->v.z;
+        vel[6 * gi + 3] = b->w.x; vel[6 * gi + 4] = b->w.y; vel[6 * gi + 5] = b->w.z;
+        if (!finite3(b->x) || !finite3(b->v) || !finite3(b->w)) flags |= ORA_F_NONFINITE;
+    }
+    if (m->arm) {
+        for (int k = 0; k < 7; k++) theta[7 * s + k] += dt * thd[k];
+        double lp[7][7];
+        arm_fk(m, m->arm_base + 3 * s, theta + 7 * s, lp, ao, aax);
+        for (int k = 0; k < 7; k++) memcpy(pose + 7 * (b0 + nb - 7 + k), lp[k], 7 * sizeof(double));
+    }
+
+    /* 12. outputs: arm contact force, cache, contacts, stats */
+    double force = 0;
+    int arm0 = m->arm ? nb - 7 : nb;
+    for (int q = 0; q < nc; q++) {
+        Con *c = &C[q];
+        if (c->a >= arm0 || (c->b >= arm0)) {
+            V P = add(scl(c->n, c->lam[0]), add(scl(c->t1, c->lam[1]), scl(c->t2, c->lam[2])));
+            force += sqrt(len2(P)) / dt;
+        }
+    }
+    if (cache) {
+        int w = nc < cache->cap ? nc : cache->cap;
+        if (nc > cache->cap) flags |= ORA_F_CAPACITY;
+        for (int q = 0; q < w; q++) {
+            Con *c = &C[q];
+            size_t o = (size_t)s * cache->cap + q;
+            cache->key[o] = c->key;
+            V F = add(scl(c->t1, c->lam[1]), scl(c->t2, c->lam[2]));
+            cache->lam[4 * o] = c->lam[0];
+            cache->lam[4 * o + 1] = F.x; cache->lam[4 * o + 2] = F.y; cache->lam[4 * o + 3] = F.z;
+        }
+        cache->count[s] = w;
+    }
+    if (out) {
+        if (out->n_pairs) out->n_pairs[s] = np;
+        if (out->pair_key) {
+            int w = np < out->max_pairs ? np : out->max_pairs;
+            memcpy(out->pair_key + (size_t)s * out->max_pairs, pk, sizeof(uint32_t) * w);
+        }
+        if (out->n_contacts) out->n_contacts[s] = nc;
+        int w = nc < out->max_contacts ? nc : out->max_contacts;
+        for (int q = 0; q < w; q++) {
+            Con *c = &C[q];
+            size_t o = (size_t)s * out->max_contacts + q;
+            if (out->c_key) out->c_key[o] = c->key;
+            if (out->c_normal) { out->c_normal[3 * o] = c->n.x; out->c_normal[3 * o + 1] = c->n.y; out->c_normal[3 * o + 2] = c->n.z; }
+            if (out->c_point) { out->c_point[3 * o] = c->p.x; out->c_point[3 * o + 1] = c->p.y; out->c_point[3 * o + 2] = c->p.z; }
+            if (out->c_phi) out->c_phi[o] = c->phi;
+            if (out->c_lambda) for (int r = 0; r < 3; r++) out->c_lambda[3 * o + r] = c->lam[r];
+            if (out->c_colour) out->c_colour[o] = c->colour;
+            if (out->c_feat) memcpy(out->c_feat + 16 * o, c->feat, 16 * sizeof(double));
+        }
+        if (out->n_colours) out->n_colours[s] = ncol;
+        if (out->sweeps) out->sweeps[s] = sweeps;
+        if (out->residual) out->residual[s] = R;
+        if (out->arm_force) out->arm_force[s] = force;
+        if (out->flags) out->flags[s] = flags;
+        if (out->ambiguous) out->ambiguous[s] = amb;
+    }
+    free(order);
+    free(C);
+    free(pk);
+    free(B);
+}
+
+int ora_step(const ora_model *m, double *pose, double *vel, double *theta,
+             ora_cache *cache, const double *actions, double dt, int iters,
+             double tol, int warm, int solver, const ora_mlp *mlp,
+             ora_out *out, int s0, int s1) {
+    if (!m || !pose || !vel || dt <= 0 || iters < 0 || s0 < 0 || s1 > m->n_scenes || s0 > s1) return -1;
+    if (m->arm && !theta) return -1;
+    if (warm == ORA_LEARNED && !mlp) return -1;
+    for (int s = s0; s < s1; s++)
+        step_scene(m, pose, vel, theta, cache, actions, dt, iters, tol, warm, solver, mlp, out, s);
+    return 0;
+}
+
+int ora_pairs(const ora_model *m, const double *pose, int s, uint32_t *keys, int cap) {
+    int b0 = m->body_offset[s], nb = m->body_offset[s + 1] - b0;
+    Body *B = malloc(sizeof(Body) * (nb ? nb : 1));
+    double *vel = calloc((size_t)6 * m->body_offset[m->n_scenes], sizeof(double));
+    load_bodies(m, pose, vel, s, B);
+    for (int i = 0; i < nb; i++) body_aabb(&B[i], m->margin);
+    int amb = 0;
+    int n = brute_pairs(B, nb, keys, cap, &amb);
+    free(vel);
+    free(B);
+    return n;
+}

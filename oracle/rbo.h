@@ -1,0 +1,136 @@
+/*
+ * rbo.h -- FP64 CPU oracle of the batched rigid-body step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the package's smoke() check and the
+ * cpu_baseline leg of bench.py may load this library.  It shares no code with
+ * the HIP path: no headers, no helpers, no tables.
+ *
+ * It computes, in plain double-precision loops and in the method's own order,
+ * one step (s_t, a_t) -> s_{t+1} of the physics engine that the paper's
+ * simulator definition names (Sec. 2, "What is a simulator?"), for a batch of
+ * independent scenes made of rigid bodies with mass, friction and restitution
+ * and simplified collision proxies (Sec. 3, asset creation; Sec. 4.3), with
+ * parts constrained to the base treated as static (Sec. 4.1) and a
+ * kinematically driven 7-DoF arm (Sec. 5, embodiment), at 1/120 s per step
+ * (Sec. 4.4).  The paper does not specify the engine's algorithms; the steps
+ * follow the readings written in the design notes: brute-force broadphase,
+ * sphere/box/capsule narrowphase, first-fit colouring, colour-major projected
+ * Gauss-Seidel (or Jacobi), semi-implicit Euler.
+ *
+ * Key layouts (identical on both sides by definition, not by shared code):
+ *   pair key    = (a << 16) | b            b = 0xFFFF for the ground
+ *   contact key = (a << 20) | (b << 8) | f b = 0xFFF  for the ground
+ */
+#ifndef RBO_H
+#define RBO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORA_SPHERE = 0, ORA_BOX = 1, ORA_CAPSULE = 2 };
+enum { ORA_DYNAMIC = 0, ORA_STATIC = 1, ORA_KINEMATIC = 2 };
+enum { ORA_COLD = 0, ORA_PREV = 1, ORA_LEARNED = 2 };
+enum { ORA_PGS = 0, ORA_JACOBI = 1 };
+enum { ORA_F_NONFINITE = 1, ORA_F_CAPACITY = 2, ORA_F_NOT_CONVERGED = 4, ORA_F_FELLBACK = 8 };
+
+typedef struct ora_model {
+    int n_scenes;
+    const int32_t *body_offset;   /* [S+1] */
+    const uint8_t *shape;         /* [N] */
+    const uint8_t *motion;        /* [N] */
+    const double *param;          /* [N*3] sphere r | box half-extents | capsule r, half-length */
+    const double *mass;           /* [N] kg (ignored unless dynamic) */
+    const double *friction;       /* [N] */
+    const double *restitution;    /* [N] */
+    int arm;                      /* 1: the last 7 bodies of every scene are the arm links */
+    const double *arm_base;       /* [S*3] */
+    double link_len[7];
+    double arm_radius;
+    double gravity[3];
+    double margin;                /* AABB fattening and contact keep distance (m) */
+    double baumgarte;
+    double slop;                  /* m */
+    double rest_thresh;           /* m/s */
+    double ground_friction;
+    double ground_restitution;
+} ora_model;
+
+typedef struct ora_cache {        /* previous step's contacts, sorted by key */
+    int cap;                      /* per-scene capacity */
+    int32_t *count;               /* [S] */
+    uint32_t *key;                /* [S*cap] */
+    double *lam;                  /* [S*cap*4]: lambda_n, world friction impulse xyz */
+} ora_cache;
+
+typedef struct ora_mlp {          /* 16-64-64-3 warm-start network */
+    const double *w1, *b1;        /* [64*16], [64] row-major (out, in) */
+    const double *w2, *b2;        /* [64*64], [64] */
+    const double *w3, *b3;        /* [3*64], [3] */
+    const double *mean, *std;     /* [16] feature normalisation */
+    int bf16;                     /* 1: round weights and layer inputs to bf16 (RNE) */
+} ora_mlp;
+
+typedef struct ora_out {          /* optional per-scene outputs (any pointer may be NULL) */
+    int max_pairs, max_contacts;
+    int32_t *n_pairs;             /* [S] */
+    uint32_t *pair_key;           /* [S*max_pairs] */
+    int32_t *n_contacts;          /* [S] */
+    uint32_t *c_key;              /* [S*max_contacts] */
+    double *c_normal;             /* [S*max_contacts*3] unit, from body b to body a */
+    double *c_point;              /* [S*max_contacts*3] */
+    double *c_phi;                /* [S*max_contacts] signed separation (m) */
+    double *c_lambda;             /* [S*max_contacts*3] impulses n, t1, t2 (N s) */
+    int32_t *c_colour;            /* [S*max_contacts] */
+    double *c_feat;               /* [S*max_contacts*16] warm-start features */
+    int32_t *n_colours;           /* [S] */
+    int32_t *sweeps;              /* [S] */
+    double *residual;             /* [S] last sweep's residual (m/s) */
+    double *arm_force;            /* [S] N */
+    int32_t *flags;               /* [S] */
+    int32_t *ambiguous;           /* [S] decisions that fell inside the tie band */
+} ora_out;
+
+/* One step for scenes [s0, s1).  pose [N*7] (x, q w x y z), vel [N*6] (v, w),
+ * theta [S*7] are read and overwritten.  cache may be NULL (then treated as
+ * empty and not written).  actions [S*7] joint velocities (rad/s) or NULL.
+ * iters: sweep cap.  tol > 0 stops a scene's sweeps once residual <= tol.
+ * Returns 0, or -1 on a bad argument. */
+int ora_step(const ora_model *m, double *pose, double *vel, double *theta,
+             ora_cache *cache, const double *actions, double dt, int iters,
+             double tol, int warm, int solver, const ora_mlp *mlp,
+             ora_out *out, int s0, int s1);
+
+/* Arm forward kinematics for all scenes: writes the arm links' pose. */
+int ora_arm_pose(const ora_model *m, double *pose, const double *theta);
+
+/* Narrowphase of one body pair, for unit tests.  Shapes as in the model;
+ * poses [7].  ground: b is the plane z = 0 (shape_b, param_b, pose_b unused).
+ * Writes up to 4 contacts (normal from b to a).  Returns the count. */
+int ora_collide(int shape_a, const double *param_a, const double *pose_a,
+                int shape_b, const double *param_b, const double *pose_b,
+                int ground, double margin, int *feature, double *normal,
+                double *point, double *phi, int *ambiguous);
+
+/* Brute-force pair set of scene s at the given poses. Returns the count. */
+int ora_pairs(const ora_model *m, const double *pose, int s, uint32_t *keys, int cap);
+
+/* MLP: forward for n rows of 16 raw features -> n*3 outputs. */
+void ora_mlp_forward(const ora_mlp *net, const double *x, int n, double *y);
+
+/* Loss 1/(3n) sum (y - t)^2 and its gradient w.r.t. every parameter
+ * (pure FP64, or with the forward pass rounded like the bf16 kernels when
+ * net->bf16 = 1).  g* have the shapes of the weights.  Returns the loss. */
+double ora_mlp_loss_grad(const ora_mlp *net, const double *x, const double *t, int n,
+                         double *gw1, double *gb1, double *gw2, double *gb2,
+                         double *gw3, double *gb3);
+
+/* Round to the nearest bf16 (ties to even), returned as a double. */
+double ora_bf16(double x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,373 @@
+"""Seeded synthetic scene batches for the batched rigid-body step.
+
+This module is the single source of inputs for both the HIP path and the
+FP64 oracle.  It draws shapes, masses, materials, initial poses, arm joint
+angles and per-step arm actions from a counter-based SplitMix64 stream
+(Steele, Lea & Flood 2014) and returns plain numpy arrays.  It holds none of
+the step's arithmetic: no inertia, no kinematics, no collision geometry, no
+solver.  Rejection of initial overlaps uses bounding spheres only.
+
+Workloads (stand-ins for the paper's ReplicaCAD/YCB rearrangement scenes,
+Sec. 3 and Sec. 4.3; physics at 1/120 s per step, Sec. 4.4):
+
+* ``drop_scene``   -- spheres and boxes dropped from uniform positions in a
+  cube onto the ground plane (64 bodies in a 2 m cube for the small case;
+  the cube edge grows as (n/64)^(1/3) for larger scenes).
+* ``clutter_scene`` -- 20 static boxes (counters, shelves, walls), 108 dynamic
+  spheres/boxes/capsules and a kinematic 7-link capsule arm.
+* ``uneven_batch`` -- scenes with log-uniform dynamic body counts.
+
+Conventions: z up, ground plane z = 0, quaternions (w, x, y, z) body->world,
+box parameters are half-extents, capsule parameters are (radius, half-length
+of the core segment along local z).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SPHERE, BOX, CAPSULE = 0, 1, 2
+DYNAMIC, STATIC, KINEMATIC = 0, 1, 2
+
+ARM_LINKS = 7
+ARM_LINK_LENGTH = (0.10, 0.30, 0.10, 0.30, 0.10, 0.20, 0.10)
+ARM_RADIUS = 0.05
+ARM_BASE = (0.0, 0.0, 0.8)
+
+_M64 = (1 << 64) - 1
+_GOLDEN = 0x9E3779B97F4A7C15
+
+
+def _mix_np(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on a uint64 array (wrapping arithmetic)."""
+    with np.errstate(over="ignore"):
+        z = z.astype(np.uint64, copy=True)
+        z ^= z >> np.uint64(30)
+        z *= np.uint64(0xBF58476D1CE4E5B9)
+        z ^= z >> np.uint64(27)
+        z *= np.uint64(0x94D049BB133111EB)
+        z ^= z >> np.uint64(31)
+    return z
+
+
+def _mix_int(z: int) -> int:
+    z &= _M64
+    z ^= z >> 30
+    z = (z * 0xBF58476D1CE4E5B9) & _M64
+    z ^= z >> 27
+    z = (z * 0x94D049BB133111EB) & _M64
+    z ^= z >> 31
+    return z
+
+
+def stream_key(*ids: int) -> int:
+    """Fold integer ids (seed, scene, purpose, ...) into one 64-bit key."""
+    h = 0x243F6A8885A308D3
+    for i in ids:
+        h = _mix_int((h + _GOLDEN) ^ (int(i) & _M64))
+    return h
+
+
+def uniforms(key: int, count: int, start: int = 0) -> np.ndarray:
+    """``count`` doubles in [0, 1) from stream ``key``: the 53 high bits of
+    mix(key + (k+1)*golden) for k = start .. start+count-1."""
+    k = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(key) + k * np.uint64(_GOLDEN)
+    z = _mix_np(z)
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+class _Stream:
+    """Sequential reader over one counter-based stream."""
+
+    def __init__(self, key: int):
+        self.key = key
+        self.pos = 0
+
+    def take(self, n: int) -> np.ndarray:
+        u = uniforms(self.key, n, self.pos)
+        self.pos += n
+        return u
+
+    def uniform(self, lo, hi, n=None):
+        if n is None:
+            return float(lo + (hi - lo) * self.take(1)[0])
+        return lo + (hi - lo) * self.take(n)
+
+
+def _random_quat(st: _Stream) -> np.ndarray:
+    """Uniform random unit quaternion (Shoemake 1992), (w, x, y, z)."""
+    u1, u2, u3 = st.take(3)
+    a, b = math.sqrt(1.0 - u1), math.sqrt(u1)
+    t2, t3 = 2.0 * math.pi * u2, 2.0 * math.pi * u3
+    return np.array([b * math.cos(t3), a * math.sin(t2), a * math.cos(t2), b * math.sin(t3)])
+
+
+def _yaw_quat(yaw: float) -> np.ndarray:
+    return np.array([math.cos(0.5 * yaw), 0.0, 0.0, math.sin(0.5 * yaw)])
+
+
+def bounding_radius(shape: int, param) -> float:
+    """Radius of a sphere about the centre that encloses the shape."""
+    if shape == SPHERE:
+        return float(param[0])
+    if shape == BOX:
+        return float(math.sqrt(param[0] ** 2 + param[1] ** 2 + param[2] ** 2))
+    return float(param[0] + param[1])
+
+
+@dataclass
+class Scene:
+    """One scene: per-body arrays (float64 until packed)."""
+
+    shape: list = field(default_factory=list)
+    motion: list = field(default_factory=list)
+    param: list = field(default_factory=list)
+    mass: list = field(default_factory=list)
+    friction: list = field(default_factory=list)
+    restitution: list = field(default_factory=list)
+    pose: list = field(default_factory=list)
+    arm: bool = False
+    arm_base: tuple = ARM_BASE
+    arm_theta0: np.ndarray | None = None
+
+    def add(self, shape, motion, param, mass, mu, e, pos, quat):
+        self.shape.append(shape)
+        self.motion.append(motion)
+        self.param.append(np.asarray(param, dtype=np.float64))
+        self.mass.append(mass)
+        self.friction.append(mu)
+        self.restitution.append(e)
+        self.pose.append(np.concatenate([np.asarray(pos, np.float64), np.asarray(quat, np.float64)]))
+
+    @property
+    def n(self):
+        return len(self.shape)
+
+
+def _static_clear(p, R, statics) -> bool:
+    """Bounding sphere (p, R) clear of every static yawed box."""
+    for (c, h, yaw) in statics:
+        d = p - c
+        cs, sn = math.cos(yaw), math.sin(yaw)
+        lx = cs * d[0] + sn * d[1]
+        ly = -sn * d[0] + cs * d[1]
+        lz = d[2]
+        qx = min(max(lx, -h[0]), h[0])
+        qy = min(max(ly, -h[1]), h[1])
+        qz = min(max(lz, -h[2]), h[2])
+        if (lx - qx) ** 2 + (ly - qy) ** 2 + (lz - qz) ** 2 < R * R:
+            return False
+    return True
+
+
+def _place(st, R, lo, hi, placed, statics=(), keepout=None, tries=4000):
+    """Rejection-sample a centre in the box [lo, hi] whose bounding sphere of
+    radius R overlaps no placed sphere, no static box and no keep-out sphere."""
+    for _ in range(tries):
+        p = lo + (hi - lo) * st.take(3)
+        ok = True
+        if placed:
+            P = np.asarray([q[0] for q in placed])
+            Rr = np.asarray([q[1] for q in placed])
+            if np.any(np.sum((P - p) ** 2, axis=1) < (Rr + R) ** 2):
+                ok = False
+        if ok and keepout is not None:
+            kc, kr = keepout
+            if np.sum((p - kc) ** 2) < (kr + R) ** 2:
+                ok = False
+        if ok and statics and not _static_clear(p, R, statics):
+            ok = False
+        if ok:
+            return p
+    raise RuntimeError("scene generator could not place a body without overlap")
+
+
+def drop_scene(seed: int, n_spheres: int = 32, n_boxes: int = 32, size=(0.05, 0.15),
+               mass=(0.1, 2.0), friction=0.5, edge: float | None = None) -> Scene:
+    """Spheres and boxes dropped from uniform positions in a cube onto the
+    ground: x, y in [-L/2, L/2], z in [0.2, 0.2 + L], L = 2 m * (n/64)^(1/3)
+    unless given; uniform orientation; zero velocity; restitution 0."""
+    st = _Stream(stream_key(seed, 1))
+    n = n_spheres + n_boxes
+    L = edge if edge is not None else 2.0 * (n / 64.0) ** (1.0 / 3.0)
+    kinds = np.array([SPHERE] * n_spheres + [BOX] * n_boxes)
+    order = np.argsort(st.take(n), kind="stable")
+    kinds = kinds[order]
+    sc = Scene()
+    placed = []
+    lo = np.array([-0.5 * L, -0.5 * L, 0.2])
+    hi = np.array([0.5 * L, 0.5 * L, 0.2 + L])
+    for k in kinds:
+        if k == SPHERE:
+            param = [st.uniform(*size), 0.0, 0.0]
+        else:
+            param = list(st.uniform(size[0], size[1], 3))
+        m = st.uniform(*mass)
+        R = bounding_radius(int(k), param)
+        p = _place(st, R, lo, hi, placed)
+        placed.append((p, R))
+        q = _random_quat(st)
+        sc.add(int(k), DYNAMIC, param, m, friction, 0.0, p, q)
+    return sc
+
+
+def clutter_scene(seed: int, n_static: int = 20, n_each: int = 36, size=(0.03, 0.30),
+                  cap_radius=(0.03, 0.15), mass=(0.05, 3.0), friction=(0.3, 0.8),
+                  arm: bool = True) -> Scene:
+    """Rearrangement clutter: static boxes on a 4 m x 4 m floor (a quarter of
+    them floating shelves), dynamic spheres/boxes/capsules dropped above, and
+    a kinematic 7-link capsule arm based at (0, 0, 0.8) m."""
+    st = _Stream(stream_key(seed, 2))
+    sc = Scene()
+    statics = []
+    for i in range(n_static):
+        hx, hy = st.uniform(0.15, 1.0), st.uniform(0.15, 1.0)
+        shelf = st.take(1)[0] < 0.25
+        if shelf:
+            hz = st.uniform(0.01, 0.05)
+            z = st.uniform(0.5, 1.5)
+        else:
+            hz = st.uniform(0.15, 1.0)
+            z = hz
+        yaw = st.uniform(0.0, 2.0 * math.pi)
+        rad = math.hypot(hx, hy)
+        for _ in range(4000):
+            x, y = st.uniform(-2.0, 2.0), st.uniform(-2.0, 2.0)
+            if math.hypot(x, y) - rad >= 0.8:
+                break
+        else:
+            raise RuntimeError("could not place static box")
+        c = np.array([x, y, z])
+        statics.append((c, np.array([hx, hy, hz]), yaw))
+        sc.add(BOX, STATIC, [hx, hy, hz], 0.0, st.uniform(*friction), 0.0, c, _yaw_quat(yaw))
+    reach = sum(ARM_LINK_LENGTH) + ARM_RADIUS
+    keepout = (np.array(ARM_BASE), reach) if arm else None
+    kinds = np.array([SPHERE] * n_each + [BOX] * n_each + [CAPSULE] * n_each)
+    kinds = kinds[np.argsort(st.take(len(kinds)), kind="stable")]
+    placed = []
+    lo = np.array([-2.0, -2.0, 0.2])
+    hi = np.array([2.0, 2.0, 4.2])
+    for k in kinds:
+        if k == SPHERE:
+            param = [st.uniform(*size), 0.0, 0.0]
+        elif k == BOX:
+            param = list(st.uniform(size[0], size[1], 3))
+        else:
+            param = [st.uniform(*cap_radius), st.uniform(*size), 0.0]
+        m = st.uniform(*mass)
+        mu = st.uniform(*friction)
+        R = bounding_radius(int(k), param)
+        p = _place(st, R, lo, hi, placed, statics, keepout)
+        placed.append((p, R))
+        sc.add(int(k), DYNAMIC, param, m, mu, 0.0, p, _random_quat(st))
+    if arm:
+        sc.arm = True
+        sc.arm_theta0 = st.uniform(-0.5, 0.5, ARM_LINKS)
+        for L in ARM_LINK_LENGTH:
+            # pose is a placeholder: arm link poses follow from joint angles
+            sc.add(CAPSULE, KINEMATIC, [ARM_RADIUS, 0.5 * L, 0.0], 0.0, 0.5, 0.0,
+                   ARM_BASE, (1.0, 0.0, 0.0, 0.0))
+    return sc
+
+
+def log_uniform_counts(seed: int, n_scenes: int, lo: int, hi: int) -> np.ndarray:
+    u = uniforms(stream_key(seed, 3), n_scenes)
+    return np.rint(np.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))).astype(np.int64)
+
+
+@dataclass
+class Batch:
+    """Packed batch of scenes (structure of arrays, bodies concatenated)."""
+
+    body_offset: np.ndarray   # int32 [S+1]
+    shape: np.ndarray         # uint8 [N]
+    motion: np.ndarray        # uint8 [N]
+    param: np.ndarray         # float32 [N,3]
+    mass: np.ndarray          # float32 [N]
+    friction: np.ndarray      # float32 [N]
+    restitution: np.ndarray   # float32 [N]
+    pose: np.ndarray          # float32 [N,7]  x y z qw qx qy qz
+    vel: np.ndarray           # float32 [N,6]  v, omega (world)
+    arm: bool
+    arm_base: np.ndarray      # float32 [S,3]
+    arm_theta: np.ndarray     # float32 [S,7]
+
+    @property
+    def n_scenes(self):
+        return len(self.body_offset) - 1
+
+    @property
+    def n_bodies(self):
+        return int(self.body_offset[-1])
+
+    def counts(self):
+        return np.diff(self.body_offset)
+
+
+def pack(scenes: list[Scene]) -> Batch:
+    if not scenes:
+        raise ValueError("empty batch")
+    arm = scenes[0].arm
+    if any(s.arm != arm for s in scenes):
+        raise ValueError("all scenes of a batch must agree on the arm")
+    off = np.zeros(len(scenes) + 1, dtype=np.int32)
+    off[1:] = np.cumsum([s.n for s in scenes])
+    cat = lambda a, dt: np.concatenate([np.asarray(getattr(s, a), dtype=dt).reshape(s.n, -1)
+                                        for s in scenes]).astype(dt)
+    pose = cat("pose", np.float64)
+    q = pose[:, 3:7]
+    pose[:, 3:7] = q / np.linalg.norm(q, axis=1, keepdims=True)
+    S = len(scenes)
+    return Batch(
+        body_offset=off,
+        shape=cat("shape", np.uint8).reshape(-1),
+        motion=cat("motion", np.uint8).reshape(-1),
+        param=cat("param", np.float64).astype(np.float32),
+        mass=cat("mass", np.float64).reshape(-1).astype(np.float32),
+        friction=cat("friction", np.float64).reshape(-1).astype(np.float32),
+        restitution=cat("restitution", np.float64).reshape(-1).astype(np.float32),
+        pose=pose.astype(np.float32),
+        vel=np.zeros((off[-1], 6), np.float32),
+        arm=arm,
+        arm_base=np.tile(np.asarray(ARM_BASE, np.float32), (S, 1)),
+        arm_theta=(np.stack([s.arm_theta0 for s in scenes]).astype(np.float32) if arm
+                   else np.zeros((S, ARM_LINKS), np.float32)),
+    )
+
+
+def batch_drop(n_scenes: int = 1, seed0: int = 0, **kw) -> Batch:
+    """Small drop case: per scene 32 spheres + 32 boxes, sizes U[0.05, 0.15] m,
+    mass U[0.1, 2] kg, friction 0.5, restitution 0, 2 m cube."""
+    return pack([drop_scene(seed0 + s, **kw) for s in range(n_scenes)])
+
+
+def batch_clutter(n_scenes: int = 1024, seed0: int = 10000, arm: bool = True, **kw) -> Batch:
+    """Clutter case: per scene 20 static boxes + 108 dynamic + 7 arm links."""
+    return pack([clutter_scene(seed0 + s, arm=arm, **kw) for s in range(n_scenes)])
+
+
+def batch_uneven(n_scenes: int = 4096, seed0: int = 20000, lo: int = 16, hi: int = 512) -> Batch:
+    """Uneven batch: dynamic counts log-uniform in [lo, hi], drop-case shapes."""
+    counts = log_uniform_counts(seed0, n_scenes, lo, hi)
+    scenes = []
+    for s, n in enumerate(counts):
+        ns = int(n) // 2
+        scenes.append(drop_scene(seed0 + 1 + s, n_spheres=ns, n_boxes=int(n) - ns))
+    return pack(scenes)
+
+
+def arm_actions(seed: int, n_scenes: int, step: int) -> np.ndarray:
+    """Joint velocities U[-1, 1] rad/s for one step, keyed (seed, scene, step, joint)."""
+    out = np.empty((n_scenes, ARM_LINKS), np.float64)
+    for s in range(n_scenes):
+        out[s] = uniforms(stream_key(seed, 4, s, step), ARM_LINKS)
+    return (2.0 * out - 1.0).astype(np.float32)
+
+
+def arm_actions_block(seed: int, n_scenes: int, step0: int, n_steps: int) -> np.ndarray:
+    """[n_steps, S, 7] joint velocities; same values as ``arm_actions``."""
+    return np.stack([arm_actions(seed, n_scenes, step0 + t) for t in range(n_steps)])
