@@ -1,0 +1,179 @@
+/*
+ * rbsim.h -- C ABI of the MI355X batched rigid-body step (librbsim.so).
+ *
+ * The library advances a batch of independent rearrangement scenes by one
+ * physics step per call: the physics-engine transition (s_t, a_t) -> s_{t+1}
+ * of the paper's simulator definition (Habitat 2.0, Sec. 2 "What is a
+ * simulator?"), for rigid objects with mass, friction and restitution and
+ * simplified collision proxies (Sec. 3, asset creation; Sec. 4.3 "simplify
+ * and reuse"), base-constrained parts treated as static (Sec. 4.1) and an
+ * arm moved kinematically by the agent's action (Sec. 5, 7-DoF arm), at
+ * 1/120 s per step (Sec. 4.4).  The per-step arm collision force in newtons
+ * is the quantity the Pick task consumes (Sec. 5; appendix, Pick reward).
+ * The paper gives no engine algorithm; the step is sort-and-sweep
+ * broadphase, sphere/box/capsule narrowphase, graph-coloured projected
+ * Gauss-Seidel (or Jacobi) contact and friction impulses, and semi-implicit
+ * Euler integration, all in hand-written HIP for gfx950.
+ *
+ * Memory.  The caller owns every buffer.  All device memory the library
+ * touches lives in one caller-allocated workspace (sim_workspace_bytes);
+ * the library never allocates device memory.  Host arrays in the
+ * descriptor are read during sim_create only.
+ *
+ * Streams.  All work is enqueued on the stream given at creation (may be
+ * changed with sim_set_stream).  Only sim_create synchronises that stream.
+ *
+ * Errors.  Functions return SIM_OK (0) or a negative code and leave the
+ * simulation unchanged; sim_last_error() returns a thread-local message.
+ * Per-scene soft faults are not return codes but bits in the stats flags
+ * (SIM_FLAG_*); a scene with NONFINITE or CAPACITY is undefined until reset.
+ *
+ * Threading.  One handle per host thread; handles are independent.
+ */
+#ifndef RBSIM_H
+#define RBSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_ABI_VERSION 1
+
+enum { SIM_OK = 0, SIM_EINVAL = -1, SIM_EDEVICE = -2, SIM_EWORKSPACE = -3, SIM_EABI = -4, SIM_ECAPACITY = -5 };
+enum { SIM_SPHERE = 0, SIM_BOX = 1, SIM_CAPSULE = 2 };
+enum { SIM_DYNAMIC = 0, SIM_STATIC = 1, SIM_KINEMATIC = 2 };
+enum { SIM_COLD = 0, SIM_PREV = 1, SIM_LEARNED = 2 };
+enum { SIM_PGS = 0, SIM_JACOBI = 1 };
+enum { SIM_FLAG_NONFINITE = 1, SIM_FLAG_CAPACITY = 2, SIM_FLAG_NOT_CONVERGED = 4, SIM_FLAG_FELLBACK = 8 };
+
+/* Batch descriptor.  N = body_offset[num_scenes] bodies in total; scene s
+ * owns bodies [body_offset[s], body_offset[s+1]).  All h_* pointers are
+ * host memory read during sim_create. */
+typedef struct sim_batch_desc {
+    int abi_version;             /* SIM_ABI_VERSION */
+    int num_scenes;              /* S >= 1 */
+    const int32_t *h_body_offset;/* [S+1], non-decreasing, body_offset[0] = 0 */
+    const uint8_t *h_shape;      /* [N] SIM_SPHERE / SIM_BOX / SIM_CAPSULE */
+    const uint8_t *h_motion;     /* [N] SIM_DYNAMIC / SIM_STATIC / SIM_KINEMATIC */
+    const float *h_param;        /* [N*3] sphere (r,-,-); box half-extents; capsule (r, half-length, -), m */
+    const float *h_mass;         /* [N] kg, > 0 for dynamic bodies */
+    const float *h_friction;     /* [N] */
+    const float *h_restitution;  /* [N] */
+    const float *h_pose;         /* [N*7] x y z (m), quaternion w x y z (body to world) */
+    const float *h_vel;          /* [N*6] linear (m/s), angular (rad/s, world frame) */
+    int arm;                     /* 1: the last 7 bodies of every scene are the arm links
+                                    (kinematic capsules); their poses follow the joint angles */
+    const float *h_arm_base;     /* [S*3] arm base position (m), or NULL when arm = 0 */
+    const float *h_arm_theta;    /* [S*7] initial joint angles (rad), or NULL when arm = 0 */
+    float link_len[7];           /* arm link lengths (m) */
+    float arm_radius;            /* arm capsule radius (m) */
+    float gravity[3];            /* m/s^2, z up */
+    float margin;                /* AABB fattening and contact keep distance (m) */
+    float baumgarte;             /* penetration correction factor per step */
+    float slop;                  /* allowed penetration (m) */
+    float rest_thresh;           /* approach speed above which restitution applies (m/s) */
+    float ground_friction;       /* friction of the plane z = 0 */
+    float ground_restitution;
+    int max_pairs;               /* per-scene capacity of broadphase pairs */
+    int max_contacts;            /* per-scene capacity of contacts */
+    int solver;                  /* SIM_PGS or SIM_JACOBI */
+    int warm_start;              /* SIM_COLD, SIM_PREV or SIM_LEARNED */
+    float tolerance;             /* > 0: stop sweeps once the residual (m/s) <= tolerance;
+                                    0: always run the requested sweeps */
+    int threads;                 /* threads per scene workgroup: 64, 128, 192 or 256 (0: 128) */
+    void *stream;                /* hipStream_t for all work; NULL = default stream */
+} sim_batch_desc;
+
+typedef struct sim_handle sim_handle;
+
+/* Device pointers of the simulation state (structure of arrays, plane
+ * stride N unless stated).  Valid until sim_destroy; the caller may read
+ * and write them between steps on the handle's stream. */
+typedef struct sim_state_view {
+    long n_bodies;        /* N */
+    float *pose;          /* [7][N]: x, y, z, qw, qx, qy, qz */
+    float *vel;           /* [6][N]: vx, vy, vz, wx, wy, wz */
+    float *theta;         /* [S][7] arm joint angles, or NULL */
+    int cache_cap;        /* per-scene contact capacity (= max_contacts) */
+    int32_t *cache_count; /* [S] contacts stored for the next step's warm start */
+    uint32_t *cache_key;  /* [S][cache_cap] sorted contact keys */
+    float *cache_lam;     /* [4][S*cache_cap]: normal impulse, world friction impulse x y z (N s) */
+} sim_state_view;
+
+/* Device pointers of the last step's contacts.  Contact q of scene s is at
+ * index s*max_contacts + q, q < count[s]; arrays with a leading [k] are
+ * planes of stride S*max_contacts.  Keys: (a << 20) | (b << 8) | feature,
+ * b = 0xFFF for the ground; pairs: (a << 16) | b, b = 0xFFFF for the ground.
+ * Normals point from body b to body a.  Filled only when export is on
+ * (sim_set_export), except count and key which are always written. */
+typedef struct sim_contact_view {
+    int max_contacts, max_pairs;
+    const int32_t *count;     /* [S] */
+    const uint32_t *key;      /* [S*max_contacts] canonical (sorted) order */
+    const float *normal;      /* [3][S*max_contacts] */
+    const float *point;       /* [3][S*max_contacts] */
+    const float *phi;         /* [S*max_contacts] signed separation (m) */
+    const float *lambda;      /* [3][S*max_contacts] normal, tangent-1, tangent-2 impulses (N s) */
+    const int32_t *colour;    /* [S*max_contacts] */
+    const float *features;    /* [16][S*max_contacts] warm-start features */
+    const int32_t *n_pairs;   /* [S] */
+    const uint32_t *pair_key; /* [S*max_pairs] */
+} sim_contact_view;
+
+/* Per-scene statistics of the last step, device arrays of length S. */
+typedef struct sim_stats_view {
+    const int32_t *pairs, *contacts, *colours, *sweeps, *flags;
+    const float *residual;    /* last sweep's max |dlambda| * k (m/s) */
+    const float *arm_force;   /* sum over arm contacts of |impulse| / dt (N) */
+} sim_stats_view;
+
+/* Bytes of device workspace the descriptor needs (0 on a bad descriptor). */
+size_t sim_workspace_bytes(const sim_batch_desc *desc);
+
+/* Validates the descriptor, lays out the workspace (>= sim_workspace_bytes,
+ * 256-byte aligned device memory owned by the caller), uploads the initial
+ * state on desc->stream and synchronises it.  *out receives the handle. */
+int sim_create(const sim_batch_desc *desc, void *d_workspace, size_t workspace_bytes, sim_handle **out);
+
+/* One step of every scene: d_actions [S*7] arm joint velocities (rad/s),
+ * device memory, or NULL (zero); dt > 0 seconds; iters >= 1 sweeps (the cap
+ * when a tolerance is set).  Asynchronous on the handle's stream. */
+int sim_step(sim_handle *h, const float *d_actions, float dt, int iters);
+
+/* Contact and pair views of the last step. */
+int sim_contacts(const sim_handle *h, sim_contact_view *out);
+
+/* State and statistics views. */
+int sim_state(const sim_handle *h, sim_state_view *out);
+int sim_stats(const sim_handle *h, sim_stats_view *out);
+
+/* Export of normals, points, phi, impulses, colours, features and pairs on (1) or off (0). */
+int sim_set_export(sim_handle *h, int on);
+
+/* Change the solver settings used by later steps. */
+int sim_set_solver(sim_handle *h, int solver, int warm_start, float tolerance);
+
+/* Learned warm start weights, device memory read during every later step
+ * in SIM_LEARNED mode: bf16 w1 [64*16], w2 [64*64], w3 [3*64] (row = output),
+ * fp32 b1 [64], b2 [64], b3 [3], feature mean [16] and std [16].  The
+ * pointers must stay valid while used. */
+int sim_set_mlp(sim_handle *h, const uint16_t *d_w1, const uint16_t *d_w2, const uint16_t *d_w3,
+                const float *d_b1, const float *d_b2, const float *d_b3, const float *d_mean, const float *d_std);
+
+/* Masked reset: for every scene s with d_mask[s] != 0, copy its bodies'
+ * pose [7][N] and velocity [6][N] from d_pose/d_vel (same layout as the
+ * state), its joint angles from d_theta [S*7] (if arm), and clear its
+ * contact cache.  Device pointers; asynchronous. */
+int sim_reset(sim_handle *h, const uint8_t *d_mask, const float *d_pose, const float *d_vel, const float *d_theta);
+
+int sim_set_stream(sim_handle *h, void *stream);
+void sim_destroy(sim_handle *h);
+const char *sim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

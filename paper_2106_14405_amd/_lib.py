@@ -1,0 +1,106 @@
+"""ctypes declarations of the C ABI in include/rbsim.h (librbsim.so).
+
+Argument marshalling only; every step of the physics runs in the HIP
+library.  Importing this module raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbsim.so")
+
+SIM_ABI_VERSION = 1
+SIM_OK, SIM_EINVAL, SIM_EDEVICE, SIM_EWORKSPACE, SIM_EABI, SIM_ECAPACITY = 0, -1, -2, -3, -4, -5
+SPHERE, BOX, CAPSULE = 0, 1, 2
+DYNAMIC, STATIC, KINEMATIC = 0, 1, 2
+COLD, PREV, LEARNED = 0, 1, 2
+PGS, JACOBI = 0, 1
+FLAG_NONFINITE, FLAG_CAPACITY, FLAG_NOT_CONVERGED, FLAG_FELLBACK = 1, 2, 4, 8
+
+_P = C.POINTER
+_f = C.c_float
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int), ("num_scenes", C.c_int),
+        ("h_body_offset", _P(C.c_int32)), ("h_shape", _P(C.c_uint8)), ("h_motion", _P(C.c_uint8)),
+        ("h_param", _P(_f)), ("h_mass", _P(_f)), ("h_friction", _P(_f)), ("h_restitution", _P(_f)),
+        ("h_pose", _P(_f)), ("h_vel", _P(_f)),
+        ("arm", C.c_int), ("h_arm_base", _P(_f)), ("h_arm_theta", _P(_f)),
+        ("link_len", _f * 7), ("arm_radius", _f),
+        ("gravity", _f * 3), ("margin", _f), ("baumgarte", _f), ("slop", _f), ("rest_thresh", _f),
+        ("ground_friction", _f), ("ground_restitution", _f),
+        ("max_pairs", C.c_int), ("max_contacts", C.c_int),
+        ("solver", C.c_int), ("warm_start", C.c_int), ("tolerance", _f), ("threads", C.c_int),
+        ("stream", C.c_void_p),
+    ]
+
+
+class StateView(C.Structure):
+    _fields_ = [("n_bodies", C.c_long), ("pose", C.c_void_p), ("vel", C.c_void_p), ("theta", C.c_void_p),
+                ("cache_cap", C.c_int), ("cache_count", C.c_void_p), ("cache_key", C.c_void_p),
+                ("cache_lam", C.c_void_p)]
+
+
+class ContactView(C.Structure):
+    _fields_ = [("max_contacts", C.c_int), ("max_pairs", C.c_int), ("count", C.c_void_p), ("key", C.c_void_p),
+                ("normal", C.c_void_p), ("point", C.c_void_p), ("phi", C.c_void_p), ("lambda_", C.c_void_p),
+                ("colour", C.c_void_p), ("features", C.c_void_p), ("n_pairs", C.c_void_p),
+                ("pair_key", C.c_void_p)]
+
+
+class StatsView(C.Structure):
+    _fields_ = [("pairs", C.c_void_p), ("contacts", C.c_void_p), ("colours", C.c_void_p), ("sweeps", C.c_void_p),
+                ("flags", C.c_void_p), ("residual", C.c_void_p), ("arm_force", C.c_void_p)]
+
+
+EXPORTED = ["sim_workspace_bytes", "sim_create", "sim_step", "sim_contacts", "sim_state", "sim_stats",
+            "sim_set_export", "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_stream", "sim_destroy",
+            "sim_last_error"]
+
+_lib = None
+
+
+def load():
+    """Load librbsim.so (built in-tree).  Raises when it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(LIB_PATH)
+    L.sim_workspace_bytes.argtypes = [_P(BatchDesc)]
+    L.sim_workspace_bytes.restype = C.c_size_t
+    L.sim_create.argtypes = [_P(BatchDesc), C.c_void_p, C.c_size_t, _P(C.c_void_p)]
+    L.sim_step.argtypes = [C.c_void_p, C.c_void_p, _f, C.c_int]
+    L.sim_contacts.argtypes = [C.c_void_p, _P(ContactView)]
+    L.sim_state.argtypes = [C.c_void_p, _P(StateView)]
+    L.sim_stats.argtypes = [C.c_void_p, _P(StatsView)]
+    L.sim_set_export.argtypes = [C.c_void_p, C.c_int]
+    L.sim_set_solver.argtypes = [C.c_void_p, C.c_int, C.c_int, _f]
+    L.sim_set_mlp.argtypes = [C.c_void_p] + [C.c_void_p] * 8
+    L.sim_reset.argtypes = [C.c_void_p] + [C.c_void_p] * 4
+    L.sim_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+    L.sim_destroy.argtypes = [C.c_void_p]
+    L.sim_destroy.restype = None
+    L.sim_last_error.argtypes = []
+    L.sim_last_error.restype = C.c_char_p
+    for name in ("sim_create", "sim_step", "sim_contacts", "sim_state", "sim_stats", "sim_set_export",
+                 "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_stream"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class SimError(RuntimeError):
+    pass
+
+
+def check(rc: int, what: str):
+    if rc != SIM_OK:
+        msg = load().sim_last_error().decode(errors="replace")
+        raise SimError(f"{what} failed ({rc}): {msg}")

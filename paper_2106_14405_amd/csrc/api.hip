@@ -1,0 +1,501 @@
+// api.hip -- host side of the C ABI declared in include/rbsim.h.
+//
+// Validates the batch descriptor, lays the whole simulation out in one
+// caller-owned device workspace (structure-of-arrays planes, 256-byte
+// aligned), uploads the initial state, and launches the step kernel with one
+// workgroup per scene, largest scenes first.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/rbsim.h"
+#include "sim_internal.h"
+
+extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L, int threads, int grid,
+                               hipStream_t stream);
+extern "C" int rbs_set_step_lds_limit(int bytes);
+extern "C" int rbs_launch_arm_pose(const rbs::StepParams* P, const uint8_t* mask, hipStream_t stream);
+extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, const float* pool_pose,
+                                const float* pool_vel, const float* pool_theta, int32_t* count_a, int32_t* count_b,
+                                hipStream_t stream);
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+struct Layout {
+  size_t off_body_offset, off_shape, off_motion, off_prm, off_inv_mass, off_inv_inertia, off_friction,
+      off_restitution, off_pose, off_vel, off_theta, off_arm_base, off_scene_list;
+  size_t off_ckey[2], off_clam[2], off_ccount[2];
+  size_t off_x_pair, off_x_npairs, off_x_normal, off_x_point, off_x_phi, off_x_lambda, off_x_colour, off_x_feat;
+  size_t off_st[7];
+  size_t total;
+};
+
+size_t align256(size_t x) { return (x + 255u) & ~size_t(255u); }
+
+Layout make_layout(long S, long N, long PM, long CM) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+  L.off_body_offset = take(4 * (S + 1));
+  L.off_shape = take(N);
+  L.off_motion = take(N);
+  L.off_prm = take(4 * 3 * N);
+  L.off_inv_mass = take(4 * N);
+  L.off_inv_inertia = take(4 * 3 * N);
+  L.off_friction = take(4 * N);
+  L.off_restitution = take(4 * N);
+  L.off_pose = take(4 * 7 * N);
+  L.off_vel = take(4 * 6 * N);
+  L.off_theta = take(4 * 7 * S);
+  L.off_arm_base = take(4 * 3 * S);
+  L.off_scene_list = take(4 * S);
+  for (int k = 0; k < 2; k++) {
+    L.off_ckey[k] = take(4 * S * CM);
+    L.off_clam[k] = take(4 * 4 * S * CM);
+    L.off_ccount[k] = take(4 * S);
+  }
+  L.off_x_pair = take(4 * S * PM);
+  L.off_x_npairs = 0;  // stats pairs array doubles as the pair count
+  L.off_x_normal = take(4 * 3 * S * CM);
+  L.off_x_point = take(4 * 3 * S * CM);
+  L.off_x_phi = take(4 * S * CM);
+  L.off_x_lambda = take(4 * 3 * S * CM);
+  L.off_x_colour = take(4 * S * CM);
+  L.off_x_feat = take(4 * 16 * S * CM);
+  for (int k = 0; k < 7; k++) L.off_st[k] = take(4 * S);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct sim_handle {
+  int S;
+  long N;
+  int NB, PM, CM;
+  int threads;
+  hipStream_t stream;
+  char* ws;
+  Layout lay;
+  int parity;  // cache buffer the next step reads
+  int export_on;
+  int arm;
+  float link_len[7];
+  float arm_radius;
+  float gravity[3], margin, baumgarte, slop, rest_thresh, ground_mu, ground_e;
+  int solver, warm;
+  float tol;
+  rbs::MlpParams mlp;
+  bool mlp_set;
+  int lds_limit;
+};
+
+namespace {
+
+template <class T>
+T* at(sim_handle* h, size_t off) {
+  return reinterpret_cast<T*>(h->ws + off);
+}
+
+rbs::StepParams params(sim_handle* h) {
+  rbs::StepParams P;
+  memset(&P, 0, sizeof(P));
+  const Layout& L = h->lay;
+  P.num_scenes = h->S;
+  P.n_bodies = h->N;
+  P.scene_cm = (long)h->S * h->CM;
+  P.scene_pm = (long)h->S * h->PM;
+  P.NB = h->NB;
+  P.PM = h->PM;
+  P.CM = h->CM;
+  P.body_offset = at<int32_t>(h, L.off_body_offset);
+  P.shape = at<uint8_t>(h, L.off_shape);
+  P.motion = at<uint8_t>(h, L.off_motion);
+  P.prm = at<float>(h, L.off_prm);
+  P.inv_mass = at<float>(h, L.off_inv_mass);
+  P.inv_inertia = at<float>(h, L.off_inv_inertia);
+  P.friction = at<float>(h, L.off_friction);
+  P.restitution = at<float>(h, L.off_restitution);
+  P.pose = at<float>(h, L.off_pose);
+  P.vel = at<float>(h, L.off_vel);
+  P.arm = h->arm;
+  P.theta = at<float>(h, L.off_theta);
+  P.arm_base = at<float>(h, L.off_arm_base);
+  for (int k = 0; k < 7; k++) P.link_len[k] = h->link_len[k];
+  P.arm_radius = h->arm_radius;
+  int rd = h->parity, wr = 1 - h->parity;
+  P.prev_key = at<uint32_t>(h, L.off_ckey[rd]);
+  P.prev_lam = at<float>(h, L.off_clam[rd]);
+  P.prev_count = at<int32_t>(h, L.off_ccount[rd]);
+  P.cur_key = at<uint32_t>(h, L.off_ckey[wr]);
+  P.cur_lam = at<float>(h, L.off_clam[wr]);
+  P.cur_count = at<int32_t>(h, L.off_ccount[wr]);
+  P.export_on = h->export_on;
+  P.x_pair = at<uint32_t>(h, L.off_x_pair);
+  P.x_normal = at<float>(h, L.off_x_normal);
+  P.x_point = at<float>(h, L.off_x_point);
+  P.x_phi = at<float>(h, L.off_x_phi);
+  P.x_lambda = at<float>(h, L.off_x_lambda);
+  P.x_colour = at<int32_t>(h, L.off_x_colour);
+  P.x_feat = at<float>(h, L.off_x_feat);
+  P.st_pairs = at<int32_t>(h, L.off_st[0]);
+  P.st_contacts = at<int32_t>(h, L.off_st[1]);
+  P.st_colours = at<int32_t>(h, L.off_st[2]);
+  P.st_sweeps = at<int32_t>(h, L.off_st[3]);
+  P.st_flags = at<int32_t>(h, L.off_st[4]);
+  P.st_residual = at<float>(h, L.off_st[5]);
+  P.st_arm_force = at<float>(h, L.off_st[6]);
+  P.gx = h->gravity[0];
+  P.gy = h->gravity[1];
+  P.gz = h->gravity[2];
+  P.margin = h->margin;
+  P.baumgarte = h->baumgarte;
+  P.slop = h->slop;
+  P.rest_thresh = h->rest_thresh;
+  P.ground_mu = h->ground_mu;
+  P.ground_e = h->ground_e;
+  P.tol = h->tol;
+  P.warm = h->warm;
+  P.solver = h->solver;
+  P.mlp = h->mlp;
+  P.scene_list = at<int32_t>(h, L.off_scene_list);
+  return P;
+}
+
+struct Caps {
+  int NB;
+  long N;
+  bool ok;
+};
+
+int validate(const sim_batch_desc* d, Caps* caps) {
+  if (!d) return fail(SIM_EINVAL, "descriptor is NULL");
+  if (d->abi_version != SIM_ABI_VERSION) return fail(SIM_EABI, "abi_version mismatch");
+  if (d->num_scenes < 1) return fail(SIM_EINVAL, "num_scenes must be >= 1");
+  if (!d->h_body_offset || !d->h_shape || !d->h_motion || !d->h_param || !d->h_mass || !d->h_friction ||
+      !d->h_restitution || !d->h_pose || !d->h_vel)
+    return fail(SIM_EINVAL, "a required host array is NULL");
+  if (d->h_body_offset[0] != 0) return fail(SIM_EINVAL, "body_offset[0] must be 0");
+  int NB = 0;
+  for (int s = 0; s < d->num_scenes; s++) {
+    int n = d->h_body_offset[s + 1] - d->h_body_offset[s];
+    if (n < 0) return fail(SIM_EINVAL, "body_offset must be non-decreasing");
+    if (n > rbs::kMaxBodiesPerScene) return fail(SIM_ECAPACITY, "a scene exceeds 1024 bodies");
+    if (d->arm && n < 7) return fail(SIM_EINVAL, "arm scenes need at least 7 bodies");
+    NB = std::max(NB, n);
+  }
+  long N = d->h_body_offset[d->num_scenes];
+  for (long i = 0; i < N; i++) {
+    if (d->h_shape[i] > SIM_CAPSULE) return fail(SIM_EINVAL, "bad shape type");
+    if (d->h_motion[i] > SIM_KINEMATIC) return fail(SIM_EINVAL, "bad motion type");
+    const float* p = d->h_param + 3 * i;
+    int sh = d->h_shape[i];
+    int need = sh == SIM_SPHERE ? 1 : (sh == SIM_BOX ? 3 : 2);
+    for (int k = 0; k < need; k++)
+      if (!(p[k] > 0.f) || !std::isfinite(p[k])) return fail(SIM_EINVAL, "shape parameters must be positive");
+    if (d->h_motion[i] == SIM_DYNAMIC && !(d->h_mass[i] > 0.f && std::isfinite(d->h_mass[i])))
+      return fail(SIM_EINVAL, "dynamic bodies need a positive mass");
+  }
+  if (d->arm) {
+    if (!d->h_arm_base || !d->h_arm_theta) return fail(SIM_EINVAL, "arm needs base and theta arrays");
+    for (int s = 0; s < d->num_scenes; s++)
+      for (int k = 0; k < 7; k++) {
+        long i = d->h_body_offset[s + 1] - 7 + k;
+        if (d->h_shape[i] != SIM_CAPSULE || d->h_motion[i] != SIM_KINEMATIC)
+          return fail(SIM_EINVAL, "the last 7 bodies of an arm scene must be kinematic capsules");
+      }
+  }
+  if (d->max_pairs < 1 || d->max_contacts < 1) return fail(SIM_EINVAL, "capacities must be >= 1");
+  if (d->max_pairs > (1 << 20) || d->max_contacts > (1 << 20)) return fail(SIM_EINVAL, "capacity too large");
+  int T = d->threads ? d->threads : 128;
+  if (T != 64 && T != 128 && T != 192 && T != 256) return fail(SIM_EINVAL, "threads must be 64, 128, 192 or 256");
+  if (d->solver != SIM_PGS && d->solver != SIM_JACOBI) return fail(SIM_EINVAL, "bad solver");
+  if (d->warm_start < SIM_COLD || d->warm_start > SIM_LEARNED) return fail(SIM_EINVAL, "bad warm start");
+  if (!(d->tolerance >= 0.f)) return fail(SIM_EINVAL, "tolerance must be >= 0");
+  if (!(d->margin >= 0.f) || !(d->slop >= 0.f) || !(d->baumgarte >= 0.f)) return fail(SIM_EINVAL, "bad constants");
+  caps->NB = NB;
+  caps->N = N;
+  caps->ok = true;
+  return SIM_OK;
+}
+
+int lds_bytes(int NB, int PM, int CM, int T, int solver, int warm) {
+  rbs::LdsLayout L = rbs::lds_layout(NB, PM, CM, T / 64, solver, warm);
+  return L.total * 4;
+}
+
+int device_lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 65536;
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sim_workspace_bytes(const sim_batch_desc* d) {
+  Caps c;
+  if (validate(d, &c) != SIM_OK) return 0;
+  return make_layout(d->num_scenes, c.N, d->max_pairs, d->max_contacts).total;
+}
+
+int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_bytes, sim_handle** out) {
+  if (!out) return fail(SIM_EINVAL, "out is NULL");
+  *out = nullptr;
+  Caps c;
+  int rc = validate(d, &c);
+  if (rc != SIM_OK) return rc;
+  const int S = d->num_scenes;
+  const long N = c.N;
+  Layout lay = make_layout(S, N, d->max_pairs, d->max_contacts);
+  if (!d_workspace || workspace_bytes < lay.total) return fail(SIM_EWORKSPACE, "workspace too small");
+  if (((uintptr_t)d_workspace & 255u) != 0) return fail(SIM_EWORKSPACE, "workspace must be 256-byte aligned");
+  const int T = d->threads ? d->threads : 128;
+  int need = lds_bytes(c.NB, d->max_pairs, d->max_contacts, T, SIM_JACOBI, SIM_LEARNED);
+  int limit = device_lds_limit();
+  if (need > limit)
+    return fail(SIM_ECAPACITY, "per-scene working set (" + std::to_string(need) + " B) exceeds LDS (" +
+                                   std::to_string(limit) + " B); lower max_contacts/max_pairs");
+  if (rbs_set_step_lds_limit(limit) != 0) return fail(SIM_EDEVICE, "hipFuncSetAttribute failed");
+
+  sim_handle* h = new sim_handle();
+  h->S = S;
+  h->N = N;
+  h->NB = c.NB;
+  h->PM = d->max_pairs;
+  h->CM = d->max_contacts;
+  h->threads = T;
+  h->stream = (hipStream_t)d->stream;
+  h->ws = (char*)d_workspace;
+  h->lay = lay;
+  h->parity = 0;
+  h->export_on = 0;
+  h->arm = d->arm ? 1 : 0;
+  for (int k = 0; k < 7; k++) h->link_len[k] = d->link_len[k];
+  h->arm_radius = d->arm_radius;
+  for (int k = 0; k < 3; k++) h->gravity[k] = d->gravity[k];
+  h->margin = d->margin;
+  h->baumgarte = d->baumgarte;
+  h->slop = d->slop;
+  h->rest_thresh = d->rest_thresh;
+  h->ground_mu = d->ground_friction;
+  h->ground_e = d->ground_restitution;
+  h->solver = d->solver;
+  h->warm = d->warm_start;
+  h->tol = d->tolerance;
+  memset(&h->mlp, 0, sizeof(h->mlp));
+  h->mlp_set = false;
+  h->lds_limit = limit;
+
+  // host staging: structure-of-arrays planes
+  std::vector<float> prm(3 * N), inv_mass(N), inv_I(3 * N), pose(7 * N), vel(6 * N);
+  for (long i = 0; i < N; i++) {
+    for (int k = 0; k < 3; k++) prm[k * N + i] = d->h_param[3 * i + k];
+    for (int k = 0; k < 7; k++) pose[k * N + i] = d->h_pose[7 * i + k];
+    for (int k = 0; k < 6; k++) vel[k * N + i] = d->h_vel[6 * i + k];
+    if (d->h_motion[i] == SIM_DYNAMIC) {
+      double m = d->h_mass[i];
+      const float* p = d->h_param + 3 * i;
+      double I[3];
+      if (d->h_shape[i] == SIM_SPHERE) {
+        I[0] = I[1] = I[2] = 0.4 * m * (double)p[0] * p[0];
+      } else if (d->h_shape[i] == SIM_BOX) {
+        double x2 = (double)p[0] * p[0], y2 = (double)p[1] * p[1], z2 = (double)p[2] * p[2];
+        I[0] = m / 3.0 * (y2 + z2);
+        I[1] = m / 3.0 * (x2 + z2);
+        I[2] = m / 3.0 * (x2 + y2);
+      } else {
+        // solid capsule: cylinder (length 2h) + two hemispheres, mass by volume
+        double r = p[0], hh = p[1];
+        double vc = 2.0 * M_PI * r * r * hh, vs = 4.0 / 3.0 * M_PI * r * r * r;
+        double mc = m * vc / (vc + vs), ms = m - mc;
+        I[2] = mc * r * r / 2.0 + 0.4 * ms * r * r;
+        I[0] = I[1] = mc * (r * r / 4.0 + hh * hh / 3.0) + ms * (0.4 * r * r + hh * hh + 0.75 * hh * r);
+      }
+      inv_mass[i] = (float)(1.0 / m);
+      for (int k = 0; k < 3; k++) inv_I[k * N + i] = (float)(1.0 / I[k]);
+    } else {
+      inv_mass[i] = 0.f;
+      for (int k = 0; k < 3; k++) inv_I[k * N + i] = 0.f;
+    }
+  }
+  // largest scenes first: the tail of the grid holds the cheap scenes
+  std::vector<int32_t> order(S);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return d->h_body_offset[a + 1] - d->h_body_offset[a] > d->h_body_offset[b + 1] - d->h_body_offset[b];
+  });
+  std::vector<float> theta(7 * S, 0.f), base(3 * S, 0.f);
+  if (d->arm) {
+    for (int i = 0; i < 7 * S; i++) theta[i] = d->h_arm_theta[i];
+    for (int i = 0; i < 3 * S; i++) base[i] = d->h_arm_base[i];
+  }
+  hipStream_t st = h->stream;
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    return hipMemcpyAsync(h->ws + off, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws, 0, lay.total, st);
+  if (e == hipSuccess) e = up(lay.off_body_offset, d->h_body_offset, 4 * (S + 1));
+  if (e == hipSuccess) e = up(lay.off_shape, d->h_shape, N);
+  if (e == hipSuccess) e = up(lay.off_motion, d->h_motion, N);
+  if (e == hipSuccess) e = up(lay.off_prm, prm.data(), 4 * 3 * N);
+  if (e == hipSuccess) e = up(lay.off_inv_mass, inv_mass.data(), 4 * N);
+  if (e == hipSuccess) e = up(lay.off_inv_inertia, inv_I.data(), 4 * 3 * N);
+  if (e == hipSuccess) e = up(lay.off_friction, d->h_friction, 4 * N);
+  if (e == hipSuccess) e = up(lay.off_restitution, d->h_restitution, 4 * N);
+  if (e == hipSuccess) e = up(lay.off_pose, pose.data(), 4 * 7 * N);
+  if (e == hipSuccess) e = up(lay.off_vel, vel.data(), 4 * 6 * N);
+  if (e == hipSuccess) e = up(lay.off_theta, theta.data(), 4 * 7 * S);
+  if (e == hipSuccess) e = up(lay.off_arm_base, base.data(), 4 * 3 * S);
+  if (e == hipSuccess) e = up(lay.off_scene_list, order.data(), 4 * S);
+  if (e == hipSuccess && h->arm) {
+    rbs::StepParams P = params(h);
+    e = (hipError_t)rbs_launch_arm_pose(&P, nullptr, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(SIM_EDEVICE, std::string("upload failed: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return SIM_OK;
+}
+
+int sim_step(sim_handle* h, const float* d_actions, float dt, int iters) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (!(dt > 0.f) || !std::isfinite(dt)) return fail(SIM_EINVAL, "dt must be > 0");
+  if (iters < 1) return fail(SIM_EINVAL, "iters must be >= 1");
+  if (h->warm == SIM_LEARNED && !h->mlp_set) return fail(SIM_EINVAL, "learned warm start needs sim_set_mlp");
+  rbs::StepParams P = params(h);
+  P.actions = d_actions;
+  P.dt = dt;
+  P.iters = iters;
+  rbs::LdsLayout L = rbs::lds_layout(h->NB, h->PM, h->CM, h->threads / 64, h->solver, h->warm);
+  if (L.total * 4 > h->lds_limit) return fail(SIM_ECAPACITY, "working set exceeds LDS");
+  int rc = rbs_launch_step(&P, &L, h->threads, h->S, h->stream);
+  if (rc != 0) return fail(SIM_EDEVICE, std::string("step launch failed: ") + hipGetErrorString((hipError_t)rc));
+  h->parity ^= 1;
+  return SIM_OK;
+}
+
+int sim_contacts(const sim_handle* hc, sim_contact_view* out) {
+  if (!hc || !out) return fail(SIM_EINVAL, "NULL argument");
+  sim_handle* h = const_cast<sim_handle*>(hc);
+  const Layout& L = h->lay;
+  int last = h->parity;  // the buffer the last step wrote is the one the next reads
+  out->max_contacts = h->CM;
+  out->max_pairs = h->PM;
+  out->count = at<int32_t>(h, L.off_ccount[last]);
+  out->key = at<uint32_t>(h, L.off_ckey[last]);
+  out->normal = at<float>(h, L.off_x_normal);
+  out->point = at<float>(h, L.off_x_point);
+  out->phi = at<float>(h, L.off_x_phi);
+  out->lambda = at<float>(h, L.off_x_lambda);
+  out->colour = at<int32_t>(h, L.off_x_colour);
+  out->features = at<float>(h, L.off_x_feat);
+  out->n_pairs = at<int32_t>(h, L.off_st[0]);
+  out->pair_key = at<uint32_t>(h, L.off_x_pair);
+  return SIM_OK;
+}
+
+int sim_state(const sim_handle* hc, sim_state_view* out) {
+  if (!hc || !out) return fail(SIM_EINVAL, "NULL argument");
+  sim_handle* h = const_cast<sim_handle*>(hc);
+  const Layout& L = h->lay;
+  out->n_bodies = h->N;
+  out->pose = at<float>(h, L.off_pose);
+  out->vel = at<float>(h, L.off_vel);
+  out->theta = h->arm ? at<float>(h, L.off_theta) : nullptr;
+  out->cache_cap = h->CM;
+  out->cache_count = at<int32_t>(h, L.off_ccount[h->parity]);
+  out->cache_key = at<uint32_t>(h, L.off_ckey[h->parity]);
+  out->cache_lam = at<float>(h, L.off_clam[h->parity]);
+  return SIM_OK;
+}
+
+int sim_stats(const sim_handle* hc, sim_stats_view* out) {
+  if (!hc || !out) return fail(SIM_EINVAL, "NULL argument");
+  sim_handle* h = const_cast<sim_handle*>(hc);
+  const Layout& L = h->lay;
+  out->pairs = at<int32_t>(h, L.off_st[0]);
+  out->contacts = at<int32_t>(h, L.off_st[1]);
+  out->colours = at<int32_t>(h, L.off_st[2]);
+  out->sweeps = at<int32_t>(h, L.off_st[3]);
+  out->flags = at<int32_t>(h, L.off_st[4]);
+  out->residual = at<float>(h, L.off_st[5]);
+  out->arm_force = at<float>(h, L.off_st[6]);
+  return SIM_OK;
+}
+
+int sim_set_export(sim_handle* h, int on) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  h->export_on = on ? 1 : 0;
+  return SIM_OK;
+}
+
+int sim_set_solver(sim_handle* h, int solver, int warm_start, float tolerance) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (solver != SIM_PGS && solver != SIM_JACOBI) return fail(SIM_EINVAL, "bad solver");
+  if (warm_start < SIM_COLD || warm_start > SIM_LEARNED) return fail(SIM_EINVAL, "bad warm start");
+  if (!(tolerance >= 0.f)) return fail(SIM_EINVAL, "tolerance must be >= 0");
+  h->solver = solver;
+  h->warm = warm_start;
+  h->tol = tolerance;
+  return SIM_OK;
+}
+
+int sim_set_mlp(sim_handle* h, const uint16_t* w1, const uint16_t* w2, const uint16_t* w3, const float* b1,
+                const float* b2, const float* b3, const float* mean, const float* stdv) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (!w1 || !w2 || !w3 || !b1 || !b2 || !b3 || !mean || !stdv) return fail(SIM_EINVAL, "NULL weight pointer");
+  h->mlp.w1 = w1;
+  h->mlp.w2 = w2;
+  h->mlp.w3 = w3;
+  h->mlp.b1 = b1;
+  h->mlp.b2 = b2;
+  h->mlp.b3 = b3;
+  h->mlp.mean = mean;
+  h->mlp.stdv = stdv;
+  h->mlp_set = true;
+  return SIM_OK;
+}
+
+int sim_reset(sim_handle* h, const uint8_t* d_mask, const float* d_pose, const float* d_vel, const float* d_theta) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (!d_mask || !d_pose || !d_vel) return fail(SIM_EINVAL, "mask, pose and vel are required");
+  if (h->arm && !d_theta) return fail(SIM_EINVAL, "arm scenes need theta");
+  rbs::StepParams P = params(h);
+  int rc = rbs_launch_reset(&P, d_mask, d_pose, d_vel, h->arm ? d_theta : nullptr,
+                            at<int32_t>(h, h->lay.off_ccount[0]), at<int32_t>(h, h->lay.off_ccount[1]), h->stream);
+  if (rc == 0 && h->arm) rc = rbs_launch_arm_pose(&P, d_mask, h->stream);
+  if (rc != 0) return fail(SIM_EDEVICE, "reset launch failed");
+  return SIM_OK;
+}
+
+int sim_set_stream(sim_handle* h, void* stream) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  h->stream = (hipStream_t)stream;
+  return SIM_OK;
+}
+
+void sim_destroy(sim_handle* h) { delete h; }
+
+const char* sim_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

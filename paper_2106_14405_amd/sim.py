@@ -1,0 +1,194 @@
+"""Python handle over the HIP library: torch owns the device memory and the
+stream, the library does all the physics.
+
+    sim = Sim(batch, max_contacts=512)
+    sim.step(actions, dt=1/120, iters=20)
+    pose = sim.pose          # [7, N] device tensor view (x y z qw qx qy qz)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import scenes
+
+DEFAULT_CONSTS = dict(margin=0.02, baumgarte=0.2, slop=0.005, rest_thresh=0.5, ground_friction=0.5,
+                      ground_restitution=0.0, gravity=(0.0, 0.0, -9.81), link_len=scenes.ARM_LINK_LENGTH,
+                      arm_radius=scenes.ARM_RADIUS)
+
+
+def _np_ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+class Sim:
+    """A batch of scenes resident in one device workspace."""
+
+    def __init__(self, batch: scenes.Batch, max_pairs: int | None = None, max_contacts: int | None = None,
+                 solver: int = L.PGS, warm: int = L.COLD, tol: float = 0.0, threads: int = 128,
+                 device: str | torch.device = "cuda", **consts):
+        lib = L.load()
+        c = dict(DEFAULT_CONSTS)
+        c.update(consts)
+        self.consts = c
+        self.device = torch.device(device)
+        self.batch = batch
+        self.S = batch.n_scenes
+        self.N = batch.n_bodies
+        nmax = int(np.max(batch.counts()))
+        self.max_pairs = int(max_pairs or max(64, 6 * nmax))
+        self.max_contacts = int(max_contacts or max(64, 6 * nmax))
+        self._host = dict(
+            off=np.ascontiguousarray(batch.body_offset, np.int32),
+            shape=np.ascontiguousarray(batch.shape, np.uint8),
+            motion=np.ascontiguousarray(batch.motion, np.uint8),
+            param=np.ascontiguousarray(batch.param, np.float32).reshape(-1),
+            mass=np.ascontiguousarray(batch.mass, np.float32),
+            friction=np.ascontiguousarray(batch.friction, np.float32),
+            restitution=np.ascontiguousarray(batch.restitution, np.float32),
+            pose=np.ascontiguousarray(batch.pose, np.float32).reshape(-1),
+            vel=np.ascontiguousarray(batch.vel, np.float32).reshape(-1),
+            arm_base=np.ascontiguousarray(batch.arm_base, np.float32).reshape(-1),
+            arm_theta=np.ascontiguousarray(batch.arm_theta, np.float32).reshape(-1),
+        )
+        h = self._host
+        d = L.BatchDesc()
+        d.abi_version = L.SIM_ABI_VERSION
+        d.num_scenes = self.S
+        d.h_body_offset = _np_ptr(h["off"], C.c_int32)
+        d.h_shape = _np_ptr(h["shape"], C.c_uint8)
+        d.h_motion = _np_ptr(h["motion"], C.c_uint8)
+        d.h_param = _np_ptr(h["param"], C.c_float)
+        d.h_mass = _np_ptr(h["mass"], C.c_float)
+        d.h_friction = _np_ptr(h["friction"], C.c_float)
+        d.h_restitution = _np_ptr(h["restitution"], C.c_float)
+        d.h_pose = _np_ptr(h["pose"], C.c_float)
+        d.h_vel = _np_ptr(h["vel"], C.c_float)
+        d.arm = int(batch.arm)
+        d.h_arm_base = _np_ptr(h["arm_base"], C.c_float)
+        d.h_arm_theta = _np_ptr(h["arm_theta"], C.c_float)
+        for i in range(7):
+            d.link_len[i] = c["link_len"][i]
+        d.arm_radius = c["arm_radius"]
+        for i in range(3):
+            d.gravity[i] = c["gravity"][i]
+        d.margin, d.baumgarte, d.slop = c["margin"], c["baumgarte"], c["slop"]
+        d.rest_thresh, d.ground_friction, d.ground_restitution = (c["rest_thresh"], c["ground_friction"],
+                                                                  c["ground_restitution"])
+        d.max_pairs, d.max_contacts = self.max_pairs, self.max_contacts
+        d.solver, d.warm_start, d.tolerance, d.threads = int(solver), int(warm), float(tol), int(threads)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            d.stream = C.c_void_p(self.stream.cuda_stream)
+            nbytes = lib.sim_workspace_bytes(C.byref(d))
+            if nbytes == 0:
+                raise L.SimError("invalid batch descriptor: " + lib.sim_last_error().decode())
+            self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            handle = C.c_void_p()
+            L.check(lib.sim_create(C.byref(d), C.c_void_p(self.ws.data_ptr()), C.c_size_t(nbytes),
+                                   C.byref(handle)), "sim_create")
+        self.h = handle
+        self.desc = d
+        self._mlp = None
+        self._views()
+
+    # ------------------------------------------------------------------ views
+    def _view(self, ptr, dtype, shape):
+        if not ptr:
+            return None
+        base = self.ws.data_ptr()
+        off = int(ptr) - base
+        n = int(np.prod(shape)) * torch.tensor([], dtype=dtype).element_size()
+        return self.ws[off:off + n].view(dtype).view(*shape)
+
+    def _views(self):
+        lib = L.load()
+        sv = L.StateView()
+        L.check(lib.sim_state(self.h, C.byref(sv)), "sim_state")
+        S, N, CM, PM = self.S, self.N, self.max_contacts, self.max_pairs
+        self.pose = self._view(sv.pose, torch.float32, (7, N))
+        self.vel = self._view(sv.vel, torch.float32, (6, N))
+        self.theta = self._view(sv.theta, torch.float32, (S, 7)) if self.batch.arm else None
+        st = L.StatsView()
+        L.check(lib.sim_stats(self.h, C.byref(st)), "sim_stats")
+        self.stats = dict(
+            pairs=self._view(st.pairs, torch.int32, (S,)), contacts=self._view(st.contacts, torch.int32, (S,)),
+            colours=self._view(st.colours, torch.int32, (S,)), sweeps=self._view(st.sweeps, torch.int32, (S,)),
+            flags=self._view(st.flags, torch.int32, (S,)), residual=self._view(st.residual, torch.float32, (S,)),
+            arm_force=self._view(st.arm_force, torch.float32, (S,)))
+
+    def cache(self):
+        """(count [S], key [S, CM], lam [4, S, CM]) of the contacts the next step warm-starts from."""
+        lib = L.load()
+        sv = L.StateView()
+        L.check(lib.sim_state(self.h, C.byref(sv)), "sim_state")
+        S, CM = self.S, self.max_contacts
+        return (self._view(sv.cache_count, torch.int32, (S,)),
+                self._view(sv.cache_key, torch.int32, (S, CM)),
+                self._view(sv.cache_lam, torch.float32, (4, S, CM)))
+
+    def contacts(self):
+        """Views of the last step's contacts (exported fields need set_export(True))."""
+        lib = L.load()
+        cv = L.ContactView()
+        L.check(lib.sim_contacts(self.h, C.byref(cv)), "sim_contacts")
+        S, CM, PM = self.S, self.max_contacts, self.max_pairs
+        return dict(
+            count=self._view(cv.count, torch.int32, (S,)), key=self._view(cv.key, torch.int32, (S, CM)),
+            normal=self._view(cv.normal, torch.float32, (3, S, CM)),
+            point=self._view(cv.point, torch.float32, (3, S, CM)),
+            phi=self._view(cv.phi, torch.float32, (S, CM)),
+            lam=self._view(cv.lambda_, torch.float32, (3, S, CM)),
+            colour=self._view(cv.colour, torch.int32, (S, CM)),
+            features=self._view(cv.features, torch.float32, (16, S, CM)),
+            n_pairs=self._view(cv.n_pairs, torch.int32, (S,)),
+            pair_key=self._view(cv.pair_key, torch.int32, (S, PM)))
+
+    # ------------------------------------------------------------------ calls
+    def step(self, actions: torch.Tensor | None = None, dt: float = 1.0 / 120.0, iters: int = 10):
+        ptr = None
+        if actions is not None:
+            if actions.device != self.device or actions.dtype != torch.float32 or not actions.is_contiguous():
+                raise ValueError("actions must be a contiguous float32 tensor on the simulation device")
+            if actions.numel() != 7 * self.S:
+                raise ValueError("actions must hold 7 joint velocities per scene")
+            ptr = C.c_void_p(actions.data_ptr())
+        L.check(L.load().sim_step(self.h, ptr, float(dt), int(iters)), "sim_step")
+
+    def set_export(self, on: bool = True):
+        L.check(L.load().sim_set_export(self.h, int(bool(on))), "sim_set_export")
+
+    def set_solver(self, solver: int = L.PGS, warm: int = L.COLD, tol: float = 0.0):
+        L.check(L.load().sim_set_solver(self.h, int(solver), int(warm), float(tol)), "sim_set_solver")
+
+    def set_mlp(self, w1, w2, w3, b1, b2, b3, mean, std):
+        """Device tensors: bf16 w1 [64,16], w2 [64,64], w3 [3,64]; fp32 biases, mean, std."""
+        ts = [w1.contiguous(), w2.contiguous(), w3.contiguous(), b1.float().contiguous(), b2.float().contiguous(),
+              b3.float().contiguous(), mean.float().contiguous(), std.float().contiguous()]
+        for t in ts[:3]:
+            if t.dtype != torch.bfloat16:
+                raise ValueError("weights must be bfloat16")
+        self._mlp = ts  # keep alive
+        L.check(L.load().sim_set_mlp(self.h, *[C.c_void_p(t.data_ptr()) for t in ts]), "sim_set_mlp")
+
+    def reset(self, mask: torch.Tensor, pose: torch.Tensor, vel: torch.Tensor, theta: torch.Tensor | None = None):
+        """Masked reset from pool arrays laid out like the state ([7, N], [6, N], [S, 7])."""
+        ts = [mask.to(torch.uint8).contiguous(), pose.contiguous(), vel.contiguous()]
+        th = theta.contiguous() if theta is not None else None
+        self._reset_keep = ts + [th]
+        L.check(L.load().sim_reset(self.h, *[C.c_void_p(t.data_ptr()) for t in ts],
+                                   C.c_void_p(th.data_ptr()) if th is not None else None), "sim_reset")
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.load().sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,192 @@
+"""GPU parity: the HIP step through the C ABI against the FP64 oracle.
+
+Both sides start every compared step from the identical float32 state (an
+oracle run rounded to float32, never a GPU output).  In scenes without a
+tie-band decision, pair keys, contact keys and colours are bit-exact;
+positions, velocities and orientations agree within 1e-4 relative (floors
+1 m, 1 m/s, 1 rad/s; 1e-4 rad for orientation).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import compare, gpu_results, gpu_sim, oracle_warmup, snapshot32
+from helpers import DT, G, S, custom_batch
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def step_both(batch, ora, warm, iters, tol=0.0, solver=O.PGS, threads=128, max_contacts=None, actions_seed=7,
+              step_index=0, use_cache=True):
+    import torch
+    pose, vel, theta, cache = snapshot32(ora)
+    sim = gpu_sim(batch, pose, vel, theta, cache if use_cache else None, max_contacts=max_contacts,
+                  max_pairs=max_contacts, warm=warm, tol=tol, solver=solver, threads=threads)
+    act = S.arm_actions(actions_seed, batch.n_scenes, step_index) if batch.arm else None
+    if act is not None:
+        sim.step(torch.as_tensor(act, device=sim.device), DT, iters)
+    else:
+        sim.step(None, DT, iters)
+    r = ora.step(actions=act, iters=iters, tol=tol, warm=warm, solver=solver, max_pairs=sim.max_pairs,
+                 max_contacts=sim.max_contacts)
+    g = gpu_results(sim)
+    return sim, g, r
+
+
+def test_ballistic_on_device(torch_cuda):
+    """Semi-implicit Euler closed form after 120 steps in float32."""
+    torch = torch_cuda
+    bodies = [dict(shape=S.SPHERE, param=[0.1, 0, 0], pos=[0, 0, 80.0], vel=[1.0, -2.0, 3.0, 0.4, -0.2, 0.1]),
+              dict(shape=S.BOX, param=[0.1, 0.2, 0.3], pos=[5, 0, 90.0], vel=[0, 0.5, 0, 0, 0, 0])]
+    b = custom_batch([bodies, bodies])
+    from paper_2106_14405_amd.sim import Sim
+    sim = Sim(b)
+    x0 = b.pose[:, :3].astype(np.float64)
+    v0 = b.vel[:, :3].astype(np.float64)
+    n = 120
+    for _ in range(n):
+        sim.step(None, DT, 4)
+    torch.cuda.synchronize()
+    x = sim.pose.cpu().numpy().T[:, :3].astype(np.float64)
+    v = sim.vel.cpu().numpy().T[:, :3].astype(np.float64)
+    g = np.array([0, 0, -G])
+    xn = x0 + n * DT * v0 + g * DT * DT * n * (n + 1) / 2
+    vn = v0 + n * g * DT
+    assert np.max(np.abs(x - xn) / np.maximum(np.abs(xn), 1.0)) < 1e-4
+    assert np.max(np.abs(v - vn) / np.maximum(np.abs(vn), 1.0)) < 1e-4
+    assert int(sim.stats["pairs"].sum()) == 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_drop_first_step_initial_state(torch_cuda, seed):
+    """Step 0 of the drop case (bodies in the air): pairs exactly as brute force."""
+    b = S.batch_drop(1, seed0=seed)
+    ora = O.OracleSim(b)
+    sim, g, r = step_both(b, ora, O.COLD, 10)
+    rep = compare(b, g, r, ora)
+    assert rep["scenes"] == 1
+
+
+@pytest.mark.parametrize("warm", [O.COLD, O.PREV])
+def test_drop_settled_parity(torch_cuda, warm):
+    """Drop case, 64 bodies, one step from 8 oracle-settled states each."""
+    flagged = 0
+    checked = 0
+    for seed in range(8):
+        b = S.batch_drop(1, seed0=100 + seed)
+        ora = oracle_warmup(b, 60 + 10 * seed, iters=10, warm=O.PREV)
+        sim, g, r = step_both(b, ora, warm, 10)
+        rep = compare(b, g, r, ora)
+        flagged += rep["flagged"]
+        checked += rep["scenes"] - rep["flagged"]
+    assert checked >= 4, f"only {checked} unflagged scenes"
+
+
+def test_drop_batch_many_scenes(torch_cuda):
+    """16 drop scenes in one launch, settled by the oracle; ragged contact counts."""
+    b = S.batch_drop(16, seed0=300)
+    ora = oracle_warmup(b, 90, iters=10, warm=O.PREV)
+    sim, g, r = step_both(b, ora, O.PREV, 10)
+    rep = compare(b, g, r, ora)
+    assert rep["scenes"] - rep["flagged"] >= 8
+
+
+@pytest.mark.parametrize("threads", [64, 192, 256])
+def test_block_size_bit_identical(torch_cuda, threads):
+    """Results are bit-identical for any workgroup size."""
+    b = S.batch_drop(4, seed0=500)
+    ora = oracle_warmup(b, 80, iters=10, warm=O.PREV)
+    pose, vel, theta, cache = snapshot32(ora)
+    outs = []
+    for T in (128, threads):
+        sim = gpu_sim(b, pose, vel, theta, cache, warm=O.PREV, threads=T)
+        sim.step(None, DT, 10)
+        outs.append(gpu_results(sim))
+    a, c = outs
+    assert np.array_equal(a["pose"], c["pose"]) and np.array_equal(a["vel"], c["vel"])
+    assert np.array_equal(a["key"], c["key"]) and np.array_equal(a["lam"], c["lam"])
+
+
+def test_two_runs_bit_identical(torch_cuda):
+    b = S.batch_drop(4, seed0=600)
+    ora = oracle_warmup(b, 70, iters=10, warm=O.PREV)
+    pose, vel, theta, cache = snapshot32(ora)
+    outs = []
+    for _ in range(2):
+        sim = gpu_sim(b, pose, vel, theta, cache, warm=O.PREV)
+        for _ in range(5):
+            sim.step(None, DT, 10)
+        outs.append(gpu_results(sim))
+    assert np.array_equal(outs[0]["pose"], outs[1]["pose"])
+    assert np.array_equal(outs[0]["vel"], outs[1]["vel"])
+
+
+def test_clutter_arm_parity(torch_cuda):
+    """Clutter scenes with statics, capsules and the kinematic arm."""
+    b = S.batch_clutter(6, seed0=10000)
+    ora = oracle_warmup(b, 100, iters=20, warm=O.PREV)
+    sim, g, r = step_both(b, ora, O.PREV, 20, step_index=100)
+    rep = compare(b, g, r, ora)
+    assert rep["scenes"] - rep["flagged"] >= 3
+    # arm joint angles and contact force
+    np.testing.assert_allclose(g["theta"], ora.theta.reshape(-1, 7), rtol=0, atol=1e-6)
+    unflagged = r["ambiguous"] == 0
+    np.testing.assert_allclose(g["stats"]["arm_force"][unflagged], r["arm_force"][unflagged], rtol=1e-3, atol=1e-2)
+
+
+def test_jacobi_parity(torch_cuda):
+    b = S.batch_drop(4, seed0=700)
+    ora = oracle_warmup(b, 80, iters=10, warm=O.PREV)
+    sim, g, r = step_both(b, ora, O.PREV, 10, solver=O.JACOBI)
+    rep = compare(b, g, r, ora)
+    assert rep["scenes"] - rep["flagged"] >= 2
+
+
+def test_tolerance_mode_sweeps(torch_cuda):
+    """Tolerance mode: same sweep counts where the residual is not at the threshold."""
+    b = S.batch_drop(4, seed0=800)
+    ora = oracle_warmup(b, 80, iters=10, warm=O.PREV)
+    sim, g, r = step_both(b, ora, O.PREV, 200, tol=1e-4)
+    rep = compare(b, g, r, ora, check_values=False)
+    ok = r["ambiguous"] == 0
+    gs, os_ = g["stats"]["sweeps"][ok], r["sweeps"][ok]
+    assert np.mean(np.abs(gs - os_) <= 1) >= 0.75, (gs, os_)
+    assert np.all(g["stats"]["residual"][g["stats"]["flags"] & 4 == 0] <= 1e-4)
+
+
+def test_contact_values(torch_cuda):
+    """Normals, points, depths and impulses of unflagged scenes."""
+    b = S.batch_drop(4, seed0=900)
+    ora = oracle_warmup(b, 90, iters=10, warm=O.PREV)
+    sim, g, r = step_both(b, ora, O.PREV, 10)
+    compare(b, g, r, ora, check_values=False)
+    for s in range(4):
+        if r["ambiguous"][s]:
+            continue
+        n = int(r["n_contacts"][s])
+        np.testing.assert_allclose(g["normal"][:, s, :n].T, r["c_normal"][s, :n], atol=1e-5)
+        np.testing.assert_allclose(g["point"][:, s, :n].T, r["c_point"][s, :n], atol=1e-5)
+        np.testing.assert_allclose(g["phi"][s, :n], r["c_phi"][s, :n], atol=1e-5)
+        lam_o = r["c_lambda"][s, :n]
+        scale = np.maximum(np.abs(lam_o).max(), 1e-3)
+        assert np.max(np.abs(g["lam"][:, s, :n].T - lam_o)) <= 1e-3 * scale + 1e-6
+
+
+def test_capacity_flag(torch_cuda):
+    """Contact capacity overflow raises the CAPACITY flag and stays in bounds."""
+    b = S.batch_drop(2, seed0=1000)
+    ora = oracle_warmup(b, 90, iters=10, warm=O.PREV)
+    pose, vel, theta, cache = snapshot32(ora)
+    sim = gpu_sim(b, pose, vel, theta, None, max_contacts=16, max_pairs=16)
+    sim.step(None, DT, 5)
+    g = gpu_results(sim)
+    assert np.all(g["stats"]["flags"] & 2)
+    assert np.all(g["count"] <= 16)
