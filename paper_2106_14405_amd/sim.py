@@ -35,6 +35,8 @@ class Sim:
         c.update(consts)
         self.consts = c
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.batch = batch
         self.S = batch.n_scenes
         self.N = batch.n_bodies

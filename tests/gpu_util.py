@@ -14,6 +14,15 @@ V_FLOOR = 1.0       # m/s and rad/s
 Q_ANGLE = 1e-4      # rad
 
 
+def quat_angle(qa, qb):
+    """Rotation angle between unit quaternions (either sign), computed as
+    2 atan2(|a - s b|, |a + s b|) after normalising both: stable near 0."""
+    qa = qa / np.linalg.norm(qa, axis=1, keepdims=True)
+    qb = qb / np.linalg.norm(qb, axis=1, keepdims=True)
+    sgn = np.where(np.sum(qa * qb, axis=1) < 0, -1.0, 1.0)[:, None]
+    return 2.0 * np.arctan2(np.linalg.norm(qa - sgn * qb, axis=1), np.linalg.norm(qa + sgn * qb, axis=1))
+
+
 def oracle_warmup(batch, steps, iters=10, warm=O.PREV, arm_seed=1, **kw):
     """Run the oracle `steps` steps from the batch's initial state (the only
     source of non-initial states for parity inputs)."""
@@ -105,9 +114,7 @@ def compare(batch, g, r, ora, check_values=True, scenes=None):
         vo, vg = vel_o[b0:b1], g["vel"][b0:b1]
         ev = np.max(np.abs(vg[:, :3] - vo[:, :3]) / np.maximum(np.abs(vo[:, :3]), V_FLOOR), initial=0.0)
         ew = np.max(np.abs(vg[:, 3:] - vo[:, 3:]) / np.maximum(np.abs(vo[:, 3:]), V_FLOOR), initial=0.0)
-        qo, qg = pose_o[b0:b1, 3:], g["pose"][b0:b1, 3:]
-        dq = np.clip(np.abs(np.sum(qo * qg, axis=1)), 0.0, 1.0)
-        eq = np.max(2.0 * np.arccos(dq), initial=0.0)
+        eq = np.max(quat_angle(pose_o[b0:b1, 3:], g["pose"][b0:b1, 3:]), initial=0.0)
         rep["max_x"] = max(rep["max_x"], ex)
         rep["max_v"] = max(rep["max_v"], ev)
         rep["max_w"] = max(rep["max_w"], ew)
