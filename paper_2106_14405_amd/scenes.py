@@ -24,6 +24,7 @@ of the core segment along local z).
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -81,15 +82,24 @@ def uniforms(key: int, count: int, start: int = 0) -> np.ndarray:
 
 
 class _Stream:
-    """Sequential reader over one counter-based stream."""
+    """Sequential reader over one counter-based stream (values are drawn in
+    blocks; the k-th value depends only on (key, k))."""
+
+    BLOCK = 4096
 
     def __init__(self, key: int):
         self.key = key
         self.pos = 0
+        self._buf = np.empty(0)
+        self._buf0 = 0
 
     def take(self, n: int) -> np.ndarray:
-        u = uniforms(self.key, n, self.pos)
-        self.pos += n
+        end = self.pos + n
+        if self.pos < self._buf0 or end > self._buf0 + len(self._buf):
+            self._buf0 = self.pos
+            self._buf = uniforms(self.key, max(n, self.BLOCK), self.pos)
+        u = self._buf[self.pos - self._buf0:end - self._buf0]
+        self.pos = end
         return u
 
     def uniform(self, lo, hi, n=None):
@@ -167,12 +177,13 @@ def _static_clear(p, R, statics) -> bool:
 def _place(st, R, lo, hi, placed, statics=(), keepout=None, tries=4000):
     """Rejection-sample a centre in the box [lo, hi] whose bounding sphere of
     radius R overlaps no placed sphere, no static box and no keep-out sphere."""
+    if placed:
+        P = np.asarray([q[0] for q in placed])
+        Rr = np.asarray([q[1] for q in placed])
     for _ in range(tries):
         p = lo + (hi - lo) * st.take(3)
         ok = True
         if placed:
-            P = np.asarray([q[0] for q in placed])
-            Rr = np.asarray([q[1] for q in placed])
             if np.any(np.sum((P - p) ** 2, axis=1) < (Rr + R) ** 2):
                 ok = False
         if ok and keepout is not None:
@@ -345,19 +356,38 @@ def batch_drop(n_scenes: int = 1, seed0: int = 0, **kw) -> Batch:
     return pack([drop_scene(seed0 + s, **kw) for s in range(n_scenes)])
 
 
-def batch_clutter(n_scenes: int = 1024, seed0: int = 10000, arm: bool = True, **kw) -> Batch:
+def _clutter_one(args):
+    seed, arm, kw = args
+    return clutter_scene(seed, arm=arm, **kw)
+
+
+def _drop_one(args):
+    seed, ns, nb = args
+    return drop_scene(seed, n_spheres=ns, n_boxes=nb)
+
+
+def _map(fn, items, workers):
+    """Map over scene seeds, in worker processes for large batches.  Uses
+    fork: call it before the GPU is initialised in this process."""
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1) if len(items) >= 64 else 1
+    if workers <= 1:
+        return [fn(a) for a in items]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(fn, items, chunksize=max(1, len(items) // (4 * workers)))
+
+
+def batch_clutter(n_scenes: int = 1024, seed0: int = 10000, arm: bool = True, workers=None, **kw) -> Batch:
     """Clutter case: per scene 20 static boxes + 108 dynamic + 7 arm links."""
-    return pack([clutter_scene(seed0 + s, arm=arm, **kw) for s in range(n_scenes)])
+    return pack(_map(_clutter_one, [(seed0 + s, arm, kw) for s in range(n_scenes)], workers))
 
 
-def batch_uneven(n_scenes: int = 4096, seed0: int = 20000, lo: int = 16, hi: int = 512) -> Batch:
+def batch_uneven(n_scenes: int = 4096, seed0: int = 20000, lo: int = 16, hi: int = 512, workers=None) -> Batch:
     """Uneven batch: dynamic counts log-uniform in [lo, hi], drop-case shapes."""
     counts = log_uniform_counts(seed0, n_scenes, lo, hi)
-    scenes = []
-    for s, n in enumerate(counts):
-        ns = int(n) // 2
-        scenes.append(drop_scene(seed0 + 1 + s, n_spheres=ns, n_boxes=int(n) - ns))
-    return pack(scenes)
+    items = [(seed0 + 1 + s, int(n) // 2, int(n) - int(n) // 2) for s, n in enumerate(counts)]
+    return pack(_map(_drop_one, items, workers))
 
 
 def arm_actions(seed: int, n_scenes: int, step: int) -> np.ndarray:
