@@ -50,7 +50,22 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-scenes", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--probe-copy-mib", type=int, default=0,
+                    help="only run an elementwise copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def probe_copy(mib):
+    """Elementwise copy b = a + 0 of `mib` MiB, 5 launches: reads and writes
+    exactly mib MiB each; used to scale the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        torch.add(a, 0.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe_copy_mib": mib, "launches": 5}))
 
 
 def kernel_hash():
@@ -96,6 +111,9 @@ def cpu_baseline(batch_fn, n_scenes, warm_steps, timed_steps, iters, tol, warm, 
 
 def main():
     a = parse()
+    if a.probe_copy_mib:
+        probe_copy(a.probe_copy_mib)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
