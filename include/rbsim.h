@@ -169,6 +169,15 @@ int sim_set_mlp(sim_handle *h, const uint16_t *d_w1, const uint16_t *d_w2, const
  * contact cache.  Device pointers; asynchronous. */
 int sim_reset(sim_handle *h, const uint8_t *d_mask, const float *d_pose, const float *d_vel, const float *d_theta);
 
+/* Phase tracing: when d_trace (device, [S][16] uint64) is non-NULL, every
+ * later step writes 15 wall-clock timestamps per scene (constant-rate
+ * counter) at its phase boundaries: start, bodies loaded, arm, AABBs, body
+ * sort, sweep, pair sort, narrowphase, setup, contact lists, colouring
+ * rounds, colour sort, warm start, sweeps, integration, outputs end; slot
+ * 15 holds the shader-clock cycles spent in the solver sweeps.
+ * NULL turns it off.  For profiling; adds one store per phase. */
+int sim_set_trace(sim_handle *h, uint64_t *d_trace);
+
 int sim_set_stream(sim_handle *h, void *stream);
 void sim_destroy(sim_handle *h);
 const char *sim_last_error(void);

@@ -58,8 +58,8 @@ class StatsView(C.Structure):
 
 
 EXPORTED = ["sim_workspace_bytes", "sim_create", "sim_step", "sim_contacts", "sim_state", "sim_stats",
-            "sim_set_export", "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_stream", "sim_destroy",
-            "sim_last_error"]
+            "sim_set_export", "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_trace", "sim_set_stream",
+            "sim_destroy", "sim_last_error"]
 
 _lib = None
 
@@ -85,12 +85,13 @@ def load():
     L.sim_set_mlp.argtypes = [C.c_void_p] + [C.c_void_p] * 8
     L.sim_reset.argtypes = [C.c_void_p] + [C.c_void_p] * 4
     L.sim_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+    L.sim_set_trace.argtypes = [C.c_void_p, C.c_void_p]
     L.sim_destroy.argtypes = [C.c_void_p]
     L.sim_destroy.restype = None
     L.sim_last_error.argtypes = []
     L.sim_last_error.restype = C.c_char_p
     for name in ("sim_create", "sim_step", "sim_contacts", "sim_state", "sim_stats", "sim_set_export",
-                 "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_stream"):
+                 "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_trace", "sim_set_stream"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

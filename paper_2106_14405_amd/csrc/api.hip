@@ -39,6 +39,7 @@ struct Layout {
       off_restitution, off_pose, off_vel, off_theta, off_arm_base, off_scene_list;
   size_t off_ckey[2], off_clam[2], off_ccount[2];
   size_t off_x_pair, off_x_npairs, off_x_normal, off_x_point, off_x_phi, off_x_lambda, off_x_colour, off_x_feat;
+  size_t off_raw, off_crec;
   size_t off_st[7];
   size_t total;
 };
@@ -75,6 +76,8 @@ Layout make_layout(long S, long N, long PM, long CM) {
   L.off_x_lambda = take(4 * 3 * S * CM);
   L.off_x_colour = take(4 * S * CM);
   L.off_x_feat = take(4 * 16 * S * CM);
+  L.off_raw = take(4 * 8 * S * CM);
+  L.off_crec = take(4 * 52 * S * CM);  // 13 float4 solver record per contact
   for (int k = 0; k < 7; k++) L.off_st[k] = take(4 * S);
   L.total = o;
   return L;
@@ -100,6 +103,7 @@ struct sim_handle {
   float tol;
   rbs::MlpParams mlp;
   bool mlp_set;
+  uint64_t* trace;
   int lds_limit;
 };
 
@@ -151,6 +155,8 @@ rbs::StepParams params(sim_handle* h) {
   P.x_lambda = at<float>(h, L.off_x_lambda);
   P.x_colour = at<int32_t>(h, L.off_x_colour);
   P.x_feat = at<float>(h, L.off_x_feat);
+  P.raw = at<float4>(h, L.off_raw);
+  P.crec = at<float4>(h, L.off_crec);
   P.st_pairs = at<int32_t>(h, L.off_st[0]);
   P.st_contacts = at<int32_t>(h, L.off_st[1]);
   P.st_colours = at<int32_t>(h, L.off_st[2]);
@@ -172,6 +178,7 @@ rbs::StepParams params(sim_handle* h) {
   P.solver = h->solver;
   P.mlp = h->mlp;
   P.scene_list = at<int32_t>(h, L.off_scene_list);
+  P.trace = h->trace;
   return P;
 }
 
@@ -220,7 +227,7 @@ int validate(const sim_batch_desc* d, Caps* caps) {
   }
   if (d->max_pairs < 1 || d->max_contacts < 1) return fail(SIM_EINVAL, "capacities must be >= 1");
   if (d->max_pairs > (1 << 20) || d->max_contacts > (1 << 20)) return fail(SIM_EINVAL, "capacity too large");
-  int T = d->threads ? d->threads : 128;
+  int T = d->threads ? d->threads : 64;
   if (T != 64 && T != 128 && T != 192 && T != 256) return fail(SIM_EINVAL, "threads must be 64, 128, 192 or 256");
   if (d->solver != SIM_PGS && d->solver != SIM_JACOBI) return fail(SIM_EINVAL, "bad solver");
   if (d->warm_start < SIM_COLD || d->warm_start > SIM_LEARNED) return fail(SIM_EINVAL, "bad warm start");
@@ -265,7 +272,7 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   Layout lay = make_layout(S, N, d->max_pairs, d->max_contacts);
   if (!d_workspace || workspace_bytes < lay.total) return fail(SIM_EWORKSPACE, "workspace too small");
   if (((uintptr_t)d_workspace & 255u) != 0) return fail(SIM_EWORKSPACE, "workspace must be 256-byte aligned");
-  const int T = d->threads ? d->threads : 128;
+  const int T = d->threads ? d->threads : 64;
   int need = lds_bytes(c.NB, d->max_pairs, d->max_contacts, T, SIM_JACOBI, SIM_LEARNED);
   int limit = device_lds_limit();
   if (need > limit)
@@ -300,6 +307,7 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   h->tol = d->tolerance;
   memset(&h->mlp, 0, sizeof(h->mlp));
   h->mlp_set = false;
+  h->trace = nullptr;
   h->lds_limit = limit;
 
   // host staging: structure-of-arrays planes
@@ -485,6 +493,12 @@ int sim_reset(sim_handle* h, const uint8_t* d_mask, const float* d_pose, const f
                             at<int32_t>(h, h->lay.off_ccount[0]), at<int32_t>(h, h->lay.off_ccount[1]), h->stream);
   if (rc == 0 && h->arm) rc = rbs_launch_arm_pose(&P, d_mask, h->stream);
   if (rc != 0) return fail(SIM_EDEVICE, "reset launch failed");
+  return SIM_OK;
+}
+
+int sim_set_trace(sim_handle* h, uint64_t* d_trace) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  h->trace = d_trace;
   return SIM_OK;
 }
 

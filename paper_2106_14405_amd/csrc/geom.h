@@ -85,6 +85,23 @@ struct PC {
   int f;
 };
 
+// Up to four contacts held in registers (fixed slots, no indexed array).
+struct Out4 {
+  PC c0, c1, c2, c3;
+  int n;
+  __device__ __forceinline__ void push(const PC& c) {
+    if (n == 0) c0 = c;
+    else if (n == 1) c1 = c;
+    else if (n == 2) c2 = c;
+    else if (n == 3) c3 = c;
+    n++;
+  }
+  __device__ __forceinline__ PC get(int k) const { return k == 0 ? c0 : (k == 1 ? c1 : (k == 2 ? c2 : c3)); }
+  __device__ __forceinline__ void flip() {
+    c0.n = -c0.n; c1.n = -c1.n; c2.n = -c2.n; c3.n = -c3.n;
+  }
+};
+
 __device__ __forceinline__ PC sphere_sphere(V3 ca, float ra, V3 cb, float rb, int f) {
   PC c;
   V3 d = ca - cb;
@@ -98,7 +115,7 @@ __device__ __forceinline__ PC sphere_sphere(V3 ca, float ra, V3 cb, float rb, in
 
 // Sphere (first) vs box (second): clamp in the box frame; a centre inside
 // leaves through the face of least penetration (ties: lower axis, + face).
-__device__ inline int sphere_box(const Geom& S, const Geom& B, float margin, PC* out) {
+__device__ inline void sphere_box(const Geom& S, const Geom& B, float margin, Out4& out) {
   float r = S.p[0];
   const float* h = B.p;
   V3 l = RTv(B.R, S.x - B.x);
@@ -130,9 +147,7 @@ __device__ inline int sphere_box(const Geom& S, const Geom& B, float margin, PC*
   c.p = (wa + wb) * 0.5f;
   c.phi = phi;
   c.f = 0;
-  if (!(phi <= margin)) return 0;
-  out[0] = c;
-  return 1;
+  if (phi <= margin) out.push(c);
 }
 
 __device__ __forceinline__ void capsule_seg(const Geom& C, V3& p0, V3& d) {
@@ -141,26 +156,23 @@ __device__ __forceinline__ void capsule_seg(const Geom& C, V3& p0, V3& d) {
   d = ax * 2.0f;
 }
 
-__device__ inline int sphere_capsule(const Geom& S, const Geom& C, float margin, PC* out) {
+__device__ inline void sphere_capsule(const Geom& S, const Geom& C, float margin, Out4& out) {
   V3 p0, d;
   capsule_seg(C, p0, d);
   float t = clampf(dot(S.x - p0, d) / len2(d), 0.f, 1.f);
   PC c = sphere_sphere(S.x, S.p[0], p0 + d * t, C.p[0], 0);
-  if (!(c.phi <= margin)) return 0;
-  out[0] = c;
-  return 1;
+  if (c.phi <= margin) out.push(c);
 }
 
 // Capsule vs capsule: closest points of the core segments; nearly parallel
 // cores whose projections overlap give contacts at both overlap ends.
-__device__ inline int capsule_capsule(const Geom& A, const Geom& B, float margin, PC* out) {
+__device__ inline void capsule_capsule(const Geom& A, const Geom& B, float margin, Out4& out) {
   V3 pa, da, pb, db;
   capsule_seg(A, pa, da);
   capsule_seg(B, pb, db);
   float ra = A.p[0], rb = B.p[0];
   float aa = len2(da), ee = len2(db);
   float cr2 = len2(cross(da, db));
-  int n = 0;
   if (cr2 <= kCapParallel * aa * ee) {
     float s0 = dot(pb - pa, da) / aa;
     float s1 = dot((pb + db) - pa, da) / aa;
@@ -172,9 +184,9 @@ __device__ inline int capsule_capsule(const Geom& A, const Geom& B, float margin
         V3 P = pa + da * s;
         float t = clampf(dot(P - pb, db) / ee, 0.f, 1.f);
         PC c = sphere_sphere(P, ra, pb + db * t, rb, k);
-        if (c.phi <= margin) out[n++] = c;
+        if (c.phi <= margin) out.push(c);
       }
-      return n;
+      return;
     }
   }
   V3 r = pa - pb;
@@ -185,8 +197,7 @@ __device__ inline int capsule_capsule(const Geom& A, const Geom& B, float margin
   if (t < 0.f) { t = 0.f; s = clampf(-c / aa, 0.f, 1.f); }
   else if (t > 1.f) { t = 1.f; s = clampf((b - c) / aa, 0.f, 1.f); }
   PC cc = sphere_sphere(pa + da * s, ra, pb + db * t, rb, 0);
-  if (cc.phi <= margin) out[n++] = cc;
-  return n;
+  if (cc.phi <= margin) out.push(cc);
 }
 
 __device__ __forceinline__ float box_d2(V3 l, const float* h) {
@@ -235,7 +246,7 @@ __device__ __forceinline__ PC cap_face_contact(V3 l, int a, float s, const float
 // box; face-parallel cores give the clipped segment ends (f 0, 1); other
 // separated cores one contact at the closest points (f 2); cores touching
 // the box leave through the face of least translation (f 0, 1, or 3).
-__device__ inline int capsule_box(const Geom& C, const Geom& B, float margin, PC* out) {
+__device__ inline void capsule_box(const Geom& C, const Geom& B, float margin, Out4& out) {
   float r = C.p[0];
   const float* h = B.p;
   V3 P0, D;
@@ -283,8 +294,8 @@ __device__ inline int capsule_box(const Geom& C, const Geom& B, float margin, PC
     if (g < bg || (g == bg && tv < bt)) { bg = g; bt = tv; }
   }
   V3 l = p0 + d * bt;
-  PC loc[2];
-  int n = 0;
+  Out4 loc;
+  loc.n = 0;
   if (bg > 0.f) {
     float dist = sqrtf(bg);
     float dl = sqrtf(len2(d));
@@ -297,8 +308,8 @@ __device__ inline int capsule_box(const Geom& C, const Geom& B, float margin, PC
       float sa = comp(l, a) > 0.f ? 1.f : -1.f;
       float t0, t1;
       if (clip_face(p0, d, h, a, t0, t1)) {
-        loc[n++] = cap_face_contact(p0 + d * t0, a, sa, h, r, 0);
-        if (t1 > t0) loc[n++] = cap_face_contact(p0 + d * t1, a, sa, h, r, 1);
+        loc.push(cap_face_contact(p0 + d * t0, a, sa, h, r, 0));
+        if (t1 > t0) loc.push(cap_face_contact(p0 + d * t1, a, sa, h, r, 1));
         done = true;
       }
     }
@@ -309,7 +320,7 @@ __device__ inline int capsule_box(const Geom& C, const Geom& B, float margin, PC
       c.phi = dist - r;
       c.p = (q + (l - c.n * r)) * 0.5f;
       c.f = 2;
-      loc[n++] = c;
+      loc.push(c);
     }
   } else {
     V3 p1 = p0 + d;
@@ -326,29 +337,29 @@ __device__ inline int capsule_box(const Geom& C, const Geom& B, float margin, PC
     }
     float t0, t1;
     if (clip_face(p0, d, h, ba, t0, t1)) {
-      loc[n++] = cap_face_contact(p0 + d * t0, ba, bs, h, r, 0);
-      if (t1 > t0) loc[n++] = cap_face_contact(p0 + d * t1, ba, bs, h, r, 1);
+      loc.push(cap_face_contact(p0 + d * t0, ba, bs, h, r, 0));
+      if (t1 > t0) loc.push(cap_face_contact(p0 + d * t1, ba, bs, h, r, 1));
     } else {
       float e0 = bs * comp(p0, ba), e1 = bs * comp(p1, ba);
-      loc[n++] = cap_face_contact(e0 <= e1 ? p0 : p1, ba, bs, h, r, 3);
+      loc.push(cap_face_contact(e0 <= e1 ? p0 : p1, ba, bs, h, r, 3));
     }
   }
-  int m = 0;
-  for (int k = 0; k < n; k++) {
-    if (!(loc[k].phi <= margin)) continue;
-    PC c = loc[k];
-    c.n = Rv(B.R, loc[k].n);
-    c.p = B.x + Rv(B.R, loc[k].p);
-    out[m++] = c;
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+    if (k >= loc.n) break;
+    PC c = loc.get(k);
+    if (!(c.phi <= margin)) continue;
+    c.n = Rv(B.R, c.n);
+    c.p = B.x + Rv(B.R, c.p);
+    out.push(c);
   }
-  return m;
 }
 
 // Box vs box: 15-axis separating-axis test; the first box's faces win near
 // ties, edges only when clearly better; face contacts clip the incident face
 // against the reference side planes (three-state: inside / on / outside)
 // and keep at most 4 points; edge contacts use the closest edge points.
-__device__ inline int box_box(const Geom& A, const Geom& B, float margin, PC* out) {
+__device__ inline void box_box(const Geom& A, const Geom& B, float margin, Out4& out) {
   V3 a[3], b[3];
 #pragma unroll
   for (int i = 0; i < 3; i++) { a[i] = col(A.R, i); b[i] = col(B.R, i); }
@@ -388,7 +399,7 @@ __device__ inline int box_box(const Geom& A, const Geom& B, float margin, PC* ou
     else if (k < 6) { if (s > sfb) { sfb = s; fb = k; sgfb = sg; } }
     else if (s > se) { se = s; e = k; sge = sg; ue = u; }
   }
-  if (smax > margin) return 0;
+  if (smax > margin) return;
   float hmax = fmaxf(fmaxf(fmaxf(ha[0], ha[1]), fmaxf(ha[2], hb[0])), fmaxf(hb[1], hb[2]));
   int face = fa;
   float sface = sfa, sgf = sgfa;
@@ -415,9 +426,8 @@ __device__ inline int box_box(const Geom& A, const Geom& B, float margin, PC* ou
     c.phi = dot(PA - PB, N);
     c.p = (PA + PB) * 0.5f;
     c.f = 0x80 | (e - 6);
-    if (!(c.phi <= margin)) return 0;
-    out[0] = c;
-    return 1;
+    if (c.phi <= margin) out.push(c);
+    return;
   }
   // face contact
   const bool refA = face < 3;
@@ -510,7 +520,6 @@ __device__ inline int box_box(const Geom& A, const Geom& B, float margin, PC* ou
     used |= 1u << i4;
     sel = used;
   }
-  int n = 0;
   for (int k = 0; k < np; k++) {
     if (!((sel >> k) & 1u)) continue;
     PC c;
@@ -518,14 +527,12 @@ __device__ inline int box_box(const Geom& A, const Geom& B, float margin, PC* ou
     c.phi = ph[k];
     c.p = poly[k] - nout * (0.5f * ph[k]);
     c.f = (refA ? 0 : 1) | (refface << 1) | (k << 4);
-    out[n++] = c;
+    out.push(c);
   }
-  return n;
 }
 
 // Ground plane z = 0 (second) vs a body (first).
-__device__ inline int ground_contacts(const Geom& A, float margin, PC* out) {
-  int n = 0;
+__device__ inline void ground_contacts(const Geom& A, float margin, Out4& out) {
   const V3 up = v3(0.f, 0.f, 1.f);
   if (A.shape == SPHERE) {
     PC c;
@@ -533,7 +540,7 @@ __device__ inline int ground_contacts(const Geom& A, float margin, PC* out) {
     c.phi = A.x.z - A.p[0];
     c.p = v3(A.x.x, A.x.y, 0.5f * (A.x.z - A.p[0]));
     c.f = 0;
-    if (c.phi <= margin) out[n++] = c;
+    if (c.phi <= margin) out.push(c);
   } else if (A.shape == CAPSULE) {
     V3 p0, d;
     capsule_seg(A, p0, d);
@@ -545,7 +552,7 @@ __device__ inline int ground_contacts(const Geom& A, float margin, PC* out) {
       c.phi = e.z - A.p[0];
       c.p = v3(e.x, e.y, 0.5f * (e.z - A.p[0]));
       c.f = k;
-      if (c.phi <= margin) out[n++] = c;
+      if (c.phi <= margin) out.push(c);
     }
   } else {
     // corners with depth <= margin; at most the 4 deepest (ties: lower index)
@@ -579,31 +586,27 @@ __device__ inline int ground_contacts(const Geom& A, float margin, PC* out) {
       c.phi = zc[k];
       c.p = v3(cn[k].x, cn[k].y, 0.5f * cn[k].z);
       c.f = k;
-      out[n++] = c;
+      out.push(c);
     }
   }
-  return n;
 }
 
 // Contacts of the pair (A, B), normal from B to A.
-__device__ inline int collide(const Geom& A, const Geom& B, float margin, PC* out) {
-  int ta = A.shape, tb = B.shape, n;
+__device__ inline void collide(const Geom& A, const Geom& B, float margin, Out4& out) {
+  int ta = A.shape, tb = B.shape;
   bool flip = false;
   if (ta == SPHERE && tb == SPHERE) {
     PC c = sphere_sphere(A.x, A.p[0], B.x, B.p[0], 0);
-    n = 0;
-    if (c.phi <= margin) out[n++] = c;
-  } else if (ta == SPHERE && tb == BOX) n = sphere_box(A, B, margin, out);
-  else if (ta == BOX && tb == SPHERE) { n = sphere_box(B, A, margin, out); flip = true; }
-  else if (ta == SPHERE && tb == CAPSULE) n = sphere_capsule(A, B, margin, out);
-  else if (ta == CAPSULE && tb == SPHERE) { n = sphere_capsule(B, A, margin, out); flip = true; }
-  else if (ta == CAPSULE && tb == BOX) n = capsule_box(A, B, margin, out);
-  else if (ta == BOX && tb == CAPSULE) { n = capsule_box(B, A, margin, out); flip = true; }
-  else if (ta == BOX && tb == BOX) n = box_box(A, B, margin, out);
-  else n = capsule_capsule(A, B, margin, out);
-  if (flip)
-    for (int k = 0; k < n; k++) out[k].n = -out[k].n;
-  return n;
+    if (c.phi <= margin) out.push(c);
+  } else if (ta == SPHERE && tb == BOX) sphere_box(A, B, margin, out);
+  else if (ta == BOX && tb == SPHERE) { sphere_box(B, A, margin, out); flip = true; }
+  else if (ta == SPHERE && tb == CAPSULE) sphere_capsule(A, B, margin, out);
+  else if (ta == CAPSULE && tb == SPHERE) { sphere_capsule(B, A, margin, out); flip = true; }
+  else if (ta == CAPSULE && tb == BOX) capsule_box(A, B, margin, out);
+  else if (ta == BOX && tb == CAPSULE) { capsule_box(B, A, margin, out); flip = true; }
+  else if (ta == BOX && tb == BOX) box_box(A, B, margin, out);
+  else capsule_capsule(A, B, margin, out);
+  if (flip) out.flip();
 }
 
 }  // namespace rbs

@@ -11,6 +11,7 @@ constexpr int kMaxColours = 128;
 constexpr int kMaxBodiesPerScene = 1024;
 constexpr uint32_t kGroundPair = 0xFFFFu;
 constexpr uint32_t kGroundKey = 0xFFFu;
+constexpr int kTraceSlots = 16;
 
 enum { WARM_COLD = 0, WARM_PREV = 1, WARM_LEARNED = 2 };
 enum { SOLVER_PGS = 0, SOLVER_JACOBI = 1 };
@@ -62,7 +63,9 @@ struct StepParams {
   float* x_phi;             // [S*CM]
   float* x_lambda;          // [3][S*CM]
   int32_t* x_colour;        // [S*CM]
-  float* x_feat;            // [16][S*CM] (export and learned only)
+  float* x_feat;            // [16][S*CM] (export only)
+  float4* raw;              // [S*CM][2] narrowphase output, canonical order: (n, phi), (p, -)
+  float4* crec;             // [S*CM][13] solver records (Jacobian rows), colour-major order
   int32_t* st_pairs;
   int32_t* st_contacts;
   int32_t* st_colours;
@@ -77,16 +80,26 @@ struct StepParams {
   int solver;
   MlpParams mlp;
   const int32_t* scene_list;  // optional scene order (null: identity)
+  uint64_t* trace;            // optional [S][kTraceSlots] phase timestamps (null: off)
 };
 
-// LDS word offsets of one scene's working set.
+// LDS word offsets of one scene's working set.  Records are float4-aligned:
+//  geo  [NB][12]: (x, y, z, meta) (qw, qx, qy, qz) (p0, p1, p2, -)
+//  dyn  [NB][16]: (vx, vy, vz, inv_mass) (wx, wy, wz, mu) (Ixx, Iyy, Izz, Ixy) (Ixz, Iyz, e, -)
+//  ckey [CM]: contact keys, canonical order
+//  lam  [CM][4]: (lambda_n, lambda_t1, lambda_t2, phi), colour-major order
+//  perm [CM]: colour-major position -> canonical contact index
+// The per-contact solver constants live in global memory (StepParams::crec).
+// The scratch region is reused phase by phase: broadphase (pairs, AABBs,
+// body sort); colouring (colours, per-body lists); setup (previous keys);
+// solver (saved velocities, Jacobi snapshot and increments); outputs (arm
+// force partial sums).
 struct LdsLayout {
-  int bx, bq, bR, bv, bw, bim, bI, bprm, bmeta, bmu, be;
-  int ckey, cab, cn, cp, cphi, cm, cbias, cmu, clam, ccol, cperm;
+  int geo, dyn, ckey, lam, perm, misc, hist, hbase;
   int scr;
-  int lo, hi, skey, sval, skey2, sval2, pk, pk2, hist, hbase;
-  int prevk, deg, lstart, list, ck0, cv0, ck1, dl, vsave, snap, force;
-  int misc;
+  int pk, pk2, lo, hi, skey, sval, skey2, sval2;
+  int colour, deg, lstart, list, rank, prevk, cv0, ck1;
+  int vsave, snap, dl, force;
   int total;  // words
 };
 
@@ -96,60 +109,49 @@ inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int wave
   LdsLayout L;
   int o = 0;
   auto take = [&](int words) { int r = o; o += (words + 3) & ~3; return r; };
-  L.bx = take(3 * NB);
-  L.bq = take(4 * NB);
-  L.bR = take(9 * NB);
-  L.bv = take(3 * NB);
-  L.bw = take(3 * NB);
-  L.bim = take(NB);
-  L.bI = take(6 * NB);
-  L.bprm = take(3 * NB);
-  L.bmeta = take(NB);
-  L.bmu = take(NB);
-  L.be = take(NB);
+  L.geo = take(12 * NB);
+  L.dyn = take(16 * NB);
   L.ckey = take(CM);
-  L.cab = take(CM);
-  L.cn = take(3 * CM);
-  L.cp = take(3 * CM);
-  L.cphi = take(CM);
-  L.cm = take(3 * CM);
-  L.cbias = take(CM);
-  L.cmu = take(CM);
-  L.clam = take(3 * CM);
-  L.ccol = take(CM);
-  L.cperm = take(CM);
+  L.lam = take(4 * CM);
+  L.perm = take(CM);
   L.misc = take(kMiscWords);
   L.hist = take(256 * waves);
   L.hbase = take(256);
   L.scr = o;
-  // broadphase scratch
   int b = L.scr;
   auto tb = [&](int words) { int r = b; b += (words + 3) & ~3; return r; };
-  L.lo = tb(3 * NB);
-  L.hi = tb(3 * NB);
+  L.pk = tb(PM);
+  L.pk2 = tb(PM);
+  L.lo = tb(4 * NB);
+  L.hi = tb(4 * NB);
   L.skey = tb(NB);
   L.sval = tb(NB);
   L.skey2 = tb(NB);
   L.sval2 = tb(NB);
-  L.pk = tb(PM);
-  L.pk2 = tb(PM);
   int bend = b;
-  // post-narrowphase scratch (reuses the broadphase region)
   int p = L.scr;
   auto tp = [&](int words) { int r = p; p += (words + 3) & ~3; return r; };
-  L.prevk = tp(CM);
+  L.colour = tp(CM);
   L.deg = tp(NB + 1);
+  const int after_deg = p;
   L.lstart = tp(NB + 1);
   L.list = tp(2 * CM);
-  L.ck0 = tp(CM);
-  L.cv0 = tp(CM);
-  L.ck1 = tp(CM);
-  L.force = L.prevk;   // per-contact arm force, after the solve (prevk is dead)
-  L.dl = (solver == SOLVER_JACOBI) ? tp(3 * CM) : -1;
-  L.snap = (solver == SOLVER_JACOBI) ? tp(6 * NB) : -1;
-  L.vsave = (warm == WARM_LEARNED) ? tp(6 * NB) : -1;
-  int pend = p;
-  L.total = (bend > pend ? bend : pend);
+  L.rank = tp(CM);
+  int cend = p;
+  L.cv0 = L.list;       // colour sort after the colouring rounds
+  L.ck1 = L.list + CM;
+  L.prevk = L.list;     // setup runs after the colour sort
+  int q = after_deg;    // solver and outputs: lists are dead, deg and colour live on
+  auto tq = [&](int words) { int r = q; q += (words + 3) & ~3; return r; };
+  L.vsave = (warm == WARM_LEARNED) ? tq(8 * NB) : -1;
+  L.snap = (solver == SOLVER_JACOBI) ? tq(8 * NB) : -1;
+  L.dl = (solver == SOLVER_JACOBI) ? tq(4 * CM) : -1;
+  L.force = after_deg;  // outputs run after the solve
+  if (q < after_deg + CM) q = after_deg + ((CM + 3) & ~3);
+  int m = bend;
+  if (cend > m) m = cend;
+  if (q > m) m = q;
+  L.total = m;
   return L;
 }
 

@@ -1,6 +1,6 @@
 // step.hip -- one physics step (s_t, a_t) -> s_{t+1} for a batch of
 // independent scenes, one workgroup per scene, the scene's working set
-// resident in LDS (gfx950: 160 KB per CU).
+// resident in LDS (gfx950: 160 KB per CU) as float4-aligned records.
 //
 // Phases of one scene (barrier between phases):
 //  a1 arm forward kinematics at theta_t and link velocities from actions
@@ -12,11 +12,12 @@
 //  a6 narrowphase, one lane per pair, wave ballot/mbcnt compaction of the
 //     0..4 contacts per pair into the canonical contact list
 //  a7 previous-step impulses by binary search of the sorted cache keys
+//  a10 constraint setup (offsets, effective masses, bias, initial impulse)
 //  a9 first-fit colouring as the parallel fixed point of
 //     c_q = mex{ c_p : p < q shares a dynamic body with q }, then a stable
 //     one-digit radix sort into colour-major order
-//  a10 constraint setup; a11 projected Gauss-Seidel (or Jacobi) sweeps,
-//     one barrier per colour, max-residual reduction per sweep
+//  a11 projected Gauss-Seidel (or Jacobi) sweeps, one barrier per colour,
+//     max-residual reduction per sweep
 //  a12 semi-implicit position/orientation update; arm theta update + FK
 //  a13 cache, contact export, arm contact force, per-scene stats
 #include <hip/hip_runtime.h>
@@ -30,12 +31,13 @@ namespace rbs {
 
 typedef unsigned long long u64;
 
-// misc word slots
-enum {
-  M_NPAIRS = 0, M_NCONT = 1, M_FLAGS = 2, M_NCOL = 3, M_RES = 4, M_CHANGED = 5, M_SWEEPS = 6,
-  M_NPREV = 7, M_STOP = 8, M_WAVE = 16,  // per-wave partials from here (<= 4 waves * 4)
-  M_COLSTART = 32                        // unused by kernels with > 31 colours; see cstart
-};
+enum { M_NPAIRS = 0, M_NCONT = 1, M_FLAGS = 2, M_NCOL = 3, M_CHANGED = 5, M_WAVE = 16, M_SCAN = 32 };
+
+// Phase timestamp (constant-rate wall clock) of scene s, slot k, if tracing.
+#define TRACE(k)                                                                    \
+  do {                                                                              \
+    if (P.trace && tid == 0) P.trace[(long)s * kTraceSlots + (k)] = wall_clock64(); \
+  } while (0)
 
 __device__ __forceinline__ unsigned lanes_below(u64 m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -46,12 +48,49 @@ __device__ __forceinline__ uint32_t orderable(float f) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// In-place exclusive prefix sum of a[0..n) in LDS; every thread takes a
+// contiguous chunk; returns the total.  misc supplies per-wave slots.
+__device__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* misc) {
+  const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, w = tid >> 6, lane = tid & 63;
+  const int chunk = (n + T - 1) / T;
+  const int i0 = tid * chunk, i1 = min(n, i0 + chunk);
+  uint32_t sum = 0;
+  for (int i = i0; i < i1; i++) sum += a[i];
+  uint32_t incl = wave_incl_scan(sum);
+  if (lane == 63) misc[M_SCAN + w] = incl;
+  __syncthreads();
+  uint32_t base = 0, total = 0;
+  for (int ww = 0; ww < W; ww++) {
+    uint32_t t = misc[M_SCAN + ww];
+    if (ww < w) base += t;
+    total += t;
+  }
+  uint32_t run = base + incl - sum;
+  for (int i = i0; i < i1; i++) {
+    uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  __syncthreads();
+  return total;
+}
+
 // Stable LSD radix sort of n (key, value) pairs held in LDS, `passes`
 // 8-bit digits from bit `shift0`.  Ranks within a wave come from eight
 // ballots that isolate the lanes holding the same digit.  Returns 1 if the
 // sorted data ended in (k1, v1), 0 if in (k0, v0).
 __device__ int lds_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int n, int shift0, int passes,
-                              uint32_t* hist, uint32_t* base) {
+                              uint32_t* hist, uint32_t* base, uint32_t* misc) {
   const int T = blockDim.x, tid = threadIdx.x, W = T >> 6, w = tid >> 6;
   int swapped = 0;
   for (int ps = 0; ps < passes; ps++) {
@@ -61,11 +100,7 @@ __device__ int lds_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t
     __syncthreads();
     for (int i = tid; i < n; i += T) atomicAdd(&base[(k0[i] >> sh) & 255u], 1u);
     __syncthreads();
-    if (tid == 0) {
-      uint32_t run = 0;
-      for (int d = 0; d < 256; d++) { uint32_t c = base[d]; base[d] = run; run += c; }
-    }
-    __syncthreads();
+    block_exclusive_scan(base, 256, misc);
     for (int t0 = 0; t0 < n; t0 += T) {
       const int i = t0 + tid;
       const bool valid = i < n;
@@ -87,12 +122,14 @@ __device__ int lds_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t
         v1[off] = val;
       }
       __syncthreads();
-      for (int dd = tid; dd < 256; dd += T) {
-        uint32_t s = 0;
-        for (int ww = 0; ww < W; ww++) { s += hist[ww * 256 + dd]; hist[ww * 256 + dd] = 0u; }
-        base[dd] += s;
+      if (t0 + T < n) {
+        for (int dd = tid; dd < 256; dd += T) {
+          uint32_t s = 0;
+          for (int ww = 0; ww < W; ww++) { s += hist[ww * 256 + dd]; hist[ww * 256 + dd] = 0u; }
+          base[dd] += s;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
     uint32_t* t;
     t = k0; k0 = k1; k1 = t;
@@ -108,22 +145,367 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+// Block-wide maximum of non-negative floats (one value per thread).
+__device__ __forceinline__ float block_max(float v, uint32_t* misc) {
+  const int tid = threadIdx.x, W = blockDim.x >> 6;
+  v = wave_max(v);
+  if ((tid & 63) == 0) misc[M_WAVE + (tid >> 6)] = __float_as_uint(v);
+  __syncthreads();
+  float r = 0.f;
+  for (int w = 0; w < W; w++) r = fmaxf(r, __uint_as_float(misc[M_WAVE + w]));
+  __syncthreads();
+  return r;
+}
+
 struct Smem {
   float* f;
   uint32_t* u;
 };
 
-__device__ __forceinline__ V3 ld3(const float* a, int stride, int i) { return v3(a[i], a[stride + i], a[2 * stride + i]); }
-__device__ __forceinline__ void st3(float* a, int stride, int i, V3 v) {
-  a[i] = v.x;
-  a[stride + i] = v.y;
-  a[2 * stride + i] = v.z;
+// Hardware reciprocal (v_rcp_f32, about 1 ulp) for the solver's hot path.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Tangent basis of a unit normal (Duff et al. 2017) with a hardware
+// reciprocal; used for every contact row of the step (setup, sweeps, cache).
+__device__ __forceinline__ void tangents_fast(V3 n, V3& t1, V3& t2) {
+  float sgn = copysignf(1.0f, n.z);
+  float a = -frcp(sgn + n.z);
+  float b = n.x * n.y * a;
+  t1 = v3(1.0f + sgn * n.x * n.x * a, sgn * b, -sgn * n.x);
+  t2 = v3(b, sgn + n.y * n.y * a, -n.y);
 }
 
-// world inverse inertia (symmetric: xx yy zz xy xz yz) times a vector
-__device__ __forceinline__ V3 Iw_mul(const float* I, int NB, int i, V3 a) {
-  float xx = I[i], yy = I[NB + i], zz = I[2 * NB + i], xy = I[3 * NB + i], xz = I[4 * NB + i], yz = I[5 * NB + i];
-  return v3(xx * a.x + xy * a.y + xz * a.z, xy * a.x + yy * a.y + yz * a.z, xz * a.x + yz * a.y + zz * a.z);
+__device__ __forceinline__ float4 ld4(const float* base, int i) { return reinterpret_cast<const float4*>(base)[i]; }
+__device__ __forceinline__ void st4(float* base, int i, float4 v) { reinterpret_cast<float4*>(base)[i] = v; }
+__device__ __forceinline__ V3 xyz(float4 a) { return v3(a.x, a.y, a.z); }
+__device__ __forceinline__ float4 f4(V3 a, float w) { return make_float4(a.x, a.y, a.z, w); }
+
+// body geometry: float4 records 3i (x, meta), 3i+1 (q), 3i+2 (params)
+__device__ __forceinline__ Geom load_geom(const LdsLayout& L, Smem S, int i) {
+  float4 g0 = ld4(S.f + L.geo, 3 * i), g1 = ld4(S.f + L.geo, 3 * i + 1), g2 = ld4(S.f + L.geo, 3 * i + 2);
+  Geom g;
+  g.shape = (int)(__float_as_uint(g0.w) & 255u);
+  g.x = xyz(g0);
+  g.R = quat_R(g1.x, g1.y, g1.z, g1.w);
+  g.p[0] = g2.x;
+  g.p[1] = g2.y;
+  g.p[2] = g2.z;
+  return g;
+}
+
+__device__ __forceinline__ uint32_t body_meta(const LdsLayout& L, Smem S, int i) {
+  return __float_as_uint(S.f[L.geo + 12 * i + 3]);
+}
+__device__ __forceinline__ bool is_dyn_meta(uint32_t meta) { return ((meta >> 8) & 255u) == DYNAMIC; }
+
+// Dynamic state of a body in registers.
+struct Dyn {
+  V3 v, w;
+  float im, mu;
+  float I[6];  // xx yy zz xy xz yz
+};
+
+__device__ __forceinline__ Dyn load_dyn(const LdsLayout& L, Smem S, int i) {
+  Dyn d;
+  float4 d0 = ld4(S.f + L.dyn, 4 * i), d1 = ld4(S.f + L.dyn, 4 * i + 1);
+  float4 d2 = ld4(S.f + L.dyn, 4 * i + 2), d3 = ld4(S.f + L.dyn, 4 * i + 3);
+  d.v = xyz(d0);
+  d.im = d0.w;
+  d.w = xyz(d1);
+  d.mu = d1.w;
+  d.I[0] = d2.x; d.I[1] = d2.y; d.I[2] = d2.z; d.I[3] = d2.w; d.I[4] = d3.x; d.I[5] = d3.y;
+  return d;
+}
+
+__device__ __forceinline__ V3 Imul(const float* I, V3 a) {
+  return v3(I[0] * a.x + I[3] * a.y + I[4] * a.z, I[3] * a.x + I[1] * a.y + I[5] * a.z,
+            I[4] * a.x + I[5] * a.y + I[2] * a.z);
+}
+
+__device__ __forceinline__ void proj_disk(float& l1, float& l2, float lim) {
+  float Ls = sqrtf(l1 * l1 + l2 * l2);
+  if (Ls > lim) {
+    if (Ls > 0.f) { float f = lim * frcp(Ls); l1 *= f; l2 *= f; }
+    else { l1 = 0.f; l2 = 0.f; }
+  }
+}
+
+// Solver record of one contact: the three rows d in {n, t1, t2} with the
+// Jacobian parts r_a x d, r_b x d, the inverse-inertia images
+// I_a^-1 (r_a x d), I_b^-1 (r_b x d), effective masses, bias, friction, key
+// and the Jacobi scale; 13 float4 in global memory, colour-major order:
+//  0 (n, m_n) 1 (t1, m_t1) 2 (t2, m_t2) 3 (ca_n, bias) 4 (ca_1, mu) 5 (ca_2, key)
+//  6 (cb_n, jsc) 7 (cb_1, ia_n.x) 8 (cb_2, ia_n.y) 9 (ia_n.z, ia_1) 10 (ia_2, ib_n.x)
+//  11 (ib_n.yz, ib_1.xy) 12 (ib_1.z, ib_2)
+constexpr int kRec = 13;
+
+struct Rec {
+  float4 r[kRec];
+};
+
+struct Row {
+  V3 d, ca, cb, ia, ib;
+  float m;
+};
+
+__device__ __forceinline__ Rec load_rec(const float4* rec, int i) {
+  Rec R;
+#pragma unroll
+  for (int k = 0; k < kRec; k++) R.r[k] = rec[kRec * i + k];
+  return R;
+}
+
+__device__ __forceinline__ int rec_a(const Rec& R) { return (int)(__float_as_uint(R.r[5].w) >> 20); }
+__device__ __forceinline__ int rec_b(const Rec& R) {
+  uint32_t bk = (__float_as_uint(R.r[5].w) >> 8) & 0xFFFu;
+  return bk == kGroundKey ? -1 : (int)bk;
+}
+
+__device__ __forceinline__ Row rec_row(const Rec& R, int k) {
+  Row w;
+  if (k == 0) {
+    w.d = xyz(R.r[0]); w.m = R.r[0].w; w.ca = xyz(R.r[3]); w.cb = xyz(R.r[6]);
+    w.ia = v3(R.r[7].w, R.r[8].w, R.r[9].x);
+    w.ib = v3(R.r[10].w, R.r[11].x, R.r[11].y);
+  } else if (k == 1) {
+    w.d = xyz(R.r[1]); w.m = R.r[1].w; w.ca = xyz(R.r[4]); w.cb = xyz(R.r[7]);
+    w.ia = v3(R.r[9].y, R.r[9].z, R.r[9].w);
+    w.ib = v3(R.r[11].z, R.r[11].w, R.r[12].x);
+  } else {
+    w.d = xyz(R.r[2]); w.m = R.r[2].w; w.ca = xyz(R.r[5]); w.cb = xyz(R.r[8]);
+    w.ia = xyz(R.r[10]);
+    w.ib = v3(R.r[12].y, R.r[12].z, R.r[12].w);
+  }
+  return w;
+}
+
+__device__ __forceinline__ void store_rec(float4* rec, int i, const Row* w, float bias, float mu, uint32_t key,
+                                          float jsc) {
+  float4* o = rec + kRec * i;
+  o[0] = f4(w[0].d, w[0].m);
+  o[1] = f4(w[1].d, w[1].m);
+  o[2] = f4(w[2].d, w[2].m);
+  o[3] = f4(w[0].ca, bias);
+  o[4] = f4(w[1].ca, mu);
+  o[5] = f4(w[2].ca, __uint_as_float(key));
+  o[6] = f4(w[0].cb, jsc);
+  o[7] = f4(w[1].cb, w[0].ia.x);
+  o[8] = f4(w[2].cb, w[0].ia.y);
+  o[9] = make_float4(w[0].ia.z, w[1].ia.x, w[1].ia.y, w[1].ia.z);
+  o[10] = f4(w[2].ia, w[0].ib.x);
+  o[11] = make_float4(w[0].ib.y, w[0].ib.z, w[1].ib.x, w[1].ib.y);
+  o[12] = make_float4(w[1].ib.z, w[2].ib.x, w[2].ib.y, w[2].ib.z);
+}
+
+// Body velocities in registers (dynamic iff im > 0).
+struct Vel {
+  V3 v, w;
+  float im, mu;
+};
+
+__device__ __forceinline__ Vel load_vel(const LdsLayout& L, Smem S, int i) {
+  Vel b;
+  if (i < 0) {
+    b.v = v3(0.f, 0.f, 0.f);
+    b.w = v3(0.f, 0.f, 0.f);
+    b.im = 0.f;
+    b.mu = 0.f;
+    return b;
+  }
+  float4 d0 = ld4(S.f + L.dyn, 4 * i), d1 = ld4(S.f + L.dyn, 4 * i + 1);
+  b.v = xyz(d0);
+  b.im = d0.w;
+  b.w = xyz(d1);
+  b.mu = d1.w;
+  return b;
+}
+
+__device__ __forceinline__ void store_vel(const LdsLayout& L, Smem S, int i, const Vel& b) {
+  st4(S.f + L.dyn, 4 * i, f4(b.v, b.im));
+  st4(S.f + L.dyn, 4 * i + 1, f4(b.w, b.mu));
+}
+
+// Velocity of contact row w: d . (v_a - v_b) + (r_a x d) . w_a - (r_b x d) . w_b
+__device__ __forceinline__ float row_u(const Row& w, const Vel& A, const Vel& B) {
+  return dot(w.d, A.v - B.v) + dot(w.ca, A.w) - dot(w.cb, B.w);
+}
+
+__device__ __forceinline__ void row_apply(const Row& w, Vel& A, Vel& B, float dl) {
+  A.v = A.v + w.d * (A.im * dl);
+  A.w = A.w + w.ia * dl;
+  B.v = B.v - w.d * (B.im * dl);
+  B.w = B.w - w.ib * dl;
+}
+
+// Synchronisation between colour batches: a single-wave workgroup needs only
+// a compiler fence (its LDS operations complete in issue order), which keeps
+// prefetched global loads in flight; wider workgroups use a barrier.
+__device__ __forceinline__ void colour_sync() {
+  if (blockDim.x == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// One Gauss-Seidel update at colour-major position i: normal row, then both
+// friction rows from the velocities after the normal update.  Returns the
+// residual max |dlambda| * k.
+__device__ __forceinline__ float pgs_update(const LdsLayout& L, Smem S, const Rec& R, int i) {
+  const int a = rec_a(R), b = rec_b(R);
+  float4 lam = ld4(S.f + L.lam, i);
+  Vel A = load_vel(L, S, a);
+  Vel B = load_vel(L, S, b);
+  const float bias = R.r[3].w, mu = R.r[4].w;
+  Row wn = rec_row(R, 0);
+  float ln = fmaxf(0.f, lam.x + wn.m * (bias - row_u(wn, A, B)));
+  float dn = ln - lam.x;
+  row_apply(wn, A, B, dn);
+  Row w1 = rec_row(R, 1), w2 = rec_row(R, 2);
+  float l1 = lam.y - w1.m * row_u(w1, A, B);
+  float l2 = lam.z - w2.m * row_u(w2, A, B);
+  proj_disk(l1, l2, mu * ln);
+  float d1 = l1 - lam.y, d2 = l2 - lam.z;
+  row_apply(w1, A, B, d1);
+  row_apply(w2, A, B, d2);
+  if (A.im > 0.f) store_vel(L, S, a, A);
+  if (B.im > 0.f) store_vel(L, S, b, B);
+  st4(S.f + L.lam, i, make_float4(ln, l1, l2, lam.w));
+  return fmaxf(fmaxf(fabsf(dn) * frcp(wn.m), fabsf(d1) * frcp(w1.m)), fabsf(d2) * frcp(w2.m));
+}
+
+// Applies the current impulses of every contact, colour-major (warm start).
+__device__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int ncol, const uint32_t* cstart) {
+  for (int c = 0; c < ncol; c++) {
+    for (int i = (int)cstart[c] + threadIdx.x; i < (int)cstart[c + 1]; i += blockDim.x) {
+      Rec R = load_rec(rec, i);
+      const int a = rec_a(R), b = rec_b(R);
+      float4 lam = ld4(S.f + L.lam, i);
+      Vel A = load_vel(L, S, a);
+      Vel B = load_vel(L, S, b);
+      row_apply(rec_row(R, 0), A, B, lam.x);
+      row_apply(rec_row(R, 1), A, B, lam.y);
+      row_apply(rec_row(R, 2), A, B, lam.z);
+      if (A.im > 0.f) store_vel(L, S, a, A);
+      if (B.im > 0.f) store_vel(L, S, b, B);
+    }
+    colour_sync();
+  }
+}
+
+// Sweeps of projected Gauss-Seidel, colour batch after colour batch; the
+// record of a lane's next batch is loaded while the current one is solved.
+// Stops after `iters` sweeps or once a sweep's residual is <= tol (tol > 0).
+__device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int ncol, const uint32_t* cstart, int iters,
+                          float tol, uint32_t* misc, int* sweeps_out, float* res_out) {
+  const int tid = threadIdx.x, T = blockDim.x;
+  int sweeps = 0;
+  float res = 0.f;
+  if (ncol == 0) {
+    *sweeps_out = iters > 0 ? 1 : 0;
+    *res_out = 0.f;
+    return;
+  }
+  const int last = (int)cstart[ncol] - 1;  // >= 0: ncol > 0 implies contacts
+  int i = (int)cstart[0] + tid;
+  bool has = i < (int)cstart[1];
+  // loads are unconditional (index clamped to a valid record) so that the
+  // next batch's loads stay in flight while the current batch is solved
+  Rec cur = load_rec(rec, min(i, last));
+  for (int it = 0; it < iters; it++) {
+    float r = 0.f;
+    for (int c = 0; c < ncol; c++) {
+      const int e = (int)cstart[c + 1];
+      // next batch: colour c + 1, or colour 0 of the next sweep
+      const int cn = c + 1 < ncol ? c + 1 : 0;
+      const int inext = (int)cstart[cn] + tid;
+      const bool hnext = inext < (int)cstart[cn + 1];
+      Rec nxt = load_rec(rec, min(inext, last));
+      if (has) r = fmaxf(r, pgs_update(L, S, cur, i));
+      for (int i2 = i + T; i2 < e; i2 += T) r = fmaxf(r, pgs_update(L, S, load_rec(rec, i2), i2));
+      colour_sync();
+      cur = nxt;
+      has = hnext;
+      i = inext;
+    }
+    sweeps++;
+    if (tol > 0.f || it == iters - 1) {
+      res = T == 64 ? wave_max(r) : block_max(r, misc);
+      if (tol > 0.f && res <= tol) break;
+    }
+  }
+  *sweeps_out = sweeps;
+  *res_out = res;
+}
+
+// Sweeps of Jacobi: rows read the velocities of the sweep start, increments
+// scaled by 1/max(n_a, n_b) contacts per dynamic body (from the record),
+// applied colour-major.
+__device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int nb, int nc, int ncol,
+                             const uint32_t* cstart, int iters, float tol, uint32_t* misc, int* sweeps_out,
+                             float* res_out) {
+  const int tid = threadIdx.x, T = blockDim.x;
+  float* snap = S.f + L.snap;
+  int sweeps = 0;
+  float res = 0.f;
+  for (int it = 0; it < iters; it++) {
+    for (int i = tid; i < nb; i += T) {
+      st4(snap, 2 * i, ld4(S.f + L.dyn, 4 * i));
+      st4(snap, 2 * i + 1, ld4(S.f + L.dyn, 4 * i + 1));
+    }
+    __syncthreads();
+    float r = 0.f;
+    for (int i = tid; i < nc; i += T) {
+      Rec R = load_rec(rec, i);
+      const int a = rec_a(R), b = rec_b(R);
+      float4 lam = ld4(S.f + L.lam, i);
+      Vel A, B;
+      A.v = xyz(ld4(snap, 2 * a));
+      A.w = xyz(ld4(snap, 2 * a + 1));
+      if (b >= 0) {
+        B.v = xyz(ld4(snap, 2 * b));
+        B.w = xyz(ld4(snap, 2 * b + 1));
+      } else {
+        B.v = v3(0.f, 0.f, 0.f);
+        B.w = v3(0.f, 0.f, 0.f);
+      }
+      const float bias = R.r[3].w, mu = R.r[4].w, sc = R.r[6].w;
+      Row wn = rec_row(R, 0), w1 = rec_row(R, 1), w2 = rec_row(R, 2);
+      float ln = fmaxf(0.f, lam.x + sc * wn.m * (bias - row_u(wn, A, B)));
+      float l1 = lam.y - sc * w1.m * row_u(w1, A, B);
+      float l2 = lam.z - sc * w2.m * row_u(w2, A, B);
+      proj_disk(l1, l2, mu * ln);
+      float dn = ln - lam.x, d1 = l1 - lam.y, d2 = l2 - lam.z;
+      st4(S.f + L.dl, i, make_float4(dn, d1, d2, 0.f));
+      st4(S.f + L.lam, i, make_float4(ln, l1, l2, lam.w));
+      r = fmaxf(r, fmaxf(fmaxf(fabsf(dn) * frcp(wn.m), fabsf(d1) * frcp(w1.m)), fabsf(d2) * frcp(w2.m)));
+    }
+    __syncthreads();
+    for (int c = 0; c < ncol; c++) {
+      for (int i = (int)cstart[c] + tid; i < (int)cstart[c + 1]; i += T) {
+        Rec R = load_rec(rec, i);
+        const int a = rec_a(R), b = rec_b(R);
+        float4 dl = ld4(S.f + L.dl, i);
+        Vel A = load_vel(L, S, a);
+        Vel B = load_vel(L, S, b);
+        row_apply(rec_row(R, 0), A, B, dl.x);
+        row_apply(rec_row(R, 1), A, B, dl.y);
+        row_apply(rec_row(R, 2), A, B, dl.z);
+        if (A.im > 0.f) store_vel(L, S, a, A);
+        if (B.im > 0.f) store_vel(L, S, b, B);
+      }
+      __syncthreads();
+    }
+    sweeps++;
+    if (tol > 0.f || it == iters - 1) {
+      res = block_max(r, misc);
+      if (tol > 0.f && res <= tol) break;
+    }
+  }
+  *sweeps_out = sweeps;
+  *res_out = res;
 }
 
 // Arm forward kinematics: joint axes z, y, z, y, z, y, z in each parent frame,
@@ -153,22 +535,18 @@ __device__ void arm_chain(const float* base, const float* th, const float* len, 
   }
 }
 
-// Arm link poses (and, if thd, link velocities from joint velocities) into
-// the LDS body slots b0..b0+6.
-__device__ void arm_fk(const StepParams& P, const LdsLayout& L, Smem S, int NB, int b0, const float* base,
-                       const float* th, const float* thd) {
+// Arm link poses (and, if thd, link velocities) into the LDS records of
+// bodies b0..b0+6.
+__device__ void arm_fk(const StepParams& P, const LdsLayout& L, Smem S, int b0, const float* base, const float* th,
+                       const float* thd) {
   V3 c[7], o[7], ax[7];
   float q[7][4];
   arm_chain(base, th, P.link_len, c, q, o, ax);
   for (int k = 0; k < 7; k++) {
     int bi = b0 + k;
-    st3(S.f + L.bx, NB, bi, c[k]);
-    for (int j = 0; j < 4; j++) S.f[L.bq + j * NB + bi] = q[k][j];
-    M3 R = quat_R(q[k][0], q[k][1], q[k][2], q[k][3]);
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-      for (int cc = 0; cc < 3; cc++) S.f[L.bR + (3 * r + cc) * NB + bi] = R.m[r][cc];
+    float meta = S.f[L.geo + 12 * bi + 3];
+    st4(S.f + L.geo, 3 * bi, f4(c[k], meta));
+    st4(S.f + L.geo, 3 * bi + 1, make_float4(q[k][0], q[k][1], q[k][2], q[k][3]));
   }
   if (thd) {
     for (int k = 0; k < 7; k++) {
@@ -177,201 +555,17 @@ __device__ void arm_fk(const StepParams& P, const LdsLayout& L, Smem S, int NB, 
         wv = wv + ax[j] * thd[j];
         vv = vv + cross(ax[j], c[k] - o[j]) * thd[j];
       }
-      st3(S.f + L.bv, NB, b0 + k, vv);
-      st3(S.f + L.bw, NB, b0 + k, wv);
+      int bi = b0 + k;
+      float mu = S.f[L.dyn + 16 * bi + 7];
+      st4(S.f + L.dyn, 4 * bi, f4(vv, 0.f));
+      st4(S.f + L.dyn, 4 * bi + 1, f4(wv, mu));
     }
   }
-}
-
-__device__ __forceinline__ Geom load_geom(const LdsLayout& L, Smem S, int NB, int i) {
-  Geom g;
-  g.shape = (int)(S.u[L.bmeta + i] & 255u);
-  g.x = ld3(S.f + L.bx, NB, i);
-#pragma unroll
-  for (int r = 0; r < 3; r++)
-#pragma unroll
-    for (int c = 0; c < 3; c++) g.R.m[r][c] = S.f[L.bR + (3 * r + c) * NB + i];
-  g.p[0] = S.f[L.bprm + i];
-  g.p[1] = S.f[L.bprm + NB + i];
-  g.p[2] = S.f[L.bprm + 2 * NB + i];
-  return g;
-}
-
-// Velocity of body i at offset r (ground: zero).
-__device__ __forceinline__ V3 point_vel(const LdsLayout& L, Smem S, int NB, int i, V3 r) {
-  if (i == 0xFFFF) return v3(0.f, 0.f, 0.f);
-  return ld3(S.f + L.bv, NB, i) + cross(ld3(S.f + L.bw, NB, i), r);
-}
-
-__device__ __forceinline__ bool is_dyn(const LdsLayout& L, Smem S, int i) {
-  return i != 0xFFFF && ((S.u[L.bmeta + i] >> 8) & 255u) == DYNAMIC;
-}
-
-// Apply impulse P at the contact (onto a; -P onto b), dynamic bodies only.
-__device__ __forceinline__ void apply_impulse(const LdsLayout& L, Smem S, int NB, int a, int b, V3 ra, V3 rb, V3 P) {
-  if (is_dyn(L, S, a)) {
-    float im = S.f[L.bim + a];
-    st3(S.f + L.bv, NB, a, ld3(S.f + L.bv, NB, a) + P * im);
-    st3(S.f + L.bw, NB, a, ld3(S.f + L.bw, NB, a) + Iw_mul(S.f + L.bI, NB, a, cross(ra, P)));
-  }
-  if (is_dyn(L, S, b)) {
-    float im = S.f[L.bim + b];
-    st3(S.f + L.bv, NB, b, ld3(S.f + L.bv, NB, b) - P * im);
-    st3(S.f + L.bw, NB, b, ld3(S.f + L.bw, NB, b) - Iw_mul(S.f + L.bI, NB, b, cross(rb, P)));
-  }
-}
-
-__device__ __forceinline__ void proj_disk(float& l1, float& l2, float lim) {
-  float Ls = sqrtf(l1 * l1 + l2 * l2);
-  if (Ls > lim) {
-    if (Ls > 0.f) { float f = lim / Ls; l1 *= f; l2 *= f; }
-    else { l1 = 0.f; l2 = 0.f; }
-  }
-}
-
-// Contact q: bodies, offsets.
-__device__ __forceinline__ void contact_geom(const LdsLayout& L, Smem S, int NB, int CM, int q, int& a, int& b, V3& n,
-                                             V3& ra, V3& rb) {
-  uint32_t ab = S.u[L.cab + q];
-  a = (int)(ab & 0xFFFFu);
-  b = (int)(ab >> 16);
-  n = ld3(S.f + L.cn, CM, q);
-  V3 p = ld3(S.f + L.cp, CM, q);
-  ra = p - ld3(S.f + L.bx, NB, a);
-  rb = b == 0xFFFF ? v3(0.f, 0.f, 0.f) : p - ld3(S.f + L.bx, NB, b);
-}
-
-// One Gauss-Seidel update of contact q: normal row, then both friction rows
-// from the velocities after the normal update.  Returns max |dlambda| * k.
-__device__ __forceinline__ float pgs_contact(const LdsLayout& L, Smem S, int NB, int CM, int q) {
-  int a, b;
-  V3 n, ra, rb;
-  contact_geom(L, S, NB, CM, q, a, b, n, ra, rb);
-  float mn = S.f[L.cm + q], m1 = S.f[L.cm + CM + q], m2 = S.f[L.cm + 2 * CM + q];
-  float ln0 = S.f[L.clam + q], l10 = S.f[L.clam + CM + q], l20 = S.f[L.clam + 2 * CM + q];
-  V3 vr = point_vel(L, S, NB, a, ra) - point_vel(L, S, NB, b, rb);
-  float u = dot(n, vr);
-  float ln = fmaxf(0.f, ln0 + mn * (S.f[L.cbias + q] - u));
-  float dn = ln - ln0;
-  apply_impulse(L, S, NB, a, b, ra, rb, n * dn);
-  vr = point_vel(L, S, NB, a, ra) - point_vel(L, S, NB, b, rb);
-  V3 t1, t2;
-  tangents(n, t1, t2);
-  float l1 = l10 - m1 * dot(t1, vr);
-  float l2 = l20 - m2 * dot(t2, vr);
-  proj_disk(l1, l2, S.f[L.cmu + q] * ln);
-  float d1 = l1 - l10, d2 = l2 - l20;
-  apply_impulse(L, S, NB, a, b, ra, rb, t1 * d1 + t2 * d2);
-  S.f[L.clam + q] = ln;
-  S.f[L.clam + CM + q] = l1;
-  S.f[L.clam + 2 * CM + q] = l2;
-  return fmaxf(fmaxf(fabsf(dn) / mn, fabsf(d1) / m1), fabsf(d2) / m2);
-}
-
-// Block-wide maximum of non-negative floats (one value per thread).
-__device__ __forceinline__ float block_max(float v, uint32_t* misc) {
-  const int tid = threadIdx.x, W = blockDim.x >> 6;
-  v = wave_max(v);
-  if ((tid & 63) == 0) misc[M_WAVE + (tid >> 6)] = __float_as_uint(v);
-  __syncthreads();
-  float r = 0.f;
-  for (int w = 0; w < W; w++) r = fmaxf(r, __uint_as_float(misc[M_WAVE + w]));
-  __syncthreads();
-  return r;
-}
-
-// Colour-major pass applying the current impulses of every contact (warm start).
-__device__ void apply_all(const LdsLayout& L, Smem S, int NB, int CM, int nc, int ncol, const uint32_t* cstart) {
-  for (int c = 0; c < ncol; c++) {
-    for (int i = (int)cstart[c] + threadIdx.x; i < (int)cstart[c + 1]; i += blockDim.x) {
-      int q = (int)S.u[L.cperm + i];
-      int a, b;
-      V3 n, ra, rb;
-      contact_geom(L, S, NB, CM, q, a, b, n, ra, rb);
-      V3 t1, t2;
-      tangents(n, t1, t2);
-      V3 P = n * S.f[L.clam + q] + t1 * S.f[L.clam + CM + q] + t2 * S.f[L.clam + 2 * CM + q];
-      apply_impulse(L, S, NB, a, b, ra, rb, P);
-    }
-    __syncthreads();
-  }
-}
-
-__device__ float sweeps_pgs(const LdsLayout& L, Smem S, int NB, int CM, int ncol, const uint32_t* cstart) {
-  float r = 0.f;
-  for (int c = 0; c < ncol; c++) {
-    for (int i = (int)cstart[c] + threadIdx.x; i < (int)cstart[c + 1]; i += blockDim.x)
-      r = fmaxf(r, pgs_contact(L, S, NB, CM, (int)S.u[L.cperm + i]));
-    __syncthreads();
-  }
-  return r;
-}
-
-// One Jacobi sweep: rows read the velocities of the sweep start, increments
-// divided by max(n_a, n_b) contacts per dynamic body, applied colour-major.
-__device__ float sweep_jacobi(const LdsLayout& L, Smem S, int NB, int CM, int nb, int nc, int ncol,
-                              const uint32_t* cstart) {
-  const int tid = threadIdx.x, T = blockDim.x;
-  float* snap = S.f + L.snap;
-  for (int i = tid; i < nb; i += T) {
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-      snap[k * NB + i] = S.f[L.bv + k * NB + i];
-      snap[(3 + k) * NB + i] = S.f[L.bw + k * NB + i];
-    }
-  }
-  __syncthreads();
-  float r = 0.f;
-  const uint32_t* deg = S.u + L.deg;
-  for (int q = tid; q < nc; q += T) {
-    int a, b;
-    V3 n, ra, rb;
-    contact_geom(L, S, NB, CM, q, a, b, n, ra, rb);
-    V3 va = v3(snap[a], snap[NB + a], snap[2 * NB + a]) + cross(v3(snap[3 * NB + a], snap[4 * NB + a], snap[5 * NB + a]), ra);
-    V3 vb = v3(0.f, 0.f, 0.f);
-    if (b != 0xFFFF)
-      vb = v3(snap[b], snap[NB + b], snap[2 * NB + b]) + cross(v3(snap[3 * NB + b], snap[4 * NB + b], snap[5 * NB + b]), rb);
-    V3 vr = va - vb;
-    int na = is_dyn(L, S, a) ? (int)deg[a] : 0;
-    int nbb = is_dyn(L, S, b) ? (int)deg[b] : 0;
-    float sc = 1.0f / (float)(na > nbb ? na : nbb);
-    float mn = S.f[L.cm + q], m1 = S.f[L.cm + CM + q], m2 = S.f[L.cm + 2 * CM + q];
-    float ln0 = S.f[L.clam + q], l10 = S.f[L.clam + CM + q], l20 = S.f[L.clam + 2 * CM + q];
-    float ln = fmaxf(0.f, ln0 + sc * mn * (S.f[L.cbias + q] - dot(n, vr)));
-    V3 t1, t2;
-    tangents(n, t1, t2);
-    float l1 = l10 - sc * m1 * dot(t1, vr);
-    float l2 = l20 - sc * m2 * dot(t2, vr);
-    proj_disk(l1, l2, S.f[L.cmu + q] * ln);
-    float dn = ln - ln0, d1 = l1 - l10, d2 = l2 - l20;
-    S.f[L.dl + q] = dn;
-    S.f[L.dl + CM + q] = d1;
-    S.f[L.dl + 2 * CM + q] = d2;
-    S.f[L.clam + q] = ln;
-    S.f[L.clam + CM + q] = l1;
-    S.f[L.clam + 2 * CM + q] = l2;
-    r = fmaxf(r, fmaxf(fmaxf(fabsf(dn) / mn, fabsf(d1) / m1), fabsf(d2) / m2));
-  }
-  __syncthreads();
-  for (int c = 0; c < ncol; c++) {
-    for (int i = (int)cstart[c] + tid; i < (int)cstart[c + 1]; i += T) {
-      int q = (int)S.u[L.cperm + i];
-      int a, b;
-      V3 n, ra, rb;
-      contact_geom(L, S, NB, CM, q, a, b, n, ra, rb);
-      V3 t1, t2;
-      tangents(n, t1, t2);
-      apply_impulse(L, S, NB, a, b, ra, rb, n * S.f[L.dl + q]);
-      apply_impulse(L, S, NB, a, b, ra, rb, t1 * S.f[L.dl + CM + q] + t2 * S.f[L.dl + 2 * CM + q]);
-    }
-    __syncthreads();
-  }
-  return r;
 }
 
 __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
-  extern __shared__ float smem_f[];
-  Smem S{smem_f, reinterpret_cast<uint32_t*>(smem_f)};
+  extern __shared__ float4 smem_f4[];
+  Smem S{reinterpret_cast<float*>(smem_f4), reinterpret_cast<uint32_t*>(smem_f4)};
   const int tid = threadIdx.x, T = blockDim.x;
   const int s = P.scene_list ? P.scene_list[blockIdx.x] : (int)blockIdx.x;
   const int b0 = P.body_offset[s];
@@ -379,33 +573,33 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
   const int NB = P.NB, PM = P.PM, CM = P.CM;
   const long N = P.n_bodies;
   uint32_t* misc = S.u + L.misc;
+  float4* raw = P.raw + (long)s * CM * 2;
+  float4* rec = P.crec + (long)s * CM * kRec;
   const float dt = P.dt;
   if (nb > NB) {  // host guarantees otherwise; leave the scene untouched
     if (tid == 0) P.st_flags[s] = FLAG_CAPACITY;
     return;
   }
   if (tid < kMiscWords) misc[tid] = 0u;
+  TRACE(0);
 
-  // ---- load bodies (a2) ------------------------------------------------
+  // ---- load bodies; a2: gravity, world inverse inertia -----------------
   const V3 g = v3(P.gx, P.gy, P.gz);
   for (int i = tid; i < nb; i += T) {
     const long gi = b0 + i;
     int shape = P.shape[gi], motion = P.motion[gi];
-    S.u[L.bmeta + i] = (uint32_t)shape | ((uint32_t)motion << 8);
+    uint32_t meta = (uint32_t)shape | ((uint32_t)motion << 8);
     V3 x = v3(P.pose[gi], P.pose[N + gi], P.pose[2 * N + gi]);
     float qw = P.pose[3 * N + gi], qx = P.pose[4 * N + gi], qy = P.pose[5 * N + gi], qz = P.pose[6 * N + gi];
-    st3(S.f + L.bx, NB, i, x);
-    S.f[L.bq + i] = qw; S.f[L.bq + NB + i] = qx; S.f[L.bq + 2 * NB + i] = qy; S.f[L.bq + 3 * NB + i] = qz;
-    M3 R = quat_R(qw, qx, qy, qz);
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-      for (int c = 0; c < 3; c++) S.f[L.bR + (3 * r + c) * NB + i] = R.m[r][c];
+    st4(S.f + L.geo, 3 * i, f4(x, __uint_as_float(meta)));
+    st4(S.f + L.geo, 3 * i + 1, make_float4(qw, qx, qy, qz));
+    st4(S.f + L.geo, 3 * i + 2, make_float4(P.prm[gi], P.prm[N + gi], P.prm[2 * N + gi], 0.f));
     V3 v = v3(P.vel[gi], P.vel[N + gi], P.vel[2 * N + gi]);
     V3 w = v3(P.vel[3 * N + gi], P.vel[4 * N + gi], P.vel[5 * N + gi]);
     float im = 0.f;
     float I[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (motion == DYNAMIC) {
+      M3 R = quat_R(qw, qx, qy, qz);
       im = P.inv_mass[gi];
       v = v + g * dt;
       float i0 = P.inv_inertia[gi], i1 = P.inv_inertia[N + gi], i2 = P.inv_inertia[2 * N + gi];
@@ -420,30 +614,25 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       v = v3(0.f, 0.f, 0.f);
       w = v3(0.f, 0.f, 0.f);
     }
-    st3(S.f + L.bv, NB, i, v);
-    st3(S.f + L.bw, NB, i, w);
-    S.f[L.bim + i] = im;
-#pragma unroll
-    for (int k = 0; k < 6; k++) S.f[L.bI + k * NB + i] = I[k];
-    S.f[L.bprm + i] = P.prm[gi];
-    S.f[L.bprm + NB + i] = P.prm[N + gi];
-    S.f[L.bprm + 2 * NB + i] = P.prm[2 * N + gi];
-    S.f[L.bmu + i] = P.friction[gi];
-    S.f[L.be + i] = P.restitution[gi];
+    st4(S.f + L.dyn, 4 * i, f4(v, im));
+    st4(S.f + L.dyn, 4 * i + 1, f4(w, P.friction[gi]));
+    st4(S.f + L.dyn, 4 * i + 2, make_float4(I[0], I[1], I[2], I[3]));
+    st4(S.f + L.dyn, 4 * i + 3, make_float4(I[4], I[5], P.restitution[gi], 0.f));
   }
   __syncthreads();
+  TRACE(1);
   // ---- a1: arm at theta_t, link velocities from the actions -------------
   float thd[7];
   if (P.arm) {
 #pragma unroll
     for (int k = 0; k < 7; k++) thd[k] = P.actions ? P.actions[7 * s + k] : 0.f;
-    if (tid == 0) arm_fk(P, L, S, NB, nb - 7, P.arm_base + 3 * s, P.theta + 7 * s, thd);
+    if (tid == 0) arm_fk(P, L, S, nb - 7, P.arm_base + 3 * s, P.theta + 7 * s, thd);
     __syncthreads();
   }
 
   // ---- a3: AABBs and sort keys ------------------------------------------
   for (int i = tid; i < nb; i += T) {
-    Geom G = load_geom(L, S, NB, i);
+    Geom G = load_geom(L, S, i);
     V3 lo, hi;
     if (G.shape == SPHERE) {
       float e = G.p[0] + P.margin;
@@ -463,30 +652,33 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       lo = v3(fminf(e0.x, e1.x) - r, fminf(e0.y, e1.y) - r, fminf(e0.z, e1.z) - r);
       hi = v3(fmaxf(e0.x, e1.x) + r, fmaxf(e0.y, e1.y) + r, fmaxf(e0.z, e1.z) + r);
     }
-    st3(S.f + L.lo, NB, i, lo);
-    st3(S.f + L.hi, NB, i, hi);
+    uint32_t meta = body_meta(L, S, i);
+    st4(S.f + L.lo, i, f4(lo, is_dyn_meta(meta) ? 1.f : 0.f));
+    st4(S.f + L.hi, i, f4(hi, 0.f));
     S.u[L.skey + i] = orderable(lo.x);
     S.u[L.sval + i] = (uint32_t)i;
   }
   __syncthreads();
+  TRACE(2);
 
   // ---- a4: radix sort bodies by AABB minimum along x --------------------
   int sw = lds_radix_sort(S.u + L.skey, S.u + L.sval, S.u + L.skey2, S.u + L.sval2, nb, 0, 4, S.u + L.hist,
-                          S.u + L.hbase);
+                          S.u + L.hbase, misc);
   const uint32_t* order = S.u + (sw ? L.sval2 : L.sval);
+  TRACE(3);
 
   // ---- a5: sweep and prune -> pairs (unordered), then canonical sort ----
   uint32_t* pk = S.u + L.pk;
   for (int p = tid; p < nb; p += T) {
     int i = (int)order[p];
-    float hix = S.f[L.hi + i];
-    V3 loi = ld3(S.f + L.lo, NB, i), hii = ld3(S.f + L.hi, NB, i);
-    bool di = is_dyn(L, S, i);
+    float4 loi = ld4(S.f + L.lo, i), hii = ld4(S.f + L.hi, i);
+    bool di = loi.w != 0.f;
     for (int q = p + 1; q < nb; q++) {
       int j = (int)order[q];
-      if (S.f[L.lo + j] > hix) break;
-      if (!di && !is_dyn(L, S, j)) continue;
-      V3 loj = ld3(S.f + L.lo, NB, j), hij = ld3(S.f + L.hi, NB, j);
+      float4 loj = ld4(S.f + L.lo, j);
+      if (loj.x > hii.x) break;
+      if (!di && loj.w == 0.f) continue;
+      float4 hij = ld4(S.f + L.hi, j);
       if (loj.y <= hii.y && loi.y <= hij.y && loj.z <= hii.z && loi.z <= hij.z) {
         int a = i < j ? i : j, bb = i < j ? j : i;
         uint32_t slot = atomicAdd(&misc[M_NPAIRS], 1u);
@@ -499,11 +691,12 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     }
   }
   __syncthreads();
+  TRACE(4);
   const int npairs_all = (int)misc[M_NPAIRS];
   const int np = npairs_all < PM ? npairs_all : PM;
   if (npairs_all > PM && tid == 0) misc[M_FLAGS] |= FLAG_CAPACITY;
-  // keys are unique: sort keys only (values unused -> sort into the same buffer pair)
-  int swp = lds_radix_sort(pk, pk, S.u + L.pk2, S.u + L.pk2, np, 0, 3, S.u + L.hist, S.u + L.hbase);
+  // keys are unique: sort keys only (values ride along in the same buffers)
+  int swp = lds_radix_sort(pk, pk, S.u + L.pk2, S.u + L.pk2, np, 0, 3, S.u + L.hist, S.u + L.hbase, misc);
   const uint32_t* pairs = swp ? S.u + L.pk2 : pk;
   if (P.export_on) {
     for (int p = tid; p < np; p += T) {
@@ -512,6 +705,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       P.x_pair[(long)s * PM + p] = (a << 16) | (bb == 2047u ? kGroundPair : bb);
     }
   }
+  TRACE(5);
 
   // ---- a6: narrowphase, compaction in canonical order --------------------
   {
@@ -519,21 +713,22 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     uint32_t base = 0;
     for (int t0 = 0; t0 < np; t0 += T) {
       int p = t0 + tid;
-      PC pc[4];
-      int cnt = 0;
+      Out4 o;
+      o.n = 0;
       int a = 0, bb = 0;
       if (p < np) {
         uint32_t k = pairs[p];
         a = (int)(k >> 11);
         bb = (int)(k & 2047u);
-        Geom A = load_geom(L, S, NB, a);
+        Geom A = load_geom(L, S, a);
         if (bb == 2047) {
-          cnt = ground_contacts(A, P.margin, pc);
+          ground_contacts(A, P.margin, o);
         } else {
-          Geom B = load_geom(L, S, NB, bb);
-          cnt = collide(A, B, P.margin, pc);
+          Geom B = load_geom(L, S, bb);
+          collide(A, B, P.margin, o);
         }
       }
+      const int cnt = o.n;
       // prefix of the counts (0..4) with three ballots per wave
       u64 b0m = __ballot(cnt & 1), b1m = __ballot((cnt >> 1) & 1), b2m = __ballot((cnt >> 2) & 1);
       uint32_t pre = lanes_below(b0m) + 2u * lanes_below(b1m) + 4u * lanes_below(b2m);
@@ -547,15 +742,16 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
         if (ww < w) off += t;
         tile += t;
       }
-      for (int k = 0; k < cnt; k++) {
+      const uint32_t bkey = bb == 2047 ? kGroundKey : (uint32_t)bb;
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (k >= cnt) break;
         uint32_t q = off + (uint32_t)k;
         if ((int)q < CM) {
-          uint32_t bkey = bb == 2047 ? kGroundKey : (uint32_t)bb;
-          S.u[L.ckey + q] = ((uint32_t)a << 20) | (bkey << 8) | (uint32_t)pc[k].f;
-          S.u[L.cab + q] = (uint32_t)a | ((uint32_t)(bb == 2047 ? 0xFFFF : bb) << 16);
-          st3(S.f + L.cn, CM, q, pc[k].n);
-          st3(S.f + L.cp, CM, q, pc[k].p);
-          S.f[L.cphi + q] = pc[k].phi;
+          PC c = o.get(k);
+          S.u[L.ckey + q] = ((uint32_t)a << 20) | (bkey << 8) | (uint32_t)c.f;
+          raw[2 * q] = f4(c.n, c.phi);
+          raw[2 * q + 1] = f4(c.p, 0.f);
         }
       }
       base += tile;
@@ -567,46 +763,191 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     }
   }
   __syncthreads();
+  TRACE(6);
   const int nc_all = (int)misc[M_NCONT];
   const int nc = nc_all < CM ? nc_all : CM;
 
-  // ---- a7/a10: previous impulses, constraint setup ----------------------
+  // ---- a9: colouring -----------------------------------------------------
+  // per-body lists of contacts (dynamic bodies only), canonical order
+  uint32_t* deg = S.u + L.deg;
+  uint32_t* lstart = S.u + L.lstart;
+  uint32_t* list = S.u + L.list;
+  uint32_t* rank = S.u + L.rank;
+  uint32_t* colour = S.u + L.colour;
+  const uint32_t* ckeys = S.u + L.ckey;
+  for (int i = tid; i <= nb; i += T) deg[i] = 0u;
+  __syncthreads();
+  for (int q = tid; q < nc; q += T) {
+    uint32_t key = ckeys[q];
+    int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
+    if (is_dyn_meta(body_meta(L, S, a))) atomicAdd(&deg[a], 1u);
+    if (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) atomicAdd(&deg[b], 1u);
+  }
+  __syncthreads();
+  for (int i = tid; i <= nb; i += T) lstart[i] = i < nb ? deg[i] : 0u;
+  __syncthreads();
+  block_exclusive_scan(lstart, nb + 1, misc);
+  // fill unordered (deg becomes the per-body count again), then
+  // insertion-sort each body's short list
+  for (int i = tid; i < nb; i += T) deg[i] = 0u;
+  __syncthreads();
+  for (int q = tid; q < nc; q += T) {
+    uint32_t key = ckeys[q];
+    int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
+    if (is_dyn_meta(body_meta(L, S, a))) list[lstart[a] + atomicAdd(&deg[a], 1u)] = (uint32_t)q;
+    if (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) list[lstart[b] + atomicAdd(&deg[b], 1u)] = (uint32_t)q;
+    colour[q] = 0u;
+    rank[q] = 0u;
+  }
+  __syncthreads();
+  for (int i = tid; i < nb; i += T) {
+    uint32_t s0 = lstart[i], e0 = lstart[i + 1];
+    for (uint32_t x = s0 + 1; x < e0; x++) {
+      uint32_t v = list[x];
+      uint32_t y = x;
+      while (y > s0 && list[y - 1] > v) { list[y] = list[y - 1]; y--; }
+      list[y] = v;
+    }
+  }
+  __syncthreads();
+  // rank of each contact in its bodies' lists: low half for a, high half for b
+  for (int i = tid; i < nb; i += T) {
+    uint32_t s0 = lstart[i], e0 = lstart[i + 1];
+    for (uint32_t x = s0; x < e0; x++) {
+      uint32_t q = list[x];
+      // both bodies of a contact write its rank word: combine atomically
+      if ((int)(ckeys[q] >> 20) == i) atomicOr(&rank[q], x - s0);
+      else atomicOr(&rank[q], (x - s0) << 16);
+    }
+  }
+  __syncthreads();
+  TRACE(7);
+  // fixed point of c_q = mex{c_p : p < q, p shares a dynamic body with q};
+  // its unique solution is sequential first fit in canonical order
+  for (int round = 0; round < nc + 2; round++) {
+    if (tid == 0) misc[M_CHANGED] = 0u;
+    __syncthreads();
+    bool changed = false;
+    for (int q = tid; q < nc; q += T) {
+      uint32_t key = ckeys[q];
+      int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
+      uint32_t rk = rank[q];
+      uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+      int la = is_dyn_meta(body_meta(L, S, a)) ? (int)(rk & 0xFFFFu) : 0;
+      int lb = (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) ? (int)(rk >> 16) : 0;
+      uint32_t sa = la ? lstart[a] : 0u, sb = lb ? lstart[b] : 0u;
+      for (int x = 0; x < la + lb; x++) {
+        uint32_t p = x < la ? list[sa + x] : list[sb + (x - la)];
+        uint32_t c = colour[p];
+        if (c < 32) m0 |= 1u << c;
+        else if (c < 64) m1 |= 1u << (c - 32);
+        else if (c < 96) m2 |= 1u << (c - 64);
+        else m3 |= 1u << (c - 96);
+      }
+      uint32_t c;
+      if (~m0) c = __builtin_ctz(~m0);
+      else if (~m1) c = 32 + __builtin_ctz(~m1);
+      else if (~m2) c = 64 + __builtin_ctz(~m2);
+      else if (~m3) c = 96 + __builtin_ctz(~m3);
+      else c = kMaxColours - 1;  // overflow: flagged below
+      if (c != colour[q]) { colour[q] = c; changed = true; }
+    }
+    if (changed) misc[M_CHANGED] = 1u;
+    __syncthreads();
+    if (misc[M_CHANGED] == 0u) break;
+    __syncthreads();
+  }
+  TRACE(8);
+  for (int q = tid; q < nc; q += T)
+    if (colour[q] == kMaxColours - 1) atomicOr(&misc[M_FLAGS], (uint32_t)FLAG_CAPACITY);
+  // stable sort of contact indices by colour -> colour-major order; the sort
+  // works on copies so `colour` stays indexed by contact
+  uint32_t* cidx = S.u + L.cv0;
+  uint32_t* csk = S.u + L.ck1;
+  for (int q = tid; q < nc; q += T) {
+    cidx[q] = (uint32_t)q;
+    csk[q] = colour[q];
+  }
+  __syncthreads();
+  lds_radix_sort(csk, cidx, rank, S.u + L.perm, nc, 0, 1, S.u + L.hist, S.u + L.hbase, misc);
+  const uint32_t* perm = S.u + L.perm;
+  const uint32_t* scol = rank;       // sorted colours (one pass: result in (k1, v1))
+  uint32_t* cstart = S.u + L.hbase;  // colour starts (hbase is free again)
+  for (int i = tid; i <= kMaxColours; i += T) cstart[i] = 0u;
+  __syncthreads();
+  for (int i = tid; i < nc; i += T) {
+    uint32_t c = scol[i];
+    if (i == 0 || scol[i - 1] != c) cstart[c] = (uint32_t)i;
+    if (i == nc - 1) misc[M_NCOL] = c + 1;
+  }
+  __syncthreads();
+  const int ncol = nc > 0 ? (int)misc[M_NCOL] : 0;
+  if (tid == 0) cstart[ncol] = (uint32_t)nc;
+  __syncthreads();
+  TRACE(9);
+
+  // ---- a7/a10: previous impulses, constraint setup (colour-major) ------
   const int nprev = P.prev_count ? (P.prev_count[s] < CM ? P.prev_count[s] : CM) : 0;
   for (int i = tid; i < nprev; i += T) S.u[L.prevk + i] = P.prev_key[(long)s * CM + i];
   __syncthreads();
   const float gmag = sqrtf(P.gx * P.gx + P.gy * P.gy + P.gz * P.gz);
-  for (int q = tid; q < nc; q += T) {
-    int a, b;
-    V3 n, ra, rb;
-    contact_geom(L, S, NB, CM, q, a, b, n, ra, rb);
-    float mub = b == 0xFFFF ? P.ground_mu : S.f[L.bmu + b];
-    float eb = b == 0xFFFF ? P.ground_e : S.f[L.be + b];
-    float mu = sqrtf(S.f[L.bmu + a] * mub);
-    float e = fmaxf(S.f[L.be + a], eb);
+  for (int i = tid; i < nc; i += T) {
+    const int q = (int)perm[i];
+    float4 r0 = raw[2 * q], r1 = raw[2 * q + 1];
+    float phi = r0.w;
+    V3 n = xyz(r0), p = xyz(r1);
+    uint32_t key = ckeys[q];
+    int a = (int)(key >> 20);
+    uint32_t bk = (key >> 8) & 0xFFFu;
+    int b = bk == kGroundKey ? -1 : (int)bk;
+    struct {
+      V3 ra, rb;
+    } c;
+    c.ra = p - xyz(ld4(S.f + L.geo, 3 * a));
+    c.rb = b >= 0 ? p - xyz(ld4(S.f + L.geo, 3 * b)) : v3(0.f, 0.f, 0.f);
+    Dyn A = load_dyn(L, S, a);
+    Dyn B;
+    if (b >= 0) {
+      B = load_dyn(L, S, b);
+    } else {
+      B.v = v3(0.f, 0.f, 0.f);
+      B.w = v3(0.f, 0.f, 0.f);
+      B.im = 0.f;
+      B.mu = 0.f;
+      for (int k = 0; k < 6; k++) B.I[k] = 0.f;
+    }
+    float eA = S.f[L.dyn + 16 * a + 14];
+    float mub = b >= 0 ? B.mu : P.ground_mu;
+    float eb = b >= 0 ? S.f[L.dyn + 16 * b + 14] : P.ground_e;
+    float mu = sqrtf(A.mu * mub);
+    float e = fmaxf(eA, eb);
     V3 t1, t2;
-    tangents(n, t1, t2);
-    float k3[3];
+    tangents_fast(n, t1, t2);
+    Row rw[3];
     V3 dirs[3] = {n, t1, t2};
+    float k3[3];
 #pragma unroll
     for (int r = 0; r < 3; r++) {
-      V3 ca = cross(ra, dirs[r]);
-      float k = S.f[L.bim + a] + dot(ca, Iw_mul(S.f + L.bI, NB, a, ca));
-      if (b != 0xFFFF) {
-        V3 cb = cross(rb, dirs[r]);
-        k += S.f[L.bim + b] + dot(cb, Iw_mul(S.f + L.bI, NB, b, cb));
+      rw[r].d = dirs[r];
+      rw[r].ca = cross(c.ra, dirs[r]);
+      rw[r].ia = Imul(A.I, rw[r].ca);
+      float k = A.im + dot(rw[r].ca, rw[r].ia);
+      if (b >= 0) {
+        rw[r].cb = cross(c.rb, dirs[r]);
+        rw[r].ib = Imul(B.I, rw[r].cb);
+        k += B.im + dot(rw[r].cb, rw[r].ib);
+      } else {
+        rw[r].cb = v3(0.f, 0.f, 0.f);
+        rw[r].ib = v3(0.f, 0.f, 0.f);
       }
       k3[r] = k;
-      S.f[L.cm + r * CM + q] = 1.0f / k;
+      rw[r].m = 1.0f / k;
     }
-    V3 vr = point_vel(L, S, NB, a, ra) - point_vel(L, S, NB, b, rb);
+    V3 vr = (A.v + cross(A.w, c.ra)) - (B.v + cross(B.w, c.rb));
     float u0 = dot(n, vr);
-    float phi = S.f[L.cphi + q];
     float bias = phi > 0.f ? -phi / dt : P.baumgarte / dt * fmaxf(0.f, -phi - P.slop);
     if (e > 0.f && u0 < -P.rest_thresh) bias = fmaxf(bias, -e * u0);
-    S.f[L.cbias + q] = bias;
-    S.f[L.cmu + q] = mu;
     // previous impulse by binary search of the sorted previous keys
-    uint32_t key = S.u[L.ckey + q];
     int lo = 0, hi = nprev - 1, hit = -1;
     while (lo <= hi) {
       int mid = (lo + hi) >> 1;
@@ -623,177 +964,67 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       lp2 = dot(F, t2);
     }
     float l0 = 0.f, l1 = 0.f, l2 = 0.f;
-    float feat[16];
     const bool need_feat = P.warm == WARM_LEARNED || (P.export_on && P.x_feat);
     if (need_feat) {
+      float feat[16];
       feat[0] = u0;
       feat[1] = dot(t1, vr);
       feat[2] = dot(t2, vr);
       feat[3] = -phi;
-      feat[4] = S.f[L.bim + a];
-      feat[5] = b == 0xFFFF ? 0.f : S.f[L.bim + b];
-      V3 can = cross(ra, n);
-      feat[6] = dot(can, Iw_mul(S.f + L.bI, NB, a, can));
-      if (b != 0xFFFF) {
-        V3 cbn = cross(rb, n);
-        feat[7] = dot(cbn, Iw_mul(S.f + L.bI, NB, b, cbn));
-      } else {
-        feat[7] = 0.f;
-      }
+      feat[4] = A.im;
+      feat[5] = B.im;
+      V3 can = cross(c.ra, n);
+      feat[6] = dot(can, Imul(A.I, can));
+      V3 cbn = cross(c.rb, n);
+      feat[7] = b >= 0 ? dot(cbn, Imul(B.I, cbn)) : 0.f;
       feat[8] = lp0; feat[9] = lp1; feat[10] = lp2;
       feat[11] = n.x; feat[12] = n.y; feat[13] = n.z;
       feat[14] = mu;
       feat[15] = hit >= 0 ? 1.f : 0.f;
       if (P.export_on && P.x_feat)
         for (int k = 0; k < 16; k++) P.x_feat[k * P.scene_cm + (long)s * CM + q] = feat[k];
+      if (P.warm == WARM_LEARNED) {
+        float y[3];
+        mlp_contact(P.mlp, feat, y);
+        float sc = gmag * dt / k3[0];
+        l0 = y[0] * sc; l1 = y[1] * sc; l2 = y[2] * sc;
+      }
     }
     if (P.warm == WARM_PREV) {
       l0 = lp0; l1 = lp1; l2 = lp2;
-    } else if (P.warm == WARM_LEARNED) {
-      float y[3];
-      mlp_contact(P.mlp, feat, y);
-      float sc = gmag * dt / k3[0];
-      l0 = y[0] * sc; l1 = y[1] * sc; l2 = y[2] * sc;
     }
     // projection of the initial impulse
     l0 = fmaxf(l0, 0.f);
     proj_disk(l1, l2, mu * l0);
-    S.f[L.clam + q] = l0;
-    S.f[L.clam + CM + q] = l1;
-    S.f[L.clam + 2 * CM + q] = l2;
+    // Jacobi scale 1/max(n_a, n_b) from the per-body contact counts
+    int na = A.im > 0.f ? (int)deg[a] : 0;
+    int nbb = (b >= 0 && B.im > 0.f) ? (int)deg[b] : 0;
+    float jsc = 1.0f / (float)(na > nbb ? na : nbb);
+    store_rec(rec, i, rw, bias, mu, key, jsc);
+    st4(S.f + L.lam, i, make_float4(l0, l1, l2, phi));
   }
   __syncthreads();
-
-  // ---- a9: colouring -----------------------------------------------------
-  // per-body lists of contacts (dynamic bodies only), canonical order
-  uint32_t* deg = S.u + L.deg;
-  uint32_t* lstart = S.u + L.lstart;
-  uint32_t* list = S.u + L.list;
-  for (int i = tid; i <= nb; i += T) deg[i] = 0u;
-  __syncthreads();
-  for (int q = tid; q < nc; q += T) {
-    uint32_t ab = S.u[L.cab + q];
-    int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
-    if (is_dyn(L, S, a)) atomicAdd(&deg[a], 1u);
-    if (is_dyn(L, S, b)) atomicAdd(&deg[b], 1u);
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t run = 0;
-    for (int i = 0; i < nb; i++) { lstart[i] = run; run += deg[i]; }
-    lstart[nb] = run;
-  }
-  __syncthreads();
-  // fill: slot of contact q in body a's list = number of earlier contacts of a;
-  // lists are built unordered and insertion-sorted per body
-  for (int i = tid; i < nb; i += T) deg[i] = 0u;
-  __syncthreads();
-  for (int q = tid; q < nc; q += T) {
-    uint32_t ab = S.u[L.cab + q];
-    int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
-    if (is_dyn(L, S, a)) list[lstart[a] + atomicAdd(&deg[a], 1u)] = (uint32_t)q;
-    if (is_dyn(L, S, b)) list[lstart[b] + atomicAdd(&deg[b], 1u)] = (uint32_t)q;
-  }
-  __syncthreads();
-  for (int i = tid; i < nb; i += T) {
-    uint32_t s0 = lstart[i], e0 = lstart[i + 1];
-    for (uint32_t x = s0 + 1; x < e0; x++) {
-      uint32_t v = list[x];
-      uint32_t y = x;
-      while (y > s0 && list[y - 1] > v) { list[y] = list[y - 1]; y--; }
-      list[y] = v;
-    }
-  }
-  uint32_t* colour = S.u + L.ck0;
-  for (int q = tid; q < nc; q += T) colour[q] = 0u;
-  __syncthreads();
-  // fixed point of c_q = mex{c_p : p < q, p shares a dynamic body with q};
-  // its unique solution is sequential first fit in canonical order
-  for (int round = 0; round < nc + 2; round++) {
-    if (tid == 0) misc[M_CHANGED] = 0u;
-    __syncthreads();
-    bool changed = false;
-    for (int q = tid; q < nc; q += T) {
-      uint32_t ab = S.u[L.cab + q];
-      int ids[2] = {(int)(ab & 0xFFFFu), (int)(ab >> 16)};
-      uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-      for (int t = 0; t < 2; t++) {
-        int i = ids[t];
-        if (!is_dyn(L, S, i)) continue;
-        for (uint32_t x = lstart[i]; x < lstart[i + 1]; x++) {
-          uint32_t p = list[x];
-          if ((int)p >= q) break;
-          uint32_t c = colour[p];
-          if (c < 32) m0 |= 1u << c;
-          else if (c < 64) m1 |= 1u << (c - 32);
-          else if (c < 96) m2 |= 1u << (c - 64);
-          else m3 |= 1u << (c - 96);
-        }
-      }
-      uint32_t c;
-      if (~m0) c = __builtin_ctz(~m0);
-      else if (~m1) c = 32 + __builtin_ctz(~m1);
-      else if (~m2) c = 64 + __builtin_ctz(~m2);
-      else if (~m3) c = 96 + __builtin_ctz(~m3);
-      else c = kMaxColours - 1;  // overflow: flagged below
-      if (c != colour[q]) { colour[q] = c; changed = true; }
-    }
-    if (changed) misc[M_CHANGED] = 1u;
-    __syncthreads();
-    if (misc[M_CHANGED] == 0u) break;
-    __syncthreads();
-  }
-  // colour overflow check (a contact whose earlier neighbours use all colours)
-  for (int q = tid; q < nc; q += T)
-    if (colour[q] == kMaxColours - 1) atomicOr(&misc[M_FLAGS], (uint32_t)FLAG_CAPACITY);
-  // stable sort of contact indices by colour -> colour-major order
-  uint32_t* cidx = S.u + L.cv0;
-  for (int q = tid; q < nc; q += T) cidx[q] = (uint32_t)q;
-  __syncthreads();
-  int swc = lds_radix_sort(colour, cidx, S.u + L.ck1, S.u + L.cperm, nc, 0, 1, S.u + L.hist, S.u + L.hbase);
-  (void)swc;  // one pass: result in (ck1, cperm)
-  const uint32_t* scol = S.u + L.ck1;
-  uint32_t* cstart = S.u + L.hbase;  // colour starts (hbase is free again)
-  for (int i = tid; i <= kMaxColours; i += T) cstart[i] = 0u;
-  __syncthreads();
-  for (int i = tid; i < nc; i += T) {
-    uint32_t c = scol[i];
-    if (i == 0 || scol[i - 1] != c) cstart[c] = (uint32_t)i;
-    if (i == nc - 1) misc[M_NCOL] = c + 1;
-    S.u[L.ccol + S.u[L.cperm + i]] = c;
-  }
-  __syncthreads();
-  const int ncol = nc > 0 ? (int)misc[M_NCOL] : 0;
-  // fill starts of empty colours below ncol (cannot happen for first fit) and the end
-  if (tid == 0) cstart[ncol] = (uint32_t)nc;
-  __syncthreads();
+  TRACE(10);
 
   // ---- a8/a11: warm start and sweeps ------------------------------------
   if (P.warm == WARM_LEARNED) {
     for (int i = tid; i < nb; i += T) {
-#pragma unroll
-      for (int k = 0; k < 3; k++) {
-        S.f[L.vsave + k * NB + i] = S.f[L.bv + k * NB + i];
-        S.f[L.vsave + (3 + k) * NB + i] = S.f[L.bw + k * NB + i];
-      }
+      st4(S.f + L.vsave, 2 * i, ld4(S.f + L.dyn, 4 * i));
+      st4(S.f + L.vsave, 2 * i + 1, ld4(S.f + L.dyn, 4 * i + 1));
     }
     __syncthreads();
   }
-  if (P.warm != WARM_COLD) apply_all(L, S, NB, CM, nc, ncol, cstart);
+  if (P.warm != WARM_COLD) apply_all(L, S, rec, ncol, cstart);
+  TRACE(11);
   int sweeps = 0;
   float res = 0.f;
+  const uint64_t clk0 = P.trace ? clock64() : 0;
   for (int attempt = 0; attempt < 2; attempt++) {
-    sweeps = 0;
-    res = 0.f;
-    for (int it = 0; it < P.iters; it++) {
-      float r = P.solver == SOLVER_JACOBI ? sweep_jacobi(L, S, NB, CM, nb, nc, ncol, cstart)
-                                          : sweeps_pgs(L, S, NB, CM, ncol, cstart);
-      sweeps++;
-      if (P.tol > 0.f || it == P.iters - 1) {
-        res = block_max(r, misc);
-        if (P.tol > 0.f && res <= P.tol) break;
-      }
-    }
+    if (P.solver == SOLVER_JACOBI)
+      solve_jacobi(L, S, rec, nb, nc, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res);
+    else
+      solve_pgs(L, S, rec, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res);
+    __syncthreads();
     if (!(P.tol > 0.f && res > P.tol)) break;
     if (P.warm != WARM_LEARNED || attempt == 1) {
       if (tid == 0) misc[M_FLAGS] |= FLAG_NOT_CONVERGED;
@@ -802,29 +1033,29 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     // learned start rejected: restore post-gravity velocities, solve cold
     if (tid == 0) misc[M_FLAGS] |= FLAG_FELLBACK;
     for (int i = tid; i < nb; i += T) {
-#pragma unroll
-      for (int k = 0; k < 3; k++) {
-        S.f[L.bv + k * NB + i] = S.f[L.vsave + k * NB + i];
-        S.f[L.bw + k * NB + i] = S.f[L.vsave + (3 + k) * NB + i];
-      }
+      st4(S.f + L.dyn, 4 * i, ld4(S.f + L.vsave, 2 * i));
+      st4(S.f + L.dyn, 4 * i + 1, ld4(S.f + L.vsave, 2 * i + 1));
     }
-    for (int q = tid; q < nc; q += T) {
-      S.f[L.clam + q] = 0.f;
-      S.f[L.clam + CM + q] = 0.f;
-      S.f[L.clam + 2 * CM + q] = 0.f;
+    for (int i = tid; i < nc; i += T) {
+      float phi = S.f[L.lam + 4 * i + 3];
+      st4(S.f + L.lam, i, make_float4(0.f, 0.f, 0.f, phi));
     }
     __syncthreads();
   }
   __syncthreads();
+  TRACE(12);
+  if (P.trace && tid == 0) P.trace[(long)s * kTraceSlots + 15] = clock64() - clk0;  // shader cycles in the solve
 
   // ---- a12: integrate positions, write state ----------------------------
   for (int i = tid; i < nb; i += T) {
     const long gi = b0 + i;
-    uint32_t mt = (S.u[L.bmeta + i] >> 8) & 255u;
-    if (mt == DYNAMIC) {
-      V3 x = ld3(S.f + L.bx, NB, i), v = ld3(S.f + L.bv, NB, i), w = ld3(S.f + L.bw, NB, i);
+    uint32_t meta = body_meta(L, S, i);
+    if (is_dyn_meta(meta)) {
+      V3 x = xyz(ld4(S.f + L.geo, 3 * i));
+      float4 qq = ld4(S.f + L.geo, 3 * i + 1);
+      V3 v = xyz(ld4(S.f + L.dyn, 4 * i)), w = xyz(ld4(S.f + L.dyn, 4 * i + 1));
       x = x + v * dt;
-      float qw = S.f[L.bq + i], qx = S.f[L.bq + NB + i], qy = S.f[L.bq + 2 * NB + i], qz = S.f[L.bq + 3 * NB + i];
+      float qw = qq.x, qx = qq.y, qy = qq.z, qz = qq.w;
       // q + dt/2 (0, w) (x) q
       float dw = -(w.x * qx + w.y * qy + w.z * qz);
       float dx = qw * w.x + (w.y * qz - w.z * qy);
@@ -843,7 +1074,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       if (!fin) atomicOr(&misc[M_FLAGS], (uint32_t)FLAG_NONFINITE);
     }
   }
-  __syncthreads();  // all reads of the arm links' LDS pose are done
+  __syncthreads();  // every read of the arm links' LDS records is done
   if (P.arm && tid == 0) {
     float th[7];
     for (int k = 0; k < 7; k++) {
@@ -851,48 +1082,47 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       P.theta[7 * s + k] = th[k];
     }
     // link velocities stay those of this step; poses move to theta_{t+1}
-    arm_fk(P, L, S, NB, nb - 7, P.arm_base + 3 * s, th, nullptr);
+    arm_fk(P, L, S, nb - 7, P.arm_base + 3 * s, th, nullptr);
     for (int k = 0; k < 7; k++) {
       int i = nb - 7 + k;
       long gi = b0 + i;
-      for (int c = 0; c < 3; c++) P.pose[c * N + gi] = S.f[L.bx + c * NB + i];
-      for (int c = 0; c < 4; c++) P.pose[(3 + c) * N + gi] = S.f[L.bq + c * NB + i];
-      for (int c = 0; c < 3; c++) {
-        P.vel[c * N + gi] = S.f[L.bv + c * NB + i];
-        P.vel[(3 + c) * N + gi] = S.f[L.bw + c * NB + i];
-      }
+      float4 x = ld4(S.f + L.geo, 3 * i), qq = ld4(S.f + L.geo, 3 * i + 1);
+      float4 v = ld4(S.f + L.dyn, 4 * i), w = ld4(S.f + L.dyn, 4 * i + 1);
+      P.pose[gi] = x.x; P.pose[N + gi] = x.y; P.pose[2 * N + gi] = x.z;
+      P.pose[3 * N + gi] = qq.x; P.pose[4 * N + gi] = qq.y; P.pose[5 * N + gi] = qq.z; P.pose[6 * N + gi] = qq.w;
+      P.vel[gi] = v.x; P.vel[N + gi] = v.y; P.vel[2 * N + gi] = v.z;
+      P.vel[3 * N + gi] = w.x; P.vel[4 * N + gi] = w.y; P.vel[5 * N + gi] = w.z;
     }
   }
+  TRACE(13);
 
   // ---- a13: cache, export, arm force, stats ------------------------------
   const int arm0 = P.arm ? nb - 7 : nb;
   float* force = S.f + L.force;
-  for (int q = tid; q < nc; q += T) {
-    uint32_t ab = S.u[L.cab + q];
-    int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
-    V3 n = ld3(S.f + L.cn, CM, q);
-    V3 t1, t2;
-    tangents(n, t1, t2);
-    float l0 = S.f[L.clam + q], l1 = S.f[L.clam + CM + q], l2 = S.f[L.clam + 2 * CM + q];
-    V3 F = t1 * l1 + t2 * l2;
+  for (int i = tid; i < nc; i += T) {
+    const int q = (int)perm[i];
+    const float4* R = rec + kRec * i;
+    float4 lam = ld4(S.f + L.lam, i);
+    V3 n = xyz(R[0]), t1 = xyz(R[1]), t2 = xyz(R[2]);
+    uint32_t key = ckeys[q];
+    int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
+    V3 F = t1 * lam.y + t2 * lam.z;
     long o = (long)s * CM + q;
-    P.cur_key[o] = S.u[L.ckey + q];
-    P.cur_lam[o] = l0;
+    P.cur_key[o] = key;
+    P.cur_lam[o] = lam.x;
     P.cur_lam[P.scene_cm + o] = F.x;
     P.cur_lam[2 * P.scene_cm + o] = F.y;
     P.cur_lam[3 * P.scene_cm + o] = F.z;
-    bool arm_c = a >= arm0 || (b != 0xFFFF && b >= arm0);
-    force[q] = arm_c ? sqrtf(len2(n * l0 + F)) / dt : 0.f;
-  }
-  if (P.export_on) {
-    for (int q = tid; q < nc; q += T) {
-      long o = (long)s * CM + q;
+    bool arm_c = a >= arm0 || (b != (int)kGroundKey && b >= arm0);
+    force[q] = arm_c ? sqrtf(len2(n * lam.x + F)) / dt : 0.f;
+    if (P.export_on) {
       const long sc = P.scene_cm;
-      P.x_normal[o] = S.f[L.cn + q]; P.x_normal[sc + o] = S.f[L.cn + CM + q]; P.x_normal[2 * sc + o] = S.f[L.cn + 2 * CM + q];
-      P.x_point[o] = S.f[L.cp + q]; P.x_point[sc + o] = S.f[L.cp + CM + q]; P.x_point[2 * sc + o] = S.f[L.cp + 2 * CM + q];
-      P.x_phi[o] = S.f[L.cphi + q];
-      P.x_lambda[o] = S.f[L.clam + q]; P.x_lambda[sc + o] = S.f[L.clam + CM + q]; P.x_lambda[2 * sc + o] = S.f[L.clam + 2 * CM + q];
-      P.x_colour[o] = (int32_t)S.u[L.ccol + q];
+      V3 pt = xyz(raw[2 * q + 1]);
+      P.x_normal[o] = n.x; P.x_normal[sc + o] = n.y; P.x_normal[2 * sc + o] = n.z;
+      P.x_point[o] = pt.x; P.x_point[sc + o] = pt.y; P.x_point[2 * sc + o] = pt.z;
+      P.x_phi[o] = lam.w;
+      P.x_lambda[o] = lam.x; P.x_lambda[sc + o] = lam.y; P.x_lambda[2 * sc + o] = lam.z;
+      P.x_colour[o] = (int32_t)colour[q];
     }
   }
   __syncthreads();
@@ -914,22 +1144,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     P.st_flags[s] = (int32_t)misc[M_FLAGS];
     P.st_arm_force[s] = nc > 0 ? force[0] : 0.f;
   }
+  TRACE(14);
 }
-
-}  // namespace rbs
-
-extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L, int threads, int grid,
-                               hipStream_t stream) {
-  size_t bytes = (size_t)L->total * 4u;
-  hipLaunchKernelGGL(rbs::step_kernel, dim3(grid), dim3(threads), bytes, stream, *P, *L);
-  return (int)hipGetLastError();
-}
-
-extern "C" int rbs_set_step_lds_limit(int bytes) {
-  return (int)hipFuncSetAttribute((const void*)rbs::step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-}
-
-namespace rbs {
 
 // Arm link poses from the joint angles, one thread per scene (set-up and resets).
 __global__ void arm_pose_kernel(int S_, const int32_t* off, float* pose, long N, const float* theta, const float* base,
@@ -968,6 +1184,17 @@ __global__ void reset_kernel(const int32_t* off, const uint8_t* mask, float* pos
 }
 
 }  // namespace rbs
+
+extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L, int threads, int grid,
+                               hipStream_t stream) {
+  size_t bytes = (size_t)L->total * 4u;
+  hipLaunchKernelGGL(rbs::step_kernel, dim3(grid), dim3(threads), bytes, stream, *P, *L);
+  return (int)hipGetLastError();
+}
+
+extern "C" int rbs_set_step_lds_limit(int bytes) {
+  return (int)hipFuncSetAttribute((const void*)rbs::step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
 
 extern "C" int rbs_launch_arm_pose(const rbs::StepParams* P, const uint8_t* mask, hipStream_t stream) {
   int S_ = P->num_scenes;

@@ -160,6 +160,15 @@ class Sim:
             ptr = C.c_void_p(actions.data_ptr())
         L.check(L.load().sim_step(self.h, ptr, float(dt), int(iters)), "sim_step")
 
+    def set_trace(self, on: bool = True):
+        """Per-scene phase timestamps ([S, 16] int64 device tensor) written by every later step."""
+        if on:
+            self.trace = torch.zeros((self.S, 16), dtype=torch.int64, device=self.device)
+            ptr = C.c_void_p(self.trace.data_ptr())
+        else:
+            self.trace, ptr = None, None
+        L.check(L.load().sim_set_trace(self.h, ptr), "sim_set_trace")
+
     def set_export(self, on: bool = True):
         L.check(L.load().sim_set_export(self.h, int(bool(on))), "sim_set_export")
 
