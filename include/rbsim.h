@@ -163,6 +163,76 @@ int sim_set_solver(sim_handle *h, int solver, int warm_start, float tolerance);
 int sim_set_mlp(sim_handle *h, const uint16_t *d_w1, const uint16_t *d_w2, const uint16_t *d_w3,
                 const float *d_b1, const float *d_b2, const float *d_b3, const float *d_mean, const float *d_std);
 
+/* ---- Learned warm start: the network outside the step ------------------
+ * The warm-start network maps 16 contact features (z-scored with a
+ * training-set mean and std, std floored at 1e-6) through 64 -> ReLU -> 64
+ * -> ReLU -> 3 outputs y; the initial impulse is y * |g| dt / k_n, projected
+ * onto the friction cone.  The paper has no learned solver: the network is
+ * this library's replacement for the classic previous-step warm start
+ * (Catto 2005).  Its z-scoring echoes the per-channel input normalization of
+ * the appendix's monolithic policy (App. B.1), and the optimizer defaults
+ * the caller is expected to use come from that policy's training setup
+ * (App. B.2: Adam, lr 1e-4 decayed linearly, gradient norm clipped at 0.5).
+ * Flat fp32 parameter vector (row = output unit):
+ *   w1 [64][16] | b1 [64] | w2 [64][64] | b2 [64] | w3 [3][64] | b3 [3]. */
+#define SIM_MLP_NPARAM 5443
+#define SIM_MLP_NWEIGHT 5312  /* bf16 weights: w1 | w2 | w3 */
+#define SIM_MLP_NBIAS 131     /* fp32 biases: b1 | b2 | b3 */
+
+/* Inference weights in the form sim_set_mlp takes (device pointers; bf16
+ * arrays 8-byte aligned). */
+typedef struct sim_mlp_weights {
+    const uint16_t *w1, *w2, *w3;
+    const float *b1, *b2, *b3, *mean, *std;
+} sim_mlp_weights;
+
+/* y [n][3] = network(x [n][16]) exactly as the step's learned warm start
+ * computes it: bf16 weights and layer inputs, fp32 accumulation on the
+ * matrix cores.  x 16-byte aligned.  Asynchronous on stream (a hipStream_t,
+ * NULL = default stream). */
+int sim_mlp_forward(const sim_mlp_weights *w, const float *d_x, long n, float *d_y, void *stream);
+
+/* Device scratch bytes sim_mlp_stats and sim_mlp_grad need for n rows
+ * (caller-owned, 256-byte aligned). */
+size_t sim_mlp_workspace_bytes(long n);
+
+/* Population mean and std of each feature of x [n][16], accumulated in
+ * double in a fixed order. */
+int sim_mlp_stats(const float *d_x, long n, float *d_mean, float *d_std, void *d_work, size_t work_bytes,
+                  void *stream);
+
+/* Gradient of the mean squared error over the 3n outputs of a batch of n
+ * rows against targets t [.][3], with respect to the flat parameters.  Row
+ * j of the batch is row d_rows[j] of x [.][16] and t (d_rows: int32 [n],
+ * device, each index in range; NULL = rows 0..n-1).  The forward rounds
+ * weights and activations to bf16 as inference does; the backward runs in
+ * fp32 through the rounded weights.  d_grad [5443]; d_loss (may be NULL)
+ * gets the loss.  Bitwise reproducible. */
+int sim_mlp_grad(const float *d_params, const float *d_mean, const float *d_std, const float *d_x, const float *d_t,
+                 const int32_t *d_rows, long n, float *d_grad, float *d_loss, void *d_work, size_t work_bytes,
+                 void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step
+ * counts from 1) on the fp32 master parameters, after scaling the gradient
+ * to global L2 norm <= clip (clip 0: no clipping).  d_m, d_v: [5443]
+ * moments, zero before the first step.  d_gnorm (may be NULL) gets the
+ * gradient norm before clipping.  The caller owns the lr schedule. */
+int sim_mlp_adam(float *d_params, float *d_m, float *d_v, const float *d_grad, int step, float lr, float clip,
+                 float *d_gnorm, void *stream);
+
+/* Inference copy of the parameters: d_wbf16 [5312] = bf16 (round to
+ * nearest even) of w1 | w2 | w3, d_bias [131] = b1 | b2 | b3. */
+int sim_mlp_export(const float *d_params, uint16_t *d_wbf16, float *d_bias, void *stream);
+
+/* Training rows from the last step (which must have run with export on):
+ * for every contact of every scene whose flags are all clear, its 16
+ * features into d_x [cap][16] and its impulses scaled by k_n / (|g| dt)
+ * (k_n from the features: w_A + w_B + the two angular terms) into
+ * d_t [cap][3], scenes in order, contacts in canonical order.  Rows past
+ * cap are dropped; *d_total (device) receives the number of rows there
+ * were.  Asynchronous on the handle's stream. */
+int sim_mlp_gather(sim_handle *h, float *d_x, float *d_t, long cap, long long *d_total);
+
 /* Masked reset: for every scene s with d_mask[s] != 0, copy its bodies'
  * pose [7][N] and velocity [6][N] from d_pose/d_vel (same layout as the
  * state), its joint angles from d_theta [S*7] (if arm), and clear its

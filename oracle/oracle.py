@@ -295,3 +295,23 @@ def mlp_loss_grad(params: dict, x, t, bf16: bool = False):
                                    *[_ptr(g[k], _d) for k in ("w1", "b1", "w2", "b2", "w3", "b3")])
     g = {k: v.reshape(np.shape(params[k])) for k, v in g.items()}
     return loss, g
+
+
+def adam_step(params, m, v, grad, step: int, lr: float, clip: float = 0.0, b1: float = 0.9, b2: float = 0.999,
+              eps: float = 1e-8):
+    """One Adam update (Kingma & Ba 2015, Algorithm 1: bias-corrected first
+    and second moments) applied after rescaling the whole gradient to global
+    L2 norm at most `clip` (gradient-norm clipping, Pascanu et al. 2013;
+    clip 0 disables it).  The clip and lr defaults the trainer uses are the
+    paper's monolithic-policy setup (appendix B.2).  float64 in and out:
+    returns (params, m, v, clipped gradient, norm before clipping)."""
+    g = np.asarray(grad, np.float64)
+    norm = float(np.sqrt(np.sum(g * g)))
+    if clip > 0.0 and norm > clip:
+        g = g * (clip / norm)
+    m = b1 * np.asarray(m, np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, np.float64) + (1.0 - b2) * g * g
+    mhat = m / (1.0 - b1 ** step)
+    vhat = v / (1.0 - b2 ** step)
+    p = np.asarray(params, np.float64) - lr * mhat / (np.sqrt(vhat) + eps)
+    return p, m, v, g, norm

@@ -57,9 +57,17 @@ class StatsView(C.Structure):
                 ("flags", C.c_void_p), ("residual", C.c_void_p), ("arm_force", C.c_void_p)]
 
 
+class MlpWeights(C.Structure):
+    _fields_ = [("w1", C.c_void_p), ("w2", C.c_void_p), ("w3", C.c_void_p), ("b1", C.c_void_p),
+                ("b2", C.c_void_p), ("b3", C.c_void_p), ("mean", C.c_void_p), ("std", C.c_void_p)]
+
+
+MLP_NPARAM, MLP_NWEIGHT, MLP_NBIAS = 5443, 5312, 131
+
 EXPORTED = ["sim_workspace_bytes", "sim_create", "sim_step", "sim_contacts", "sim_state", "sim_stats",
             "sim_set_export", "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_trace", "sim_set_stream",
-            "sim_destroy", "sim_last_error"]
+            "sim_destroy", "sim_last_error", "sim_mlp_forward", "sim_mlp_workspace_bytes", "sim_mlp_stats",
+            "sim_mlp_grad", "sim_mlp_adam", "sim_mlp_export", "sim_mlp_gather"]
 
 _lib = None
 
@@ -90,8 +98,19 @@ def load():
     L.sim_destroy.restype = None
     L.sim_last_error.argtypes = []
     L.sim_last_error.restype = C.c_char_p
+    _v = C.c_void_p
+    L.sim_mlp_forward.argtypes = [_P(MlpWeights), _v, C.c_long, _v, _v]
+    L.sim_mlp_workspace_bytes.argtypes = [C.c_long]
+    L.sim_mlp_workspace_bytes.restype = C.c_size_t
+    L.sim_mlp_stats.argtypes = [_v, C.c_long, _v, _v, _v, C.c_size_t, _v]
+    L.sim_mlp_grad.argtypes = [_v, _v, _v, _v, _v, _v, C.c_long, _v, _v, _v, C.c_size_t, _v]
+    L.sim_mlp_adam.argtypes = [_v, _v, _v, _v, C.c_int, _f, _f, _v, _v]
+    L.sim_mlp_export.argtypes = [_v, _v, _v, _v]
+    L.sim_mlp_gather.argtypes = [_v, _v, _v, C.c_long, _v]
     for name in ("sim_create", "sim_step", "sim_contacts", "sim_state", "sim_stats", "sim_set_export",
-                 "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_trace", "sim_set_stream"):
+                 "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_trace", "sim_set_stream",
+                 "sim_mlp_forward", "sim_mlp_stats", "sim_mlp_grad", "sim_mlp_adam", "sim_mlp_export",
+                 "sim_mlp_gather"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

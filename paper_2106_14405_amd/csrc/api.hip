@@ -20,6 +20,17 @@
 extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L, int threads, int grid,
                                hipStream_t stream);
 extern "C" int rbs_set_step_lds_limit(int bytes);
+extern "C" int rbs_mlp_forward(const rbs::MlpParams* M, const float* x, long n, float* y, hipStream_t st);
+extern "C" size_t rbs_mlp_work_bytes(long n);
+extern "C" int rbs_mlp_stats(const float* x, long n, float* mean, float* stdv, void* work, hipStream_t st);
+extern "C" int rbs_mlp_grad(const float* prm, const float* mean, const float* stdv, const float* x, const float* t,
+                            const int32_t* rows, long n, float* grad, float* loss, void* work, hipStream_t st);
+extern "C" int rbs_mlp_adam(float* prm, float* m1, float* m2, const float* grad, int step, float lr, float clip,
+                            float* gnorm, hipStream_t st);
+extern "C" int rbs_mlp_export(const float* prm, uint16_t* wbf, float* bias, hipStream_t st);
+extern "C" int rbs_gather(const int32_t* count, const int32_t* flags, int S, int CM, long scm, const float* feat,
+                          const float* lam, float inv_gdt, int64_t* offs, float* x, float* t, long cap,
+                          long long* total, hipStream_t st);
 extern "C" int rbs_launch_arm_pose(const rbs::StepParams* P, const uint8_t* mask, hipStream_t stream);
 extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, const float* pool_pose,
                                 const float* pool_vel, const float* pool_theta, int32_t* count_a, int32_t* count_b,
@@ -41,6 +52,7 @@ struct Layout {
   size_t off_x_pair, off_x_npairs, off_x_normal, off_x_point, off_x_phi, off_x_lambda, off_x_colour, off_x_feat;
   size_t off_raw, off_crec;
   size_t off_st[7];
+  size_t off_gather;
   size_t total;
 };
 
@@ -79,6 +91,7 @@ Layout make_layout(long S, long N, long PM, long CM) {
   L.off_raw = take(4 * 8 * S * CM);
   L.off_crec = take(4 * 52 * S * CM);  // 13 float4 solver record per contact
   for (int k = 0; k < 7; k++) L.off_st[k] = take(4 * S);
+  L.off_gather = take(8 * S);  // per-scene row offsets of sim_mlp_gather
   L.total = o;
   return L;
 }
@@ -95,6 +108,8 @@ struct sim_handle {
   Layout lay;
   int parity;  // cache buffer the next step reads
   int export_on;
+  float last_dt;    // dt of the last step (0 before the first)
+  int last_export;  // export was on during the last step
   int arm;
   float link_len[7];
   float arm_radius;
@@ -244,6 +259,8 @@ int lds_bytes(int NB, int PM, int CM, int T, int solver, int warm) {
   return L.total * 4;
 }
 
+bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
 int device_lds_limit() {
   int dev = 0, v = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 65536;
@@ -292,6 +309,8 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   h->lay = lay;
   h->parity = 0;
   h->export_on = 0;
+  h->last_dt = 0.f;
+  h->last_export = 0;
   h->arm = d->arm ? 1 : 0;
   for (int k = 0; k < 7; k++) h->link_len[k] = d->link_len[k];
   h->arm_radius = d->arm_radius;
@@ -399,6 +418,8 @@ int sim_step(sim_handle* h, const float* d_actions, float dt, int iters) {
   int rc = rbs_launch_step(&P, &L, h->threads, h->S, h->stream);
   if (rc != 0) return fail(SIM_EDEVICE, std::string("step launch failed: ") + hipGetErrorString((hipError_t)rc));
   h->parity ^= 1;
+  h->last_dt = dt;
+  h->last_export = h->export_on;
   return SIM_OK;
 }
 
@@ -472,6 +493,7 @@ int sim_set_mlp(sim_handle* h, const uint16_t* w1, const uint16_t* w2, const uin
                 const float* b2, const float* b3, const float* mean, const float* stdv) {
   if (!h) return fail(SIM_EINVAL, "handle is NULL");
   if (!w1 || !w2 || !w3 || !b1 || !b2 || !b3 || !mean || !stdv) return fail(SIM_EINVAL, "NULL weight pointer");
+  if (!aligned(w1, 8) || !aligned(w2, 8) || !aligned(w3, 8)) return fail(SIM_EINVAL, "bf16 weights must be 8-byte aligned");
   h->mlp.w1 = w1;
   h->mlp.w2 = w2;
   h->mlp.w3 = w3;
@@ -509,6 +531,77 @@ int sim_set_stream(sim_handle* h, void* stream) {
 }
 
 void sim_destroy(sim_handle* h) { delete h; }
+
+int sim_mlp_forward(const sim_mlp_weights* w, const float* d_x, long n, float* d_y, void* stream) {
+  if (!w || !w->w1 || !w->w2 || !w->w3 || !w->b1 || !w->b2 || !w->b3 || !w->mean || !w->std)
+    return fail(SIM_EINVAL, "NULL weight pointer");
+  if (n < 0) return fail(SIM_EINVAL, "n must be >= 0");
+  if (n > 0 && (!d_x || !d_y)) return fail(SIM_EINVAL, "x and y are required");
+  if (!aligned(w->w1, 8) || !aligned(w->w2, 8) || !aligned(w->w3, 8) || !aligned(d_x, 16))
+    return fail(SIM_EINVAL, "bf16 weights need 8-byte and x 16-byte alignment");
+  rbs::MlpParams M{w->w1, w->w2, w->w3, w->b1, w->b2, w->b3, w->mean, w->std};
+  if (rbs_mlp_forward(&M, d_x, n, d_y, (hipStream_t)stream) != 0) return fail(SIM_EDEVICE, "forward launch failed");
+  return SIM_OK;
+}
+
+size_t sim_mlp_workspace_bytes(long n) { return n < 0 ? 0 : rbs_mlp_work_bytes(n); }
+
+int sim_mlp_stats(const float* d_x, long n, float* d_mean, float* d_std, void* d_work, size_t work_bytes,
+                  void* stream) {
+  if (n < 1) return fail(SIM_EINVAL, "n must be >= 1");
+  if (!d_x || !d_mean || !d_std) return fail(SIM_EINVAL, "NULL pointer");
+  if (!d_work || work_bytes < rbs_mlp_work_bytes(n) || !aligned(d_work, 256))
+    return fail(SIM_EWORKSPACE, "workspace too small or not 256-byte aligned");
+  if (rbs_mlp_stats(d_x, n, d_mean, d_std, d_work, (hipStream_t)stream) != 0)
+    return fail(SIM_EDEVICE, "stats launch failed");
+  return SIM_OK;
+}
+
+int sim_mlp_grad(const float* d_params, const float* d_mean, const float* d_std, const float* d_x, const float* d_t,
+                 const int32_t* d_rows, long n, float* d_grad, float* d_loss, void* d_work, size_t work_bytes,
+                 void* stream) {
+  if (n < 1) return fail(SIM_EINVAL, "n must be >= 1");
+  if (n > (1L << 30)) return fail(SIM_EINVAL, "n too large");
+  if (!d_params || !d_mean || !d_std || !d_x || !d_t || !d_grad) return fail(SIM_EINVAL, "NULL pointer");
+  if (!d_work || work_bytes < rbs_mlp_work_bytes(n) || !aligned(d_work, 256))
+    return fail(SIM_EWORKSPACE, "workspace too small or not 256-byte aligned");
+  if (rbs_mlp_grad(d_params, d_mean, d_std, d_x, d_t, d_rows, n, d_grad, d_loss, d_work, (hipStream_t)stream) != 0)
+    return fail(SIM_EDEVICE, "gradient launch failed");
+  return SIM_OK;
+}
+
+int sim_mlp_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int step, float lr, float clip,
+                 float* d_gnorm, void* stream) {
+  if (!d_params || !d_m || !d_v || !d_grad) return fail(SIM_EINVAL, "NULL pointer");
+  if (step < 1) return fail(SIM_EINVAL, "step counts from 1");
+  if (!(lr >= 0.f) || !(clip >= 0.f)) return fail(SIM_EINVAL, "lr and clip must be >= 0");
+  if (rbs_mlp_adam(d_params, d_m, d_v, d_grad, step, lr, clip, d_gnorm, (hipStream_t)stream) != 0)
+    return fail(SIM_EDEVICE, "adam launch failed");
+  return SIM_OK;
+}
+
+int sim_mlp_export(const float* d_params, uint16_t* d_wbf16, float* d_bias, void* stream) {
+  if (!d_params || !d_wbf16 || !d_bias) return fail(SIM_EINVAL, "NULL pointer");
+  if (rbs_mlp_export(d_params, d_wbf16, d_bias, (hipStream_t)stream) != 0)
+    return fail(SIM_EDEVICE, "export launch failed");
+  return SIM_OK;
+}
+
+int sim_mlp_gather(sim_handle* h, float* d_x, float* d_t, long cap, long long* d_total) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (!d_x || !d_t || !d_total || cap < 0) return fail(SIM_EINVAL, "bad output arguments");
+  if (!(h->last_dt > 0.f) || !h->last_export) return fail(SIM_EINVAL, "gather needs a previous step with export on");
+  const float gm = std::sqrt(h->gravity[0] * h->gravity[0] + h->gravity[1] * h->gravity[1] +
+                             h->gravity[2] * h->gravity[2]);
+  if (!(gm > 0.f)) return fail(SIM_EINVAL, "gather scales targets by |g| dt; gravity is zero");
+  const Layout& L = h->lay;
+  // the last step wrote its cache into the buffer the next step reads
+  int rc = rbs_gather(at<int32_t>(h, L.off_ccount[h->parity]), at<int32_t>(h, L.off_st[4]), h->S, h->CM,
+                      (long)h->S * h->CM, at<float>(h, L.off_x_feat), at<float>(h, L.off_x_lambda),
+                      1.0f / (gm * h->last_dt), at<int64_t>(h, L.off_gather), d_x, d_t, cap, d_total, h->stream);
+  if (rc != 0) return fail(SIM_EDEVICE, "gather launch failed");
+  return SIM_OK;
+}
 
 const char* sim_last_error(void) { return g_err.c_str(); }
 

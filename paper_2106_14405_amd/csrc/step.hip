@@ -24,7 +24,7 @@
 #include <stdint.h>
 
 #include "geom.h"
-#include "mlp_infer.h"
+#include "mlp_mfma.h"
 #include "sim_internal.h"
 
 namespace rbs {
@@ -891,7 +891,12 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
   for (int i = tid; i < nprev; i += T) S.u[L.prevk + i] = P.prev_key[(long)s * CM + i];
   __syncthreads();
   const float gmag = sqrtf(P.gx * P.gx + P.gy * P.gy + P.gz * P.gz);
-  for (int i = tid; i < nc; i += T) {
+  // Wave-uniform trip count: the network's matrix-core calls need all 64
+  // lanes of a wave; lanes past the end redo the last contact, store nothing.
+  const int lane = tid & 63;
+  for (int ib = tid - lane; ib < nc; ib += T) {
+    const bool live = ib + lane < nc;
+    const int i = live ? ib + lane : nc - 1;
     const int q = (int)perm[i];
     float4 r0 = raw[2 * q], r1 = raw[2 * q + 1];
     float phi = r0.w;
@@ -981,11 +986,11 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       feat[11] = n.x; feat[12] = n.y; feat[13] = n.z;
       feat[14] = mu;
       feat[15] = hit >= 0 ? 1.f : 0.f;
-      if (P.export_on && P.x_feat)
+      if (live && P.export_on && P.x_feat)
         for (int k = 0; k < 16; k++) P.x_feat[k * P.scene_cm + (long)s * CM + q] = feat[k];
       if (P.warm == WARM_LEARNED) {
         float y[3];
-        mlp_contact(P.mlp, feat, y);
+        mlp_wave(P.mlp, feat, live, y);
         float sc = gmag * dt / k3[0];
         l0 = y[0] * sc; l1 = y[1] * sc; l2 = y[2] * sc;
       }
@@ -1000,8 +1005,10 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     int na = A.im > 0.f ? (int)deg[a] : 0;
     int nbb = (b >= 0 && B.im > 0.f) ? (int)deg[b] : 0;
     float jsc = 1.0f / (float)(na > nbb ? na : nbb);
-    store_rec(rec, i, rw, bias, mu, key, jsc);
-    st4(S.f + L.lam, i, make_float4(l0, l1, l2, phi));
+    if (live) {
+      store_rec(rec, i, rw, bias, mu, key, jsc);
+      st4(S.f + L.lam, i, make_float4(l0, l1, l2, phi));
+    }
   }
   __syncthreads();
   TRACE(10);

@@ -624,3 +624,45 @@ def test_bf16_rounding_matches_torch():
     ref = torch.tensor(xs, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
     got = np.array([O.bf16(v) for v in xs])
     np.testing.assert_array_equal(got, ref)
+
+
+# ------------------------------------------------------------ Adam
+def test_adam_first_step_is_lr_times_sign():
+    """Bias correction makes the first update exactly lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(5)
+    g = rng.normal(size=50) * 10 ** rng.uniform(-3, 3, size=50)
+    p0 = rng.normal(size=50)
+    p, m, v, _, _ = O.adam_step(p0, np.zeros(50), np.zeros(50), g, 1, 1e-3)
+    np.testing.assert_allclose(p0 - p, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
+
+
+def test_adam_constant_gradient_constant_step():
+    """With a constant gradient the corrected moments equal g and g^2 at
+    every step, so each update is lr * sign(g) (up to eps)."""
+    g = np.array([0.3, -2.0, 5e-3])
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for k in range(1, 40):
+        q, m, v, _, _ = O.adam_step(p, m, v, g, k, 1e-2)
+        np.testing.assert_allclose(p - q, 1e-2 * np.sign(g), rtol=1e-5)
+        p = q
+
+
+def test_adam_scale_invariant_and_clip_norm():
+    """Rescaling every gradient by one constant leaves the trajectory
+    unchanged (eps aside); clipping yields norm min(|g|, clip) along g."""
+    rng = np.random.default_rng(6)
+    gs = [rng.normal(size=20) for _ in range(5)]
+    pa = pb = rng.normal(size=20)
+    ma = va = mb = vb = np.zeros(20)
+    for k, g in enumerate(gs, 1):
+        pa, ma, va, _, _ = O.adam_step(pa, ma, va, g, k, 1e-3)
+        pb, mb, vb, _, _ = O.adam_step(pb, mb, vb, 1e3 * g, k, 1e-3)
+    np.testing.assert_allclose(pa, pb, rtol=0, atol=1e-9)
+    g = gs[0]
+    n = np.linalg.norm(g)
+    _, _, _, gc, norm = O.adam_step(np.zeros(20), np.zeros(20), np.zeros(20), g, 1, 1e-3, clip=0.5 * n)
+    assert abs(norm - n) <= 1e-12 * n
+    assert abs(np.linalg.norm(gc) - 0.5 * n) <= 1e-12 * n
+    assert abs(gc @ g / (np.linalg.norm(gc) * n) - 1) <= 1e-12
+    _, _, _, gc, _ = O.adam_step(np.zeros(20), np.zeros(20), np.zeros(20), g, 1, 1e-3, clip=2 * n)
+    np.testing.assert_array_equal(gc, g)
