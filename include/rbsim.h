@@ -123,7 +123,12 @@ typedef struct sim_contact_view {
     const uint32_t *pair_key; /* [S*max_pairs] */
 } sim_contact_view;
 
-/* Per-scene statistics of the last step, device arrays of length S. */
+/* Per-scene statistics of the last step, device arrays of length S.
+ * Flags: NOT_CONVERGED when the tolerance was set and the last sweep's
+ * residual is above it (the step is not solved, whatever its start);
+ * FELLBACK when the network's start impulses were rejected before the
+ * sweeps (they raised the solver's objective) and the new contacts started
+ * from zero. */
 typedef struct sim_stats_view {
     const int32_t *pairs, *contacts, *colours, *sweeps, *flags;
     const float *residual;    /* last sweep's max |dlambda| * k (m/s) */
@@ -166,10 +171,22 @@ int sim_set_mlp(sim_handle *h, const uint16_t *d_w1, const uint16_t *d_w2, const
 /* ---- Learned warm start: the network outside the step ------------------
  * The warm-start network maps 16 contact features (z-scored with a
  * training-set mean and std, std floored at 1e-6) through 64 -> ReLU -> 64
- * -> ReLU -> 3 outputs y; the initial impulse is y * |g| dt / k_n, projected
- * onto the friction cone.  The paper has no learned solver: the network is
- * this library's replacement for the classic previous-step warm start
- * (Catto 2005).  Its z-scoring echoes the per-channel input normalization of
+ * -> ReLU -> 3 outputs y.  Features, world frame, SI units: 0-2 relative
+ * velocity along n, t1, t2; 3 depth -phi; 4-5 inverse masses of A and B;
+ * 6-7 (r x n) . I^-1 (r x n) of A and B; 8-10 previous impulses along n,
+ * t1, t2 in units of |g| dt / k_n; 11-13 the normal n; 14 friction
+ * coefficient; 15 for a new contact 1 / max(n_A, n_B) (n_X: contacts
+ * touching dynamic body X), 0 for a persisting one.  In SIM_LEARNED mode a contact that persists
+ * from the previous step starts from its previous impulse (the classic warm
+ * start, Catto 2005) and a new contact from y |g| dt / k_n, in units of the
+ * impulse that cancels one step of gravity along the normal (features 8-10
+ * are the previous impulses in the same units); starts are projected onto
+ * the friction cone.  Before any sweep the solver scores the network's part
+ * on its quadratic objective f(l) = 1/2 l^T A l + l^T (u_free - b) (rows:
+ * normal with target velocity b = bias, two friction rows with b = 0): if
+ * adding the new contacts' impulses raises f, they are dropped (the new
+ * contacts start from zero as in SIM_PREV) and SIM_FLAG_FELLBACK is set.  The paper has no learned
+ * solver: the network is this library's addition to the classic warm start.  Its z-scoring echoes the per-channel input normalization of
  * the appendix's monolithic policy (App. B.1), and the optimizer defaults
  * the caller is expected to use come from that policy's training setup
  * (App. B.2: Adam, lr 1e-4 decayed linearly, gradient norm clipped at 0.5).
@@ -225,13 +242,16 @@ int sim_mlp_adam(float *d_params, float *d_m, float *d_v, const float *d_grad, i
 int sim_mlp_export(const float *d_params, uint16_t *d_wbf16, float *d_bias, void *stream);
 
 /* Training rows from the last step (which must have run with export on):
- * for every contact of every scene whose flags are all clear, its 16
- * features into d_x [cap][16] and its impulses scaled by k_n / (|g| dt)
- * (k_n from the features: w_A + w_B + the two angular terms) into
- * d_t [cap][3], scenes in order, contacts in canonical order.  Rows past
- * cap are dropped; *d_total (device) receives the number of rows there
- * were.  Asynchronous on the handle's stream. */
-int sim_mlp_gather(sim_handle *h, float *d_x, float *d_t, long cap, long long *d_total);
+ * for every new contact (feature 15 > 0) of every scene whose flags are all
+ * clear, its 16 features into d_x [cap][16] and into d_t [cap][3] the
+ * network's target, its converged impulses in units of |g| dt / k_n, i.e.
+ * lambda k_n / (|g| dt) (k_n from the features: w_A + w_B + the two
+ * angular terms), each saturated to [-target_clip, target_clip] when
+ * target_clip > 0 (the converged impulses of stacked light bodies are
+ * heavy-tailed and not unique), scenes in order, contacts in canonical
+ * order.  Rows past cap are dropped; *d_total (device) receives the
+ * number of rows there were.  Asynchronous on the handle's stream. */
+int sim_mlp_gather(sim_handle *h, float *d_x, float *d_t, long cap, float target_clip, long long *d_total);
 
 /* Masked reset: for every scene s with d_mask[s] != 0, copy its bodies'
  * pose [7][N] and velocity [6][N] from d_pose/d_vel (same layout as the

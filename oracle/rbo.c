@@ -1143,9 +1143,34 @@ static int solve(Body *B, int nb, Con *C, const int *order, int nc, int iters, d
     return sw;
 }
 
-static void warm_apply(Body *B, Con *C, const int *order, int nc) {
+/* Change of the solver's quadratic objective f(l) = 1/2 l^T A l +
+ * l^T (u_free - b) when the network's start impulses of the new contacts,
+ * l_n, are added to the persisting contacts' previous impulses l_p:
+ * f(l_p + l_n) - f(l_p) = sum over the new contacts' rows of the impulse
+ * times (the mean of the row velocity before and after l_n was applied)
+ * minus the row's target velocity (the bias for the normal row, zero for
+ * the friction rows); vs holds the velocities before l_n was applied. */
+static double start_objective(const Body *B, const Con *C, int nc, const V *vs) {
+    double f = 0;
+    for (int q = 0; q < nc; q++) {
+        const Con *c = &C[q];
+        if (c->matched) continue;
+        V va = add(vs[2 * c->a], cross(vs[2 * c->a + 1], c->ra));
+        V vb = c->b >= 0 ? add(vs[2 * c->b], cross(vs[2 * c->b + 1], c->rb)) : mk(0, 0, 0);
+        V v0 = sub(va, vb), v1 = vrel(B, c);
+        f += c->lam[0] * (0.5 * (dot(c->n, v0) + dot(c->n, v1)) - c->bias);
+        f += c->lam[1] * 0.5 * (dot(c->t1, v0) + dot(c->t1, v1));
+        f += c->lam[2] * 0.5 * (dot(c->t2, v0) + dot(c->t2, v1));
+    }
+    return f;
+}
+
+/* Applies the start impulses in solver order (sel < 0), or only those of
+ * the persisting (sel 0) or new (sel 1) contacts. */
+static void warm_apply(Body *B, Con *C, const int *order, int nc, int sel) {
     for (int q = 0; q < nc; q++) {
         Con *c = &C[order[q]];
+        if (sel >= 0 && (c->matched ? 0 : 1) != sel) continue;
         project(c);
         apply(B, c, add(scl(c->n, c->lam[0]), add(scl(c->t1, c->lam[1]), scl(c->t2, c->lam[2]))));
     }
@@ -1220,7 +1245,12 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         }
     }
 
-    /* 7. setup */
+    /* 7. setup; contacts per dynamic body first (a feature of new contacts) */
+    int *ndyn = calloc((size_t)(nb ? nb : 1), sizeof(int));
+    for (int q = 0; q < nc; q++) {
+        if (B[C[q].a].motion == ORA_DYNAMIC) ndyn[C[q].a]++;
+        if (C[q].b >= 0 && B[C[q].b].motion == ORA_DYNAMIC) ndyn[C[q].b]++;
+    }
     for (int q = 0; q < nc; q++) {
         Con *c = &C[q];
         Body *A = &B[c->a];
@@ -1257,18 +1287,35 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         f[6] = dot(can, Mv(&A->Iw, can));
         if (c->b >= 0) { V cbn = cross(c->rb, c->n); f[7] = dot(cbn, Mv(&B[c->b].Iw, cbn)); }
         else f[7] = 0;
-        f[8] = lp[0]; f[9] = lp[1]; f[10] = lp[2];
+        /* previous impulses in units of |g| dt / k_n (the impulse that
+         * cancels one step of gravity along the normal; 1 m/s^2 stands in for
+         * |g| when gravity is off), the units of the network's outputs */
+        double unit = (gmag > 0 ? gmag : 1.0) * dt * c->m[0];
+        f[8] = lp[0] / unit; f[9] = lp[1] / unit; f[10] = lp[2] / unit;
         f[11] = c->n.x; f[12] = c->n.y; f[13] = c->n.z;
-        f[14] = c->mu; f[15] = c->matched ? 1.0 : 0.0;
+        f[14] = c->mu;
+        /* new contact: its share 1 / max(n_A, n_B) of the busier body's
+         * contacts (the impulse that stops a body splits over them); a
+         * persisting contact: 0 */
+        {
+            int na = ndyn[c->a], nbc = c->b >= 0 ? ndyn[c->b] : 0;
+            int mx = na > nbc ? na : nbc;
+            f[15] = c->matched ? 0.0 : 1.0 / (double)(mx > 1 ? mx : 1);
+        }
         c->lam[0] = c->lam[1] = c->lam[2] = 0;
         if (warm == ORA_PREV) { c->lam[0] = lp[0]; c->lam[1] = lp[1]; c->lam[2] = lp[2]; }
         else if (warm == ORA_LEARNED && mlp) {
             double y[3];
             ora_mlp_forward(mlp, f, 1, y);
+            /* a persisting contact keeps its previous impulse (the classic
+             * warm start); the network predicts the impulse of a new contact,
+             * in units of |g| dt / k_n */
             double sc = gmag * dt * c->m[0];
-            for (int r = 0; r < 3; r++) c->lam[r] = y[r] * sc;
+            for (int r = 0; r < 3; r++) c->lam[r] = c->matched ? lp[r] : y[r] * sc;
         }
     }
+
+    free(ndyn);
 
     /* 9. colouring: first fit in canonical order; only dynamic bodies conflict */
     uint64_t *used = calloc((size_t)(nb ? nb : 1) * (MAXCOL / 64), sizeof(uint64_t));
@@ -1304,21 +1351,28 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
 
     /* 8. initial impulses, 10. sweeps */
     V *vsave = malloc(sizeof(V) * 2 * (nb ? nb : 1));
-    for (int i = 0; i < nb; i++) { vsave[2 * i] = B[i].v; vsave[2 * i + 1] = B[i].w; }
-    warm_apply(B, C, order, nc);
-    double R = 0;
-    int sweeps = solve(B, nb, C, order, nc, iters, tol, solver, &R);
-    if (tol > 0 && R > tol) {
-        if (warm == ORA_LEARNED) {
+    /* Learned start: the persisting contacts' previous impulses first, then
+     * the network's impulses of the new contacts.  The plain solver judges
+     * the network's part before any sweep: if it raises the solver's
+     * objective it is dropped (new contacts start from zero, the classic
+     * warm start) and the step is flagged. */
+    if (warm == ORA_LEARNED) {
+        warm_apply(B, C, order, nc, 0);
+        for (int i = 0; i < nb; i++) { vsave[2 * i] = B[i].v; vsave[2 * i + 1] = B[i].w; }
+        warm_apply(B, C, order, nc, 1);
+        if (start_objective(B, C, nc, vsave) > 0) {
             flags |= ORA_F_FELLBACK;
             for (int i = 0; i < nb; i++) { B[i].v = vsave[2 * i]; B[i].w = vsave[2 * i + 1]; }
-            for (int q = 0; q < nc; q++) C[q].lam[0] = C[q].lam[1] = C[q].lam[2] = 0;
-            sweeps = solve(B, nb, C, order, nc, iters, tol, solver, &R);
-            if (R > tol) flags |= ORA_F_NOT_CONVERGED;
-        } else {
-            flags |= ORA_F_NOT_CONVERGED;
+            for (int q = 0; q < nc; q++)
+                if (!C[q].matched) C[q].lam[0] = C[q].lam[1] = C[q].lam[2] = 0;
         }
+    } else {
+        warm_apply(B, C, order, nc, -1);
     }
+    double R = 0;
+    int sweeps = solve(B, nb, C, order, nc, iters, tol, solver, &R);
+    /* a step counts as solved only once its residual reached the tolerance */
+    if (tol > 0 && R > tol) flags |= ORA_F_NOT_CONVERGED;
     free(vsave);
 
     /* 11. position integration; arm joint update */

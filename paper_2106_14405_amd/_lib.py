@@ -106,7 +106,7 @@ def load():
     L.sim_mlp_grad.argtypes = [_v, _v, _v, _v, _v, _v, C.c_long, _v, _v, _v, C.c_size_t, _v]
     L.sim_mlp_adam.argtypes = [_v, _v, _v, _v, C.c_int, _f, _f, _v, _v]
     L.sim_mlp_export.argtypes = [_v, _v, _v, _v]
-    L.sim_mlp_gather.argtypes = [_v, _v, _v, C.c_long, _v]
+    L.sim_mlp_gather.argtypes = [_v, _v, _v, C.c_long, _f, _v]
     for name in ("sim_create", "sim_step", "sim_contacts", "sim_state", "sim_stats", "sim_set_export",
                  "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_trace", "sim_set_stream",
                  "sim_mlp_forward", "sim_mlp_stats", "sim_mlp_grad", "sim_mlp_adam", "sim_mlp_export",

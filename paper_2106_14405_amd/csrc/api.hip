@@ -29,8 +29,8 @@ extern "C" int rbs_mlp_adam(float* prm, float* m1, float* m2, const float* grad,
                             float* gnorm, hipStream_t st);
 extern "C" int rbs_mlp_export(const float* prm, uint16_t* wbf, float* bias, hipStream_t st);
 extern "C" int rbs_gather(const int32_t* count, const int32_t* flags, int S, int CM, long scm, const float* feat,
-                          const float* lam, float inv_gdt, int64_t* offs, float* x, float* t, long cap,
-                          long long* total, hipStream_t st);
+                          const float* lam, float inv_gdt, float tclip, int64_t* offs, int32_t* cnt, float* x,
+                          float* t, long cap, long long* total, hipStream_t st);
 extern "C" int rbs_launch_arm_pose(const rbs::StepParams* P, const uint8_t* mask, hipStream_t stream);
 extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, const float* pool_pose,
                                 const float* pool_vel, const float* pool_theta, int32_t* count_a, int32_t* count_b,
@@ -52,7 +52,7 @@ struct Layout {
   size_t off_x_pair, off_x_npairs, off_x_normal, off_x_point, off_x_phi, off_x_lambda, off_x_colour, off_x_feat;
   size_t off_raw, off_crec;
   size_t off_st[7];
-  size_t off_gather;
+  size_t off_gather, off_gcount;
   size_t total;
 };
 
@@ -91,7 +91,8 @@ Layout make_layout(long S, long N, long PM, long CM) {
   L.off_raw = take(4 * 8 * S * CM);
   L.off_crec = take(4 * 52 * S * CM);  // 13 float4 solver record per contact
   for (int k = 0; k < 7; k++) L.off_st[k] = take(4 * S);
-  L.off_gather = take(8 * S);  // per-scene row offsets of sim_mlp_gather
+  L.off_gather = take(8 * S);  // per-scene row offsets and counts of sim_mlp_gather
+  L.off_gcount = take(4 * S);
   L.total = o;
   return L;
 }
@@ -587,9 +588,10 @@ int sim_mlp_export(const float* d_params, uint16_t* d_wbf16, float* d_bias, void
   return SIM_OK;
 }
 
-int sim_mlp_gather(sim_handle* h, float* d_x, float* d_t, long cap, long long* d_total) {
+int sim_mlp_gather(sim_handle* h, float* d_x, float* d_t, long cap, float target_clip, long long* d_total) {
   if (!h) return fail(SIM_EINVAL, "handle is NULL");
   if (!d_x || !d_t || !d_total || cap < 0) return fail(SIM_EINVAL, "bad output arguments");
+  if (!(target_clip >= 0.f)) return fail(SIM_EINVAL, "target_clip must be >= 0");
   if (!(h->last_dt > 0.f) || !h->last_export) return fail(SIM_EINVAL, "gather needs a previous step with export on");
   const float gm = std::sqrt(h->gravity[0] * h->gravity[0] + h->gravity[1] * h->gravity[1] +
                              h->gravity[2] * h->gravity[2]);
@@ -598,7 +600,8 @@ int sim_mlp_gather(sim_handle* h, float* d_x, float* d_t, long cap, long long* d
   // the last step wrote its cache into the buffer the next step reads
   int rc = rbs_gather(at<int32_t>(h, L.off_ccount[h->parity]), at<int32_t>(h, L.off_st[4]), h->S, h->CM,
                       (long)h->S * h->CM, at<float>(h, L.off_x_feat), at<float>(h, L.off_x_lambda),
-                      1.0f / (gm * h->last_dt), at<int64_t>(h, L.off_gather), d_x, d_t, cap, d_total, h->stream);
+                      1.0f / (gm * h->last_dt), target_clip, at<int64_t>(h, L.off_gather),
+                      at<int32_t>(h, L.off_gcount), d_x, d_t, cap, d_total, h->stream);
   if (rc != 0) return fail(SIM_EDEVICE, "gather launch failed");
   return SIM_OK;
 }

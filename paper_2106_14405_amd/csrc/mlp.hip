@@ -1,7 +1,7 @@
 // mlp.hip -- kernels of the learned warm start's network outside the step:
 // batched inference (the same wave-level matrix-core routine the step runs),
 // feature statistics, the loss gradient, Adam with global-norm clipping,
-// the bf16 export of the weights, and the gather of logged contacts.
+// the bf16 export of the weights, and the gather of logged new contacts.
 //
 // Network: 16 features -> 64 -> ReLU -> 64 -> ReLU -> 3, features z-scored
 // with a training-set mean and std (std floored at 1e-6); inference rounds
@@ -293,17 +293,32 @@ __global__ __launch_bounds__(256) void mlp_export_kernel(const float* __restrict
 }
 
 // ---- gather of logged contacts ---------------------------------------------------
-// Scenes with any flag set are skipped.  Offsets: exclusive scan of the
-// kept scenes' contact counts (one workgroup, fixed order).
-__global__ __launch_bounds__(1024) void gather_scan(const int32_t* __restrict__ count,
-                                                    const int32_t* __restrict__ flags, int S, int CM,
+// The network warm-starts new contacts only (a persisting contact keeps its
+// previous impulse), so the rows are the new contacts (feature 15 > 0) of
+// the scenes whose flags are all clear.  Per-scene counts, an exclusive scan
+// of them (one workgroup, fixed order), then an order-preserving copy.
+__global__ __launch_bounds__(64) void gather_count(const int32_t* __restrict__ count,
+                                                   const int32_t* __restrict__ flags, int CM, long scm,
+                                                   const float* __restrict__ feat, int32_t* __restrict__ cnt) {
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int nc = flags[s] ? 0 : min(count[s], CM);
+  const float* share = feat + 15 * scm + (long)s * CM;
+  int c = 0;
+  for (int q0 = 0; q0 < nc; q0 += 64) {
+    const bool fresh = q0 + lane < nc && share[q0 + lane] > 0.f;
+    c += __popcll(__ballot(fresh));
+  }
+  if (lane == 0) cnt[s] = c;
+}
+
+__global__ __launch_bounds__(1024) void gather_scan(const int32_t* __restrict__ cnt, int S,
                                                     int64_t* __restrict__ offs, long long* total) {
   __shared__ int64_t part[1024];
   const int t = threadIdx.x;
   const int per = (S + 1023) / 1024;
   const int s0 = t * per, s1 = min(S, s0 + per);
   int64_t a = 0;
-  for (int s = s0; s < s1; s++) a += flags[s] ? 0 : min(count[s], CM);
+  for (int s = s0; s < s1; s++) a += cnt[s];
   part[t] = a;
   __syncthreads();
   // Hillis-Steele inclusive scan
@@ -316,7 +331,7 @@ __global__ __launch_bounds__(1024) void gather_scan(const int32_t* __restrict__ 
   int64_t o = t ? part[t - 1] : 0;
   for (int s = s0; s < s1; s++) {
     offs[s] = o;
-    o += flags[s] ? 0 : min(count[s], CM);
+    o += cnt[s];
   }
   if (t == 1023) *total = part[1023];
 }
@@ -324,23 +339,32 @@ __global__ __launch_bounds__(1024) void gather_scan(const int32_t* __restrict__ 
 __global__ __launch_bounds__(64) void gather_rows(const int32_t* __restrict__ count,
                                                   const int32_t* __restrict__ flags, int CM, long scm,
                                                   const float* __restrict__ feat, const float* __restrict__ lam,
-                                                  float inv_gdt, const int64_t* __restrict__ offs, float* __restrict__ x,
-                                                  float* __restrict__ tg, long cap) {
-  const int s = blockIdx.x;
+                                                  float inv_gdt, float tclip, const int64_t* __restrict__ offs,
+                                                  float* __restrict__ x, float* __restrict__ tg, long cap) {
+  const int s = blockIdx.x, lane = threadIdx.x;
   if (flags[s]) return;
   const int nc = min(count[s], CM);
-  for (int q = threadIdx.x; q < nc; q += 64) {
-    const long row = offs[s] + q;
-    if (row >= cap) continue;
-    const long o = (long)s * CM + q;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  long base = offs[s];
+  for (int q0 = 0; q0 < nc; q0 += 64) {
+    const int q = q0 + lane;
+    const long o = (long)s * CM + (q < nc ? q : 0);
+    const bool fresh = q < nc && feat[15 * scm + o] > 0.f;
+    const uint64_t m = __ballot(fresh);
+    const long row = base + __popcll(m & below);
+    base += __popcll(m);
+    if (!fresh || row >= cap) continue;
     float f[16];
     for (int k = 0; k < 16; k++) f[k] = feat[k * scm + o];
     for (int k = 0; k < 16; k++) x[16 * row + k] = f[k];
-    // effective inverse mass along the normal from the features:
-    // w_A + w_B + (r_A x n) I_A^-1 (r_A x n) + (r_B x n) I_B^-1 (r_B x n)
-    const float kn = f[4] + f[5] + f[6] + f[7];
-    const float sc = kn * inv_gdt;
-    for (int k = 0; k < 3; k++) tg[3 * row + k] = lam[k * scm + o] * sc;
+    // target: the converged impulse in units of |g| dt / k_n, with k_n from
+    // the features: w_A + w_B + (r_A x n) I_A^-1 (r_A x n) + (r_B x n) I_B^-1 (r_B x n)
+    const float sc = (f[4] + f[5] + f[6] + f[7]) * inv_gdt;
+    for (int k = 0; k < 3; k++) {
+      float v = lam[k * scm + o] * sc;
+      if (tclip > 0.f) v = fminf(fmaxf(v, -tclip), tclip);
+      tg[3 * row + k] = v;
+    }
   }
 }
 
@@ -391,10 +415,11 @@ extern "C" int rbs_mlp_export(const float* prm, uint16_t* wbf, float* bias, hipS
 }
 
 extern "C" int rbs_gather(const int32_t* count, const int32_t* flags, int S, int CM, long scm, const float* feat,
-                          const float* lam, float inv_gdt, int64_t* offs, float* x, float* t, long cap,
-                          long long* total, hipStream_t st) {
-  hipLaunchKernelGGL(gather_scan, dim3(1), dim3(1024), 0, st, count, flags, S, CM, offs, total);
-  hipLaunchKernelGGL(gather_rows, dim3(S), dim3(64), 0, st, count, flags, CM, scm, feat, lam, inv_gdt,
+                          const float* lam, float inv_gdt, float tclip, int64_t* offs, int32_t* cnt, float* x,
+                          float* t, long cap, long long* total, hipStream_t st) {
+  hipLaunchKernelGGL(gather_count, dim3(S), dim3(64), 0, st, count, flags, CM, scm, feat, cnt);
+  hipLaunchKernelGGL(gather_scan, dim3(1), dim3(1024), 0, st, (const int32_t*)cnt, S, offs, total);
+  hipLaunchKernelGGL(gather_rows, dim3(S), dim3(64), 0, st, count, flags, CM, scm, feat, lam, inv_gdt, tclip,
                      (const int64_t*)offs, x, t, cap);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

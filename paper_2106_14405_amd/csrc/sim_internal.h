@@ -89,17 +89,19 @@ struct StepParams {
 //  ckey [CM]: contact keys, canonical order
 //  lam  [CM][4]: (lambda_n, lambda_t1, lambda_t2, phi), colour-major order
 //  perm [CM]: colour-major position -> canonical contact index
+//  fresh [CM/32] (learned warm start only): bit i set when colour-major
+//       contact i is new, i.e. started from the network
 // The per-contact solver constants live in global memory (StepParams::crec).
 // The scratch region is reused phase by phase: broadphase (pairs, AABBs,
 // body sort); colouring (colours, per-body lists); setup (previous keys);
-// solver (saved velocities, Jacobi snapshot and increments); outputs (arm
-// force partial sums).
+// solver (saved velocities and start objective terms of a learned start,
+// Jacobi snapshot and increments); outputs (arm force partial sums).
 struct LdsLayout {
-  int geo, dyn, ckey, lam, perm, misc, hist, hbase;
+  int geo, dyn, ckey, lam, perm, fresh, misc, hist, hbase;
   int scr;
   int pk, pk2, lo, hi, skey, sval, skey2, sval2;
   int colour, deg, lstart, list, rank, prevk, cv0, ck1;
-  int vsave, snap, dl, force;
+  int vsave, fval, snap, dl, force;
   int total;  // words
 };
 
@@ -114,6 +116,7 @@ inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int wave
   L.ckey = take(CM);
   L.lam = take(4 * CM);
   L.perm = take(CM);
+  L.fresh = (warm == WARM_LEARNED) ? take((CM + 31) / 32) : -1;
   L.misc = take(kMiscWords);
   L.hist = take(256 * waves);
   L.hbase = take(256);
@@ -144,6 +147,7 @@ inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int wave
   int q = after_deg;    // solver and outputs: lists are dead, deg and colour live on
   auto tq = [&](int words) { int r = q; q += (words + 3) & ~3; return r; };
   L.vsave = (warm == WARM_LEARNED) ? tq(8 * NB) : -1;
+  L.fval = (warm == WARM_LEARNED) ? tq(CM) : -1;
   L.snap = (solver == SOLVER_JACOBI) ? tq(8 * NB) : -1;
   L.dl = (solver == SOLVER_JACOBI) ? tq(4 * CM) : -1;
   L.force = after_deg;  // outputs run after the solve

@@ -376,10 +376,40 @@ __device__ __forceinline__ float pgs_update(const LdsLayout& L, Smem S, const Re
   return fmaxf(fmaxf(fabsf(dn) * frcp(wn.m), fabsf(d1) * frcp(w1.m)), fabsf(d2) * frcp(w2.m));
 }
 
-// Applies the current impulses of every contact, colour-major (warm start).
-__device__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int ncol, const uint32_t* cstart) {
+// Objective change from adding the network's start impulses of colour-major
+// contact i (zero for a persisting contact): the impulse times (the mean of
+// the row velocity before and after the new contacts' impulses were
+// applied) minus the row's target (bias for the normal row, zero for
+// friction).  Summed over the contacts this is f(l_p + l_n) - f(l_p) for the
+// solver's quadratic objective f(l) = 1/2 l^T A l + l^T (u_free - b).
+__device__ __forceinline__ float start_objective(const LdsLayout& L, Smem S, const float4* rec, int i) {
+  if (!((S.u[L.fresh + (i >> 5)] >> (i & 31)) & 1u)) return 0.f;
+  Rec R = load_rec(rec, i);
+  const int a = rec_a(R), b = rec_b(R);
+  const float4 lam = ld4(S.f + L.lam, i);
+  Vel A1 = load_vel(L, S, a), B1 = load_vel(L, S, b);
+  Vel A0 = A1, B0 = B1;  // velocities before the new contacts' impulses: saved copy
+  A0.v = xyz(ld4(S.f + L.vsave, 2 * a));
+  A0.w = xyz(ld4(S.f + L.vsave, 2 * a + 1));
+  if (b >= 0) {
+    B0.v = xyz(ld4(S.f + L.vsave, 2 * b));
+    B0.w = xyz(ld4(S.f + L.vsave, 2 * b + 1));
+  }
+  const float bias = R.r[3].w;
+  Row wn = rec_row(R, 0), w1 = rec_row(R, 1), w2 = rec_row(R, 2);
+  float f = lam.x * (0.5f * (row_u(wn, A0, B0) + row_u(wn, A1, B1)) - bias);
+  f += lam.y * 0.5f * (row_u(w1, A0, B0) + row_u(w1, A1, B1));
+  f += lam.z * 0.5f * (row_u(w2, A0, B0) + row_u(w2, A1, B1));
+  return f;
+}
+
+// Applies the current impulses of every contact, colour-major (warm start);
+// with `select` >= 0 only the contacts whose fresh bit equals it.
+__device__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int ncol, const uint32_t* cstart,
+                          int select = -1) {
   for (int c = 0; c < ncol; c++) {
     for (int i = (int)cstart[c] + threadIdx.x; i < (int)cstart[c + 1]; i += blockDim.x) {
+      if (select >= 0 && (int)((S.u[L.fresh + (i >> 5)] >> (i & 31)) & 1u) != select) continue;
       Rec R = load_rec(rec, i);
       const int a = rec_a(R), b = rec_b(R);
       float4 lam = ld4(S.f + L.lam, i);
@@ -889,6 +919,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
   // ---- a7/a10: previous impulses, constraint setup (colour-major) ------
   const int nprev = P.prev_count ? (P.prev_count[s] < CM ? P.prev_count[s] : CM) : 0;
   for (int i = tid; i < nprev; i += T) S.u[L.prevk + i] = P.prev_key[(long)s * CM + i];
+  if (P.warm == WARM_LEARNED)
+    for (int i = tid; i < (nc + 31) / 32; i += T) S.u[L.fresh + i] = 0u;
   __syncthreads();
   const float gmag = sqrtf(P.gx * P.gx + P.gy * P.gy + P.gz * P.gz);
   // Wave-uniform trip count: the network's matrix-core calls need all 64
@@ -982,17 +1014,32 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       feat[6] = dot(can, Imul(A.I, can));
       V3 cbn = cross(c.rb, n);
       feat[7] = b >= 0 ? dot(cbn, Imul(B.I, cbn)) : 0.f;
-      feat[8] = lp0; feat[9] = lp1; feat[10] = lp2;
+      // previous impulses in units of |g| dt / k_n (1 m/s^2 when gravity is off)
+      const float unit = (gmag > 0.f ? gmag : 1.f) * dt / k3[0];
+      feat[8] = lp0 / unit; feat[9] = lp1 / unit; feat[10] = lp2 / unit;
       feat[11] = n.x; feat[12] = n.y; feat[13] = n.z;
       feat[14] = mu;
-      feat[15] = hit >= 0 ? 1.f : 0.f;
+      // new contact: its share 1 / max(n_a, n_b) of the busier body's
+      // contacts; a persisting contact: 0
+      {
+        const int na = A.im > 0.f ? (int)deg[a] : 0;
+        const int nbc = (b >= 0 && B.im > 0.f) ? (int)deg[b] : 0;
+        const int mx = na > nbc ? na : nbc;
+        feat[15] = hit >= 0 ? 0.f : 1.f / (float)(mx > 1 ? mx : 1);
+      }
       if (live && P.export_on && P.x_feat)
         for (int k = 0; k < 16; k++) P.x_feat[k * P.scene_cm + (long)s * CM + q] = feat[k];
       if (P.warm == WARM_LEARNED) {
         float y[3];
         mlp_wave(P.mlp, feat, live, y);
+        // a persisting contact keeps its previous impulse; the network
+        // predicts a new contact's, in units of |g| dt / k_n
         float sc = gmag * dt / k3[0];
-        l0 = y[0] * sc; l1 = y[1] * sc; l2 = y[2] * sc;
+        if (hit >= 0) {
+          l0 = lp0; l1 = lp1; l2 = lp2;
+        } else {
+          l0 = y[0] * sc; l1 = y[1] * sc; l2 = y[2] * sc;
+        }
       }
     }
     if (P.warm == WARM_PREV) {
@@ -1008,47 +1055,66 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     if (live) {
       store_rec(rec, i, rw, bias, mu, key, jsc);
       st4(S.f + L.lam, i, make_float4(l0, l1, l2, phi));
+      if (P.warm == WARM_LEARNED && hit < 0) atomicOr(S.u + L.fresh + (i >> 5), 1u << (i & 31));
     }
   }
   __syncthreads();
   TRACE(10);
 
   // ---- a8/a11: warm start and sweeps ------------------------------------
+  // Learned start: persisting contacts' previous impulses are applied first,
+  // then the network's impulses of the new contacts.  The plain solver
+  // judges the network's part before any sweep: if it raises the solver's
+  // objective it is dropped (the new contacts start from zero, the classic
+  // warm start) and the step is flagged.
   if (P.warm == WARM_LEARNED) {
+    apply_all(L, S, rec, ncol, cstart, 0);
+    __syncthreads();
     for (int i = tid; i < nb; i += T) {
       st4(S.f + L.vsave, 2 * i, ld4(S.f + L.dyn, 4 * i));
       st4(S.f + L.vsave, 2 * i + 1, ld4(S.f + L.dyn, 4 * i + 1));
     }
     __syncthreads();
+    apply_all(L, S, rec, ncol, cstart, 1);
+    __syncthreads();
+    float* fval = S.f + L.fval;
+    for (int i = tid; i < nc; i += T) fval[i] = start_objective(L, S, rec, i);
+    __syncthreads();
+    // fixed-shape tree sum: same result for any block size
+    int width = 1;
+    while (width < nc) width <<= 1;
+    for (int half = width >> 1; half > 0; half >>= 1) {
+      for (int i = tid; i < half; i += T)
+        if (i + half < nc) fval[i] += fval[i + half];
+      __syncthreads();
+    }
+    if (nc > 0 && fval[0] > 0.f) {  // uniform across the workgroup
+      if (tid == 0) misc[M_FLAGS] |= FLAG_FELLBACK;
+      for (int i = tid; i < nb; i += T) {
+        st4(S.f + L.dyn, 4 * i, ld4(S.f + L.vsave, 2 * i));
+        st4(S.f + L.dyn, 4 * i + 1, ld4(S.f + L.vsave, 2 * i + 1));
+      }
+      for (int i = tid; i < nc; i += T) {
+        if (!((S.u[L.fresh + (i >> 5)] >> (i & 31)) & 1u)) continue;
+        float phi = S.f[L.lam + 4 * i + 3];
+        st4(S.f + L.lam, i, make_float4(0.f, 0.f, 0.f, phi));
+      }
+    }
+    __syncthreads();
+  } else if (P.warm == WARM_PREV) {
+    apply_all(L, S, rec, ncol, cstart);
   }
-  if (P.warm != WARM_COLD) apply_all(L, S, rec, ncol, cstart);
   TRACE(11);
   int sweeps = 0;
   float res = 0.f;
   const uint64_t clk0 = P.trace ? clock64() : 0;
-  for (int attempt = 0; attempt < 2; attempt++) {
-    if (P.solver == SOLVER_JACOBI)
-      solve_jacobi(L, S, rec, nb, nc, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res);
-    else
-      solve_pgs(L, S, rec, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res);
-    __syncthreads();
-    if (!(P.tol > 0.f && res > P.tol)) break;
-    if (P.warm != WARM_LEARNED || attempt == 1) {
-      if (tid == 0) misc[M_FLAGS] |= FLAG_NOT_CONVERGED;
-      break;
-    }
-    // learned start rejected: restore post-gravity velocities, solve cold
-    if (tid == 0) misc[M_FLAGS] |= FLAG_FELLBACK;
-    for (int i = tid; i < nb; i += T) {
-      st4(S.f + L.dyn, 4 * i, ld4(S.f + L.vsave, 2 * i));
-      st4(S.f + L.dyn, 4 * i + 1, ld4(S.f + L.vsave, 2 * i + 1));
-    }
-    for (int i = tid; i < nc; i += T) {
-      float phi = S.f[L.lam + 4 * i + 3];
-      st4(S.f + L.lam, i, make_float4(0.f, 0.f, 0.f, phi));
-    }
-    __syncthreads();
-  }
+  if (P.solver == SOLVER_JACOBI)
+    solve_jacobi(L, S, rec, nb, nc, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res);
+  else
+    solve_pgs(L, S, rec, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res);
+  __syncthreads();
+  // a step counts as solved only once its residual reached the tolerance
+  if (P.tol > 0.f && res > P.tol && tid == 0) misc[M_FLAGS] |= FLAG_NOT_CONVERGED;
   __syncthreads();
   TRACE(12);
   if (P.trace && tid == 0) P.trace[(long)s * kTraceSlots + 15] = clock64() - clk0;  // shader cycles in the solve

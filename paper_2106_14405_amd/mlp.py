@@ -156,14 +156,15 @@ class Net:
         L.check(self.lib.sim_set_mlp(sim.h, w.w1, w.w2, w.w3, w.b1, w.b2, w.b3, w.mean, w.std), "sim_set_mlp")
 
 
-def gather(sim, cap: int | None = None):
-    """Training rows (features [n, 16], scaled targets [n, 3]) of the sim's last step."""
+def gather(sim, cap: int | None = None, target_clip: float = 0.0):
+    """Training rows (features [n, 16], scaled targets [n, 3], saturated at
+    +-target_clip when > 0) of the sim's last step."""
     lib = L.load()
     cap = int(cap if cap is not None else sim.S * sim.max_contacts)
     x = torch.empty((max(cap, 1), 16), dtype=torch.float32, device=sim.device)
     t = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=sim.device)
     total = torch.zeros(1, dtype=torch.int64, device=sim.device)
-    L.check(lib.sim_mlp_gather(sim.h, _p(x), _p(t), cap, _p(total)), "sim_mlp_gather")
+    L.check(lib.sim_mlp_gather(sim.h, _p(x), _p(t), cap, float(target_clip), _p(total)), "sim_mlp_gather")
     n = min(int(total.item()), cap)
     return x[:n], t[:n]
 

@@ -666,3 +666,80 @@ def test_adam_scale_invariant_and_clip_norm():
     assert abs(gc @ g / (np.linalg.norm(gc) * n) - 1) <= 1e-12
     _, _, _, gc, _ = O.adam_step(np.zeros(20), np.zeros(20), np.zeros(20), g, 1, 1e-3, clip=2 * n)
     np.testing.assert_array_equal(gc, g)
+
+
+# ------------------------------------------------------------ learned warm start in the step
+def _const_net(y=(0.0, 0.0, 0.0), scale=0.0, seed=0):
+    """Network with output y everywhere (scale 0), or random weights times scale."""
+    rng = np.random.default_rng(seed)
+    p = dict(w1=rng.normal(size=(64, 16)) * scale, b1=np.zeros(64), w2=rng.normal(size=(64, 64)) * scale,
+             b2=np.zeros(64), w3=rng.normal(size=(3, 64)) * scale, b3=np.asarray(y, float),
+             mean=np.zeros(16), std=np.ones(16))
+    if scale:
+        p["b1"] = np.ones(64) * scale
+        p["b2"] = np.ones(64) * scale
+    return p
+
+
+def test_learned_new_contact_unit_is_gravity_impulse():
+    """A new resting sphere contact started from network output (1, 0, 0)
+    starts at exactly m g dt (k_n = 1/m at the centre), which is the
+    converged impulse: one sweep reaches the tolerance."""
+    b = custom_batch([[dict(shape=S.SPHERE, param=[0.1, 0, 0], mass=1.3, pos=[0, 0, 0.1])]])
+    sim = sim_of(b)
+    sim.set_mlp(_const_net((1.0, 0.0, 0.0)))
+    r = sim.step(iters=50, tol=1e-10, warm=O.LEARNED)
+    assert r["c_feat"][0, 0, 15] == 1.0
+    assert abs(r["c_lambda"][0, 0, 0] - float(b.mass[0]) * G * DT) < 1e-12
+    assert r["sweeps"][0] == 1 and not (r["flags"][0] & O.F_FELLBACK)
+
+
+def _stack_state():
+    h = 0.1
+    bodies = [dict(shape=S.BOX, param=[h, h, h], mass=1.0 + 0.5 * k, pos=[0.01 * k, 0, h + 2 * h * k])
+              for k in range(3)]
+    b = custom_batch([bodies])
+    sim = sim_of(b)
+    for _ in range(60):
+        sim.step(iters=100, tol=1e-8, warm=O.PREV)
+    return b, sim
+
+
+def test_learned_zero_net_is_classic_warm_start():
+    """Persisting contacts keep their previous impulses: with a zero network
+    (new contacts start at zero, as in PREV) the learned step is the PREV
+    step, bit for bit, and the start is not rejected."""
+    b, sim = _stack_state()
+    pose, vel, theta = sim.pose.copy(), sim.vel.copy(), sim.theta.copy()
+    cache = sim.cache_arrays()
+    ra = sim.step(iters=100, tol=1e-4, warm=O.PREV)
+    pa, va = sim.pose.copy(), sim.vel.copy()
+    sim.set_state(pose, vel, theta, cache)
+    sim.set_mlp(_const_net())
+    rb = sim.step(iters=100, tol=1e-4, warm=O.LEARNED)
+    assert not (rb["flags"][0] & O.F_FELLBACK)
+    assert ra["sweeps"][0] == rb["sweeps"][0]
+    np.testing.assert_array_equal(sim.pose, pa)
+    np.testing.assert_array_equal(sim.vel, va)
+    np.testing.assert_array_equal(ra["c_lambda"], rb["c_lambda"])
+
+
+def test_learned_bad_start_rejected_for_cold():
+    """Huge impulses on new contacts raise the solver's objective: the
+    network's part is dropped (FELLBACK); with every contact new, the step
+    is the COLD step."""
+    b = custom_batch([[dict(shape=S.SPHERE, param=[0.1, 0, 0], mass=1.0, pos=[0, 0, 0.11], vel=[0, 0, -0.5, 0, 0, 0]),
+                       dict(shape=S.BOX, param=[0.1, 0.1, 0.1], mass=2.0, pos=[1, 0, 0.105])]])
+    sim = sim_of(b)
+    pose, vel, theta = sim.pose.copy(), sim.vel.copy(), sim.theta.copy()
+    cache = sim.cache_arrays()
+    ra = sim.step(iters=100, tol=1e-6, warm=O.COLD)
+    pa, va = sim.pose.copy(), sim.vel.copy()
+    sim.set_state(pose, vel, theta, cache)
+    sim.set_mlp(_const_net((500.0, 300.0, -200.0)))
+    rb = sim.step(iters=100, tol=1e-6, warm=O.LEARNED)
+    assert ra["n_contacts"][0] >= 2
+    assert rb["flags"][0] & O.F_FELLBACK
+    assert ra["sweeps"][0] == rb["sweeps"][0]
+    np.testing.assert_array_equal(sim.pose, pa)
+    np.testing.assert_array_equal(sim.vel, va)
