@@ -77,8 +77,9 @@ typedef struct sim_batch_desc {
     float rest_thresh;           /* approach speed above which restitution applies (m/s) */
     float ground_friction;       /* friction of the plane z = 0 */
     float ground_restitution;
-    int max_pairs;               /* per-scene capacity of broadphase pairs */
-    int max_contacts;            /* per-scene capacity of contacts */
+    int max_pairs;               /* per-scene capacity of broadphase pairs (a scene of n
+                                    bodies holds at most min(max_pairs, max(64, 6 n))) */
+    int max_contacts;            /* per-scene capacity of contacts (same rule) */
     int solver;                  /* SIM_PGS or SIM_JACOBI */
     int warm_start;              /* SIM_COLD, SIM_PREV or SIM_LEARNED */
     float tolerance;             /* > 0: stop sweeps once the residual (m/s) <= tolerance;
@@ -267,6 +268,36 @@ int sim_reset(sim_handle *h, const uint8_t *d_mask, const float *d_pose, const f
  * 15 holds the shader-clock cycles spent in the solver sweeps.
  * NULL turns it off.  For profiling; adds one store per phase. */
 int sim_set_trace(sim_handle *h, uint64_t *d_trace);
+
+/* ---- Batches of uneven scene sizes ---------------------------------------
+ * The paper benchmarks many environments stepped in parallel (Sec. 4.4)
+ * and names their synchronisation, and reloading on episode reset, as what
+ * bounds the whole loop (Sec. 7).  Scene sizes differ, so one workgroup per
+ * scene sized for the largest scene wastes the LDS.
+ * With on = 1 every later sim_step is one persistent launch (after a queue
+ * reset) replayed from a HIP graph captured on first use and again whenever
+ * the step's arguments change: each workgroup (256 threads, the device's
+ * whole LDS) first steps scenes from a queue of large scenes with all its
+ * threads, then each of its four waves steps scenes from a queue of small
+ * scenes alone in a quarter of the LDS.  Both queues run largest first.  A
+ * scene is small when it has at most wave_max_bodies bodies (< 0: no limit)
+ * and its working set fits a quarter of the LDS.  Results are identical to
+ * the one-workgroup-per-scene launch.  on = 0 restores that launch.
+ * SIM_ECAPACITY if a scene fits no workgroup. */
+int sim_set_persistent(sim_handle *h, int on, int wave_max_bodies);
+
+/* Device scratch (256-byte aligned) sim_autotune needs to save and restore
+ * the simulation state: pose, velocity, joint angles and contact caches. */
+size_t sim_autotune_scratch_bytes(const sim_handle *h);
+
+/* Picks wave_max_bodies for the persistent launch by timing `steps` steps
+ * (zero actions, dt, iters sweeps) for each candidate (0 and the powers of
+ * two from 16 up to the largest scene) and restoring the state after each;
+ * leaves the persistent launch on with the fastest and reports it in
+ * *out_wave_max_bodies (may be NULL).  Synchronises the handle's stream;
+ * the last step's contact and stats views then hold a trial step's values. */
+int sim_autotune(sim_handle *h, void *d_scratch, size_t scratch_bytes, int steps, float dt, int iters,
+                 int *out_wave_max_bodies);
 
 int sim_set_stream(sim_handle *h, void *stream);
 void sim_destroy(sim_handle *h);

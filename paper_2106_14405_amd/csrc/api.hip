@@ -20,6 +20,8 @@
 extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L, int threads, int grid,
                                hipStream_t stream);
 extern "C" int rbs_set_step_lds_limit(int bytes);
+extern "C" int rbs_launch_persistent(const rbs::StepParams* P, const rbs::QueueParams* Q, int grid,
+                                     hipStream_t stream);
 extern "C" int rbs_mlp_forward(const rbs::MlpParams* M, const float* x, long n, float* y, hipStream_t st);
 extern "C" size_t rbs_mlp_work_bytes(long n);
 extern "C" int rbs_mlp_stats(const float* x, long n, float* mean, float* stdv, void* work, hipStream_t st);
@@ -53,6 +55,7 @@ struct Layout {
   size_t off_raw, off_crec;
   size_t off_st[7];
   size_t off_gather, off_gcount;
+  size_t off_queue, off_head;
   size_t total;
 };
 
@@ -93,6 +96,8 @@ Layout make_layout(long S, long N, long PM, long CM) {
   for (int k = 0; k < 7; k++) L.off_st[k] = take(4 * S);
   L.off_gather = take(8 * S);  // per-scene row offsets and counts of sim_mlp_gather
   L.off_gcount = take(4 * S);
+  L.off_queue = take(4 * 2 * S);  // persistent launch: team queue, wave queue
+  L.off_head = take(256);
   L.total = o;
   return L;
 }
@@ -121,7 +126,22 @@ struct sim_handle {
   bool mlp_set;
   uint64_t* trace;
   int lds_limit;
+  std::vector<int> body_offset;  // host copy, [S + 1]
+  // persistent launch
+  bool persistent = false;
+  int wave_max_bodies = 0;
+  int n_team = 0, n_wave = 0, lds_words = 0, grid = 0;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  rbs::StepParams exec_key[2];
+  ~sim_handle();
 };
+
+sim_handle::~sim_handle() {
+  for (int k = 0; k < 2; k++)
+    if (exec[k]) hipGraphExecDestroy(exec[k]);
+  if (capture_stream) hipStreamDestroy(capture_stream);
+}
 
 namespace {
 
@@ -269,6 +289,139 @@ int device_lds_limit() {
   return v;
 }
 
+// Persistent launch: a queue for whole-workgroup teams and one for single-wave
+// teams, each in descending body count (ties by scene index).  A scene goes
+// to a wave when it has at most wave_max_bodies bodies and its working set
+// (for the current solver mode) fits a quarter of the workgroup's LDS.
+int build_queues(sim_handle* h, int wave_max_bodies) {
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SIM_EDEVICE, "hipGetDevice failed");
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+    return fail(SIM_EDEVICE, "multiprocessor count unavailable");
+  // the workgroup's dynamic LDS: the device limit less its static words, a multiple of 16 words
+  const int lds_words = ((h->lds_limit - 256) / 4) & ~15;
+  std::vector<int> team, wave;
+  for (int s = 0; s < h->S; s++) {
+    const int nb = h->body_offset[s + 1] - h->body_offset[s];
+    const int pm = rbs::scene_cap(nb, h->PM), cm = rbs::scene_cap(nb, h->CM);
+    const int need_wave = rbs::lds_layout(nb, pm, cm, 1, h->solver, h->warm).total;
+    const int need_team = rbs::lds_layout(nb, pm, cm, 4, h->solver, h->warm).total;
+    if (nb <= wave_max_bodies && need_wave <= lds_words / 4)
+      wave.push_back(s);
+    else if (need_team <= lds_words)
+      team.push_back(s);
+    else
+      return fail(SIM_ECAPACITY, "scene " + std::to_string(s) + " does not fit a workgroup's LDS");
+  }
+  auto by_size = [&](int a, int b) {
+    const int na = h->body_offset[a + 1] - h->body_offset[a], nb = h->body_offset[b + 1] - h->body_offset[b];
+    return na != nb ? na > nb : a < b;
+  };
+  std::sort(team.begin(), team.end(), by_size);
+  std::sort(wave.begin(), wave.end(), by_size);
+  std::vector<int32_t> q(2 * (size_t)h->S, 0);
+  std::copy(team.begin(), team.end(), q.begin());
+  std::copy(wave.begin(), wave.end(), q.begin() + h->S);
+  hipError_t e = hipMemcpyAsync(at<int32_t>(h, h->lay.off_queue), q.data(), q.size() * 4, hipMemcpyHostToDevice,
+                                h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(SIM_EDEVICE, "queue upload failed");
+  h->n_team = (int)team.size();
+  h->n_wave = (int)wave.size();
+  h->lds_words = lds_words;
+  h->grid = ncu;
+  h->wave_max_bodies = wave_max_bodies;
+  for (int k = 0; k < 2; k++)
+    if (h->exec[k]) {
+      hipGraphExecDestroy(h->exec[k]);
+      h->exec[k] = nullptr;
+    }
+  return SIM_OK;
+}
+
+rbs::QueueParams queue_params(sim_handle* h) {
+  rbs::QueueParams Q;
+  Q.team = at<int32_t>(h, h->lay.off_queue);
+  Q.wave = at<int32_t>(h, h->lay.off_queue) + h->S;
+  Q.n_team = h->n_team;
+  Q.n_wave = h->n_wave;
+  Q.head = at<uint32_t>(h, h->lay.off_head);
+  Q.lds_words = h->lds_words;
+  return Q;
+}
+
+// One step through a graph of (queue reset, persistent kernel) captured once
+// per cache parity and argument set, replayed on the handle's stream.
+int launch_persistent(sim_handle* h, const rbs::StepParams& P) {
+  const int par = h->parity;
+  if (!h->exec[par] || memcmp(&h->exec_key[par], &P, sizeof(P)) != 0) {
+    if (h->exec[par]) {
+      hipGraphExecDestroy(h->exec[par]);
+      h->exec[par] = nullptr;
+    }
+    hipError_t e;
+    if (!h->capture_stream) {
+      e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return (int)e;
+    }
+    rbs::QueueParams Q = queue_params(h);
+    e = hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return (int)e;
+    int rc = rbs_launch_persistent(&P, &Q, h->grid, h->capture_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->capture_stream, &g);
+    if (rc != 0) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return (int)e;
+    e = hipGraphInstantiate(&h->exec[par], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      h->exec[par] = nullptr;
+      return (int)e;
+    }
+    h->exec_key[par] = P;
+  }
+  return (int)hipGraphLaunch(h->exec[par], h->stream);
+}
+
+// State a step changes (and the autotuner restores): pose, velocity, joint
+// angles and both contact caches.
+struct StateSpan {
+  size_t off, bytes;
+};
+
+std::vector<StateSpan> state_spans(const sim_handle* h) {
+  const Layout& L = h->lay;
+  const size_t S = h->S, N = h->N, CM = h->CM;
+  std::vector<StateSpan> v = {{L.off_pose, 4 * 7 * N}, {L.off_vel, 4 * 6 * N}, {L.off_theta, 4 * 7 * S}};
+  for (int k = 0; k < 2; k++) {
+    v.push_back({L.off_ckey[k], 4 * S * CM});
+    v.push_back({L.off_clam[k], 4 * 4 * S * CM});
+    v.push_back({L.off_ccount[k], 4 * S});
+  }
+  return v;
+}
+
+size_t state_bytes(const sim_handle* h) {
+  size_t t = 0;
+  for (const StateSpan& sp : state_spans(h)) t += align256(sp.bytes);
+  return t;
+}
+
+int copy_state(sim_handle* h, char* scratch, bool save) {
+  size_t o = 0;
+  for (const StateSpan& sp : state_spans(h)) {
+    void* dev = h->ws + sp.off;
+    hipError_t e = save ? hipMemcpyAsync(scratch + o, dev, sp.bytes, hipMemcpyDeviceToDevice, h->stream)
+                        : hipMemcpyAsync(dev, scratch + o, sp.bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return (int)e;
+    o += align256(sp.bytes);
+  }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -291,7 +444,9 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   if (!d_workspace || workspace_bytes < lay.total) return fail(SIM_EWORKSPACE, "workspace too small");
   if (((uintptr_t)d_workspace & 255u) != 0) return fail(SIM_EWORKSPACE, "workspace must be 256-byte aligned");
   const int T = d->threads ? d->threads : 64;
-  int need = lds_bytes(c.NB, d->max_pairs, d->max_contacts, T, SIM_JACOBI, SIM_LEARNED);
+  // the working set of the largest scene under the descriptor's solver mode
+  // (sim_set_solver and sim_step check again for later modes)
+  int need = lds_bytes(c.NB, d->max_pairs, d->max_contacts, T, d->solver, d->warm_start);
   int limit = device_lds_limit();
   if (need > limit)
     return fail(SIM_ECAPACITY, "per-scene working set (" + std::to_string(need) + " B) exceeds LDS (" +
@@ -329,6 +484,7 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   h->mlp_set = false;
   h->trace = nullptr;
   h->lds_limit = limit;
+  h->body_offset.assign(d->h_body_offset, d->h_body_offset + S + 1);
 
   // host staging: structure-of-arrays planes
   std::vector<float> prm(3 * N), inv_mass(N), inv_I(3 * N), pose(7 * N), vel(6 * N);
@@ -414,10 +570,16 @@ int sim_step(sim_handle* h, const float* d_actions, float dt, int iters) {
   P.actions = d_actions;
   P.dt = dt;
   P.iters = iters;
-  rbs::LdsLayout L = rbs::lds_layout(h->NB, h->PM, h->CM, h->threads / 64, h->solver, h->warm);
-  if (L.total * 4 > h->lds_limit) return fail(SIM_ECAPACITY, "working set exceeds LDS");
-  int rc = rbs_launch_step(&P, &L, h->threads, h->S, h->stream);
-  if (rc != 0) return fail(SIM_EDEVICE, std::string("step launch failed: ") + hipGetErrorString((hipError_t)rc));
+  int rc;
+  if (h->persistent) {
+    rc = launch_persistent(h, P);
+    if (rc != 0) return fail(SIM_EDEVICE, std::string("persistent step failed: ") + hipGetErrorString((hipError_t)rc));
+  } else {
+    rbs::LdsLayout L = rbs::lds_layout(h->NB, h->PM, h->CM, h->threads / 64, h->solver, h->warm);
+    if (L.total * 4 > h->lds_limit) return fail(SIM_ECAPACITY, "working set exceeds LDS");
+    rc = rbs_launch_step(&P, &L, h->threads, h->S, h->stream);
+    if (rc != 0) return fail(SIM_EDEVICE, std::string("step launch failed: ") + hipGetErrorString((hipError_t)rc));
+  }
   h->parity ^= 1;
   h->last_dt = dt;
   h->last_export = h->export_on;
@@ -484,8 +646,19 @@ int sim_set_solver(sim_handle* h, int solver, int warm_start, float tolerance) {
   if (solver != SIM_PGS && solver != SIM_JACOBI) return fail(SIM_EINVAL, "bad solver");
   if (warm_start < SIM_COLD || warm_start > SIM_LEARNED) return fail(SIM_EINVAL, "bad warm start");
   if (!(tolerance >= 0.f)) return fail(SIM_EINVAL, "tolerance must be >= 0");
+  const int old_solver = h->solver, old_warm = h->warm;
   h->solver = solver;
   h->warm = warm_start;
+  if (h->persistent && (solver != old_solver || warm_start != old_warm)) {
+    // the working sets change size: route the scenes again
+    int rc = build_queues(h, h->wave_max_bodies);
+    if (rc != SIM_OK) {
+      h->solver = old_solver;
+      h->warm = old_warm;
+      build_queues(h, h->wave_max_bodies);
+      return rc;
+    }
+  }
   h->tol = tolerance;
   return SIM_OK;
 }
@@ -532,6 +705,79 @@ int sim_set_stream(sim_handle* h, void* stream) {
 }
 
 void sim_destroy(sim_handle* h) { delete h; }
+
+int sim_set_persistent(sim_handle* h, int on, int wave_max_bodies) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (!on) {
+    h->persistent = false;
+    return SIM_OK;
+  }
+  int rc = build_queues(h, wave_max_bodies < 0 ? rbs::kMaxBodiesPerScene : wave_max_bodies);
+  if (rc != SIM_OK) return rc;
+  h->persistent = true;
+  return SIM_OK;
+}
+
+size_t sim_autotune_scratch_bytes(const sim_handle* h) { return h ? state_bytes(h) : 0; }
+
+int sim_autotune(sim_handle* h, void* d_scratch, size_t scratch_bytes, int steps, float dt, int iters,
+                 int* out_wave_max_bodies) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (steps < 1 || !(dt > 0.f) || iters < 1) return fail(SIM_EINVAL, "steps, dt and iters must be positive");
+  if (!d_scratch || scratch_bytes < state_bytes(h) || ((uintptr_t)d_scratch & 255u))
+    return fail(SIM_EWORKSPACE, "scratch too small or not 256-byte aligned");
+  if (h->warm == SIM_LEARNED && !h->mlp_set) return fail(SIM_EINVAL, "learned warm start needs sim_set_mlp");
+  // candidate thresholds: none, then the body-count buckets present in the batch
+  std::vector<int> cand = {0};
+  int nmax = 0;
+  for (int s = 0; s < h->S; s++) nmax = std::max(nmax, h->body_offset[s + 1] - h->body_offset[s]);
+  for (int b = 16; b / 2 < nmax && b <= rbs::kMaxBodiesPerScene; b *= 2) cand.push_back(b);
+  const bool was_persistent = h->persistent;
+  const int was_threshold = h->wave_max_bodies, parity0 = h->parity;
+  char* scratch = static_cast<char*>(d_scratch);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return fail(SIM_EDEVICE, "event creation failed");
+  }
+  int best = -1, rc = SIM_OK;
+  float best_ms = 0.f;
+  if (copy_state(h, scratch, true) != 0) rc = fail(SIM_EDEVICE, "state save failed");
+  for (size_t k = 0; k < cand.size() && rc == SIM_OK; k++) {
+    rc = build_queues(h, cand[k]);
+    if (rc != SIM_OK) break;
+    if (k > 0 && h->n_wave == 0) continue;  // same routing as no waves
+    h->persistent = true;
+    // one untimed step captures the graphs' first parity; then the timed ones
+    for (int it = 0; it <= steps && rc == SIM_OK; it++) {
+      if (it == 1 && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(SIM_EDEVICE, "event record failed");
+      if (rc == SIM_OK) rc = sim_step(h, nullptr, dt, iters);
+    }
+    float ms = 0.f;
+    if (rc == SIM_OK && (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = fail(SIM_EDEVICE, "timing failed");
+    if (rc == SIM_OK && copy_state(h, scratch, false) != 0) rc = fail(SIM_EDEVICE, "state restore failed");
+    h->parity = parity0;
+    if (rc == SIM_OK && (best < 0 || ms < best_ms)) {
+      best = cand[k];
+      best_ms = ms;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == SIM_OK) hipStreamSynchronize(h->stream);
+  if (rc != SIM_OK) {
+    h->persistent = was_persistent;
+    if (was_persistent) build_queues(h, was_threshold);
+    return rc;
+  }
+  rc = build_queues(h, best);
+  if (rc != SIM_OK) return rc;
+  h->persistent = true;
+  if (out_wave_max_bodies) *out_wave_max_bodies = best;
+  return SIM_OK;
+}
 
 int sim_mlp_forward(const sim_mlp_weights* w, const float* d_x, long n, float* d_y, void* stream) {
   if (!w || !w->w1 || !w->w2 || !w->w3 || !w->b1 || !w->b2 || !w->b3 || !w->mean || !w->std)

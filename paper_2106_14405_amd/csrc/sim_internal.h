@@ -12,6 +12,15 @@ constexpr int kMaxBodiesPerScene = 1024;
 constexpr uint32_t kGroundPair = 0xFFFFu;
 constexpr uint32_t kGroundKey = 0xFFFu;
 constexpr int kTraceSlots = 16;
+constexpr int kCapPerBody = 6;   // per-scene pair and contact capacity: kCapPerBody * bodies,
+constexpr int kCapFloor = 64;    // at least kCapFloor, at most the batch-wide capacity
+
+// Pair or contact capacity of a scene of nb bodies under batch capacity cap.
+inline __host__ __device__ int scene_cap(int nb, int cap) {
+  int c = kCapPerBody * nb;
+  if (c < kCapFloor) c = kCapFloor;
+  return c < cap ? c : cap;
+}
 
 enum { WARM_COLD = 0, WARM_PREV = 1, WARM_LEARNED = 2 };
 enum { SOLVER_PGS = 0, SOLVER_JACOBI = 1 };
@@ -81,6 +90,17 @@ struct StepParams {
   MlpParams mlp;
   const int32_t* scene_list;  // optional scene order (null: identity)
   uint64_t* trace;            // optional [S][kTraceSlots] phase timestamps (null: off)
+};
+
+// Work queues of the persistent launch: scenes stepped by a whole workgroup
+// (`team`) and scenes stepped by one wave each (`wave`), largest first, and
+// the two queue heads (zeroed before every launch).
+struct QueueParams {
+  const int32_t* team;
+  const int32_t* wave;
+  int n_team, n_wave;
+  uint32_t* head;        // [2]
+  int lds_words;         // dynamic LDS of a workgroup; a wave owns a quarter
 };
 
 // LDS word offsets of one scene's working set.  Records are float4-aligned:

@@ -33,6 +33,28 @@ typedef unsigned long long u64;
 
 enum { M_NPAIRS = 0, M_NCONT = 1, M_FLAGS = 2, M_NCOL = 3, M_CHANGED = 5, M_WAVE = 16, M_SCAN = 32 };
 
+// The threads that step one scene: a whole workgroup, or a single wave of a
+// larger workgroup (persistent launch).  A team starts on a wave boundary.
+template <bool kWave>
+struct Team {
+  static constexpr bool wave = kWave;  // one wave of a multi-wave workgroup
+  int tid, T;                          // index within the team; team size, a multiple of 64
+};
+
+// Barrier among a team's threads: a workgroup barrier, or for one wave of a
+// larger workgroup the wave's own memory fences (its LDS operations
+// complete in issue order; the fence also waits for its global stores).
+template <class TM>
+__device__ __forceinline__ void team_sync(const TM& tm) {
+  if constexpr (TM::wave) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Phase timestamp (constant-rate wall clock) of scene s, slot k, if tracing.
 #define TRACE(k)                                                                    \
   do {                                                                              \
@@ -60,15 +82,16 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 
 // In-place exclusive prefix sum of a[0..n) in LDS; every thread takes a
 // contiguous chunk; returns the total.  misc supplies per-wave slots.
-__device__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* misc) {
-  const int tid = threadIdx.x, T = blockDim.x, W = T >> 6, w = tid >> 6, lane = tid & 63;
+template <class TM>
+__device__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* misc, const TM& tm) {
+  const int tid = tm.tid, T = tm.T, W = T >> 6, w = tid >> 6, lane = tid & 63;
   const int chunk = (n + T - 1) / T;
   const int i0 = tid * chunk, i1 = min(n, i0 + chunk);
   uint32_t sum = 0;
   for (int i = i0; i < i1; i++) sum += a[i];
   uint32_t incl = wave_incl_scan(sum);
   if (lane == 63) misc[M_SCAN + w] = incl;
-  __syncthreads();
+  team_sync(tm);
   uint32_t base = 0, total = 0;
   for (int ww = 0; ww < W; ww++) {
     uint32_t t = misc[M_SCAN + ww];
@@ -81,7 +104,7 @@ __device__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* misc) {
     a[i] = run;
     run += v;
   }
-  __syncthreads();
+  team_sync(tm);
   return total;
 }
 
@@ -89,18 +112,19 @@ __device__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* misc) {
 // 8-bit digits from bit `shift0`.  Ranks within a wave come from eight
 // ballots that isolate the lanes holding the same digit.  Returns 1 if the
 // sorted data ended in (k1, v1), 0 if in (k0, v0).
+template <class TM>
 __device__ int lds_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int n, int shift0, int passes,
-                              uint32_t* hist, uint32_t* base, uint32_t* misc) {
-  const int T = blockDim.x, tid = threadIdx.x, W = T >> 6, w = tid >> 6;
+                              uint32_t* hist, uint32_t* base, uint32_t* misc, const TM& tm) {
+  const int T = tm.T, tid = tm.tid, W = T >> 6, w = tid >> 6;
   int swapped = 0;
   for (int ps = 0; ps < passes; ps++) {
     const int sh = shift0 + 8 * ps;
     for (int i = tid; i < 256; i += T) base[i] = 0u;
     for (int i = tid; i < 256 * W; i += T) hist[i] = 0u;
-    __syncthreads();
+    team_sync(tm);
     for (int i = tid; i < n; i += T) atomicAdd(&base[(k0[i] >> sh) & 255u], 1u);
-    __syncthreads();
-    block_exclusive_scan(base, 256, misc);
+    team_sync(tm);
+    block_exclusive_scan(base, 256, misc, tm);
     for (int t0 = 0; t0 < n; t0 += T) {
       const int i = t0 + tid;
       const bool valid = i < n;
@@ -114,21 +138,21 @@ __device__ int lds_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t
       }
       unsigned rank = lanes_below(peers);
       if (valid && rank == 0) hist[w * 256 + d] = (uint32_t)__popcll(peers);
-      __syncthreads();
+      team_sync(tm);
       if (valid) {
         uint32_t off = base[d] + rank;
         for (int ww = 0; ww < w; ww++) off += hist[ww * 256 + d];
         k1[off] = key;
         v1[off] = val;
       }
-      __syncthreads();
+      team_sync(tm);
       if (t0 + T < n) {
         for (int dd = tid; dd < 256; dd += T) {
           uint32_t s = 0;
           for (int ww = 0; ww < W; ww++) { s += hist[ww * 256 + dd]; hist[ww * 256 + dd] = 0u; }
           base[dd] += s;
         }
-        __syncthreads();
+        team_sync(tm);
       }
     }
     uint32_t* t;
@@ -146,14 +170,16 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // Block-wide maximum of non-negative floats (one value per thread).
-__device__ __forceinline__ float block_max(float v, uint32_t* misc) {
-  const int tid = threadIdx.x, W = blockDim.x >> 6;
+template <class TM>
+__device__ __forceinline__ float block_max(float v, uint32_t* misc, const TM& tm) {
+  const int tid = tm.tid, W = tm.T >> 6;
   v = wave_max(v);
+  if (W == 1) return v;
   if ((tid & 63) == 0) misc[M_WAVE + (tid >> 6)] = __float_as_uint(v);
-  __syncthreads();
+  team_sync(tm);
   float r = 0.f;
   for (int w = 0; w < W; w++) r = fmaxf(r, __uint_as_float(misc[M_WAVE + w]));
-  __syncthreads();
+  team_sync(tm);
   return r;
 }
 
@@ -337,16 +363,17 @@ __device__ __forceinline__ void row_apply(const Row& w, Vel& A, Vel& B, float dl
   B.w = B.w - w.ib * dl;
 }
 
-// Synchronisation between colour batches: a single-wave workgroup needs only
-// a compiler fence (its LDS operations complete in issue order), which keeps
-// prefetched global loads in flight; wider workgroups use a barrier.
-__device__ __forceinline__ void colour_sync() {
-  if (blockDim.x == 64) {
+// Synchronisation between colour batches: a single-wave team needs only a
+// compiler fence (its LDS operations complete in issue order), which keeps
+// prefetched global loads in flight; wider teams use a barrier.
+template <class TM>
+__device__ __forceinline__ void colour_sync(const TM& tm) {
+  if (tm.T == 64) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   } else {
-    __syncthreads();
+    team_sync(tm);
   }
 }
 
@@ -405,10 +432,11 @@ __device__ __forceinline__ float start_objective(const LdsLayout& L, Smem S, con
 
 // Applies the current impulses of every contact, colour-major (warm start);
 // with `select` >= 0 only the contacts whose fresh bit equals it.
+template <class TM>
 __device__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int ncol, const uint32_t* cstart,
-                          int select = -1) {
+                          const TM& tm, int select = -1) {
   for (int c = 0; c < ncol; c++) {
-    for (int i = (int)cstart[c] + threadIdx.x; i < (int)cstart[c + 1]; i += blockDim.x) {
+    for (int i = (int)cstart[c] + tm.tid; i < (int)cstart[c + 1]; i += tm.T) {
       if (select >= 0 && (int)((S.u[L.fresh + (i >> 5)] >> (i & 31)) & 1u) != select) continue;
       Rec R = load_rec(rec, i);
       const int a = rec_a(R), b = rec_b(R);
@@ -421,16 +449,17 @@ __device__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int nco
       if (A.im > 0.f) store_vel(L, S, a, A);
       if (B.im > 0.f) store_vel(L, S, b, B);
     }
-    colour_sync();
+    colour_sync(tm);
   }
 }
 
 // Sweeps of projected Gauss-Seidel, colour batch after colour batch; the
 // record of a lane's next batch is loaded while the current one is solved.
 // Stops after `iters` sweeps or once a sweep's residual is <= tol (tol > 0).
+template <class TM>
 __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int ncol, const uint32_t* cstart, int iters,
-                          float tol, uint32_t* misc, int* sweeps_out, float* res_out) {
-  const int tid = threadIdx.x, T = blockDim.x;
+                          float tol, uint32_t* misc, int* sweeps_out, float* res_out, const TM& tm) {
+  const int tid = tm.tid, T = tm.T;
   int sweeps = 0;
   float res = 0.f;
   if (ncol == 0) {
@@ -455,14 +484,14 @@ __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int nco
       Rec nxt = load_rec(rec, min(inext, last));
       if (has) r = fmaxf(r, pgs_update(L, S, cur, i));
       for (int i2 = i + T; i2 < e; i2 += T) r = fmaxf(r, pgs_update(L, S, load_rec(rec, i2), i2));
-      colour_sync();
+      colour_sync(tm);
       cur = nxt;
       has = hnext;
       i = inext;
     }
     sweeps++;
     if (tol > 0.f || it == iters - 1) {
-      res = T == 64 ? wave_max(r) : block_max(r, misc);
+      res = block_max(r, misc, tm);
       if (tol > 0.f && res <= tol) break;
     }
   }
@@ -473,10 +502,11 @@ __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int nco
 // Sweeps of Jacobi: rows read the velocities of the sweep start, increments
 // scaled by 1/max(n_a, n_b) contacts per dynamic body (from the record),
 // applied colour-major.
+template <class TM>
 __device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int nb, int nc, int ncol,
                              const uint32_t* cstart, int iters, float tol, uint32_t* misc, int* sweeps_out,
-                             float* res_out) {
-  const int tid = threadIdx.x, T = blockDim.x;
+                             float* res_out, const TM& tm) {
+  const int tid = tm.tid, T = tm.T;
   float* snap = S.f + L.snap;
   int sweeps = 0;
   float res = 0.f;
@@ -485,7 +515,7 @@ __device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int 
       st4(snap, 2 * i, ld4(S.f + L.dyn, 4 * i));
       st4(snap, 2 * i + 1, ld4(S.f + L.dyn, 4 * i + 1));
     }
-    __syncthreads();
+    team_sync(tm);
     float r = 0.f;
     for (int i = tid; i < nc; i += T) {
       Rec R = load_rec(rec, i);
@@ -512,7 +542,7 @@ __device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int 
       st4(S.f + L.lam, i, make_float4(ln, l1, l2, lam.w));
       r = fmaxf(r, fmaxf(fmaxf(fabsf(dn) * frcp(wn.m), fabsf(d1) * frcp(w1.m)), fabsf(d2) * frcp(w2.m)));
     }
-    __syncthreads();
+    team_sync(tm);
     for (int c = 0; c < ncol; c++) {
       for (int i = (int)cstart[c] + tid; i < (int)cstart[c + 1]; i += T) {
         Rec R = load_rec(rec, i);
@@ -526,11 +556,11 @@ __device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int 
         if (A.im > 0.f) store_vel(L, S, a, A);
         if (B.im > 0.f) store_vel(L, S, b, B);
       }
-      __syncthreads();
+      team_sync(tm);
     }
     sweeps++;
     if (tol > 0.f || it == iters - 1) {
-      res = block_max(r, misc);
+      res = block_max(r, misc, tm);
       if (tol > 0.f && res <= tol) break;
     }
   }
@@ -593,11 +623,12 @@ __device__ void arm_fk(const StepParams& P, const LdsLayout& L, Smem S, int b0, 
   }
 }
 
-__global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
-  extern __shared__ float4 smem_f4[];
-  Smem S{reinterpret_cast<float*>(smem_f4), reinterpret_cast<uint32_t*>(smem_f4)};
-  const int tid = threadIdx.x, T = blockDim.x;
-  const int s = P.scene_list ? P.scene_list[blockIdx.x] : (int)blockIdx.x;
+// One step of scene s by team tm, its working set in the LDS at S laid
+// out by L.
+template <class TM>
+__device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L, Smem S, const int s,
+                                           const TM& tm) {
+  const int tid = tm.tid, T = tm.T;
   const int b0 = P.body_offset[s];
   const int nb = P.body_offset[s + 1] - b0;
   const int NB = P.NB, PM = P.PM, CM = P.CM;
@@ -610,6 +641,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     if (tid == 0) P.st_flags[s] = FLAG_CAPACITY;
     return;
   }
+  // this scene's pair and contact capacities (global arrays keep the batch stride)
+  const int PMs = scene_cap(nb, PM), CMs = scene_cap(nb, CM);
   if (tid < kMiscWords) misc[tid] = 0u;
   TRACE(0);
 
@@ -649,7 +682,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     st4(S.f + L.dyn, 4 * i + 2, make_float4(I[0], I[1], I[2], I[3]));
     st4(S.f + L.dyn, 4 * i + 3, make_float4(I[4], I[5], P.restitution[gi], 0.f));
   }
-  __syncthreads();
+  team_sync(tm);
   TRACE(1);
   // ---- a1: arm at theta_t, link velocities from the actions -------------
   float thd[7];
@@ -657,7 +690,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
 #pragma unroll
     for (int k = 0; k < 7; k++) thd[k] = P.actions ? P.actions[7 * s + k] : 0.f;
     if (tid == 0) arm_fk(P, L, S, nb - 7, P.arm_base + 3 * s, P.theta + 7 * s, thd);
-    __syncthreads();
+    team_sync(tm);
   }
 
   // ---- a3: AABBs and sort keys ------------------------------------------
@@ -688,12 +721,12 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     S.u[L.skey + i] = orderable(lo.x);
     S.u[L.sval + i] = (uint32_t)i;
   }
-  __syncthreads();
+  team_sync(tm);
   TRACE(2);
 
   // ---- a4: radix sort bodies by AABB minimum along x --------------------
   int sw = lds_radix_sort(S.u + L.skey, S.u + L.sval, S.u + L.skey2, S.u + L.sval2, nb, 0, 4, S.u + L.hist,
-                          S.u + L.hbase, misc);
+                          S.u + L.hbase, misc, tm);
   const uint32_t* order = S.u + (sw ? L.sval2 : L.sval);
   TRACE(3);
 
@@ -712,21 +745,21 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       if (loj.y <= hii.y && loi.y <= hij.y && loj.z <= hii.z && loi.z <= hij.z) {
         int a = i < j ? i : j, bb = i < j ? j : i;
         uint32_t slot = atomicAdd(&misc[M_NPAIRS], 1u);
-        if ((int)slot < PM) pk[slot] = ((uint32_t)a << 11) | (uint32_t)bb;
+        if ((int)slot < PMs) pk[slot] = ((uint32_t)a << 11) | (uint32_t)bb;
       }
     }
     if (di && loi.z <= 0.f) {
       uint32_t slot = atomicAdd(&misc[M_NPAIRS], 1u);
-      if ((int)slot < PM) pk[slot] = ((uint32_t)i << 11) | 2047u;
+      if ((int)slot < PMs) pk[slot] = ((uint32_t)i << 11) | 2047u;
     }
   }
-  __syncthreads();
+  team_sync(tm);
   TRACE(4);
   const int npairs_all = (int)misc[M_NPAIRS];
-  const int np = npairs_all < PM ? npairs_all : PM;
-  if (npairs_all > PM && tid == 0) misc[M_FLAGS] |= FLAG_CAPACITY;
+  const int np = npairs_all < PMs ? npairs_all : PMs;
+  if (npairs_all > PMs && tid == 0) misc[M_FLAGS] |= FLAG_CAPACITY;
   // keys are unique: sort keys only (values ride along in the same buffers)
-  int swp = lds_radix_sort(pk, pk, S.u + L.pk2, S.u + L.pk2, np, 0, 3, S.u + L.hist, S.u + L.hbase, misc);
+  int swp = lds_radix_sort(pk, pk, S.u + L.pk2, S.u + L.pk2, np, 0, 3, S.u + L.hist, S.u + L.hbase, misc, tm);
   const uint32_t* pairs = swp ? S.u + L.pk2 : pk;
   if (P.export_on) {
     for (int p = tid; p < np; p += T) {
@@ -764,7 +797,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       uint32_t pre = lanes_below(b0m) + 2u * lanes_below(b1m) + 4u * lanes_below(b2m);
       uint32_t wtot = (uint32_t)(__popcll(b0m) + 2 * __popcll(b1m) + 4 * __popcll(b2m));
       if (lane == 0) misc[M_WAVE + w] = wtot;
-      __syncthreads();
+      team_sync(tm);
       uint32_t off = base + pre;
       uint32_t tile = 0;
       for (int ww = 0; ww < W; ww++) {
@@ -777,7 +810,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       for (int k = 0; k < 4; k++) {
         if (k >= cnt) break;
         uint32_t q = off + (uint32_t)k;
-        if ((int)q < CM) {
+        if ((int)q < CMs) {
           PC c = o.get(k);
           S.u[L.ckey + q] = ((uint32_t)a << 20) | (bkey << 8) | (uint32_t)c.f;
           raw[2 * q] = f4(c.n, c.phi);
@@ -785,17 +818,17 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
         }
       }
       base += tile;
-      __syncthreads();
+      team_sync(tm);
     }
     if (tid == 0) {
       misc[M_NCONT] = base;
-      if ((int)base > CM) misc[M_FLAGS] |= FLAG_CAPACITY;
+      if ((int)base > CMs) misc[M_FLAGS] |= FLAG_CAPACITY;
     }
   }
-  __syncthreads();
+  team_sync(tm);
   TRACE(6);
   const int nc_all = (int)misc[M_NCONT];
-  const int nc = nc_all < CM ? nc_all : CM;
+  const int nc = nc_all < CMs ? nc_all : CMs;
 
   // ---- a9: colouring -----------------------------------------------------
   // per-body lists of contacts (dynamic bodies only), canonical order
@@ -806,21 +839,21 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
   uint32_t* colour = S.u + L.colour;
   const uint32_t* ckeys = S.u + L.ckey;
   for (int i = tid; i <= nb; i += T) deg[i] = 0u;
-  __syncthreads();
+  team_sync(tm);
   for (int q = tid; q < nc; q += T) {
     uint32_t key = ckeys[q];
     int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
     if (is_dyn_meta(body_meta(L, S, a))) atomicAdd(&deg[a], 1u);
     if (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) atomicAdd(&deg[b], 1u);
   }
-  __syncthreads();
+  team_sync(tm);
   for (int i = tid; i <= nb; i += T) lstart[i] = i < nb ? deg[i] : 0u;
-  __syncthreads();
-  block_exclusive_scan(lstart, nb + 1, misc);
+  team_sync(tm);
+  block_exclusive_scan(lstart, nb + 1, misc, tm);
   // fill unordered (deg becomes the per-body count again), then
   // insertion-sort each body's short list
   for (int i = tid; i < nb; i += T) deg[i] = 0u;
-  __syncthreads();
+  team_sync(tm);
   for (int q = tid; q < nc; q += T) {
     uint32_t key = ckeys[q];
     int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
@@ -829,7 +862,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     colour[q] = 0u;
     rank[q] = 0u;
   }
-  __syncthreads();
+  team_sync(tm);
   for (int i = tid; i < nb; i += T) {
     uint32_t s0 = lstart[i], e0 = lstart[i + 1];
     for (uint32_t x = s0 + 1; x < e0; x++) {
@@ -839,7 +872,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       list[y] = v;
     }
   }
-  __syncthreads();
+  team_sync(tm);
   // rank of each contact in its bodies' lists: low half for a, high half for b
   for (int i = tid; i < nb; i += T) {
     uint32_t s0 = lstart[i], e0 = lstart[i + 1];
@@ -850,13 +883,13 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       else atomicOr(&rank[q], (x - s0) << 16);
     }
   }
-  __syncthreads();
+  team_sync(tm);
   TRACE(7);
   // fixed point of c_q = mex{c_p : p < q, p shares a dynamic body with q};
   // its unique solution is sequential first fit in canonical order
   for (int round = 0; round < nc + 2; round++) {
     if (tid == 0) misc[M_CHANGED] = 0u;
-    __syncthreads();
+    team_sync(tm);
     bool changed = false;
     for (int q = tid; q < nc; q += T) {
       uint32_t key = ckeys[q];
@@ -883,9 +916,9 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       if (c != colour[q]) { colour[q] = c; changed = true; }
     }
     if (changed) misc[M_CHANGED] = 1u;
-    __syncthreads();
+    team_sync(tm);
     if (misc[M_CHANGED] == 0u) break;
-    __syncthreads();
+    team_sync(tm);
   }
   TRACE(8);
   for (int q = tid; q < nc; q += T)
@@ -898,30 +931,30 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     cidx[q] = (uint32_t)q;
     csk[q] = colour[q];
   }
-  __syncthreads();
-  lds_radix_sort(csk, cidx, rank, S.u + L.perm, nc, 0, 1, S.u + L.hist, S.u + L.hbase, misc);
+  team_sync(tm);
+  lds_radix_sort(csk, cidx, rank, S.u + L.perm, nc, 0, 1, S.u + L.hist, S.u + L.hbase, misc, tm);
   const uint32_t* perm = S.u + L.perm;
   const uint32_t* scol = rank;       // sorted colours (one pass: result in (k1, v1))
   uint32_t* cstart = S.u + L.hbase;  // colour starts (hbase is free again)
   for (int i = tid; i <= kMaxColours; i += T) cstart[i] = 0u;
-  __syncthreads();
+  team_sync(tm);
   for (int i = tid; i < nc; i += T) {
     uint32_t c = scol[i];
     if (i == 0 || scol[i - 1] != c) cstart[c] = (uint32_t)i;
     if (i == nc - 1) misc[M_NCOL] = c + 1;
   }
-  __syncthreads();
+  team_sync(tm);
   const int ncol = nc > 0 ? (int)misc[M_NCOL] : 0;
   if (tid == 0) cstart[ncol] = (uint32_t)nc;
-  __syncthreads();
+  team_sync(tm);
   TRACE(9);
 
   // ---- a7/a10: previous impulses, constraint setup (colour-major) ------
-  const int nprev = P.prev_count ? (P.prev_count[s] < CM ? P.prev_count[s] : CM) : 0;
+  const int nprev = P.prev_count ? (P.prev_count[s] < CMs ? P.prev_count[s] : CMs) : 0;
   for (int i = tid; i < nprev; i += T) S.u[L.prevk + i] = P.prev_key[(long)s * CM + i];
   if (P.warm == WARM_LEARNED)
     for (int i = tid; i < (nc + 31) / 32; i += T) S.u[L.fresh + i] = 0u;
-  __syncthreads();
+  team_sync(tm);
   const float gmag = sqrtf(P.gx * P.gx + P.gy * P.gy + P.gz * P.gz);
   // Wave-uniform trip count: the network's matrix-core calls need all 64
   // lanes of a wave; lanes past the end redo the last contact, store nothing.
@@ -1058,7 +1091,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       if (P.warm == WARM_LEARNED && hit < 0) atomicOr(S.u + L.fresh + (i >> 5), 1u << (i & 31));
     }
   }
-  __syncthreads();
+  team_sync(tm);
   TRACE(10);
 
   // ---- a8/a11: warm start and sweeps ------------------------------------
@@ -1068,25 +1101,25 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
   // objective it is dropped (the new contacts start from zero, the classic
   // warm start) and the step is flagged.
   if (P.warm == WARM_LEARNED) {
-    apply_all(L, S, rec, ncol, cstart, 0);
-    __syncthreads();
+    apply_all(L, S, rec, ncol, cstart, tm, 0);
+    team_sync(tm);
     for (int i = tid; i < nb; i += T) {
       st4(S.f + L.vsave, 2 * i, ld4(S.f + L.dyn, 4 * i));
       st4(S.f + L.vsave, 2 * i + 1, ld4(S.f + L.dyn, 4 * i + 1));
     }
-    __syncthreads();
-    apply_all(L, S, rec, ncol, cstart, 1);
-    __syncthreads();
+    team_sync(tm);
+    apply_all(L, S, rec, ncol, cstart, tm, 1);
+    team_sync(tm);
     float* fval = S.f + L.fval;
     for (int i = tid; i < nc; i += T) fval[i] = start_objective(L, S, rec, i);
-    __syncthreads();
+    team_sync(tm);
     // fixed-shape tree sum: same result for any block size
     int width = 1;
     while (width < nc) width <<= 1;
     for (int half = width >> 1; half > 0; half >>= 1) {
       for (int i = tid; i < half; i += T)
         if (i + half < nc) fval[i] += fval[i + half];
-      __syncthreads();
+      team_sync(tm);
     }
     if (nc > 0 && fval[0] > 0.f) {  // uniform across the workgroup
       if (tid == 0) misc[M_FLAGS] |= FLAG_FELLBACK;
@@ -1100,22 +1133,22 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
         st4(S.f + L.lam, i, make_float4(0.f, 0.f, 0.f, phi));
       }
     }
-    __syncthreads();
+    team_sync(tm);
   } else if (P.warm == WARM_PREV) {
-    apply_all(L, S, rec, ncol, cstart);
+    apply_all(L, S, rec, ncol, cstart, tm);
   }
   TRACE(11);
   int sweeps = 0;
   float res = 0.f;
   const uint64_t clk0 = P.trace ? clock64() : 0;
   if (P.solver == SOLVER_JACOBI)
-    solve_jacobi(L, S, rec, nb, nc, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res);
+    solve_jacobi(L, S, rec, nb, nc, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res, tm);
   else
-    solve_pgs(L, S, rec, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res);
-  __syncthreads();
+    solve_pgs(L, S, rec, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res, tm);
+  team_sync(tm);
   // a step counts as solved only once its residual reached the tolerance
   if (P.tol > 0.f && res > P.tol && tid == 0) misc[M_FLAGS] |= FLAG_NOT_CONVERGED;
-  __syncthreads();
+  team_sync(tm);
   TRACE(12);
   if (P.trace && tid == 0) P.trace[(long)s * kTraceSlots + 15] = clock64() - clk0;  // shader cycles in the solve
 
@@ -1147,7 +1180,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       if (!fin) atomicOr(&misc[M_FLAGS], (uint32_t)FLAG_NONFINITE);
     }
   }
-  __syncthreads();  // every read of the arm links' LDS records is done
+  team_sync(tm);  // every read of the arm links' LDS records is done
   if (P.arm && tid == 0) {
     float th[7];
     for (int k = 0; k < 7; k++) {
@@ -1198,14 +1231,14 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
       P.x_colour[o] = (int32_t)colour[q];
     }
   }
-  __syncthreads();
+  team_sync(tm);
   // fixed-shape tree sum over the contact slots: same result for any block size
   int width = 1;
   while (width < nc) width <<= 1;
   for (int half = width >> 1; half > 0; half >>= 1) {
     for (int i = tid; i < half; i += T)
       if (i + half < nc) force[i] += force[i + half];
-    __syncthreads();
+    team_sync(tm);
   }
   if (tid == 0) {
     P.cur_count[s] = nc;
@@ -1218,6 +1251,56 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
     P.st_arm_force[s] = nc > 0 ? force[0] : 0.f;
   }
   TRACE(14);
+}
+
+__global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
+  extern __shared__ float4 smem_f4[];
+  Smem S{reinterpret_cast<float*>(smem_f4), reinterpret_cast<uint32_t*>(smem_f4)};
+  const Team<false> tm{(int)threadIdx.x, (int)blockDim.x};
+  const int s = P.scene_list ? P.scene_list[blockIdx.x] : (int)blockIdx.x;
+  scene_step(P, L, S, s, tm);
+}
+
+// Persistent launch over scenes of uneven size: every workgroup first takes
+// scenes from the `team` queue and steps each with all its threads and all
+// its LDS, then each of its waves takes scenes from the `wave` queue and
+// steps each alone in its quarter of the LDS.  Queues are in descending
+// body count, so the largest scenes start first; a workgroup leaves once
+// both queues are drained.
+__global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams Q) {
+  extern __shared__ float4 smem_f4[];
+  __shared__ int next_scene;
+  float* lds = reinterpret_cast<float*>(smem_f4);
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) next_scene = (int)atomicAdd(&Q.head[0], 1u);
+    __syncthreads();
+    const int k = next_scene;
+    __syncthreads();
+    if (k >= Q.n_team) break;
+    const int s = Q.team[k];
+    const int nb = P.body_offset[s + 1] - P.body_offset[s];
+    const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), (int)blockDim.x >> 6, P.solver,
+                                   P.warm);
+    scene_step(P, L, Smem{lds, reinterpret_cast<uint32_t*>(lds)}, s, Team<false>{tid, (int)blockDim.x});
+    __syncthreads();
+  }
+  const int w = tid >> 6, lane = tid & 63;
+  float* mine = lds + w * (Q.lds_words / ((int)blockDim.x >> 6));
+  for (;;) {
+    int k = 0;
+    if (lane == 0) k = (int)atomicAdd(&Q.head[1], 1u);
+    k = __shfl(k, 0);
+    if (k >= Q.n_wave) break;
+    const int s = Q.wave[k];
+    const int nb = P.body_offset[s + 1] - P.body_offset[s];
+    const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), 1, P.solver, P.warm);
+    scene_step(P, L, Smem{mine, reinterpret_cast<uint32_t*>(mine)}, s, Team<true>{lane, 64});
+  }
+}
+
+__global__ void queue_reset_kernel(uint32_t* head) {
+  if (threadIdx.x < 2) head[threadIdx.x] = 0u;
 }
 
 // Arm link poses from the joint angles, one thread per scene (set-up and resets).
@@ -1266,7 +1349,18 @@ extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L
 }
 
 extern "C" int rbs_set_step_lds_limit(int bytes) {
-  return (int)hipFuncSetAttribute((const void*)rbs::step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  int e = (int)hipFuncSetAttribute((const void*)rbs::step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e) return e;
+  return (int)hipFuncSetAttribute((const void*)rbs::step_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  bytes);
+}
+
+// Queue heads reset, then the persistent step; grid = workgroups resident at once.
+extern "C" int rbs_launch_persistent(const rbs::StepParams* P, const rbs::QueueParams* Q, int grid,
+                                     hipStream_t stream) {
+  hipLaunchKernelGGL(rbs::queue_reset_kernel, dim3(1), dim3(64), 0, stream, Q->head);
+  hipLaunchKernelGGL(rbs::step_persistent, dim3(grid), dim3(256), (size_t)Q->lds_words * 4u, stream, *P, *Q);
+  return (int)hipGetLastError();
 }
 
 extern "C" int rbs_launch_arm_pose(const rbs::StepParams* P, const uint8_t* mask, hipStream_t stream) {

@@ -28,7 +28,7 @@ class Sim:
     """A batch of scenes resident in one device workspace."""
 
     def __init__(self, batch: scenes.Batch, max_pairs: int | None = None, max_contacts: int | None = None,
-                 solver: int = L.PGS, warm: int = L.COLD, tol: float = 0.0, threads: int = 128,
+                 solver: int = L.PGS, warm: int = L.COLD, tol: float = 0.0, threads: int = 64,
                  device: str | torch.device = "cuda", **consts):
         lib = L.load()
         c = dict(DEFAULT_CONSTS)
@@ -184,6 +184,21 @@ class Sim:
                 raise ValueError("weights must be bfloat16")
         self._mlp = ts  # keep alive
         L.check(L.load().sim_set_mlp(self.h, *[C.c_void_p(t.data_ptr()) for t in ts]), "sim_set_mlp")
+
+    def set_persistent(self, on: bool = True, wave_max_bodies: int = -1):
+        """Persistent launch over two size-ordered scene queues, replayed from a HIP graph."""
+        L.check(L.load().sim_set_persistent(self.h, int(bool(on)), int(wave_max_bodies)), "sim_set_persistent")
+
+    def autotune(self, steps: int = 5, dt: float = 1.0 / 120.0, iters: int = 10) -> int:
+        """Times the persistent launch's queue split and keeps the fastest; state is unchanged."""
+        lib = L.load()
+        need = int(lib.sim_autotune_scratch_bytes(self.h))
+        scratch = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        ptr = (scratch.data_ptr() + 255) // 256 * 256
+        out = C.c_int(0)
+        L.check(lib.sim_autotune(self.h, C.c_void_p(ptr), need, int(steps), float(dt), int(iters), C.byref(out)),
+                "sim_autotune")
+        return out.value
 
     def reset(self, mask: torch.Tensor, pose: torch.Tensor, vel: torch.Tensor, theta: torch.Tensor | None = None):
         """Masked reset from pool arrays laid out like the state ([7, N], [6, N], [S, 7])."""
