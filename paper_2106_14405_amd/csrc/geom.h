@@ -85,6 +85,24 @@ struct PC {
   int f;
 };
 
+// Up to eight polygon vertices in registers: indexed access is an unrolled
+// select over the slots, so the array never goes to scratch memory.
+struct Poly8 {
+  V3 v[8];
+  __device__ __forceinline__ V3 get(int k) const {
+    V3 r = v[0];
+#pragma unroll
+    for (int j = 1; j < 8; j++)
+      if (j == k) r = v[j];
+    return r;
+  }
+  __device__ __forceinline__ void set(int k, V3 x) {
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+      if (j == k) v[j] = x;
+  }
+};
+
 // Up to four contacts held in registers (fixed slots, no indexed array).
 struct Out4 {
   PC c0, c1, c2, c3;
@@ -452,80 +470,97 @@ __device__ inline void box_box(const Geom& A, const Geom& B, float margin, Out4&
   int j1 = j == 2 ? 0 : j + 1, j2 = j == 0 ? 2 : j - 1;
   V3 fc = inc.x + ic[j] * (si * hi[j]);
   V3 e1 = ic[j1] * hi[j1], e2 = ic[j2] * hi[j2];
-  V3 poly[8], tmp[8];
+  // polygons in fixed register slots: every access is an unrolled select
+  Poly8 poly, tmp;
   int np = 4;
-  poly[0] = (fc + e1) + e2;
-  poly[1] = (fc - e1) + e2;
-  poly[2] = (fc - e1) - e2;
-  poly[3] = (fc + e1) - e2;
+  poly.v[0] = (fc + e1) + e2;
+  poly.v[1] = (fc - e1) + e2;
+  poly.v[2] = (fc - e1) - e2;
+  poly.v[3] = (fc + e1) - e2;
   const int r1 = ax == 2 ? 0 : ax + 1, r2 = ax == 0 ? 2 : ax - 1;
-  for (int pl = 0; pl < 4 && np > 0; pl++) {
+#pragma unroll
+  for (int pl = 0; pl < 4; pl++) {
+    if (np == 0) break;
     int pa = pl < 2 ? r1 : r2;
     V3 pn = (pl & 1) ? -rc[pa] : rc[pa];
     float off = hr[pa];
     int no = 0;
-    V3 prev = poly[np - 1];
+    V3 prev = poly.get(np - 1);
     float dp = dot(prev - ref.x, pn) - off;
-    for (int k = 0; k < np; k++) {
-      V3 cur = poly[k];
-      float dc = dot(cur - ref.x, pn) - off;
-      int cs = dc < -kClipOn ? -1 : (dc > kClipOn ? 1 : 0);
-      int ps = dp < -kClipOn ? -1 : (dp > kClipOn ? 1 : 0);
-      if (ps * cs < 0 && no < 8) tmp[no++] = prev + (cur - prev) * (dp / (dp - dc));
-      if (cs <= 0 && no < 8) tmp[no++] = cur;
-      prev = cur;
-      dp = dc;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      if (k < np) {
+        V3 cur = poly.v[k];
+        float dc = dot(cur - ref.x, pn) - off;
+        int cs = dc < -kClipOn ? -1 : (dc > kClipOn ? 1 : 0);
+        int ps = dp < -kClipOn ? -1 : (dp > kClipOn ? 1 : 0);
+        if (ps * cs < 0 && no < 8) tmp.set(no++, prev + (cur - prev) * (dp / (dp - dc)));
+        if (cs <= 0 && no < 8) tmp.set(no++, cur);
+        prev = cur;
+        dp = dc;
+      }
     }
     np = no;
-    for (int k = 0; k < np; k++) poly[k] = tmp[k];
+    poly = tmp;
   }
   float ph[8];
   int nk = 0;
   unsigned keepm = 0u;
-  for (int k = 0; k < np; k++) {
-    ph[k] = dot(poly[k] - cref, nout);
-    if (ph[k] <= margin) { keepm |= 1u << k; nk++; }
+#pragma unroll
+  for (int k = 0; k < 8; k++) {
+    ph[k] = 0.f;
+    if (k < np) {
+      ph[k] = dot(poly.v[k] - cref, nout);
+      if (ph[k] <= margin) { keepm |= 1u << k; nk++; }
+    }
   }
   unsigned sel = keepm;
   if (nk > 4) {
     // first kept point; farthest from it; largest triangle; largest quad
     int i1 = __builtin_ctz(keepm);
     unsigned used = 1u << i1;
+    const V3 p1 = poly.get(i1);
     int i2 = -1;
     float bd = -1.f;
-    for (int k = 0; k < np; k++) {
-      if (!((keepm >> k) & 1u) || ((used >> k) & 1u)) continue;
-      float dd = sqrtf(len2(poly[k] - poly[i1]));
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      if (k >= np || !((keepm >> k) & 1u) || ((used >> k) & 1u)) continue;
+      float dd = sqrtf(len2(poly.v[k] - p1));
       if (dd > bd) { bd = dd; i2 = k; }
     }
     used |= 1u << i2;
-    V3 e12 = poly[i2] - poly[i1];
+    const V3 p2 = poly.get(i2);
+    V3 e12 = p2 - p1;
     int i3 = -1;
     float ba = -1.f;
-    for (int k = 0; k < np; k++) {
-      if (!((keepm >> k) & 1u) || ((used >> k) & 1u)) continue;
-      float ar = sqrtf(len2(cross(e12, poly[k] - poly[i1])));
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      if (k >= np || !((keepm >> k) & 1u) || ((used >> k) & 1u)) continue;
+      float ar = sqrtf(len2(cross(e12, poly.v[k] - p1)));
       if (ar > ba) { ba = ar; i3 = k; }
     }
     used |= 1u << i3;
-    V3 e23 = poly[i3] - poly[i2], e31 = poly[i1] - poly[i3];
+    const V3 p3 = poly.get(i3);
+    V3 e23 = p3 - p2, e31 = p1 - p3;
     int i4 = -1;
     float bq = -1.f;
-    for (int k = 0; k < np; k++) {
-      if (!((keepm >> k) & 1u) || ((used >> k) & 1u)) continue;
-      float sc = sqrtf(len2(cross(e12, poly[k] - poly[i1]))) + sqrtf(len2(cross(e23, poly[k] - poly[i2]))) +
-                 sqrtf(len2(cross(e31, poly[k] - poly[i3])));
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      if (k >= np || !((keepm >> k) & 1u) || ((used >> k) & 1u)) continue;
+      float sc = sqrtf(len2(cross(e12, poly.v[k] - p1))) + sqrtf(len2(cross(e23, poly.v[k] - p2))) +
+                 sqrtf(len2(cross(e31, poly.v[k] - p3)));
       if (sc > bq) { bq = sc; i4 = k; }
     }
     used |= 1u << i4;
     sel = used;
   }
-  for (int k = 0; k < np; k++) {
-    if (!((sel >> k) & 1u)) continue;
+#pragma unroll
+  for (int k = 0; k < 8; k++) {
+    if (k >= np || !((sel >> k) & 1u)) continue;
     PC c;
     c.n = N;
     c.phi = ph[k];
-    c.p = poly[k] - nout * (0.5f * ph[k]);
+    c.p = poly.v[k] - nout * (0.5f * ph[k]);
     c.f = (refA ? 0 : 1) | (refface << 1) | (k << 4);
     out.push(c);
   }

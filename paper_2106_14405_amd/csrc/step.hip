@@ -625,7 +625,9 @@ __device__ void arm_fk(const StepParams& P, const LdsLayout& L, Smem S, int b0, 
 
 // One step of scene s by team tm, its working set in the LDS at S laid
 // out by L.
-template <class TM>
+// kLearned: the learned warm start (P.warm == WARM_LEARNED) is compiled in;
+// the other modes use an instantiation without the network's registers.
+template <bool kLearned, class TM>
 __device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L, Smem S, const int s,
                                            const TM& tm) {
   const int tid = tm.tid, T = tm.T;
@@ -952,7 +954,7 @@ __device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L
   // ---- a7/a10: previous impulses, constraint setup (colour-major) ------
   const int nprev = P.prev_count ? (P.prev_count[s] < CMs ? P.prev_count[s] : CMs) : 0;
   for (int i = tid; i < nprev; i += T) S.u[L.prevk + i] = P.prev_key[(long)s * CM + i];
-  if (P.warm == WARM_LEARNED)
+  if (kLearned)
     for (int i = tid; i < (nc + 31) / 32; i += T) S.u[L.fresh + i] = 0u;
   team_sync(tm);
   const float gmag = sqrtf(P.gx * P.gx + P.gy * P.gy + P.gz * P.gz);
@@ -1034,7 +1036,7 @@ __device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L
       lp2 = dot(F, t2);
     }
     float l0 = 0.f, l1 = 0.f, l2 = 0.f;
-    const bool need_feat = P.warm == WARM_LEARNED || (P.export_on && P.x_feat);
+    const bool need_feat = kLearned || (P.export_on && P.x_feat);
     if (need_feat) {
       float feat[16];
       feat[0] = u0;
@@ -1062,7 +1064,7 @@ __device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L
       }
       if (live && P.export_on && P.x_feat)
         for (int k = 0; k < 16; k++) P.x_feat[k * P.scene_cm + (long)s * CM + q] = feat[k];
-      if (P.warm == WARM_LEARNED) {
+      if constexpr (kLearned) {
         float y[3];
         mlp_wave(P.mlp, feat, live, y);
         // a persisting contact keeps its previous impulse; the network
@@ -1088,7 +1090,7 @@ __device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L
     if (live) {
       store_rec(rec, i, rw, bias, mu, key, jsc);
       st4(S.f + L.lam, i, make_float4(l0, l1, l2, phi));
-      if (P.warm == WARM_LEARNED && hit < 0) atomicOr(S.u + L.fresh + (i >> 5), 1u << (i & 31));
+      if (kLearned && hit < 0) atomicOr(S.u + L.fresh + (i >> 5), 1u << (i & 31));
     }
   }
   team_sync(tm);
@@ -1100,7 +1102,7 @@ __device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L
   // judges the network's part before any sweep: if it raises the solver's
   // objective it is dropped (the new contacts start from zero, the classic
   // warm start) and the step is flagged.
-  if (P.warm == WARM_LEARNED) {
+  if (kLearned) {
     apply_all(L, S, rec, ncol, cstart, tm, 0);
     team_sync(tm);
     for (int i = tid; i < nb; i += T) {
@@ -1253,12 +1255,13 @@ __device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L
   TRACE(14);
 }
 
+template <bool kLearned>
 __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
   extern __shared__ float4 smem_f4[];
   Smem S{reinterpret_cast<float*>(smem_f4), reinterpret_cast<uint32_t*>(smem_f4)};
   const Team<false> tm{(int)threadIdx.x, (int)blockDim.x};
   const int s = P.scene_list ? P.scene_list[blockIdx.x] : (int)blockIdx.x;
-  scene_step(P, L, S, s, tm);
+  scene_step<kLearned>(P, L, S, s, tm);
 }
 
 // Persistent launch over scenes of uneven size: every workgroup first takes
@@ -1267,6 +1270,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
 // steps each alone in its quarter of the LDS.  Queues are in descending
 // body count, so the largest scenes start first; a workgroup leaves once
 // both queues are drained.
+template <bool kLearned>
 __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams Q) {
   extern __shared__ float4 smem_f4[];
   __shared__ int next_scene;
@@ -1282,7 +1286,7 @@ __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams
     const int nb = P.body_offset[s + 1] - P.body_offset[s];
     const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), (int)blockDim.x >> 6, P.solver,
                                    P.warm);
-    scene_step(P, L, Smem{lds, reinterpret_cast<uint32_t*>(lds)}, s, Team<false>{tid, (int)blockDim.x});
+    scene_step<kLearned>(P, L, Smem{lds, reinterpret_cast<uint32_t*>(lds)}, s, Team<false>{tid, (int)blockDim.x});
     __syncthreads();
   }
   const int w = tid >> 6, lane = tid & 63;
@@ -1295,7 +1299,7 @@ __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams
     const int s = Q.wave[k];
     const int nb = P.body_offset[s + 1] - P.body_offset[s];
     const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), 1, P.solver, P.warm);
-    scene_step(P, L, Smem{mine, reinterpret_cast<uint32_t*>(mine)}, s, Team<true>{lane, 64});
+    scene_step<kLearned>(P, L, Smem{mine, reinterpret_cast<uint32_t*>(mine)}, s, Team<true>{lane, 64});
   }
 }
 
@@ -1344,22 +1348,37 @@ __global__ void reset_kernel(const int32_t* off, const uint8_t* mask, float* pos
 extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L, int threads, int grid,
                                hipStream_t stream) {
   size_t bytes = (size_t)L->total * 4u;
-  hipLaunchKernelGGL(rbs::step_kernel, dim3(grid), dim3(threads), bytes, stream, *P, *L);
+  if (P->warm == rbs::WARM_LEARNED)
+    hipLaunchKernelGGL(rbs::step_kernel<true>, dim3(grid), dim3(threads), bytes, stream, *P, *L);
+  else
+    hipLaunchKernelGGL(rbs::step_kernel<false>, dim3(grid), dim3(threads), bytes, stream, *P, *L);
   return (int)hipGetLastError();
 }
 
+// Dynamic LDS limits: the whole budget for the per-scene kernels; the
+// persistent kernel keeps 256 bytes for its static words.
 extern "C" int rbs_set_step_lds_limit(int bytes) {
-  int e = (int)hipFuncSetAttribute((const void*)rbs::step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e) return e;
-  return (int)hipFuncSetAttribute((const void*)rbs::step_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  bytes);
+  const void* k[4] = {(const void*)rbs::step_kernel<false>, (const void*)rbs::step_kernel<true>,
+                      (const void*)rbs::step_persistent<false>, (const void*)rbs::step_persistent<true>};
+  for (int i = 0; i < 4; i++) {
+    int e = (int)hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, i < 2 ? bytes : bytes - 256);
+    if (e) {
+      (void)hipGetLastError();  // leave no sticky error behind
+      return e;
+    }
+  }
+  return 0;
 }
 
 // Queue heads reset, then the persistent step; grid = workgroups resident at once.
 extern "C" int rbs_launch_persistent(const rbs::StepParams* P, const rbs::QueueParams* Q, int grid,
                                      hipStream_t stream) {
   hipLaunchKernelGGL(rbs::queue_reset_kernel, dim3(1), dim3(64), 0, stream, Q->head);
-  hipLaunchKernelGGL(rbs::step_persistent, dim3(grid), dim3(256), (size_t)Q->lds_words * 4u, stream, *P, *Q);
+  const size_t bytes = (size_t)Q->lds_words * 4u;
+  if (P->warm == rbs::WARM_LEARNED)
+    hipLaunchKernelGGL(rbs::step_persistent<true>, dim3(grid), dim3(256), bytes, stream, *P, *Q);
+  else
+    hipLaunchKernelGGL(rbs::step_persistent<false>, dim3(grid), dim3(256), bytes, stream, *P, *Q);
   return (int)hipGetLastError();
 }
 
