@@ -263,6 +263,8 @@ int validate(const sim_batch_desc* d, Caps* caps) {
   }
   if (d->max_pairs < 1 || d->max_contacts < 1) return fail(SIM_EINVAL, "capacities must be >= 1");
   if (d->max_pairs > (1 << 20) || d->max_contacts > (1 << 20)) return fail(SIM_EINVAL, "capacity too large");
+  // the narrowphase stages 4 contacts per pair in a contact record slot set
+  if (8L * d->max_pairs > 13L * d->max_contacts) return fail(SIM_EINVAL, "max_pairs exceeds 13/8 max_contacts");
   int T = d->threads ? d->threads : 64;
   if (T != 64 && T != 128 && T != 192 && T != 256) return fail(SIM_EINVAL, "threads must be 64, 128, 192 or 256");
   if (d->solver != SIM_PGS && d->solver != SIM_JACOBI) return fail(SIM_EINVAL, "bad solver");

@@ -119,7 +119,7 @@ struct QueueParams {
 struct LdsLayout {
   int geo, dyn, ckey, lam, perm, fresh, misc, hist, hbase;
   int scr;
-  int pk, pk2, lo, hi, skey, sval, skey2, sval2;
+  int pk, pk2, lo, hi, skey, sval, skey2, sval2, nperm, ncnt;
   int colour, deg, lstart, list, rank, prevk, cv0, ck1;
   int vsave, fval, snap, dl, force;
   int total;  // words
@@ -152,6 +152,11 @@ inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int wave
   L.skey2 = tb(NB);
   L.sval2 = tb(NB);
   int bend = b;
+  // narrowphase (the AABBs and body sort are dead by then): class-sorted pair
+  // order and contacts per pair (bytes), over the AABB region
+  L.nperm = L.lo;
+  L.ncnt = L.lo + ((PM + 3) & ~3);
+  if (L.ncnt + (PM + 3) / 4 > bend) bend = L.ncnt + (((PM + 3) / 4 + 3) & ~3);
   int p = L.scr;
   auto tp = [&](int words) { int r = p; p += (words + 3) & ~3; return r; };
   L.colour = tp(CM);

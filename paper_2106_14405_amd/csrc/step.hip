@@ -773,28 +773,101 @@ __device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L
   TRACE(5);
 
   // ---- a6: narrowphase, compaction in canonical order --------------------
+  // Pairs run grouped by shape class, so that a wave executes one contact
+  // routine at a time; each pair's contacts (at most 4) are staged in the
+  // record buffer (free until setup), then compacted in canonical order.
+  // (8 PMs <= 13 CMs: sim_create checks the batch capacities.)
   {
     const int lane = tid & 63, w = tid >> 6, W = T >> 6;
-    uint32_t base = 0;
+    uint32_t* nperm = S.u + L.nperm;
+    uint8_t* ncnt = reinterpret_cast<uint8_t*>(S.u + L.ncnt);
+    uint32_t* cbase = S.u + L.hbase;  // class bases (hbase and hist are free after the pair sort)
+    uint32_t* whist = S.u + L.hist;   // [W][16] per-wave class counts of a tile
+    float4* stage = rec;              // [PMs][4][2] float4
+    auto pair_class = [&](int p) -> uint32_t {
+      const uint32_t k = pairs[p];
+      const int a = (int)(k >> 11), bb = (int)(k & 2047u);
+      const uint32_t sa = body_meta(L, S, a) & 255u;
+      if (bb == 2047) return 9u + sa;
+      const uint32_t sb = body_meta(L, S, bb) & 255u;
+      return sa < sb ? 3u * sa + sb : 3u * sb + sa;
+    };
+    for (int i = tid; i < 16 + 16 * W; i += T) {
+      if (i < 16) cbase[i] = 0u;
+      else whist[i - 16] = 0u;
+    }
+    team_sync(tm);
+    for (int p = tid; p < np; p += T) atomicAdd(&cbase[pair_class(p)], 1u);
+    team_sync(tm);
+    if (tid == 0) {
+      uint32_t run = 0;
+      for (int c = 0; c < 16; c++) {
+        const uint32_t v = cbase[c];
+        cbase[c] = run;
+        run += v;
+      }
+    }
+    team_sync(tm);
+    // stable placement by class: rank among the wave's lanes of the same
+    // class (four ballots), then the counts of earlier waves and tiles
     for (int t0 = 0; t0 < np; t0 += T) {
-      int p = t0 + tid;
+      const int p = t0 + tid;
+      const bool valid = p < np;
+      const uint32_t c = valid ? pair_class(p) : 0u;
+      u64 peers = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < 4; bit++) {
+        const u64 bb = __ballot(valid && ((c >> bit) & 1u));
+        peers &= ((c >> bit) & 1u) ? bb : ~bb;
+      }
+      const unsigned rank = lanes_below(peers);
+      if (valid && rank == 0) whist[w * 16 + c] = (uint32_t)__popcll(peers);
+      team_sync(tm);
+      if (valid) {
+        uint32_t off = cbase[c] + rank;
+        for (int ww = 0; ww < w; ww++) off += whist[ww * 16 + c];
+        nperm[off] = (uint32_t)p;
+      }
+      team_sync(tm);
+      for (int cc = tid; cc < 16; cc += T) {
+        uint32_t sum = 0;
+        for (int ww = 0; ww < W; ww++) {
+          sum += whist[ww * 16 + cc];
+          whist[ww * 16 + cc] = 0u;
+        }
+        cbase[cc] += sum;
+      }
+      team_sync(tm);
+    }
+    // contacts of every pair, class by class, staged at the pair's slots
+    for (int j = tid; j < np; j += T) {
+      const int p = (int)nperm[j];
+      const uint32_t k = pairs[p];
+      const int a = (int)(k >> 11), bb = (int)(k & 2047u);
       Out4 o;
       o.n = 0;
-      int a = 0, bb = 0;
-      if (p < np) {
-        uint32_t k = pairs[p];
-        a = (int)(k >> 11);
-        bb = (int)(k & 2047u);
-        Geom A = load_geom(L, S, a);
-        if (bb == 2047) {
-          ground_contacts(A, P.margin, o);
-        } else {
-          Geom B = load_geom(L, S, bb);
-          collide(A, B, P.margin, o);
-        }
+      Geom A = load_geom(L, S, a);
+      if (bb == 2047) {
+        ground_contacts(A, P.margin, o);
+      } else {
+        Geom B = load_geom(L, S, bb);
+        collide(A, B, P.margin, o);
       }
-      const int cnt = o.n;
-      // prefix of the counts (0..4) with three ballots per wave
+      ncnt[p] = (uint8_t)o.n;
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) {
+        if (kk >= o.n) break;
+        const PC c = o.get(kk);
+        stage[8 * p + 2 * kk] = f4(c.n, c.phi);
+        stage[8 * p + 2 * kk + 1] = f4(c.p, __int_as_float(c.f));
+      }
+    }
+    team_sync(tm);
+    // compaction in canonical pair order: prefix of the counts by ballots
+    uint32_t base = 0;
+    for (int t0 = 0; t0 < np; t0 += T) {
+      const int p = t0 + tid;
+      const int cnt = p < np ? (int)ncnt[p] : 0;
       u64 b0m = __ballot(cnt & 1), b1m = __ballot((cnt >> 1) & 1), b2m = __ballot((cnt >> 2) & 1);
       uint32_t pre = lanes_below(b0m) + 2u * lanes_below(b1m) + 4u * lanes_below(b2m);
       uint32_t wtot = (uint32_t)(__popcll(b0m) + 2 * __popcll(b1m) + 4 * __popcll(b2m));
@@ -807,16 +880,18 @@ __device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L
         if (ww < w) off += t;
         tile += t;
       }
-      const uint32_t bkey = bb == 2047 ? kGroundKey : (uint32_t)bb;
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        if (k >= cnt) break;
-        uint32_t q = off + (uint32_t)k;
-        if ((int)q < CMs) {
-          PC c = o.get(k);
-          S.u[L.ckey + q] = ((uint32_t)a << 20) | (bkey << 8) | (uint32_t)c.f;
-          raw[2 * q] = f4(c.n, c.phi);
-          raw[2 * q + 1] = f4(c.p, 0.f);
+      if (cnt > 0) {
+        const uint32_t k = pairs[p];
+        const uint32_t a = k >> 11, bb = k & 2047u;
+        const uint32_t bkey = bb == 2047u ? kGroundKey : bb;
+        for (int kk = 0; kk < cnt; kk++) {
+          const uint32_t q = off + (uint32_t)kk;
+          if ((int)q < CMs) {
+            const float4 s0 = stage[8 * p + 2 * kk], s1 = stage[8 * p + 2 * kk + 1];
+            S.u[L.ckey + q] = (a << 20) | (bkey << 8) | (uint32_t)__float_as_int(s1.w);
+            raw[2 * q] = s0;
+            raw[2 * q + 1] = make_float4(s1.x, s1.y, s1.z, 0.f);
+          }
         }
       }
       base += tile;
