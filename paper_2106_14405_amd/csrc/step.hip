@@ -470,24 +470,35 @@ __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int nco
   const int last = (int)cstart[ncol] - 1;  // >= 0: ncol > 0 implies contacts
   int i = (int)cstart[0] + tid;
   bool has = i < (int)cstart[1];
-  // loads are unconditional (index clamped to a valid record) so that the
-  // next batch's loads stay in flight while the current batch is solved
-  Rec cur = load_rec(rec, min(i, last));
+  float r = 0.f;
+  // One colour batch: load the next batch's records (unconditionally, the
+  // index clamped to a valid record, so that the loads stay in flight),
+  // solve this batch, synchronise.  Two record buffers alternate between
+  // batches so that no registers are copied between them.
+  auto batch = [&](int c, const Rec& cur, Rec& nxt) {
+    const int e = (int)cstart[c + 1];
+    // next batch: colour c + 1, or colour 0 of the next sweep
+    const int cn = c + 1 < ncol ? c + 1 : 0;
+    const int inext = (int)cstart[cn] + tid;
+    const bool hnext = inext < (int)cstart[cn + 1];
+    nxt = load_rec(rec, min(inext, last));
+    if (has) r = fmaxf(r, pgs_update(L, S, cur, i));
+    for (int i2 = i + T; i2 < e; i2 += T) r = fmaxf(r, pgs_update(L, S, load_rec(rec, i2), i2));
+    colour_sync(tm);
+    has = hnext;
+    i = inext;
+  };
+  Rec ra = load_rec(rec, min(i, last)), rb;
   for (int it = 0; it < iters; it++) {
-    float r = 0.f;
-    for (int c = 0; c < ncol; c++) {
-      const int e = (int)cstart[c + 1];
-      // next batch: colour c + 1, or colour 0 of the next sweep
-      const int cn = c + 1 < ncol ? c + 1 : 0;
-      const int inext = (int)cstart[cn] + tid;
-      const bool hnext = inext < (int)cstart[cn + 1];
-      Rec nxt = load_rec(rec, min(inext, last));
-      if (has) r = fmaxf(r, pgs_update(L, S, cur, i));
-      for (int i2 = i + T; i2 < e; i2 += T) r = fmaxf(r, pgs_update(L, S, load_rec(rec, i2), i2));
-      colour_sync(tm);
-      cur = nxt;
-      has = hnext;
-      i = inext;
+    r = 0.f;
+    int c = 0;
+    for (; c + 1 < ncol; c += 2) {
+      batch(c, ra, rb);
+      batch(c + 1, rb, ra);
+    }
+    if (c < ncol) {  // odd colour count: colour 0 of the next sweep is in rb
+      batch(c, ra, rb);
+      ra = rb;
     }
     sweeps++;
     if (tol > 0.f || it == iters - 1) {
