@@ -744,26 +744,66 @@ __device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L
   TRACE(3);
 
   // ---- a5: sweep and prune -> pairs (unordered), then canonical sort ----
+  // Sorted position p's candidates are the positions after it whose AABB
+  // starts at or before its end along x.  Their counts are found by binary
+  // search and scanned, and the candidates are dealt to the lanes in equal
+  // contiguous runs (a long body's run no longer holds up the team).
   uint32_t* pk = S.u + L.pk;
-  for (int p = tid; p < nb; p += T) {
-    int i = (int)order[p];
-    float4 loi = ld4(S.f + L.lo, i), hii = ld4(S.f + L.hi, i);
-    bool di = loi.w != 0.f;
-    for (int q = p + 1; q < nb; q++) {
-      int j = (int)order[q];
-      float4 loj = ld4(S.f + L.lo, j);
-      if (loj.x > hii.x) break;
-      if (!di && loj.w == 0.f) continue;
-      float4 hij = ld4(S.f + L.hi, j);
-      if (loj.y <= hii.y && loi.y <= hij.y && loj.z <= hii.z && loi.z <= hij.z) {
-        int a = i < j ? i : j, bb = i < j ? j : i;
-        uint32_t slot = atomicAdd(&misc[M_NPAIRS], 1u);
-        if ((int)slot < PMs) pk[slot] = ((uint32_t)a << 11) | (uint32_t)bb;
+  {
+    uint32_t* run = S.u + (sw ? L.skey : L.skey2);  // free sort buffer: [nb] run starts
+    for (int p = tid; p < nb; p += T) {
+      const float hx = ld4(S.f + L.hi, (int)order[p]).x;
+      int lo = p + 1, hi = nb;  // first position whose minimum x exceeds hx
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ld4(S.f + L.lo, (int)order[mid]).x > hx) hi = mid;
+        else lo = mid + 1;
+      }
+      run[p] = (uint32_t)(lo - p - 1);
+    }
+    team_sync(tm);
+    const uint32_t total = block_exclusive_scan(run, nb, misc, tm);
+    const uint32_t c0 = (uint32_t)(((uint64_t)total * tid) / T), c1 = (uint32_t)(((uint64_t)total * (tid + 1)) / T);
+    if (c0 < c1) {
+      // the last position whose run starts at or before c0
+      int lo = 0, hi = nb;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (run[mid] <= c0) lo = mid;
+        else hi = mid;
+      }
+      int p = lo;
+      uint32_t pend = p + 1 < nb ? run[p + 1] : total;
+      int q = p + 1 + (int)(c0 - run[p]);
+      int i = (int)order[p];
+      float4 loi = ld4(S.f + L.lo, i), hii = ld4(S.f + L.hi, i);
+      for (uint32_t c = c0; c < c1; c++) {
+        while (c >= pend) {  // next position with a non-empty run
+          p++;
+          pend = p + 1 < nb ? run[p + 1] : total;
+          q = p + 1;
+          i = (int)order[p];
+          loi = ld4(S.f + L.lo, i);
+          hii = ld4(S.f + L.hi, i);
+        }
+        const int j = (int)order[q++];
+        const float4 loj = ld4(S.f + L.lo, j);
+        if (loi.w == 0.f && loj.w == 0.f) continue;  // neither body is dynamic
+        const float4 hij = ld4(S.f + L.hi, j);
+        if (loj.y <= hii.y && loi.y <= hij.y && loj.z <= hii.z && loi.z <= hij.z) {
+          int a = i < j ? i : j, bb = i < j ? j : i;
+          uint32_t slot = atomicAdd(&misc[M_NPAIRS], 1u);
+          if ((int)slot < PMs) pk[slot] = ((uint32_t)a << 11) | (uint32_t)bb;
+        }
       }
     }
-    if (di && loi.z <= 0.f) {
-      uint32_t slot = atomicAdd(&misc[M_NPAIRS], 1u);
-      if ((int)slot < PMs) pk[slot] = ((uint32_t)i << 11) | 2047u;
+    // ground pairs of dynamic bodies reaching z <= 0
+    for (int i = tid; i < nb; i += T) {
+      const float4 loi = ld4(S.f + L.lo, i);
+      if (loi.w != 0.f && loi.z <= 0.f) {
+        uint32_t slot = atomicAdd(&misc[M_NPAIRS], 1u);
+        if ((int)slot < PMs) pk[slot] = ((uint32_t)i << 11) | 2047u;
+      }
     }
   }
   team_sync(tm);
