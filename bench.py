@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--warm", default="cold", choices=["cold", "prev"])
     ap.add_argument("--threads", type=int, default=64)
     ap.add_argument("--max-contacts", type=int, default=None)
+    ap.add_argument("--max-pairs", type=int, default=None)
     ap.add_argument("--learned-eval", type=int, default=1)
     ap.add_argument("--learned-scenes", type=int, default=2048)
     ap.add_argument("--learned-steps", type=int, default=240)
@@ -176,16 +177,19 @@ def main():
         batch_fn = lambda n: S.batch_clutter(n, seed0=10000)
         arm = True
         max_contacts = a.max_contacts or 512
+        max_pairs = a.max_pairs or max_contacts
     elif a.workload == "uneven":
         n_scenes = a.scenes or 4096
         batch_fn = lambda n: S.batch_uneven(n, seed0=20000, lo=16, hi=512)
         arm = False
         max_contacts = a.max_contacts or 2048
+        max_pairs = a.max_pairs or 2560   # 512-body piles reach 4.2 pairs per body
     else:
         n_scenes = a.scenes or 1024
         batch_fn = lambda n: S.batch_drop(n, seed0=0)
         arm = False
         max_contacts = a.max_contacts or 384
+        max_pairs = a.max_pairs or max_contacts
     batch = batch_fn(n_scenes)              # generated before the GPU is touched
     K, W = a.steps, a.warmup
     acts_np = (np.stack([S.arm_actions(1, n_scenes, t) for t in range(W + K)]) if arm else None)
@@ -197,7 +201,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     warm = L.PREV if a.warm == "prev" else L.COLD
-    sim = Sim(batch, max_contacts=max_contacts, max_pairs=max_contacts, warm=warm, tol=a.tol,
+    sim = Sim(batch, max_contacts=max_contacts, max_pairs=max_pairs, warm=warm, tol=a.tol,
               threads=a.threads, device=dev)
     acts = torch.as_tensor(acts_np, device=dev) if arm else None
     resets = None
@@ -268,7 +272,7 @@ def main():
             "dt": 1.0 / 120.0, "sweep_cap": a.iters, "tolerance_m_per_s": a.tol,
             "warm_start": a.warm, "solver": "pgs",
             "threads_per_scene": a.threads if a.workload != "uneven" else "autotuned: 64 (one wave) or 256",
-            "max_contacts_per_scene": max_contacts,
+            "max_contacts_per_scene": max_contacts, "max_pairs_per_scene": max_pairs,
             **({"launch": "persistent, HIP graph", "wave_max_bodies": tuned,
                 "resets": "each scene after U[100, 300] steps"} if a.workload == "uneven" else {}),
         },
