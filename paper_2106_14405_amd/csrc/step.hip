@@ -1014,39 +1014,52 @@ __device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L
   team_sync(tm);
   TRACE(7);
   // fixed point of c_q = mex{c_p : p < q, p shares a dynamic body with q};
-  // its unique solution is sequential first fit in canonical order
-  for (int round = 0; round < nc + 2; round++) {
-    if (tid == 0) misc[M_CHANGED] = 0u;
-    team_sync(tm);
-    bool changed = false;
-    for (int q = tid; q < nc; q += T) {
-      uint32_t key = ckeys[q];
-      int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
-      uint32_t rk = rank[q];
-      uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-      int la = is_dyn_meta(body_meta(L, S, a)) ? (int)(rk & 0xFFFFu) : 0;
-      int lb = (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) ? (int)(rk >> 16) : 0;
-      uint32_t sa = la ? lstart[a] : 0u, sb = lb ? lstart[b] : 0u;
-      for (int x = 0; x < la + lb; x++) {
-        uint32_t p = x < la ? list[sa + x] : list[sb + (x - la)];
-        uint32_t c = colour[p];
-        if (c < 32) m0 |= 1u << c;
-        else if (c < 64) m1 |= 1u << (c - 32);
-        else if (c < 96) m2 |= 1u << (c - 64);
-        else m3 |= 1u << (c - 96);
-      }
-      uint32_t c;
-      if (~m0) c = __builtin_ctz(~m0);
-      else if (~m1) c = 32 + __builtin_ctz(~m1);
-      else if (~m2) c = 64 + __builtin_ctz(~m2);
-      else if (~m3) c = 96 + __builtin_ctz(~m3);
-      else c = kMaxColours - 1;  // overflow: flagged below
-      if (c != colour[q]) { colour[q] = c; changed = true; }
+  // its unique solution is sequential first fit in canonical order.  The
+  // contacts are taken a team's width at a time in canonical order: earlier
+  // chunks are final, so each chunk iterates to its own fixed point, which
+  // takes as many rounds as its longest dependency chain.
+  for (int c0 = 0; c0 < nc; c0 += T) {
+    const int q = c0 + tid;
+    const bool valid = q < nc;
+    int a = 0, b = 0, la = 0, lb = 0;
+    uint32_t sa = 0u, sb = 0u;
+    if (valid) {
+      const uint32_t key = ckeys[q];
+      a = (int)(key >> 20);
+      b = (int)((key >> 8) & 0xFFFu);
+      const uint32_t rk = rank[q];
+      la = is_dyn_meta(body_meta(L, S, a)) ? (int)(rk & 0xFFFFu) : 0;
+      lb = (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) ? (int)(rk >> 16) : 0;
+      sa = la ? lstart[a] : 0u;
+      sb = lb ? lstart[b] : 0u;
     }
-    if (changed) misc[M_CHANGED] = 1u;
-    team_sync(tm);
-    if (misc[M_CHANGED] == 0u) break;
-    team_sync(tm);
+    for (int round = 0; round <= T + 1; round++) {
+      if (tid == 0) misc[M_CHANGED] = 0u;
+      team_sync(tm);
+      bool changed = false;
+      if (valid) {
+        uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+        for (int x = 0; x < la + lb; x++) {
+          uint32_t p = x < la ? list[sa + x] : list[sb + (x - la)];
+          uint32_t c = colour[p];
+          if (c < 32) m0 |= 1u << c;
+          else if (c < 64) m1 |= 1u << (c - 32);
+          else if (c < 96) m2 |= 1u << (c - 64);
+          else m3 |= 1u << (c - 96);
+        }
+        uint32_t c;
+        if (~m0) c = __builtin_ctz(~m0);
+        else if (~m1) c = 32 + __builtin_ctz(~m1);
+        else if (~m2) c = 64 + __builtin_ctz(~m2);
+        else if (~m3) c = 96 + __builtin_ctz(~m3);
+        else c = kMaxColours - 1;  // overflow: flagged below
+        if (c != colour[q]) { colour[q] = c; changed = true; }
+      }
+      if (changed) misc[M_CHANGED] = 1u;
+      team_sync(tm);
+      if (misc[M_CHANGED] == 0u) break;
+      team_sync(tm);
+    }
   }
   TRACE(8);
   for (int q = tid; q < nc; q += T)
