@@ -639,7 +639,7 @@ __device__ void arm_fk(const StepParams& P, const LdsLayout& L, Smem S, int b0, 
 // kLearned: the learned warm start (P.warm == WARM_LEARNED) is compiled in;
 // the other modes use an instantiation without the network's registers.
 template <bool kLearned, class TM>
-__device__ __forceinline__ void scene_step(const StepParams P, const LdsLayout L, Smem S, const int s,
+__device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout& L, Smem S, const int s,
                                            const TM& tm) {
   const int tid = tm.tid, T = tm.T;
   const int b0 = P.body_offset[s];
