@@ -287,6 +287,18 @@ int sim_set_trace(sim_handle *h, uint64_t *d_trace);
  * SIM_ECAPACITY if a scene fits no workgroup. */
 int sim_set_persistent(sim_handle *h, int on, int wave_max_bodies);
 
+/* ---- Checkpoint and resume ----------------------------------------------
+ * A state blob holds what later steps depend on: pose, velocity, joint
+ * angles and both contact caches (the warm-start impulses), with a header
+ * naming the batch layout.  sim_save_state copies the state into d_blob
+ * (device memory, 256-byte aligned, sim_state_bytes long); sim_load_state
+ * restores it into a handle created from the same batch layout (SIM_EINVAL
+ * otherwise).  Both synchronise the handle's stream for the header; the
+ * bulk copies are queued on it. */
+size_t sim_state_bytes(const sim_handle *h);
+int sim_save_state(sim_handle *h, void *d_blob);
+int sim_load_state(sim_handle *h, const void *d_blob);
+
 /* Device scratch (256-byte aligned) sim_autotune needs to save and restore
  * the simulation state: pose, velocity, joint angles and contact caches. */
 size_t sim_autotune_scratch_bytes(const sim_handle *h);

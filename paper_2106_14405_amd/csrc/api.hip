@@ -722,6 +722,40 @@ int sim_set_persistent(sim_handle* h, int on, int wave_max_bodies) {
 
 size_t sim_autotune_scratch_bytes(const sim_handle* h) { return h ? state_bytes(h) : 0; }
 
+size_t sim_state_bytes(const sim_handle* h) { return h ? state_bytes(h) + 256 : 0; }
+
+// Blob: 256-byte header (cache parity, scene and body counts) then the state
+// spans in workspace order.
+int sim_save_state(sim_handle* h, void* d_blob) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (!d_blob || ((uintptr_t)d_blob & 255u)) return fail(SIM_EINVAL, "blob must be 256-byte aligned device memory");
+  static thread_local int32_t hdr[4];
+  hdr[0] = h->parity;
+  hdr[1] = h->S;
+  hdr[2] = (int32_t)h->N;
+  hdr[3] = h->CM;
+  if (hipMemcpyAsync(d_blob, hdr, sizeof(hdr), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return fail(SIM_EDEVICE, "state header copy failed");
+  if (copy_state(h, static_cast<char*>(d_blob) + 256, true) != 0) return fail(SIM_EDEVICE, "state copy failed");
+  return SIM_OK;
+}
+
+int sim_load_state(sim_handle* h, const void* d_blob) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (!d_blob || ((uintptr_t)d_blob & 255u)) return fail(SIM_EINVAL, "blob must be 256-byte aligned device memory");
+  int32_t hdr[4];
+  if (hipMemcpyAsync(hdr, d_blob, sizeof(hdr), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return fail(SIM_EDEVICE, "state header copy failed");
+  if (hdr[1] != h->S || hdr[2] != (int32_t)h->N || hdr[3] != h->CM || (hdr[0] != 0 && hdr[0] != 1))
+    return fail(SIM_EINVAL, "blob was saved from a different batch layout");
+  if (copy_state(h, const_cast<char*>(static_cast<const char*>(d_blob)) + 256, false) != 0)
+    return fail(SIM_EDEVICE, "state copy failed");
+  h->parity = hdr[0];
+  return SIM_OK;
+}
+
 int sim_autotune(sim_handle* h, void* d_scratch, size_t scratch_bytes, int steps, float dt, int iters,
                  int* out_wave_max_bodies) {
   if (!h) return fail(SIM_EINVAL, "handle is NULL");

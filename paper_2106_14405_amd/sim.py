@@ -200,6 +200,19 @@ class Sim:
                 "sim_autotune")
         return out.value
 
+    def save_state(self) -> torch.Tensor:
+        """Device blob of the state (pose, velocity, joint angles, contact caches)."""
+        lib = L.load()
+        blob = torch.empty(int(lib.sim_state_bytes(self.h)), dtype=torch.uint8, device=self.device)
+        L.check(lib.sim_save_state(self.h, C.c_void_p(blob.data_ptr())), "sim_save_state")
+        return blob
+
+    def load_state(self, blob: torch.Tensor):
+        """Restore a blob from save_state of a simulation with the same batch layout."""
+        if blob.device != self.device or blob.dtype != torch.uint8 or not blob.is_contiguous():
+            raise ValueError("blob must be a contiguous uint8 tensor on the simulation device")
+        L.check(L.load().sim_load_state(self.h, C.c_void_p(blob.data_ptr())), "sim_load_state")
+
     def reset(self, mask: torch.Tensor, pose: torch.Tensor, vel: torch.Tensor, theta: torch.Tensor | None = None):
         """Masked reset from pool arrays laid out like the state ([7, N], [6, N], [S, 7])."""
         ts = [mask.to(torch.uint8).contiguous(), pose.contiguous(), vel.contiguous()]

@@ -97,7 +97,8 @@ def test_workspace_bytes_and_validation():
     d2, keep2 = _desc(b, max_contacts=512)
     assert lib.sim_workspace_bytes(C.byref(d2)) > n
     for bad in (dict(abi_version=99), dict(num_scenes=0), dict(max_contacts=0), dict(threads=96),
-                dict(solver=5), dict(warm_start=7), dict(tolerance=-1.0)):
+                dict(solver=5), dict(warm_start=7), dict(tolerance=-1.0),
+                dict(max_pairs=417, max_contacts=256)):  # pairs above 13/8 of the contacts
         db, kb = _desc(b, **bad)
         assert lib.sim_workspace_bytes(C.byref(db)) == 0, bad
         h = C.c_void_p()
