@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--threads", type=int, default=64)
     ap.add_argument("--max-contacts", type=int, default=None)
     ap.add_argument("--max-pairs", type=int, default=None)
+    ap.add_argument("--launch", default=None, choices=["plain", "persistent"],
+                    help="uneven workload: persistent (default) or one workgroup per scene")
     ap.add_argument("--learned-eval", type=int, default=1)
     ap.add_argument("--learned-scenes", type=int, default=2048)
     ap.add_argument("--learned-steps", type=int, default=240)
@@ -206,9 +208,11 @@ def main():
     acts = torch.as_tensor(acts_np, device=dev) if arm else None
     resets = None
     tuned = None
+    persistent = a.workload == "uneven" and a.launch != "plain"
     if a.workload == "uneven":
-        sim.set_persistent(True)
-        tuned = sim.autotune(steps=3, dt=1.0 / 120.0, iters=a.iters)
+        if persistent:
+            sim.set_persistent(True)
+            tuned = sim.autotune(steps=3, dt=1.0 / 120.0, iters=a.iters)
         resets = torch.as_tensor(reset_schedule(n_scenes, W + K), device=dev)
         pose0 = sim.pose.clone()
         vel0 = sim.vel.clone()
@@ -251,7 +255,7 @@ def main():
     bytes_launch = B_DYN * n_dyn + B_STATIC * n_other + B_CONTACT * contacts * n_scenes
     achieved = bytes_launch / (ms_step / 1e3) / 1e9
     traffic = measured_traffic(a.workload)
-    kname = "step_persistent" if a.workload == "uneven" else "step_kernel"
+    kname = "step_persistent" if persistent else "step_kernel"
     sweep_bytes = B_SWEEP * contacts * n_scenes * float(np.mean(st["sweeps"]))
     out = {
         "metric": METRIC,
@@ -271,10 +275,11 @@ def main():
             "scenes": n_scenes, "bodies": int(batch.n_bodies), "dynamic_bodies": n_dyn,
             "dt": 1.0 / 120.0, "sweep_cap": a.iters, "tolerance_m_per_s": a.tol,
             "warm_start": a.warm, "solver": "pgs",
-            "threads_per_scene": a.threads if a.workload != "uneven" else "autotuned: 64 (one wave) or 256",
+            "threads_per_scene": a.threads if not persistent else "autotuned: 64 (one wave) or 256",
             "max_contacts_per_scene": max_contacts, "max_pairs_per_scene": max_pairs,
-            **({"launch": "persistent, HIP graph", "wave_max_bodies": tuned,
-                "resets": "each scene after U[100, 300] steps"} if a.workload == "uneven" else {}),
+            **({"launch": "persistent, HIP graph" if persistent else "one workgroup per scene",
+                "wave_max_bodies": tuned, "resets": "each scene after U[100, 300] steps"}
+               if a.workload == "uneven" else {}),
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
