@@ -105,7 +105,10 @@ struct QueueParams {
 
 // LDS word offsets of one scene's working set.  Records are float4-aligned:
 //  geo  [NB][12]: (x, y, z, meta) (qw, qx, qy, qz) (p0, p1, p2, -)
-//  dyn  [NB][16]: (vx, vy, vz, inv_mass) (wx, wy, wz, mu) (Ixx, Iyy, Izz, Ixy) (Ixz, Iyz, e, -)
+//  dyn  [NB][16]: (vx, vy, vz, inv_mass) (wx, wy, wz, mu) (Ixx, Iyy, Izz, Ixy) (Ixz, Iyz, e, -),
+//       preceded by two body slots: index -1 the ground (zero velocity and
+//       inverse mass, read by contacts with the ground), index -2 a sink for
+//       the solver's writes of bodies that are not dynamic (never read)
 //  ckey [CM]: contact keys, canonical order
 //  lam  [CM][4]: (lambda_n, lambda_t1, lambda_t2, phi), colour-major order
 //  perm [CM]: colour-major position -> canonical contact index
@@ -132,6 +135,7 @@ inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int wave
   int o = 0;
   auto take = [&](int words) { int r = o; o += (words + 3) & ~3; return r; };
   L.geo = take(12 * NB);
+  take(32);  // ground and sink slots
   L.dyn = take(16 * NB);
   L.ckey = take(CM);
   L.lam = take(4 * CM);

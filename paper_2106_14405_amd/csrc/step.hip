@@ -248,11 +248,14 @@ __device__ __forceinline__ V3 Imul(const float* I, V3 a) {
             I[4] * a.x + I[5] * a.y + I[2] * a.z);
 }
 
+// Projection of the friction impulse onto the disk of radius lim >= 0; the
+// scale lim / |l| comes from the hardware reciprocal square root (about 1 ulp).
 __device__ __forceinline__ void proj_disk(float& l1, float& l2, float lim) {
-  float Ls = sqrtf(l1 * l1 + l2 * l2);
-  if (Ls > lim) {
-    if (Ls > 0.f) { float f = lim * frcp(Ls); l1 *= f; l2 *= f; }
-    else { l1 = 0.f; l2 = 0.f; }
+  const float s2 = l1 * l1 + l2 * l2;
+  if (s2 > lim * lim) {  // then s2 > 0
+    const float f = lim * __builtin_amdgcn_rsqf(s2);
+    l1 *= f;
+    l2 *= f;
   }
 }
 
@@ -329,15 +332,9 @@ struct Vel {
   float im, mu;
 };
 
+// Index -1 (the ground) reads the zero slot in front of the bodies.
 __device__ __forceinline__ Vel load_vel(const LdsLayout& L, Smem S, int i) {
   Vel b;
-  if (i < 0) {
-    b.v = v3(0.f, 0.f, 0.f);
-    b.w = v3(0.f, 0.f, 0.f);
-    b.im = 0.f;
-    b.mu = 0.f;
-    return b;
-  }
   float4 d0 = ld4(S.f + L.dyn, 4 * i), d1 = ld4(S.f + L.dyn, 4 * i + 1);
   b.v = xyz(d0);
   b.im = d0.w;
@@ -349,6 +346,12 @@ __device__ __forceinline__ Vel load_vel(const LdsLayout& L, Smem S, int i) {
 __device__ __forceinline__ void store_vel(const LdsLayout& L, Smem S, int i, const Vel& b) {
   st4(S.f + L.dyn, 4 * i, f4(b.v, b.im));
   st4(S.f + L.dyn, 4 * i + 1, f4(b.w, b.mu));
+}
+
+// Writes back a body of a contact update: dynamic bodies to their slot, the
+// others (ground, static, kinematic) to the sink slot, without a branch.
+__device__ __forceinline__ void store_vel_dyn(const LdsLayout& L, Smem S, int i, const Vel& b) {
+  store_vel(L, S, b.im > 0.f ? i : -2, b);
 }
 
 // Velocity of contact row w: d . (v_a - v_b) + (r_a x d) . w_a - (r_b x d) . w_b
@@ -397,8 +400,8 @@ __device__ __forceinline__ float pgs_update(const LdsLayout& L, Smem S, const Re
   float d1 = l1 - lam.y, d2 = l2 - lam.z;
   row_apply(w1, A, B, d1);
   row_apply(w2, A, B, d2);
-  if (A.im > 0.f) store_vel(L, S, a, A);
-  if (B.im > 0.f) store_vel(L, S, b, B);
+  store_vel_dyn(L, S, a, A);
+  store_vel_dyn(L, S, b, B);
   st4(S.f + L.lam, i, make_float4(ln, l1, l2, lam.w));
   return fmaxf(fmaxf(fabsf(dn) * frcp(wn.m), fabsf(d1) * frcp(w1.m)), fabsf(d2) * frcp(w2.m));
 }
@@ -467,20 +470,30 @@ __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int nco
     *res_out = 0.f;
     return;
   }
-  const int last = (int)cstart[ncol] - 1;  // >= 0: ncol > 0 implies contacts
-  int i = (int)cstart[0] + tid;
-  bool has = i < (int)cstart[1];
+  // Colour starts in registers, read by a uniform colour index: lane k of
+  // every wave holds cstart[k] and cstart[64 + k] (entries past ncol are 0).
+  static_assert(kMaxColours == 128, "colour starts held in two lanes' words");
+  const int lane = tid & 63;
+  const int cs_lo = (int)cstart[lane], cs_hi = (int)cstart[64 + lane];
+  const int cs_end = __builtin_amdgcn_readfirstlane((int)cstart[kMaxColours]);
+  auto cst = [&](int c) -> int {
+    return c < 64 ? __builtin_amdgcn_readlane(cs_lo, c)
+                  : (c < 128 ? __builtin_amdgcn_readlane(cs_hi, c - 64) : cs_end);
+  };
+  const int last = cst(ncol) - 1;  // >= 0: ncol > 0 implies contacts
+  int i = cst(0) + tid;
+  bool has = i < cst(1);
   float r = 0.f;
   // One colour batch: load the next batch's records (unconditionally, the
   // index clamped to a valid record, so that the loads stay in flight),
   // solve this batch, synchronise.  Two record buffers alternate between
   // batches so that no registers are copied between them.
   auto batch = [&](int c, const Rec& cur, Rec& nxt) {
-    const int e = (int)cstart[c + 1];
+    const int e = cst(c + 1);
     // next batch: colour c + 1, or colour 0 of the next sweep
     const int cn = c + 1 < ncol ? c + 1 : 0;
-    const int inext = (int)cstart[cn] + tid;
-    const bool hnext = inext < (int)cstart[cn + 1];
+    const int inext = cst(cn) + tid;
+    const bool hnext = inext < cst(cn + 1);
     nxt = load_rec(rec, min(inext, last));
     if (has) r = fmaxf(r, pgs_update(L, S, cur, i));
     for (int i2 = i + T; i2 < e; i2 += T) r = fmaxf(r, pgs_update(L, S, load_rec(rec, i2), i2));
@@ -695,6 +708,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     st4(S.f + L.dyn, 4 * i + 2, make_float4(I[0], I[1], I[2], I[3]));
     st4(S.f + L.dyn, 4 * i + 3, make_float4(I[4], I[5], P.restitution[gi], 0.f));
   }
+  if (tid < 8) S.f[L.dyn - 16 + tid] = 0.f;  // ground slot: v = w = 0, inverse mass 0
   team_sync(tm);
   TRACE(1);
   // ---- a1: arm at theta_t, link velocities from the actions -------------
