@@ -105,10 +105,12 @@ struct QueueParams {
 
 // LDS word offsets of one scene's working set.  Records are float4-aligned:
 //  geo  [NB][12]: (x, y, z, meta) (qw, qx, qy, qz) (p0, p1, p2, -)
-//  dyn  [NB][16]: (vx, vy, vz, inv_mass) (wx, wy, wz, mu) (Ixx, Iyy, Izz, Ixy) (Ixz, Iyz, e, -),
+//  dyn  [NB][12]: (vx, vy, vz, inv_mass) (wx, wy, wz, mu) (Ixx, Iyy, Izz, Ixy),
 //       preceded by two body slots: index -1 the ground (zero velocity and
 //       inverse mass, read by contacts with the ground), index -2 a sink for
-//       the solver's writes of bodies that are not dynamic (never read)
+//       the solver's writes of bodies that are not dynamic (never read).  The
+//       48-byte stride spreads the solver's velocity gathers over all LDS banks
+//  dyn2 [NB][4]: (Ixz, Iyz, e, -)
 //  ckey [CM]: contact keys, canonical order
 //  lam  [CM][4]: (lambda_n, lambda_t1, lambda_t2, phi), colour-major order
 //  perm [CM]: colour-major position -> canonical contact index
@@ -120,7 +122,7 @@ struct QueueParams {
 // solver (saved velocities and start objective terms of a learned start,
 // Jacobi snapshot and increments); outputs (arm force partial sums).
 struct LdsLayout {
-  int geo, dyn, ckey, lam, perm, fresh, misc, hist, hbase;
+  int geo, dyn, dyn2, ckey, lam, perm, fresh, misc, hist, hbase;
   int scr;
   int pk, pk2, lo, hi, skey, sval, skey2, sval2, nperm, ncnt;
   int colour, deg, lstart, list, rank, prevk, cv0, ck1;
@@ -129,14 +131,16 @@ struct LdsLayout {
 };
 
 constexpr int kMiscWords = 64;
+constexpr int kDynWords = 12;  // words per body in the dyn region (three float4)
 
 inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int waves, int solver, int warm) {
   LdsLayout L;
   int o = 0;
   auto take = [&](int words) { int r = o; o += (words + 3) & ~3; return r; };
   L.geo = take(12 * NB);
-  take(32);  // ground and sink slots
-  L.dyn = take(16 * NB);
+  take(2 * kDynWords);  // ground and sink slots
+  L.dyn = take(kDynWords * NB);
+  L.dyn2 = take(4 * NB);
   L.ckey = take(CM);
   L.lam = take(4 * CM);
   L.perm = take(CM);

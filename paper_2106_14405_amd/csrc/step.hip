@@ -233,8 +233,8 @@ struct Dyn {
 
 __device__ __forceinline__ Dyn load_dyn(const LdsLayout& L, Smem S, int i) {
   Dyn d;
-  float4 d0 = ld4(S.f + L.dyn, 4 * i), d1 = ld4(S.f + L.dyn, 4 * i + 1);
-  float4 d2 = ld4(S.f + L.dyn, 4 * i + 2), d3 = ld4(S.f + L.dyn, 4 * i + 3);
+  float4 d0 = ld4(S.f + L.dyn, 3 * i), d1 = ld4(S.f + L.dyn, 3 * i + 1);
+  float4 d2 = ld4(S.f + L.dyn, 3 * i + 2), d3 = ld4(S.f + L.dyn2, i);
   d.v = xyz(d0);
   d.im = d0.w;
   d.w = xyz(d1);
@@ -335,7 +335,7 @@ struct Vel {
 // Index -1 (the ground) reads the zero slot in front of the bodies.
 __device__ __forceinline__ Vel load_vel(const LdsLayout& L, Smem S, int i) {
   Vel b;
-  float4 d0 = ld4(S.f + L.dyn, 4 * i), d1 = ld4(S.f + L.dyn, 4 * i + 1);
+  float4 d0 = ld4(S.f + L.dyn, 3 * i), d1 = ld4(S.f + L.dyn, 3 * i + 1);
   b.v = xyz(d0);
   b.im = d0.w;
   b.w = xyz(d1);
@@ -344,8 +344,8 @@ __device__ __forceinline__ Vel load_vel(const LdsLayout& L, Smem S, int i) {
 }
 
 __device__ __forceinline__ void store_vel(const LdsLayout& L, Smem S, int i, const Vel& b) {
-  st4(S.f + L.dyn, 4 * i, f4(b.v, b.im));
-  st4(S.f + L.dyn, 4 * i + 1, f4(b.w, b.mu));
+  st4(S.f + L.dyn, 3 * i, f4(b.v, b.im));
+  st4(S.f + L.dyn, 3 * i + 1, f4(b.w, b.mu));
 }
 
 // Writes back a body of a contact update: dynamic bodies to their slot, the
@@ -536,8 +536,8 @@ __device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int 
   float res = 0.f;
   for (int it = 0; it < iters; it++) {
     for (int i = tid; i < nb; i += T) {
-      st4(snap, 2 * i, ld4(S.f + L.dyn, 4 * i));
-      st4(snap, 2 * i + 1, ld4(S.f + L.dyn, 4 * i + 1));
+      st4(snap, 2 * i, ld4(S.f + L.dyn, 3 * i));
+      st4(snap, 2 * i + 1, ld4(S.f + L.dyn, 3 * i + 1));
     }
     team_sync(tm);
     float r = 0.f;
@@ -640,9 +640,9 @@ __device__ void arm_fk(const StepParams& P, const LdsLayout& L, Smem S, int b0, 
         vv = vv + cross(ax[j], c[k] - o[j]) * thd[j];
       }
       int bi = b0 + k;
-      float mu = S.f[L.dyn + 16 * bi + 7];
-      st4(S.f + L.dyn, 4 * bi, f4(vv, 0.f));
-      st4(S.f + L.dyn, 4 * bi + 1, f4(wv, mu));
+      float mu = S.f[L.dyn + kDynWords * bi + 7];
+      st4(S.f + L.dyn, 3 * bi, f4(vv, 0.f));
+      st4(S.f + L.dyn, 3 * bi + 1, f4(wv, mu));
     }
   }
 }
@@ -703,12 +703,12 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       v = v3(0.f, 0.f, 0.f);
       w = v3(0.f, 0.f, 0.f);
     }
-    st4(S.f + L.dyn, 4 * i, f4(v, im));
-    st4(S.f + L.dyn, 4 * i + 1, f4(w, P.friction[gi]));
-    st4(S.f + L.dyn, 4 * i + 2, make_float4(I[0], I[1], I[2], I[3]));
-    st4(S.f + L.dyn, 4 * i + 3, make_float4(I[4], I[5], P.restitution[gi], 0.f));
+    st4(S.f + L.dyn, 3 * i, f4(v, im));
+    st4(S.f + L.dyn, 3 * i + 1, f4(w, P.friction[gi]));
+    st4(S.f + L.dyn, 3 * i + 2, make_float4(I[0], I[1], I[2], I[3]));
+    st4(S.f + L.dyn2, i, make_float4(I[4], I[5], P.restitution[gi], 0.f));
   }
-  if (tid < 8) S.f[L.dyn - 16 + tid] = 0.f;  // ground slot: v = w = 0, inverse mass 0
+  if (tid < 8) S.f[L.dyn - kDynWords + tid] = 0.f;  // ground slot: v = w = 0, inverse mass 0
   team_sync(tm);
   TRACE(1);
   // ---- a1: arm at theta_t, link velocities from the actions -------------
@@ -1141,9 +1141,9 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       B.mu = 0.f;
       for (int k = 0; k < 6; k++) B.I[k] = 0.f;
     }
-    float eA = S.f[L.dyn + 16 * a + 14];
+    float eA = S.f[L.dyn2 + 4 * a + 2];
     float mub = b >= 0 ? B.mu : P.ground_mu;
-    float eb = b >= 0 ? S.f[L.dyn + 16 * b + 14] : P.ground_e;
+    float eb = b >= 0 ? S.f[L.dyn2 + 4 * b + 2] : P.ground_e;
     float mu = sqrtf(A.mu * mub);
     float e = fmaxf(eA, eb);
     V3 t1, t2;
@@ -1259,8 +1259,8 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     apply_all(L, S, rec, ncol, cstart, tm, 0);
     team_sync(tm);
     for (int i = tid; i < nb; i += T) {
-      st4(S.f + L.vsave, 2 * i, ld4(S.f + L.dyn, 4 * i));
-      st4(S.f + L.vsave, 2 * i + 1, ld4(S.f + L.dyn, 4 * i + 1));
+      st4(S.f + L.vsave, 2 * i, ld4(S.f + L.dyn, 3 * i));
+      st4(S.f + L.vsave, 2 * i + 1, ld4(S.f + L.dyn, 3 * i + 1));
     }
     team_sync(tm);
     apply_all(L, S, rec, ncol, cstart, tm, 1);
@@ -1279,8 +1279,8 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     if (nc > 0 && fval[0] > 0.f) {  // uniform across the workgroup
       if (tid == 0) misc[M_FLAGS] |= FLAG_FELLBACK;
       for (int i = tid; i < nb; i += T) {
-        st4(S.f + L.dyn, 4 * i, ld4(S.f + L.vsave, 2 * i));
-        st4(S.f + L.dyn, 4 * i + 1, ld4(S.f + L.vsave, 2 * i + 1));
+        st4(S.f + L.dyn, 3 * i, ld4(S.f + L.vsave, 2 * i));
+        st4(S.f + L.dyn, 3 * i + 1, ld4(S.f + L.vsave, 2 * i + 1));
       }
       for (int i = tid; i < nc; i += T) {
         if (!((S.u[L.fresh + (i >> 5)] >> (i & 31)) & 1u)) continue;
@@ -1314,7 +1314,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     if (is_dyn_meta(meta)) {
       V3 x = xyz(ld4(S.f + L.geo, 3 * i));
       float4 qq = ld4(S.f + L.geo, 3 * i + 1);
-      V3 v = xyz(ld4(S.f + L.dyn, 4 * i)), w = xyz(ld4(S.f + L.dyn, 4 * i + 1));
+      V3 v = xyz(ld4(S.f + L.dyn, 3 * i)), w = xyz(ld4(S.f + L.dyn, 3 * i + 1));
       x = x + v * dt;
       float qw = qq.x, qx = qq.y, qy = qq.z, qz = qq.w;
       // q + dt/2 (0, w) (x) q
@@ -1348,7 +1348,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       int i = nb - 7 + k;
       long gi = b0 + i;
       float4 x = ld4(S.f + L.geo, 3 * i), qq = ld4(S.f + L.geo, 3 * i + 1);
-      float4 v = ld4(S.f + L.dyn, 4 * i), w = ld4(S.f + L.dyn, 4 * i + 1);
+      float4 v = ld4(S.f + L.dyn, 3 * i), w = ld4(S.f + L.dyn, 3 * i + 1);
       P.pose[gi] = x.x; P.pose[N + gi] = x.y; P.pose[2 * N + gi] = x.z;
       P.pose[3 * N + gi] = qq.x; P.pose[4 * N + gi] = qq.y; P.pose[5 * N + gi] = qq.z; P.pose[6 * N + gi] = qq.w;
       P.vel[gi] = v.x; P.vel[N + gi] = v.y; P.vel[2 * N + gi] = v.z;
