@@ -78,8 +78,7 @@ typedef struct sim_batch_desc {
     float ground_friction;       /* friction of the plane z = 0 */
     float ground_restitution;
     int max_pairs;               /* per-scene capacity of broadphase pairs (a scene of n
-                                    bodies holds at most min(max_pairs, max(64, 6 n)));
-                                    at most 13/8 max_contacts */
+                                    bodies holds at most min(max_pairs, max(64, 6 n))) */
     int max_contacts;            /* per-scene capacity of contacts (same rule) */
     int solver;                  /* SIM_PGS or SIM_JACOBI */
     int warm_start;              /* SIM_COLD, SIM_PREV or SIM_LEARNED */

@@ -92,7 +92,7 @@ Layout make_layout(long S, long N, long PM, long CM) {
   L.off_x_colour = take(4 * S * CM);
   L.off_x_feat = take(4 * 16 * S * CM);
   L.off_raw = take(4 * 8 * S * CM);
-  L.off_crec = take(4 * 52 * S * CM);  // 13 float4 solver record per contact
+  L.off_crec = take(sizeof(float4) * rbs::rec_stride(PM, CM) * S);  // solver records, narrowphase staging
   for (int k = 0; k < 7; k++) L.off_st[k] = take(4 * S);
   L.off_gather = take(8 * S);  // per-scene row offsets and counts of sim_mlp_gather
   L.off_gcount = take(4 * S);
@@ -264,7 +264,6 @@ int validate(const sim_batch_desc* d, Caps* caps) {
   if (d->max_pairs < 1 || d->max_contacts < 1) return fail(SIM_EINVAL, "capacities must be >= 1");
   if (d->max_pairs > (1 << 20) || d->max_contacts > (1 << 20)) return fail(SIM_EINVAL, "capacity too large");
   // the narrowphase stages 4 contacts per pair in a contact record slot set
-  if (8L * d->max_pairs > 13L * d->max_contacts) return fail(SIM_EINVAL, "max_pairs exceeds 13/8 max_contacts");
   int T = d->threads ? d->threads : 64;
   if (T != 64 && T != 128 && T != 192 && T != 256) return fail(SIM_EINVAL, "threads must be 64, 128, 192 or 256");
   if (d->solver != SIM_PGS && d->solver != SIM_JACOBI) return fail(SIM_EINVAL, "bad solver");

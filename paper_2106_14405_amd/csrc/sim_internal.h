@@ -74,7 +74,7 @@ struct StepParams {
   int32_t* x_colour;        // [S*CM]
   float* x_feat;            // [16][S*CM] (export only)
   float4* raw;              // [S*CM][2] narrowphase output, canonical order: (n, phi), (p, -)
-  float4* crec;             // [S*CM][13] solver records (Jacobian rows), colour-major order
+  float4* crec;             // [S][rec_stride(PM, CM)] solver records, colour-major order
   int32_t* st_pairs;
   int32_t* st_contacts;
   int32_t* st_colours;
@@ -110,7 +110,7 @@ struct QueueParams {
 //       inverse mass, read by contacts with the ground), index -2 a sink for
 //       the solver's writes of bodies that are not dynamic (never read).  The
 //       48-byte stride spreads the solver's velocity gathers over all LDS banks
-//  dyn2 [NB][4]: (Ixz, Iyz, e, -)
+//  dyn2 [NB][4]: (Ixz, Iyz, e, -), preceded by the same two slots
 //  ckey [CM]: contact keys, canonical order
 //  lam  [CM][4]: (lambda_n, lambda_t1, lambda_t2, phi), colour-major order
 //  perm [CM]: colour-major position -> canonical contact index
@@ -132,6 +132,14 @@ struct LdsLayout {
 
 constexpr int kMiscWords = 64;
 constexpr int kDynWords = 12;  // words per body in the dyn region (three float4)
+constexpr int kRec = 5;        // float4 per contact in the solver records
+
+// float4 per scene of the solver-record buffer: the records of CM contacts,
+// or, earlier in the step, the narrowphase's staging of up to 4 contacts
+// (2 float4 each) for every one of PM pairs, whichever is larger.
+inline __host__ __device__ long rec_stride(long PM, long CM) {
+  return kRec * CM > 8 * PM ? kRec * CM : 8 * PM;
+}
 
 inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int waves, int solver, int warm) {
   LdsLayout L;
@@ -140,6 +148,7 @@ inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int wave
   L.geo = take(12 * NB);
   take(2 * kDynWords);  // ground and sink slots
   L.dyn = take(kDynWords * NB);
+  take(2 * 4);  // ground and sink slots of dyn2
   L.dyn2 = take(4 * NB);
   L.ckey = take(CM);
   L.lam = take(4 * CM);

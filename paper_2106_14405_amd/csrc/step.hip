@@ -259,19 +259,26 @@ __device__ __forceinline__ void proj_disk(float& l1, float& l2, float lim) {
   }
 }
 
-// Solver record of one contact: the three rows d in {n, t1, t2} with the
-// Jacobian parts r_a x d, r_b x d, the inverse-inertia images
-// I_a^-1 (r_a x d), I_b^-1 (r_b x d), effective masses, bias, friction, key
-// and the Jacobi scale; 13 float4 in global memory, colour-major order:
-//  0 (n, m_n) 1 (t1, m_t1) 2 (t2, m_t2) 3 (ca_n, bias) 4 (ca_1, mu) 5 (ca_2, key)
-//  6 (cb_n, jsc) 7 (cb_1, ia_n.x) 8 (cb_2, ia_n.y) 9 (ia_n.z, ia_1) 10 (ia_2, ib_n.x)
-//  11 (ib_n.yz, ib_1.xy) 12 (ib_1.z, ib_2)
-constexpr int kRec = 13;
+// Solver record of one contact, 5 float4 in global memory, colour-major
+// order:
+//  0 (n, m_n)  1 (r_a, m_t1)  2 (r_b, m_t2)  3 (k_1n, k_2n, bias, mu)
+//  4 (key, Jacobi scale, 0, 0)
+// n the normal (the tangents t1, t2 follow from it by tangents_fast, as in
+// the setup), r_a, r_b the contact point relative to the bodies' centres,
+// m_d = 1 / k_d the effective mass of row d, and k_dn the change of row d's
+// velocity per unit normal impulse (the normal-friction coupling inside one
+// contact).  The angular parts r x d and I^-1 (r x d) of the Jacobian rows
+// are not stored: the velocity of a row is d . (v_a + w_a x r_a - v_b -
+// w_b x r_b) and an impulse P changes w by I^-1 (r x P), with the world
+// inverse inertia I^-1 read from LDS.  80 bytes instead of the 208 of
+// explicit rows keep a sweep's records in L2.
+static_assert(kRec == 5, "record layout below");
 
 struct Rec {
   float4 r[kRec];
 };
 
+// One Jacobian row during the setup (effective masses and couplings).
 struct Row {
   V3 d, ca, cb, ia, ib;
   float m;
@@ -284,62 +291,40 @@ __device__ __forceinline__ Rec load_rec(const float4* rec, int i) {
   return R;
 }
 
-__device__ __forceinline__ int rec_a(const Rec& R) { return (int)(__float_as_uint(R.r[5].w) >> 20); }
+__device__ __forceinline__ int rec_a(const Rec& R) { return (int)(__float_as_uint(R.r[4].x) >> 20); }
 __device__ __forceinline__ int rec_b(const Rec& R) {
-  uint32_t bk = (__float_as_uint(R.r[5].w) >> 8) & 0xFFFu;
+  uint32_t bk = (__float_as_uint(R.r[4].x) >> 8) & 0xFFFu;
   return bk == kGroundKey ? -1 : (int)bk;
 }
 
-__device__ __forceinline__ Row rec_row(const Rec& R, int k) {
-  Row w;
-  if (k == 0) {
-    w.d = xyz(R.r[0]); w.m = R.r[0].w; w.ca = xyz(R.r[3]); w.cb = xyz(R.r[6]);
-    w.ia = v3(R.r[7].w, R.r[8].w, R.r[9].x);
-    w.ib = v3(R.r[10].w, R.r[11].x, R.r[11].y);
-  } else if (k == 1) {
-    w.d = xyz(R.r[1]); w.m = R.r[1].w; w.ca = xyz(R.r[4]); w.cb = xyz(R.r[7]);
-    w.ia = v3(R.r[9].y, R.r[9].z, R.r[9].w);
-    w.ib = v3(R.r[11].z, R.r[11].w, R.r[12].x);
-  } else {
-    w.d = xyz(R.r[2]); w.m = R.r[2].w; w.ca = xyz(R.r[5]); w.cb = xyz(R.r[8]);
-    w.ia = xyz(R.r[10]);
-    w.ib = v3(R.r[12].y, R.r[12].z, R.r[12].w);
-  }
-  return w;
-}
-
-__device__ __forceinline__ void store_rec(float4* rec, int i, const Row* w, float bias, float mu, uint32_t key,
-                                          float jsc) {
+__device__ __forceinline__ void store_rec(float4* rec, int i, V3 n, V3 ra, V3 rb, const float* m, float k1n, float k2n,
+                                          float bias, float mu, uint32_t key, float jsc) {
   float4* o = rec + kRec * i;
-  o[0] = f4(w[0].d, w[0].m);
-  o[1] = f4(w[1].d, w[1].m);
-  o[2] = f4(w[2].d, w[2].m);
-  o[3] = f4(w[0].ca, bias);
-  o[4] = f4(w[1].ca, mu);
-  o[5] = f4(w[2].ca, __uint_as_float(key));
-  o[6] = f4(w[0].cb, jsc);
-  o[7] = f4(w[1].cb, w[0].ia.x);
-  o[8] = f4(w[2].cb, w[0].ia.y);
-  o[9] = make_float4(w[0].ia.z, w[1].ia.x, w[1].ia.y, w[1].ia.z);
-  o[10] = f4(w[2].ia, w[0].ib.x);
-  o[11] = make_float4(w[0].ib.y, w[0].ib.z, w[1].ib.x, w[1].ib.y);
-  o[12] = make_float4(w[1].ib.z, w[2].ib.x, w[2].ib.y, w[2].ib.z);
+  o[0] = f4(n, m[0]);
+  o[1] = f4(ra, m[1]);
+  o[2] = f4(rb, m[2]);
+  o[3] = make_float4(k1n, k2n, bias, mu);
+  o[4] = make_float4(__uint_as_float(key), jsc, 0.f, 0.f);
 }
 
-// Body velocities in registers (dynamic iff im > 0).
+// A body as the solver sees it in LDS: velocities, inverse mass (dynamic
+// iff > 0), friction coefficient, world inverse inertia (xx yy zz xy xz yz).
+// Index -1 (the ground) reads the zero slots in front of the bodies.
 struct Vel {
   V3 v, w;
   float im, mu;
+  float I[6];
 };
 
-// Index -1 (the ground) reads the zero slot in front of the bodies.
 __device__ __forceinline__ Vel load_vel(const LdsLayout& L, Smem S, int i) {
   Vel b;
-  float4 d0 = ld4(S.f + L.dyn, 3 * i), d1 = ld4(S.f + L.dyn, 3 * i + 1);
+  const float4 d0 = ld4(S.f + L.dyn, 3 * i), d1 = ld4(S.f + L.dyn, 3 * i + 1);
+  const float4 d2 = ld4(S.f + L.dyn, 3 * i + 2), d3 = ld4(S.f + L.dyn2, i);
   b.v = xyz(d0);
   b.im = d0.w;
   b.w = xyz(d1);
   b.mu = d1.w;
+  b.I[0] = d2.x; b.I[1] = d2.y; b.I[2] = d2.z; b.I[3] = d2.w; b.I[4] = d3.x; b.I[5] = d3.y;
   return b;
 }
 
@@ -354,16 +339,17 @@ __device__ __forceinline__ void store_vel_dyn(const LdsLayout& L, Smem S, int i,
   store_vel(L, S, b.im > 0.f ? i : -2, b);
 }
 
-// Velocity of contact row w: d . (v_a - v_b) + (r_a x d) . w_a - (r_b x d) . w_b
-__device__ __forceinline__ float row_u(const Row& w, const Vel& A, const Vel& B) {
-  return dot(w.d, A.v - B.v) + dot(w.ca, A.w) - dot(w.cb, B.w);
+// Relative velocity of the contact point: (v_a + w_a x r_a) - (v_b + w_b x r_b).
+__device__ __forceinline__ V3 point_vel(V3 va, V3 wa, V3 vb, V3 wb, V3 ra, V3 rb) {
+  return (va + cross(wa, ra)) - (vb + cross(wb, rb));
 }
 
-__device__ __forceinline__ void row_apply(const Row& w, Vel& A, Vel& B, float dl) {
-  A.v = A.v + w.d * (A.im * dl);
-  A.w = A.w + w.ia * dl;
-  B.v = B.v - w.d * (B.im * dl);
-  B.w = B.w - w.ib * dl;
+// Impulse P at the contact point on body a and -P on body b.
+__device__ __forceinline__ void apply_impulse(Vel& A, Vel& B, V3 ra, V3 rb, V3 P) {
+  A.v = A.v + P * A.im;
+  A.w = A.w + Imul(A.I, cross(ra, P));
+  B.v = B.v - P * B.im;
+  B.w = B.w - Imul(B.I, cross(rb, P));
 }
 
 // Synchronisation between colour batches: a single-wave team needs only a
@@ -380,30 +366,32 @@ __device__ __forceinline__ void colour_sync(const TM& tm) {
   }
 }
 
-// One Gauss-Seidel update at colour-major position i: normal row, then both
-// friction rows from the velocities after the normal update.  Returns the
+// One Gauss-Seidel update at colour-major position i: the normal row, then
+// both friction rows from the velocities after the normal impulse (through
+// the couplings k_1n, k_2n), then the contact's total impulse.  Returns the
 // residual max |dlambda| * k.
 __device__ __forceinline__ float pgs_update(const LdsLayout& L, Smem S, const Rec& R, int i) {
   const int a = rec_a(R), b = rec_b(R);
-  float4 lam = ld4(S.f + L.lam, i);
+  const float4 lam = ld4(S.f + L.lam, i);
   Vel A = load_vel(L, S, a);
   Vel B = load_vel(L, S, b);
-  const float bias = R.r[3].w, mu = R.r[4].w;
-  Row wn = rec_row(R, 0);
-  float ln = fmaxf(0.f, lam.x + wn.m * (bias - row_u(wn, A, B)));
-  float dn = ln - lam.x;
-  row_apply(wn, A, B, dn);
-  Row w1 = rec_row(R, 1), w2 = rec_row(R, 2);
-  float l1 = lam.y - w1.m * row_u(w1, A, B);
-  float l2 = lam.z - w2.m * row_u(w2, A, B);
+  const V3 n = xyz(R.r[0]), ra = xyz(R.r[1]), rb = xyz(R.r[2]);
+  const float mn = R.r[0].w, m1 = R.r[1].w, m2 = R.r[2].w;
+  const float k1n = R.r[3].x, k2n = R.r[3].y, bias = R.r[3].z, mu = R.r[3].w;
+  V3 t1, t2;
+  tangents_fast(n, t1, t2);
+  const V3 dv = point_vel(A.v, A.w, B.v, B.w, ra, rb);
+  const float ln = fmaxf(0.f, lam.x + mn * (bias - dot(n, dv)));
+  const float dn = ln - lam.x;
+  float l1 = lam.y - m1 * (dot(t1, dv) + k1n * dn);
+  float l2 = lam.z - m2 * (dot(t2, dv) + k2n * dn);
   proj_disk(l1, l2, mu * ln);
-  float d1 = l1 - lam.y, d2 = l2 - lam.z;
-  row_apply(w1, A, B, d1);
-  row_apply(w2, A, B, d2);
+  const float d1 = l1 - lam.y, d2 = l2 - lam.z;
+  apply_impulse(A, B, ra, rb, n * dn + t1 * d1 + t2 * d2);
   store_vel_dyn(L, S, a, A);
   store_vel_dyn(L, S, b, B);
   st4(S.f + L.lam, i, make_float4(ln, l1, l2, lam.w));
-  return fmaxf(fmaxf(fabsf(dn) * frcp(wn.m), fabsf(d1) * frcp(w1.m)), fabsf(d2) * frcp(w2.m));
+  return fmaxf(fmaxf(fabsf(dn) * frcp(mn), fabsf(d1) * frcp(m1)), fabsf(d2) * frcp(m2));
 }
 
 // Objective change from adding the network's start impulses of colour-major
@@ -417,19 +405,22 @@ __device__ __forceinline__ float start_objective(const LdsLayout& L, Smem S, con
   Rec R = load_rec(rec, i);
   const int a = rec_a(R), b = rec_b(R);
   const float4 lam = ld4(S.f + L.lam, i);
-  Vel A1 = load_vel(L, S, a), B1 = load_vel(L, S, b);
-  Vel A0 = A1, B0 = B1;  // velocities before the new contacts' impulses: saved copy
-  A0.v = xyz(ld4(S.f + L.vsave, 2 * a));
-  A0.w = xyz(ld4(S.f + L.vsave, 2 * a + 1));
+  const Vel A1 = load_vel(L, S, a), B1 = load_vel(L, S, b);
+  // velocities before the new contacts' impulses: saved copy (ground: zero)
+  const V3 va0 = xyz(ld4(S.f + L.vsave, 2 * a)), wa0 = xyz(ld4(S.f + L.vsave, 2 * a + 1));
+  V3 vb0 = v3(0.f, 0.f, 0.f), wb0 = vb0;
   if (b >= 0) {
-    B0.v = xyz(ld4(S.f + L.vsave, 2 * b));
-    B0.w = xyz(ld4(S.f + L.vsave, 2 * b + 1));
+    vb0 = xyz(ld4(S.f + L.vsave, 2 * b));
+    wb0 = xyz(ld4(S.f + L.vsave, 2 * b + 1));
   }
-  const float bias = R.r[3].w;
-  Row wn = rec_row(R, 0), w1 = rec_row(R, 1), w2 = rec_row(R, 2);
-  float f = lam.x * (0.5f * (row_u(wn, A0, B0) + row_u(wn, A1, B1)) - bias);
-  f += lam.y * 0.5f * (row_u(w1, A0, B0) + row_u(w1, A1, B1));
-  f += lam.z * 0.5f * (row_u(w2, A0, B0) + row_u(w2, A1, B1));
+  const V3 n = xyz(R.r[0]), ra = xyz(R.r[1]), rb = xyz(R.r[2]);
+  const float bias = R.r[3].z;
+  V3 t1, t2;
+  tangents_fast(n, t1, t2);
+  const V3 dv0 = point_vel(va0, wa0, vb0, wb0, ra, rb), dv1 = point_vel(A1.v, A1.w, B1.v, B1.w, ra, rb);
+  float f = lam.x * (0.5f * (dot(n, dv0) + dot(n, dv1)) - bias);
+  f += lam.y * 0.5f * (dot(t1, dv0) + dot(t1, dv1));
+  f += lam.z * 0.5f * (dot(t2, dv0) + dot(t2, dv1));
   return f;
 }
 
@@ -443,14 +434,15 @@ __device__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int nco
       if (select >= 0 && (int)((S.u[L.fresh + (i >> 5)] >> (i & 31)) & 1u) != select) continue;
       Rec R = load_rec(rec, i);
       const int a = rec_a(R), b = rec_b(R);
-      float4 lam = ld4(S.f + L.lam, i);
+      const float4 lam = ld4(S.f + L.lam, i);
       Vel A = load_vel(L, S, a);
       Vel B = load_vel(L, S, b);
-      row_apply(rec_row(R, 0), A, B, lam.x);
-      row_apply(rec_row(R, 1), A, B, lam.y);
-      row_apply(rec_row(R, 2), A, B, lam.z);
-      if (A.im > 0.f) store_vel(L, S, a, A);
-      if (B.im > 0.f) store_vel(L, S, b, B);
+      const V3 n = xyz(R.r[0]);
+      V3 t1, t2;
+      tangents_fast(n, t1, t2);
+      apply_impulse(A, B, xyz(R.r[1]), xyz(R.r[2]), n * lam.x + t1 * lam.y + t2 * lam.z);
+      store_vel_dyn(L, S, a, A);
+      store_vel_dyn(L, S, b, B);
     }
     colour_sync(tm);
   }
@@ -544,41 +536,42 @@ __device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int 
     for (int i = tid; i < nc; i += T) {
       Rec R = load_rec(rec, i);
       const int a = rec_a(R), b = rec_b(R);
-      float4 lam = ld4(S.f + L.lam, i);
-      Vel A, B;
-      A.v = xyz(ld4(snap, 2 * a));
-      A.w = xyz(ld4(snap, 2 * a + 1));
+      const float4 lam = ld4(S.f + L.lam, i);
+      const V3 va = xyz(ld4(snap, 2 * a)), wa = xyz(ld4(snap, 2 * a + 1));
+      V3 vb = v3(0.f, 0.f, 0.f), wb = vb;
       if (b >= 0) {
-        B.v = xyz(ld4(snap, 2 * b));
-        B.w = xyz(ld4(snap, 2 * b + 1));
-      } else {
-        B.v = v3(0.f, 0.f, 0.f);
-        B.w = v3(0.f, 0.f, 0.f);
+        vb = xyz(ld4(snap, 2 * b));
+        wb = xyz(ld4(snap, 2 * b + 1));
       }
-      const float bias = R.r[3].w, mu = R.r[4].w, sc = R.r[6].w;
-      Row wn = rec_row(R, 0), w1 = rec_row(R, 1), w2 = rec_row(R, 2);
-      float ln = fmaxf(0.f, lam.x + sc * wn.m * (bias - row_u(wn, A, B)));
-      float l1 = lam.y - sc * w1.m * row_u(w1, A, B);
-      float l2 = lam.z - sc * w2.m * row_u(w2, A, B);
+      const V3 n = xyz(R.r[0]), ra = xyz(R.r[1]), rb = xyz(R.r[2]);
+      const float mn = R.r[0].w, m1 = R.r[1].w, m2 = R.r[2].w;
+      const float bias = R.r[3].z, mu = R.r[3].w, sc = R.r[4].y;
+      V3 t1, t2;
+      tangents_fast(n, t1, t2);
+      const V3 dv = point_vel(va, wa, vb, wb, ra, rb);
+      float ln = fmaxf(0.f, lam.x + sc * mn * (bias - dot(n, dv)));
+      float l1 = lam.y - sc * m1 * dot(t1, dv);
+      float l2 = lam.z - sc * m2 * dot(t2, dv);
       proj_disk(l1, l2, mu * ln);
       float dn = ln - lam.x, d1 = l1 - lam.y, d2 = l2 - lam.z;
       st4(S.f + L.dl, i, make_float4(dn, d1, d2, 0.f));
       st4(S.f + L.lam, i, make_float4(ln, l1, l2, lam.w));
-      r = fmaxf(r, fmaxf(fmaxf(fabsf(dn) * frcp(wn.m), fabsf(d1) * frcp(w1.m)), fabsf(d2) * frcp(w2.m)));
+      r = fmaxf(r, fmaxf(fmaxf(fabsf(dn) * frcp(mn), fabsf(d1) * frcp(m1)), fabsf(d2) * frcp(m2)));
     }
     team_sync(tm);
     for (int c = 0; c < ncol; c++) {
       for (int i = (int)cstart[c] + tid; i < (int)cstart[c + 1]; i += T) {
         Rec R = load_rec(rec, i);
         const int a = rec_a(R), b = rec_b(R);
-        float4 dl = ld4(S.f + L.dl, i);
+        const float4 dl = ld4(S.f + L.dl, i);
         Vel A = load_vel(L, S, a);
         Vel B = load_vel(L, S, b);
-        row_apply(rec_row(R, 0), A, B, dl.x);
-        row_apply(rec_row(R, 1), A, B, dl.y);
-        row_apply(rec_row(R, 2), A, B, dl.z);
-        if (A.im > 0.f) store_vel(L, S, a, A);
-        if (B.im > 0.f) store_vel(L, S, b, B);
+        const V3 n = xyz(R.r[0]);
+        V3 t1, t2;
+        tangents_fast(n, t1, t2);
+        apply_impulse(A, B, xyz(R.r[1]), xyz(R.r[2]), n * dl.x + t1 * dl.y + t2 * dl.z);
+        store_vel_dyn(L, S, a, A);
+        store_vel_dyn(L, S, b, B);
       }
       team_sync(tm);
     }
@@ -661,7 +654,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   const long N = P.n_bodies;
   uint32_t* misc = S.u + L.misc;
   float4* raw = P.raw + (long)s * CM * 2;
-  float4* rec = P.crec + (long)s * CM * kRec;
+  float4* rec = P.crec + (long)s * rec_stride(PM, CM);
   const float dt = P.dt;
   if (nb > NB) {  // host guarantees otherwise; leave the scene untouched
     if (tid == 0) P.st_flags[s] = FLAG_CAPACITY;
@@ -708,7 +701,9 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     st4(S.f + L.dyn, 3 * i + 2, make_float4(I[0], I[1], I[2], I[3]));
     st4(S.f + L.dyn2, i, make_float4(I[4], I[5], P.restitution[gi], 0.f));
   }
-  if (tid < 8) S.f[L.dyn - kDynWords + tid] = 0.f;  // ground slot: v = w = 0, inverse mass 0
+  // ground slot: zero velocity, inverse mass and inverse inertia
+  if (tid < kDynWords) S.f[L.dyn - kDynWords + tid] = 0.f;
+  if (tid < 4) S.f[L.dyn2 - 4 + tid] = 0.f;
   team_sync(tm);
   TRACE(1);
   // ---- a1: arm at theta_t, link velocities from the actions -------------
@@ -840,8 +835,8 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   // ---- a6: narrowphase, compaction in canonical order --------------------
   // Pairs run grouped by shape class, so that a wave executes one contact
   // routine at a time; each pair's contacts (at most 4) are staged in the
-  // record buffer (free until setup), then compacted in canonical order.
-  // (8 PMs <= 13 CMs: sim_create checks the batch capacities.)
+  // record buffer (free until setup; 8 PM float4 per scene), then compacted
+  // in canonical order.
   {
     const int lane = tid & 63, w = tid >> 6, W = T >> 6;
     uint32_t* nperm = S.u + L.nperm;
@@ -1031,43 +1026,74 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   // its unique solution is sequential first fit in canonical order.  The
   // contacts are taken a team's width at a time in canonical order: earlier
   // chunks are final, so each chunk iterates to its own fixed point, which
-  // takes as many rounds as its longest dependency chain.
+  // takes as many rounds as its longest dependency chain.  From here on the
+  // per-body lists hold colours: slot lstart[i] + k is the colour of body
+  // i's k-th contact, written by that contact, so that a contact reads its
+  // predecessors' colours as one contiguous run per body.
+  const int ltot = (int)lstart[nb];
+  for (int x = tid; x < ltot; x += T) list[x] = 0u;
+  team_sync(tm);
   for (int c0 = 0; c0 < nc; c0 += T) {
     const int q = c0 + tid;
     const bool valid = q < nc;
-    int a = 0, b = 0, la = 0, lb = 0;
+    int la = 0, lb = 0;
+    bool da = false, db = false;
     uint32_t sa = 0u, sb = 0u;
     if (valid) {
       const uint32_t key = ckeys[q];
-      a = (int)(key >> 20);
-      b = (int)((key >> 8) & 0xFFFu);
+      const int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
       const uint32_t rk = rank[q];
-      la = is_dyn_meta(body_meta(L, S, a)) ? (int)(rk & 0xFFFFu) : 0;
-      lb = (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) ? (int)(rk >> 16) : 0;
-      sa = la ? lstart[a] : 0u;
-      sb = lb ? lstart[b] : 0u;
+      da = is_dyn_meta(body_meta(L, S, a));
+      db = b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b));
+      la = da ? (int)(rk & 0xFFFFu) : 0;
+      lb = db ? (int)(rk >> 16) : 0;
+      sa = da ? lstart[a] : 0u;
+      sb = db ? lstart[b] : 0u;
     }
     for (int round = 0; round <= T + 1; round++) {
       if (tid == 0) misc[M_CHANGED] = 0u;
       team_sync(tm);
       bool changed = false;
       if (valid) {
-        uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-        for (int x = 0; x < la + lb; x++) {
-          uint32_t p = x < la ? list[sa + x] : list[sb + (x - la)];
-          uint32_t c = colour[p];
-          if (c < 32) m0 |= 1u << c;
-          else if (c < 64) m1 |= 1u << (c - 32);
-          else if (c < 96) m2 |= 1u << (c - 64);
-          else m3 |= 1u << (c - 96);
-        }
+        // colours below 64 as one 64-bit mask, four independent reads at a time
+        u64 m = 0ull;
+        uint32_t cmax = 0u;
+        auto scan = [&](uint32_t s0, int n) {
+          int x = 0;
+          for (; x + 4 <= n; x += 4) {
+            const uint32_t c0 = list[s0 + x], c1 = list[s0 + x + 1], c2 = list[s0 + x + 2], c3 = list[s0 + x + 3];
+            m |= (1ull << (c0 & 63u)) | (1ull << (c1 & 63u)) | (1ull << (c2 & 63u)) | (1ull << (c3 & 63u));
+            cmax = max(cmax, max(max(c0, c1), max(c2, c3)));
+          }
+          for (; x < n; x++) {
+            const uint32_t c = list[s0 + x];
+            m |= 1ull << (c & 63u);
+            cmax = max(cmax, c);
+          }
+        };
+        scan(sa, la);
+        scan(sb, lb);
         uint32_t c;
-        if (~m0) c = __builtin_ctz(~m0);
-        else if (~m1) c = 32 + __builtin_ctz(~m1);
-        else if (~m2) c = 64 + __builtin_ctz(~m2);
-        else if (~m3) c = 96 + __builtin_ctz(~m3);
-        else c = kMaxColours - 1;  // overflow: flagged below
-        if (c != colour[q]) { colour[q] = c; changed = true; }
+        if (cmax < 64u) {
+          c = ~m ? (uint32_t)__builtin_ctzll(~m) : 64u;
+        } else {  // colours of 64 and above: the full 128-bit mask
+          uint32_t m4[4] = {0u, 0u, 0u, 0u};
+          for (int x = 0; x < la + lb; x++) {
+            const uint32_t cc = x < la ? list[sa + x] : list[sb + (x - la)];
+            m4[cc >> 5] |= 1u << (cc & 31u);
+          }
+          if (~m4[0]) c = __builtin_ctz(~m4[0]);
+          else if (~m4[1]) c = 32 + __builtin_ctz(~m4[1]);
+          else if (~m4[2]) c = 64 + __builtin_ctz(~m4[2]);
+          else if (~m4[3]) c = 96 + __builtin_ctz(~m4[3]);
+          else c = kMaxColours - 1;  // overflow: flagged below
+        }
+        if (c != colour[q]) {
+          colour[q] = c;
+          if (da) list[sa + la] = c;
+          if (db) list[sb + lb] = c;
+          changed = true;
+        }
       }
       if (changed) misc[M_CHANGED] = 1u;
       team_sync(tm);
@@ -1241,7 +1267,12 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     int nbb = (b >= 0 && B.im > 0.f) ? (int)deg[b] : 0;
     float jsc = 1.0f / (float)(na > nbb ? na : nbb);
     if (live) {
-      store_rec(rec, i, rw, bias, mu, key, jsc);
+      // normal-friction couplings: change of row d's velocity per unit normal impulse
+      const float ims = A.im + B.im;
+      const float k1n = dot(t1, n) * ims + dot(rw[1].ca, rw[0].ia) + dot(rw[1].cb, rw[0].ib);
+      const float k2n = dot(t2, n) * ims + dot(rw[2].ca, rw[0].ia) + dot(rw[2].cb, rw[0].ib);
+      const float m3[3] = {rw[0].m, rw[1].m, rw[2].m};
+      store_rec(rec, i, n, c.ra, c.rb, m3, k1n, k2n, bias, mu, key, jsc);
       st4(S.f + L.lam, i, make_float4(l0, l1, l2, phi));
       if (kLearned && hit < 0) atomicOr(S.u + L.fresh + (i >> 5), 1u << (i & 31));
     }
@@ -1364,7 +1395,9 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     const int q = (int)perm[i];
     const float4* R = rec + kRec * i;
     float4 lam = ld4(S.f + L.lam, i);
-    V3 n = xyz(R[0]), t1 = xyz(R[1]), t2 = xyz(R[2]);
+    const V3 n = xyz(R[0]);
+    V3 t1, t2;
+    tangents_fast(n, t1, t2);
     uint32_t key = ckeys[q];
     int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
     V3 F = t1 * lam.y + t2 * lam.z;

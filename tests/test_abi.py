@@ -97,14 +97,29 @@ def test_workspace_bytes_and_validation():
     d2, keep2 = _desc(b, max_contacts=512)
     assert lib.sim_workspace_bytes(C.byref(d2)) > n
     for bad in (dict(abi_version=99), dict(num_scenes=0), dict(max_contacts=0), dict(threads=96),
-                dict(solver=5), dict(warm_start=7), dict(tolerance=-1.0),
-                dict(max_pairs=417, max_contacts=256)):  # pairs above 13/8 of the contacts
+                dict(solver=5), dict(warm_start=7), dict(tolerance=-1.0), dict(max_pairs=0),
+                dict(max_pairs=(1 << 20) + 1)):
         db, kb = _desc(b, **bad)
         assert lib.sim_workspace_bytes(C.byref(db)) == 0, bad
         h = C.c_void_p()
         rc = lib.sim_create(C.byref(db), None, 0, C.byref(h))
         assert rc < 0 and not h.value
         assert lib.sim_last_error()
+
+
+def test_workspace_holds_narrowphase_staging():
+    """The narrowphase stages up to 4 contacts (2 float4 each) per pair in a
+    scene's solver-record block, so that block must grow with the pair
+    capacity even when the contact capacity is small."""
+    from paper_2106_14405_amd import _lib as L
+    lib = L.load()
+    b = S.batch_drop(3)
+    S_ = b.n_scenes
+    small, k1 = _desc(b, max_pairs=128, max_contacts=256)
+    big, k2 = _desc(b, max_pairs=1024, max_contacts=256)
+    grow = lib.sim_workspace_bytes(C.byref(big)) - lib.sim_workspace_bytes(C.byref(small))
+    # record block per scene: max(5 * 256, 8 * pairs) float4 of 16 bytes
+    assert grow >= S_ * (8 * 1024 - 5 * 256) * 16
 
 
 def test_bad_bodies_rejected():
