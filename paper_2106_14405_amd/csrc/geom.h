@@ -40,6 +40,14 @@ __device__ __forceinline__ void setc(V3& a, int i, float s) {
   if (i == 0) a.x = s; else if (i == 1) a.y = s; else a.z = s;
 }
 __device__ __forceinline__ V3 unitv(int i) { return v3(i == 0 ? 1.f : 0.f, i == 1 ? 1.f : 0.f, i == 2 ? 1.f : 0.f); }
+// Element i of a three-element array, as selects (a runtime index into a
+// local array would put the array in scratch memory).
+__device__ __forceinline__ float at3(const float* h, int i) { return i == 0 ? h[0] : (i == 1 ? h[1] : h[2]); }
+__device__ __forceinline__ V3 sel3(V3 a0, V3 a1, V3 a2, int i) {
+  return v3(i == 0 ? a0.x : (i == 1 ? a1.x : a2.x), i == 0 ? a0.y : (i == 1 ? a1.y : a2.y),
+            i == 0 ? a0.z : (i == 1 ? a1.z : a2.z));
+}
+__device__ __forceinline__ V3 selv(bool s, V3 a, V3 b) { return v3(s ? a.x : b.x, s ? a.y : b.y, s ? a.z : b.z); }
 
 // Rotation matrix, row-major m[r][c]; columns are the body axes in world.
 struct M3 {
@@ -62,7 +70,9 @@ __device__ __forceinline__ V3 RTv(const M3& R, V3 a) {
             R.m[0][1] * a.x + R.m[1][1] * a.y + R.m[2][1] * a.z,
             R.m[0][2] * a.x + R.m[1][2] * a.y + R.m[2][2] * a.z);
 }
-__device__ __forceinline__ V3 col(const M3& R, int j) { return v3(R.m[0][j], R.m[1][j], R.m[2][j]); }
+__device__ __forceinline__ V3 col(const M3& R, int j) {
+  return v3(at3(R.m[0], j), at3(R.m[1], j), at3(R.m[2], j));
+}
 
 // Orthonormal tangents of a unit normal (Duff et al. 2017).
 __device__ __forceinline__ void tangents(V3 n, V3& t1, V3& t2) {
@@ -92,29 +102,35 @@ struct Poly8 {
   __device__ __forceinline__ V3 get(int k) const {
     V3 r = v[0];
 #pragma unroll
-    for (int j = 1; j < 8; j++)
-      if (j == k) r = v[j];
+    for (int j = 1; j < 8; j++) r = selv(j == k, v[j], r);
     return r;
   }
   __device__ __forceinline__ void set(int k, V3 x) {
 #pragma unroll
-    for (int j = 0; j < 8; j++)
-      if (j == k) v[j] = x;
+    for (int j = 0; j < 8; j++) v[j] = selv(j == k, x, v[j]);
   }
 };
 
 // Up to four contacts held in registers (fixed slots, no indexed array).
+__device__ __forceinline__ PC selpc(bool s, const PC& a, const PC& b) {
+  PC r;
+  r.n = selv(s, a.n, b.n);
+  r.p = selv(s, a.p, b.p);
+  r.phi = s ? a.phi : b.phi;
+  r.f = s ? a.f : b.f;
+  return r;
+}
 struct Out4 {
   PC c0, c1, c2, c3;
   int n;
   __device__ __forceinline__ void push(const PC& c) {
-    if (n == 0) c0 = c;
-    else if (n == 1) c1 = c;
-    else if (n == 2) c2 = c;
-    else if (n == 3) c3 = c;
+    c0 = selpc(n == 0, c, c0);
+    c1 = selpc(n == 1, c, c1);
+    c2 = selpc(n == 2, c, c2);
+    c3 = selpc(n == 3, c, c3);
     n++;
   }
-  __device__ __forceinline__ PC get(int k) const { return k == 0 ? c0 : (k == 1 ? c1 : (k == 2 ? c2 : c3)); }
+  __device__ __forceinline__ PC get(int k) const { return selpc(k == 0, c0, selpc(k == 1, c1, selpc(k == 2, c2, c3))); }
   __device__ __forceinline__ void flip() {
     c0.n = -c0.n; c1.n = -c1.n; c2.n = -c2.n; c3.n = -c3.n;
   }
@@ -155,7 +171,7 @@ __device__ inline void sphere_box(const Geom& S, const Geom& B, float margin, Ou
     float la = comp(l, a);
     float s = la >= 0.f ? 1.f : -1.f;
     nl = unitv(a) * s;
-    setc(q, a, s * h[a]);
+    setc(q, a, s * at3(h, a));
     phi = -pa - r;
   }
   PC c;
@@ -230,6 +246,7 @@ __device__ __forceinline__ float box_d2(V3 l, const float* h) {
 // the two axes b != a.  False when empty.
 __device__ inline bool clip_face(V3 p0, V3 d, const float* h, int a, float& t0, float& t1) {
   float lo = 0.f, hi = 1.f;
+#pragma unroll
   for (int b = 0; b < 3; b++) {
     if (b == a) continue;
     float pb = comp(p0, b), db = comp(d, b);
@@ -250,9 +267,10 @@ __device__ inline bool clip_face(V3 p0, V3 d, const float* h, int a, float& t0, 
 __device__ __forceinline__ PC cap_face_contact(V3 l, int a, float s, const float* h, float r, int f) {
   PC c;
   c.n = unitv(a) * s;
-  c.phi = s * comp(l, a) - h[a] - r;
+  const float ha = at3(h, a);
+  c.phi = s * comp(l, a) - ha - r;
   V3 q = l;
-  setc(q, a, s * h[a]);
+  setc(q, a, s * ha);
   V3 wc = l - c.n * r;
   c.p = (q + wc) * 0.5f;
   c.f = f;
@@ -271,10 +289,14 @@ __device__ inline void capsule_box(const Geom& C, const Geom& B, float margin, O
   capsule_seg(C, P0, D);
   V3 p0 = RTv(B.R, P0 - B.x);
   V3 d = RTv(B.R, D);
+  // breakpoints 0, 1 and the slab crossings inside (0, 1), in register
+  // slots (unused slots hold +inf), sorted by a fixed network
   float ts[8];
-  int nt = 0;
-  ts[nt++] = 0.f;
-  ts[nt++] = 1.f;
+#pragma unroll
+  for (int k = 0; k < 8; k++) ts[k] = INFINITY;
+  ts[0] = 0.f;
+  ts[1] = 1.f;
+  int nt = 2;
 #pragma unroll
   for (int a = 0; a < 3; a++) {
     float da = comp(d, a);
@@ -282,19 +304,36 @@ __device__ inline void capsule_box(const Geom& C, const Geom& B, float margin, O
 #pragma unroll
     for (int sg = -1; sg <= 1; sg += 2) {
       float t = ((float)sg * h[a] - comp(p0, a)) / da;
-      if (t > 0.f && t < 1.f) ts[nt++] = t;
+      if (t > 0.f && t < 1.f) {
+#pragma unroll
+        for (int k = 2; k < 8; k++) ts[k] = k == nt ? t : ts[k];
+        nt++;
+      }
     }
   }
-  for (int i = 1; i < nt; i++)
-    for (int j = i; j > 0 && ts[j] < ts[j - 1]; j--) { float x = ts[j]; ts[j] = ts[j - 1]; ts[j - 1] = x; }
+  {
+    // Batcher's odd-even merge sort of 8 values: 19 compare-exchanges
+    constexpr int kNet[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6},
+                                 {0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+    for (int k = 0; k < 19; k++) {
+      const float x = ts[kNet[k][0]], y = ts[kNet[k][1]];
+      ts[kNet[k][0]] = fminf(x, y);
+      ts[kNet[k][1]] = fmaxf(x, y);
+    }
+  }
   // candidates: breakpoints first, then each piece's vertex
   float bt = ts[0];
   float bg = box_d2(p0 + d * bt, h);
-  for (int i = 1; i < nt; i++) {
+#pragma unroll
+  for (int i = 1; i < 8; i++) {
+    if (i >= nt) break;
     float g = box_d2(p0 + d * ts[i], h);
     if (g < bg || (g == bg && ts[i] < bt)) { bg = g; bt = ts[i]; }
   }
-  for (int i = 0; i + 1 < nt; i++) {
+#pragma unroll
+  for (int i = 0; i + 1 < 8; i++) {
+    if (i + 1 >= nt) break;
     float tl = ts[i], th = ts[i + 1];
     if (!(th > tl)) continue;
     float tm = 0.5f * (tl + th), num = 0.f, den = 0.f;
@@ -432,13 +471,15 @@ __device__ inline void box_box(const Geom& A, const Geom& B, float margin, Out4&
       if (m != j) { float c = dot(N, b[m]); pb = pb + b[m] * (c > 0.f ? hb[m] : -hb[m]); }
     }
     V3 w = pa - pb;
-    float bb = dot(a[i], b[j]), dd = dot(a[i], w), ee = dot(b[j], w);
+    const V3 ai = sel3(a[0], a[1], a[2], i), bj = sel3(b[0], b[1], b[2], j);
+    const float hai = at3(ha, i), hbj = at3(hb, j);
+    float bb = dot(ai, bj), dd = dot(ai, w), ee = dot(bj, w);
     float den = 1.0f - bb * bb;
     float ta = (bb * ee - dd) / den;
     float tb = ee + ta * bb;
-    ta = clampf(ta, -ha[i], ha[i]);
-    tb = clampf(tb, -hb[j], hb[j]);
-    V3 PA = pa + a[i] * ta, PB = pb + b[j] * tb;
+    ta = clampf(ta, -hai, hai);
+    tb = clampf(tb, -hbj, hbj);
+    V3 PA = pa + ai * ta, PB = pb + bj * tb;
     PC c;
     c.n = N;
     c.phi = dot(PA - PB, N);
@@ -450,26 +491,34 @@ __device__ inline void box_box(const Geom& A, const Geom& B, float margin, Out4&
   // face contact
   const bool refA = face < 3;
   const int ax = refA ? face : face - 3;
-  V3 N = (refA ? a[ax] : b[ax]) * sgf;     // from B to A
+  // reference and incident boxes' axes and half-extents, selected slot by
+  // slot and read with runtime indices through selects (no scratch)
+  V3 rc[3], ic[3];
+  float hr[3], hi[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    rc[k] = selv(refA, a[k], b[k]);
+    ic[k] = selv(refA, b[k], a[k]);
+    hr[k] = refA ? ha[k] : hb[k];
+    hi[k] = refA ? hb[k] : ha[k];
+  }
+  const V3 refx = selv(refA, A.x, B.x), incx = selv(refA, B.x, A.x);
+  const V3 rax = sel3(rc[0], rc[1], rc[2], ax);
+  V3 N = rax * sgf;                        // from B to A
   V3 nout = refA ? -N : N;                 // reference face normal, towards the incident box
-  const Geom& ref = refA ? A : B;
-  const Geom& inc = refA ? B : A;
-  const V3* rc = refA ? a : b;
-  const V3* ic = refA ? b : a;
-  const float* hr = ref.p;
-  const float* hi = inc.p;
-  int side = dot(nout, rc[ax]) > 0.f ? 0 : 1;
+  int side = dot(nout, rax) > 0.f ? 0 : 1;
   int refface = ax * 2 + side;
-  V3 cref = ref.x + nout * hr[ax];
+  V3 cref = refx + nout * at3(hr, ax);
   int j = 0;
   float best = fabsf(dot(ic[0], nout));
   float c1 = fabsf(dot(ic[1], nout)), c2 = fabsf(dot(ic[2], nout));
   if (c1 > best) { best = c1; j = 1; }
   if (c2 > best) { best = c2; j = 2; }
-  float si = dot(ic[j], nout) > 0.f ? -1.f : 1.f;
+  const V3 icj = sel3(ic[0], ic[1], ic[2], j);
+  float si = dot(icj, nout) > 0.f ? -1.f : 1.f;
   int j1 = j == 2 ? 0 : j + 1, j2 = j == 0 ? 2 : j - 1;
-  V3 fc = inc.x + ic[j] * (si * hi[j]);
-  V3 e1 = ic[j1] * hi[j1], e2 = ic[j2] * hi[j2];
+  V3 fc = incx + icj * (si * at3(hi, j));
+  V3 e1 = sel3(ic[0], ic[1], ic[2], j1) * at3(hi, j1), e2 = sel3(ic[0], ic[1], ic[2], j2) * at3(hi, j2);
   // polygons in fixed register slots: every access is an unrolled select
   Poly8 poly, tmp;
   int np = 4;
@@ -482,16 +531,17 @@ __device__ inline void box_box(const Geom& A, const Geom& B, float margin, Out4&
   for (int pl = 0; pl < 4; pl++) {
     if (np == 0) break;
     int pa = pl < 2 ? r1 : r2;
-    V3 pn = (pl & 1) ? -rc[pa] : rc[pa];
-    float off = hr[pa];
+    const V3 rpa = sel3(rc[0], rc[1], rc[2], pa);
+    V3 pn = (pl & 1) ? -rpa : rpa;
+    float off = at3(hr, pa);
     int no = 0;
     V3 prev = poly.get(np - 1);
-    float dp = dot(prev - ref.x, pn) - off;
+    float dp = dot(prev - refx, pn) - off;
 #pragma unroll
     for (int k = 0; k < 8; k++) {
       if (k < np) {
         V3 cur = poly.v[k];
-        float dc = dot(cur - ref.x, pn) - off;
+        float dc = dot(cur - refx, pn) - off;
         int cs = dc < -kClipOn ? -1 : (dc > kClipOn ? 1 : 0);
         int ps = dp < -kClipOn ? -1 : (dp > kClipOn ? 1 : 0);
         if (ps * cs < 0 && no < 8) tmp.set(no++, prev + (cur - prev) * (dp / (dp - dc)));
@@ -604,16 +654,20 @@ __device__ inline void ground_contacts(const Geom& A, float margin, Out4& out) {
     }
     if (m > 4) {
       unsigned sel = 0u;
+#pragma unroll
       for (int t = 0; t < 4; t++) {
         int bi = -1;
+        float bz = 0.f;
+#pragma unroll
         for (int k = 0; k < 8; k++) {
           if (!((keepm >> k) & 1u) || ((sel >> k) & 1u)) continue;
-          if (bi < 0 || zc[k] < zc[bi]) bi = k;
+          if (bi < 0 || zc[k] < bz) { bi = k; bz = zc[k]; }
         }
         sel |= 1u << bi;
       }
       keepm = sel;
     }
+#pragma unroll
     for (int k = 0; k < 8; k++) {
       if (!((keepm >> k) & 1u)) continue;
       PC c;
