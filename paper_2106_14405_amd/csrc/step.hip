@@ -163,6 +163,71 @@ __device__ int lds_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t
   return swapped;
 }
 
+// Stable sort of n <= kRankSortMax (key, value) pairs in LDS by rank: the
+// rank of element i is the number of elements j with (key_j, j) < (key_i, i)
+// (the order the radix sort yields).  Each thread holds E <= 8 elements in
+// register slots; the keys are read as uniform broadcasts, four at a time,
+// and compared with every slot (an instantiation per E, so the loop has no
+// branches; unique keys need only a 32-bit compare).  k0 must be 16-byte
+// aligned; the result goes to (k1, v1), which must not overlap (k0, v0) (v0
+// and v1 may be null for keys only).
+constexpr int kRankSortMax = 512;
+
+template <int E, bool kUnique>
+__device__ __forceinline__ void rank_count(const uint32_t* k0, int n, const uint32_t* mk, const uint32_t* mi,
+                                           uint32_t* rk) {
+  auto one = [&](uint32_t kj, uint32_t j) {
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      if constexpr (kUnique) rk[e] += kj < mk[e] ? 1u : 0u;
+      else rk[e] += (((u64)kj << 32) | j) < (((u64)mk[e] << 32) | mi[e]) ? 1u : 0u;
+    }
+  };
+  int j = 0;
+  for (; j + 4 <= n; j += 4) {
+    const uint4 k4 = reinterpret_cast<const uint4*>(k0)[j >> 2];
+    one(k4.x, (uint32_t)j);
+    one(k4.y, (uint32_t)j + 1u);
+    one(k4.z, (uint32_t)j + 2u);
+    one(k4.w, (uint32_t)j + 3u);
+  }
+  for (; j < n; j++) one(k0[j], (uint32_t)j);
+}
+
+template <bool kUnique, class TM>
+__device__ void lds_rank_sort(const uint32_t* k0, const uint32_t* v0, uint32_t* k1, uint32_t* v1, int n,
+                              const TM& tm) {
+  const int T = tm.T, tid = tm.tid;
+  uint32_t mk[8], mi[8], rk[8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int i = e * T + tid;
+    mk[e] = i < n ? k0[i] : 0xFFFFFFFFu;
+    mi[e] = (uint32_t)i;
+    rk[e] = 0u;
+  }
+  switch ((n + T - 1) / T) {
+    case 1: rank_count<1, kUnique>(k0, n, mk, mi, rk); break;
+    case 2: rank_count<2, kUnique>(k0, n, mk, mi, rk); break;
+    case 3: rank_count<3, kUnique>(k0, n, mk, mi, rk); break;
+    case 4: rank_count<4, kUnique>(k0, n, mk, mi, rk); break;
+    case 5: rank_count<5, kUnique>(k0, n, mk, mi, rk); break;
+    case 6: rank_count<6, kUnique>(k0, n, mk, mi, rk); break;
+    case 7: rank_count<7, kUnique>(k0, n, mk, mi, rk); break;
+    case 8: rank_count<8, kUnique>(k0, n, mk, mi, rk); break;
+    default: break;
+  }
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int i = e * T + tid;
+    if (i < n) {
+      k1[rk[e]] = mk[e];
+      if (v1) v1[rk[e]] = v0[i];
+    }
+  }
+  team_sync(tm);
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
@@ -747,8 +812,12 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   TRACE(2);
 
   // ---- a4: radix sort bodies by AABB minimum along x --------------------
-  int sw = lds_radix_sort(S.u + L.skey, S.u + L.sval, S.u + L.skey2, S.u + L.sval2, nb, 0, 4, S.u + L.hist,
-                          S.u + L.hbase, misc, tm);
+  int sw = 1;
+  if (nb <= kRankSortMax)
+    lds_rank_sort<false>(S.u + L.skey, S.u + L.sval, S.u + L.skey2, S.u + L.sval2, nb, tm);
+  else
+    sw = lds_radix_sort(S.u + L.skey, S.u + L.sval, S.u + L.skey2, S.u + L.sval2, nb, 0, 4, S.u + L.hist,
+                        S.u + L.hbase, misc, tm);
   const uint32_t* order = S.u + (sw ? L.sval2 : L.sval);
   TRACE(3);
 
@@ -821,7 +890,11 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   const int np = npairs_all < PMs ? npairs_all : PMs;
   if (npairs_all > PMs && tid == 0) misc[M_FLAGS] |= FLAG_CAPACITY;
   // keys are unique: sort keys only (values ride along in the same buffers)
-  int swp = lds_radix_sort(pk, pk, S.u + L.pk2, S.u + L.pk2, np, 0, 3, S.u + L.hist, S.u + L.hbase, misc, tm);
+  int swp = 1;
+  if (np <= kRankSortMax)
+    lds_rank_sort<true>(pk, nullptr, S.u + L.pk2, nullptr, np, tm);
+  else
+    swp = lds_radix_sort(pk, pk, S.u + L.pk2, S.u + L.pk2, np, 0, 3, S.u + L.hist, S.u + L.hbase, misc, tm);
   const uint32_t* pairs = swp ? S.u + L.pk2 : pk;
   if (P.export_on) {
     for (int p = tid; p < np; p += T) {
