@@ -35,6 +35,13 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
 }
 __device__ __forceinline__ float len2(V3 a) { return dot(a, a); }
 __device__ __forceinline__ float clampf(float x, float lo, float hi) { return x < lo ? lo : (x > hi ? hi : x); }
+// Hardware reciprocal, square root and reciprocal square root (about 1 ulp):
+// contact geometry is continuous in them, and a rounding-level difference is
+// far inside the tie band of every discrete decision.
+__device__ __forceinline__ float frcpg(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float comp(V3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
 __device__ __forceinline__ void setc(V3& a, int i, float s) {
   if (i == 0) a.x = s; else if (i == 1) a.y = s; else a.z = s;
@@ -139,8 +146,8 @@ struct Out4 {
 __device__ __forceinline__ PC sphere_sphere(V3 ca, float ra, V3 cb, float rb, int f) {
   PC c;
   V3 d = ca - cb;
-  float L = sqrtf(len2(d));
-  c.n = L < 1e-9f ? v3(0.f, 0.f, 1.f) : d * (1.0f / L);
+  float L = fsqrt(len2(d));
+  c.n = L < 1e-9f ? v3(0.f, 0.f, 1.f) : d * frcpg(L);
   c.phi = L - ra - rb;
   c.p = ((ca - c.n * ra) + (cb + c.n * rb)) * 0.5f;
   c.f = f;
@@ -159,8 +166,8 @@ __device__ inline void sphere_box(const Geom& S, const Geom& B, float margin, Ou
   if (!inside) {
     q = v3(clampf(l.x, -h[0], h[0]), clampf(l.y, -h[1], h[1]), clampf(l.z, -h[2], h[2]));
     V3 d = l - q;
-    float L = sqrtf(len2(d));
-    nl = d * (1.0f / L);
+    float L = fsqrt(len2(d));
+    nl = d * frcpg(L);
     phi = L - r;
   } else {
     float pen0 = h[0] - fabsf(l.x), pen1 = h[1] - fabsf(l.y), pen2 = h[2] - fabsf(l.z);
@@ -193,7 +200,7 @@ __device__ __forceinline__ void capsule_seg(const Geom& C, V3& p0, V3& d) {
 __device__ inline void sphere_capsule(const Geom& S, const Geom& C, float margin, Out4& out) {
   V3 p0, d;
   capsule_seg(C, p0, d);
-  float t = clampf(dot(S.x - p0, d) / len2(d), 0.f, 1.f);
+  float t = clampf(fdiv(dot(S.x - p0, d), len2(d)), 0.f, 1.f);
   PC c = sphere_sphere(S.x, S.p[0], p0 + d * t, C.p[0], 0);
   if (c.phi <= margin) out.push(c);
 }
@@ -208,15 +215,15 @@ __device__ inline void capsule_capsule(const Geom& A, const Geom& B, float margi
   float aa = len2(da), ee = len2(db);
   float cr2 = len2(cross(da, db));
   if (cr2 <= kCapParallel * aa * ee) {
-    float s0 = dot(pb - pa, da) / aa;
-    float s1 = dot((pb + db) - pa, da) / aa;
+    float s0 = fdiv(dot(pb - pa, da), aa);
+    float s1 = fdiv(dot((pb + db) - pa, da), aa);
     float lo = fmaxf(0.f, fminf(s0, s1)), hi = fminf(1.f, fmaxf(s0, s1));
     if (lo <= hi) {
       for (int k = 0; k < 2; k++) {
         if (k == 1 && !(hi > lo)) break;
         float s = k == 0 ? lo : hi;
         V3 P = pa + da * s;
-        float t = clampf(dot(P - pb, db) / ee, 0.f, 1.f);
+        float t = clampf(fdiv(dot(P - pb, db), ee), 0.f, 1.f);
         PC c = sphere_sphere(P, ra, pb + db * t, rb, k);
         if (c.phi <= margin) out.push(c);
       }
@@ -226,10 +233,10 @@ __device__ inline void capsule_capsule(const Geom& A, const Geom& B, float margi
   V3 r = pa - pb;
   float b = dot(da, db), c = dot(da, r), f = dot(db, r);
   float den = aa * ee - b * b;
-  float s = den != 0.f ? clampf((b * f - c * ee) / den, 0.f, 1.f) : 0.f;
-  float t = (b * s + f) / ee;
-  if (t < 0.f) { t = 0.f; s = clampf(-c / aa, 0.f, 1.f); }
-  else if (t > 1.f) { t = 1.f; s = clampf((b - c) / aa, 0.f, 1.f); }
+  float s = den != 0.f ? clampf(fdiv(b * f - c * ee, den), 0.f, 1.f) : 0.f;
+  float t = fdiv(b * s + f, ee);
+  if (t < 0.f) { t = 0.f; s = clampf(fdiv(-c, aa), 0.f, 1.f); }
+  else if (t > 1.f) { t = 1.f; s = clampf(fdiv(b - c, aa), 0.f, 1.f); }
   PC cc = sphere_sphere(pa + da * s, ra, pb + db * t, rb, 0);
   if (cc.phi <= margin) out.push(cc);
 }
@@ -254,7 +261,8 @@ __device__ inline bool clip_face(V3 p0, V3 d, const float* h, int a, float& t0, 
       if (fabsf(pb) > h[b]) return false;
       continue;
     }
-    float ta = (-h[b] - pb) / db, tb = (h[b] - pb) / db;
+    const float idb = frcpg(db);
+    float ta = (-h[b] - pb) * idb, tb = (h[b] - pb) * idb;
     if (ta > tb) { float x = ta; ta = tb; tb = x; }
     if (ta > lo) lo = ta;
     if (tb < hi) hi = tb;
@@ -303,7 +311,7 @@ __device__ inline void capsule_box(const Geom& C, const Geom& B, float margin, O
     if (da == 0.f) continue;
 #pragma unroll
     for (int sg = -1; sg <= 1; sg += 2) {
-      float t = ((float)sg * h[a] - comp(p0, a)) / da;
+      float t = fdiv((float)sg * h[a] - comp(p0, a), da);
       if (t > 0.f && t < 1.f) {
 #pragma unroll
         for (int k = 2; k < 8; k++) ts[k] = k == nt ? t : ts[k];
@@ -346,7 +354,7 @@ __device__ inline void capsule_box(const Geom& C, const Geom& B, float margin, O
       num += comp(d, a) * (ca - comp(p0, a));
       den += comp(d, a) * comp(d, a);
     }
-    float tv = den > 0.f ? clampf(num / den, tl, th) : tl;
+    float tv = den > 0.f ? clampf(fdiv(num, den), tl, th) : tl;
     float g = box_d2(p0 + d * tv, h);
     if (g < bg || (g == bg && tv < bt)) { bg = g; bt = tv; }
   }
@@ -354,8 +362,8 @@ __device__ inline void capsule_box(const Geom& C, const Geom& B, float margin, O
   Out4 loc;
   loc.n = 0;
   if (bg > 0.f) {
-    float dist = sqrtf(bg);
-    float dl = sqrtf(len2(d));
+    float dist = fsqrt(bg);
+    float dl = fsqrt(len2(d));
     int ncl = 0, a = -1;
 #pragma unroll
     for (int k = 0; k < 3; k++)
@@ -373,7 +381,7 @@ __device__ inline void capsule_box(const Geom& C, const Geom& B, float margin, O
     if (!done) {
       V3 q = v3(clampf(l.x, -h[0], h[0]), clampf(l.y, -h[1], h[1]), clampf(l.z, -h[2], h[2]));
       PC c;
-      c.n = (l - q) * (1.0f / dist);
+      c.n = (l - q) * frcpg(dist);
       c.phi = dist - r;
       c.p = (q + (l - c.n * r)) * 0.5f;
       c.f = 2;
@@ -444,7 +452,7 @@ __device__ inline void box_box(const Geom& A, const Geom& B, float margin, Out4&
       V3 c = cross(a[(k - 6) / 3], b[(k - 6) % 3]);
       float L2 = len2(c);
       if (L2 < kEdgeDegenerate) continue;
-      u = c * (1.0f / sqrtf(L2));
+      u = c * frsq(L2);
       ra = ha[0] * fabsf(dot(a[0], u)) + ha[1] * fabsf(dot(a[1], u)) + ha[2] * fabsf(dot(a[2], u));
       rb = hb[0] * fabsf(dot(b[0], u)) + hb[1] * fabsf(dot(b[1], u)) + hb[2] * fabsf(dot(b[2], u));
     }
@@ -475,7 +483,7 @@ __device__ inline void box_box(const Geom& A, const Geom& B, float margin, Out4&
     const float hai = at3(ha, i), hbj = at3(hb, j);
     float bb = dot(ai, bj), dd = dot(ai, w), ee = dot(bj, w);
     float den = 1.0f - bb * bb;
-    float ta = (bb * ee - dd) / den;
+    float ta = fdiv(bb * ee - dd, den);
     float tb = ee + ta * bb;
     ta = clampf(ta, -hai, hai);
     tb = clampf(tb, -hbj, hbj);
@@ -544,7 +552,7 @@ __device__ inline void box_box(const Geom& A, const Geom& B, float margin, Out4&
         float dc = dot(cur - refx, pn) - off;
         int cs = dc < -kClipOn ? -1 : (dc > kClipOn ? 1 : 0);
         int ps = dp < -kClipOn ? -1 : (dp > kClipOn ? 1 : 0);
-        if (ps * cs < 0 && no < 8) tmp.set(no++, prev + (cur - prev) * (dp / (dp - dc)));
+        if (ps * cs < 0 && no < 8) tmp.set(no++, prev + (cur - prev) * fdiv(dp, dp - dc));
         if (cs <= 0 && no < 8) tmp.set(no++, cur);
         prev = cur;
         dp = dc;
@@ -575,7 +583,7 @@ __device__ inline void box_box(const Geom& A, const Geom& B, float margin, Out4&
 #pragma unroll
     for (int k = 0; k < 8; k++) {
       if (k >= np || !((keepm >> k) & 1u) || ((used >> k) & 1u)) continue;
-      float dd = sqrtf(len2(poly.v[k] - p1));
+      float dd = fsqrt(len2(poly.v[k] - p1));
       if (dd > bd) { bd = dd; i2 = k; }
     }
     used |= 1u << i2;
@@ -586,7 +594,7 @@ __device__ inline void box_box(const Geom& A, const Geom& B, float margin, Out4&
 #pragma unroll
     for (int k = 0; k < 8; k++) {
       if (k >= np || !((keepm >> k) & 1u) || ((used >> k) & 1u)) continue;
-      float ar = sqrtf(len2(cross(e12, poly.v[k] - p1)));
+      float ar = fsqrt(len2(cross(e12, poly.v[k] - p1)));
       if (ar > ba) { ba = ar; i3 = k; }
     }
     used |= 1u << i3;
@@ -597,8 +605,8 @@ __device__ inline void box_box(const Geom& A, const Geom& B, float margin, Out4&
 #pragma unroll
     for (int k = 0; k < 8; k++) {
       if (k >= np || !((keepm >> k) & 1u) || ((used >> k) & 1u)) continue;
-      float sc = sqrtf(len2(cross(e12, poly.v[k] - p1))) + sqrtf(len2(cross(e23, poly.v[k] - p2))) +
-                 sqrtf(len2(cross(e31, poly.v[k] - p3)));
+      float sc = fsqrt(len2(cross(e12, poly.v[k] - p1))) + fsqrt(len2(cross(e23, poly.v[k] - p2))) +
+                 fsqrt(len2(cross(e31, poly.v[k] - p3)));
       if (sc > bq) { bq = sc; i4 = k; }
     }
     used |= 1u << i4;
