@@ -996,11 +996,21 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       }
     }
     team_sync(tm);
-    // compaction in canonical pair order: prefix of the counts by ballots
+    // compaction in canonical pair order: prefix of the counts by ballots;
+    // a tile's staged contacts are read first, so that the loads overlap the
+    // prefix and its synchronisation
     uint32_t base = 0;
     for (int t0 = 0; t0 < np; t0 += T) {
       const int p = t0 + tid;
       const int cnt = p < np ? (int)ncnt[p] : 0;
+      float4 sv[8];
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) {
+        if (kk < cnt) {
+          sv[2 * kk] = stage[8 * p + 2 * kk];
+          sv[2 * kk + 1] = stage[8 * p + 2 * kk + 1];
+        }
+      }
       u64 b0m = __ballot(cnt & 1), b1m = __ballot((cnt >> 1) & 1), b2m = __ballot((cnt >> 2) & 1);
       uint32_t pre = lanes_below(b0m) + 2u * lanes_below(b1m) + 4u * lanes_below(b2m);
       uint32_t wtot = (uint32_t)(__popcll(b0m) + 2 * __popcll(b1m) + 4 * __popcll(b2m));
@@ -1017,10 +1027,11 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
         const uint32_t k = pairs[p];
         const uint32_t a = k >> 11, bb = k & 2047u;
         const uint32_t bkey = bb == 2047u ? kGroundKey : bb;
-        for (int kk = 0; kk < cnt; kk++) {
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++) {
           const uint32_t q = off + (uint32_t)kk;
-          if ((int)q < CMs) {
-            const float4 s0 = stage[8 * p + 2 * kk], s1 = stage[8 * p + 2 * kk + 1];
+          if (kk < cnt && (int)q < CMs) {
+            const float4 s0 = sv[2 * kk], s1 = sv[2 * kk + 1];
             S.u[L.ckey + q] = (a << 20) | (bkey << 8) | (uint32_t)__float_as_int(s1.w);
             raw[2 * q] = s0;
             raw[2 * q + 1] = make_float4(s1.x, s1.y, s1.z, 0.f);
