@@ -1220,15 +1220,56 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   if (kLearned)
     for (int i = tid; i < (nc + 31) / 32; i += T) S.u[L.fresh + i] = 0u;
   team_sync(tm);
+  // previous-impulse slot of every contact by binary search of the sorted
+  // previous keys, in a pass of its own so that the setup loop can load the
+  // impulses together with its other inputs (rank is free after the colour
+  // sort)
+  int32_t* hits = reinterpret_cast<int32_t*>(S.u + L.rank);
+  for (int i = tid; i < nc; i += T) {
+    const uint32_t key = ckeys[perm[i]];
+    int lo = 0, hi = nprev - 1, hit = -1;
+    while (lo <= hi) {
+      int mid = (lo + hi) >> 1;
+      uint32_t km = S.u[L.prevk + mid];
+      if (km == key) { hit = mid; break; }
+      if (km < key) lo = mid + 1; else hi = mid - 1;
+    }
+    hits[i] = hit;
+  }
+  team_sync(tm);
   const float gmag = sqrtf(P.gx * P.gx + P.gy * P.gy + P.gz * P.gz);
+  // The global inputs of a contact (narrowphase output, previous impulses)
+  // are loaded one tile ahead of its setup.
+  struct SetupIn {
+    float4 r0, r1, pl;
+    int hit;
+  };
+  auto fetch = [&](int i) {
+    SetupIn f;
+    const int q = (int)perm[i];
+    f.r0 = raw[2 * q];
+    f.r1 = raw[2 * q + 1];
+    f.hit = hits[i];
+    f.pl = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (f.hit >= 0) {
+      const long o = (long)s * CM + f.hit;
+      f.pl = make_float4(P.prev_lam[o], P.prev_lam[P.scene_cm + o], P.prev_lam[2 * P.scene_cm + o],
+                         P.prev_lam[3 * P.scene_cm + o]);
+    }
+    return f;
+  };
   // Wave-uniform trip count: the network's matrix-core calls need all 64
   // lanes of a wave; lanes past the end redo the last contact, store nothing.
   const int lane = tid & 63;
+  SetupIn nxt;
+  if (tid - lane < nc) nxt = fetch(tid < nc ? tid : nc - 1);
   for (int ib = tid - lane; ib < nc; ib += T) {
     const bool live = ib + lane < nc;
     const int i = live ? ib + lane : nc - 1;
     const int q = (int)perm[i];
-    float4 r0 = raw[2 * q], r1 = raw[2 * q + 1];
+    const SetupIn in = nxt;
+    if (ib + T < nc) nxt = fetch(ib + T + lane < nc ? ib + T + lane : nc - 1);
+    float4 r0 = in.r0, r1 = in.r1;
     float phi = r0.w;
     V3 n = xyz(r0), p = xyz(r1);
     uint32_t key = ckeys[q];
@@ -1282,19 +1323,13 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     float u0 = dot(n, vr);
     float bias = phi > 0.f ? -phi / dt : P.baumgarte / dt * fmaxf(0.f, -phi - P.slop);
     if (e > 0.f && u0 < -P.rest_thresh) bias = fmaxf(bias, -e * u0);
-    // previous impulse by binary search of the sorted previous keys
-    int lo = 0, hi = nprev - 1, hit = -1;
-    while (lo <= hi) {
-      int mid = (lo + hi) >> 1;
-      uint32_t km = S.u[L.prevk + mid];
-      if (km == key) { hit = mid; break; }
-      if (km < key) lo = mid + 1; else hi = mid - 1;
-    }
+    // previous impulse (normal, and the friction impulse re-projected on the
+    // new tangents)
+    const int hit = in.hit;
     float lp0 = 0.f, lp1 = 0.f, lp2 = 0.f;
     if (hit >= 0) {
-      long o = (long)s * CM + hit;
-      V3 F = v3(P.prev_lam[P.scene_cm + o], P.prev_lam[2 * P.scene_cm + o], P.prev_lam[3 * P.scene_cm + o]);
-      lp0 = P.prev_lam[o];
+      const V3 F = v3(in.pl.y, in.pl.z, in.pl.w);
+      lp0 = in.pl.x;
       lp1 = dot(F, t1);
       lp2 = dot(F, t2);
     }
