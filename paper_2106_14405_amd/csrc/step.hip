@@ -828,13 +828,14 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   // contiguous runs (a long body's run no longer holds up the team).
   uint32_t* pk = S.u + L.pk;
   {
-    uint32_t* run = S.u + (sw ? L.skey : L.skey2);  // free sort buffer: [nb] run starts
+    const uint32_t* skeys = S.u + (sw ? L.skey2 : L.skey);  // sorted orderable minimum x
+    uint32_t* run = S.u + (sw ? L.skey : L.skey2);          // free sort buffer: [nb] run starts
     for (int p = tid; p < nb; p += T) {
-      const float hx = ld4(S.f + L.hi, (int)order[p]).x;
+      const uint32_t hx = orderable(ld4(S.f + L.hi, (int)order[p]).x);
       int lo = p + 1, hi = nb;  // first position whose minimum x exceeds hx
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (ld4(S.f + L.lo, (int)order[mid]).x > hx) hi = mid;
+        if (skeys[mid] > hx) hi = mid;
         else lo = mid + 1;
       }
       run[p] = (uint32_t)(lo - p - 1);
