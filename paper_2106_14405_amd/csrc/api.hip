@@ -50,7 +50,7 @@ int fail(int code, const std::string& msg) {
 struct Layout {
   size_t off_body_offset, off_shape, off_motion, off_prm, off_inv_mass, off_inv_inertia, off_friction,
       off_restitution, off_pose, off_vel, off_theta, off_arm_base, off_scene_list;
-  size_t off_ckey[2], off_clam[2], off_ccount[2];
+  size_t off_ckey[2], off_clam[2], off_ccount[2], off_ccol[2];
   size_t off_x_pair, off_x_npairs, off_x_normal, off_x_point, off_x_phi, off_x_lambda, off_x_colour, off_x_feat;
   size_t off_raw, off_crec;
   size_t off_st[7];
@@ -82,6 +82,7 @@ Layout make_layout(long S, long N, long PM, long CM) {
     L.off_ckey[k] = take(4 * S * CM);
     L.off_clam[k] = take(4 * 4 * S * CM);
     L.off_ccount[k] = take(4 * S);
+    L.off_ccol[k] = take(S * CM);  // colour hints: not state (any content gives the same step)
   }
   L.off_x_pair = take(4 * S * PM);
   L.off_x_npairs = 0;  // stats pairs array doubles as the pair count
@@ -183,6 +184,8 @@ rbs::StepParams params(sim_handle* h) {
   P.cur_key = at<uint32_t>(h, L.off_ckey[wr]);
   P.cur_lam = at<float>(h, L.off_clam[wr]);
   P.cur_count = at<int32_t>(h, L.off_ccount[wr]);
+  P.prev_col = at<uint8_t>(h, L.off_ccol[rd]);
+  P.cur_col = at<uint8_t>(h, L.off_ccol[wr]);
   P.export_on = h->export_on;
   P.x_pair = at<uint32_t>(h, L.off_x_pair);
   P.x_normal = at<float>(h, L.off_x_normal);

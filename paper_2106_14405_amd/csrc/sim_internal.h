@@ -62,6 +62,8 @@ struct StepParams {
   const uint32_t* prev_key; // [S*CM]
   const float* prev_lam;    // [4][S*CM]
   const int32_t* prev_count;// [S]
+  const uint8_t* prev_col;  // [S*CM] colours of the previous step's contacts (a hint only)
+  uint8_t* cur_col;
   uint32_t* cur_key;
   float* cur_lam;
   int32_t* cur_count;

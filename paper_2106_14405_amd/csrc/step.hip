@@ -1053,13 +1053,37 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   const int nc = nc_all < CMs ? nc_all : CMs;
 
   // ---- a9: colouring -----------------------------------------------------
-  // per-body lists of contacts (dynamic bodies only), canonical order
   uint32_t* deg = S.u + L.deg;
   uint32_t* lstart = S.u + L.lstart;
   uint32_t* list = S.u + L.list;
   uint32_t* rank = S.u + L.rank;
   uint32_t* colour = S.u + L.colour;
   const uint32_t* ckeys = S.u + L.ckey;
+  // Starting colours: the colour a contact had in the previous step (found
+  // by its key among the sorted previous keys, copied for the search into
+  // the scratch that the lists use next), else 0.  The colouring's fixed
+  // point does not depend on where the iteration starts; a start close to
+  // it only takes fewer rounds.
+  {
+    const int np0 = P.prev_count ? (P.prev_count[s] < CMs ? P.prev_count[s] : CMs) : 0;
+    uint32_t* pkeys = S.u + L.deg;
+    for (int i = tid; i < np0; i += T) pkeys[i] = P.prev_key[(long)s * CM + i];
+    team_sync(tm);
+    for (int q = tid; q < nc; q += T) {
+      const uint32_t key = ckeys[q];
+      int lo = 0, hi = np0 - 1, hit = -1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const uint32_t km = pkeys[mid];
+        if (km == key) { hit = mid; break; }
+        if (km < key) lo = mid + 1; else hi = mid - 1;
+      }
+      const uint32_t g = hit >= 0 ? (uint32_t)P.prev_col[(long)s * CM + hit] : 0u;
+      colour[q] = g < (uint32_t)kMaxColours ? g : 0u;
+    }
+    team_sync(tm);
+  }
+  // per-body lists of contacts (dynamic bodies only), canonical order
   for (int i = tid; i <= nb; i += T) deg[i] = 0u;
   team_sync(tm);
   for (int q = tid; q < nc; q += T) {
@@ -1081,7 +1105,6 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
     if (is_dyn_meta(body_meta(L, S, a))) list[lstart[a] + atomicAdd(&deg[a], 1u)] = (uint32_t)q;
     if (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) list[lstart[b] + atomicAdd(&deg[b], 1u)] = (uint32_t)q;
-    colour[q] = 0u;
     rank[q] = 0u;
   }
   team_sync(tm);
@@ -1111,12 +1134,18 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   // its unique solution is sequential first fit in canonical order.  The
   // contacts are taken a team's width at a time in canonical order: earlier
   // chunks are final, so each chunk iterates to its own fixed point, which
-  // takes as many rounds as its longest dependency chain.  From here on the
+  // takes at most as many rounds as its longest dependency chain (one when
+  // the starting colours are already the solution).  From here on the
   // per-body lists hold colours: slot lstart[i] + k is the colour of body
   // i's k-th contact, written by that contact, so that a contact reads its
   // predecessors' colours as one contiguous run per body.
-  const int ltot = (int)lstart[nb];
-  for (int x = tid; x < ltot; x += T) list[x] = 0u;
+  for (int q = tid; q < nc; q += T) {
+    const uint32_t key = ckeys[q];
+    const int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
+    const uint32_t rk = rank[q];
+    if (is_dyn_meta(body_meta(L, S, a))) list[lstart[a] + (rk & 0xFFFFu)] = colour[q];
+    if (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) list[lstart[b] + (rk >> 16)] = colour[q];
+  }
   team_sync(tm);
   for (int c0 = 0; c0 < nc; c0 += T) {
     const int q = c0 + tid;
@@ -1523,6 +1552,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     V3 F = t1 * lam.y + t2 * lam.z;
     long o = (long)s * CM + q;
     P.cur_key[o] = key;
+    P.cur_col[o] = (uint8_t)colour[q];
     P.cur_lam[o] = lam.x;
     P.cur_lam[P.scene_cm + o] = F.x;
     P.cur_lam[2 * P.scene_cm + o] = F.y;
