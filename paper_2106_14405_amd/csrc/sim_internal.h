@@ -120,14 +120,16 @@ struct QueueParams {
 //       contact i is new, i.e. started from the network
 // The per-contact solver constants live in global memory (StepParams::crec).
 // The scratch region is reused phase by phase: broadphase (pairs, AABBs,
-// body sort); colouring (colours, per-body lists); setup (previous keys);
-// solver (saved velocities and start objective terms of a learned start,
-// Jacobi snapshot and increments); outputs (arm force partial sums).
+// body sort); colouring (previous keys for the starting colours, colours,
+// per-body lists); setup (previous-impulse slots); solver (saved
+// velocities and start objective terms of a learned start, Jacobi snapshot
+// and increments); outputs (arm force partial sums).  Until the setup
+// writes it, lam holds each contact's previous-impulse slot.
 struct LdsLayout {
   int geo, dyn, dyn2, ckey, lam, perm, fresh, misc, hist, hbase;
   int scr;
   int pk, pk2, lo, hi, skey, sval, skey2, sval2, nperm, ncnt;
-  int colour, deg, lstart, list, rank, prevk, cv0, ck1;
+  int colour, deg, lstart, list, rank, cv0, ck1;
   int vsave, fval, snap, dl, force;
   int total;  // words
 };
@@ -187,7 +189,6 @@ inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int wave
   int cend = p;
   L.cv0 = L.list;       // colour sort after the colouring rounds
   L.ck1 = L.list + CM;
-  L.prevk = L.list;     // setup runs after the colour sort
   int q = after_deg;    // solver and outputs: lists are dead, deg and colour live on
   auto tq = [&](int words) { int r = q; q += (words + 3) & ~3; return r; };
   L.vsave = (warm == WARM_LEARNED) ? tq(8 * NB) : -1;

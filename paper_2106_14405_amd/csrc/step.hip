@@ -1080,6 +1080,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       }
       const uint32_t g = hit >= 0 ? (uint32_t)P.prev_col[(long)s * CM + hit] : 0u;
       colour[q] = g < (uint32_t)kMaxColours ? g : 0u;
+      S.u[L.lam + q] = (uint32_t)hit;  // the setup's previous-impulse slot (lam is free until then)
     }
     team_sync(tm);
   }
@@ -1245,27 +1246,14 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   TRACE(9);
 
   // ---- a7/a10: previous impulses, constraint setup (colour-major) ------
-  const int nprev = P.prev_count ? (P.prev_count[s] < CMs ? P.prev_count[s] : CMs) : 0;
-  for (int i = tid; i < nprev; i += T) S.u[L.prevk + i] = P.prev_key[(long)s * CM + i];
+  // previous-impulse slot of every contact (found with the starting colours
+  // and parked in the impulse array), colour-major, so that the setup loop
+  // can load the impulses together with its other inputs (rank is free
+  // after the colour sort)
+  int32_t* hits = reinterpret_cast<int32_t*>(S.u + L.rank);
+  for (int i = tid; i < nc; i += T) hits[i] = (int32_t)S.u[L.lam + perm[i]];
   if (kLearned)
     for (int i = tid; i < (nc + 31) / 32; i += T) S.u[L.fresh + i] = 0u;
-  team_sync(tm);
-  // previous-impulse slot of every contact by binary search of the sorted
-  // previous keys, in a pass of its own so that the setup loop can load the
-  // impulses together with its other inputs (rank is free after the colour
-  // sort)
-  int32_t* hits = reinterpret_cast<int32_t*>(S.u + L.rank);
-  for (int i = tid; i < nc; i += T) {
-    const uint32_t key = ckeys[perm[i]];
-    int lo = 0, hi = nprev - 1, hit = -1;
-    while (lo <= hi) {
-      int mid = (lo + hi) >> 1;
-      uint32_t km = S.u[L.prevk + mid];
-      if (km == key) { hit = mid; break; }
-      if (km < key) lo = mid + 1; else hi = mid - 1;
-    }
-    hits[i] = hit;
-  }
   team_sync(tm);
   const float gmag = sqrtf(P.gx * P.gx + P.gy * P.gy + P.gz * P.gz);
   // The global inputs of a contact (narrowphase output, previous impulses)
