@@ -1060,14 +1060,18 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   uint32_t* colour = S.u + L.colour;
   const uint32_t* ckeys = S.u + L.ckey;
   // Starting colours: the colour a contact had in the previous step (found
-  // by its key among the sorted previous keys, copied for the search into
-  // the scratch that the lists use next), else 0.  The colouring's fixed
+  // by its key among the sorted previous keys; keys and colours are copied
+  // for the search into the scratch that the lists use next), else 0.  The colouring's fixed
   // point does not depend on where the iteration starts; a start close to
   // it only takes fewer rounds.
   {
     const int np0 = P.prev_count ? (P.prev_count[s] < CMs ? P.prev_count[s] : CMs) : 0;
     uint32_t* pkeys = S.u + L.deg;
-    for (int i = tid; i < np0; i += T) pkeys[i] = P.prev_key[(long)s * CM + i];
+    uint8_t* pcols = reinterpret_cast<uint8_t*>(S.u + L.deg + CM);  // [CM] bytes after the keys
+    for (int i = tid; i < np0; i += T) {
+      pkeys[i] = P.prev_key[(long)s * CM + i];
+      pcols[i] = P.prev_col[(long)s * CM + i];
+    }
     team_sync(tm);
     for (int q = tid; q < nc; q += T) {
       const uint32_t key = ckeys[q];
@@ -1078,7 +1082,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
         if (km == key) { hit = mid; break; }
         if (km < key) lo = mid + 1; else hi = mid - 1;
       }
-      const uint32_t g = hit >= 0 ? (uint32_t)P.prev_col[(long)s * CM + hit] : 0u;
+      const uint32_t g = hit >= 0 ? (uint32_t)pcols[hit] : 0u;
       colour[q] = g < (uint32_t)kMaxColours ? g : 0u;
       S.u[L.lam + q] = (uint32_t)hit;  // the setup's previous-impulse slot (lam is free until then)
     }

@@ -1,6 +1,9 @@
 """Checkpoint and resume through the C ABI: a saved state restored into the
 same handle (or a fresh one of the same batch layout) continues bit for bit
-as the run it was saved from; a blob of another layout is refused."""
+as the run it was saved from; a blob of another layout is refused.  The
+colouring's starting colours (the previous step's colours, kept beside the
+contact cache) are not part of the state and differ between these runs: the
+results must not depend on them."""
 import numpy as np
 import pytest
 
