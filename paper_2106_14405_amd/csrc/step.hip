@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "geom.h"
 #include "mlp_mfma.h"
 #include "sim_internal.h"
@@ -533,49 +535,58 @@ __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int nco
   const int lane = tid & 63;
   const int cs_lo = (int)cstart[lane], cs_hi = (int)cstart[64 + lane];
   const int cs_end = __builtin_amdgcn_readfirstlane((int)cstart[kMaxColours]);
-  auto cst = [&](int c) -> int {
-    return c < 64 ? __builtin_amdgcn_readlane(cs_lo, c)
-                  : (c < 128 ? __builtin_amdgcn_readlane(cs_hi, c - 64) : cs_end);
+  // The sweeps, instantiated twice: with fewer than 64 colours every colour
+  // start is one readlane of cs_lo, without the branches of the general
+  // lookup in the loop.
+  auto sweep_all = [&](auto small) {
+    constexpr bool kSmall = decltype(small)::value;
+    auto cst = [&](int c) -> int {
+      if constexpr (kSmall) return __builtin_amdgcn_readlane(cs_lo, c);
+      else return c < 64 ? __builtin_amdgcn_readlane(cs_lo, c)
+                         : (c < 128 ? __builtin_amdgcn_readlane(cs_hi, c - 64) : cs_end);
+    };
+    const int last = cst(ncol) - 1;  // >= 0: ncol > 0 implies contacts
+    int i = cst(0) + tid;
+    bool has = i < cst(1);
+    float r = 0.f;
+    // One colour batch: load the next batch's records (unconditionally, the
+    // index clamped to a valid record, so that the loads stay in flight),
+    // solve this batch, synchronise.  Two record buffers alternate between
+    // batches so that no registers are copied between them.
+    auto batch = [&](int c, const Rec& cur, Rec& nxt) {
+      const int e = cst(c + 1);
+      // next batch: colour c + 1, or colour 0 of the next sweep
+      const int cn = c + 1 < ncol ? c + 1 : 0;
+      const int inext = cst(cn) + tid;
+      const bool hnext = inext < cst(cn + 1);
+      nxt = load_rec(rec, min(inext, last));
+      if (has) r = fmaxf(r, pgs_update(L, S, cur, i));
+      for (int i2 = i + T; i2 < e; i2 += T) r = fmaxf(r, pgs_update(L, S, load_rec(rec, i2), i2));
+      colour_sync(tm);
+      has = hnext;
+      i = inext;
+    };
+    Rec ra = load_rec(rec, min(i, last)), rb;
+    for (int it = 0; it < iters; it++) {
+      r = 0.f;
+      int c = 0;
+      for (; c + 1 < ncol; c += 2) {
+        batch(c, ra, rb);
+        batch(c + 1, rb, ra);
+      }
+      if (c < ncol) {  // odd colour count: colour 0 of the next sweep is in rb
+        batch(c, ra, rb);
+        ra = rb;
+      }
+      sweeps++;
+      if (tol > 0.f || it == iters - 1) {
+        res = block_max(r, misc, tm);
+        if (tol > 0.f && res <= tol) break;
+      }
+    }
   };
-  const int last = cst(ncol) - 1;  // >= 0: ncol > 0 implies contacts
-  int i = cst(0) + tid;
-  bool has = i < cst(1);
-  float r = 0.f;
-  // One colour batch: load the next batch's records (unconditionally, the
-  // index clamped to a valid record, so that the loads stay in flight),
-  // solve this batch, synchronise.  Two record buffers alternate between
-  // batches so that no registers are copied between them.
-  auto batch = [&](int c, const Rec& cur, Rec& nxt) {
-    const int e = cst(c + 1);
-    // next batch: colour c + 1, or colour 0 of the next sweep
-    const int cn = c + 1 < ncol ? c + 1 : 0;
-    const int inext = cst(cn) + tid;
-    const bool hnext = inext < cst(cn + 1);
-    nxt = load_rec(rec, min(inext, last));
-    if (has) r = fmaxf(r, pgs_update(L, S, cur, i));
-    for (int i2 = i + T; i2 < e; i2 += T) r = fmaxf(r, pgs_update(L, S, load_rec(rec, i2), i2));
-    colour_sync(tm);
-    has = hnext;
-    i = inext;
-  };
-  Rec ra = load_rec(rec, min(i, last)), rb;
-  for (int it = 0; it < iters; it++) {
-    r = 0.f;
-    int c = 0;
-    for (; c + 1 < ncol; c += 2) {
-      batch(c, ra, rb);
-      batch(c + 1, rb, ra);
-    }
-    if (c < ncol) {  // odd colour count: colour 0 of the next sweep is in rb
-      batch(c, ra, rb);
-      ra = rb;
-    }
-    sweeps++;
-    if (tol > 0.f || it == iters - 1) {
-      res = block_max(r, misc, tm);
-      if (tol > 0.f && res <= tol) break;
-    }
-  }
+  if (ncol < 64) sweep_all(std::true_type{});
+  else sweep_all(std::false_type{});
   *sweeps_out = sweeps;
   *res_out = res;
 }
