@@ -72,13 +72,20 @@ __device__ __forceinline__ uint32_t orderable(float f) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// Cross-lane steps by data-parallel primitives (DPP) instead of LDS
+// permutes: shifts right by 1, 2, 4 and 8 lanes inside each row of 16
+// (lanes with no source read 0), then the last lane of a row broadcast to
+// the next row (rows 1 and 3) and lane 31 to rows 2 and 3.
+#define RBS_DPP(v, ctrl, rows) __builtin_amdgcn_update_dpp(0u, (v), (ctrl), (rows), 0xf, false)
+
+// Inclusive prefix sum over the 64 lanes of a wave.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t t = __shfl_up(v, o);
-    if (lane >= o) v += t;
-  }
+  v += RBS_DPP(v, 0x111, 0xf);  // row_shr:1
+  v += RBS_DPP(v, 0x112, 0xf);  // row_shr:2
+  v += RBS_DPP(v, 0x114, 0xf);  // row_shr:4
+  v += RBS_DPP(v, 0x118, 0xf);  // row_shr:8
+  v += RBS_DPP(v, 0x142, 0xa);  // row_bcast:15
+  v += RBS_DPP(v, 0x143, 0xc);  // row_bcast:31
   return v;
 }
 
@@ -230,10 +237,17 @@ __device__ void lds_rank_sort(const uint32_t* k0, const uint32_t* v0, uint32_t* 
   team_sync(tm);
 }
 
+// Maximum over the wave of non-negative floats (their bit patterns order
+// like the values; absent lanes read 0), in every lane.
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
+  uint32_t u = __float_as_uint(v);
+  u = max(u, RBS_DPP(u, 0x111, 0xf));
+  u = max(u, RBS_DPP(u, 0x112, 0xf));
+  u = max(u, RBS_DPP(u, 0x114, 0xf));
+  u = max(u, RBS_DPP(u, 0x118, 0xf));
+  u = max(u, RBS_DPP(u, 0x142, 0xa));
+  u = max(u, RBS_DPP(u, 0x143, 0xc));
+  return __uint_as_float(__builtin_amdgcn_readlane(u, 63));
 }
 
 // Block-wide maximum of non-negative floats (one value per thread).
