@@ -99,6 +99,19 @@ def test_drop_batch_many_scenes(torch_cuda):
     assert rep["scenes"] - rep["flagged"] >= 8
 
 
+def test_large_scene_parity(torch_cuda):
+    """Scenes above 512 bodies sort their bodies by LSD radix passes (smaller
+    ones rank by counting): two 520-body drop scenes, one 256-thread
+    workgroup each, one step from oracle-settled states."""
+    b = S.batch_drop(2, seed0=900, n_spheres=260, n_boxes=260)
+    assert b.counts().min() > 512
+    ora = oracle_warmup(b, 60, iters=10, warm=O.PREV)
+    sim, g, r = step_both(b, ora, O.PREV, 10, threads=256, max_contacts=1536)
+    rep = compare(b, g, r, ora)
+    assert rep["scenes"] - rep["flagged"] >= 1
+    assert rep["contacts"] > 50
+
+
 @pytest.mark.parametrize("threads", [64, 192, 256])
 def test_block_size_bit_identical(torch_cuda, threads):
     """Results are bit-identical for any workgroup size."""
