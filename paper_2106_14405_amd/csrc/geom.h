@@ -6,7 +6,7 @@
 // of the two witness points; f is a small feature id.  A contact is kept
 // iff phi <= margin.  Standard methods: closest points (Ericson 2005),
 // oriented-box separating axes (Gottschalk et al. 1996), polygon clipping
-// (Sutherland and Hodgman 1974), tangent basis (Duff et al. 2017).
+// (Sutherland and Hodgman 1974).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -79,15 +79,6 @@ __device__ __forceinline__ V3 RTv(const M3& R, V3 a) {
 }
 __device__ __forceinline__ V3 col(const M3& R, int j) {
   return v3(at3(R.m[0], j), at3(R.m[1], j), at3(R.m[2], j));
-}
-
-// Orthonormal tangents of a unit normal (Duff et al. 2017).
-__device__ __forceinline__ void tangents(V3 n, V3& t1, V3& t2) {
-  float sgn = copysignf(1.0f, n.z);
-  float a = -1.0f / (sgn + n.z);
-  float b = n.x * n.y * a;
-  t1 = v3(1.0f + sgn * n.x * n.x * a, sgn * b, -sgn * n.x);
-  t2 = v3(b, sgn + n.y * n.y * a, -n.y);
 }
 
 struct Geom {
