@@ -1138,25 +1138,23 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     rank[q] = 0u;
   }
   team_sync(tm);
-  for (int i = tid; i < nb; i += T) {
-    uint32_t s0 = lstart[i], e0 = lstart[i + 1];
-    for (uint32_t x = s0 + 1; x < e0; x++) {
-      uint32_t v = list[x];
-      uint32_t y = x;
-      while (y > s0 && list[y - 1] > v) { list[y] = list[y - 1]; y--; }
-      list[y] = v;
+  // rank of each contact in its bodies' lists (canonical order): the number
+  // of smaller contact indices in the same list, one list entry per lane
+  // (its body by binary search of the list starts); low half for a, high
+  // half for b.  The lists themselves stay unordered.
+  const int ltot = (int)lstart[nb];
+  for (int x = tid; x < ltot; x += T) {
+    int lo = 0, hi = nb;  // the body i with lstart[i] <= x < lstart[i + 1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if ((int)lstart[mid] <= x) lo = mid;
+      else hi = mid;
     }
-  }
-  team_sync(tm);
-  // rank of each contact in its bodies' lists: low half for a, high half for b
-  for (int i = tid; i < nb; i += T) {
-    uint32_t s0 = lstart[i], e0 = lstart[i + 1];
-    for (uint32_t x = s0; x < e0; x++) {
-      uint32_t q = list[x];
-      // both bodies of a contact write its rank word: combine atomically
-      if ((int)(ckeys[q] >> 20) == i) atomicOr(&rank[q], x - s0);
-      else atomicOr(&rank[q], (x - s0) << 16);
-    }
+    const uint32_t s0 = lstart[lo], e0 = lstart[lo + 1], v = list[x];
+    uint32_t r = 0u;
+    for (uint32_t y = s0; y < e0; y++) r += list[y] < v ? 1u : 0u;
+    // both bodies of a contact write its rank word: combine atomically
+    atomicOr(&rank[v], (int)(ckeys[v] >> 20) == lo ? r : r << 16);
   }
   team_sync(tm);
   TRACE(7);
