@@ -1098,18 +1098,25 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       pcols[i] = P.prev_col[(long)s * CM + i];
     }
     team_sync(tm);
-    for (int q = tid; q < nc; q += T) {
-      const uint32_t key = ckeys[q];
-      int lo = 0, hi = np0 - 1, hit = -1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const uint32_t km = pkeys[mid];
-        if (km == key) { hit = mid; break; }
-        if (km < key) lo = mid + 1; else hi = mid - 1;
+    // both key lists are sorted: each thread takes a contiguous run of
+    // contacts, finds the first by binary search and merges the rest
+    const int chunk = (nc + T - 1) / T, q0 = tid * chunk, q1 = min(nc, q0 + chunk);
+    if (q0 < q1) {
+      int pos = 0, hi = np0;  // first previous key >= the run's first key
+      const uint32_t k0 = ckeys[q0];
+      while (pos < hi) {
+        const int mid = (pos + hi) >> 1;
+        if (pkeys[mid] < k0) pos = mid + 1;
+        else hi = mid;
       }
-      const uint32_t g = hit >= 0 ? (uint32_t)pcols[hit] : 0u;
-      colour[q] = g < (uint32_t)kMaxColours ? g : 0u;
-      S.u[L.lam + q] = (uint32_t)hit;  // the setup's previous-impulse slot (lam is free until then)
+      for (int q = q0; q < q1; q++) {
+        const uint32_t key = ckeys[q];
+        while (pos < np0 && pkeys[pos] < key) pos++;
+        const int hit = pos < np0 && pkeys[pos] == key ? pos : -1;
+        const uint32_t g = hit >= 0 ? (uint32_t)pcols[hit] : 0u;
+        colour[q] = g < (uint32_t)kMaxColours ? g : 0u;
+        S.u[L.lam + q] = (uint32_t)hit;  // the setup's previous-impulse slot (lam is free until then)
+      }
     }
     team_sync(tm);
   }
