@@ -274,13 +274,16 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 
 // Tangent basis of a unit normal (Duff et al. 2017) with a hardware
 // reciprocal; used for every contact row of the step (setup, sweeps, cache).
-__device__ __forceinline__ void tangents_fast(V3 n, V3& t1, V3& t2) {
+__device__ __forceinline__ float tangent_coef(V3 n) { return -frcp(copysignf(1.0f, n.z) + n.z); }
+// The basis from its coefficient a = -1 / (sign(n.z) + n.z) (kept in the
+// solver record so that the sweeps need no reciprocal).
+__device__ __forceinline__ void tangents_coef(V3 n, float a, V3& t1, V3& t2) {
   float sgn = copysignf(1.0f, n.z);
-  float a = -frcp(sgn + n.z);
   float b = n.x * n.y * a;
   t1 = v3(1.0f + sgn * n.x * n.x * a, sgn * b, -sgn * n.x);
   t2 = v3(b, sgn + n.y * n.y * a, -n.y);
 }
+__device__ __forceinline__ void tangents_fast(V3 n, V3& t1, V3& t2) { tangents_coef(n, tangent_coef(n), t1, t2); }
 
 __device__ __forceinline__ float4 ld4(const float* base, int i) { return reinterpret_cast<const float4*>(base)[i]; }
 __device__ __forceinline__ void st4(float* base, int i, float4 v) { reinterpret_cast<float4*>(base)[i] = v; }
@@ -343,9 +346,9 @@ __device__ __forceinline__ void proj_disk(float& l1, float& l2, float lim) {
 // Solver record of one contact, 5 float4 in global memory, colour-major
 // order:
 //  0 (n, m_n)  1 (r_a, m_t1)  2 (r_b, m_t2)  3 (k_1n, k_2n, bias, mu)
-//  4 (key, Jacobi scale, 0, 0)
-// n the normal (the tangents t1, t2 follow from it by tangents_fast, as in
-// the setup), r_a, r_b the contact point relative to the bodies' centres,
+//  4 (key, Jacobi scale, tangent coefficient, 0)
+// n the normal (the tangents t1, t2 follow from it and the coefficient
+// exactly as in the setup), r_a, r_b the contact point relative to the bodies' centres,
 // m_d = 1 / k_d the effective mass of row d, and k_dn the change of row d's
 // velocity per unit normal impulse (the normal-friction coupling inside one
 // contact).  The angular parts r x d and I^-1 (r x d) of the Jacobian rows
@@ -385,7 +388,7 @@ __device__ __forceinline__ void store_rec(float4* rec, int i, V3 n, V3 ra, V3 rb
   o[1] = f4(ra, m[1]);
   o[2] = f4(rb, m[2]);
   o[3] = make_float4(k1n, k2n, bias, mu);
-  o[4] = make_float4(__uint_as_float(key), jsc, 0.f, 0.f);
+  o[4] = make_float4(__uint_as_float(key), jsc, tangent_coef(n), 0.f);
 }
 
 // A body as the solver sees it in LDS: velocities, inverse mass (dynamic
@@ -460,7 +463,7 @@ __device__ __forceinline__ float pgs_update(const LdsLayout& L, Smem S, const Re
   const float mn = R.r[0].w, m1 = R.r[1].w, m2 = R.r[2].w;
   const float k1n = R.r[3].x, k2n = R.r[3].y, bias = R.r[3].z, mu = R.r[3].w;
   V3 t1, t2;
-  tangents_fast(n, t1, t2);
+  tangents_coef(n, R.r[4].z, t1, t2);
   const V3 dv = point_vel(A.v, A.w, B.v, B.w, ra, rb);
   const float ln = fmaxf(0.f, lam.x + mn * (bias - dot(n, dv)));
   const float dn = ln - lam.x;
@@ -497,7 +500,7 @@ __device__ __forceinline__ float start_objective(const LdsLayout& L, Smem S, con
   const V3 n = xyz(R.r[0]), ra = xyz(R.r[1]), rb = xyz(R.r[2]);
   const float bias = R.r[3].z;
   V3 t1, t2;
-  tangents_fast(n, t1, t2);
+  tangents_coef(n, R.r[4].z, t1, t2);
   const V3 dv0 = point_vel(va0, wa0, vb0, wb0, ra, rb), dv1 = point_vel(A1.v, A1.w, B1.v, B1.w, ra, rb);
   float f = lam.x * (0.5f * (dot(n, dv0) + dot(n, dv1)) - bias);
   f += lam.y * 0.5f * (dot(t1, dv0) + dot(t1, dv1));
@@ -520,7 +523,7 @@ __device__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int nco
       Vel B = load_vel(L, S, b);
       const V3 n = xyz(R.r[0]);
       V3 t1, t2;
-      tangents_fast(n, t1, t2);
+      tangents_coef(n, R.r[4].z, t1, t2);
       apply_impulse(A, B, xyz(R.r[1]), xyz(R.r[2]), n * lam.x + t1 * lam.y + t2 * lam.z);
       store_vel_dyn(L, S, a, A);
       store_vel_dyn(L, S, b, B);
@@ -637,7 +640,7 @@ __device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int 
       const float mn = R.r[0].w, m1 = R.r[1].w, m2 = R.r[2].w;
       const float bias = R.r[3].z, mu = R.r[3].w, sc = R.r[4].y;
       V3 t1, t2;
-      tangents_fast(n, t1, t2);
+      tangents_coef(n, R.r[4].z, t1, t2);
       const V3 dv = point_vel(va, wa, vb, wb, ra, rb);
       float ln = fmaxf(0.f, lam.x + sc * mn * (bias - dot(n, dv)));
       float l1 = lam.y - sc * m1 * dot(t1, dv);
@@ -658,7 +661,7 @@ __device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int 
         Vel B = load_vel(L, S, b);
         const V3 n = xyz(R.r[0]);
         V3 t1, t2;
-        tangents_fast(n, t1, t2);
+        tangents_coef(n, R.r[4].z, t1, t2);
         apply_impulse(A, B, xyz(R.r[1]), xyz(R.r[2]), n * dl.x + t1 * dl.y + t2 * dl.z);
         store_vel_dyn(L, S, a, A);
         store_vel_dyn(L, S, b, B);
@@ -1568,7 +1571,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     float4 lam = ld4(S.f + L.lam, i);
     const V3 n = xyz(R[0]);
     V3 t1, t2;
-    tangents_fast(n, t1, t2);
+    tangents_coef(n, R[4].z, t1, t2);
     uint32_t key = ckeys[q];
     int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
     V3 F = t1 * lam.y + t2 * lam.z;
