@@ -172,6 +172,62 @@ __device__ int lds_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t
   return swapped;
 }
 
+// Bitonic sort of 64 S unique 32-bit keys held by one wave, S consecutive
+// elements per lane in registers (element S lane + s), ascending; padding
+// keys are ~0u.  Partners within a lane compare in registers, partners in
+// other lanes are exchanged by a lane permute.
+template <int S>
+__device__ __forceinline__ void wave_bitonic(uint32_t (&v)[8], int lane) {
+  constexpr int N = 64 * S;
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= S) {
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+          const uint32_t o = __shfl_xor(v[s], j / S);
+          const int e = S * lane + s;
+          const bool up = (e & k) == 0, low = (e & j) == 0;
+          v[s] = up == low ? min(v[s], o) : max(v[s], o);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+          if (s & j) continue;
+          const bool up = ((S * lane + s) & k) == 0;
+          const uint32_t a = v[s], b = v[s + j];
+          v[s] = up ? min(a, b) : max(a, b);
+          v[s + j] = up ? max(a, b) : min(a, b);
+        }
+      }
+    }
+  }
+}
+
+// Sorts n <= 512 unique keys with one wave: load (key of element e from
+// `key(e)`, e < n), sort, and hand each sorted (position, key) to `put`.
+template <class KeyF, class PutF>
+__device__ __forceinline__ void wave_sort512(int n, int lane, KeyF key, PutF put) {
+  uint32_t v[8];
+  auto run = [&](auto sz) {
+    constexpr int S = decltype(sz)::value;
+#pragma unroll
+    for (int s = 0; s < 8; s++) {
+      const int e = S * lane + s;
+      v[s] = s < S && e < n ? key(e) : ~0u;
+    }
+    wave_bitonic<S>(v, lane);
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+      const int e = S * lane + s;
+      if (e < n) put(e, v[s]);
+    }
+  };
+  if (n <= 256) run(std::integral_constant<int, 4>{});
+  else run(std::integral_constant<int, 8>{});
+}
+
 // Stable sort of n <= kRankSortMax (key, value) pairs in LDS by rank: the
 // rank of element i is the number of elements j with (key_j, j) < (key_i, i)
 // (the order the radix sort yields).  Each thread holds E <= 8 elements in
@@ -920,10 +976,15 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   if (npairs_all > PMs && tid == 0) misc[M_FLAGS] |= FLAG_CAPACITY;
   // keys are unique: sort keys only (values ride along in the same buffers)
   int swp = 1;
-  if (np <= kRankSortMax)
+  if (T == 64 && np <= 512) {  // one wave: bitonic sort in registers
+    uint32_t* pk2 = S.u + L.pk2;
+    wave_sort512(np, tid, [&](int e) { return pk[e]; }, [&](int e, uint32_t k) { pk2[e] = k; });
+    team_sync(tm);
+  } else if (np <= kRankSortMax) {
     lds_rank_sort<true>(pk, nullptr, S.u + L.pk2, nullptr, np, tm);
-  else
+  } else {
     swp = lds_radix_sort(pk, pk, S.u + L.pk2, S.u + L.pk2, np, 0, 3, S.u + L.hist, S.u + L.hbase, misc, tm);
+  }
   const uint32_t* pairs = swp ? S.u + L.pk2 : pk;
   if (P.export_on) {
     for (int p = tid; p < np; p += T) {
@@ -1258,14 +1319,21 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     if (colour[q] == kMaxColours - 1) atomicOr(&misc[M_FLAGS], (uint32_t)FLAG_CAPACITY);
   // stable sort of contact indices by colour -> colour-major order; the sort
   // works on copies so `colour` stays indexed by contact
-  uint32_t* cidx = S.u + L.cv0;
-  uint32_t* csk = S.u + L.ck1;
-  for (int q = tid; q < nc; q += T) {
-    cidx[q] = (uint32_t)q;
-    csk[q] = colour[q];
+  if (T == 64 && nc <= 512) {  // one wave: bitonic sort of (colour, contact) keys in registers
+    uint32_t* permw = S.u + L.perm;
+    wave_sort512(nc, tid, [&](int e) { return (colour[e] << 16) | (uint32_t)e; },
+                 [&](int e, uint32_t k) { permw[e] = k & 0xFFFFu; rank[e] = k >> 16; });
+    team_sync(tm);
+  } else {
+    uint32_t* cidx = S.u + L.cv0;
+    uint32_t* csk = S.u + L.ck1;
+    for (int q = tid; q < nc; q += T) {
+      cidx[q] = (uint32_t)q;
+      csk[q] = colour[q];
+    }
+    team_sync(tm);
+    lds_radix_sort(csk, cidx, rank, S.u + L.perm, nc, 0, 1, S.u + L.hist, S.u + L.hbase, misc, tm);
   }
-  team_sync(tm);
-  lds_radix_sort(csk, cidx, rank, S.u + L.perm, nc, 0, 1, S.u + L.hist, S.u + L.hbase, misc, tm);
   const uint32_t* perm = S.u + L.perm;
   const uint32_t* scol = rank;       // sorted colours (one pass: result in (k1, v1))
   uint32_t* cstart = S.u + L.hbase;  // colour starts (hbase is free again)
