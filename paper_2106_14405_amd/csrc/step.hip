@@ -534,6 +534,45 @@ __device__ __forceinline__ float pgs_update(const LdsLayout& L, Smem S, const Re
   return fmaxf(fmaxf(fabsf(dn) * frcp(mn), fabsf(d1) * frcp(m1)), fabsf(d2) * frcp(m2));
 }
 
+// Value of the partner lane in a lane pair (lanes 2k, 2k + 1): a DPP quad
+// permutation [1, 0, 3, 2], one VALU operation.
+__device__ __forceinline__ float pair_swap(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xf, 0xf, false));
+}
+
+// The update of pgs_update on a lane pair: lane `side` 0 holds body a, lane
+// 1 body b.  Each lane projects its body's point velocity on the three rows
+// (signed: + for a, - for b) and adds its partner's projection, so both
+// lanes hold the same row velocities (the addition commutes exactly), take
+// the same impulse step and apply it to their own body only.  Halves the
+// dependent work of one update; used for colours of at most 32 contacts.
+__device__ __forceinline__ float pgs_update_pair(const LdsLayout& L, Smem S, const Rec& R, int i, int side) {
+  const int me = side ? rec_b(R) : rec_a(R);
+  const float sg = side ? -1.f : 1.f;
+  const float4 lam = ld4(S.f + L.lam, i);
+  Vel M = load_vel(L, S, me);
+  const V3 n = xyz(R.r[0]), r = side ? xyz(R.r[2]) : xyz(R.r[1]);
+  const float mn = R.r[0].w, m1 = R.r[1].w, m2 = R.r[2].w;
+  const float k1n = R.r[3].x, k2n = R.r[3].y, bias = R.r[3].z, mu = R.r[3].w;
+  V3 t1, t2;
+  tangents_coef(n, R.r[4].z, t1, t2);
+  const V3 pv = M.v + cross(M.w, r);
+  const float cn = sg * dot(n, pv), c1 = sg * dot(t1, pv), c2 = sg * dot(t2, pv);
+  const float un = cn + pair_swap(cn), u1 = c1 + pair_swap(c1), u2 = c2 + pair_swap(c2);
+  const float ln = fmaxf(0.f, lam.x + mn * (bias - un));
+  const float dn = ln - lam.x;
+  float l1 = lam.y - m1 * (u1 + k1n * dn);
+  float l2 = lam.z - m2 * (u2 + k2n * dn);
+  proj_disk(l1, l2, mu * ln);
+  const float d1 = l1 - lam.y, d2 = l2 - lam.z;
+  const V3 P = (n * dn + t1 * d1 + t2 * d2) * sg;
+  M.v = M.v + P * M.im;
+  M.w = M.w + Imul(M.I, cross(r, P));
+  store_vel_dyn(L, S, me, M);
+  if (!side) st4(S.f + L.lam, i, make_float4(ln, l1, l2, lam.w));
+  return fmaxf(fmaxf(fabsf(dn) * frcp(mn), fabsf(d1) * frcp(m1)), fabsf(d2) * frcp(m2));
+}
+
 // Objective change from adding the network's start impulses of colour-major
 // contact i (zero for a persisting contact): the impulse times (the mean of
 // the row velocity before and after the new contacts' impulses were
@@ -591,7 +630,9 @@ __device__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int nco
 // Sweeps of projected Gauss-Seidel, colour batch after colour batch; the
 // record of a lane's next batch is loaded while the current one is solved.
 // Stops after `iters` sweeps or once a sweep's residual is <= tol (tol > 0).
-template <class TM>
+// kPairs: small colours by lane pairs (off where the network's registers
+// leave no room for the second update's code).
+template <bool kPairs, class TM>
 __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int ncol, const uint32_t* cstart, int iters,
                           float tol, uint32_t* misc, int* sweeps_out, float* res_out, const TM& tm) {
   const int tid = tm.tid, T = tm.T;
@@ -611,7 +652,7 @@ __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int nco
   // The sweeps, instantiated twice: with fewer than 64 colours every colour
   // start is one readlane of cs_lo, without the branches of the general
   // lookup in the loop.
-  auto sweep_all = [&](auto small) {
+  auto sweep_all = [&](auto small) __attribute__((always_inline)) {
     constexpr bool kSmall = decltype(small)::value;
     auto cst = [&](int c) -> int {
       if constexpr (kSmall) return __builtin_amdgcn_readlane(cs_lo, c);
@@ -619,25 +660,37 @@ __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int nco
                          : (c < 128 ? __builtin_amdgcn_readlane(cs_hi, c - 64) : cs_end);
     };
     const int last = cst(ncol) - 1;  // >= 0: ncol > 0 implies contacts
-    int i = cst(0) + tid;
+    // A colour of at most 32 contacts is solved by lane pairs (contact
+    // tid / 2, one batch for any team of >= 64 threads), a larger one a
+    // contact per lane (contact tid, tid + T, ...).  The choice depends on
+    // the colour only, so results do not depend on the team size.
+    auto paired = [&](int c) { return kPairs && cst(c + 1) - cst(c) <= 32; };
+    bool pair = paired(0);
+    int i = cst(0) + (pair ? tid >> 1 : tid);
     bool has = i < cst(1);
     float r = 0.f;
     // One colour batch: load the next batch's records (unconditionally, the
     // index clamped to a valid record, so that the loads stay in flight),
     // solve this batch, synchronise.  Two record buffers alternate between
     // batches so that no registers are copied between them.
-    auto batch = [&](int c, const Rec& cur, Rec& nxt) {
+    auto batch = [&](int c, const Rec& cur, Rec& nxt) __attribute__((always_inline)) {
       const int e = cst(c + 1);
       // next batch: colour c + 1, or colour 0 of the next sweep
       const int cn = c + 1 < ncol ? c + 1 : 0;
-      const int inext = cst(cn) + tid;
+      const bool pnext = paired(cn);
+      const int inext = cst(cn) + (pnext ? tid >> 1 : tid);
       const bool hnext = inext < cst(cn + 1);
       nxt = load_rec(rec, min(inext, last));
-      if (has) r = fmaxf(r, pgs_update(L, S, cur, i));
-      for (int i2 = i + T; i2 < e; i2 += T) r = fmaxf(r, pgs_update(L, S, load_rec(rec, i2), i2));
+      if (kPairs && pair) {
+        if (has) r = fmaxf(r, pgs_update_pair(L, S, cur, i, tid & 1));
+      } else {
+        if (has) r = fmaxf(r, pgs_update(L, S, cur, i));
+        for (int i2 = i + T; i2 < e; i2 += T) r = fmaxf(r, pgs_update(L, S, load_rec(rec, i2), i2));
+      }
       colour_sync(tm);
       has = hnext;
       i = inext;
+      pair = pnext;
     };
     Rec ra = load_rec(rec, min(i, last)), rb;
     for (int it = 0; it < iters; it++) {
@@ -1572,7 +1625,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   if (P.solver == SOLVER_JACOBI)
     solve_jacobi(L, S, rec, nb, nc, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res, tm);
   else
-    solve_pgs(L, S, rec, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res, tm);
+    solve_pgs<!kLearned>(L, S, rec, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res, tm);
   team_sync(tm);
   // a step counts as solved only once its residual reached the tolerance
   if (P.tol > 0.f && res > P.tol && tid == 0) misc[M_FLAGS] |= FLAG_NOT_CONVERGED;
