@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import math
 import os
+import sys
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -366,11 +367,26 @@ def _drop_one(args):
     return drop_scene(seed, n_spheres=ns, n_boxes=nb)
 
 
+def _gpu_initialised() -> bool:
+    """True once this process has initialised the GPU runtime (torch imported
+    and its CUDA/HIP state set up); a fork after that point is not allowed."""
+    torch = sys.modules.get("torch")
+    if torch is None:
+        return False
+    try:
+        return bool(torch.cuda.is_initialized())
+    except Exception:
+        return True
+
+
 def _map(fn, items, workers):
-    """Map over scene seeds, in worker processes for large batches.  Uses
-    fork: call it before the GPU is initialised in this process."""
+    """Map over scene seeds, in forked worker processes for large batches
+    while the GPU runtime is not initialised in this process; serially after
+    that (a process that has initialised the GPU must not fork)."""
     if workers is None:
         workers = min(16, os.cpu_count() or 1) if len(items) >= 64 else 1
+    if workers > 1 and _gpu_initialised():
+        workers = 1
     if workers <= 1:
         return [fn(a) for a in items]
     import multiprocessing as mp

@@ -55,20 +55,51 @@ def custom_batch(scenes_bodies, arm=False, theta=None):
     return b
 
 
+def _quad(f, a, b, breaks=()):
+    """Integral of f over [a, b] split at the given interior points (scipy's
+    adaptive Gauss-Kronrod; every integrand below is a polynomial piece by
+    piece, so the result is exact to rounding)."""
+    from scipy.integrate import quad
+    pts = [a, *sorted(x for x in breaks if a < x < b), b]
+    return sum(quad(f, lo, hi, epsabs=0.0, epsrel=1e-13, limit=200)[0] for lo, hi in zip(pts[:-1], pts[1:]))
+
+
+def _inertia_of_slices(rho2, z0, z1, breaks, m):
+    """Principal moments about the centre of mass of a uniform solid of
+    revolution about z whose cross-section at height z is a disk of squared
+    radius rho2(z), scaled to mass m.  A disk of radius R at height z adds
+    pi R^4 / 2 to I_z and pi R^4 / 4 + pi R^2 z^2 to I_x (per unit density
+    and height); the volume is the integral of pi R^2."""
+    vol = _quad(lambda z: math.pi * rho2(z), z0, z1, breaks)
+    iz = _quad(lambda z: 0.5 * math.pi * rho2(z) ** 2, z0, z1, breaks)
+    ix = _quad(lambda z: 0.25 * math.pi * rho2(z) ** 2 + math.pi * rho2(z) * z * z, z0, z1, breaks)
+    return np.array([ix, ix, iz]) * (m / vol)
+
+
 def inertia(shape, p, m):
-    """Principal moments (textbook solid bodies) for the momentum pins."""
-    if shape == S.SPHERE:
-        return np.full(3, 0.4 * m * p[0] ** 2)
+    """Principal moments of a solid body of uniform density and mass m,
+    integrated numerically over its volume (not from closed forms): a box
+    as the separable integrals of y^2 + z^2 etc. over its extents, a sphere
+    and a capsule (cylinder of half-length h with hemispherical caps) as
+    stacks of disks along z."""
+    p = [float(x) for x in p]
     if shape == S.BOX:
-        x2, y2, z2 = p[0] ** 2, p[1] ** 2, p[2] ** 2
-        return np.array([m / 3 * (y2 + z2), m / 3 * (x2 + z2), m / 3 * (x2 + y2)])
+        hx, hy, hz = p
+        vol = 8 * hx * hy * hz
+        sx = _quad(lambda x: x * x, -hx, hx) * 4 * hy * hz / vol
+        sy = _quad(lambda y: y * y, -hy, hy) * 4 * hx * hz / vol
+        sz = _quad(lambda z: z * z, -hz, hz) * 4 * hx * hy / vol
+        return m * np.array([sy + sz, sx + sz, sx + sy])
+    if shape == S.SPHERE:
+        r = p[0]
+        return _inertia_of_slices(lambda z: r * r - z * z, -r, r, (), m)
     r, h = p[0], p[1]
-    vc, vs = 2 * math.pi * r * r * h, 4 / 3 * math.pi * r ** 3
-    mc = m * vc / (vc + vs)
-    ms = m - mc
-    Iz = mc * r * r / 2 + 0.4 * ms * r * r
-    Ix = mc * (r * r / 4 + h * h / 3) + ms * (0.4 * r * r + h * h + 0.75 * h * r)
-    return np.array([Ix, Ix, Iz])
+
+    def rho2(z):
+        u = abs(z) - h
+        return r * r if u <= 0.0 else r * r - u * u
+
+    return _inertia_of_slices(rho2, -h - r, h + r, (-h, h), m)
 
 
 def momenta(batch, pose, vel):
