@@ -1,24 +1,36 @@
-"""Benchmark: env-steps/s of the batched rigid-body step on one MI355X.
+"""Benchmark: env-steps/s of the batched rigid-body step on one MI355X at
+contact residual 1e-4, and PGS sweeps with the learned warm start against
+plain PGS.
 
 One env-step = one scene advanced by one call of the step at dt = 1/120 s.
-Workload (default): 1,024 clutter scenes x (20 static boxes + 108 dynamic
+Default workload (clutter): 1,024 scenes x (20 static boxes + 108 dynamic
 spheres/boxes/capsules + a kinematic 7-link capsule arm driven by seeded
-joint velocities in [-1, 1] rad/s), plain projected Gauss-Seidel (no learned
-warm start), residual tolerance 1e-4 m/s with a cap of 20 sweeps, float32.
-Synthetic, seeded inputs stand in for the paper's rearrangement scenes.
---workload uneven: 4,096 drop scenes with 16-512 dynamic bodies
-(log-uniform) through the persistent launch (autotuned queue split, HIP
-graph replay), every scene reset to its initial state after an episode of
-U[100, 300] steps.  --workload drop: 1,024 drop scenes of 64 bodies.
+joint velocities in [-1, 1] rad/s), float32.  Synthetic, seeded inputs stand
+in for the paper's rearrangement scenes (ReplicaCAD furniture, YCB objects,
+the Fetch arm).
 
-After the timed run (untimed), learned vs plain: the committed warm-start
-network against plain PGS (cold start) and the classic warm start on
-held-out drop scenes at residual 1e-4 with a cap of 200 sweeps.
+Protocol.  The dropped objects are first settled, untimed, for --settle
+steps (the scenes start from a settled pile whatever --warmup says, as the
+paper's clutter is settled offline before episodes start).  The settled
+state is saved; then for each warm-start mode (cold: plain PGS from zero
+impulses; prev: the classic warm start from the previous step's impulses;
+learned: the committed network) the state is restored, W untimed and K
+timed steps run at residual tolerance --tol (m/s) with a sweep cap --cap,
+timed with HIP events on the simulation's stream.  The same W + K steps are
+then replayed from the restored state (the step is deterministic, so the
+replay reproduces the timed steps bit for bit) to collect per scene-step
+sweeps, residuals and flags.  `value` is the headline mode's env-steps/s;
+`frac_at_tol` says how many scene-steps reached the tolerance.
+
+Also reported: the roofline of the step kernel (algorithmic HBM bytes per
+launch over its measured duration, against the 8 TB/s peak; measured
+traffic from committed rocprofv3 counters of the same window), learned vs
+plain on held-out small drop scenes (64 bodies, seeds 2000+, tolerance 1e-4,
+cap 200), and the FP64 oracle on the host cores as a CPU baseline.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload clutter|uneven|drop]
 
-Prints one JSON line.  W untimed steps let the dropped objects land; the K
-timed steps run back to back on the simulation's stream between HIP events.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -27,6 +39,7 @@ import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -36,23 +49,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "env-steps/sec at contact residual 1e-4; PGS iterations, learned vs plain"
 HBM_PEAK_GBS = 8000.0
+DT = 1.0 / 120.0
 # algorithmic bytes per unit of work (float32 structure of arrays):
 B_DYN = 144.0      # per dynamic body per step: state read+write 104 B + constants 40 B
 B_STATIC = 52.0    # per static or kinematic body per step: pose + shape + material
 B_CONTACT = 40.0   # per contact per step: cache read 20 B + write 20 B
 B_SWEEP = 240.0    # per contact per sweep if the solver state were streamed from memory
+MODES = ("cold", "prev", "learned")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=150)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--settle", type=int, default=300, help="untimed settling steps before any mode runs")
     ap.add_argument("--workload", default="clutter", choices=["clutter", "drop", "uneven"])
     ap.add_argument("--scenes", type=int, default=None)
-    ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--tol", type=float, default=1e-4)
-    ap.add_argument("--warm", default="cold", choices=["cold", "prev"])
+    ap.add_argument("--cap", type=int, default=None, help="sweep cap at the tolerance")
+    ap.add_argument("--headline", default="prev", choices=MODES)
+    ap.add_argument("--modes", default=",".join(MODES))
+    ap.add_argument("--no-replay", action="store_true", help="skip the statistics replay (profiling runs)")
     ap.add_argument("--threads", type=int, default=64)
     ap.add_argument("--max-contacts", type=int, default=None)
     ap.add_argument("--max-pairs", type=int, default=None)
@@ -62,8 +80,8 @@ def parse():
     ap.add_argument("--learned-scenes", type=int, default=2048)
     ap.add_argument("--learned-steps", type=int, default=240)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-scenes", type=int, default=32)
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-scenes-per-thread", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="only run an elementwise copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -91,36 +109,62 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
+def window_tag(workload, mode, settle, tol, cap, n_scenes):
+    return f"{workload}{n_scenes}-settle{settle}-{mode}-tol{tol:g}-cap{cap}"
+
+
+def measured_traffic(workload, tag):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source and on the same window; else None."""
     p = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_hash") != kernel_hash():
+    if d.get("kernel_hash") != kernel_hash() or d.get("window") != tag:
         return None
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(batch_fn, n_scenes, warm_steps, timed_steps, iters, tol, warm, arm):
-    """The FP64 oracle, single thread, on a sample of the same workload."""
+def host_threads():
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    lim = os.environ.get("OMP_NUM_THREADS")
+    if lim and lim.isdigit() and int(lim) > 0:
+        n = min(n, int(lim))
+    return max(1, n)
+
+
+def cpu_baseline(batch, settle, timed_steps, cap, tol, warm, arm):
+    """The FP64 oracle on the host cores: the same workload on a sample of
+    scenes (one contiguous chunk per thread), settled in the oracle itself
+    (untimed), then `timed_steps` steps at the same tolerance, cap and warm
+    start, all threads timed together."""
     from oracle import oracle as O
     from paper_2106_14405_amd import scenes as S
-    b = batch_fn(n_scenes)
-    o = O.OracleSim(b)
-    w = O.PREV if warm == "prev" else O.COLD
-    for t in range(warm_steps):
-        o.step(actions=S.arm_actions(1, n_scenes, t) if arm else None, iters=iters, tol=tol, warm=w,
-               outputs=False)
-    acts = [S.arm_actions(1, n_scenes, warm_steps + t) if arm else None for t in range(timed_steps)]
-    t0 = time.perf_counter()
-    for t in range(timed_steps):
-        o.step(actions=acts[t], iters=iters, tol=tol, warm=w, outputs=False)
-    dt = time.perf_counter() - t0
-    return dict(value=n_scenes * timed_steps / dt, unit="env-steps/s", cores=1, kind="oracle",
-                sample=f"{n_scenes} scenes x {timed_steps} steps after {warm_steps} untimed steps, "
-                       f"same workload, same sweep cap and tolerance, one host thread")
+    n = batch.n_scenes
+    o = O.OracleSim(batch)
+    nth = min(host_threads(), n)
+    acts = [S.arm_actions(1, n, t) if arm else None for t in range(settle + timed_steps)]
+    w = {"cold": O.COLD, "prev": O.PREV}.get(warm, O.PREV)
+    bounds = [(k * n // nth, (k + 1) * n // nth) for k in range(nth)]
+
+    def run(t0, t1, iters, tl, wm):
+        def work(s0, s1):
+            for t in range(t0, t1):
+                o.step(actions=acts[t], iters=iters, tol=tl, warm=wm, outputs=False, scenes=(s0, s1))
+        th = [threading.Thread(target=work, args=b) for b in bounds]
+        start = time.perf_counter()
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        return time.perf_counter() - start
+
+    run(0, settle, 20, 0.0, O.PREV)
+    secs = run(settle, settle + timed_steps, cap, tol, w)
+    return dict(value=n * timed_steps / secs, unit="env-steps/s", cores=nth, kind="oracle",
+                sample=(f"{n} scenes x {timed_steps} steps of the same workload after {settle} untimed settling steps "
+                        f"in the oracle; tolerance {tol:g} m/s, cap {cap}, {warm} start; {nth} host threads, "
+                        f"one chunk of scenes each; {secs:.1f} s wall"))
 
 
 def reset_schedule(n_scenes, n_steps, seed=7):
@@ -138,31 +182,51 @@ def reset_schedule(n_scenes, n_steps, seed=7):
 def workload_name(w, n_scenes, batch):
     if w == "clutter":
         return (f"clutter: {n_scenes} scenes x {batch.n_bodies // n_scenes} bodies (20 static boxes, "
-                "108 dynamic spheres/boxes/capsules, 7-link kinematic arm)")
+                "108 dynamic spheres/boxes/capsules, 7-link kinematic arm), settled")
     if w == "uneven":
         c = batch.counts()
         return (f"uneven: {n_scenes} drop scenes, {int(c.min())}-{int(c.max())} dynamic spheres/boxes "
                 f"(log-uniform), {batch.n_bodies} bodies")
-    return f"drop: {n_scenes} scenes x 64 dynamic bodies (32 spheres + 32 boxes)"
+    return f"drop: {n_scenes} scenes x 64 dynamic bodies (32 spheres + 32 boxes), settled"
 
 
 def learned_vs_plain(n_scenes, steps):
-    """Held-out drop scenes (seeds 2000+) at residual 1e-4, cap 200 sweeps:
-    plain PGS (cold), classic warm start, the committed learned warm start."""
+    """Held-out small drop scenes (64 bodies, seeds 2000+) at residual 1e-4,
+    cap 200 sweeps: plain PGS (cold), classic warm start, the committed
+    learned warm start; paired per-scene differences with 95% intervals."""
     from paper_2106_14405_amd import _lib as L
     from paper_2106_14405_amd import train as T
     path = os.path.join(ROOT, "paper_2106_14405_amd", "weights", "warmstart_drop.npz")
     if not os.path.exists(path):
         return None
     net = T.load(path)
-    res = {}
+    res, raw = {}, {}
     for name, mode in (("cold", L.COLD), ("prev", L.PREV), ("learned", L.LEARNED)):
         r = T.evaluate(mode, net if mode == L.LEARNED else None, n_scenes=n_scenes, seed0=2000, steps=steps,
                        tol=1e-4, cap=200)
+        raw[name] = r
         res[name] = T.summary(r)
+    res["learned_minus_prev"] = T.paired(raw["learned"], raw["prev"])
+    res["learned_minus_cold"] = T.paired(raw["learned"], raw["cold"])
     res["workload"] = (f"{n_scenes} held-out drop scenes x {steps} steps, tolerance 1e-4 m/s, cap 200 sweeps; "
-                       "mean/p50/p95 sweeps per scene-step with contacts, ms per step of the whole batch")
+                       "mean/p50/p95 sweeps per scene-step with contacts, ms per step of the whole batch; "
+                       "paired: per-scene mean sweeps and per-step ms, mean difference and 95% interval")
     return res
+
+
+def summarise(sweeps, resid, flags, contacts, tol):
+    """Statistics over scene-steps [K, S] (scene-steps with contacts for sweeps)."""
+    from paper_2106_14405_amd import _lib as L
+    m = contacts > 0
+    s = sweeps[m].astype(np.float64)
+    pct = lambda q: float(np.percentile(s, q)) if s.size else 0.0
+    return dict(sweeps_mean=float(s.mean()) if s.size else 0.0, sweeps_p50=pct(50), sweeps_p95=pct(95),
+                sweeps_p99=pct(99), sweeps_max=int(s.max()) if s.size else 0,
+                worst_scene_sweeps_mean=float(sweeps.max(axis=1).mean()),
+                frac_at_tol=float(np.mean(resid <= tol)), median_residual=float(np.median(resid)),
+                frac_fellback=float(np.mean((flags & L.FLAG_FELLBACK) != 0)),
+                frac_capacity_or_nonfinite=float(np.mean((flags & (L.FLAG_NONFINITE | L.FLAG_CAPACITY)) != 0)),
+                contacts_per_scene=float(contacts.mean()))
 
 
 def main():
@@ -180,31 +244,41 @@ def main():
         arm = True
         max_contacts = a.max_contacts or 512
         max_pairs = a.max_pairs or max_contacts
+        cap = a.cap or 1000
     elif a.workload == "uneven":
         n_scenes = a.scenes or 4096
         batch_fn = lambda n: S.batch_uneven(n, seed0=20000, lo=16, hi=512)
         arm = False
         max_contacts = a.max_contacts or 2048
         max_pairs = a.max_pairs or 2560   # 512-body piles reach 4.2 pairs per body
+        cap = a.cap or 1000
     else:
         n_scenes = a.scenes or 1024
         batch_fn = lambda n: S.batch_drop(n, seed0=0)
         arm = False
         max_contacts = a.max_contacts or 384
         max_pairs = a.max_pairs or max_contacts
-    batch = batch_fn(n_scenes)              # generated before the GPU is touched
-    K, W = a.steps, a.warmup
-    acts_np = (np.stack([S.arm_actions(1, n_scenes, t) for t in range(W + K)]) if arm else None)
+        cap = a.cap or 1000
+    modes = [m for m in a.modes.split(",") if m]
+    if a.headline not in modes:
+        modes.append(a.headline)
+    # every host-side input is generated before the GPU is touched
+    batch = batch_fn(n_scenes)
+    cpu_batch = None
+    if a.cpu_baseline and a.workload != "uneven":
+        cpu_batch = batch_fn(a.cpu_scenes_per_thread * host_threads())
+    K, W, T0 = a.steps, a.warmup, a.settle
+    acts_np = (np.stack([S.arm_actions(1, n_scenes, t) for t in range(T0 + W + K)]) if arm else None)
 
     import torch
 
     from paper_2106_14405_amd import _lib as L
+    from paper_2106_14405_amd import train as TR
     from paper_2106_14405_amd.sim import Sim
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    warm = L.PREV if a.warm == "prev" else L.COLD
-    sim = Sim(batch, max_contacts=max_contacts, max_pairs=max_pairs, warm=warm, tol=a.tol,
-              threads=a.threads, device=dev)
+    sim = Sim(batch, max_contacts=max_contacts, max_pairs=max_pairs, warm=L.PREV, tol=0.0, threads=a.threads,
+              device=dev)
     acts = torch.as_tensor(acts_np, device=dev) if arm else None
     resets = None
     tuned = None
@@ -212,54 +286,82 @@ def main():
     if a.workload == "uneven":
         if persistent:
             sim.set_persistent(True)
-            tuned = sim.autotune(steps=3, dt=1.0 / 120.0, iters=a.iters)
-        resets = torch.as_tensor(reset_schedule(n_scenes, W + K), device=dev)
+            tuned = sim.autotune(steps=3, dt=DT, iters=20)
+        resets = torch.as_tensor(reset_schedule(n_scenes, T0 + W + K), device=dev)
         pose0 = sim.pose.clone()
         vel0 = sim.vel.clone()
+    net = None
+    if "learned" in modes:
+        wpath = os.path.join(ROOT, "paper_2106_14405_amd", "weights", "warmstart_drop.npz")
+        net = TR.load(wpath, device=str(dev))
+        net.attach(sim)
 
-    def one(t):
+    def one(t, iters):
         if resets is not None:
             sim.reset(resets[t], pose0, vel0)
-        sim.step(acts[t] if arm else None, 1.0 / 120.0, a.iters)
+        sim.step(acts[t] if arm else None, DT, iters)
 
-    for t in range(W):
-        one(t)
+    # settle (untimed): classic warm start, 20 sweeps per step
+    sim.set_solver(L.PGS, L.PREV, 0.0)
+    for t in range(T0):
+        one(t, 20)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(sim.stream)
-    for t in range(K):
-        one(W + t)
-    ev1.record(sim.stream)
+    settled = sim.save_state()
+    contacts_settled = float(sim.stats["contacts"].float().mean().item())
+
+    results = {}
+    for name in modes:
+        mode = {"cold": L.COLD, "prev": L.PREV, "learned": L.LEARNED}[name]
+        sim.load_state(settled)
+        sim.set_solver(L.PGS, mode, a.tol)
+        for t in range(W):
+            one(T0 + t, cap)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(sim.stream)
+        for t in range(K):
+            one(T0 + W + t, cap)
+        ev1.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        r = dict(ms_per_step=ms / K, env_steps_per_s=n_scenes * K / (ms / 1e3))
+        if not a.no_replay:
+            # replay of the same W + K steps from the same state: bit-identical
+            # to the timed steps; statistics of the K timed ones
+            sim.load_state(settled)
+            for t in range(W):
+                one(T0 + t, cap)
+            rec = {k: torch.zeros((K, n_scenes), dtype=v.dtype, device=dev)
+                   for k, v in sim.stats.items() if k in ("sweeps", "residual", "flags", "contacts", "pairs", "colours")}
+            for t in range(K):
+                one(T0 + W + t, cap)
+                for k in rec:
+                    rec[k][t].copy_(sim.stats[k])
+            torch.cuda.synchronize()
+            rec = {k: v.cpu().numpy() for k, v in rec.items()}
+            r.update(summarise(rec["sweeps"], rec["residual"], rec["flags"], rec["contacts"], a.tol))
+            r["pairs_per_scene"] = float(rec["pairs"].mean())
+            r["colours_per_scene"] = float(rec["colours"].mean())
+        results[name] = r
+    sim.close()
+    del sim
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    ms_step = ms / K
-    value = n_scenes * K / (ms / 1e3)
-    # statistics pass (untimed): the same trajectory continued for 10 steps
-    st = dict(contacts=[], sweeps=[], conv=[], flags=[], pairs=[], colours=[], resid=[])
-    for t in range(10):
-        if resets is not None:
-            sim.reset(torch.zeros_like(resets[0]), pose0, vel0)
-        sim.step(acts[(W + K + t) % (W + K)] if arm else None, 1.0 / 120.0, a.iters)
-        s = {k: v.cpu().numpy() for k, v in sim.stats.items()}
-        st["contacts"].append(s["contacts"].mean())
-        st["pairs"].append(s["pairs"].mean())
-        st["colours"].append(s["colours"].mean())
-        st["sweeps"].append(s["sweeps"].mean())
-        st["conv"].append(np.mean(s["residual"] <= a.tol) if a.tol > 0 else float("nan"))
-        st["flags"].append(np.mean((s["flags"] & (L.FLAG_NONFINITE | L.FLAG_CAPACITY)) != 0))
-        st["resid"].append(np.median(s["residual"]))
-    contacts = float(np.mean(st["contacts"]))
+
+    head = results[a.headline]
     motion = batch.motion
     n_dyn = int(np.sum(motion == S.DYNAMIC))
     n_other = int(batch.n_bodies - n_dyn)
+    contacts = head.get("contacts_per_scene", contacts_settled)
     bytes_launch = B_DYN * n_dyn + B_STATIC * n_other + B_CONTACT * contacts * n_scenes
+    ms_step = head["ms_per_step"]
     achieved = bytes_launch / (ms_step / 1e3) / 1e9
-    traffic = measured_traffic(a.workload)
+    tag = window_tag(a.workload, a.headline, T0, a.tol, cap, n_scenes)
+    traffic = measured_traffic(a.workload, tag)
     kname = "step_persistent" if persistent else "step_kernel"
-    sweep_bytes = B_SWEEP * contacts * n_scenes * float(np.mean(st["sweeps"]))
+    sweep_bytes = B_SWEEP * contacts * n_scenes * head.get("sweeps_mean", 0.0)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["env_steps_per_s"],
         "unit": "env-steps/s",
         "n_gpus": 1,
         "steps": K,
@@ -273,8 +375,9 @@ def main():
         "config": {
             "workload": workload_name(a.workload, n_scenes, batch),
             "scenes": n_scenes, "bodies": int(batch.n_bodies), "dynamic_bodies": n_dyn,
-            "dt": 1.0 / 120.0, "sweep_cap": a.iters, "tolerance_m_per_s": a.tol,
-            "warm_start": a.warm, "solver": "pgs",
+            "dt": DT, "tolerance_m_per_s": a.tol, "sweep_cap": cap, "warm_start": a.headline, "solver": "pgs",
+            "settle_steps": T0, "contacts_per_scene_settled": contacts_settled,
+            "frac_scene_steps_at_tol": head.get("frac_at_tol"),
             "threads_per_scene": a.threads if not persistent else "autotuned: 64 (one wave) or 256",
             "max_contacts_per_scene": max_contacts, "max_pairs_per_scene": max_pairs,
             **({"launch": "persistent, HIP graph" if persistent else "one workgroup per scene",
@@ -284,29 +387,23 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": kname, "bytes_per_launch": bytes_launch,
+            "kernel": kname, "bytes_per_launch": bytes_launch, "window": tag,
             "sweep_equivalent_GBs": sweep_bytes / (ms_step / 1e3) / 1e9,
         },
+        "modes": results,
         "solver_stats": {
-            "contacts_per_scene": contacts, "pairs_per_scene": float(np.mean(st["pairs"])),
-            "colours_per_scene": float(np.mean(st["colours"])), "sweeps_mean": float(np.mean(st["sweeps"])),
-            "frac_scene_steps_at_tol": float(np.mean(st["conv"])), "median_residual": float(np.mean(st["resid"])),
-            "frac_capacity_or_nonfinite": float(np.mean(st["flags"])),
-            "sweeps_learned": None, "sweeps_plain": float(np.mean(st["sweeps"])),
+            "sweeps_learned": results.get("learned", {}).get("sweeps_mean"),
+            "sweeps_plain": results.get("cold", {}).get("sweeps_mean"),
+            "sweeps_prev": results.get("prev", {}).get("sweeps_mean"),
         },
         "cpu_baseline": None,
     }
-    sim.close()
-    del sim
-    torch.cuda.synchronize()
     if a.learned_eval:
         lv = learned_vs_plain(a.learned_scenes, a.learned_steps)
         if lv is not None:
-            out["solver_stats"]["sweeps_learned"] = lv["learned"]["mean"]
-            out["solver_stats"]["sweeps_plain"] = lv["cold"]["mean"]
             out["learned_vs_plain"] = lv
-    if a.cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(batch_fn, a.cpu_scenes, W, a.cpu_steps, a.iters, a.tol, a.warm, arm)
+    if cpu_batch is not None:
+        out["cpu_baseline"] = cpu_baseline(cpu_batch, T0, a.cpu_steps, cap, a.tol, a.headline, arm)
     print(json.dumps(out), flush=True)
 
 

@@ -136,34 +136,57 @@ typedef struct sim_stats_view {
     const float *arm_force;   /* sum over arm contacts of |impulse| / dt (N) */
 } sim_stats_view;
 
-/* Bytes of device workspace the descriptor needs (0 on a bad descriptor). */
+/* Bytes of device workspace the descriptor needs (0 on a bad descriptor):
+ * the state, contact caches and step buffers of all the batch's scenes,
+ * the many environments stepped in parallel of Sec. 4.4. */
 size_t sim_workspace_bytes(const sim_batch_desc *desc);
 
-/* Validates the descriptor, lays out the workspace (>= sim_workspace_bytes,
- * 256-byte aligned device memory owned by the caller), uploads the initial
- * state on desc->stream and synchronises it.  *out receives the handle. */
+/* The initial state s_0 of every scene (Sec. 2, the simulator's state;
+ * rigid objects with mass, friction and restitution and simplified
+ * collision proxies, Sec. 3 and Sec. 4.3; static parts, Sec. 4.1; the arm,
+ * Sec. 5).  Validates the descriptor (SIM_EINVAL, SIM_EABI, SIM_ECAPACITY
+ * when a scene's working set does not fit the device), lays out the
+ * workspace (>= sim_workspace_bytes, 256-byte aligned device memory owned by
+ * the caller; SIM_EWORKSPACE otherwise), uploads the initial state on
+ * desc->stream and synchronises it.  *out receives the handle, which owns
+ * host metadata only. */
 int sim_create(const sim_batch_desc *desc, void *d_workspace, size_t workspace_bytes, sim_handle **out);
 
-/* One step of every scene: d_actions [S*7] arm joint velocities (rad/s),
- * device memory, or NULL (zero); dt > 0 seconds; iters >= 1 sweeps (the cap
- * when a tolerance is set).  Asynchronous on the handle's stream. */
+/* One transition (s_t, a_t) -> s_{t+1} of every scene (Sec. 2), a physics
+ * step of dt (1/120 s in Sec. 4.4): d_actions [S*7] arm joint velocities
+ * (rad/s; the agent's arm action of Sec. 5), device memory, or NULL (zero);
+ * dt > 0 seconds; iters >= 1 sweeps (the cap when a tolerance is set).
+ * SIM_EINVAL on bad arguments (nothing launched).  Asynchronous on the
+ * handle's stream; per-scene soft faults go to the stats flags. */
 int sim_step(sim_handle *h, const float *d_actions, float dt, int iters);
 
-/* Contact and pair views of the last step. */
+/* Contact and pair views of the last step (device pointers into the
+ * workspace, valid until the next step): the contacts whose impulses make
+ * up the arm's collision force that the Pick task reads (Sec. 5; appendix,
+ * Pick reward). */
 int sim_contacts(const sim_handle *h, sim_contact_view *out);
 
-/* State and statistics views. */
+/* State view (the s_t of Sec. 2: poses, velocities, joint angles and the
+ * warm-start contact cache) and per-scene statistics of the last step
+ * (pairs, contacts, colours, sweeps, residual, flags and the arm force of
+ * Sec. 5).  Device pointers into the workspace; SIM_EINVAL on NULL. */
 int sim_state(const sim_handle *h, sim_state_view *out);
 int sim_stats(const sim_handle *h, sim_stats_view *out);
 
-/* Export of normals, points, phi, impulses, colours, features and pairs on (1) or off (0). */
+/* Export of normals, points, phi, impulses, colours, features and pairs on
+ * (1) or off (0) for later steps (for analysis and for logging the learned
+ * warm start's training rows; off in the hot loop). */
 int sim_set_export(sim_handle *h, int on);
 
-/* Change the solver settings used by later steps. */
+/* Change the solver settings used by later steps: SIM_PGS or SIM_JACOBI,
+ * SIM_COLD / SIM_PREV / SIM_LEARNED start, residual tolerance (m/s; 0 =
+ * fixed sweeps).  SIM_EINVAL on a bad value, SIM_ECAPACITY if a scene no
+ * longer fits the persistent launch's LDS (settings unchanged). */
 int sim_set_solver(sim_handle *h, int solver, int warm_start, float tolerance);
 
-/* Learned warm start weights, device memory read during every later step
- * in SIM_LEARNED mode: bf16 w1 [64*16], w2 [64*64], w3 [3*64] (row = output),
+/* Learned warm start weights (this library's addition; the paper has no
+ * learned solver), device memory read during every later step in
+ * SIM_LEARNED mode: bf16 w1 [64*16], w2 [64*64], w3 [3*64] (row = output),
  * fp32 b1 [64], b2 [64], b3 [3], feature mean [16] and std [16].  The
  * pointers must stay valid while used. */
 int sim_set_mlp(sim_handle *h, const uint16_t *d_w1, const uint16_t *d_w2, const uint16_t *d_w3,
@@ -215,12 +238,15 @@ int sim_mlp_forward(const sim_mlp_weights *w, const float *d_x, long n, float *d
 size_t sim_mlp_workspace_bytes(long n);
 
 /* Population mean and std of each feature of x [n][16], accumulated in
- * double in a fixed order. */
+ * double in a fixed order: the network's input normalisation (per-channel,
+ * as for the appendix's policy inputs, App. B.1).  SIM_EINVAL for n < 1 or
+ * NULL, SIM_EWORKSPACE for a short or misaligned d_work. */
 int sim_mlp_stats(const float *d_x, long n, float *d_mean, float *d_std, void *d_work, size_t work_bytes,
                   void *stream);
 
 /* Gradient of the mean squared error over the 3n outputs of a batch of n
- * rows against targets t [.][3], with respect to the flat parameters.  Row
+ * rows against targets t [.][3], with respect to the flat parameters (the
+ * training half of the learned warm start; optimizer setup after App. B.2).  Row
  * j of the batch is row d_rows[j] of x [.][16] and t (d_rows: int32 [n],
  * device, each index in range; NULL = rows 0..n-1).  The forward rounds
  * weights and activations to bf16 as inference does; the backward runs in
@@ -230,19 +256,20 @@ int sim_mlp_grad(const float *d_params, const float *d_mean, const float *d_std,
                  const int32_t *d_rows, long n, float *d_grad, float *d_loss, void *d_work, size_t work_bytes,
                  void *stream);
 
-/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step
- * counts from 1) on the fp32 master parameters, after scaling the gradient
+/* One Adam step (the optimizer of App. B.2; beta1 0.9, beta2 0.999, eps
+ * 1e-8, bias-corrected; step counts from 1) on the fp32 master parameters, after scaling the gradient
  * to global L2 norm <= clip (clip 0: no clipping).  d_m, d_v: [5443]
  * moments, zero before the first step.  d_gnorm (may be NULL) gets the
  * gradient norm before clipping.  The caller owns the lr schedule. */
 int sim_mlp_adam(float *d_params, float *d_m, float *d_v, const float *d_grad, int step, float lr, float clip,
                  float *d_gnorm, void *stream);
 
-/* Inference copy of the parameters: d_wbf16 [5312] = bf16 (round to
+/* Inference copy of the parameters for sim_set_mlp: d_wbf16 [5312] = bf16 (round to
  * nearest even) of w1 | w2 | w3, d_bias [131] = b1 | b2 | b3. */
 int sim_mlp_export(const float *d_params, uint16_t *d_wbf16, float *d_bias, void *stream);
 
-/* Training rows from the last step (which must have run with export on):
+/* Training rows from the last step (which must have run with export on;
+ * SIM_EINVAL otherwise), the impulses the plain solver itself converged to:
  * for every new contact (feature 15 > 0) of every scene whose flags are all
  * clear, its 16 features into d_x [cap][16] and into d_t [cap][3] the
  * network's target, its converged impulses in units of |g| dt / k_n, i.e.
@@ -254,13 +281,15 @@ int sim_mlp_export(const float *d_params, uint16_t *d_wbf16, float *d_bias, void
  * number of rows there were.  Asynchronous on the handle's stream. */
 int sim_mlp_gather(sim_handle *h, float *d_x, float *d_t, long cap, float target_clip, long long *d_total);
 
-/* Masked reset: for every scene s with d_mask[s] != 0, copy its bodies'
- * pose [7][N] and velocity [6][N] from d_pose/d_vel (same layout as the
- * state), its joint angles from d_theta [S*7] (if arm), and clear its
- * contact cache.  Device pointers; asynchronous. */
+/* Masked reset of episodes (Sec. 4.3 caches assets for fast resets; Sec. 7
+ * names reloading on reset as a bottleneck of the training loop): for every
+ * scene s with d_mask[s] != 0, copy its bodies' pose [7][N] and velocity
+ * [6][N] from d_pose/d_vel (a pool laid out like the state), its joint
+ * angles from d_theta [S*7] (if arm), and clear its contact cache.  Device
+ * pointers; asynchronous; SIM_EINVAL on NULL. */
 int sim_reset(sim_handle *h, const uint8_t *d_mask, const float *d_pose, const float *d_vel, const float *d_theta);
 
-/* Phase tracing: when d_trace (device, [S][16] uint64) is non-NULL, every
+/* Phase tracing (profiling aid, no counterpart in the paper): when d_trace (device, [S][16] uint64) is non-NULL, every
  * later step writes 15 wall-clock timestamps per scene (constant-rate
  * counter) at its phase boundaries: start, bodies loaded, arm, AABBs, body
  * sort, sweep, pair sort, narrowphase, setup, contact lists, colouring
@@ -287,7 +316,8 @@ int sim_set_trace(sim_handle *h, uint64_t *d_trace);
 int sim_set_persistent(sim_handle *h, int on, int wave_max_bodies);
 
 /* ---- Checkpoint and resume ----------------------------------------------
- * A state blob holds what later steps depend on: pose, velocity, joint
+ * The state s_t of Sec. 2 as a blob, for resuming a batch: it holds what
+ * later steps depend on: pose, velocity, joint
  * angles and both contact caches (the warm-start impulses), with a header
  * naming the batch layout.  sim_save_state copies the state into d_blob
  * (device memory, 256-byte aligned, sim_state_bytes long); sim_load_state
@@ -299,10 +329,13 @@ int sim_save_state(sim_handle *h, void *d_blob);
 int sim_load_state(sim_handle *h, const void *d_blob);
 
 /* Device scratch (256-byte aligned) sim_autotune needs to save and restore
- * the simulation state: pose, velocity, joint angles and contact caches. */
+ * the simulation state: pose, velocity, joint angles and contact caches
+ * (0 for a NULL handle). */
 size_t sim_autotune_scratch_bytes(const sim_handle *h);
 
-/* Picks wave_max_bodies for the persistent launch by timing `steps` steps
+/* Autotuning of the persistent launch over the batch's own scenes (the
+ * parallel environments of Sec. 4.4, whose synchronisation Sec. 7 names as
+ * the loop's bound).  Picks wave_max_bodies by timing `steps` steps
  * (zero actions, dt, iters sweeps) for each candidate (0 and the powers of
  * two from 16 up to the largest scene) and restoring the state after each;
  * leaves the persistent launch on with the fastest and reports it in
@@ -311,8 +344,12 @@ size_t sim_autotune_scratch_bytes(const sim_handle *h);
 int sim_autotune(sim_handle *h, void *d_scratch, size_t scratch_bytes, int steps, float dt, int iters,
                  int *out_wave_max_bodies);
 
+/* The stream (hipStream_t, NULL = default) for later work of the handle. */
 int sim_set_stream(sim_handle *h, void *stream);
+/* Frees the handle's host metadata, graphs and capture stream (the
+ * workspace stays the caller's).  NULL is ignored. */
 void sim_destroy(sim_handle *h);
+/* Message of the calling thread's last failed call. */
 const char *sim_last_error(void);
 
 #ifdef __cplusplus

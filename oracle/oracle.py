@@ -32,7 +32,7 @@ DEFAULTS = dict(margin=0.02, baumgarte=0.2, slop=0.005, rest_thresh=0.5,
 def build(force: bool = False) -> str:
     """Compile rbo.c with gcc into liboracle.so next to it."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-Wall",
+        cmd = ["gcc", "-O3", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-Wall",
                "-o", LIB + ".tmp", SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(LIB + ".tmp", LIB)

@@ -56,6 +56,7 @@ struct Layout {
   size_t off_st[7];
   size_t off_gather, off_gcount;
   size_t off_queue, off_head;
+  size_t off_actions;
   size_t total;
 };
 
@@ -99,6 +100,7 @@ Layout make_layout(long S, long N, long PM, long CM) {
   L.off_gcount = take(4 * S);
   L.off_queue = take(4 * 2 * S);  // persistent launch: team queue, wave queue
   L.off_head = take(256);
+  L.off_actions = take(4 * 7 * S);  // persistent launch: the step's actions at a fixed address
   L.total = o;
   return L;
 }
@@ -576,6 +578,18 @@ int sim_step(sim_handle* h, const float* d_actions, float dt, int iters) {
   P.iters = iters;
   int rc;
   if (h->persistent) {
+    // The graph's kernel reads the actions from a fixed buffer, so that a
+    // new action array each step does not force a new capture.
+    if (h->arm) {
+      float* fixed = at<float>(h, h->lay.off_actions);
+      const size_t bytes = sizeof(float) * 7 * (size_t)h->S;
+      hipError_t e = d_actions ? hipMemcpyAsync(fixed, d_actions, bytes, hipMemcpyDeviceToDevice, h->stream)
+                               : hipMemsetAsync(fixed, 0, bytes, h->stream);
+      if (e != hipSuccess) return fail(SIM_EDEVICE, std::string("action copy failed: ") + hipGetErrorString(e));
+      P.actions = fixed;
+    } else {
+      P.actions = nullptr;
+    }
     rc = launch_persistent(h, P);
     if (rc != 0) return fail(SIM_EDEVICE, std::string("persistent step failed: ") + hipGetErrorString((hipError_t)rc));
   } else {

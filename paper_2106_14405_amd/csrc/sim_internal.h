@@ -135,6 +135,10 @@ struct LdsLayout {
 };
 
 constexpr int kMiscWords = 64;
+// word slots of the misc region: counters, flags, per-wave partials (one
+// word per wave of a 256-thread team from M_WAVE and from M_SCAN)
+enum { M_NPAIRS = 0, M_NCONT = 1, M_FLAGS = 2, M_NCOL = 3, M_CHANGED = 5, M_WAVE = 16, M_SCAN = 32 };
+static_assert(M_SCAN + kMaxThreads / 64 <= kMiscWords && M_WAVE + kMaxThreads / 64 <= M_SCAN, "misc slots");
 constexpr int kDynWords = 12;  // words per body in the dyn region (three float4)
 constexpr int kRec = 5;        // float4 per contact in the solver records
 

@@ -33,8 +33,6 @@ namespace rbs {
 
 typedef unsigned long long u64;
 
-enum { M_NPAIRS = 0, M_NCONT = 1, M_FLAGS = 2, M_NCOL = 3, M_CHANGED = 5, M_WAVE = 16, M_SCAN = 32 };
-
 // The threads that step one scene: a whole workgroup, or a single wave of a
 // larger workgroup (persistent launch).  A team starts on a wave boundary.
 template <bool kWave>

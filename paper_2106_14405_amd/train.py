@@ -117,6 +117,22 @@ def summary(r: dict, skip: int = 0) -> dict:
                 ms=float(np.mean(r["ms"][skip:])), scene_steps=int(m.sum()))
 
 
+def paired(ra: dict, rb: dict, skip: int = 0) -> dict:
+    """Paired comparison of two modes run on the same scenes: per scene, the
+    mean sweeps over the scene-steps with contacts in both runs, and per step
+    the batch's wall milliseconds; mean difference (a - b) and its 95%
+    interval (1.96 standard errors)."""
+    sa, sb = ra["sweeps"][skip:].astype(np.float64), rb["sweeps"][skip:].astype(np.float64)
+    m = (ra["contacts"][skip:] > 0) & (rb["contacts"][skip:] > 0)
+    cnt = m.sum(axis=0)
+    ok = cnt > 0
+    d = ((sa * m).sum(axis=0)[ok] - (sb * m).sum(axis=0)[ok]) / cnt[ok]
+    dm = np.asarray(ra["ms"][skip:], np.float64) - np.asarray(rb["ms"][skip:], np.float64)
+    ci = lambda x: float(1.96 * x.std(ddof=1) / np.sqrt(x.size)) if x.size > 1 else float("nan")
+    return dict(sweeps=float(d.mean()) if d.size else 0.0, sweeps_ci95=ci(d), ms=float(dm.mean()),
+                ms_ci95=ci(dm), scenes=int(d.size), steps=int(dm.size))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--scenes", type=int, default=512)
