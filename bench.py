@@ -64,11 +64,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--settle", type=int, default=300, help="untimed settling steps before any mode runs")
-    ap.add_argument("--workload", default="clutter", choices=["clutter", "drop", "uneven"])
+    ap.add_argument("--workload", default="clutter", choices=["clutter", "drop", "uneven", "scale"])
     ap.add_argument("--scenes", type=int, default=None)
-    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--tol", type=float, default=None, help="residual tolerance (m/s); 1e-4, scale 1e-5")
     ap.add_argument("--cap", type=int, default=None, help="sweep cap at the tolerance")
-    ap.add_argument("--headline", default="prev", choices=MODES)
+    ap.add_argument("--headline", default=None, choices=MODES, help="prev; scale: learned")
     ap.add_argument("--modes", default=",".join(MODES))
     ap.add_argument("--no-replay", action="store_true", help="skip the statistics replay (profiling runs)")
     ap.add_argument("--threads", type=int, default=64)
@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--max-pairs", type=int, default=None)
     ap.add_argument("--launch", default=None, choices=["plain", "persistent"],
                     help="uneven workload: persistent (default) or one workgroup per scene")
+    ap.add_argument("--pool", type=int, default=4, help="uneven workload: fresh states per scene in the reset pool")
     ap.add_argument("--learned-eval", type=int, default=1)
     ap.add_argument("--learned-scenes", type=int, default=2048)
     ap.add_argument("--learned-steps", type=int, default=240)
@@ -125,6 +126,11 @@ def measured_traffic(workload, tag):
     return d.get("hbm_bytes_per_launch")
 
 
+def progress(msg):
+    """One line on stderr per finished phase."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def host_threads():
     n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     lim = os.environ.get("OMP_NUM_THREADS")
@@ -167,16 +173,46 @@ def cpu_baseline(batch, settle, timed_steps, cap, tol, warm, arm):
                         f"one chunk of scenes each; {secs:.1f} s wall"))
 
 
-def reset_schedule(n_scenes, n_steps, seed=7):
-    """[n_steps, S] uint8 masks: each scene restarts after U[100, 300] steps."""
+def batch_in_chunks(fn, n, chunk=1024):
+    """A batch generated in chunks of scenes (fn(first scene, count)), with a
+    progress line per chunk; chunk k uses seeds shifted by its first scene."""
+    from paper_2106_14405_amd import scenes as S
+    parts = []
+    for k in range(0, n, chunk):
+        parts.append(fn(k, min(chunk, n - k)))
+        progress(f"generated {min(k + chunk, n)} of {n} scenes")
+    return concat_batches(parts) if len(parts) > 1 else parts[0]
+
+
+def concat_batches(parts):
+    from paper_2106_14405_amd import scenes as S
+    off = [np.zeros(1, np.int32)]
+    base = 0
+    for b in parts:
+        off.append(b.body_offset[1:] + base)
+        base += b.n_bodies
+    cat = lambda k: np.concatenate([getattr(b, k) for b in parts])
+    return S.Batch(body_offset=np.concatenate(off).astype(np.int32), shape=cat("shape"), motion=cat("motion"),
+                   param=cat("param"), mass=cat("mass"), friction=cat("friction"), restitution=cat("restitution"),
+                   pose=cat("pose"), vel=cat("vel"), arm=parts[0].arm, arm_base=cat("arm_base"),
+                   arm_theta=cat("arm_theta"))
+
+
+def reset_schedule(n_scenes, n_steps, pool_size, seed=7):
+    """[n_steps, S] uint8 masks (each scene restarts after U[100, 300] steps)
+    and int32 pool entries (a scene's r-th reset takes entry r mod K)."""
     rng = np.random.default_rng(seed)
     m = np.zeros((n_steps, n_scenes), np.uint8)
+    idx = np.zeros((n_steps, n_scenes), np.int32)
+    done = np.zeros(n_scenes, np.int64)
     nxt = rng.integers(100, 301, size=n_scenes)
     for t in range(n_steps):
         hit = nxt == t
         m[t, hit] = 1
+        idx[t] = done % pool_size
+        done[hit] += 1
         nxt[hit] += rng.integers(100, 301, size=int(hit.sum()))
-    return m
+    return m, idx
 
 
 def workload_name(w, n_scenes, batch):
@@ -187,6 +223,11 @@ def workload_name(w, n_scenes, batch):
         c = batch.counts()
         return (f"uneven: {n_scenes} drop scenes, {int(c.min())}-{int(c.max())} dynamic spheres/boxes "
                 f"(log-uniform), {batch.n_bodies} bodies")
+    if w == "scale":
+        c = batch.counts() - 27
+        return (f"scale: {n_scenes} clutter scenes, {int(c.min())}-{int(c.max())} dynamic spheres/boxes/capsules "
+                f"(log-uniform, mean {c.mean():.0f}) + 20 static boxes + 7-link kinematic arm, {batch.n_bodies} "
+                "bodies, settled")
     return f"drop: {n_scenes} scenes x 64 dynamic bodies (32 spheres + 32 boxes), settled"
 
 
@@ -245,6 +286,13 @@ def main():
         max_contacts = a.max_contacts or 512
         max_pairs = a.max_pairs or max_contacts
         cap = a.cap or 1000
+    elif a.workload == "scale":
+        n_scenes = a.scenes or 16384
+        batch_fn = lambda n: batch_in_chunks(lambda k, m: S.batch_scale(m, seed0=30000 + k, lo=64, hi=1024), n)
+        arm = True
+        max_contacts = a.max_contacts or 4096
+        max_pairs = a.max_pairs or 6144    # a settled 1,024-body pile reaches 3.9 pairs per body
+        cap = a.cap or 500
     elif a.workload == "uneven":
         n_scenes = a.scenes or 4096
         batch_fn = lambda n: S.batch_uneven(n, seed0=20000, lo=16, hi=512)
@@ -259,11 +307,16 @@ def main():
         max_contacts = a.max_contacts or 384
         max_pairs = a.max_pairs or max_contacts
         cap = a.cap or 1000
+    if a.tol is None:
+        a.tol = 1e-5 if a.workload == "scale" else 1e-4
+    if a.headline is None:
+        a.headline = "learned" if a.workload == "scale" else "prev"
     modes = [m for m in a.modes.split(",") if m]
     if a.headline not in modes:
         modes.append(a.headline)
     # every host-side input is generated before the GPU is touched
     batch = batch_fn(n_scenes)
+    pool = S.reset_pool(batch, a.pool, seed=40000, kind="drop") if a.workload == "uneven" else None
     cpu_batch = None
     if a.cpu_baseline and a.workload != "uneven":
         cpu_batch = batch_fn(a.cpu_scenes_per_thread * host_threads())
@@ -282,14 +335,17 @@ def main():
     acts = torch.as_tensor(acts_np, device=dev) if arm else None
     resets = None
     tuned = None
-    persistent = a.workload == "uneven" and a.launch != "plain"
+    persistent = a.workload in ("uneven", "scale") and a.launch != "plain"
+    if persistent:
+        sim.set_persistent(True)
+        tuned = sim.autotune(steps=3, dt=DT, iters=20)
+        progress(f"autotuned: wave_max_bodies {tuned}")
     if a.workload == "uneven":
-        if persistent:
-            sim.set_persistent(True)
-            tuned = sim.autotune(steps=3, dt=DT, iters=20)
-        resets = torch.as_tensor(reset_schedule(n_scenes, T0 + W + K), device=dev)
-        pose0 = sim.pose.clone()
-        vel0 = sim.vel.clone()
+        masks, index = reset_schedule(n_scenes, T0 + W + K, a.pool)
+        resets = torch.as_tensor(masks, device=dev)
+        reset_index = torch.as_tensor(index, device=dev)
+        pool_pose = torch.as_tensor(np.ascontiguousarray(pool[0].transpose(0, 2, 1)), device=dev)
+        pool_vel = torch.as_tensor(np.ascontiguousarray(pool[1].transpose(0, 2, 1)), device=dev)
     net = None
     if "learned" in modes:
         wpath = os.path.join(ROOT, "paper_2106_14405_amd", "weights", "warmstart_drop.npz")
@@ -298,7 +354,7 @@ def main():
 
     def one(t, iters):
         if resets is not None:
-            sim.reset(resets[t], pose0, vel0)
+            sim.reset(resets[t], pool_pose, pool_vel, None, reset_index[t])
         sim.step(acts[t] if arm else None, DT, iters)
 
     # settle (untimed): classic warm start, 20 sweeps per step
@@ -308,6 +364,7 @@ def main():
     torch.cuda.synchronize()
     settled = sim.save_state()
     contacts_settled = float(sim.stats["contacts"].float().mean().item())
+    progress(f"settled {T0} steps, {contacts_settled:.1f} contacts per scene")
 
     results = {}
     for name in modes:
@@ -343,6 +400,7 @@ def main():
             r["pairs_per_scene"] = float(rec["pairs"].mean())
             r["colours_per_scene"] = float(rec["colours"].mean())
         results[name] = r
+        progress(f"{name}: {r['ms_per_step']:.3f} ms per step")
     sim.close()
     del sim
     torch.cuda.synchronize()
@@ -381,7 +439,8 @@ def main():
             "threads_per_scene": a.threads if not persistent else "autotuned: 64 (one wave) or 256",
             "max_contacts_per_scene": max_contacts, "max_pairs_per_scene": max_pairs,
             **({"launch": "persistent, HIP graph" if persistent else "one workgroup per scene",
-                "wave_max_bodies": tuned, "resets": "each scene after U[100, 300] steps"}
+                "wave_max_bodies": tuned,
+                "resets": f"each scene after U[100, 300] steps, from a pool of {a.pool} fresh states per scene"}
                if a.workload == "uneven" else {}),
         },
         "roofline": {
@@ -402,6 +461,7 @@ def main():
         lv = learned_vs_plain(a.learned_scenes, a.learned_steps)
         if lv is not None:
             out["learned_vs_plain"] = lv
+        progress("learned vs plain done")
     if cpu_batch is not None:
         out["cpu_baseline"] = cpu_baseline(cpu_batch, T0, a.cpu_steps, cap, a.tol, a.headline, arm)
     print(json.dumps(out), flush=True)

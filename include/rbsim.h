@@ -40,18 +40,19 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 1
+#define SIM_ABI_VERSION 2
 
 enum { SIM_OK = 0, SIM_EINVAL = -1, SIM_EDEVICE = -2, SIM_EWORKSPACE = -3, SIM_EABI = -4, SIM_ECAPACITY = -5 };
 enum { SIM_SPHERE = 0, SIM_BOX = 1, SIM_CAPSULE = 2 };
 enum { SIM_DYNAMIC = 0, SIM_STATIC = 1, SIM_KINEMATIC = 2 };
 enum { SIM_COLD = 0, SIM_PREV = 1, SIM_LEARNED = 2 };
 enum { SIM_PGS = 0, SIM_JACOBI = 1 };
-enum { SIM_FLAG_NONFINITE = 1, SIM_FLAG_CAPACITY = 2, SIM_FLAG_NOT_CONVERGED = 4, SIM_FLAG_FELLBACK = 8 };
+enum { SIM_FLAG_NONFINITE = 1, SIM_FLAG_CAPACITY = 2, SIM_FLAG_NOT_CONVERGED = 4, SIM_FLAG_FELLBACK = 8,
+       SIM_FLAG_BAD_RESET = 16 };
 
 /* Batch descriptor.  N = body_offset[num_scenes] bodies in total; scene s
- * owns bodies [body_offset[s], body_offset[s+1]).  All h_* pointers are
- * host memory read during sim_create. */
+ * owns bodies [body_offset[s], body_offset[s+1]), at most 2046 bodies.  All
+ * h_* pointers are host memory read during sim_create. */
 typedef struct sim_batch_desc {
     int abi_version;             /* SIM_ABI_VERSION */
     int num_scenes;              /* S >= 1 */
@@ -86,6 +87,11 @@ typedef struct sim_batch_desc {
                                     0: always run the requested sweeps */
     int threads;                 /* threads per scene workgroup: 64, 128, 192 or 256 (0: 128) */
     void *stream;                /* hipStream_t for all work; NULL = default stream */
+    int hbm_min_bodies;          /* 0: a scene keeps its step's working set in LDS when it fits
+                                    a workgroup's LDS in every solver mode, else in global memory
+                                    (HBM, through the caches); > 0: also every scene of at least
+                                    this many bodies uses global memory.  Results do not depend
+                                    on where the working set lives. */
 } sim_batch_desc;
 
 typedef struct sim_handle sim_handle;
@@ -281,13 +287,30 @@ int sim_mlp_export(const float *d_params, uint16_t *d_wbf16, float *d_bias, void
  * number of rows there were.  Asynchronous on the handle's stream. */
 int sim_mlp_gather(sim_handle *h, float *d_x, float *d_t, long cap, float target_clip, long long *d_total);
 
-/* Masked reset of episodes (Sec. 4.3 caches assets for fast resets; Sec. 7
- * names reloading on reset as a bottleneck of the training loop): for every
- * scene s with d_mask[s] != 0, copy its bodies' pose [7][N] and velocity
- * [6][N] from d_pose/d_vel (a pool laid out like the state), its joint
- * angles from d_theta [S*7] (if arm), and clear its contact cache.  Device
- * pointers; asynchronous; SIM_EINVAL on NULL. */
-int sim_reset(sim_handle *h, const uint8_t *d_mask, const float *d_pose, const float *d_vel, const float *d_theta);
+/* Masked reset of episodes from a pre-generated pool of fresh states
+ * (Sec. 4.3 prefetches and caches assets so that an episode reset does not
+ * reload them; Sec. 7 names reloading on reset as a bottleneck of the
+ * training loop).  The pool holds `size` = K >= 1 complete states of the
+ * batch, device memory laid out like the state: pose [K][7][N], velocity
+ * [K][6][N] and, for arm batches, joint angles [K][S][7] (NULL otherwise).
+ * For every scene s with d_mask[s] != 0 the library copies entry
+ * k = index[s] of the pool into the scene's bodies (and joint angles,
+ * recomputing the arm link poses) and clears its contact cache; index is a
+ * device int32 [S] (NULL: entry 0 for every scene).  A scene whose index
+ * lies outside [0, K) is left unchanged and gets SIM_FLAG_BAD_RESET in its
+ * stats flags (visible until the next step).  Static and kinematic bodies
+ * are copied like the others.  Asynchronous on the handle's stream;
+ * SIM_EINVAL on NULL mask, pool, pose or vel, size < 1, or a missing theta
+ * for an arm batch. */
+typedef struct sim_reset_pool {
+    int size;                 /* K */
+    const float *pose;        /* [K][7][N] */
+    const float *vel;         /* [K][6][N] */
+    const float *theta;       /* [K][S][7] or NULL when the batch has no arm */
+    const int32_t *index;     /* [S] pool entry per scene, or NULL (entry 0) */
+} sim_reset_pool;
+
+int sim_reset(sim_handle *h, const uint8_t *d_mask, const sim_reset_pool *pool);
 
 /* Phase tracing (profiling aid, no counterpart in the paper): when d_trace (device, [S][16] uint64) is non-NULL, every
  * later step writes 15 wall-clock timestamps per scene (constant-rate

@@ -71,7 +71,7 @@ class Out(C.Structure):
                 ("c_lambda", _P(_d)), ("c_colour", _P(C.c_int32)), ("c_feat", _P(_d)),
                 ("n_colours", _P(C.c_int32)), ("sweeps", _P(C.c_int32)),
                 ("residual", _P(_d)), ("arm_force", _P(_d)), ("flags", _P(C.c_int32)),
-                ("ambiguous", _P(C.c_int32))]
+                ("ambiguous", _P(C.c_int32)), ("tied", _P(C.c_uint8)), ("tol_gap", _P(_d))]
 
 
 _lib = None
@@ -211,13 +211,14 @@ class OracleSim:
                 c_feat=np.zeros(S * max_contacts * 16),
                 n_colours=np.zeros(S, np.int32), sweeps=np.zeros(S, np.int32),
                 residual=np.zeros(S), arm_force=np.zeros(S), flags=np.zeros(S, np.int32),
-                ambiguous=np.zeros(S, np.int32))
+                ambiguous=np.zeros(S, np.int32), tied=np.zeros(int(self.off[-1]), np.uint8),
+                tol_gap=np.zeros(S))
             out = Out()
             out.max_pairs = max_pairs
             out.max_contacts = max_contacts
             for k, v in res.items():
                 ct = {np.dtype(np.int32): C.c_int32, np.dtype(np.uint32): C.c_uint32,
-                      np.dtype(np.float64): _d}[v.dtype]
+                      np.dtype(np.uint8): C.c_uint8, np.dtype(np.float64): _d}[v.dtype]
                 setattr(out, k, _ptr(v, ct))
         act = None
         if actions is not None:

@@ -825,7 +825,7 @@ static int is_dyn(const Body *b) { return b->motion == ORA_DYNAMIC; }
 /* Brute-force pair set: every i < j with at least one dynamic body whose
  * closed AABBs overlap on x, y and z, then (i, ground) for dynamic i whose
  * AABB reaches z <= 0; lexicographic order. */
-static int brute_pairs(const Body *B, int n, uint32_t *keys, int cap, int *amb) {
+static int brute_pairs(const Body *B, int n, uint32_t *keys, int cap, int *amb, uint8_t *tied) {
     int np = 0;
     for (int i = 0; i < n; i++) {
         for (int j = i + 1; j < n; j++) {
@@ -836,14 +836,20 @@ static int brute_pairs(const Body *B, int n, uint32_t *keys, int cap, int *amb) 
                 double s2 = comp(B[j].hi, a) - comp(B[i].lo, a);
                 sl = fmin(sl, fmin(s1, s2));
             }
-            if (fabs(sl) < BAND) (*amb)++;
+            if (fabs(sl) < BAND) {
+                (*amb)++;
+                if (tied) tied[i] = tied[j] = 1;
+            }
             if (sl >= 0) {
                 if (np < cap) keys[np] = ((uint32_t)i << 16) | (uint32_t)j;
                 np++;
             }
         }
         if (is_dyn(&B[i])) {
-            if (fabs(B[i].lo.z) < BAND) (*amb)++;
+            if (fabs(B[i].lo.z) < BAND) {
+                (*amb)++;
+                if (tied) tied[i] = 1;
+            }
             if (B[i].lo.z <= 0) {
                 if (np < cap) keys[np] = ((uint32_t)i << 16) | PAIR_GROUND;
                 np++;
@@ -1130,13 +1136,19 @@ static int lookup(const ora_cache *cache, int s, uint32_t key) {
 
 static int finite3(V a) { return isfinite(a.x) && isfinite(a.y) && isfinite(a.z); }
 
+/* Sweeps until the residual reaches tol (tol > 0) or iters sweeps ran.
+ * *gap receives the smallest |R - tol| / tol over the sweeps whose residual
+ * was tested against the tolerance (infinity when none was): how close the
+ * stopping decision came to going the other way. */
 static int solve(Body *B, int nb, Con *C, const int *order, int nc, int iters, double tol,
-                 int solver, double *res) {
+                 int solver, double *res, double *gap) {
     int sw = 0;
     double R = 0;
+    *gap = INFINITY;
     for (int it = 0; it < iters; it++) {
         R = solver == ORA_JACOBI ? jacobi_sweep(B, nb, C, order, nc) : pgs_sweep(B, C, order, nc);
         sw++;
+        if (tol > 0) *gap = fmin(*gap, fabs(R - tol) / tol);
         if (tol > 0 && R <= tol) break;
     }
     *res = R;
@@ -1216,7 +1228,8 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
     for (int i = 0; i < nb; i++) body_aabb(&B[i], margin);
     int maxp = nb * (nb + 1) / 2 + 1;
     uint32_t *pk = malloc(sizeof(uint32_t) * maxp);
-    int np = brute_pairs(B, nb, pk, maxp, &amb);
+    uint8_t *tied = calloc((size_t)(nb ? nb : 1), 1);
+    int np = brute_pairs(B, nb, pk, maxp, &amb, tied);
 
     /* 5. narrowphase in canonical pair order; 6. contact list */
     int capc = 4 * np + 1;
@@ -1229,12 +1242,16 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         GA.shape = B[a].shape; GA.x = B[a].x; GA.R = B[a].R;
         memcpy(GA.prm, B[a].prm, sizeof GA.prm);
         PC pc[4];
-        int k;
+        int k, amb0 = amb;
         if (ground) k = ground_contacts(&GA, margin, pc, &amb);
         else {
             GB.shape = B[b].shape; GB.x = B[b].x; GB.R = B[b].R;
             memcpy(GB.prm, B[b].prm, sizeof GB.prm);
             k = collide(&GA, &GB, margin, pc, &amb);
+        }
+        if (amb != amb0) {
+            tied[a] = 1;
+            if (!ground) tied[b] = 1;
         }
         for (int i = 0; i < k; i++) {
             Con *c = &C[nc++];
@@ -1369,8 +1386,8 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
     } else {
         warm_apply(B, C, order, nc, -1);
     }
-    double R = 0;
-    int sweeps = solve(B, nb, C, order, nc, iters, tol, solver, &R);
+    double R = 0, gap = INFINITY;
+    int sweeps = solve(B, nb, C, order, nc, iters, tol, solver, &R, &gap);
     /* a step counts as solved only once its residual reached the tolerance */
     if (tol > 0 && R > tol) flags |= ORA_F_NOT_CONVERGED;
     free(vsave);
@@ -1448,7 +1465,10 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         if (out->arm_force) out->arm_force[s] = force;
         if (out->flags) out->flags[s] = flags;
         if (out->ambiguous) out->ambiguous[s] = amb;
+        if (out->tied) memcpy(out->tied + b0, tied, (size_t)nb);
+        if (out->tol_gap) out->tol_gap[s] = gap;
     }
+    free(tied);
     free(order);
     free(C);
     free(pk);
@@ -1474,7 +1494,7 @@ int ora_pairs(const ora_model *m, const double *pose, int s, uint32_t *keys, int
     load_bodies(m, pose, vel, s, B);
     for (int i = 0; i < nb; i++) body_aabb(&B[i], m->margin);
     int amb = 0;
-    int n = brute_pairs(B, nb, keys, cap, &amb);
+    int n = brute_pairs(B, nb, keys, cap, &amb, NULL);
     free(vel);
     free(B);
     return n;

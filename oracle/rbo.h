@@ -91,6 +91,8 @@ typedef struct ora_out {          /* optional per-scene outputs (any pointer may
     double *arm_force;            /* [S] N */
     int32_t *flags;               /* [S] */
     int32_t *ambiguous;           /* [S] decisions that fell inside the tie band */
+    uint8_t *tied;                /* [N] 1 for the bodies of a pair with such a decision */
+    double *tol_gap;              /* [S] min over the tested sweeps of |residual - tol| / tol */
 } ora_out;
 
 /* One step for scenes [s0, s1).  pose [N*7] (x, q w x y z), vel [N*6] (v, w),

@@ -11,13 +11,13 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbsim.so")
 
-SIM_ABI_VERSION = 1
+SIM_ABI_VERSION = 2
 SIM_OK, SIM_EINVAL, SIM_EDEVICE, SIM_EWORKSPACE, SIM_EABI, SIM_ECAPACITY = 0, -1, -2, -3, -4, -5
 SPHERE, BOX, CAPSULE = 0, 1, 2
 DYNAMIC, STATIC, KINEMATIC = 0, 1, 2
 COLD, PREV, LEARNED = 0, 1, 2
 PGS, JACOBI = 0, 1
-FLAG_NONFINITE, FLAG_CAPACITY, FLAG_NOT_CONVERGED, FLAG_FELLBACK = 1, 2, 4, 8
+FLAG_NONFINITE, FLAG_CAPACITY, FLAG_NOT_CONVERGED, FLAG_FELLBACK, FLAG_BAD_RESET = 1, 2, 4, 8, 16
 
 _P = C.POINTER
 _f = C.c_float
@@ -35,7 +35,7 @@ class BatchDesc(C.Structure):
         ("ground_friction", _f), ("ground_restitution", _f),
         ("max_pairs", C.c_int), ("max_contacts", C.c_int),
         ("solver", C.c_int), ("warm_start", C.c_int), ("tolerance", _f), ("threads", C.c_int),
-        ("stream", C.c_void_p),
+        ("stream", C.c_void_p), ("hbm_min_bodies", C.c_int),
     ]
 
 
@@ -55,6 +55,11 @@ class ContactView(C.Structure):
 class StatsView(C.Structure):
     _fields_ = [("pairs", C.c_void_p), ("contacts", C.c_void_p), ("colours", C.c_void_p), ("sweeps", C.c_void_p),
                 ("flags", C.c_void_p), ("residual", C.c_void_p), ("arm_force", C.c_void_p)]
+
+
+class ResetPool(C.Structure):
+    _fields_ = [("size", C.c_int), ("pose", C.c_void_p), ("vel", C.c_void_p), ("theta", C.c_void_p),
+                ("index", C.c_void_p)]
 
 
 class MlpWeights(C.Structure):
@@ -93,7 +98,7 @@ def load():
     L.sim_set_export.argtypes = [C.c_void_p, C.c_int]
     L.sim_set_solver.argtypes = [C.c_void_p, C.c_int, C.c_int, _f]
     L.sim_set_mlp.argtypes = [C.c_void_p] + [C.c_void_p] * 8
-    L.sim_reset.argtypes = [C.c_void_p] + [C.c_void_p] * 4
+    L.sim_reset.argtypes = [C.c_void_p, C.c_void_p, _P(ResetPool)]
     L.sim_set_stream.argtypes = [C.c_void_p, C.c_void_p]
     L.sim_set_trace.argtypes = [C.c_void_p, C.c_void_p]
     L.sim_destroy.argtypes = [C.c_void_p]

@@ -20,6 +20,7 @@
 extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L, int threads, int grid,
                                hipStream_t stream);
 extern "C" int rbs_set_step_lds_limit(int bytes);
+extern "C" int rbs_launch_step_hbm(const rbs::StepParams* P, const rbs::LdsLayout* L, int n, hipStream_t stream);
 extern "C" int rbs_launch_persistent(const rbs::StepParams* P, const rbs::QueueParams* Q, int grid,
                                      hipStream_t stream);
 extern "C" int rbs_mlp_forward(const rbs::MlpParams* M, const float* x, long n, float* y, hipStream_t st);
@@ -34,9 +35,9 @@ extern "C" int rbs_gather(const int32_t* count, const int32_t* flags, int S, int
                           const float* lam, float inv_gdt, float tclip, int64_t* offs, int32_t* cnt, float* x,
                           float* t, long cap, long long* total, hipStream_t st);
 extern "C" int rbs_launch_arm_pose(const rbs::StepParams* P, const uint8_t* mask, hipStream_t stream);
-extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, const float* pool_pose,
-                                const float* pool_vel, const float* pool_theta, int32_t* count_a, int32_t* count_b,
-                                hipStream_t stream);
+extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, int K, const int32_t* index,
+                                const float* pool_pose, const float* pool_vel, const float* pool_theta,
+                                int32_t* count_a, int32_t* count_b, hipStream_t stream);
 
 namespace {
 
@@ -57,12 +58,13 @@ struct Layout {
   size_t off_gather, off_gcount;
   size_t off_queue, off_head;
   size_t off_actions;
+  size_t off_glist, off_gscr;
   size_t total;
 };
 
 size_t align256(size_t x) { return (x + 255u) & ~size_t(255u); }
 
-Layout make_layout(long S, long N, long PM, long CM) {
+Layout make_layout(long S, long N, long PM, long CM, long n_hbm, long hbm_words) {
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
@@ -101,6 +103,8 @@ Layout make_layout(long S, long N, long PM, long CM) {
   L.off_queue = take(4 * 2 * S);  // persistent launch: team queue, wave queue
   L.off_head = take(256);
   L.off_actions = take(4 * 7 * S);  // persistent launch: the step's actions at a fixed address
+  L.off_glist = take(4 * S);                    // scenes stepped with their working set in global memory
+  L.off_gscr = take(4 * (size_t)n_hbm * hbm_words);  // and those working sets
   L.total = o;
   return L;
 }
@@ -130,6 +134,13 @@ struct sim_handle {
   uint64_t* trace;
   int lds_limit;
   std::vector<int> body_offset;  // host copy, [S + 1]
+  // scenes whose working set lives in global memory, and the largest body
+  // count of the others
+  std::vector<int> hbm;
+  long hbm_words = 0;
+  int nb_lds = 0;
+  hipStream_t capture_stream2 = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // persistent launch
   bool persistent = false;
   int wave_max_bodies = 0;
@@ -144,6 +155,9 @@ sim_handle::~sim_handle() {
   for (int k = 0; k < 2; k++)
     if (exec[k]) hipGraphExecDestroy(exec[k]);
   if (capture_stream) hipStreamDestroy(capture_stream);
+  if (capture_stream2) hipStreamDestroy(capture_stream2);
+  if (fork_ev) hipEventDestroy(fork_ev);
+  if (join_ev) hipEventDestroy(join_ev);
 }
 
 namespace {
@@ -219,6 +233,9 @@ rbs::StepParams params(sim_handle* h) {
   P.solver = h->solver;
   P.mlp = h->mlp;
   P.scene_list = at<int32_t>(h, L.off_scene_list);
+  P.gscr = at<float>(h, L.off_gscr);
+  P.gwords = h->hbm_words;
+  P.glist = at<int32_t>(h, L.off_glist);
   P.trace = h->trace;
   return P;
 }
@@ -241,7 +258,7 @@ int validate(const sim_batch_desc* d, Caps* caps) {
   for (int s = 0; s < d->num_scenes; s++) {
     int n = d->h_body_offset[s + 1] - d->h_body_offset[s];
     if (n < 0) return fail(SIM_EINVAL, "body_offset must be non-decreasing");
-    if (n > rbs::kMaxBodiesPerScene) return fail(SIM_ECAPACITY, "a scene exceeds 1024 bodies");
+    if (n > rbs::kMaxBodiesPerScene) return fail(SIM_ECAPACITY, "a scene exceeds 2046 bodies");
     if (d->arm && n < 7) return fail(SIM_EINVAL, "arm scenes need at least 7 bodies");
     NB = std::max(NB, n);
   }
@@ -275,6 +292,7 @@ int validate(const sim_batch_desc* d, Caps* caps) {
   if (d->warm_start < SIM_COLD || d->warm_start > SIM_LEARNED) return fail(SIM_EINVAL, "bad warm start");
   if (!(d->tolerance >= 0.f)) return fail(SIM_EINVAL, "tolerance must be >= 0");
   if (!(d->margin >= 0.f) || !(d->slop >= 0.f) || !(d->baumgarte >= 0.f)) return fail(SIM_EINVAL, "bad constants");
+  if (d->hbm_min_bodies < 0) return fail(SIM_EINVAL, "hbm_min_bodies must be >= 0");
   caps->NB = NB;
   caps->N = N;
   caps->ok = true;
@@ -295,6 +313,45 @@ int device_lds_limit() {
   return v;
 }
 
+// LDS words a 256-thread workgroup of the persistent launch may use for a
+// scene (the device limit less the kernel's static words).
+int team_lds_words(int lds_limit) { return ((lds_limit - 256) / 4) & ~15; }
+
+// Working-set words of a scene of nb bodies in its largest solver mode
+// (Jacobi with the learned start) for a 256-thread team.
+long worst_words(int nb, int PM, int CM) {
+  return rbs::lds_layout(nb, rbs::scene_cap(nb, PM), rbs::scene_cap(nb, CM), 4, rbs::SOLVER_JACOBI, rbs::WARM_LEARNED)
+      .total;
+}
+
+// Scenes stepped with their working set in global memory: those whose
+// largest working set exceeds a workgroup's LDS, and those of at least
+// min_bodies bodies when min_bodies > 0.  Largest first; words: the region
+// each gets (the largest such working set, a multiple of 64 words).
+struct HbmSplit {
+  std::vector<int> scenes;
+  long words = 0;
+  int nb_lds = 0;  // largest body count among the other scenes
+};
+
+HbmSplit hbm_split(const int32_t* off, int S, int PM, int CM, int lds_limit, int min_bodies) {
+  HbmSplit r;
+  const long budget = team_lds_words(lds_limit);
+  for (int s = 0; s < S; s++) {
+    const int nb = off[s + 1] - off[s];
+    const long w = worst_words(nb, PM, CM);
+    if (w > budget || (min_bodies > 0 && nb >= min_bodies)) {
+      r.scenes.push_back(s);
+      r.words = std::max(r.words, (w + 63) & ~63L);
+    } else {
+      r.nb_lds = std::max(r.nb_lds, nb);
+    }
+  }
+  std::stable_sort(r.scenes.begin(), r.scenes.end(),
+                   [&](int a, int b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
+  return r;
+}
+
 // Persistent launch: a queue for whole-workgroup teams and one for single-wave
 // teams, each in descending body count (ties by scene index).  A scene goes
 // to a wave when it has at most wave_max_bodies bodies and its working set
@@ -305,9 +362,12 @@ int build_queues(sim_handle* h, int wave_max_bodies) {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
     return fail(SIM_EDEVICE, "multiprocessor count unavailable");
   // the workgroup's dynamic LDS: the device limit less its static words, a multiple of 16 words
-  const int lds_words = ((h->lds_limit - 256) / 4) & ~15;
+  const int lds_words = team_lds_words(h->lds_limit);
   std::vector<int> team, wave;
+  std::vector<char> in_hbm(h->S, 0);
+  for (int s : h->hbm) in_hbm[s] = 1;
   for (int s = 0; s < h->S; s++) {
+    if (in_hbm[s]) continue;
     const int nb = h->body_offset[s + 1] - h->body_offset[s];
     const int pm = rbs::scene_cap(nb, h->PM), cm = rbs::scene_cap(nb, h->CM);
     const int need_wave = rbs::lds_layout(nb, pm, cm, 1, h->solver, h->warm).total;
@@ -356,8 +416,19 @@ rbs::QueueParams queue_params(sim_handle* h) {
   return Q;
 }
 
+// LDS layout shared by the scenes stepped out of global memory (their largest
+// scene, current solver mode, 256-thread teams).
+rbs::LdsLayout hbm_layout(const sim_handle* h) {
+  int nb = 0;
+  for (int s : h->hbm) nb = std::max(nb, h->body_offset[s + 1] - h->body_offset[s]);
+  return rbs::lds_layout(nb, rbs::scene_cap(nb, h->PM), rbs::scene_cap(nb, h->CM), 4, h->solver, h->warm);
+}
+
 // One step through a graph of (queue reset, persistent kernel) captured once
-// per cache parity and argument set, replayed on the handle's stream.
+// per cache parity and argument set, replayed on the handle's stream.  When
+// scenes run out of global memory, their kernel is a parallel branch of the
+// graph (forked onto a second capture stream), so that it shares the device
+// with the persistent kernel.
 int launch_persistent(sim_handle* h, const rbs::StepParams& P) {
   const int par = h->parity;
   if (!h->exec[par] || memcmp(&h->exec_key[par], &P, sizeof(P)) != 0) {
@@ -370,10 +441,27 @@ int launch_persistent(sim_handle* h, const rbs::StepParams& P) {
       e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
       if (e != hipSuccess) return (int)e;
     }
+    const bool fork = !h->hbm.empty();
+    if (fork && !h->capture_stream2) {
+      e = hipStreamCreateWithFlags(&h->capture_stream2, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming);
+      if (e != hipSuccess) return (int)e;
+    }
     rbs::QueueParams Q = queue_params(h);
+    const rbs::LdsLayout LH = hbm_layout(h);
     e = hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return (int)e;
-    int rc = rbs_launch_persistent(&P, &Q, h->grid, h->capture_stream);
+    int rc = 0;
+    if (fork) {
+      if (hipEventRecord(h->fork_ev, h->capture_stream) != hipSuccess ||
+          hipStreamWaitEvent(h->capture_stream2, h->fork_ev, 0) != hipSuccess)
+        rc = -1;
+      if (rc == 0) rc = rbs_launch_step_hbm(&P, &LH, (int)h->hbm.size(), h->capture_stream2);
+      if (rc == 0 && hipEventRecord(h->join_ev, h->capture_stream2) != hipSuccess) rc = -1;
+    }
+    if (rc == 0) rc = rbs_launch_persistent(&P, &Q, h->grid, h->capture_stream);
+    if (fork && rc == 0 && hipStreamWaitEvent(h->capture_stream, h->join_ev, 0) != hipSuccess) rc = -1;
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(h->capture_stream, &g);
     if (rc != 0) {
@@ -435,7 +523,9 @@ extern "C" {
 size_t sim_workspace_bytes(const sim_batch_desc* d) {
   Caps c;
   if (validate(d, &c) != SIM_OK) return 0;
-  return make_layout(d->num_scenes, c.N, d->max_pairs, d->max_contacts).total;
+  const HbmSplit sp = hbm_split(d->h_body_offset, d->num_scenes, d->max_pairs, d->max_contacts, device_lds_limit(),
+                                d->hbm_min_bodies);
+  return make_layout(d->num_scenes, c.N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words).total;
 }
 
 int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_bytes, sim_handle** out) {
@@ -446,17 +536,21 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   if (rc != SIM_OK) return rc;
   const int S = d->num_scenes;
   const long N = c.N;
-  Layout lay = make_layout(S, N, d->max_pairs, d->max_contacts);
+  const int limit = device_lds_limit();
+  HbmSplit sp = hbm_split(d->h_body_offset, S, d->max_pairs, d->max_contacts, limit, d->hbm_min_bodies);
+  Layout lay = make_layout(S, N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words);
   if (!d_workspace || workspace_bytes < lay.total) return fail(SIM_EWORKSPACE, "workspace too small");
   if (((uintptr_t)d_workspace & 255u) != 0) return fail(SIM_EWORKSPACE, "workspace must be 256-byte aligned");
   const int T = d->threads ? d->threads : 64;
-  // the working set of the largest scene under the descriptor's solver mode
-  // (sim_set_solver and sim_step check again for later modes)
-  int need = lds_bytes(c.NB, d->max_pairs, d->max_contacts, T, d->solver, d->warm_start);
-  int limit = device_lds_limit();
+  // the working set of the largest scene kept in LDS, under any solver mode
+  // (the split above sends every larger one to global memory)
+  const int nbl = sp.nb_lds;
+  int need = nbl ? lds_bytes(nbl, rbs::scene_cap(nbl, d->max_pairs), rbs::scene_cap(nbl, d->max_contacts), T,
+                             rbs::SOLVER_JACOBI, rbs::WARM_LEARNED)
+                 : 0;
   if (need > limit)
     return fail(SIM_ECAPACITY, "per-scene working set (" + std::to_string(need) + " B) exceeds LDS (" +
-                                   std::to_string(limit) + " B); lower max_contacts/max_pairs");
+                                   std::to_string(limit) + " B)");
   if (rbs_set_step_lds_limit(limit) != 0) return fail(SIM_EDEVICE, "hipFuncSetAttribute failed");
 
   sim_handle* h = new sim_handle();
@@ -491,6 +585,9 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   h->trace = nullptr;
   h->lds_limit = limit;
   h->body_offset.assign(d->h_body_offset, d->h_body_offset + S + 1);
+  h->hbm = sp.scenes;
+  h->hbm_words = sp.words;
+  h->nb_lds = nbl;
 
   // host staging: structure-of-arrays planes
   std::vector<float> prm(3 * N), inv_mass(N), inv_I(3 * N), pose(7 * N), vel(6 * N);
@@ -524,12 +621,19 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
       for (int k = 0; k < 3; k++) inv_I[k * N + i] = 0.f;
     }
   }
-  // largest scenes first: the tail of the grid holds the cheap scenes
-  std::vector<int32_t> order(S);
-  std::iota(order.begin(), order.end(), 0);
+  // largest scenes first: the tail of the grid holds the cheap scenes; the
+  // scenes stepped out of global memory have their own list
+  std::vector<char> in_hbm(S, 0);
+  for (int s : sp.scenes) in_hbm[s] = 1;
+  std::vector<int32_t> order;
+  for (int s = 0; s < S; s++)
+    if (!in_hbm[s]) order.push_back(s);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return d->h_body_offset[a + 1] - d->h_body_offset[a] > d->h_body_offset[b + 1] - d->h_body_offset[b];
   });
+  order.resize(S, 0);
+  std::vector<int32_t> glist(sp.scenes.begin(), sp.scenes.end());
+  glist.resize(S, 0);
   std::vector<float> theta(7 * S, 0.f), base(3 * S, 0.f);
   if (d->arm) {
     for (int i = 0; i < 7 * S; i++) theta[i] = d->h_arm_theta[i];
@@ -554,6 +658,7 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   if (e == hipSuccess) e = up(lay.off_theta, theta.data(), 4 * 7 * S);
   if (e == hipSuccess) e = up(lay.off_arm_base, base.data(), 4 * 3 * S);
   if (e == hipSuccess) e = up(lay.off_scene_list, order.data(), 4 * S);
+  if (e == hipSuccess) e = up(lay.off_glist, glist.data(), 4 * S);
   if (e == hipSuccess && h->arm) {
     rbs::StepParams P = params(h);
     e = (hipError_t)rbs_launch_arm_pose(&P, nullptr, st);
@@ -593,9 +698,18 @@ int sim_step(sim_handle* h, const float* d_actions, float dt, int iters) {
     rc = launch_persistent(h, P);
     if (rc != 0) return fail(SIM_EDEVICE, std::string("persistent step failed: ") + hipGetErrorString((hipError_t)rc));
   } else {
-    rbs::LdsLayout L = rbs::lds_layout(h->NB, h->PM, h->CM, h->threads / 64, h->solver, h->warm);
-    if (L.total * 4 > h->lds_limit) return fail(SIM_ECAPACITY, "working set exceeds LDS");
-    rc = rbs_launch_step(&P, &L, h->threads, h->S, h->stream);
+    const int nl = h->S - (int)h->hbm.size(), nbl = h->nb_lds;
+    rc = 0;
+    if (nl > 0) {
+      rbs::LdsLayout L = rbs::lds_layout(nbl, rbs::scene_cap(nbl, h->PM), rbs::scene_cap(nbl, h->CM),
+                                         h->threads / 64, h->solver, h->warm);
+      if (L.total * 4 > h->lds_limit) return fail(SIM_ECAPACITY, "working set exceeds LDS");
+      rc = rbs_launch_step(&P, &L, h->threads, nl, h->stream);
+    }
+    if (rc == 0 && !h->hbm.empty()) {
+      const rbs::LdsLayout LH = hbm_layout(h);
+      rc = rbs_launch_step_hbm(&P, &LH, (int)h->hbm.size(), h->stream);
+    }
     if (rc != 0) return fail(SIM_EDEVICE, std::string("step launch failed: ") + hipGetErrorString((hipError_t)rc));
   }
   h->parity ^= 1;
@@ -698,12 +812,13 @@ int sim_set_mlp(sim_handle* h, const uint16_t* w1, const uint16_t* w2, const uin
   return SIM_OK;
 }
 
-int sim_reset(sim_handle* h, const uint8_t* d_mask, const float* d_pose, const float* d_vel, const float* d_theta) {
+int sim_reset(sim_handle* h, const uint8_t* d_mask, const sim_reset_pool* pool) {
   if (!h) return fail(SIM_EINVAL, "handle is NULL");
-  if (!d_mask || !d_pose || !d_vel) return fail(SIM_EINVAL, "mask, pose and vel are required");
-  if (h->arm && !d_theta) return fail(SIM_EINVAL, "arm scenes need theta");
+  if (!d_mask || !pool || !pool->pose || !pool->vel) return fail(SIM_EINVAL, "mask, pool, pose and vel are required");
+  if (pool->size < 1) return fail(SIM_EINVAL, "pool size must be >= 1");
+  if (h->arm && !pool->theta) return fail(SIM_EINVAL, "arm scenes need theta");
   rbs::StepParams P = params(h);
-  int rc = rbs_launch_reset(&P, d_mask, d_pose, d_vel, h->arm ? d_theta : nullptr,
+  int rc = rbs_launch_reset(&P, d_mask, pool->size, pool->index, pool->pose, pool->vel, h->arm ? pool->theta : nullptr,
                             at<int32_t>(h, h->lay.off_ccount[0]), at<int32_t>(h, h->lay.off_ccount[1]), h->stream);
   if (rc == 0 && h->arm) rc = rbs_launch_arm_pose(&P, d_mask, h->stream);
   if (rc != 0) return fail(SIM_EDEVICE, "reset launch failed");

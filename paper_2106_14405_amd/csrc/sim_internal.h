@@ -8,7 +8,7 @@ namespace rbs {
 
 constexpr int kMaxThreads = 256;
 constexpr int kMaxColours = 128;
-constexpr int kMaxBodiesPerScene = 1024;
+constexpr int kMaxBodiesPerScene = 2046;  // local body index field: 11 bits, 2047 = ground
 constexpr uint32_t kGroundPair = 0xFFFFu;
 constexpr uint32_t kGroundKey = 0xFFFu;
 constexpr int kTraceSlots = 16;
@@ -24,7 +24,7 @@ inline __host__ __device__ int scene_cap(int nb, int cap) {
 
 enum { WARM_COLD = 0, WARM_PREV = 1, WARM_LEARNED = 2 };
 enum { SOLVER_PGS = 0, SOLVER_JACOBI = 1 };
-enum { FLAG_NONFINITE = 1, FLAG_CAPACITY = 2, FLAG_NOT_CONVERGED = 4, FLAG_FELLBACK = 8 };
+enum { FLAG_NONFINITE = 1, FLAG_CAPACITY = 2, FLAG_NOT_CONVERGED = 4, FLAG_FELLBACK = 8, FLAG_BAD_RESET = 16 };
 
 struct MlpParams {
   const uint16_t* w1;  // bf16 [64][16]  (out, in)
@@ -77,6 +77,9 @@ struct StepParams {
   float* x_feat;            // [16][S*CM] (export only)
   float4* raw;              // [S*CM][2] narrowphase output, canonical order: (n, phi), (p, -)
   float4* crec;             // [S][rec_stride(PM, CM)] solver records, colour-major order
+  float* gscr;              // working sets of the scenes stepped out of HBM: [n][gwords] words
+  long gwords;
+  const int32_t* glist;     // those scenes, largest first
   int32_t* st_pairs;
   int32_t* st_contacts;
   int32_t* st_colours;
@@ -101,7 +104,7 @@ struct QueueParams {
   const int32_t* team;
   const int32_t* wave;
   int n_team, n_wave;
-  uint32_t* head;        // [2]
+  uint32_t* head;        // [2]: team queue, wave queue
   int lds_words;         // dynamic LDS of a workgroup; a wave owns a quarter
 };
 

@@ -1744,6 +1744,19 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
   scene_step<kLearned>(P, L, S, s, tm);
 }
 
+// Scenes whose working set exceeds a workgroup's LDS: the same step with the
+// working set in global memory (one region of P.gwords words per scene of
+// P.glist, L2 and HBM resident) instead of LDS; one workgroup per scene.
+// The team barriers are workgroup-scope fences, which order global memory
+// as they order LDS, so the step computes exactly what it computes in LDS.
+template <bool kLearned>
+__global__ __launch_bounds__(256) void step_kernel_hbm(StepParams P, LdsLayout L) {
+  const int k = (int)blockIdx.x;
+  float* ws = P.gscr + (size_t)k * (size_t)P.gwords;
+  const Team<false> tm{(int)threadIdx.x, (int)blockDim.x};
+  scene_step<kLearned>(P, L, Smem{ws, reinterpret_cast<uint32_t*>(ws)}, P.glist[k], tm);
+}
+
 // Persistent launch over scenes of uneven size: every workgroup first takes
 // scenes from the `team` queue and steps each with all its threads and all
 // its LDS, then each of its waves takes scenes from the `wave` queue and
@@ -1804,19 +1817,30 @@ __global__ void arm_pose_kernel(int S_, const int32_t* off, float* pose, long N,
   }
 }
 
-// Masked reset: one workgroup per scene copies pose/velocity (and joint
-// angles) from the caller's pool arrays and empties the contact cache.
-__global__ void reset_kernel(const int32_t* off, const uint8_t* mask, float* pose, float* vel, long N,
-                             const float* pool_pose, const float* pool_vel, float* theta, const float* pool_theta,
-                             int32_t* cache_count_a, int32_t* cache_count_b) {
-  int s = blockIdx.x;
+// Masked reset from a pool of K states: one workgroup per flagged scene
+// copies pool entry index[s] (pose [K][7][N], velocity [K][6][N], joint
+// angles [K][S][7]) into the scene and empties its contact cache; an entry
+// outside [0, K) leaves the scene as it is and flags it.
+__global__ void reset_kernel(const int32_t* off, const uint8_t* mask, float* pose, float* vel, long N, int S_,
+                             int K, const int32_t* index, const float* pool_pose, const float* pool_vel, float* theta,
+                             const float* pool_theta, int32_t* cache_count_a, int32_t* cache_count_b,
+                             int32_t* flags) {
+  const int s = blockIdx.x;
   if (!mask[s]) return;
-  int b0 = off[s], b1 = off[s + 1];
-  for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-    for (int k = 0; k < 7; k++) pose[k * N + i] = pool_pose[k * N + i];
-    for (int k = 0; k < 6; k++) vel[k * N + i] = pool_vel[k * N + i];
+  const int k = index ? index[s] : 0;
+  if (k < 0 || k >= K) {
+    if (threadIdx.x == 0) flags[s] |= FLAG_BAD_RESET;
+    return;
   }
-  if (threadIdx.x < 7 && theta && pool_theta) theta[7 * s + threadIdx.x] = pool_theta[7 * s + threadIdx.x];
+  const float* pp = pool_pose + (size_t)k * 7 * N;
+  const float* pv = pool_vel + (size_t)k * 6 * N;
+  const int b0 = off[s], b1 = off[s + 1];
+  for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+    for (int c = 0; c < 7; c++) pose[c * N + i] = pp[c * N + i];
+    for (int c = 0; c < 6; c++) vel[c * N + i] = pv[c * N + i];
+  }
+  if (threadIdx.x < 7 && theta && pool_theta)
+    theta[7 * s + threadIdx.x] = pool_theta[(size_t)k * 7 * S_ + 7 * s + threadIdx.x];
   if (threadIdx.x == 0) {
     cache_count_a[s] = 0;
     cache_count_b[s] = 0;
@@ -1832,6 +1856,15 @@ extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L
     hipLaunchKernelGGL(rbs::step_kernel<true>, dim3(grid), dim3(threads), bytes, stream, *P, *L);
   else
     hipLaunchKernelGGL(rbs::step_kernel<false>, dim3(grid), dim3(threads), bytes, stream, *P, *L);
+  return (int)hipGetLastError();
+}
+
+extern "C" int rbs_launch_step_hbm(const rbs::StepParams* P, const rbs::LdsLayout* L, int n, hipStream_t stream) {
+  if (n <= 0) return 0;
+  if (P->warm == rbs::WARM_LEARNED)
+    hipLaunchKernelGGL(rbs::step_kernel_hbm<true>, dim3(n), dim3(256), 0, stream, *P, *L);
+  else
+    hipLaunchKernelGGL(rbs::step_kernel_hbm<false>, dim3(n), dim3(256), 0, stream, *P, *L);
   return (int)hipGetLastError();
 }
 
@@ -1869,10 +1902,11 @@ extern "C" int rbs_launch_arm_pose(const rbs::StepParams* P, const uint8_t* mask
   return (int)hipGetLastError();
 }
 
-extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, const float* pool_pose,
-                                const float* pool_vel, const float* pool_theta, int32_t* count_a, int32_t* count_b,
-                                hipStream_t stream) {
+extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, int K, const int32_t* index,
+                                const float* pool_pose, const float* pool_vel, const float* pool_theta,
+                                int32_t* count_a, int32_t* count_b, hipStream_t stream) {
   hipLaunchKernelGGL(rbs::reset_kernel, dim3(P->num_scenes), dim3(128), 0, stream, P->body_offset, mask, P->pose,
-                     P->vel, P->n_bodies, pool_pose, pool_vel, P->theta, pool_theta, count_a, count_b);
+                     P->vel, P->n_bodies, P->num_scenes, K, index, pool_pose, pool_vel, P->theta, pool_theta, count_a,
+                     count_b, P->st_flags);
   return (int)hipGetLastError();
 }

@@ -229,11 +229,14 @@ def drop_scene(seed: int, n_spheres: int = 32, n_boxes: int = 32, size=(0.05, 0.
 
 def clutter_scene(seed: int, n_static: int = 20, n_each: int = 36, size=(0.03, 0.30),
                   cap_radius=(0.03, 0.15), mass=(0.05, 3.0), friction=(0.3, 0.8),
-                  arm: bool = True) -> Scene:
+                  arm: bool = True, n_dynamic: int | None = None) -> Scene:
     """Rearrangement clutter: static boxes on a 4 m x 4 m floor (a quarter of
     them floating shelves), dynamic spheres/boxes/capsules dropped above, and
-    a kinematic 7-link capsule arm based at (0, 0, 0.8) m."""
-    st = _Stream(stream_key(seed, 2))
+    a kinematic 7-link capsule arm based at (0, 0, 0.8) m.  With n_dynamic
+    given, that many dynamic bodies (a third of each shape, the remainder to
+    spheres then boxes) dropped from a region scaled by (n_dynamic/108)^(1/3)
+    (x, y within +-2 m times the scale, z from 0.2 m up to 4 m times it)."""
+    st = _Stream(stream_key(seed, 2) if n_dynamic is None else stream_key(seed, 6, n_dynamic))
     sc = Scene()
     statics = []
     for i in range(n_static):
@@ -258,11 +261,18 @@ def clutter_scene(seed: int, n_static: int = 20, n_each: int = 36, size=(0.03, 0
         sc.add(BOX, STATIC, [hx, hy, hz], 0.0, st.uniform(*friction), 0.0, c, _yaw_quat(yaw))
     reach = sum(ARM_LINK_LENGTH) + ARM_RADIUS
     keepout = (np.array(ARM_BASE), reach) if arm else None
-    kinds = np.array([SPHERE] * n_each + [BOX] * n_each + [CAPSULE] * n_each)
+    if n_dynamic is None:
+        counts, scale = (n_each, n_each, n_each), 1.0
+    else:
+        third = n_dynamic // 3
+        rem = n_dynamic - 3 * third
+        counts = (third + (rem > 0), third + (rem > 1), third)
+        scale = (n_dynamic / 108.0) ** (1.0 / 3.0)
+    kinds = np.array([SPHERE] * counts[0] + [BOX] * counts[1] + [CAPSULE] * counts[2])
     kinds = kinds[np.argsort(st.take(len(kinds)), kind="stable")]
     placed = []
-    lo = np.array([-2.0, -2.0, 0.2])
-    hi = np.array([2.0, 2.0, 4.2])
+    lo = np.array([-2.0 * scale, -2.0 * scale, 0.2])
+    hi = np.array([2.0 * scale, 2.0 * scale, 0.2 + 4.0 * scale])
     for k in kinds:
         if k == SPHERE:
             param = [st.uniform(*size), 0.0, 0.0]
@@ -284,6 +294,20 @@ def clutter_scene(seed: int, n_static: int = 20, n_each: int = 36, size=(0.03, 0
             sc.add(CAPSULE, KINEMATIC, [ARM_RADIUS, 0.5 * L, 0.0], 0.0, 0.5, 0.0,
                    ARM_BASE, (1.0, 0.0, 0.0, 0.0))
     return sc
+
+
+def _scale_one(args):
+    seed, n, arm = args
+    return clutter_scene(seed, arm=arm, n_dynamic=n)
+
+
+def batch_scale(n_scenes: int = 16384, seed0: int = 30000, lo: int = 64, hi: int = 1024, arm: bool = True,
+                workers=None) -> Batch:
+    """Large clutter: per scene round(exp(U[ln lo, ln hi])) dynamic
+    spheres/boxes/capsules with the clutter distributions in a scaled drop
+    region, the 20 static boxes and the arm."""
+    counts = log_uniform_counts(seed0, n_scenes, lo, hi)
+    return pack(_map(_scale_one, [(seed0 + 1 + s, int(n), arm) for s, n in enumerate(counts)], workers))
 
 
 def log_uniform_counts(seed: int, n_scenes: int, lo: int, hi: int) -> np.ndarray:
@@ -406,12 +430,84 @@ def batch_uneven(n_scenes: int = 4096, seed0: int = 20000, lo: int = 16, hi: int
     return pack(_map(_drop_one, items, workers))
 
 
+def _fresh_one(args):
+    """Pool entry k of scene s: the scene's dynamic bodies re-placed (same
+    shapes, masses and materials) at new rejection-sampled positions and
+    uniform orientations in the scene's drop region, at rest; static bodies
+    and the arm base stay; new joint angles for the arm."""
+    key, kind, shape, motion, param, pose, arm = args
+    st = _Stream(key)
+    out = pose.astype(np.float64).copy()
+    dyn = np.nonzero(motion == DYNAMIC)[0]
+    statics = []
+    for i in np.nonzero(motion == STATIC)[0]:
+        q = pose[i, 3:7].astype(np.float64)
+        statics.append((pose[i, :3].astype(np.float64), param[i].astype(np.float64),
+                        2.0 * math.atan2(q[3], q[0])))
+    if kind == "clutter":
+        lo, hi = np.array([-2.0, -2.0, 0.2]), np.array([2.0, 2.0, 4.2])
+        keepout = (np.array(ARM_BASE), sum(ARM_LINK_LENGTH) + ARM_RADIUS) if arm else None
+    else:
+        L = 2.0 * (len(dyn) / 64.0) ** (1.0 / 3.0)
+        lo, hi = np.array([-0.5 * L, -0.5 * L, 0.2]), np.array([0.5 * L, 0.5 * L, 0.2 + L])
+        keepout = None
+    placed = []
+    for i in dyn:
+        R = bounding_radius(int(shape[i]), param[i])
+        p = _place(st, R, lo, hi, placed, statics, keepout)
+        placed.append((p, R))
+        q = _random_quat(st)
+        out[i, :3] = p
+        out[i, 3:7] = q / np.linalg.norm(q)
+    theta = st.uniform(-0.5, 0.5, ARM_LINKS) if arm else np.zeros(ARM_LINKS)
+    return out.astype(np.float32), theta.astype(np.float32)
+
+
+def reset_pool(batch: Batch, size: int, seed: int, kind: str = "drop", workers=None):
+    """A pool of `size` fresh states of every scene of the batch, for masked
+    episode resets: pose [K, N, 7] float32, velocity zeros [K, N, 6] and arm
+    joint angles [K, S, 7].  Entry k of scene s comes from stream
+    (seed, 5, s, k); kind "drop" re-drops the dynamic bodies in the scene's
+    cube (edge 2 m (n/64)^(1/3)), "clutter" in the clutter region, clear of
+    the statics and the arm's reach."""
+    S_, N = batch.n_scenes, batch.n_bodies
+    items = []
+    for k in range(size):
+        for s in range(S_):
+            b0, b1 = int(batch.body_offset[s]), int(batch.body_offset[s + 1])
+            items.append((stream_key(seed, 5, s, k), kind, batch.shape[b0:b1], batch.motion[b0:b1],
+                          batch.param[b0:b1], batch.pose[b0:b1], bool(batch.arm)))
+    res = _map(_fresh_one, items, workers)
+    pose = np.empty((size, N, 7), np.float32)
+    theta = np.zeros((size, S_, ARM_LINKS), np.float32)
+    for k in range(size):
+        for s in range(S_):
+            b0, b1 = int(batch.body_offset[s]), int(batch.body_offset[s + 1])
+            p, th = res[k * S_ + s]
+            pose[k, b0:b1] = p
+            theta[k, s] = th
+    return pose, np.zeros((size, N, 6), np.float32), theta
+
+
+def _stream_keys(ids) -> np.ndarray:
+    """stream_key over arrays: ids is a sequence of ints or uint64 arrays
+    (broadcast together); same folding as stream_key."""
+    with np.errstate(over="ignore"):
+        h = np.uint64(0x243F6A8885A308D3)
+        for i in ids:
+            h = _mix_np((np.asarray(h, np.uint64) + np.uint64(_GOLDEN)) ^ np.asarray(i, np.uint64))
+    return h
+
+
 def arm_actions(seed: int, n_scenes: int, step: int) -> np.ndarray:
-    """Joint velocities U[-1, 1] rad/s for one step, keyed (seed, scene, step, joint)."""
-    out = np.empty((n_scenes, ARM_LINKS), np.float64)
-    for s in range(n_scenes):
-        out[s] = uniforms(stream_key(seed, 4, s, step), ARM_LINKS)
-    return (2.0 * out - 1.0).astype(np.float32)
+    """Joint velocities U[-1, 1] rad/s for one step, keyed (seed, scene, step, joint):
+    joint k of scene s is value k of stream_key(seed, 4, s, step)."""
+    keys = _stream_keys([seed, 4, np.arange(n_scenes, dtype=np.uint64), step])
+    k = np.arange(1, ARM_LINKS + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = keys[:, None] + k[None, :] * np.uint64(_GOLDEN)
+    u = (_mix_np(z) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return (2.0 * u - 1.0).astype(np.float32)
 
 
 def arm_actions_block(seed: int, n_scenes: int, step0: int, n_steps: int) -> np.ndarray:

@@ -29,7 +29,7 @@ class Sim:
 
     def __init__(self, batch: scenes.Batch, max_pairs: int | None = None, max_contacts: int | None = None,
                  solver: int = L.PGS, warm: int = L.COLD, tol: float = 0.0, threads: int = 64,
-                 device: str | torch.device = "cuda", **consts):
+                 device: str | torch.device = "cuda", hbm_min_bodies: int = 0, **consts):
         lib = L.load()
         c = dict(DEFAULT_CONSTS)
         c.update(consts)
@@ -82,6 +82,7 @@ class Sim:
                                                                   c["ground_restitution"])
         d.max_pairs, d.max_contacts = self.max_pairs, self.max_contacts
         d.solver, d.warm_start, d.tolerance, d.threads = int(solver), int(warm), float(tol), int(threads)
+        d.hbm_min_bodies = int(hbm_min_bodies)
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             d.stream = C.c_void_p(self.stream.cuda_stream)
@@ -213,13 +214,20 @@ class Sim:
             raise ValueError("blob must be a contiguous uint8 tensor on the simulation device")
         L.check(L.load().sim_load_state(self.h, C.c_void_p(blob.data_ptr())), "sim_load_state")
 
-    def reset(self, mask: torch.Tensor, pose: torch.Tensor, vel: torch.Tensor, theta: torch.Tensor | None = None):
-        """Masked reset from pool arrays laid out like the state ([7, N], [6, N], [S, 7])."""
-        ts = [mask.to(torch.uint8).contiguous(), pose.contiguous(), vel.contiguous()]
-        th = theta.contiguous() if theta is not None else None
-        self._reset_keep = ts + [th]
-        L.check(L.load().sim_reset(self.h, *[C.c_void_p(t.data_ptr()) for t in ts],
-                                   C.c_void_p(th.data_ptr()) if th is not None else None), "sim_reset")
+    def reset(self, mask: torch.Tensor, pose: torch.Tensor, vel: torch.Tensor, theta: torch.Tensor | None = None,
+              index: torch.Tensor | None = None):
+        """Masked reset from a pool of K states: pose [K, 7, N], vel [K, 6, N],
+        theta [K, S, 7] (arm batches); a single state may be given without
+        the leading K.  index: int32 [S] pool entry per scene (None: 0)."""
+        pose = pose.reshape(-1, 7, self.N)
+        K = pose.shape[0]
+        ts = [mask.to(torch.uint8).contiguous(), pose.contiguous(), vel.reshape(K, 6, self.N).contiguous()]
+        th = theta.reshape(K, self.S, 7).contiguous() if theta is not None else None
+        ix = index.to(torch.int32).contiguous() if index is not None else None
+        self._reset_keep = ts + [th, ix]
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        pool = L.ResetPool(K, ptr(ts[1]), ptr(ts[2]), ptr(th), ptr(ix))
+        L.check(L.load().sim_reset(self.h, ptr(ts[0]), C.byref(pool)), "sim_reset")
 
     def close(self):
         if getattr(self, "h", None):

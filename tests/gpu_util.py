@@ -80,41 +80,164 @@ def gpu_results(sim):
     return out
 
 
-def compare(batch, g, r, ora, check_values=True, scenes=None):
-    """Element-by-element comparison.  Returns a report dict; raises on a
-    mismatch in an unflagged scene."""
-    rep = dict(scenes=0, flagged=0, contacts=0, max_x=0.0, max_v=0.0, max_w=0.0, max_q=0.0, max_lam=0.0)
+def _find(par, x):
+    while par[x] != x:
+        par[x] = par[par[x]]
+        x = par[x]
+    return x
+
+
+def affected_bodies(batch, s, g, r):
+    """Local indices of the bodies of scene s whose results may differ
+    between the two sides: the bodies of a pair with a tie-band decision in
+    the oracle, and every dynamic body linked to one of them through the
+    contacts of either side (a contact couples its bodies' impulses; static,
+    kinematic bodies and the ground do not link).  Outside this set, a
+    step's pairs, contacts, colours (first fit only looks at contacts that
+    share a dynamic body) and, with a fixed sweep count, the solve are
+    independent of the tied decision."""
+    b0, b1 = int(batch.body_offset[s]), int(batch.body_offset[s + 1])
+    nb = b1 - b0
+    tied = np.nonzero(r["tied"][b0:b1])[0]
+    if tied.size == 0:
+        return np.zeros(nb, bool)
+    dyn = batch.motion[b0:b1] == S.DYNAMIC
+    par = list(range(nb))
+    keys = [r["c_key"][s, :int(r["n_contacts"][s])], g["key"][s, :int(g["count"][s])].astype(np.uint32)]
+    for kk in keys:
+        for k in kk:
+            a, b = int(k) >> 20, (int(k) >> 8) & 0xFFF
+            if b == 0xFFF or b >= nb or a >= nb or not (dyn[a] and dyn[b]):
+                continue
+            ra, rb = _find(par, a), _find(par, b)
+            if ra != rb:
+                par[ra] = rb
+    roots = {_find(par, int(t)) for t in tied}
+    aff = np.array([_find(par, i) in roots for i in range(nb)])
+    aff[tied] = True
+    return aff
+
+
+def _keep_pairs(keys, aff):
+    a = keys >> 16
+    b = keys & 0xFFFF
+    ok = ~aff[a]
+    gb = b != 0xFFFF
+    ok[gb] &= ~aff[b[gb]]
+    return ok
+
+
+def _keep_contacts(keys, aff):
+    a = keys >> 20
+    b = (keys >> 8) & 0xFFF
+    ok = ~aff[a]
+    gb = b != 0xFFF
+    ok[gb] &= ~aff[b[gb]]
+    return ok
+
+
+# contact value bars (float32 geometry of lengths up to a few metres)
+N_ATOL = 1e-5      # unit normal
+P_ATOL = 1e-5      # m
+PHI_ATOL = 1e-5    # m
+LAM_REL = 2e-4     # impulses, relative to the scene's largest impulse ...
+LAM_ABS = 1e-6     # ... plus this (N s)
+
+
+def compare(batch, g, r, ora, check_values=True, contact_values=False, partial=True, tol_band=None, scenes=None):
+    """Element-by-element comparison of one step.
+
+    Unflagged scenes (no oracle decision in the tie band): pair keys,
+    contact keys, colours and colour counts bit-exact; with check_values,
+    positions, velocities (1e-4 relative, floors 1 m, 1 m/s, 1 rad/s) and
+    orientations (1e-4 rad); with contact_values, normals, points, depths
+    and impulses of every contact.  Flagged scenes (partial=True): the same
+    comparisons restricted to what lies outside `affected_bodies`.
+
+    Sweep counts: with a fixed sweep count they are equal by construction.
+    In tolerance mode (tol_band set) they must be equal in unflagged scenes
+    unless the oracle's residual came within tol_band * tol of the tolerance
+    at one of its stopping tests (r["tol_gap"] < tol_band, the stop
+    decision's own tie band); where the counts differ, impulses and states
+    are not compared (the pre-solve results still are).  Returns a report;
+    raises on a mismatch."""
+    rep = dict(scenes=0, flagged=0, flagged_compared=0, skipped=0, sweeps_equal=0, sweeps_band=0,
+               values_skipped=0, bodies=0, bodies_excluded=0, contacts=0, pairs=0, max_x=0.0, max_v=0.0,
+               max_w=0.0, max_q=0.0, max_n=0.0, max_p=0.0, max_phi=0.0, max_lam=0.0)
     Sn = batch.n_scenes
     pose_o = ora.pose.reshape(-1, 7)
     vel_o = ora.vel.reshape(-1, 6)
     for s in (range(Sn) if scenes is None else scenes):
         rep["scenes"] += 1
-        if r["ambiguous"][s] != 0:
+        b0, b1 = int(batch.body_offset[s]), int(batch.body_offset[s + 1])
+        flagged = r["ambiguous"][s] != 0
+        same_sweeps = int(g["stats"]["sweeps"][s]) == int(r["sweeps"][s])
+        rep["sweeps_equal"] += int(same_sweeps)
+        if not same_sweeps and not flagged:
+            near = tol_band is not None and r["tol_gap"][s] < tol_band
+            assert near, (f"scene {s}: {int(g['stats']['sweeps'][s])} sweeps on the GPU, {int(r['sweeps'][s])} "
+                          f"in the oracle (residual gap to the tolerance {r['tol_gap'][s]:.3g})")
+            rep["sweeps_band"] += 1
+        if flagged:
             rep["flagged"] += 1
-            continue
+            if not partial:
+                rep["skipped"] += 1
+                continue
+            rep["flagged_compared"] += 1
+        values = same_sweeps
+        rep["values_skipped"] += int(not values)
+        aff = affected_bodies(batch, s, g, r)
+        rep["bodies"] += b1 - b0
+        rep["bodies_excluded"] += int(aff.sum())
         # pair sets
         np_o = int(r["n_pairs"][s])
         np_g = int(g["stats"]["pairs"][s])
-        assert np_g == np_o, f"scene {s}: {np_g} pairs on the GPU, {np_o} in the oracle"
+        pk_o = r["pair_key"][s, :np_o]
         pk_g = g["pair_key"][s, :np_g].astype(np.uint32)
-        assert np.array_equal(pk_g, r["pair_key"][s, :np_o]), f"scene {s}: pair keys differ"
+        if not flagged:
+            assert np_g == np_o, f"scene {s}: {np_g} pairs on the GPU, {np_o} in the oracle"
+        ko, kg_ = pk_o[_keep_pairs(pk_o, aff)], pk_g[_keep_pairs(pk_g, aff)]
+        assert np.array_equal(kg_, ko), f"scene {s}: pair keys differ (flagged={flagged})"
+        rep["pairs"] += len(ko)
         # contact keys, colours
         nc = int(r["n_contacts"][s])
-        assert int(g["count"][s]) == nc, f"scene {s}: {int(g['count'][s])} contacts on the GPU, {nc} in the oracle"
-        kg = g["key"][s, :nc].astype(np.uint32)
-        assert np.array_equal(kg, r["c_key"][s, :nc]), f"scene {s}: contact keys differ"
-        assert np.array_equal(g["colour"][s, :nc], r["c_colour"][s, :nc]), f"scene {s}: colours differ"
-        assert int(g["stats"]["colours"][s]) == int(r["n_colours"][s])
-        rep["contacts"] += nc
-        if not check_values:
+        ncg = int(g["count"][s])
+        if not flagged:
+            assert ncg == nc, f"scene {s}: {ncg} contacts on the GPU, {nc} in the oracle"
+            assert int(g["stats"]["colours"][s]) == int(r["n_colours"][s])
+        ck_o = r["c_key"][s, :nc]
+        ck_g = g["key"][s, :ncg].astype(np.uint32)
+        mo, mg = _keep_contacts(ck_o, aff), _keep_contacts(ck_g, aff)
+        assert np.array_equal(ck_g[mg], ck_o[mo]), f"scene {s}: contact keys differ (flagged={flagged})"
+        assert np.array_equal(g["colour"][s, :ncg][mg], r["c_colour"][s, :nc][mo]), \
+            f"scene {s}: colours differ (flagged={flagged})"
+        rep["contacts"] += int(mo.sum())
+        if contact_values and mo.any():
+            io, ig = np.nonzero(mo)[0], np.nonzero(mg)[0]
+            en = np.max(np.abs(g["normal"][:, s, ig].T - r["c_normal"][s, io]))
+            ep = np.max(np.abs(g["point"][:, s, ig].T - r["c_point"][s, io]))
+            eph = np.max(np.abs(g["phi"][s, ig] - r["c_phi"][s, io]))
+            rep["max_n"] = max(rep["max_n"], en)
+            rep["max_p"] = max(rep["max_p"], ep)
+            rep["max_phi"] = max(rep["max_phi"], eph)
+            assert en <= N_ATOL, f"scene {s}: normal error {en:.3e}"
+            assert ep <= P_ATOL, f"scene {s}: point error {ep:.3e}"
+            assert eph <= PHI_ATOL, f"scene {s}: depth error {eph:.3e}"
+            if values:
+                lam_o = r["c_lambda"][s, io]
+                scale = float(np.abs(r["c_lambda"][s, :nc]).max())
+                el = np.max(np.abs(g["lam"][:, s, ig].T - lam_o))
+                rep["max_lam"] = max(rep["max_lam"], el / max(scale, 1e-12))
+                assert el <= LAM_REL * scale + LAM_ABS, f"scene {s}: impulse error {el:.3e} (scale {scale:.3e})"
+        if not check_values or not values:
             continue
-        b0, b1 = int(batch.body_offset[s]), int(batch.body_offset[s + 1])
-        xo, xg = pose_o[b0:b1, :3], g["pose"][b0:b1, :3]
+        keep = ~aff
+        xo, xg = pose_o[b0:b1, :3][keep], g["pose"][b0:b1, :3][keep]
         ex = np.max(np.abs(xg - xo) / np.maximum(np.abs(xo), X_FLOOR), initial=0.0)
-        vo, vg = vel_o[b0:b1], g["vel"][b0:b1]
+        vo, vg = vel_o[b0:b1][keep], g["vel"][b0:b1][keep]
         ev = np.max(np.abs(vg[:, :3] - vo[:, :3]) / np.maximum(np.abs(vo[:, :3]), V_FLOOR), initial=0.0)
         ew = np.max(np.abs(vg[:, 3:] - vo[:, 3:]) / np.maximum(np.abs(vo[:, 3:]), V_FLOOR), initial=0.0)
-        eq = np.max(quat_angle(pose_o[b0:b1, 3:], g["pose"][b0:b1, 3:]), initial=0.0)
+        eq = np.max(quat_angle(pose_o[b0:b1, 3:][keep], g["pose"][b0:b1, 3:][keep]), initial=0.0)
         rep["max_x"] = max(rep["max_x"], ex)
         rep["max_v"] = max(rep["max_v"], ev)
         rep["max_w"] = max(rep["max_w"], ew)
@@ -123,4 +246,17 @@ def compare(batch, g, r, ora, check_values=True, scenes=None):
         assert ev <= REL, f"scene {s}: velocity error {ev:.3e}"
         assert ew <= REL, f"scene {s}: angular velocity error {ew:.3e}"
         assert eq <= Q_ANGLE, f"scene {s}: orientation error {eq:.3e} rad"
+    rep["flagged_frac"] = rep["flagged"] / max(rep["scenes"], 1)
+    rep["excluded_frac"] = rep["bodies_excluded"] / max(rep["bodies"], 1)
     return rep
+
+
+def report(name, rep):
+    """One line per parity check: how much was compared and how much the tie band excluded."""
+    print(f"[parity] {name}: scenes {rep['scenes']}, flagged {rep['flagged']} "
+          f"({100 * rep['flagged_frac']:.0f}%, {rep['flagged_compared']} compared outside the tied islands, "
+          f"{rep['skipped']} skipped), sweeps equal in {rep['sweeps_equal']} ({rep['sweeps_band']} differ inside "
+          f"the stop band, values skipped in {rep['values_skipped']}), bodies excluded {100 * rep['excluded_frac']:.1f}%, pairs {rep['pairs']}, "
+          f"contacts {rep['contacts']}; max err x {rep['max_x']:.1e} v {rep['max_v']:.1e} w {rep['max_w']:.1e} "
+          f"q {rep['max_q']:.1e} n {rep['max_n']:.1e} p {rep['max_p']:.1e} phi {rep['max_phi']:.1e} "
+          f"lam/scale {rep['max_lam']:.1e}", flush=True)

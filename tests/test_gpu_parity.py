@@ -4,12 +4,14 @@ Both sides start every compared step from the identical float32 state (an
 oracle run rounded to float32, never a GPU output).  In scenes without a
 tie-band decision, pair keys, contact keys and colours are bit-exact;
 positions, velocities and orientations agree within 1e-4 relative (floors
-1 m, 1 m/s, 1 rad/s; 1e-4 rad for orientation).
+1 m, 1 m/s, 1 rad/s; 1e-4 rad for orientation).  In scenes with one, the
+same holds outside the tied bodies' contact islands.  Every check prints
+how many scenes the tie band flagged and how many bodies it excluded.
 """
 import numpy as np
 import pytest
 
-from gpu_util import compare, gpu_results, gpu_sim, oracle_warmup, snapshot32
+from gpu_util import compare, gpu_results, gpu_sim, oracle_warmup, report, snapshot32
 from helpers import DT, G, S, custom_batch
 from oracle import oracle as O
 
@@ -71,23 +73,26 @@ def test_drop_first_step_initial_state(torch_cuda, seed):
     b = S.batch_drop(1, seed0=seed)
     ora = O.OracleSim(b)
     sim, g, r = step_both(b, ora, O.COLD, 10)
-    rep = compare(b, g, r, ora)
+    rep = compare(b, g, r, ora, contact_values=True)
+    report(f"drop step 0 seed {seed}", rep)
     assert rep["scenes"] == 1
 
 
 @pytest.mark.parametrize("warm", [O.COLD, O.PREV])
 def test_drop_settled_parity(torch_cuda, warm):
     """Drop case, 64 bodies, one step from 8 oracle-settled states each."""
-    flagged = 0
-    checked = 0
+    tot = None
     for seed in range(8):
         b = S.batch_drop(1, seed0=100 + seed)
         ora = oracle_warmup(b, 60 + 10 * seed, iters=10, warm=O.PREV)
         sim, g, r = step_both(b, ora, warm, 10)
-        rep = compare(b, g, r, ora)
-        flagged += rep["flagged"]
-        checked += rep["scenes"] - rep["flagged"]
-    assert checked >= 4, f"only {checked} unflagged scenes"
+        rep = compare(b, g, r, ora, contact_values=True)
+        tot = rep if tot is None else {k: (max(tot[k], v) if k.startswith("max") else tot[k] + v)
+                                       for k, v in rep.items()}
+    tot["flagged_frac"] = tot["flagged"] / tot["scenes"]
+    tot["excluded_frac"] = tot["bodies_excluded"] / max(tot["bodies"], 1)
+    report(f"drop settled warm={warm}", tot)
+    assert tot["excluded_frac"] <= 0.5 and tot["contacts"] >= 100
 
 
 def test_drop_batch_many_scenes(torch_cuda):
@@ -95,8 +100,9 @@ def test_drop_batch_many_scenes(torch_cuda):
     b = S.batch_drop(16, seed0=300)
     ora = oracle_warmup(b, 90, iters=10, warm=O.PREV)
     sim, g, r = step_both(b, ora, O.PREV, 10)
-    rep = compare(b, g, r, ora)
-    assert rep["scenes"] - rep["flagged"] >= 8
+    rep = compare(b, g, r, ora, contact_values=True)
+    report("drop 16 scenes", rep)
+    assert rep["excluded_frac"] <= 0.5
 
 
 def test_large_scene_parity(torch_cuda):
@@ -107,8 +113,8 @@ def test_large_scene_parity(torch_cuda):
     assert b.counts().min() > 512
     ora = oracle_warmup(b, 60, iters=10, warm=O.PREV)
     sim, g, r = step_both(b, ora, O.PREV, 10, threads=256, max_contacts=1536)
-    rep = compare(b, g, r, ora)
-    assert rep["scenes"] - rep["flagged"] >= 1
+    rep = compare(b, g, r, ora, contact_values=True)
+    report("drop 520 bodies", rep)
     assert rep["contacts"] > 50
 
 
@@ -147,8 +153,9 @@ def test_clutter_arm_parity(torch_cuda):
     b = S.batch_clutter(6, seed0=10000)
     ora = oracle_warmup(b, 100, iters=20, warm=O.PREV)
     sim, g, r = step_both(b, ora, O.PREV, 20, step_index=100)
-    rep = compare(b, g, r, ora)
-    assert rep["scenes"] - rep["flagged"] >= 3
+    rep = compare(b, g, r, ora, contact_values=True)
+    report("clutter PREV 20 sweeps, 128 threads", rep)
+    assert rep["excluded_frac"] <= 0.5
     # arm joint angles and contact force
     np.testing.assert_allclose(g["theta"], ora.theta.reshape(-1, 7), rtol=0, atol=1e-6)
     unflagged = r["ambiguous"] == 0
@@ -159,38 +166,126 @@ def test_jacobi_parity(torch_cuda):
     b = S.batch_drop(4, seed0=700)
     ora = oracle_warmup(b, 80, iters=10, warm=O.PREV)
     sim, g, r = step_both(b, ora, O.PREV, 10, solver=O.JACOBI)
-    rep = compare(b, g, r, ora)
-    assert rep["scenes"] - rep["flagged"] >= 2
+    rep = compare(b, g, r, ora, contact_values=True)
+    report("drop Jacobi", rep)
+    assert rep["excluded_frac"] <= 0.5
 
 
 def test_tolerance_mode_sweeps(torch_cuda):
-    """Tolerance mode: same sweep counts where the residual is not at the threshold."""
-    b = S.batch_drop(4, seed0=800)
+    """Tolerance mode: sweep counts equal unless the oracle's residual came
+    within 2% of the tolerance at a stopping test; states and impulses
+    compared wherever the counts are equal."""
+    b = S.batch_drop(8, seed0=800)
     ora = oracle_warmup(b, 80, iters=10, warm=O.PREV)
     sim, g, r = step_both(b, ora, O.PREV, 200, tol=1e-4)
-    rep = compare(b, g, r, ora, check_values=False)
-    ok = r["ambiguous"] == 0
-    gs, os_ = g["stats"]["sweeps"][ok], r["sweeps"][ok]
-    assert np.mean(np.abs(gs - os_) <= 1) >= 0.75, (gs, os_)
+    rep = compare(b, g, r, ora, contact_values=True, tol_band=0.02)
+    report("drop tolerance 1e-4 PREV", rep)
+    assert rep["sweeps_equal"] >= 6
     assert np.all(g["stats"]["residual"][g["stats"]["flags"] & 4 == 0] <= 1e-4)
 
 
-def test_contact_values(torch_cuda):
-    """Normals, points, depths and impulses of unflagged scenes."""
-    b = S.batch_drop(4, seed0=900)
-    ora = oracle_warmup(b, 90, iters=10, warm=O.PREV)
-    sim, g, r = step_both(b, ora, O.PREV, 10)
-    compare(b, g, r, ora, check_values=False)
-    for s in range(4):
-        if r["ambiguous"][s]:
-            continue
-        n = int(r["n_contacts"][s])
-        np.testing.assert_allclose(g["normal"][:, s, :n].T, r["c_normal"][s, :n], atol=1e-5)
-        np.testing.assert_allclose(g["point"][:, s, :n].T, r["c_point"][s, :n], atol=1e-5)
-        np.testing.assert_allclose(g["phi"][s, :n], r["c_phi"][s, :n], atol=1e-5)
-        lam_o = r["c_lambda"][s, :n]
-        scale = np.maximum(np.abs(lam_o).max(), 1e-3)
-        assert np.max(np.abs(g["lam"][:, s, :n].T - lam_o)) <= 1e-3 * scale + 1e-6
+@pytest.mark.parametrize("warm", [O.COLD, O.PREV])
+def test_clutter_timed_configuration(torch_cuda, warm):
+    """The configuration the benchmark times: clutter scenes (statics,
+    spheres, boxes, capsules, the arm) settled by the oracle, one wave per
+    scene (64 threads), residual tolerance 1e-4 m/s with a 1,000-sweep cap,
+    cold and classic warm starts; keys, colours, contact geometry, impulses
+    and states compared."""
+    b = S.batch_clutter(8, seed0=10000)
+    ora = oracle_warmup(b, 150, iters=20, warm=O.PREV)
+    sim, g, r = step_both(b, ora, warm, 1000, tol=1e-4, threads=64, step_index=150)
+    rep = compare(b, g, r, ora, contact_values=True, tol_band=0.02)
+    report(f"clutter timed configuration warm={warm}", rep)
+    assert rep["contacts"] >= 500
+    assert rep["excluded_frac"] <= 0.5
+    np.testing.assert_allclose(g["theta"], ora.theta.reshape(-1, 7), rtol=0, atol=1e-6)
+    conv = (g["stats"]["flags"] & 4) == 0
+    assert np.all(g["stats"]["residual"][conv] <= 1e-4)
+
+
+def test_contact_values_clutter(torch_cuda):
+    """Normals, points, depths and impulses on clutter scenes (capsules,
+    static boxes and arm links among the pairs), fixed 20 sweeps."""
+    b = S.batch_clutter(4, seed0=10100)
+    ora = oracle_warmup(b, 120, iters=20, warm=O.PREV)
+    sim, g, r = step_both(b, ora, O.PREV, 20, threads=64, step_index=120)
+    rep = compare(b, g, r, ora, contact_values=True)
+    report("clutter contact values", rep)
+    # the compared contacts cover every kind of body
+    shapes, motion = b.shape, b.motion
+    kinds = set()
+    for s in range(b.n_scenes):
+        b0 = int(b.body_offset[s])
+        for k in g["key"][s, :int(g["count"][s])].astype(np.int64):
+            a, bb = int(k >> 20), int((k >> 8) & 0xFFF)
+            kinds.add(("shape", int(shapes[b0 + a])))
+            if bb != 0xFFF:
+                kinds.add(("shape", int(shapes[b0 + bb])))
+                kinds.add(("motion", int(motion[b0 + bb])))
+    assert {("shape", S.SPHERE), ("shape", S.BOX), ("shape", S.CAPSULE), ("motion", S.STATIC)} <= kinds, kinds
+
+
+def _tie_scene(reverse=False):
+    """Bodies whose AABBs touch exactly in float32 and float64 alike: margin
+    2^-6 m, sphere radius 7/64 m (AABB half-size 1/8), box half-extents 7/64
+    and 15/64 m, capsule radius 7/64 and half-length 1/8 m, identity
+    orientations, positions on a 1/4 m lattice: every AABB bound is a short
+    dyadic number, computed exactly on both sides."""
+    r, h = 7.0 / 64.0, 15.0 / 64.0
+    z0 = 1.0
+    bodies = []
+    # a row along x: consecutive spheres touch exactly (closed intervals)
+    for i in range(6):
+        bodies.append(dict(shape=S.SPHERE, param=[r, 0, 0], pos=[0.25 * i, 0.0, z0]))
+    # equal minima: a column along y at x = 0 (each touches its neighbour in y)
+    for j in range(1, 4):
+        bodies.append(dict(shape=S.SPHERE, param=[r, 0, 0], pos=[0.0, 0.25 * j, z0]))
+    # diagonal corner contact of AABBs
+    bodies.append(dict(shape=S.BOX, param=[r, r, r], pos=[0.25, 0.25, z0 + 0.25]))
+    # coincident bodies
+    bodies.append(dict(shape=S.SPHERE, param=[r, 0, 0], pos=[2.0, 2.0, z0]))
+    bodies.append(dict(shape=S.BOX, param=[r, r, r], pos=[2.0, 2.0, z0]))
+    # a long box spanning several spheres, touching on its end faces
+    bodies.append(dict(shape=S.BOX, param=[h, r, r], pos=[0.375, -0.25, z0]))
+    # just separated: a gap of 2^-20 m along x
+    bodies.append(dict(shape=S.SPHERE, param=[r, 0, 0], pos=[-0.25 - 2.0 ** -20, 0.0, z0]))
+    # capsule along z touching the row from above
+    bodies.append(dict(shape=S.CAPSULE, param=[r, 0.125, 0], pos=[0.5, 0.0, z0 + 0.375]))
+    # resting exactly on the ground (AABB minimum z = 0) and just above it
+    bodies.append(dict(shape=S.SPHERE, param=[r, 0, 0], pos=[-1.0, -1.0, 0.125]))
+    bodies.append(dict(shape=S.SPHERE, param=[r, 0, 0], pos=[-1.5, -1.0, 0.125 + 2.0 ** -20]))
+    # static boxes touching each other (no pair) and a dynamic sphere (a pair)
+    bodies.append(dict(shape=S.BOX, motion=S.STATIC, param=[r, r, r], pos=[-1.0, 1.0, z0]))
+    bodies.append(dict(shape=S.BOX, motion=S.STATIC, param=[r, r, r], pos=[-0.75, 1.0, z0]))
+    bodies.append(dict(shape=S.SPHERE, param=[r, 0, 0], pos=[-1.0, 1.25, z0]))
+    if reverse:
+        bodies = bodies[::-1]
+    return bodies
+
+
+@pytest.mark.parametrize("reverse", [False, True])
+def test_broadphase_exact_ties(torch_cuda, reverse):
+    """Sort-and-sweep against brute force on boxes that touch exactly: the
+    GPU's pair set equals the oracle's O(n^2) enumeration bit for bit with
+    no tie band (closed intervals: touching boxes pair; static-only pairs
+    never), for input in and against x order."""
+    bodies = _tie_scene(reverse)
+    b = custom_batch([bodies, bodies[::-1]])
+    consts = dict(margin=2.0 ** -6)
+    ora = O.OracleSim(b, **consts)
+    pose, vel, theta, cache = snapshot32(ora)
+    for threads in (64, 256):
+        sim = gpu_sim(b, pose, vel, theta, None, warm=O.COLD, threads=threads, **consts)
+        sim.step(None, DT, 1)
+        g = gpu_results(sim)
+        ora.set_state(pose, vel, theta)
+        r = ora.step(iters=1, warm=O.COLD, max_pairs=sim.max_pairs, max_contacts=sim.max_contacts)
+        for s in range(b.n_scenes):
+            n = int(r["n_pairs"][s])
+            assert int(g["stats"]["pairs"][s]) == n
+            assert np.array_equal(g["pair_key"][s, :n].astype(np.uint32), r["pair_key"][s, :n]), (s, threads)
+            assert n >= 20
+        assert r["ambiguous"].min() > 0          # the oracle does see the ties
 
 
 def test_capacity_flag(torch_cuda):
