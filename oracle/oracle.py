@@ -91,6 +91,9 @@ def lib():
         L.ora_collide.restype = C.c_int
         L.ora_pairs.argtypes = [_P(Model), _P(_d), C.c_int, _P(C.c_uint32), C.c_int]
         L.ora_pairs.restype = C.c_int
+        L.ora_arm_query.argtypes = [_P(Model), _P(_d), _P(_d), C.c_int, _d, _P(C.c_uint8), _P(_d),
+                                    _P(C.c_int32), C.c_int, C.c_int]
+        L.ora_arm_query.restype = C.c_int
         L.ora_mlp_forward.argtypes = [_P(Mlp), _P(_d), C.c_int, _P(_d)]
         L.ora_mlp_loss_grad.argtypes = [_P(Mlp), _P(_d), _P(_d), C.c_int] + [_P(_d)] * 6
         L.ora_mlp_loss_grad.restype = _d
@@ -193,6 +196,25 @@ class OracleSim:
         self._mlp_keep = keep
         self.mlp = Mlp(*[_ptr(keep[k], _d) for k in ("w1", "b1", "w2", "b2", "w3", "b3", "mean", "std")],
                        int(bf16))
+
+    # ---------------------------------------------------------------- queries
+    def arm_query(self, theta_q, clearance=0.0, scenes=None):
+        """Collision checks of arm configurations theta_q [S, M, 7] (float64)
+        against the current state.  Returns (hit [S, M] uint8, min_phi [S, M],
+        ambiguous [S, M] int32)."""
+        q = np.ascontiguousarray(np.asarray(theta_q, np.float64))
+        if q.ndim != 3 or q.shape[0] != self.S or q.shape[2] != 7:
+            raise ValueError("theta_q must be [S, M, 7]")
+        M = q.shape[1]
+        hit = np.zeros((self.S, M), np.uint8)
+        phi = np.full((self.S, M), np.inf)
+        amb = np.zeros((self.S, M), np.int32)
+        s0, s1 = (0, self.S) if scenes is None else scenes
+        rc = lib().ora_arm_query(C.byref(self.m), _ptr(self.pose, _d), _ptr(q, _d), int(M), float(clearance),
+                                 _ptr(hit, C.c_uint8), _ptr(phi, _d), _ptr(amb, C.c_int32), int(s0), int(s1))
+        if rc != 0:
+            raise ValueError("oracle rejected the query arguments")
+        return hit, phi, amb
 
     # ---------------------------------------------------------------- step
     def step(self, actions=None, dt=1.0 / 120.0, iters=10, tol=0.0, warm=COLD, solver=PGS,

@@ -1499,3 +1499,54 @@ int ora_pairs(const ora_model *m, const double *pose, int s, uint32_t *keys, int
     free(B);
     return n;
 }
+
+/* ---------------------------------------------------------------- arm queries
+ * Collision checks of candidate arm configurations, the test a sampling
+ * motion planner makes at every configuration it visits (Sec. 4.5 and
+ * App. C: the planner checks the arm against the scene at fine joint-space
+ * steps).  For scene s and configuration j the arm links are placed by the
+ * forward kinematics of theta_q[(s*M + j)*7 ..] and every link (a capsule)
+ * is tested against every body of the scene that is not an arm link (its
+ * pose as given) and against the ground plane; the arm itself is left out
+ * (its neighbouring links overlap at the joints by construction).  The
+ * separation of a (link, obstacle) pair is the least signed separation of
+ * its contacts (the narrowphase above, run with a margin just wider than the
+ * clearance so that its kept set holds every contact that decides); min_phi
+ * is the least over all pairs (+INF when no contact is within reach) and the
+ * configuration collides, hit = 1, iff min_phi <= clearance.  ambiguous
+ * counts configurations whose min_phi lies within BAND of the clearance. */
+int ora_arm_query(const ora_model *m, const double *pose, const double *theta_q, int M, double clearance,
+                  uint8_t *hit, double *min_phi, int32_t *ambiguous, int s0, int s1) {
+    if (!m || !m->arm || !pose || M < 0 || !(clearance >= 0) || s0 < 0 || s1 > m->n_scenes || s0 > s1) return -1;
+    if (M > 0 && (!theta_q || !hit)) return -1;
+    const double reach = clearance + 2.0 * BAND;
+    for (int s = s0; s < s1; s++) {
+        int b0 = m->body_offset[s], nb = m->body_offset[s + 1] - b0;
+        if (nb < 7) return -1;
+        int nobs = nb - 7;
+        for (int j = 0; j < M; j++) {
+            const size_t q = (size_t)s * (size_t)M + (size_t)j;
+            double lp[7][7];
+            V o[7], ax[7];
+            arm_fk(m, m->arm_base + 3 * s, theta_q + 7 * q, lp, o, ax);
+            double best = INFINITY;
+            for (int k = 0; k < 7; k++) {
+                Geom L = geom_of(ORA_CAPSULE, m->param + 3 * (size_t)(b0 + nobs + k), lp[k]);
+                PC c[4];
+                int amb = 0;
+                int n = ground_contacts(&L, reach, c, &amb);
+                for (int i = 0; i < n; i++) best = fmin(best, c[i].phi);
+                for (int b = 0; b < nobs; b++) {
+                    int g = b0 + b;
+                    Geom O = geom_of(m->shape[g], m->param + 3 * (size_t)g, pose + 7 * (size_t)g);
+                    n = collide(&L, &O, reach, c, &amb);
+                    for (int i = 0; i < n; i++) best = fmin(best, c[i].phi);
+                }
+            }
+            hit[q] = best <= clearance;
+            if (min_phi) min_phi[q] = best;
+            if (ambiguous) ambiguous[q] = fabs(best - clearance) < BAND;
+        }
+    }
+    return 0;
+}

@@ -119,6 +119,15 @@ int ora_collide(int shape_a, const double *param_a, const double *pose_a,
 /* Brute-force pair set of scene s at the given poses. Returns the count. */
 int ora_pairs(const ora_model *m, const double *pose, int s, uint32_t *keys, int cap);
 
+/* Collision queries of M arm configurations per scene (motion planning):
+ * theta_q [S*M*7] joint angles; hit [S*M] 1 iff some arm link comes within
+ * `clearance` of a body that is not an arm link or of the ground; min_phi
+ * [S*M] (may be NULL) the least separation found (+INF if none within
+ * reach); ambiguous [S*M] (may be NULL) 1 where min_phi is within the tie
+ * band of the clearance.  pose [N*7].  Returns 0, or -1 on a bad argument. */
+int ora_arm_query(const ora_model *m, const double *pose, const double *theta_q, int M, double clearance,
+                  uint8_t *hit, double *min_phi, int32_t *ambiguous, int s0, int s1);
+
 /* MLP: forward for n rows of 16 raw features -> n*3 outputs. */
 void ora_mlp_forward(const ora_mlp *net, const double *x, int n, double *y);
 

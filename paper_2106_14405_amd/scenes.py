@@ -513,3 +513,22 @@ def arm_actions(seed: int, n_scenes: int, step: int) -> np.ndarray:
 def arm_actions_block(seed: int, n_scenes: int, step0: int, n_steps: int) -> np.ndarray:
     """[n_steps, S, 7] joint velocities; same values as ``arm_actions``."""
     return np.stack([arm_actions(seed, n_scenes, step0 + t) for t in range(n_steps)])
+
+
+def arm_configurations(seed: int, n_scenes: int, M: int) -> np.ndarray:
+    """[S, M, 7] candidate arm configurations (rad) as a sampling planner
+    draws them, keyed (seed, 7, scene, configuration, joint): even-numbered
+    configurations uniform in [-pi, pi] per joint, odd-numbered ones with
+    joint 1 in [0.6, 2.4] rad (the arm leaning out and down over the floor and
+    the furniture) and the rest uniform in [-pi, pi]."""
+    s_ids = np.arange(n_scenes, dtype=np.uint64)[:, None]
+    j_ids = np.arange(M, dtype=np.uint64)[None, :]
+    keys = _stream_keys([seed, 7, s_ids, j_ids])                      # [S, M]
+    k = np.arange(1, ARM_LINKS + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = keys[..., None] + k * np.uint64(_GOLDEN)
+    u = (_mix_np(z) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    th = (2.0 * u - 1.0) * np.pi
+    lean = np.arange(M) % 2 == 1
+    th[:, lean, 1] = 0.6 + 1.8 * u[:, lean, 1]
+    return th.astype(np.float32)
