@@ -392,7 +392,10 @@ __device__ __forceinline__ V3 Imul(const float* I, V3 a) {
 __device__ __forceinline__ void proj_disk(float& l1, float& l2, float lim) {
   const float s2 = l1 * l1 + l2 * l2;
   if (s2 > lim * lim) {  // then s2 > 0
-    const float f = lim * __builtin_amdgcn_rsqf(s2);
+    // v_rsq_f32 reads a denormal s2 (|l| below 1e-19 N s) as zero and
+    // returns +inf, and 0 * inf is NaN when lim = 0; below 1e-30 the scale
+    // is taken at 1e-30, which still lands inside the disk (|l| f <= lim)
+    const float f = lim * __builtin_amdgcn_rsqf(fmaxf(s2, 1e-30f));
     l1 *= f;
     l2 *= f;
   }
