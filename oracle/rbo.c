@@ -908,9 +908,15 @@ typedef struct {
 } Con;
 
 /* Orthonormal tangents from a unit normal (Duff et al. 2017, "Building an
- * Orthonormal Basis, Revisited"). */
+ * Orthonormal Basis, Revisited").  Their construction has two branches, for
+ * the upper and the lower hemisphere of normals; the branch is taken at
+ * n.z = TAN_SPLIT instead of n.z = 0, so that the horizontal normals of
+ * side-by-side contacts (frequent under gravity along z) lie far from the
+ * switch.  Either branch is a valid basis wherever its denominator
+ * sgn + n.z stays away from 0 (|sgn + n.z| >= 1/2 here). */
+#define TAN_SPLIT (-0.5)
 static void tangents(V n, V *t1, V *t2) {
-    double sgn = copysign(1.0, n.z);
+    double sgn = n.z >= TAN_SPLIT ? 1.0 : -1.0;
     double a = -1.0 / (sgn + n.z);
     double b = n.x * n.y * a;
     *t1 = mk(1.0 + sgn * n.x * n.x * a, sgn * b, -sgn * n.x);
@@ -1278,6 +1284,11 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         c->ra = sub(c->p, A->x);
         c->rb = c->b >= 0 ? sub(c->p, B[c->b].x) : mk(0, 0, 0);
         tangents(c->n, &c->t1, &c->t2);
+        if (fabs(c->n.z - TAN_SPLIT) < BAND_DIM) {     /* the basis branch is a decision */
+            amb++;
+            tied[c->a] = 1;
+            if (c->b >= 0) tied[c->b] = 1;
+        }
         c->k[0] = row_k(B, c, c->n);
         c->k[1] = row_k(B, c, c->t1);
         c->k[2] = row_k(B, c, c->t2);

@@ -329,11 +329,16 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 
 // Tangent basis of a unit normal (Duff et al. 2017) with a hardware
 // reciprocal; used for every contact row of the step (setup, sweeps, cache).
-__device__ __forceinline__ float tangent_coef(V3 n) { return -frcp(copysignf(1.0f, n.z) + n.z); }
-// The basis from its coefficient a = -1 / (sign(n.z) + n.z) (kept in the
-// solver record so that the sweeps need no reciprocal).
+// The construction's two branches (upper and lower hemisphere) switch at
+// n.z = -1/2 rather than at 0, away from the horizontal normals of
+// side-by-side contacts; each branch's denominator stays >= 1/2 in size.
+constexpr float kTangentSplit = -0.5f;
+__device__ __forceinline__ float tangent_sign(V3 n) { return n.z >= kTangentSplit ? 1.0f : -1.0f; }
+__device__ __forceinline__ float tangent_coef(V3 n) { return -frcp(tangent_sign(n) + n.z); }
+// The basis from its coefficient a = -1 / (sgn + n.z) (kept in the solver
+// record so that the sweeps need no reciprocal).
 __device__ __forceinline__ void tangents_coef(V3 n, float a, V3& t1, V3& t2) {
-  float sgn = copysignf(1.0f, n.z);
+  float sgn = tangent_sign(n);
   float b = n.x * n.y * a;
   t1 = v3(1.0f + sgn * n.x * n.x * a, sgn * b, -sgn * n.x);
   t2 = v3(b, sgn + n.y * n.y * a, -n.y);
