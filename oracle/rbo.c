@@ -354,11 +354,11 @@ static int capsule_box(const Geom *C, const Geom *B, double margin, PC *out, int
         cand[nc] = tv; curv[nc] = den; nc++;
     }
     int bi = 0;
-    double bg = box_d2(add(p0, scl(d, cand[0])), h);
-    for (int i = 1; i < nc; i++) {
-        double g = box_d2(add(p0, scl(d, cand[i])), h);
-        if (g < bg || (g == bg && cand[i] < cand[bi])) { bg = g; bi = i; }
-    }
+    double gc[16];
+    for (int i = 0; i < nc; i++) gc[i] = box_d2(add(p0, scl(d, cand[i])), h);
+    double bg = gc[0];
+    for (int i = 1; i < nc; i++)
+        if (gc[i] < bg || (gc[i] == bg && cand[i] < cand[bi])) { bg = gc[i]; bi = i; }
     double t = cand[bi];
     V l = add(p0, scl(d, t));
     int n = 0;
@@ -367,7 +367,23 @@ static int capsule_box(const Geom *C, const Geom *B, double margin, PC *out, int
         double dist = sqrt(bg);
         if (dist < BAND) (*amb)++;
         int ncl = 0, a = -1;
-        for (int k = 0; k < 3; k++) if (fabs(comp(l, k)) > h[k]) { ncl++; a = k; }
+        for (int k = 0; k < 3; k++) {
+            if (fabs(fabs(comp(l, k)) - h[k]) < BAND) (*amb)++;   /* face / edge / corner region */
+            if (fabs(comp(l, k)) > h[k]) { ncl++; a = k; }
+        }
+        const int face = ncl == 1 && fabs(comp(d, a)) <= SIN_PAR * dl;
+        /* a plateau of the distance: another candidate as close within the
+         * band, at a different place, where the contacts would differ (the
+         * clipped segment does not depend on the point chosen on one face;
+         * a single contact sits at the point) */
+        for (int i = 0; i < nc; i++) {
+            if (i == bi || fabs(sqrt(gc[i]) - dist) >= BAND || fabs(cand[i] - t) * dl <= BAND) continue;
+            V li = add(p0, scl(d, cand[i]));
+            int nci = 0, ai = -1;
+            for (int k = 0; k < 3; k++) if (fabs(comp(li, k)) > h[k]) { nci++; ai = k; }
+            const int facei = nci == 1 && fabs(comp(d, ai)) <= SIN_PAR * dl;
+            if (!face || !facei || ai != a || (comp(li, ai) > 0) != (comp(l, a) > 0)) { (*amb)++; break; }
+        }
         int done = 0;
         if (ncl == 1) {
             double sa = comp(l, a) > 0 ? 1.0 : -1.0;
