@@ -75,16 +75,8 @@ __device__ inline void mlp_wave(const MlpParams& M, const float* x, bool valid, 
     }
     zp[p] = f2bf(z0) | (f2bf(z1) << 16);
   }
-  // weights as A tiles (shared by the four contact tiles)
-  mfma_s4 w1[4], w2[4][4], w3[4];
-#pragma unroll
-  for (int mb = 0; mb < 4; mb++) w1[mb] = load_a_tile(M.w1, 16, 64, 16 * mb, 0);
-#pragma unroll
-  for (int mb = 0; mb < 4; mb++)
-#pragma unroll
-    for (int kb = 0; kb < 4; kb++) w2[mb][kb] = load_a_tile(M.w2, 64, 64, 16 * mb, 16 * kb);
-#pragma unroll
-  for (int kb = 0; kb < 4; kb++) w3[kb] = load_a_tile(M.w3, 64, 3, 0, 16 * kb);
+  // weight tiles are loaded where they are used (the caches serve the
+  // repeats of the four contact tiles), so that few registers hold them
   float yt[4][3];
 #pragma unroll
   for (int t = 0; t < 4; t++) {
@@ -105,7 +97,7 @@ __device__ inline void mlp_wave(const MlpParams& M, const float* x, bool valid, 
     for (int mb = 0; mb < 4; mb++) {
       const int r = 16 * mb + 4 * g;
       mfma_f4 acc = {M.b1[r], M.b1[r + 1], M.b1[r + 2], M.b1[r + 3]};
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[mb], xb, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(load_a_tile(M.w1, 16, 64, 16 * mb, 0), xb, acc, 0, 0, 0);
       h1[mb] = pack4(fmaxf(acc.x, 0.f), fmaxf(acc.y, 0.f), fmaxf(acc.z, 0.f), fmaxf(acc.w, 0.f));
     }
 #pragma unroll
@@ -113,12 +105,15 @@ __device__ inline void mlp_wave(const MlpParams& M, const float* x, bool valid, 
       const int r = 16 * mb + 4 * g;
       mfma_f4 acc = {M.b2[r], M.b2[r + 1], M.b2[r + 2], M.b2[r + 3]};
 #pragma unroll
-      for (int kb = 0; kb < 4; kb++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2[mb][kb], h1[kb], acc, 0, 0, 0);
+      for (int kb = 0; kb < 4; kb++)
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(load_a_tile(M.w2, 64, 64, 16 * mb, 16 * kb), h1[kb], acc, 0,
+                                                        0, 0);
       h2[mb] = pack4(fmaxf(acc.x, 0.f), fmaxf(acc.y, 0.f), fmaxf(acc.z, 0.f), fmaxf(acc.w, 0.f));
     }
     mfma_f4 acc = {g == 0 ? M.b3[0] : 0.f, g == 0 ? M.b3[1] : 0.f, g == 0 ? M.b3[2] : 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < 4; kb++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w3[kb], h2[kb], acc, 0, 0, 0);
+    for (int kb = 0; kb < 4; kb++)
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(load_a_tile(M.w3, 64, 3, 0, 16 * kb), h2[kb], acc, 0, 0, 0);
     // outputs of contact 16t + col sit in lane col (rows 0..2 of the tile)
     yt[t][0] = acc.x;
     yt[t][1] = acc.y;
