@@ -142,6 +142,14 @@ P_ATOL = 1e-5      # m
 PHI_ATOL = 1e-5    # m
 LAM_REL = 2e-4     # impulses, relative to the scene's largest impulse ...
 LAM_ABS = 1e-6     # ... plus this (N s)
+# In tolerance mode a step runs hundreds of sweeps.  The impulses of a
+# statically indeterminate contact set (a box's four corners on a face, a
+# body wedged between two supports) are not unique: only their resultant on
+# each body is, and that is what the velocities check.  The split among
+# such contacts drifts with rounding over many sweeps (measured: 1e-3 of
+# the scene's largest impulse after 300 to 1,000 sweeps), so tolerance-mode
+# impulses are held only to this gross bar (a wrong sign, row or contact).
+LAM_REL_TOL = 1e-2
 
 
 def compare(batch, g, r, ora, check_values=True, contact_values=False, partial=True, tol_band=None, scenes=None):
@@ -149,10 +157,14 @@ def compare(batch, g, r, ora, check_values=True, contact_values=False, partial=T
 
     Unflagged scenes (no oracle decision in the tie band): pair keys,
     contact keys, colours and colour counts bit-exact; with check_values,
-    positions, velocities (1e-4 relative, floors 1 m, 1 m/s, 1 rad/s) and
-    orientations (1e-4 rad); with contact_values, normals, points, depths
-    and impulses of every contact.  Flagged scenes (partial=True): the same
-    comparisons restricted to what lies outside `affected_bodies`.
+    positions (1e-4 relative, floor 1 m), velocities (1e-4 relative to the
+    speed, floor 1 m/s; angular velocities as the surface speed |w| r of
+    the body) and orientations (1e-4 rad); with contact_values, normals,
+    points, depths and impulses of every contact (impulses at LAM_REL with a
+    fixed sweep count, at LAM_REL_TOL in tolerance mode).  Flagged scenes
+    (partial=True): pairs, contact keys and contact geometry outside the
+    tied pairs' bodies, colours, impulses and states outside their islands
+    (`affected_bodies`).
 
     Sweep counts: with a fixed sweep count they are equal by construction.
     In tolerance mode (tol_band set) they must be equal in unflagged scenes
@@ -162,7 +174,8 @@ def compare(batch, g, r, ora, check_values=True, contact_values=False, partial=T
     are not compared (the pre-solve results still are).  Returns a report;
     raises on a mismatch."""
     rep = dict(scenes=0, flagged=0, flagged_compared=0, skipped=0, sweeps_equal=0, sweeps_band=0,
-               values_skipped=0, bodies=0, bodies_excluded=0, contacts=0, pairs=0, max_x=0.0, max_v=0.0,
+               values_skipped=0, bodies=0, bodies_excluded=0, bodies_tied=0, contacts=0, contacts_solved=0,
+               pairs=0, max_x=0.0, max_v=0.0,
                max_w=0.0, max_q=0.0, max_n=0.0, max_p=0.0, max_phi=0.0, max_lam=0.0)
     Sn = batch.n_scenes
     pose_o = ora.pose.reshape(-1, 7)
@@ -186,9 +199,14 @@ def compare(batch, g, r, ora, check_values=True, contact_values=False, partial=T
             rep["flagged_compared"] += 1
         values = same_sweeps
         rep["values_skipped"] += int(not values)
+        # pairs, contact keys and contact geometry are per pair: only the
+        # tied pairs' own bodies are left out; colours, impulses and states
+        # couple through the contacts: the tied bodies' islands are left out
+        tied = r["tied"][b0:b1].astype(bool)
         aff = affected_bodies(batch, s, g, r)
         rep["bodies"] += b1 - b0
         rep["bodies_excluded"] += int(aff.sum())
+        rep["bodies_tied"] += int(tied.sum())
         # pair sets
         np_o = int(r["n_pairs"][s])
         np_g = int(g["stats"]["pairs"][s])
@@ -196,7 +214,7 @@ def compare(batch, g, r, ora, check_values=True, contact_values=False, partial=T
         pk_g = g["pair_key"][s, :np_g].astype(np.uint32)
         if not flagged:
             assert np_g == np_o, f"scene {s}: {np_g} pairs on the GPU, {np_o} in the oracle"
-        ko, kg_ = pk_o[_keep_pairs(pk_o, aff)], pk_g[_keep_pairs(pk_g, aff)]
+        ko, kg_ = pk_o[_keep_pairs(pk_o, tied)], pk_g[_keep_pairs(pk_g, tied)]
         assert np.array_equal(kg_, ko), f"scene {s}: pair keys differ (flagged={flagged})"
         rep["pairs"] += len(ko)
         # contact keys, colours
@@ -207,10 +225,8 @@ def compare(batch, g, r, ora, check_values=True, contact_values=False, partial=T
             assert int(g["stats"]["colours"][s]) == int(r["n_colours"][s])
         ck_o = r["c_key"][s, :nc]
         ck_g = g["key"][s, :ncg].astype(np.uint32)
-        mo, mg = _keep_contacts(ck_o, aff), _keep_contacts(ck_g, aff)
+        mo, mg = _keep_contacts(ck_o, tied), _keep_contacts(ck_g, tied)
         assert np.array_equal(ck_g[mg], ck_o[mo]), f"scene {s}: contact keys differ (flagged={flagged})"
-        assert np.array_equal(g["colour"][s, :ncg][mg], r["c_colour"][s, :nc][mo]), \
-            f"scene {s}: colours differ (flagged={flagged})"
         rep["contacts"] += int(mo.sum())
         if contact_values and mo.any():
             io, ig = np.nonzero(mo)[0], np.nonzero(mg)[0]
@@ -223,20 +239,35 @@ def compare(batch, g, r, ora, check_values=True, contact_values=False, partial=T
             assert en <= N_ATOL, f"scene {s}: normal error {en:.3e}"
             assert ep <= P_ATOL, f"scene {s}: point error {ep:.3e}"
             assert eph <= PHI_ATOL, f"scene {s}: depth error {eph:.3e}"
+        # colours and impulses: outside the tied islands
+        mo, mg = _keep_contacts(ck_o, aff), _keep_contacts(ck_g, aff)
+        assert np.array_equal(ck_g[mg], ck_o[mo]), f"scene {s}: contact keys differ (flagged={flagged})"
+        assert np.array_equal(g["colour"][s, :ncg][mg], r["c_colour"][s, :nc][mo]), \
+            f"scene {s}: colours differ (flagged={flagged})"
+        rep["contacts_solved"] += int(mo.sum())
+        if contact_values and mo.any():
+            io, ig = np.nonzero(mo)[0], np.nonzero(mg)[0]
             if values:
                 lam_o = r["c_lambda"][s, io]
                 scale = float(np.abs(r["c_lambda"][s, :nc]).max())
                 el = np.max(np.abs(g["lam"][:, s, ig].T - lam_o))
                 rep["max_lam"] = max(rep["max_lam"], el / max(scale, 1e-12))
-                assert el <= LAM_REL * scale + LAM_ABS, f"scene {s}: impulse error {el:.3e} (scale {scale:.3e})"
+                bar = LAM_REL if tol_band is None else LAM_REL_TOL
+                assert el <= bar * scale + LAM_ABS, f"scene {s}: impulse error {el:.3e} (scale {scale:.3e})"
         if not check_values or not values:
             continue
         keep = ~aff
         xo, xg = pose_o[b0:b1, :3][keep], g["pose"][b0:b1, :3][keep]
         ex = np.max(np.abs(xg - xo) / np.maximum(np.abs(xo), X_FLOOR), initial=0.0)
         vo, vg = vel_o[b0:b1][keep], g["vel"][b0:b1][keep]
-        ev = np.max(np.abs(vg[:, :3] - vo[:, :3]) / np.maximum(np.abs(vo[:, :3]), V_FLOOR), initial=0.0)
-        ew = np.max(np.abs(vg[:, 3:] - vo[:, 3:]) / np.maximum(np.abs(vo[:, 3:]), V_FLOOR), initial=0.0)
+        # velocities as vectors: the error relative to the oracle's speed
+        # (floor 1 m/s); an angular velocity by the surface speed |w| r it
+        # gives the body (r its bounding radius), with the same floor
+        rad = np.array([S.bounding_radius(int(batch.shape[i]), batch.param[i]) for i in range(b0, b1)])[keep]
+        nv = np.linalg.norm
+        ev = np.max(nv(vg[:, :3] - vo[:, :3], axis=1) / np.maximum(nv(vo[:, :3], axis=1), V_FLOOR), initial=0.0)
+        ew = np.max(nv(vg[:, 3:] - vo[:, 3:], axis=1) * rad / np.maximum(nv(vo[:, 3:], axis=1) * rad, V_FLOOR),
+                    initial=0.0)
         eq = np.max(quat_angle(pose_o[b0:b1, 3:][keep], g["pose"][b0:b1, 3:][keep]), initial=0.0)
         rep["max_x"] = max(rep["max_x"], ex)
         rep["max_v"] = max(rep["max_v"], ev)
@@ -256,7 +287,8 @@ def report(name, rep):
     print(f"[parity] {name}: scenes {rep['scenes']}, flagged {rep['flagged']} "
           f"({100 * rep['flagged_frac']:.0f}%, {rep['flagged_compared']} compared outside the tied islands, "
           f"{rep['skipped']} skipped), sweeps equal in {rep['sweeps_equal']} ({rep['sweeps_band']} differ inside "
-          f"the stop band, values skipped in {rep['values_skipped']}), bodies excluded {100 * rep['excluded_frac']:.1f}%, pairs {rep['pairs']}, "
-          f"contacts {rep['contacts']}; max err x {rep['max_x']:.1e} v {rep['max_v']:.1e} w {rep['max_w']:.1e} "
+          f"the stop band, values skipped in {rep['values_skipped']}), bodies tied {rep['bodies_tied']}, "
+          f"in tied islands {100 * rep['excluded_frac']:.1f}%, pairs {rep['pairs']}, "
+          f"contacts {rep['contacts']} ({rep['contacts_solved']} outside tied islands); max err x {rep['max_x']:.1e} v {rep['max_v']:.1e} w {rep['max_w']:.1e} "
           f"q {rep['max_q']:.1e} n {rep['max_n']:.1e} p {rep['max_p']:.1e} phi {rep['max_phi']:.1e} "
           f"lam/scale {rep['max_lam']:.1e}", flush=True)

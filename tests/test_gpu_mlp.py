@@ -247,7 +247,10 @@ def test_features_match_oracle(torch_cuda, warm):
     sim.step(None, DT, 300)
     r = ora.step(iters=300, tol=1e-6, warm=warm, max_pairs=sim.max_pairs, max_contacts=sim.max_contacts)
     g = gpu_results(sim)
-    rep = compare(b, g, r, ora)
+    # at 1e-6 m/s the float32 residual is within a decade of its rounding
+    # floor (impulses near 1 N s, 6e-8 relative, effective inverse masses
+    # near 10): stop decisions within a factor 2 of the tolerance are ties
+    rep = compare(b, g, r, ora, tol_band=1.0)
     assert rep["contacts"] >= 50
     for s in range(b.n_scenes):
         if r["ambiguous"][s]:

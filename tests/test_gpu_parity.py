@@ -219,6 +219,7 @@ def test_contact_values_clutter(torch_cuda):
         for k in g["key"][s, :int(g["count"][s])].astype(np.int64):
             a, bb = int(k >> 20), int((k >> 8) & 0xFFF)
             kinds.add(("shape", int(shapes[b0 + a])))
+            kinds.add(("motion", int(motion[b0 + a])))
             if bb != 0xFFF:
                 kinds.add(("shape", int(shapes[b0 + bb])))
                 kinds.add(("motion", int(motion[b0 + bb])))
