@@ -166,6 +166,23 @@ int sim_create(const sim_batch_desc *desc, void *d_workspace, size_t workspace_b
  * handle's stream; per-scene soft faults go to the stats flags. */
 int sim_step(sim_handle *h, const float *d_actions, float dt, int iters);
 
+/* Collision checks of candidate arm configurations, the test a sampling
+ * motion planner runs at every configuration it visits (Sec. 4.5 and
+ * App. C: the planner checks the arm against the scene at fine joint-space
+ * steps): for each scene s and configuration j, the arm links placed by the
+ * forward kinematics of d_theta[(s*M + j)*7 .. +7] (rad, device float32
+ * [S][M][7]) are tested against every body of scene s that is not an arm
+ * link, at its current pose, and against the ground plane; the arm itself
+ * is left out.  d_hit[s*M + j] (device uint8 [S][M]) = 1 iff some link has a
+ * contact with signed separation <= clearance (m, finite, >= 0);
+ * d_min_phi (device float32 [S][M], or NULL) gets the least separation of
+ * those contacts, +INF when none is within the clearance.  The scenes'
+ * state is read, not changed; no solver runs.  SIM_EINVAL for a batch
+ * without the arm, M < 0, a bad clearance or NULL/misaligned arrays
+ * (nothing launched); M = 0 does nothing.  Asynchronous on the handle's
+ * stream, after any step enqueued before it. */
+int sim_query_arm(sim_handle *h, const float *d_theta, int M, float clearance, uint8_t *d_hit, float *d_min_phi);
+
 /* Contact and pair views of the last step (device pointers into the
  * workspace, valid until the next step): the contacts whose impulses make
  * up the arm's collision force that the Pick task reads (Sec. 5; appendix,

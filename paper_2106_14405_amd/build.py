@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librbsim.so")
-SOURCES = ["step.hip", "mlp.hip", "api.hip"]
+SOURCES = ["step.hip", "query.hip", "mlp.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed fp32 instructions (v_pk_*_f32) in any generated code

@@ -34,6 +34,10 @@ extern "C" int rbs_mlp_export(const float* prm, uint16_t* wbf, float* bias, hipS
 extern "C" int rbs_gather(const int32_t* count, const int32_t* flags, int S, int CM, long scm, const float* feat,
                           const float* lam, float inv_gdt, float tclip, int64_t* offs, int32_t* cnt, float* x,
                           float* t, long cap, long long* total, hipStream_t st);
+extern "C" int rbs_launch_query(int n_scenes, int max_bodies, long n_bodies, const int32_t* body_offset,
+                                const uint8_t* shape, const float* prm, const float* pose, const float* arm_base,
+                                const float* link_len, const float* theta, int M, float clearance, uint8_t* hit,
+                                float* min_phi, hipStream_t stream);
 extern "C" int rbs_launch_arm_pose(const rbs::StepParams* P, const uint8_t* mask, hipStream_t stream);
 extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, int K, const int32_t* index,
                                 const float* pool_pose, const float* pool_vel, const float* pool_theta,
@@ -715,6 +719,24 @@ int sim_step(sim_handle* h, const float* d_actions, float dt, int iters) {
   h->parity ^= 1;
   h->last_dt = dt;
   h->last_export = h->export_on;
+  return SIM_OK;
+}
+
+int sim_query_arm(sim_handle* h, const float* d_theta, int M, float clearance, uint8_t* d_hit, float* d_min_phi) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (!h->arm) return fail(SIM_EINVAL, "the batch has no arm");
+  if (M < 0) return fail(SIM_EINVAL, "M must be >= 0");
+  if (!(clearance >= 0.f) || !std::isfinite(clearance)) return fail(SIM_EINVAL, "clearance must be finite and >= 0");
+  if (M == 0) return SIM_OK;
+  if (!d_theta || !d_hit) return fail(SIM_EINVAL, "NULL pointer");
+  if (!aligned(d_theta, 4) || (d_min_phi && !aligned(d_min_phi, 4))) return fail(SIM_EINVAL, "misaligned array");
+  int nb_max = 0;
+  for (int s = 0; s < h->S; s++) nb_max = std::max(nb_max, h->body_offset[s + 1] - h->body_offset[s]);
+  const rbs::StepParams P = params(h);
+  const int rc = rbs_launch_query(h->S, nb_max, h->N, P.body_offset, P.shape, P.prm, P.pose, P.arm_base,
+                                  h->link_len, d_theta, M, clearance, d_hit, d_min_phi, h->stream);
+  if (rc == -2) return fail(SIM_EINVAL, "too many scenes x configuration blocks for one launch");
+  if (rc != 0) return fail(SIM_EDEVICE, std::string("query launch failed: ") + hipGetErrorString((hipError_t)rc));
   return SIM_OK;
 }
 

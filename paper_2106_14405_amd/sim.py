@@ -161,6 +161,24 @@ class Sim:
             ptr = C.c_void_p(actions.data_ptr())
         L.check(L.load().sim_step(self.h, ptr, float(dt), int(iters)), "sim_step")
 
+    def query_arm(self, theta: torch.Tensor, clearance: float = 0.0, min_phi: bool = True):
+        """Collision checks of arm configurations theta [S, M, 7] (float32, rad)
+        against the current state: returns hit [S, M] uint8 and, if asked,
+        the least separation [S, M] float32 (+inf when none is within the
+        clearance)."""
+        if theta.device != self.device or theta.dtype != torch.float32 or not theta.is_contiguous():
+            raise ValueError("theta must be a contiguous float32 tensor on the simulation device")
+        if theta.dim() != 3 or theta.shape[0] != self.S or theta.shape[2] != 7:
+            raise ValueError("theta must be [S, M, 7]")
+        M = int(theta.shape[1])
+        hit = torch.empty((self.S, M), dtype=torch.uint8, device=self.device)
+        phi = torch.empty((self.S, M), dtype=torch.float32, device=self.device) if min_phi else None
+        L.check(L.load().sim_query_arm(self.h, C.c_void_p(theta.data_ptr()), M, float(clearance),
+                                       C.c_void_p(hit.data_ptr()),
+                                       C.c_void_p(phi.data_ptr()) if phi is not None else None),
+                "sim_query_arm")
+        return hit, phi
+
     def set_trace(self, on: bool = True):
         """Per-scene phase timestamps ([S, 16] int64 device tensor) written by every later step."""
         if on:
