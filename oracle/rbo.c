@@ -363,7 +363,25 @@ static int capsule_box(const Geom *C, const Geom *B, double margin, PC *out, int
     V l = add(p0, scl(d, t));
     int n = 0;
     PC loc[4];
-    if (bg > 0.0) {
+    /* Whether the core meets the box: the segment clipped to the box's three
+     * slabs (Liang and Barsky 1984) is non-empty, t_in <= t_out.  A core that
+     * passes through the box gives a clear margin t_out - t_in; the zero
+     * distance of its crossing point would be at the mercy of rounding. */
+    double t_in = 0.0, t_out = 1.0;
+    for (int k = 0; k < 3; k++) {
+        double dk = comp(d, k), pk = comp(p0, k);
+        if (dk == 0.0) {
+            if (fabs(fabs(pk) - h[k]) < BAND) (*amb)++;
+            if (fabs(pk) > h[k]) t_out = -1.0;
+            continue;
+        }
+        double u0 = (-h[k] - pk) / dk, u1 = (h[k] - pk) / dk;
+        t_in = fmax(t_in, fmin(u0, u1));
+        t_out = fmin(t_out, fmax(u0, u1));
+    }
+    int meets = t_in <= t_out || bg <= 0.0;
+    if (fabs(t_out - t_in) * dl < BAND) (*amb)++;           /* grazing */
+    if (!meets) {
         double dist = sqrt(bg);
         if (dist < BAND) (*amb)++;
         int ncl = 0, a = -1;

@@ -352,7 +352,24 @@ __device__ inline void capsule_box(const Geom& C, const Geom& B, float margin, O
   V3 l = p0 + d * bt;
   Out4 loc;
   loc.n = 0;
-  if (bg > 0.f) {
+  // the core meets the box iff the segment clipped to the three slabs
+  // (Liang and Barsky 1984) is non-empty: a core passing through the box
+  // is told apart by the clipped length, not by a crossing point's zero
+  // distance, which rounding can leave slightly positive
+  float t_in = 0.f, t_out = 1.f;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const float dk = comp(d, k), pk = comp(p0, k);
+    if (dk == 0.f) {
+      if (fabsf(pk) > h[k]) t_out = -1.f;
+      continue;
+    }
+    const float u0 = fdiv(-h[k] - pk, dk), u1 = fdiv(h[k] - pk, dk);
+    t_in = fmaxf(t_in, fminf(u0, u1));
+    t_out = fminf(t_out, fmaxf(u0, u1));
+  }
+  const bool meets = t_in <= t_out || !(bg > 0.f);
+  if (!meets) {
     float dist = fsqrt(bg);
     float dl = fsqrt(len2(d));
     int ncl = 0, a = -1;
