@@ -81,8 +81,8 @@ def parse():
     ap.add_argument("--learned-scenes", type=int, default=2048)
     ap.add_argument("--learned-steps", type=int, default=240)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-scenes-per-thread", type=int, default=4)
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-scenes-per-thread", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="only run an elementwise copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -103,7 +103,7 @@ def probe_copy(mib):
 
 def kernel_hash():
     h = hashlib.sha256()
-    for f in ("step.hip", "geom.h", "sim_internal.h", "mlp_mfma.h", "mlp.hip"):
+    for f in ("step.hip", "arm.h", "geom.h", "sim_internal.h", "mlp_mfma.h", "mlp.hip"):
         p = os.path.join(ROOT, "paper_2106_14405_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
