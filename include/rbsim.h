@@ -279,6 +279,22 @@ int sim_mlp_grad(const float *d_params, const float *d_mean, const float *d_std,
                  const int32_t *d_rows, long n, float *d_grad, float *d_loss, void *d_work, size_t work_bytes,
                  void *stream);
 
+/* sim_mlp_grad without a caller workspace, for callers that cannot allocate
+ * device memory (code under stream capture, tight training loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and result as
+ * sim_mlp_grad, bit for bit; the per-workgroup partial sums live in a
+ * library-owned static device array of 5.6 MB, one copy per device, held
+ * until the process ends.  n must lie in [1, sim_mlp_grad_noalloc_max_rows()]
+ * (16384): SIM_EINVAL otherwise, before any device work.  Allocates nothing
+ * (its first call on a device looks the array's address up).  Every call on
+ * a device shares that device's array: calls that overlap in time on one
+ * device (two streams, two host threads) race and give undefined gradients;
+ * calls ordered on one stream are safe.  Asynchronous on stream. */
+int sim_mlp_grad_noalloc(const float *d_params, const float *d_mean, const float *d_std, const float *d_x,
+                         const float *d_t, const int32_t *d_rows, long n, float *d_grad, float *d_loss,
+                         void *stream);
+long sim_mlp_grad_noalloc_max_rows(void);
+
 /* One Adam step (the optimizer of App. B.2; beta1 0.9, beta2 0.999, eps
  * 1e-8, bias-corrected; step counts from 1) on the fp32 master parameters, after scaling the gradient
  * to global L2 norm <= clip (clip 0: no clipping).  d_m, d_v: [5443]

@@ -74,7 +74,7 @@ EXPORTED = ["sim_workspace_bytes", "sim_create", "sim_step", "sim_contacts", "si
             "sim_destroy", "sim_last_error", "sim_mlp_forward", "sim_mlp_workspace_bytes", "sim_mlp_stats",
             "sim_mlp_grad", "sim_mlp_adam", "sim_mlp_export", "sim_mlp_gather", "sim_set_persistent",
             "sim_autotune_scratch_bytes", "sim_autotune", "sim_state_bytes", "sim_save_state",
-            "sim_load_state", "sim_query_arm"]
+            "sim_load_state", "sim_mlp_grad_noalloc", "sim_mlp_grad_noalloc_max_rows", "sim_query_arm"]
 
 _lib = None
 
@@ -111,6 +111,9 @@ def load():
     L.sim_mlp_workspace_bytes.restype = C.c_size_t
     L.sim_mlp_stats.argtypes = [_v, C.c_long, _v, _v, _v, C.c_size_t, _v]
     L.sim_mlp_grad.argtypes = [_v, _v, _v, _v, _v, _v, C.c_long, _v, _v, _v, C.c_size_t, _v]
+    L.sim_mlp_grad_noalloc.argtypes = [_v, _v, _v, _v, _v, _v, C.c_long, _v, _v, _v]
+    L.sim_mlp_grad_noalloc_max_rows.argtypes = []
+    L.sim_mlp_grad_noalloc_max_rows.restype = C.c_long
     L.sim_mlp_adam.argtypes = [_v, _v, _v, _v, C.c_int, _f, _f, _v, _v]
     L.sim_mlp_export.argtypes = [_v, _v, _v, _v]
     L.sim_mlp_gather.argtypes = [_v, _v, _v, C.c_long, _f, _v]
@@ -125,7 +128,7 @@ def load():
     L.sim_load_state.argtypes = [_v, _v]
     for name in ("sim_create", "sim_step", "sim_contacts", "sim_state", "sim_stats", "sim_set_export",
                  "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_trace", "sim_set_stream",
-                 "sim_mlp_forward", "sim_mlp_stats", "sim_mlp_grad", "sim_mlp_adam", "sim_mlp_export",
+                 "sim_mlp_forward", "sim_mlp_stats", "sim_mlp_grad", "sim_mlp_grad_noalloc", "sim_mlp_adam", "sim_mlp_export",
                  "sim_mlp_gather", "sim_set_persistent", "sim_query_arm", "sim_autotune", "sim_save_state", "sim_load_state"):
         getattr(L, name).restype = C.c_int
     _lib = L

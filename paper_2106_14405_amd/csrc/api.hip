@@ -28,6 +28,10 @@ extern "C" size_t rbs_mlp_work_bytes(long n);
 extern "C" int rbs_mlp_stats(const float* x, long n, float* mean, float* stdv, void* work, hipStream_t st);
 extern "C" int rbs_mlp_grad(const float* prm, const float* mean, const float* stdv, const float* x, const float* t,
                             const int32_t* rows, long n, float* grad, float* loss, void* work, hipStream_t st);
+extern "C" long rbs_mlp_grad_static_max_rows();
+extern "C" int rbs_mlp_grad_static(const float* prm, const float* mean, const float* stdv, const float* x,
+                                   const float* t, const int32_t* rows, long n, float* grad, float* loss,
+                                   hipStream_t st);
 extern "C" int rbs_mlp_adam(float* prm, float* m1, float* m2, const float* grad, int step, float lr, float clip,
                             float* gnorm, hipStream_t st);
 extern "C" int rbs_mlp_export(const float* prm, uint16_t* wbf, float* bias, hipStream_t st);
@@ -1003,6 +1007,21 @@ int sim_mlp_grad(const float* d_params, const float* d_mean, const float* d_std,
     return fail(SIM_EWORKSPACE, "workspace too small or not 256-byte aligned");
   if (rbs_mlp_grad(d_params, d_mean, d_std, d_x, d_t, d_rows, n, d_grad, d_loss, d_work, (hipStream_t)stream) != 0)
     return fail(SIM_EDEVICE, "gradient launch failed");
+  return SIM_OK;
+}
+
+long sim_mlp_grad_noalloc_max_rows(void) { return rbs_mlp_grad_static_max_rows(); }
+
+int sim_mlp_grad_noalloc(const float* d_params, const float* d_mean, const float* d_std, const float* d_x,
+                         const float* d_t, const int32_t* d_rows, long n, float* d_grad, float* d_loss, void* stream) {
+  if (n < 1) return fail(SIM_EINVAL, "n must be >= 1");
+  if (n > rbs_mlp_grad_static_max_rows())
+    return fail(SIM_EINVAL, "n = " + std::to_string(n) + " exceeds the " +
+                                std::to_string(rbs_mlp_grad_static_max_rows()) + " rows of the static scratch");
+  if (!d_params || !d_mean || !d_std || !d_x || !d_t || !d_grad) return fail(SIM_EINVAL, "NULL pointer");
+  const int rc = rbs_mlp_grad_static(d_params, d_mean, d_std, d_x, d_t, d_rows, n, d_grad, d_loss,
+                                     (hipStream_t)stream);
+  if (rc != 0) return fail(SIM_EDEVICE, "static scratch lookup or gradient launch failed");
   return SIM_OK;
 }
 

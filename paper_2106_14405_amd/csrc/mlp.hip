@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "mlp_mfma.h"
 #include "sim_internal.h"
 
@@ -400,6 +402,44 @@ extern "C" int rbs_mlp_grad(const float* prm, const float* mean, const float* st
   hipLaunchKernelGGL(mlp_grad_reduce, dim3((kNP + 1 + 255) / 256), dim3(256), 0, st, (const float*)work, (int)nblk,
                      grad, loss);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---- the gradient without caller scratch -------------------------------------
+// The per-workgroup partial sums of the gradient live in a file-scope device
+// array instead of a caller workspace, for callers that cannot allocate.
+// Each device holds its own copy; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device (the array's name is a
+// host-side stand-in, not a device address).
+constexpr long kStaticGradRows = 16384;  // 256 workgroups of partial sums, 5.6 MB
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) float scratch[(kStaticGradRows / kGradRows) * (kNP + 1)];
+
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device, looked up once per device.
+static int static_scratch(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return -1;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+extern "C" long rbs_mlp_grad_static_max_rows() { return kStaticGradRows; }
+
+extern "C" int rbs_mlp_grad_static(const float* prm, const float* mean, const float* stdv, const float* x,
+                                   const float* t, const int32_t* rows, long n, float* grad, float* loss,
+                                   hipStream_t st) {
+  if (n < 1 || n > kStaticGradRows) return -2;
+  float* work = nullptr;
+  if (static_scratch(&work) != 0) return -1;
+  return rbs_mlp_grad(prm, mean, stdv, x, t, rows, n, grad, loss, work, st);
 }
 
 extern "C" int rbs_mlp_adam(float* prm, float* m1, float* m2, const float* grad, int step, float lr, float clip,

@@ -138,6 +138,23 @@ class Net:
                 "sim_mlp_grad")
         return self.grad
 
+    def compute_grad_noalloc(self, x: torch.Tensor, t: torch.Tensor, rows: torch.Tensor | None = None,
+                             n: int | None = None) -> torch.Tensor:
+        """compute_grad through sim_mlp_grad_noalloc: no workspace, at most
+        sim_mlp_grad_noalloc_max_rows() rows."""
+        self._check_rows(x, 16, "x")
+        self._check_rows(t, 3, "t")
+        if rows is not None:
+            if rows.dtype != torch.int32 or rows.device != self.device or not rows.is_contiguous():
+                raise ValueError("rows must be a contiguous int32 device tensor")
+            n = int(rows.numel()) if n is None else int(n)
+        else:
+            n = int(x.shape[0]) if n is None else int(n)
+        L.check(self.lib.sim_mlp_grad_noalloc(_p(self.params), _p(self.mean), _p(self.std), _p(x), _p(t), _p(rows),
+                                              n, _p(self.grad), _p(self.loss), _stream(self.device)),
+                "sim_mlp_grad_noalloc")
+        return self.grad
+
     def adam(self, lr: float, clip: float = 0.5):
         self.step_count += 1
         L.check(self.lib.sim_mlp_adam(_p(self.params), _p(self.m), _p(self.v), _p(self.grad), self.step_count,
