@@ -49,7 +49,8 @@ class Model(C.Structure):
                 ("friction", _P(_d)), ("restitution", _P(_d)), ("arm", C.c_int),
                 ("arm_base", _P(_d)), ("link_len", _d * 7), ("arm_radius", _d),
                 ("gravity", _d * 3), ("margin", _d), ("baumgarte", _d), ("slop", _d),
-                ("rest_thresh", _d), ("ground_friction", _d), ("ground_restitution", _d)]
+                ("rest_thresh", _d), ("ground_friction", _d), ("ground_restitution", _d),
+                ("sleep_speed", _d), ("sleep_steps", C.c_int)]
 
 
 class Cache(C.Structure):
@@ -82,7 +83,7 @@ def lib():
     if _lib is None:
         path = build()
         L = C.CDLL(path)
-        L.ora_step.argtypes = [_P(Model), _P(_d), _P(_d), _P(_d), _P(Cache), _P(_d), _d, C.c_int,
+        L.ora_step.argtypes = [_P(Model), _P(_d), _P(_d), _P(_d), _P(C.c_int32), _P(Cache), _P(_d), _d, C.c_int,
                                _d, C.c_int, C.c_int, _P(Mlp), _P(Out), C.c_int, C.c_int]
         L.ora_step.restype = C.c_int
         L.ora_arm_pose.argtypes = [_P(Model), _P(_d), _P(_d)]
@@ -131,6 +132,7 @@ class OracleSim:
         self.pose = np.ascontiguousarray(b.pose, np.float64).reshape(-1).copy()
         self.vel = np.ascontiguousarray(b.vel, np.float64).reshape(-1).copy()
         self.theta = np.ascontiguousarray(b.arm_theta, np.float64).reshape(-1).copy()
+        self.rest = np.zeros(int(self.off[-1]), np.int32)   # steps at rest per body (sleeping)
         self.m = Model()
         self.m.n_scenes = self.S
         self.m.body_offset = _ptr(self.off, C.c_int32)
@@ -160,11 +162,18 @@ class OracleSim:
             lib().ora_arm_pose(C.byref(self.m), _ptr(self.pose, _d), _ptr(self.theta, _d))
         self._mlp_keep = None
 
+    def set_sleep(self, speed: float, steps: int):
+        """Sleeping islands on (speed m/s > 0, steps >= 1) or off (speed 0)."""
+        self.m.sleep_speed = float(speed)
+        self.m.sleep_steps = int(steps)
+
     # ---------------------------------------------------------------- state
-    def set_state(self, pose, vel, theta=None, cache=None):
+    def set_state(self, pose, vel, theta=None, cache=None, rest=None):
         """Overwrite the state with (float32) arrays, widened exactly."""
         self.pose[:] = np.asarray(pose, np.float64).reshape(-1)
         self.vel[:] = np.asarray(vel, np.float64).reshape(-1)
+        if rest is not None:
+            self.rest[:] = np.asarray(rest, np.int32).reshape(-1)
         if theta is not None:
             self.theta[:] = np.asarray(theta, np.float64).reshape(-1)
         if cache is not None:
@@ -247,7 +256,8 @@ class OracleSim:
             act = np.ascontiguousarray(np.asarray(actions, np.float64).reshape(-1))
         mlp = C.byref(self.mlp) if warm == LEARNED else None
         rc = lib().ora_step(C.byref(self.m), _ptr(self.pose, _d), _ptr(self.vel, _d),
-                            _ptr(self.theta, _d), C.byref(self.cache) if use_cache else None,
+                            _ptr(self.theta, _d), _ptr(self.rest, C.c_int32),
+                            C.byref(self.cache) if use_cache else None,
                             _ptr(act, _d) if act is not None else None, dt, int(iters), float(tol),
                             int(warm), int(solver), mlp, C.byref(out) if out is not None else None,
                             s0, s1)

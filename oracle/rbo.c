@@ -29,6 +29,7 @@
 #define KEY_GROUND 0xFFFu
 #define BAND 1e-5       /* tie band for decisions on lengths (m) */
 #define BAND_DIM 1e-5   /* tie band for dimensionless decisions */
+#define BAND_V 1e-4     /* tie band for decisions on speeds (m/s) */
 #define SIN_PAR 1e-3    /* "parallel" threshold: sine of 1 mrad (approx.) */
 #define MAXCOL 256
 #define CLIP_ON 1e-4  /* clip vertices within this distance of a plane lie on it (m) */
@@ -939,6 +940,7 @@ typedef struct {
     double lam[3];
     double feat[16];
     int colour, matched;
+    int active;             /* 0: every dynamic body of the contact sleeps (not solved) */
 } Con;
 
 /* Orthonormal tangents from a unit normal (Duff et al. 2017, "Building an
@@ -1206,7 +1208,7 @@ static double start_objective(const Body *B, const Con *C, int nc, const V *vs) 
     double f = 0;
     for (int q = 0; q < nc; q++) {
         const Con *c = &C[q];
-        if (c->matched) continue;
+        if (c->matched || !c->active) continue;
         V va = add(vs[2 * c->a], cross(vs[2 * c->a + 1], c->ra));
         V vb = c->b >= 0 ? add(vs[2 * c->b], cross(vs[2 * c->b + 1], c->rb)) : mk(0, 0, 0);
         V v0 = sub(va, vb), v1 = vrel(B, c);
@@ -1228,7 +1230,20 @@ static void warm_apply(Body *B, Con *C, const int *order, int nc, int sel) {
     }
 }
 
-static void step_scene(const ora_model *m, double *pose, double *vel, double *theta,
+/* Bounding radius of a body about its centre: the lever arm that turns an
+ * angular speed into the largest surface speed. */
+static double bound_radius(const Body *b) {
+    if (b->shape == ORA_SPHERE) return b->prm[0];
+    if (b->shape == ORA_BOX) return sqrt(b->prm[0] * b->prm[0] + b->prm[1] * b->prm[1] + b->prm[2] * b->prm[2]);
+    return b->prm[0] + b->prm[1];
+}
+
+static int uf_find(int *par, int x) {
+    while (par[x] != x) { par[x] = par[par[x]]; x = par[x]; }
+    return x;
+}
+
+static void step_scene(const ora_model *m, double *pose, double *vel, double *theta, int32_t *rest,
                        ora_cache *cache, const double *actions, double dt, int iters,
                        double tol, int warm, int solver, const ora_mlp *mlp, ora_out *out, int s) {
     int b0 = m->body_offset[s], nb = m->body_offset[s + 1] - b0;
@@ -1302,11 +1317,57 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         }
     }
 
-    /* 7. setup; contacts per dynamic body first (a feature of new contacts) */
+    /* Sleeping (localized physics, Sec. 4.1): an island is a set of dynamic
+     * bodies joined by this step's contacts between two dynamic bodies.  It
+     * sleeps when every body in it has been at rest for sleep_steps steps
+     * and none of them touches a kinematic body (the arm: the robot is the
+     * only source of forces other than gravity).  A sleeping body keeps its
+     * pose, has zero velocity and counts as not dynamic for the solver: its
+     * contacts are neither coloured nor solved and carry their previous
+     * impulses into the cache. */
+    const int sleeping = m->sleep_speed > 0 && m->sleep_steps > 0 && rest != NULL;
+    uint8_t *asleep = calloc((size_t)(nb ? nb : 1), 1);
+    for (int q = 0; q < nc; q++) C[q].active = 1;
+    if (sleeping) {
+        int *par = malloc(sizeof(int) * (nb ? nb : 1));
+        uint8_t *wake = calloc((size_t)(nb ? nb : 1), 1);
+        for (int i = 0; i < nb; i++) par[i] = i;
+        for (int q = 0; q < nc; q++) {
+            int a = C[q].a, b = C[q].b;
+            if (b < 0 || B[a].motion != ORA_DYNAMIC || B[b].motion != ORA_DYNAMIC) continue;
+            int ra = uf_find(par, a), rb = uf_find(par, b);
+            if (ra != rb) par[ra < rb ? rb : ra] = ra < rb ? ra : rb;
+        }
+        for (int i = 0; i < nb; i++)
+            if (B[i].motion == ORA_DYNAMIC && rest[b0 + i] < m->sleep_steps) wake[uf_find(par, i)] = 1;
+        for (int q = 0; q < nc; q++) {
+            int a = C[q].a, b = C[q].b;
+            if (b < 0) continue;
+            if (B[a].motion == ORA_KINEMATIC && B[b].motion == ORA_DYNAMIC) wake[uf_find(par, b)] = 1;
+            if (B[b].motion == ORA_KINEMATIC && B[a].motion == ORA_DYNAMIC) wake[uf_find(par, a)] = 1;
+        }
+        for (int i = 0; i < nb; i++) {
+            if (B[i].motion != ORA_DYNAMIC || wake[uf_find(par, i)]) continue;
+            asleep[i] = 1;
+            B[i].v = mk(0, 0, 0);
+            B[i].w = mk(0, 0, 0);
+        }
+        for (int q = 0; q < nc; q++) {
+            int a = C[q].a, b = C[q].b;
+            int awake_a = B[a].motion == ORA_DYNAMIC && !asleep[a];
+            int awake_b = b >= 0 && B[b].motion == ORA_DYNAMIC && !asleep[b];
+            C[q].active = awake_a || awake_b;
+        }
+        free(wake);
+        free(par);
+    }
+#define AWAKE(i) ((i) >= 0 && B[i].motion == ORA_DYNAMIC && !asleep[i])
+
+    /* 7. setup; contacts per awake dynamic body first (a feature of new contacts) */
     int *ndyn = calloc((size_t)(nb ? nb : 1), sizeof(int));
     for (int q = 0; q < nc; q++) {
-        if (B[C[q].a].motion == ORA_DYNAMIC) ndyn[C[q].a]++;
-        if (C[q].b >= 0 && B[C[q].b].motion == ORA_DYNAMIC) ndyn[C[q].b]++;
+        if (AWAKE(C[q].a)) ndyn[C[q].a]++;
+        if (AWAKE(C[q].b)) ndyn[C[q].b]++;
     }
     for (int q = 0; q < nc; q++) {
         Con *c = &C[q];
@@ -1375,6 +1436,7 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
             double sc = gmag * dt * c->m[0];
             for (int r = 0; r < 3; r++) c->lam[r] = c->matched ? lp[r] : y[r] * sc;
         }
+        if (!c->active) { c->lam[0] = lp[0]; c->lam[1] = lp[1]; c->lam[2] = lp[2]; }
     }
 
     free(ndyn);
@@ -1384,11 +1446,12 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
     int ncol = 0;
     for (int q = 0; q < nc; q++) {
         Con *c = &C[q];
+        if (!c->active) { c->colour = -1; continue; }
         int ids[2] = {c->a, c->b};
         uint64_t mask[MAXCOL / 64] = {0};
         for (int t = 0; t < 2; t++) {
             int i = ids[t];
-            if (i < 0 || B[i].motion != ORA_DYNAMIC) continue;
+            if (!AWAKE(i)) continue;
             for (int w = 0; w < MAXCOL / 64; w++) mask[w] |= used[(size_t)i * (MAXCOL / 64) + w];
         }
         int col_ = -1;
@@ -1398,18 +1461,16 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         if (col_ + 1 > ncol) ncol = col_ + 1;
         for (int t = 0; t < 2; t++) {
             int i = ids[t];
-            if (i < 0 || B[i].motion != ORA_DYNAMIC) continue;
+            if (!AWAKE(i)) continue;
             used[(size_t)i * (MAXCOL / 64) + col_ / 64] |= 1ull << (col_ % 64);
             B[i].ncon++;
         }
     }
     free(used);
     int *order = malloc(sizeof(int) * (nc ? nc : 1));
-    {
-        int w = 0;
-        for (int k = 0; k < ncol; k++)
-            for (int q = 0; q < nc; q++) if (C[q].colour == k) order[w++] = q;
-    }
+    int nact = 0;
+    for (int k = 0; k < ncol; k++)
+        for (int q = 0; q < nc; q++) if (C[q].colour == k) order[nact++] = q;
 
     /* 8. initial impulses, 10. sweeps */
     V *vsave = malloc(sizeof(V) * 2 * (nb ? nb : 1));
@@ -1419,20 +1480,20 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
      * objective it is dropped (new contacts start from zero, the classic
      * warm start) and the step is flagged. */
     if (warm == ORA_LEARNED) {
-        warm_apply(B, C, order, nc, 0);
+        warm_apply(B, C, order, nact, 0);
         for (int i = 0; i < nb; i++) { vsave[2 * i] = B[i].v; vsave[2 * i + 1] = B[i].w; }
-        warm_apply(B, C, order, nc, 1);
+        warm_apply(B, C, order, nact, 1);
         if (start_objective(B, C, nc, vsave) > 0) {
             flags |= ORA_F_FELLBACK;
             for (int i = 0; i < nb; i++) { B[i].v = vsave[2 * i]; B[i].w = vsave[2 * i + 1]; }
             for (int q = 0; q < nc; q++)
-                if (!C[q].matched) C[q].lam[0] = C[q].lam[1] = C[q].lam[2] = 0;
+                if (!C[q].matched && C[q].active) C[q].lam[0] = C[q].lam[1] = C[q].lam[2] = 0;
         }
     } else {
-        warm_apply(B, C, order, nc, -1);
+        warm_apply(B, C, order, nact, -1);
     }
     double R = 0, gap = INFINITY;
-    int sweeps = solve(B, nb, C, order, nc, iters, tol, solver, &R, &gap);
+    int sweeps = solve(B, nb, C, order, nact, iters, tol, solver, &R, &gap);
     /* a step counts as solved only once its residual reached the tolerance */
     if (tol > 0 && R > tol) flags |= ORA_F_NOT_CONVERGED;
     free(vsave);
@@ -1441,6 +1502,20 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
     for (int i = 0; i < nb; i++) {
         Body *b = &B[i];
         if (b->motion != ORA_DYNAMIC) continue;
+        int gi0 = b0 + i;
+        if (asleep[i]) {             /* pose kept, velocity zero, counter kept */
+            for (int k = 0; k < 6; k++) vel[6 * gi0 + k] = 0.0;
+            continue;
+        }
+        if (sleeping) {              /* at rest: speed and surface speed at most sleep_speed */
+            double sp = sqrt(len2(b->v)), sw = sqrt(len2(b->w)) * bound_radius(b);
+            if (fabs(sp - m->sleep_speed) < BAND_V || fabs(sw - m->sleep_speed) < BAND_V) {
+                amb++;
+                tied[i] = 1;
+            }
+            int at_rest = sp <= m->sleep_speed && sw <= m->sleep_speed;
+            rest[gi0] = at_rest ? (rest[gi0] < (1 << 30) ? rest[gi0] + 1 : rest[gi0]) : 0;
+        }
         b->x = add(b->x, scl(b->v, dt));
         double wq[4] = {0, b->w.x, b->w.y, b->w.z}, dq[4];
         quat_mul(wq, b->q, dq);
@@ -1513,6 +1588,8 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         if (out->tied) memcpy(out->tied + b0, tied, (size_t)nb);
         if (out->tol_gap) out->tol_gap[s] = gap;
     }
+#undef AWAKE
+    free(asleep);
     free(tied);
     free(order);
     free(C);
@@ -1520,7 +1597,7 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
     free(B);
 }
 
-int ora_step(const ora_model *m, double *pose, double *vel, double *theta,
+int ora_step(const ora_model *m, double *pose, double *vel, double *theta, int32_t *rest,
              ora_cache *cache, const double *actions, double dt, int iters,
              double tol, int warm, int solver, const ora_mlp *mlp,
              ora_out *out, int s0, int s1) {
@@ -1528,7 +1605,7 @@ int ora_step(const ora_model *m, double *pose, double *vel, double *theta,
     if (m->arm && !theta) return -1;
     if (warm == ORA_LEARNED && !mlp) return -1;
     for (int s = s0; s < s1; s++)
-        step_scene(m, pose, vel, theta, cache, actions, dt, iters, tol, warm, solver, mlp, out, s);
+        step_scene(m, pose, vel, theta, rest, cache, actions, dt, iters, tol, warm, solver, mlp, out, s);
     return 0;
 }
 

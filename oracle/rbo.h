@@ -56,6 +56,8 @@ typedef struct ora_model {
     double rest_thresh;           /* m/s */
     double ground_friction;
     double ground_restitution;
+    double sleep_speed;           /* m/s; > 0 with sleep_steps > 0 and a rest array: sleeping on */
+    int sleep_steps;              /* steps at rest before an island may sleep */
 } ora_model;
 
 typedef struct ora_cache {        /* previous step's contacts, sorted by key */
@@ -83,7 +85,7 @@ typedef struct ora_out {          /* optional per-scene outputs (any pointer may
     double *c_point;              /* [S*max_contacts*3] */
     double *c_phi;                /* [S*max_contacts] signed separation (m) */
     double *c_lambda;             /* [S*max_contacts*3] impulses n, t1, t2 (N s) */
-    int32_t *c_colour;            /* [S*max_contacts] */
+    int32_t *c_colour;            /* [S*max_contacts], -1 for a contact of sleeping bodies */
     double *c_feat;               /* [S*max_contacts*16] warm-start features */
     int32_t *n_colours;           /* [S] */
     int32_t *sweeps;              /* [S] */
@@ -96,11 +98,13 @@ typedef struct ora_out {          /* optional per-scene outputs (any pointer may
 } ora_out;
 
 /* One step for scenes [s0, s1).  pose [N*7] (x, q w x y z), vel [N*6] (v, w),
- * theta [S*7] are read and overwritten.  cache may be NULL (then treated as
+ * theta [S*7] are read and overwritten.  rest [N] (may be NULL: no
+ * sleeping) counts the steps each dynamic body has ended at rest and is
+ * updated.  cache may be NULL (then treated as
  * empty and not written).  actions [S*7] joint velocities (rad/s) or NULL.
  * iters: sweep cap.  tol > 0 stops a scene's sweeps once residual <= tol.
  * Returns 0, or -1 on a bad argument. */
-int ora_step(const ora_model *m, double *pose, double *vel, double *theta,
+int ora_step(const ora_model *m, double *pose, double *vel, double *theta, int32_t *rest,
              ora_cache *cache, const double *actions, double dt, int iters,
              double tol, int warm, int solver, const ora_mlp *mlp,
              ora_out *out, int s0, int s1);
