@@ -26,7 +26,7 @@ F_NONFINITE, F_CAPACITY, F_NOT_CONVERGED, F_FELLBACK = 1, 2, 4, 8
 DEFAULTS = dict(margin=0.02, baumgarte=0.2, slop=0.005, rest_thresh=0.5,
                 ground_friction=0.5, ground_restitution=0.0,
                 gravity=(0.0, 0.0, -9.81), link_len=(0.10, 0.30, 0.10, 0.30, 0.10, 0.20, 0.10),
-                arm_radius=0.05)
+                arm_radius=0.05, motor_kp=0.3, motor_max=10.0)
 
 
 def build(force: bool = False) -> str:
@@ -50,7 +50,7 @@ class Model(C.Structure):
                 ("arm_base", _P(_d)), ("link_len", _d * 7), ("arm_radius", _d),
                 ("gravity", _d * 3), ("margin", _d), ("baumgarte", _d), ("slop", _d),
                 ("rest_thresh", _d), ("ground_friction", _d), ("ground_restitution", _d),
-                ("sleep_speed", _d), ("sleep_steps", C.c_int)]
+                ("sleep_speed", _d), ("sleep_steps", C.c_int), ("motor_kp", _d), ("motor_max", _d)]
 
 
 class Cache(C.Structure):
@@ -83,7 +83,7 @@ def lib():
     if _lib is None:
         path = build()
         L = C.CDLL(path)
-        L.ora_step.argtypes = [_P(Model), _P(_d), _P(_d), _P(_d), _P(C.c_int32), _P(Cache), _P(_d), _d, C.c_int,
+        L.ora_step.argtypes = [_P(Model), _P(_d), _P(_d), _P(_d), _P(C.c_int32), _P(_d), _P(Cache), _P(_d), _d, C.c_int,
                                _d, C.c_int, C.c_int, _P(Mlp), _P(Out), C.c_int, C.c_int]
         L.ora_step.restype = C.c_int
         L.ora_arm_pose.argtypes = [_P(Model), _P(_d), _P(_d)]
@@ -127,12 +127,17 @@ class OracleSim:
         self.mass = np.ascontiguousarray(b.mass, np.float64)
         self.friction = np.ascontiguousarray(b.friction, np.float64)
         self.restitution = np.ascontiguousarray(b.restitution, np.float64)
-        self.arm = bool(b.arm)
+        self.arm = int(b.arm)            # 0 none, 1 kinematic, 2 dynamic with joint motors
         self.arm_base = np.ascontiguousarray(b.arm_base, np.float64).reshape(-1)
         self.pose = np.ascontiguousarray(b.pose, np.float64).reshape(-1).copy()
         self.vel = np.ascontiguousarray(b.vel, np.float64).reshape(-1).copy()
         self.theta = np.ascontiguousarray(b.arm_theta, np.float64).reshape(-1).copy()
         self.rest = np.zeros(int(self.off[-1]), np.int32)   # steps at rest per body (sleeping)
+        # dynamic arm: per scene the joint rates, the motor targets and the
+        # motor impulses of the last step (7 each); targets start at theta
+        self.arm_state = np.zeros((self.S, 3, 7))
+        self.arm_state[:, 1] = self.theta.reshape(self.S, 7)
+        self.arm_state = self.arm_state.reshape(-1)
         self.m = Model()
         self.m.n_scenes = self.S
         self.m.body_offset = _ptr(self.off, C.c_int32)
@@ -142,7 +147,7 @@ class OracleSim:
         self.m.mass = _ptr(self.mass, _d)
         self.m.friction = _ptr(self.friction, _d)
         self.m.restitution = _ptr(self.restitution, _d)
-        self.m.arm = int(self.arm)
+        self.m.arm = self.arm
         self.m.arm_base = _ptr(self.arm_base, _d)
         for i in range(7):
             self.m.link_len[i] = c["link_len"][i]
@@ -150,7 +155,7 @@ class OracleSim:
         for i in range(3):
             self.m.gravity[i] = c["gravity"][i]
         for k in ("margin", "baumgarte", "slop", "rest_thresh", "ground_friction",
-                  "ground_restitution"):
+                  "ground_restitution", "motor_kp", "motor_max"):
             setattr(self.m, k, c[k])
         self.cache_cap = cache_cap
         self.c_count = np.zeros(self.S, np.int32)
@@ -162,16 +167,38 @@ class OracleSim:
             lib().ora_arm_pose(C.byref(self.m), _ptr(self.pose, _d), _ptr(self.theta, _d))
         self._mlp_keep = None
 
+    def set_motors(self, kp: float, max_impulse: float):
+        """Dynamic arm: motor position gain and largest impulse per step (N s)."""
+        self.m.motor_kp = float(kp)
+        self.m.motor_max = float(max_impulse)
+
+    @property
+    def qd(self):
+        """Dynamic arm: joint rates [S, 7] (a view)."""
+        return self.arm_state.reshape(self.S, 3, 7)[:, 0]
+
+    @property
+    def target(self):
+        """Dynamic arm: motor targets [S, 7] (a view)."""
+        return self.arm_state.reshape(self.S, 3, 7)[:, 1]
+
+    @property
+    def motor_impulse(self):
+        """Dynamic arm: motor impulses of the last step [S, 7] (a view)."""
+        return self.arm_state.reshape(self.S, 3, 7)[:, 2]
+
     def set_sleep(self, speed: float, steps: int):
         """Sleeping islands on (speed m/s > 0, steps >= 1) or off (speed 0)."""
         self.m.sleep_speed = float(speed)
         self.m.sleep_steps = int(steps)
 
     # ---------------------------------------------------------------- state
-    def set_state(self, pose, vel, theta=None, cache=None, rest=None):
+    def set_state(self, pose, vel, theta=None, cache=None, rest=None, arm_state=None):
         """Overwrite the state with (float32) arrays, widened exactly."""
         self.pose[:] = np.asarray(pose, np.float64).reshape(-1)
         self.vel[:] = np.asarray(vel, np.float64).reshape(-1)
+        if arm_state is not None:
+            self.arm_state[:] = np.asarray(arm_state, np.float64).reshape(-1)
         if rest is not None:
             self.rest[:] = np.asarray(rest, np.int32).reshape(-1)
         if theta is not None:
@@ -256,7 +283,7 @@ class OracleSim:
             act = np.ascontiguousarray(np.asarray(actions, np.float64).reshape(-1))
         mlp = C.byref(self.mlp) if warm == LEARNED else None
         rc = lib().ora_step(C.byref(self.m), _ptr(self.pose, _d), _ptr(self.vel, _d),
-                            _ptr(self.theta, _d), _ptr(self.rest, C.c_int32),
+                            _ptr(self.theta, _d), _ptr(self.rest, C.c_int32), _ptr(self.arm_state, _d),
                             C.byref(self.cache) if use_cache else None,
                             _ptr(act, _d) if act is not None else None, dt, int(iters), float(tol),
                             int(warm), int(solver), mlp, C.byref(out) if out is not None else None,

@@ -855,16 +855,22 @@ int ora_arm_pose(const ora_model *m, double *pose, const double *theta) {
 }
 
 /* ---------------------------------------------------------------- pairs */
-static int is_dyn(const Body *b) { return b->motion == ORA_DYNAMIC; }
+
+/* Links of the dynamic arm (arm 2) move with the arm's joint rates, not as
+ * free bodies: within a step they carry no velocity or mass of their own
+ * (the arm holds both), and they collide with everything but each other. */
+#define ORA_ARMLINK 3
+static int movable(const Body *b) { return b->motion == ORA_DYNAMIC || b->motion == ORA_ARMLINK; }
 
 /* Brute-force pair set: every i < j with at least one dynamic body whose
  * closed AABBs overlap on x, y and z, then (i, ground) for dynamic i whose
  * AABB reaches z <= 0; lexicographic order. */
-static int brute_pairs(const Body *B, int n, uint32_t *keys, int cap, int *amb, uint8_t *tied) {
+static int brute_pairs(const Body *B, int n, int arm0, uint32_t *keys, int cap, int *amb, uint8_t *tied) {
     int np = 0;
     for (int i = 0; i < n; i++) {
         for (int j = i + 1; j < n; j++) {
-            if (!is_dyn(&B[i]) && !is_dyn(&B[j])) continue;
+            if (!movable(&B[i]) && !movable(&B[j])) continue;
+            if (i >= arm0) continue;     /* two links of the dynamic arm: joined, not in contact */
             double sl = INFINITY;
             for (int a = 0; a < 3; a++) {
                 double s1 = comp(B[i].hi, a) - comp(B[j].lo, a);
@@ -880,7 +886,7 @@ static int brute_pairs(const Body *B, int n, uint32_t *keys, int cap, int *amb, 
                 np++;
             }
         }
-        if (is_dyn(&B[i])) {
+        if (movable(&B[i])) {
             if (fabs(B[i].lo.z) < BAND) {
                 (*amb)++;
                 if (tied) tied[i] = 1;
@@ -941,6 +947,8 @@ typedef struct {
     double feat[16];
     int colour, matched;
     int active;             /* 0: every dynamic body of the contact sleeps (not solved) */
+    int arm;                /* dynamic arm: +1 body a is a link, -1 body b is, 0 neither */
+    double g[3][7], w[3][7];/* arm side of rows n, t1, t2: joint-space row g and M^-1 g */
 } Con;
 
 /* Orthonormal tangents from a unit normal (Duff et al. 2017, "Building an
@@ -997,6 +1005,125 @@ static V vrel(const Body *B, const Con *c) {
     return sub(bvel(B, c->a, c->ra), bvel(B, c->b, c->rb));
 }
 
+
+/* ------------------------------------------------------------ dynamic arm
+ * The dynamic arm (arm 2) is one articulated body in reduced coordinates
+ * (Sec. 1: articulated robots; Sec. 5: joint motors with PD position
+ * control).  Its state is the joint angles q (theta) and rates qd: the link
+ * poses follow q by the forward kinematics and the link velocities follow
+ * qd through the link Jacobians, so the joints hold exactly.  M(q), the
+ * joint-space mass matrix, is the sum over links of Jv^T m Jv + Jw^T I Jw
+ * (column i of link j's Jacobians: a_i x (c_j - o_i) and a_i for i <= j);
+ * velocity-product (Coriolis) terms are left out, as the free bodies'
+ * gyroscopic term is.  Gravity adds dt M^-1 tau_g to qd.  A contact row d
+ * at point p on link j acts on the arm through g_i = d . (a_i x (p - o_i))
+ * (i <= j): the arm adds g . qd to the row's velocity and an impulse l
+ * changes qd by l M^-1 g.  Motor k is the row e_k: velocity qd_k, target
+ * Kp (target_k - q_k) / dt (the error wrapped into [-pi, pi]), effective
+ * mass 1 / (M^-1)_kk, impulse bounded by the motor's largest impulse per
+ * step.  Motors are solved after the contacts in every sweep, joints 0..6
+ * in order, and warm-start from their last impulses. */
+typedef struct {
+    double q[7], qd[7];
+    V o[7], ax[7], c[7];          /* joint origins and axes, link centres (world) */
+    double Mi[7][7];              /* M^-1 */
+    double lam[7], bias[7], lim;  /* motor rows */
+    int l0;                       /* local index of link 0 */
+} Arm;
+
+/* M^-1 of the arm at its current links: M from the link Jacobians, then
+ * its Cholesky factor, then the inverse column by column. */
+static void arm_mass(const ora_model *m, const Body *B, int g0, Arm *A) {
+    double M[7][7] = {{0}};
+    for (int j = 0; j < 7; j++) {
+        const Body *L = &B[A->l0 + j];
+        double mass = m->mass[g0 + A->l0 + j], Ip[3];
+        body_inertia(ORA_CAPSULE, L->prm, mass, Ip);
+        M3 Iw;   /* world inertia R diag(Ip) R^T */
+        for (int r = 0; r < 3; r++)
+            for (int q = 0; q < 3; q++) {
+                double sum = 0;
+                for (int k = 0; k < 3; k++) sum += L->R.m[r][k] * Ip[k] * L->R.m[q][k];
+                Iw.m[r][q] = sum;
+            }
+        V jv[7], jw[7];
+        for (int i = 0; i <= j; i++) { jw[i] = A->ax[i]; jv[i] = cross(A->ax[i], sub(A->c[j], A->o[i])); }
+        for (int i = 0; i <= j; i++)
+            for (int k = 0; k <= j; k++) M[i][k] += mass * dot(jv[i], jv[k]) + dot(jw[i], Mv(&Iw, jw[k]));
+    }
+    double Lc[7][7] = {{0}};
+    for (int i = 0; i < 7; i++)
+        for (int k = 0; k <= i; k++) {
+            double sum = M[i][k];
+            for (int t = 0; t < k; t++) sum -= Lc[i][t] * Lc[k][t];
+            Lc[i][k] = i == k ? sqrt(sum) : sum / Lc[k][k];
+        }
+    for (int col_ = 0; col_ < 7; col_++) {
+        double y[7], x[7];
+        for (int i = 0; i < 7; i++) {
+            double sum = i == col_ ? 1.0 : 0.0;
+            for (int t = 0; t < i; t++) sum -= Lc[i][t] * y[t];
+            y[i] = sum / Lc[i][i];
+        }
+        for (int i = 6; i >= 0; i--) {
+            double sum = y[i];
+            for (int t = i + 1; t < 7; t++) sum -= Lc[t][i] * x[t];
+            x[i] = sum / Lc[i][i];
+        }
+        for (int i = 0; i < 7; i++) A->Mi[i][col_] = x[i];
+    }
+}
+
+static void arm_add(Arm *A, const double *w, double l) {
+    for (int i = 0; i < 7; i++) A->qd[i] += l * w[i];
+}
+
+static double dot7(const double *a, const double *b) {
+    double s = 0;
+    for (int i = 0; i < 7; i++) s += a[i] * b[i];
+    return s;
+}
+
+/* Joint-space rows of contact c's directions on its arm link, and M^-1 of them. */
+static void arm_contact_rows(const Arm *A, Con *c) {
+    int j = (c->arm > 0 ? c->a : c->b) - A->l0;
+    V d[3] = {c->n, c->t1, c->t2};
+    for (int r = 0; r < 3; r++) {
+        for (int i = 0; i < 7; i++) c->g[r][i] = i <= j ? dot(d[r], cross(A->ax[i], sub(c->p, A->o[i]))) : 0.0;
+        for (int i = 0; i < 7; i++) c->w[r][i] = dot7(A->Mi[i], c->g[r]);
+    }
+}
+
+/* Velocity of row r of contact c, the arm's part included. */
+static double row_u(const Body *B, const Arm *A, const Con *c, int r) {
+    V d = r == 0 ? c->n : (r == 1 ? c->t1 : c->t2);
+    double u = dot(d, vrel(B, c));
+    if (c->arm) u += c->arm * dot7(c->g[r], A->qd);
+    return u;
+}
+
+/* Impulse l along row r of contact c (the bodies' part by apply). */
+static void row_apply(Body *B, Arm *A, const Con *c, int r, double l) {
+    V d = r == 0 ? c->n : (r == 1 ? c->t1 : c->t2);
+    apply(B, c, scl(d, l));
+    if (c->arm) arm_add(A, c->w[r], c->arm * l);
+}
+
+/* One Gauss-Seidel pass over the motor rows; returns max |dlambda| * k. */
+static double motor_sweep(Arm *A) {
+    double R = 0;
+    for (int k = 0; k < 7; k++) {
+        double kk = A->Mi[k][k];
+        double l = A->lam[k] + (A->bias[k] - A->qd[k]) / kk;
+        l = fmin(fmax(l, -A->lim), A->lim);
+        double dl = l - A->lam[k];
+        A->lam[k] = l;
+        for (int i = 0; i < 7; i++) A->qd[i] += dl * A->Mi[i][k];
+        R = fmax(R, fabs(dl) * kk);
+    }
+    return R;
+}
+
 /* Projection of the friction impulse onto the disk of radius mu*lambda_n. */
 static void proj_disk(double *l1, double *l2, double lim) {
     double L = sqrt(*l1 * *l1 + *l2 * *l2);
@@ -1014,23 +1141,25 @@ static void project(Con *c) {
 /* One projected Gauss-Seidel sweep in colour-major order.  Rows of one
  * contact: the normal row, then both friction rows from the velocities that
  * follow the normal update.  Returns the sweep residual max |dlambda|*k. */
-static double pgs_sweep(Body *B, Con *C, const int *order, int nc) {
+static double pgs_sweep(Body *B, Arm *A, Con *C, const int *order, int nc) {
     double R = 0;
     for (int q = 0; q < nc; q++) {
         Con *c = &C[order[q]];
-        V vr = vrel(B, c);
-        double u = dot(c->n, vr);
+        double u = row_u(B, A, c, 0);
         double ln = fmax(0.0, c->lam[0] + c->m[0] * (c->bias - u));
         double dn = ln - c->lam[0];
         c->lam[0] = ln;
-        apply(B, c, scl(c->n, dn));
-        vr = vrel(B, c);
-        double l1 = c->lam[1] - c->m[1] * dot(c->t1, vr);
-        double l2 = c->lam[2] - c->m[2] * dot(c->t2, vr);
+        row_apply(B, A, c, 0, dn);
+        double l1 = c->lam[1] - c->m[1] * row_u(B, A, c, 1);
+        double l2 = c->lam[2] - c->m[2] * row_u(B, A, c, 2);
         proj_disk(&l1, &l2, c->mu * ln);
         double d1 = l1 - c->lam[1], d2 = l2 - c->lam[2];
         c->lam[1] = l1; c->lam[2] = l2;
         apply(B, c, add(scl(c->t1, d1), scl(c->t2, d2)));
+        if (c->arm) {
+            arm_add(A, c->w[1], c->arm * d1);
+            arm_add(A, c->w[2], c->arm * d2);
+        }
         R = fmax(R, fabs(dn) * c->k[0]);
         R = fmax(R, fabs(d1) * c->k[1]);
         R = fmax(R, fabs(d2) * c->k[2]);
@@ -1178,17 +1307,19 @@ static int lookup(const ora_cache *cache, int s, uint32_t key) {
 
 static int finite3(V a) { return isfinite(a.x) && isfinite(a.y) && isfinite(a.z); }
 
+
 /* Sweeps until the residual reaches tol (tol > 0) or iters sweeps ran.
  * *gap receives the smallest |R - tol| / tol over the sweeps whose residual
  * was tested against the tolerance (infinity when none was): how close the
  * stopping decision came to going the other way. */
-static int solve(Body *B, int nb, Con *C, const int *order, int nc, int iters, double tol,
+static int solve(Body *B, int nb, Arm *A, Con *C, const int *order, int nc, int iters, double tol,
                  int solver, double *res, double *gap) {
     int sw = 0;
     double R = 0;
     *gap = INFINITY;
     for (int it = 0; it < iters; it++) {
-        R = solver == ORA_JACOBI ? jacobi_sweep(B, nb, C, order, nc) : pgs_sweep(B, C, order, nc);
+        R = solver == ORA_JACOBI ? jacobi_sweep(B, nb, C, order, nc) : pgs_sweep(B, A, C, order, nc);
+        if (A) R = fmax(R, motor_sweep(A));
         sw++;
         if (tol > 0) *gap = fmin(*gap, fabs(R - tol) / tol);
         if (tol > 0 && R <= tol) break;
@@ -1221,12 +1352,14 @@ static double start_objective(const Body *B, const Con *C, int nc, const V *vs) 
 
 /* Applies the start impulses in solver order (sel < 0), or only those of
  * the persisting (sel 0) or new (sel 1) contacts. */
-static void warm_apply(Body *B, Con *C, const int *order, int nc, int sel) {
+static void warm_apply(Body *B, Arm *A, Con *C, const int *order, int nc, int sel) {
     for (int q = 0; q < nc; q++) {
         Con *c = &C[order[q]];
         if (sel >= 0 && (c->matched ? 0 : 1) != sel) continue;
         project(c);
         apply(B, c, add(scl(c->n, c->lam[0]), add(scl(c->t1, c->lam[1]), scl(c->t2, c->lam[2]))));
+        if (c->arm)
+            for (int r = 0; r < 3; r++) arm_add(A, c->w[r], c->arm * c->lam[r]);
     }
 }
 
@@ -1244,7 +1377,7 @@ static int uf_find(int *par, int x) {
 }
 
 static void step_scene(const ora_model *m, double *pose, double *vel, double *theta, int32_t *rest,
-                       ora_cache *cache, const double *actions, double dt, int iters,
+                       double *arm_state, ora_cache *cache, const double *actions, double dt, int iters,
                        double tol, int warm, int solver, const ora_mlp *mlp, ora_out *out, int s) {
     int b0 = m->body_offset[s], nb = m->body_offset[s + 1] - b0;
     int flags = 0, amb = 0;
@@ -1255,9 +1388,9 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
     /* 1. arm: poses at theta_t, link velocities from the joint velocities */
     double thd[7] = {0};
     V ao[7], aax[7];
-    if (m->arm) {
+    if (m->arm && actions) for (int k = 0; k < 7; k++) thd[k] = actions[7 * s + k];
+    if (m->arm == 1) {
         double lp[7][7];
-        if (actions) for (int k = 0; k < 7; k++) thd[k] = actions[7 * s + k];
         arm_fk(m, m->arm_base + 3 * s, theta + 7 * s, lp, ao, aax);
         for (int k = 0; k < 7; k++) {
             int gi = b0 + nb - 7 + k;
@@ -1272,19 +1405,55 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
             vel[6 * gi + 3] = w.x; vel[6 * gi + 4] = w.y; vel[6 * gi + 5] = w.z;
         }
     }
+    double *ast = m->arm == 2 ? arm_state + 21 * s : NULL;   /* qd, target, motor impulses */
+    if (m->arm == 2) {
+        /* the motor targets move at the commanded rates; links at q_t */
+        for (int k = 0; k < 7; k++) ast[7 + k] += dt * thd[k];
+        double lp[7][7];
+        arm_fk(m, m->arm_base + 3 * s, theta + 7 * s, lp, ao, aax);
+        for (int k = 0; k < 7; k++) memcpy(pose + 7 * (b0 + nb - 7 + k), lp[k], 7 * sizeof(double));
+    }
     Body *B = malloc(sizeof(Body) * (nb ? nb : 1));
     load_bodies(m, pose, vel, s, B);
+    Arm AR;
+    if (m->arm == 2) {
+        AR.l0 = nb - 7;
+        for (int k = 0; k < 7; k++) {
+            Body *L = &B[AR.l0 + k];
+            L->motion = ORA_ARMLINK;
+            L->im = 0;
+            memset(&L->Iw, 0, sizeof(M3));
+            L->v = mk(0, 0, 0);
+            L->w = mk(0, 0, 0);
+            AR.q[k] = theta[7 * s + k];
+            AR.qd[k] = ast[k];
+            AR.o[k] = ao[k];
+            AR.ax[k] = aax[k];
+            AR.c[k] = L->x;
+        }
+        arm_mass(m, B, b0, &AR);
+    }
 
-    /* 2. velocity integration (no gyroscopic term) */
+    /* 2. velocity integration (no gyroscopic term; the arm: dt M^-1 tau_g) */
     for (int i = 0; i < nb; i++)
         if (B[i].motion == ORA_DYNAMIC) B[i].v = add(B[i].v, scl(g, dt));
+    if (m->arm == 2) {
+        double tg[7];
+        for (int i = 0; i < 7; i++) {
+            V t = mk(0, 0, 0);
+            for (int j = i; j < 7; j++) t = add(t, cross(sub(AR.c[j], AR.o[i]), scl(g, m->mass[b0 + AR.l0 + j])));
+            tg[i] = dot(AR.ax[i], t);
+        }
+        for (int i = 0; i < 7; i++) AR.qd[i] += dt * dot7(AR.Mi[i], tg);
+    }
 
     /* 3. AABBs; 4. pairs */
     for (int i = 0; i < nb; i++) body_aabb(&B[i], margin);
     int maxp = nb * (nb + 1) / 2 + 1;
     uint32_t *pk = malloc(sizeof(uint32_t) * maxp);
     uint8_t *tied = calloc((size_t)(nb ? nb : 1), 1);
-    int np = brute_pairs(B, nb, pk, maxp, &amb, tied);
+    const int arm0 = m->arm == 2 ? nb - 7 : nb;   /* first link of the dynamic arm */
+    int np = brute_pairs(B, nb, arm0, pk, maxp, &amb, tied);
 
     /* 5. narrowphase in canonical pair order; 6. contact list */
     int capc = 4 * np + 1;
@@ -1343,8 +1512,10 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         for (int q = 0; q < nc; q++) {
             int a = C[q].a, b = C[q].b;
             if (b < 0) continue;
-            if (B[a].motion == ORA_KINEMATIC && B[b].motion == ORA_DYNAMIC) wake[uf_find(par, b)] = 1;
-            if (B[b].motion == ORA_KINEMATIC && B[a].motion == ORA_DYNAMIC) wake[uf_find(par, a)] = 1;
+            int ka = B[a].motion == ORA_KINEMATIC || B[a].motion == ORA_ARMLINK;
+            int kb = B[b].motion == ORA_KINEMATIC || B[b].motion == ORA_ARMLINK;
+            if (ka && B[b].motion == ORA_DYNAMIC) wake[uf_find(par, b)] = 1;
+            if (kb && B[a].motion == ORA_DYNAMIC) wake[uf_find(par, a)] = 1;
         }
         for (int i = 0; i < nb; i++) {
             if (B[i].motion != ORA_DYNAMIC || wake[uf_find(par, i)]) continue;
@@ -1356,7 +1527,8 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
             int a = C[q].a, b = C[q].b;
             int awake_a = B[a].motion == ORA_DYNAMIC && !asleep[a];
             int awake_b = b >= 0 && B[b].motion == ORA_DYNAMIC && !asleep[b];
-            C[q].active = awake_a || awake_b;
+            int on_arm = B[a].motion == ORA_ARMLINK || (b >= 0 && B[b].motion == ORA_ARMLINK);
+            C[q].active = awake_a || awake_b || on_arm;
         }
         free(wake);
         free(par);
@@ -1384,11 +1556,18 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
             tied[c->a] = 1;
             if (c->b >= 0) tied[c->b] = 1;
         }
+        c->arm = m->arm == 2 ? (c->a >= arm0 ? 1 : (c->b >= arm0 ? -1 : 0)) : 0;
+        if (c->arm) arm_contact_rows(&AR, c);
         c->k[0] = row_k(B, c, c->n);
         c->k[1] = row_k(B, c, c->t1);
         c->k[2] = row_k(B, c, c->t2);
+        if (c->arm)
+            for (int r = 0; r < 3; r++) c->k[r] += dot7(c->g[r], c->w[r]);
         for (int r = 0; r < 3; r++) c->m[r] = 1.0 / c->k[r];
         V vr = vrel(B, c);
+        if (c->arm)   /* the arm link's point velocity, in the contact frame */
+            vr = add(vr, add(scl(c->n, c->arm * dot7(c->g[0], AR.qd)),
+                             add(scl(c->t1, c->arm * dot7(c->g[1], AR.qd)), scl(c->t2, c->arm * dot7(c->g[2], AR.qd)))));
         double u0 = dot(c->n, vr);
         if (c->phi > 0) c->bias = -c->phi / dt;
         else c->bias = m->baumgarte / dt * fmax(0.0, -c->phi - m->slop);
@@ -1441,17 +1620,19 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
 
     free(ndyn);
 
-    /* 9. colouring: first fit in canonical order; only dynamic bodies conflict */
-    uint64_t *used = calloc((size_t)(nb ? nb : 1) * (MAXCOL / 64), sizeof(uint64_t));
+    /* 9. colouring: first fit in canonical order; only dynamic bodies
+     * conflict, and the dynamic arm as one body (slot nb: its contacts all
+     * move the same joint rates) */
+    uint64_t *used = calloc((size_t)(nb + 1) * (MAXCOL / 64), sizeof(uint64_t));
     int ncol = 0;
     for (int q = 0; q < nc; q++) {
         Con *c = &C[q];
         if (!c->active) { c->colour = -1; continue; }
-        int ids[2] = {c->a, c->b};
+        int ids[3] = {AWAKE(c->a) ? c->a : -1, AWAKE(c->b) ? c->b : -1, c->arm ? nb : -1};
         uint64_t mask[MAXCOL / 64] = {0};
-        for (int t = 0; t < 2; t++) {
+        for (int t = 0; t < 3; t++) {
             int i = ids[t];
-            if (!AWAKE(i)) continue;
+            if (i < 0) continue;
             for (int w = 0; w < MAXCOL / 64; w++) mask[w] |= used[(size_t)i * (MAXCOL / 64) + w];
         }
         int col_ = -1;
@@ -1459,11 +1640,11 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         if (col_ < 0) { flags |= ORA_F_CAPACITY; col_ = MAXCOL - 1; }
         c->colour = col_;
         if (col_ + 1 > ncol) ncol = col_ + 1;
-        for (int t = 0; t < 2; t++) {
+        for (int t = 0; t < 3; t++) {
             int i = ids[t];
-            if (!AWAKE(i)) continue;
+            if (i < 0) continue;
             used[(size_t)i * (MAXCOL / 64) + col_ / 64] |= 1ull << (col_ % 64);
-            B[i].ncon++;
+            if (i < nb) B[i].ncon++;
         }
     }
     free(used);
@@ -1479,10 +1660,11 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
      * the network's part before any sweep: if it raises the solver's
      * objective it is dropped (new contacts start from zero, the classic
      * warm start) and the step is flagged. */
+    Arm *AP = m->arm == 2 ? &AR : NULL;
     if (warm == ORA_LEARNED) {
-        warm_apply(B, C, order, nact, 0);
+        warm_apply(B, AP, C, order, nact, 0);
         for (int i = 0; i < nb; i++) { vsave[2 * i] = B[i].v; vsave[2 * i + 1] = B[i].w; }
-        warm_apply(B, C, order, nact, 1);
+        warm_apply(B, AP, C, order, nact, 1);
         if (start_objective(B, C, nc, vsave) > 0) {
             flags |= ORA_F_FELLBACK;
             for (int i = 0; i < nb; i++) { B[i].v = vsave[2 * i]; B[i].w = vsave[2 * i + 1]; }
@@ -1490,10 +1672,20 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
                 if (!C[q].matched && C[q].active) C[q].lam[0] = C[q].lam[1] = C[q].lam[2] = 0;
         }
     } else {
-        warm_apply(B, C, order, nact, -1);
+        warm_apply(B, AP, C, order, nact, -1);
+    }
+    if (AP) {   /* motor rows: targets, bound, warm start from the last impulses */
+        AR.lim = m->motor_max;
+        for (int k = 0; k < 7; k++) {
+            double err = remainder(ast[7 + k] - AR.q[k], 2.0 * M_PI);
+            if (fabs(fabs(err) - M_PI) < BAND_DIM) { amb++; tied[AR.l0 + k] = 1; }
+            AR.bias[k] = m->motor_kp * err / dt;
+            AR.lam[k] = warm == ORA_COLD ? 0.0 : fmin(fmax(ast[14 + k], -AR.lim), AR.lim);
+            for (int i = 0; i < 7; i++) AR.qd[i] += AR.lam[k] * AR.Mi[i][k];
+        }
     }
     double R = 0, gap = INFINITY;
-    int sweeps = solve(B, nb, C, order, nact, iters, tol, solver, &R, &gap);
+    int sweeps = solve(B, nb, AP, C, order, nact, iters, tol, solver, &R, &gap);
     /* a step counts as solved only once its residual reached the tolerance */
     if (tol > 0 && R > tol) flags |= ORA_F_NOT_CONVERGED;
     free(vsave);
@@ -1530,19 +1722,40 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         vel[6 * gi + 3] = b->w.x; vel[6 * gi + 4] = b->w.y; vel[6 * gi + 5] = b->w.z;
         if (!finite3(b->x) || !finite3(b->v) || !finite3(b->w)) flags |= ORA_F_NONFINITE;
     }
-    if (m->arm) {
+    if (m->arm == 1) {
         for (int k = 0; k < 7; k++) theta[7 * s + k] += dt * thd[k];
         double lp[7][7];
         arm_fk(m, m->arm_base + 3 * s, theta + 7 * s, lp, ao, aax);
         for (int k = 0; k < 7; k++) memcpy(pose + 7 * (b0 + nb - 7 + k), lp[k], 7 * sizeof(double));
+    } else if (m->arm == 2) {
+        /* joint angles advance by their rates; links follow; rates, motor impulses out */
+        for (int k = 0; k < 7; k++) {
+            theta[7 * s + k] += dt * AR.qd[k];
+            ast[k] = AR.qd[k];
+            ast[14 + k] = AR.lam[k];
+            if (!isfinite(AR.qd[k])) flags |= ORA_F_NONFINITE;
+        }
+        double lp[7][7];
+        arm_fk(m, m->arm_base + 3 * s, theta + 7 * s, lp, ao, aax);
+        for (int k = 0; k < 7; k++) {
+            int gi = b0 + nb - 7 + k;
+            memcpy(pose + 7 * gi, lp[k], 7 * sizeof(double));
+            V c = mk(lp[k][0], lp[k][1], lp[k][2]), v = mk(0, 0, 0), w = mk(0, 0, 0);
+            for (int j = 0; j <= k; j++) {
+                w = add(w, scl(aax[j], AR.qd[j]));
+                v = add(v, scl(cross(aax[j], sub(c, ao[j])), AR.qd[j]));
+            }
+            vel[6 * gi] = v.x; vel[6 * gi + 1] = v.y; vel[6 * gi + 2] = v.z;
+            vel[6 * gi + 3] = w.x; vel[6 * gi + 4] = w.y; vel[6 * gi + 5] = w.z;
+        }
     }
 
     /* 12. outputs: arm contact force, cache, contacts, stats */
     double force = 0;
-    int arm0 = m->arm ? nb - 7 : nb;
+    int arml = m->arm ? nb - 7 : nb;     /* first arm link (either arm) */
     for (int q = 0; q < nc; q++) {
         Con *c = &C[q];
-        if (c->a >= arm0 || (c->b >= arm0)) {
+        if (c->a >= arml || (c->b >= arml)) {
             V P = add(scl(c->n, c->lam[0]), add(scl(c->t1, c->lam[1]), scl(c->t2, c->lam[2])));
             force += sqrt(len2(P)) / dt;
         }
@@ -1598,14 +1811,16 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
 }
 
 int ora_step(const ora_model *m, double *pose, double *vel, double *theta, int32_t *rest,
-             ora_cache *cache, const double *actions, double dt, int iters,
+             double *arm_state, ora_cache *cache, const double *actions, double dt, int iters,
              double tol, int warm, int solver, const ora_mlp *mlp,
              ora_out *out, int s0, int s1) {
     if (!m || !pose || !vel || dt <= 0 || iters < 0 || s0 < 0 || s1 > m->n_scenes || s0 > s1) return -1;
     if (m->arm && !theta) return -1;
+    if (m->arm < 0 || m->arm > 2) return -1;
+    if (m->arm == 2 && (!arm_state || solver != ORA_PGS || warm == ORA_LEARNED)) return -1;
     if (warm == ORA_LEARNED && !mlp) return -1;
     for (int s = s0; s < s1; s++)
-        step_scene(m, pose, vel, theta, rest, cache, actions, dt, iters, tol, warm, solver, mlp, out, s);
+        step_scene(m, pose, vel, theta, rest, arm_state, cache, actions, dt, iters, tol, warm, solver, mlp, out, s);
     return 0;
 }
 
@@ -1616,7 +1831,7 @@ int ora_pairs(const ora_model *m, const double *pose, int s, uint32_t *keys, int
     load_bodies(m, pose, vel, s, B);
     for (int i = 0; i < nb; i++) body_aabb(&B[i], m->margin);
     int amb = 0;
-    int n = brute_pairs(B, nb, keys, cap, &amb, NULL);
+    int n = brute_pairs(B, nb, m->arm == 2 ? nb - 7 : nb, keys, cap, &amb, NULL);
     free(vel);
     free(B);
     return n;

@@ -45,7 +45,10 @@ typedef struct ora_model {
     const double *mass;           /* [N] kg (ignored unless dynamic) */
     const double *friction;       /* [N] */
     const double *restitution;    /* [N] */
-    int arm;                      /* 1: the last 7 bodies of every scene are the arm links */
+    int arm;                      /* 1: the last 7 bodies of every scene are the arm links,
+                                     kinematic (poses follow theta); 2: the arm is one
+                                     articulated body in reduced coordinates (theta and its
+                                     rates) driven by PD position motors */
     const double *arm_base;       /* [S*3] */
     double link_len[7];
     double arm_radius;
@@ -58,6 +61,9 @@ typedef struct ora_model {
     double ground_restitution;
     double sleep_speed;           /* m/s; > 0 with sleep_steps > 0 and a rest array: sleeping on */
     int sleep_steps;              /* steps at rest before an island may sleep */
+    double motor_kp;              /* arm 2: position gain of the joint motors (fraction of the
+                                     angle error closed per step) */
+    double motor_max;             /* arm 2: largest motor impulse per step (N s) */
 } ora_model;
 
 typedef struct ora_cache {        /* previous step's contacts, sorted by key */
@@ -100,17 +106,22 @@ typedef struct ora_out {          /* optional per-scene outputs (any pointer may
 /* One step for scenes [s0, s1).  pose [N*7] (x, q w x y z), vel [N*6] (v, w),
  * theta [S*7] are read and overwritten.  rest [N] (may be NULL: no
  * sleeping) counts the steps each dynamic body has ended at rest and is
- * updated.  cache may be NULL (then treated as
- * empty and not written).  actions [S*7] joint velocities (rad/s) or NULL.
+ * updated.  arm_state [S*21] (arm 2 only, PGS without the learned start;
+ * may be NULL otherwise): per scene the joint rates (rad/s), the motor
+ * targets (rad) and the motor impulses of the last step (N m s, the warm
+ * start), 7 each, read and overwritten.  cache may be NULL (then treated as
+ * empty and not written).  actions [S*7] joint velocities (rad/s; arm 2:
+ * velocities of the motor targets) or NULL.
  * iters: sweep cap.  tol > 0 stops a scene's sweeps once residual <= tol.
  * Returns 0, or -1 on a bad argument. */
 int ora_step(const ora_model *m, double *pose, double *vel, double *theta, int32_t *rest,
-             ora_cache *cache, const double *actions, double dt, int iters,
+             double *arm_state, ora_cache *cache, const double *actions, double dt, int iters,
              double tol, int warm, int solver, const ora_mlp *mlp,
              ora_out *out, int s0, int s1);
 
 /* Arm forward kinematics for all scenes: writes the arm links' pose. */
 int ora_arm_pose(const ora_model *m, double *pose, const double *theta);
+
 
 /* Narrowphase of one body pair, for unit tests.  Shapes as in the model;
  * poses [7].  ground: b is the plane z = 0 (shape_b, param_b, pose_b unused).

@@ -37,6 +37,8 @@ ARM_LINKS = 7
 ARM_LINK_LENGTH = (0.10, 0.30, 0.10, 0.30, 0.10, 0.20, 0.10)
 ARM_RADIUS = 0.05
 ARM_BASE = (0.0, 0.0, 0.8)
+# link masses of the dynamic arm (kg), heavier near the base
+ARM_LINK_MASS = (2.0, 2.0, 1.5, 1.5, 1.0, 1.0, 0.5)
 
 _M64 = (1 << 64) - 1
 _GOLDEN = 0x9E3779B97F4A7C15
@@ -229,10 +231,12 @@ def drop_scene(seed: int, n_spheres: int = 32, n_boxes: int = 32, size=(0.05, 0.
 
 def clutter_scene(seed: int, n_static: int = 20, n_each: int = 36, size=(0.03, 0.30),
                   cap_radius=(0.03, 0.15), mass=(0.05, 3.0), friction=(0.3, 0.8),
-                  arm: bool = True, n_dynamic: int | None = None) -> Scene:
+                  arm: int = True, n_dynamic: int | None = None) -> Scene:
     """Rearrangement clutter: static boxes on a 4 m x 4 m floor (a quarter of
     them floating shelves), dynamic spheres/boxes/capsules dropped above, and
-    a kinematic 7-link capsule arm based at (0, 0, 0.8) m.  With n_dynamic
+    a 7-link capsule arm based at (0, 0, 0.8) m: kinematic (arm True or 1) or
+    dynamic links of ARM_LINK_MASS joined by motorised joints (arm 2), the
+    same scene otherwise.  With n_dynamic
     given, that many dynamic bodies (a third of each shape, the remainder to
     spheres then boxes) dropped from a region scaled by (n_dynamic/108)^(1/3)
     (x, y within +-2 m times the scale, z from 0.2 m up to 4 m times it)."""
@@ -287,12 +291,13 @@ def clutter_scene(seed: int, n_static: int = 20, n_each: int = 36, size=(0.03, 0
         placed.append((p, R))
         sc.add(int(k), DYNAMIC, param, m, mu, 0.0, p, _random_quat(st))
     if arm:
-        sc.arm = True
+        dyn = int(arm) == 2
+        sc.arm = 2 if dyn else True
         sc.arm_theta0 = st.uniform(-0.5, 0.5, ARM_LINKS)
-        for L in ARM_LINK_LENGTH:
+        for L, lm in zip(ARM_LINK_LENGTH, ARM_LINK_MASS):
             # pose is a placeholder: arm link poses follow from joint angles
-            sc.add(CAPSULE, KINEMATIC, [ARM_RADIUS, 0.5 * L, 0.0], 0.0, 0.5, 0.0,
-                   ARM_BASE, (1.0, 0.0, 0.0, 0.0))
+            sc.add(CAPSULE, DYNAMIC if dyn else KINEMATIC, [ARM_RADIUS, 0.5 * L, 0.0], lm if dyn else 0.0,
+                   0.5, 0.0, ARM_BASE, (1.0, 0.0, 0.0, 0.0))
     return sc
 
 
@@ -328,7 +333,7 @@ class Batch:
     restitution: np.ndarray   # float32 [N]
     pose: np.ndarray          # float32 [N,7]  x y z qw qx qy qz
     vel: np.ndarray           # float32 [N,6]  v, omega (world)
-    arm: bool
+    arm: int                  # 0 none, 1 (True) kinematic, 2 dynamic with joint motors
     arm_base: np.ndarray      # float32 [S,3]
     arm_theta: np.ndarray     # float32 [S,7]
 

@@ -42,12 +42,13 @@ def custom_batch(scenes_bodies, arm=False, theta=None):
                    b.get("mass", 1.0), b.get("mu", 0.5), b.get("e", 0.0), b["pos"],
                    b.get("quat", (1.0, 0.0, 0.0, 0.0)))
             vels.append(np.asarray(b.get("vel", np.zeros(6)), np.float64))
-        if arm:
-            sc.arm = True
+        if arm:  # True / 1: kinematic links; 2: dynamic links with joint motors
+            dyn = int(arm) == 2
+            sc.arm = 2 if dyn else True
             sc.arm_theta0 = np.zeros(7) if theta is None else np.asarray(theta, np.float64)
-            for L in S.ARM_LINK_LENGTH:
-                sc.add(S.CAPSULE, S.KINEMATIC, [S.ARM_RADIUS, 0.5 * L, 0.0], 0.0, 0.5, 0.0,
-                       S.ARM_BASE, (1.0, 0.0, 0.0, 0.0))
+            for L, lm in zip(S.ARM_LINK_LENGTH, S.ARM_LINK_MASS):
+                sc.add(S.CAPSULE, S.DYNAMIC if dyn else S.KINEMATIC, [S.ARM_RADIUS, 0.5 * L, 0.0],
+                       lm if dyn else 0.0, 0.5, 0.0, S.ARM_BASE, (1.0, 0.0, 0.0, 0.0))
                 vels.append(np.zeros(6))
         scs.append(sc)
     b = S.pack(scs)
