@@ -55,7 +55,7 @@ B_DYN = 144.0      # per dynamic body per step: state read+write 104 B + constan
 B_STATIC = 52.0    # per static or kinematic body per step: pose + shape + material
 B_CONTACT = 40.0   # per contact per step: cache read 20 B + write 20 B
 B_SWEEP = 240.0    # per contact per sweep if the solver state were streamed from memory
-MODES = ("cold", "prev", "learned")
+MODES = ("cold", "prev", "learned", "prev_sleep")
 
 
 def parse():
@@ -68,8 +68,11 @@ def parse():
     ap.add_argument("--scenes", type=int, default=None)
     ap.add_argument("--tol", type=float, default=None, help="residual tolerance (m/s); 1e-4, scale 1e-5")
     ap.add_argument("--cap", type=int, default=None, help="sweep cap at the tolerance")
-    ap.add_argument("--headline", default=None, choices=MODES, help="prev; scale: learned")
-    ap.add_argument("--modes", default=",".join(MODES))
+    ap.add_argument("--headline", default=None, help="prev; scale: learned")
+    ap.add_argument("--modes", default=",".join(MODES),
+                    help="warm starts to time; a _sleep suffix turns sleeping islands on for that mode")
+    ap.add_argument("--sleep-speed", type=float, default=0.02, help="sleeping islands: at-rest speed (m/s)")
+    ap.add_argument("--sleep-steps", type=int, default=30, help="sleeping islands: steps at rest before sleep")
     ap.add_argument("--no-replay", action="store_true", help="skip the statistics replay (profiling runs)")
     ap.add_argument("--threads", type=int, default=64)
     ap.add_argument("--max-contacts", type=int, default=None)
@@ -321,7 +324,8 @@ def main():
     if a.cpu_baseline and a.workload != "uneven":
         cpu_batch = batch_fn(a.cpu_scenes_per_thread * host_threads())
     K, W, T0 = a.steps, a.warmup, a.settle
-    acts_np = (np.stack([S.arm_actions(1, n_scenes, t) for t in range(T0 + W + K)]) if arm else None)
+    Wmax = max(W, 2 * a.sleep_steps) if any(m.endswith("_sleep") for m in modes) else W
+    acts_np = (np.stack([S.arm_actions(1, n_scenes, t) for t in range(T0 + Wmax + K)]) if arm else None)
 
     import torch
 
@@ -338,10 +342,12 @@ def main():
     persistent = a.workload in ("uneven", "scale") and a.launch != "plain"
     if persistent:
         sim.set_persistent(True)
-        tuned = sim.autotune(steps=3, dt=DT, iters=20)
-        progress(f"autotuned: wave_max_bodies {tuned}")
+        mask = sim.autotune(steps=3, dt=DT, iters=20)
+        edges = ["1-16", "17-32", "33-64", "65-128", "129-256", "257-512", "513-1024", "1025-2046"]
+        tuned = {e: ("wave" if (mask >> k) & 1 else "workgroup") for k, e in enumerate(edges)}
+        progress(f"autotuned routing: {tuned}")
     if a.workload == "uneven":
-        masks, index = reset_schedule(n_scenes, T0 + W + K, a.pool)
+        masks, index = reset_schedule(n_scenes, T0 + Wmax + K, a.pool)
         resets = torch.as_tensor(masks, device=dev)
         reset_index = torch.as_tensor(index, device=dev)
         pool_pose = torch.as_tensor(np.ascontiguousarray(pool[0].transpose(0, 2, 1)), device=dev)
@@ -368,16 +374,23 @@ def main():
 
     results = {}
     for name in modes:
-        mode = {"cold": L.COLD, "prev": L.PREV, "learned": L.LEARNED}[name]
+        sleep = name.endswith("_sleep")
+        mode = {"cold": L.COLD, "prev": L.PREV, "learned": L.LEARNED}[name[:-6] if sleep else name]
         sim.load_state(settled)
+        sim.set_sleep(0.0, 0)
         sim.set_solver(L.PGS, mode, a.tol)
-        for t in range(W):
+        # sleeping: the rest counters start at zero after the settling, so the
+        # untimed warm-up lasts long enough for islands to fall asleep
+        Wm = max(W, 2 * a.sleep_steps) if sleep else W
+        if sleep:
+            sim.set_sleep(a.sleep_speed, a.sleep_steps)
+        for t in range(Wm):
             one(T0 + t, cap)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(sim.stream)
         for t in range(K):
-            one(T0 + W + t, cap)
+            one(T0 + Wm + t, cap)
         ev1.record(sim.stream)
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1)
@@ -386,12 +399,12 @@ def main():
             # replay of the same W + K steps from the same state: bit-identical
             # to the timed steps; statistics of the K timed ones
             sim.load_state(settled)
-            for t in range(W):
+            for t in range(Wm):
                 one(T0 + t, cap)
             rec = {k: torch.zeros((K, n_scenes), dtype=v.dtype, device=dev)
                    for k, v in sim.stats.items() if k in ("sweeps", "residual", "flags", "contacts", "pairs", "colours")}
             for t in range(K):
-                one(T0 + W + t, cap)
+                one(T0 + Wm + t, cap)
                 for k in rec:
                     rec[k][t].copy_(sim.stats[k])
             torch.cuda.synchronize()
@@ -399,8 +412,11 @@ def main():
             r.update(summarise(rec["sweeps"], rec["residual"], rec["flags"], rec["contacts"], a.tol))
             r["pairs_per_scene"] = float(rec["pairs"].mean())
             r["colours_per_scene"] = float(rec["colours"].mean())
+        if sleep:
+            r["sleep"] = dict(speed_m_per_s=a.sleep_speed, steps=a.sleep_steps, untimed_warmup=Wm)
         results[name] = r
         progress(f"{name}: {r['ms_per_step']:.3f} ms per step")
+    sim.set_sleep(0.0, 0)
     sim.close()
     del sim
     torch.cuda.synchronize()
@@ -439,7 +455,7 @@ def main():
             "threads_per_scene": a.threads if not persistent else "autotuned: 64 (one wave) or 256",
             "max_contacts_per_scene": max_contacts, "max_pairs_per_scene": max_pairs,
             **({"launch": "persistent, HIP graph" if persistent else "one workgroup per scene",
-                "wave_max_bodies": tuned,
+                "routing_by_body_count": tuned,
                 "resets": f"each scene after U[100, 300] steps, from a pool of {a.pool} fresh states per scene"}
                if a.workload == "uneven" else {}),
         },

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 2
+#define SIM_ABI_VERSION 4
 
 enum { SIM_OK = 0, SIM_EINVAL = -1, SIM_EDEVICE = -2, SIM_EWORKSPACE = -3, SIM_EABI = -4, SIM_ECAPACITY = -5 };
 enum { SIM_SPHERE = 0, SIM_BOX = 1, SIM_CAPSULE = 2 };
@@ -66,7 +66,18 @@ typedef struct sim_batch_desc {
     const float *h_pose;         /* [N*7] x y z (m), quaternion w x y z (body to world) */
     const float *h_vel;          /* [N*6] linear (m/s), angular (rad/s, world frame) */
     int arm;                     /* 1: the last 7 bodies of every scene are the arm links
-                                    (kinematic capsules); their poses follow the joint angles */
+                                    (kinematic capsules); their poses follow the joint angles.
+                                    2: the same links as dynamic capsules (h_mass their masses)
+                                    of one articulated body in reduced coordinates (Sec. 1:
+                                    articulated robots; Sec. 5: joint motors under PD position
+                                    control): the state is the joint angles and rates, link
+                                    poses and velocities follow them, contacts on the links act
+                                    on the joint rates through the link Jacobians, and motor k
+                                    drives rate k towards Kp (target_k - theta_k) / dt with at
+                                    most the motor impulse bound per step (sim_set_motors;
+                                    Kp 0.3 and 10 N s by default).  Needs the PGS solver
+                                    without the learned warm start.  Initial link poses follow
+                                    h_arm_theta, at rest, motor targets at h_arm_theta. */
     const float *h_arm_base;     /* [S*3] arm base position (m), or NULL when arm = 0 */
     const float *h_arm_theta;    /* [S*7] initial joint angles (rad), or NULL when arm = 0 */
     float link_len[7];           /* arm link lengths (m) */
@@ -103,7 +114,11 @@ typedef struct sim_state_view {
     long n_bodies;        /* N */
     float *pose;          /* [7][N]: x, y, z, qw, qx, qy, qz */
     float *vel;           /* [6][N]: vx, vy, vz, wx, wy, wz */
+    int32_t *rest;        /* [N] steps each dynamic body has ended at rest (sleeping islands) */
     float *theta;         /* [S][7] arm joint angles, or NULL */
+    float *arm_state;     /* articulated arm only (else NULL): [S][21] per scene the joint rates
+                             (rad/s), the motor targets (rad) and the last step's motor impulses
+                             (N m s, the motors' warm start), 7 each */
     int cache_cap;        /* per-scene contact capacity (= max_contacts) */
     int32_t *cache_count; /* [S] contacts stored for the next step's warm start */
     uint32_t *cache_key;  /* [S][cache_cap] sorted contact keys */
@@ -124,7 +139,7 @@ typedef struct sim_contact_view {
     const float *point;       /* [3][S*max_contacts] */
     const float *phi;         /* [S*max_contacts] signed separation (m) */
     const float *lambda;      /* [3][S*max_contacts] normal, tangent-1, tangent-2 impulses (N s) */
-    const int32_t *colour;    /* [S*max_contacts] */
+    const int32_t *colour;    /* [S*max_contacts]; -1 for a contact of sleeping bodies */
     const float *features;    /* [16][S*max_contacts] warm-start features */
     const int32_t *n_pairs;   /* [S] */
     const uint32_t *pair_key; /* [S*max_pairs] */
@@ -160,7 +175,9 @@ int sim_create(const sim_batch_desc *desc, void *d_workspace, size_t workspace_b
 
 /* One transition (s_t, a_t) -> s_{t+1} of every scene (Sec. 2), a physics
  * step of dt (1/120 s in Sec. 4.4): d_actions [S*7] arm joint velocities
- * (rad/s; the agent's arm action of Sec. 5), device memory, or NULL (zero);
+ * (rad/s; the agent's arm action of Sec. 5; with the articulated arm the
+ * rates of the motor targets, which move by dt times them before the
+ * step's motors aim at them), device memory, or NULL (zero);
  * dt > 0 seconds; iters >= 1 sweeps (the cap when a tolerance is set).
  * SIM_EINVAL on bad arguments (nothing launched).  Asynchronous on the
  * handle's stream; per-scene soft faults go to the stats flags. */
@@ -206,6 +223,30 @@ int sim_set_export(sim_handle *h, int on);
  * fixed sweeps).  SIM_EINVAL on a bad value, SIM_ECAPACITY if a scene no
  * longer fits the persistent launch's LDS (settings unchanged). */
 int sim_set_solver(sim_handle *h, int solver, int warm_start, float tolerance);
+
+/* Sleeping islands for later steps (localized physics, Sec. 4.1: the robot
+ * is the only source of forces besides gravity, and the engine's sleeping
+ * state spares settled objects): speed > 0 (m/s) turns them on, 0 off.  An
+ * island (dynamic bodies joined by the step's contacts between two dynamic
+ * bodies) sleeps when every body in it has ended at least `steps` steps at
+ * rest (speed and surface speed |w| r, r the body's bounding radius, both at
+ * most `speed`; sim_state_view.rest counts them) and none of its bodies
+ * touches a kinematic body (the arm).  A sleeping body keeps its pose with
+ * zero velocity; its contacts are found as usual but are not coloured or
+ * solved (exported colour -1) and keep their previous impulses in the
+ * cache.  The counters are part of the state (checkpoints, resets clear
+ * them).  SIM_EINVAL for a negative or non-finite speed, steps < 1 with
+ * speed > 0, or speed > 0 with the learned warm start (and sim_set_solver
+ * refuses the learned start while sleeping is on). */
+int sim_set_sleep(sim_handle *h, float speed, int steps);
+
+/* Joint motors of the articulated arm (Sec. 5: PD position control with
+ * gain Kp = 0.3 and at most 10 N s of motor impulse per step, the
+ * defaults): kp in [0, 1] is the fraction of a joint's angle error its motor
+ * closes per step when unloaded; max_impulse >= 0 (N m s) bounds each
+ * motor's impulse in a step.  Applies from the next step.  SIM_EINVAL
+ * without an articulated arm (arm 2) or for a value out of range. */
+int sim_set_motors(sim_handle *h, float kp, float max_impulse);
 
 /* Learned warm start weights (this library's addition; the paper has no
  * learned solver), device memory read during every later step in
@@ -389,16 +430,28 @@ int sim_load_state(sim_handle *h, const void *d_blob);
  * (0 for a NULL handle). */
 size_t sim_autotune_scratch_bytes(const sim_handle *h);
 
+/* Routing table of the persistent launch: bit k of wave_buckets sends the
+ * scenes of body-count bucket k to single-wave teams (four scenes per
+ * workgroup), the others to whole-workgroup teams; buckets are [1, 16],
+ * (16, 32], (32, 64], ..., (512, 1024], (1024, 2046] bodies (k = 0..7).  A
+ * scene whose working set does not fit a quarter of the LDS stays with a
+ * whole workgroup whatever the table says.  Turns the persistent launch on.
+ * The table is what sim_autotune chooses and may be stored and applied to a
+ * later batch of the same workload.  SIM_EINVAL for bits beyond bucket 7,
+ * SIM_ECAPACITY if a scene fits no workgroup.  Results do not depend on it. */
+int sim_set_persistent_table(sim_handle *h, uint32_t wave_buckets);
+
 /* Autotuning of the persistent launch over the batch's own scenes (the
  * parallel environments of Sec. 4.4, whose synchronisation Sec. 7 names as
- * the loop's bound).  Picks wave_max_bodies by timing `steps` steps
- * (zero actions, dt, iters sweeps) for each candidate (0 and the powers of
- * two from 16 up to the largest scene) and restoring the state after each;
- * leaves the persistent launch on with the fastest and reports it in
- * *out_wave_max_bodies (may be NULL).  Synchronises the handle's stream;
- * the last step's contact and stats views then hold a trial step's values. */
+ * the loop's bound): the routing table, bucket by bucket in ascending body
+ * count, each bucket's scenes moved to single waves if that makes `steps`
+ * timed steps (zero actions, dt, iters sweeps, after an untimed one)
+ * faster, the state restored after each trial; leaves the persistent
+ * launch on with the table found and reports it in *out_wave_buckets (may
+ * be NULL).  Synchronises the handle's stream; the last step's contact and
+ * stats views then hold a trial step's values. */
 int sim_autotune(sim_handle *h, void *d_scratch, size_t scratch_bytes, int steps, float dt, int iters,
-                 int *out_wave_max_bodies);
+                 uint32_t *out_wave_buckets);
 
 /* The stream (hipStream_t, NULL = default) for later work of the handle. */
 int sim_set_stream(sim_handle *h, void *stream);

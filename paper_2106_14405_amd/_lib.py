@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbsim.so")
 
-SIM_ABI_VERSION = 2
+SIM_ABI_VERSION = 4
 SIM_OK, SIM_EINVAL, SIM_EDEVICE, SIM_EWORKSPACE, SIM_EABI, SIM_ECAPACITY = 0, -1, -2, -3, -4, -5
 SPHERE, BOX, CAPSULE = 0, 1, 2
 DYNAMIC, STATIC, KINEMATIC = 0, 1, 2
@@ -40,7 +40,8 @@ class BatchDesc(C.Structure):
 
 
 class StateView(C.Structure):
-    _fields_ = [("n_bodies", C.c_long), ("pose", C.c_void_p), ("vel", C.c_void_p), ("theta", C.c_void_p),
+    _fields_ = [("n_bodies", C.c_long), ("pose", C.c_void_p), ("vel", C.c_void_p), ("rest", C.c_void_p),
+                ("theta", C.c_void_p), ("arm_state", C.c_void_p),
                 ("cache_cap", C.c_int), ("cache_count", C.c_void_p), ("cache_key", C.c_void_p),
                 ("cache_lam", C.c_void_p)]
 
@@ -74,7 +75,8 @@ EXPORTED = ["sim_workspace_bytes", "sim_create", "sim_step", "sim_contacts", "si
             "sim_destroy", "sim_last_error", "sim_mlp_forward", "sim_mlp_workspace_bytes", "sim_mlp_stats",
             "sim_mlp_grad", "sim_mlp_adam", "sim_mlp_export", "sim_mlp_gather", "sim_set_persistent",
             "sim_autotune_scratch_bytes", "sim_autotune", "sim_state_bytes", "sim_save_state",
-            "sim_load_state", "sim_mlp_grad_noalloc", "sim_mlp_grad_noalloc_max_rows", "sim_query_arm"]
+            "sim_load_state", "sim_mlp_grad_noalloc", "sim_mlp_grad_noalloc_max_rows", "sim_query_arm", "sim_set_sleep", "sim_set_persistent_table",
+            "sim_set_motors"]
 
 _lib = None
 
@@ -119,9 +121,12 @@ def load():
     L.sim_mlp_gather.argtypes = [_v, _v, _v, C.c_long, _f, _v]
     L.sim_set_persistent.argtypes = [_v, C.c_int, C.c_int]
     L.sim_query_arm.argtypes = [_v, _v, C.c_int, _f, _v, _v]
+    L.sim_set_sleep.argtypes = [_v, _f, C.c_int]
+    L.sim_set_motors.argtypes = [_v, _f, _f]
     L.sim_autotune_scratch_bytes.argtypes = [_v]
     L.sim_autotune_scratch_bytes.restype = C.c_size_t
-    L.sim_autotune.argtypes = [_v, _v, C.c_size_t, C.c_int, _f, C.c_int, _P(C.c_int)]
+    L.sim_autotune.argtypes = [_v, _v, C.c_size_t, C.c_int, _f, C.c_int, _P(C.c_uint32)]
+    L.sim_set_persistent_table.argtypes = [_v, C.c_uint32]
     L.sim_state_bytes.argtypes = [_v]
     L.sim_state_bytes.restype = C.c_size_t
     L.sim_save_state.argtypes = [_v, _v]
@@ -129,7 +134,8 @@ def load():
     for name in ("sim_create", "sim_step", "sim_contacts", "sim_state", "sim_stats", "sim_set_export",
                  "sim_set_solver", "sim_set_mlp", "sim_reset", "sim_set_trace", "sim_set_stream",
                  "sim_mlp_forward", "sim_mlp_stats", "sim_mlp_grad", "sim_mlp_grad_noalloc", "sim_mlp_adam", "sim_mlp_export",
-                 "sim_mlp_gather", "sim_set_persistent", "sim_query_arm", "sim_autotune", "sim_save_state", "sim_load_state"):
+                 "sim_mlp_gather", "sim_set_persistent", "sim_query_arm", "sim_set_sleep", "sim_set_persistent_table", "sim_autotune", "sim_save_state", "sim_load_state",
+                 "sim_set_motors"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

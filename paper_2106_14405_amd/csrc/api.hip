@@ -58,7 +58,8 @@ int fail(int code, const std::string& msg) {
 
 struct Layout {
   size_t off_body_offset, off_shape, off_motion, off_prm, off_inv_mass, off_inv_inertia, off_friction,
-      off_restitution, off_pose, off_vel, off_theta, off_arm_base, off_scene_list;
+      off_restitution, off_pose, off_vel, off_rest, off_theta, off_arm_state, off_arm_base, off_scene_list;
+  size_t off_arm_rows;
   size_t off_ckey[2], off_clam[2], off_ccount[2], off_ccol[2];
   size_t off_x_pair, off_x_npairs, off_x_normal, off_x_point, off_x_phi, off_x_lambda, off_x_colour, off_x_feat;
   size_t off_raw, off_crec;
@@ -72,7 +73,7 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255u) & ~size_t(255u); }
 
-Layout make_layout(long S, long N, long PM, long CM, long n_hbm, long hbm_words) {
+Layout make_layout(long S, long N, long PM, long CM, long n_hbm, long hbm_words, int arm) {
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
@@ -86,7 +87,9 @@ Layout make_layout(long S, long N, long PM, long CM, long n_hbm, long hbm_words)
   L.off_restitution = take(4 * N);
   L.off_pose = take(4 * 7 * N);
   L.off_vel = take(4 * 6 * N);
+  L.off_rest = take(4 * N);  // steps each body has ended at rest (sleeping)
   L.off_theta = take(4 * 7 * S);
+  L.off_arm_state = take(arm == 2 ? 4 * 21 * S : 0);  // articulated arm: joint rates, motor targets, impulses
   L.off_arm_base = take(4 * 3 * S);
   L.off_scene_list = take(4 * S);
   for (int k = 0; k < 2; k++) {
@@ -105,6 +108,8 @@ Layout make_layout(long S, long N, long PM, long CM, long n_hbm, long hbm_words)
   L.off_x_feat = take(4 * 16 * S * CM);
   L.off_raw = take(4 * 8 * S * CM);
   L.off_crec = take(sizeof(float4) * rbs::rec_stride(PM, CM) * S);  // solver records, narrowphase staging
+  // articulated arm: joint-space rows of the contact on the arm in each colour
+  L.off_arm_rows = take(arm == 2 ? 4 * (size_t)rbs::kMaxColours * rbs::kArmRowWords * S : 0);
   for (int k = 0; k < 7; k++) L.off_st[k] = take(4 * S);
   L.off_gather = take(8 * S);  // per-scene row offsets and counts of sim_mlp_gather
   L.off_gcount = take(4 * S);
@@ -131,12 +136,15 @@ struct sim_handle {
   int export_on;
   float last_dt;    // dt of the last step (0 before the first)
   int last_export;  // export was on during the last step
-  int arm;
+  int arm;                 // 0 none, 1 kinematic, 2 articulated with joint motors
+  float motor_kp, motor_max;
   float link_len[7];
   float arm_radius;
   float gravity[3], margin, baumgarte, slop, rest_thresh, ground_mu, ground_e;
   int solver, warm;
   float tol;
+  float sleep_speed = 0.f;  // sleeping islands: off at 0
+  int sleep_steps = 0;
   rbs::MlpParams mlp;
   bool mlp_set;
   uint64_t* trace;
@@ -152,6 +160,8 @@ struct sim_handle {
   // persistent launch
   bool persistent = false;
   int wave_max_bodies = 0;
+  bool wave_by_table = false;  // route by the bucket table instead of the threshold
+  uint32_t wave_buckets = 0;   // bit k: the scenes of body-count bucket k go to single waves
   int n_team = 0, n_wave = 0, lds_words = 0, grid = 0;
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -196,8 +206,15 @@ rbs::StepParams params(sim_handle* h) {
   P.restitution = at<float>(h, L.off_restitution);
   P.pose = at<float>(h, L.off_pose);
   P.vel = at<float>(h, L.off_vel);
+  P.rest = at<int32_t>(h, L.off_rest);
+  P.sleep_speed = h->sleep_speed;
+  P.sleep_steps = h->sleep_steps;
   P.arm = h->arm;
   P.theta = at<float>(h, L.off_theta);
+  P.arm_state = h->arm == 2 ? at<float>(h, L.off_arm_state) : nullptr;
+  P.arm_rows = h->arm == 2 ? at<float>(h, L.off_arm_rows) : nullptr;
+  P.motor_kp = h->motor_kp;
+  P.motor_max = h->motor_max;
   P.arm_base = at<float>(h, L.off_arm_base);
   for (int k = 0; k < 7; k++) P.link_len[k] = h->link_len[k];
   P.arm_radius = h->arm_radius;
@@ -282,13 +299,18 @@ int validate(const sim_batch_desc* d, Caps* caps) {
     if (d->h_motion[i] == SIM_DYNAMIC && !(d->h_mass[i] > 0.f && std::isfinite(d->h_mass[i])))
       return fail(SIM_EINVAL, "dynamic bodies need a positive mass");
   }
+  if (d->arm < 0 || d->arm > 2) return fail(SIM_EINVAL, "arm must be 0, 1 or 2");
+  if (d->arm == 2 && (d->solver != SIM_PGS || d->warm_start == SIM_LEARNED))
+    return fail(SIM_EINVAL, "the articulated arm needs the PGS solver without the learned warm start");
   if (d->arm) {
     if (!d->h_arm_base || !d->h_arm_theta) return fail(SIM_EINVAL, "arm needs base and theta arrays");
+    const int want = d->arm == 2 ? SIM_DYNAMIC : SIM_KINEMATIC;
     for (int s = 0; s < d->num_scenes; s++)
       for (int k = 0; k < 7; k++) {
         long i = d->h_body_offset[s + 1] - 7 + k;
-        if (d->h_shape[i] != SIM_CAPSULE || d->h_motion[i] != SIM_KINEMATIC)
-          return fail(SIM_EINVAL, "the last 7 bodies of an arm scene must be kinematic capsules");
+        if (d->h_shape[i] != SIM_CAPSULE || d->h_motion[i] != want)
+          return fail(SIM_EINVAL, d->arm == 2 ? "the last 7 bodies of an articulated arm scene must be dynamic capsules"
+                                              : "the last 7 bodies of an arm scene must be kinematic capsules");
       }
   }
   if (d->max_pairs < 1 || d->max_contacts < 1) return fail(SIM_EINVAL, "capacities must be >= 1");
@@ -307,8 +329,8 @@ int validate(const sim_batch_desc* d, Caps* caps) {
   return SIM_OK;
 }
 
-int lds_bytes(int NB, int PM, int CM, int T, int solver, int warm) {
-  rbs::LdsLayout L = rbs::lds_layout(NB, PM, CM, T / 64, solver, warm);
+int lds_bytes(int NB, int PM, int CM, int T, int solver, int warm, int arm) {
+  rbs::LdsLayout L = rbs::lds_layout(NB, PM, CM, T / 64, solver, warm, arm);
   return L.total * 4;
 }
 
@@ -327,8 +349,9 @@ int team_lds_words(int lds_limit) { return ((lds_limit - 256) / 4) & ~15; }
 
 // Working-set words of a scene of nb bodies in its largest solver mode
 // (Jacobi with the learned start) for a 256-thread team.
-long worst_words(int nb, int PM, int CM) {
-  return rbs::lds_layout(nb, rbs::scene_cap(nb, PM), rbs::scene_cap(nb, CM), 4, rbs::SOLVER_JACOBI, rbs::WARM_LEARNED)
+long worst_words(int nb, int PM, int CM, int arm) {
+  return rbs::lds_layout(nb, rbs::scene_cap(nb, PM), rbs::scene_cap(nb, CM), 4, rbs::SOLVER_JACOBI, rbs::WARM_LEARNED,
+                         arm)
       .total;
 }
 
@@ -342,12 +365,12 @@ struct HbmSplit {
   int nb_lds = 0;  // largest body count among the other scenes
 };
 
-HbmSplit hbm_split(const int32_t* off, int S, int PM, int CM, int lds_limit, int min_bodies) {
+HbmSplit hbm_split(const int32_t* off, int S, int PM, int CM, int lds_limit, int min_bodies, int arm) {
   HbmSplit r;
   const long budget = team_lds_words(lds_limit);
   for (int s = 0; s < S; s++) {
     const int nb = off[s + 1] - off[s];
-    const long w = worst_words(nb, PM, CM);
+    const long w = worst_words(nb, PM, CM, arm);
     if (w > budget || (min_bodies > 0 && nb >= min_bodies)) {
       r.scenes.push_back(s);
       r.words = std::max(r.words, (w + 63) & ~63L);
@@ -360,11 +383,21 @@ HbmSplit hbm_split(const int32_t* off, int S, int PM, int CM, int lds_limit, int
   return r;
 }
 
+// Body-count buckets of the persistent launch's routing table: [1, 16],
+// (16, 32], ..., (512, 1024], (1024, 2046].
+constexpr int kBuckets = 8;
+int body_bucket(int nb) {
+  int k = 0;
+  for (int hi = 16; k < kBuckets - 1 && nb > hi; hi *= 2) k++;
+  return k;
+}
+
 // Persistent launch: a queue for whole-workgroup teams and one for single-wave
 // teams, each in descending body count (ties by scene index).  A scene goes
-// to a wave when it has at most wave_max_bodies bodies and its working set
-// (for the current solver mode) fits a quarter of the workgroup's LDS.
-int build_queues(sim_handle* h, int wave_max_bodies) {
+// to a wave when its routing says so (at most wave_max_bodies bodies, or its
+// body-count bucket's bit in the table) and its working set (for the current
+// solver mode) fits a quarter of the workgroup's LDS.
+int build_queues(sim_handle* h, int wave_max_bodies, bool by_table = false, uint32_t buckets = 0) {
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(SIM_EDEVICE, "hipGetDevice failed");
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
@@ -378,9 +411,10 @@ int build_queues(sim_handle* h, int wave_max_bodies) {
     if (in_hbm[s]) continue;
     const int nb = h->body_offset[s + 1] - h->body_offset[s];
     const int pm = rbs::scene_cap(nb, h->PM), cm = rbs::scene_cap(nb, h->CM);
-    const int need_wave = rbs::lds_layout(nb, pm, cm, 1, h->solver, h->warm).total;
-    const int need_team = rbs::lds_layout(nb, pm, cm, 4, h->solver, h->warm).total;
-    if (nb <= wave_max_bodies && need_wave <= lds_words / 4)
+    const int need_wave = rbs::lds_layout(nb, pm, cm, 1, h->solver, h->warm, h->arm).total;
+    const int need_team = rbs::lds_layout(nb, pm, cm, 4, h->solver, h->warm, h->arm).total;
+    const bool to_wave = by_table ? ((buckets >> body_bucket(nb)) & 1u) != 0u : nb <= wave_max_bodies;
+    if (to_wave && need_wave <= lds_words / 4)
       wave.push_back(s);
     else if (need_team <= lds_words)
       team.push_back(s);
@@ -405,6 +439,8 @@ int build_queues(sim_handle* h, int wave_max_bodies) {
   h->lds_words = lds_words;
   h->grid = ncu;
   h->wave_max_bodies = wave_max_bodies;
+  h->wave_by_table = by_table;
+  h->wave_buckets = buckets;
   for (int k = 0; k < 2; k++)
     if (h->exec[k]) {
       hipGraphExecDestroy(h->exec[k]);
@@ -429,7 +465,7 @@ rbs::QueueParams queue_params(sim_handle* h) {
 rbs::LdsLayout hbm_layout(const sim_handle* h) {
   int nb = 0;
   for (int s : h->hbm) nb = std::max(nb, h->body_offset[s + 1] - h->body_offset[s]);
-  return rbs::lds_layout(nb, rbs::scene_cap(nb, h->PM), rbs::scene_cap(nb, h->CM), 4, h->solver, h->warm);
+  return rbs::lds_layout(nb, rbs::scene_cap(nb, h->PM), rbs::scene_cap(nb, h->CM), 4, h->solver, h->warm, h->arm);
 }
 
 // One step through a graph of (queue reset, persistent kernel) captured once
@@ -497,7 +533,9 @@ struct StateSpan {
 std::vector<StateSpan> state_spans(const sim_handle* h) {
   const Layout& L = h->lay;
   const size_t S = h->S, N = h->N, CM = h->CM;
-  std::vector<StateSpan> v = {{L.off_pose, 4 * 7 * N}, {L.off_vel, 4 * 6 * N}, {L.off_theta, 4 * 7 * S}};
+  std::vector<StateSpan> v = {{L.off_pose, 4 * 7 * N}, {L.off_vel, 4 * 6 * N}, {L.off_rest, 4 * N},
+                              {L.off_theta, 4 * 7 * S}};
+  if (h->arm == 2) v.push_back({L.off_arm_state, 4 * 21 * S});
   for (int k = 0; k < 2; k++) {
     v.push_back({L.off_ckey[k], 4 * S * CM});
     v.push_back({L.off_clam[k], 4 * 4 * S * CM});
@@ -532,8 +570,9 @@ size_t sim_workspace_bytes(const sim_batch_desc* d) {
   Caps c;
   if (validate(d, &c) != SIM_OK) return 0;
   const HbmSplit sp = hbm_split(d->h_body_offset, d->num_scenes, d->max_pairs, d->max_contacts, device_lds_limit(),
-                                d->hbm_min_bodies);
-  return make_layout(d->num_scenes, c.N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words).total;
+                                d->hbm_min_bodies, d->arm);
+  return make_layout(d->num_scenes, c.N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words, d->arm)
+      .total;
 }
 
 int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_bytes, sim_handle** out) {
@@ -545,8 +584,8 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   const int S = d->num_scenes;
   const long N = c.N;
   const int limit = device_lds_limit();
-  HbmSplit sp = hbm_split(d->h_body_offset, S, d->max_pairs, d->max_contacts, limit, d->hbm_min_bodies);
-  Layout lay = make_layout(S, N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words);
+  HbmSplit sp = hbm_split(d->h_body_offset, S, d->max_pairs, d->max_contacts, limit, d->hbm_min_bodies, d->arm);
+  Layout lay = make_layout(S, N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words, d->arm);
   if (!d_workspace || workspace_bytes < lay.total) return fail(SIM_EWORKSPACE, "workspace too small");
   if (((uintptr_t)d_workspace & 255u) != 0) return fail(SIM_EWORKSPACE, "workspace must be 256-byte aligned");
   const int T = d->threads ? d->threads : 64;
@@ -554,7 +593,7 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   // (the split above sends every larger one to global memory)
   const int nbl = sp.nb_lds;
   int need = nbl ? lds_bytes(nbl, rbs::scene_cap(nbl, d->max_pairs), rbs::scene_cap(nbl, d->max_contacts), T,
-                             rbs::SOLVER_JACOBI, rbs::WARM_LEARNED)
+                             rbs::SOLVER_JACOBI, rbs::WARM_LEARNED, d->arm)
                  : 0;
   if (need > limit)
     return fail(SIM_ECAPACITY, "per-scene working set (" + std::to_string(need) + " B) exceeds LDS (" +
@@ -575,7 +614,9 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   h->export_on = 0;
   h->last_dt = 0.f;
   h->last_export = 0;
-  h->arm = d->arm ? 1 : 0;
+  h->arm = d->arm;
+  h->motor_kp = 0.3f;      // position gain of the joint motors (Sec. 5)
+  h->motor_max = 10.0f;    // largest motor impulse per step, N s (Sec. 5)
   for (int k = 0; k < 7; k++) h->link_len[k] = d->link_len[k];
   h->arm_radius = d->arm_radius;
   for (int k = 0; k < 3; k++) h->gravity[k] = d->gravity[k];
@@ -664,6 +705,13 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   if (e == hipSuccess) e = up(lay.off_pose, pose.data(), 4 * 7 * N);
   if (e == hipSuccess) e = up(lay.off_vel, vel.data(), 4 * 6 * N);
   if (e == hipSuccess) e = up(lay.off_theta, theta.data(), 4 * 7 * S);
+  std::vector<float> arm_state;
+  if (d->arm == 2) {  // at rest, motor targets at the initial angles, no motor impulses yet
+    arm_state.assign(21 * (size_t)S, 0.f);
+    for (int s2 = 0; s2 < S; s2++)
+      for (int k = 0; k < 7; k++) arm_state[21 * s2 + 7 + k] = theta[7 * s2 + k];
+    if (e == hipSuccess) e = up(lay.off_arm_state, arm_state.data(), 4 * 21 * S);
+  }
   if (e == hipSuccess) e = up(lay.off_arm_base, base.data(), 4 * 3 * S);
   if (e == hipSuccess) e = up(lay.off_scene_list, order.data(), 4 * S);
   if (e == hipSuccess) e = up(lay.off_glist, glist.data(), 4 * S);
@@ -710,7 +758,7 @@ int sim_step(sim_handle* h, const float* d_actions, float dt, int iters) {
     rc = 0;
     if (nl > 0) {
       rbs::LdsLayout L = rbs::lds_layout(nbl, rbs::scene_cap(nbl, h->PM), rbs::scene_cap(nbl, h->CM),
-                                         h->threads / 64, h->solver, h->warm);
+                                         h->threads / 64, h->solver, h->warm, h->arm);
       if (L.total * 4 > h->lds_limit) return fail(SIM_ECAPACITY, "working set exceeds LDS");
       rc = rbs_launch_step(&P, &L, h->threads, nl, h->stream);
     }
@@ -771,7 +819,9 @@ int sim_state(const sim_handle* hc, sim_state_view* out) {
   out->n_bodies = h->N;
   out->pose = at<float>(h, L.off_pose);
   out->vel = at<float>(h, L.off_vel);
+  out->rest = at<int32_t>(h, L.off_rest);
   out->theta = h->arm ? at<float>(h, L.off_theta) : nullptr;
+  out->arm_state = h->arm == 2 ? at<float>(h, L.off_arm_state) : nullptr;
   out->cache_cap = h->CM;
   out->cache_count = at<int32_t>(h, L.off_ccount[h->parity]);
   out->cache_key = at<uint32_t>(h, L.off_ckey[h->parity]);
@@ -799,21 +849,35 @@ int sim_set_export(sim_handle* h, int on) {
   return SIM_OK;
 }
 
+int sim_set_motors(sim_handle* h, float kp, float max_impulse) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (h->arm != 2) return fail(SIM_EINVAL, "the batch has no articulated arm");
+  if (!(kp >= 0.f && kp <= 1.f)) return fail(SIM_EINVAL, "motor gain must be in [0, 1]");
+  if (!(max_impulse >= 0.f) || !std::isfinite(max_impulse)) return fail(SIM_EINVAL, "motor impulse bound must be >= 0");
+  h->motor_kp = kp;
+  h->motor_max = max_impulse;
+  return SIM_OK;
+}
+
 int sim_set_solver(sim_handle* h, int solver, int warm_start, float tolerance) {
   if (!h) return fail(SIM_EINVAL, "handle is NULL");
   if (solver != SIM_PGS && solver != SIM_JACOBI) return fail(SIM_EINVAL, "bad solver");
   if (warm_start < SIM_COLD || warm_start > SIM_LEARNED) return fail(SIM_EINVAL, "bad warm start");
   if (!(tolerance >= 0.f)) return fail(SIM_EINVAL, "tolerance must be >= 0");
+  if (warm_start == SIM_LEARNED && h->sleep_speed > 0.f)
+    return fail(SIM_EINVAL, "the learned warm start is not available with sleeping islands");
+  if (h->arm == 2 && (solver != SIM_PGS || warm_start == SIM_LEARNED))
+    return fail(SIM_EINVAL, "the articulated arm needs the PGS solver without the learned warm start");
   const int old_solver = h->solver, old_warm = h->warm;
   h->solver = solver;
   h->warm = warm_start;
   if (h->persistent && (solver != old_solver || warm_start != old_warm)) {
     // the working sets change size: route the scenes again
-    int rc = build_queues(h, h->wave_max_bodies);
+    int rc = build_queues(h, h->wave_max_bodies, h->wave_by_table, h->wave_buckets);
     if (rc != SIM_OK) {
       h->solver = old_solver;
       h->warm = old_warm;
-      build_queues(h, h->wave_max_bodies);
+      build_queues(h, h->wave_max_bodies, h->wave_by_table, h->wave_buckets);
       return rc;
     }
   }
@@ -851,6 +915,17 @@ int sim_reset(sim_handle* h, const uint8_t* d_mask, const sim_reset_pool* pool) 
   return SIM_OK;
 }
 
+int sim_set_sleep(sim_handle* h, float speed, int steps) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (!(speed >= 0.f) || !std::isfinite(speed)) return fail(SIM_EINVAL, "speed must be finite and >= 0");
+  if (speed > 0.f && steps < 1) return fail(SIM_EINVAL, "steps must be >= 1");
+  if (speed > 0.f && h->warm == SIM_LEARNED)
+    return fail(SIM_EINVAL, "sleeping islands are not available with the learned warm start");
+  h->sleep_speed = speed;
+  h->sleep_steps = speed > 0.f ? steps : 0;
+  return SIM_OK;
+}
+
 int sim_set_trace(sim_handle* h, uint64_t* d_trace) {
   if (!h) return fail(SIM_EINVAL, "handle is NULL");
   h->trace = d_trace;
@@ -872,6 +947,15 @@ int sim_set_persistent(sim_handle* h, int on, int wave_max_bodies) {
     return SIM_OK;
   }
   int rc = build_queues(h, wave_max_bodies < 0 ? rbs::kMaxBodiesPerScene : wave_max_bodies);
+  if (rc != SIM_OK) return rc;
+  h->persistent = true;
+  return SIM_OK;
+}
+
+int sim_set_persistent_table(sim_handle* h, uint32_t wave_buckets) {
+  if (!h) return fail(SIM_EINVAL, "handle is NULL");
+  if (wave_buckets >> kBuckets) return fail(SIM_EINVAL, "bucket bits beyond the table");
+  int rc = build_queues(h, 0, true, wave_buckets);
   if (rc != SIM_OK) return rc;
   h->persistent = true;
   return SIM_OK;
@@ -914,46 +998,59 @@ int sim_load_state(sim_handle* h, const void* d_blob) {
 }
 
 int sim_autotune(sim_handle* h, void* d_scratch, size_t scratch_bytes, int steps, float dt, int iters,
-                 int* out_wave_max_bodies) {
+                 uint32_t* out_wave_buckets) {
   if (!h) return fail(SIM_EINVAL, "handle is NULL");
   if (steps < 1 || !(dt > 0.f) || iters < 1) return fail(SIM_EINVAL, "steps, dt and iters must be positive");
   if (!d_scratch || scratch_bytes < state_bytes(h) || ((uintptr_t)d_scratch & 255u))
     return fail(SIM_EWORKSPACE, "scratch too small or not 256-byte aligned");
   if (h->warm == SIM_LEARNED && !h->mlp_set) return fail(SIM_EINVAL, "learned warm start needs sim_set_mlp");
-  // candidate thresholds: none, then the body-count buckets present in the batch
-  std::vector<int> cand = {0};
-  int nmax = 0;
-  for (int s = 0; s < h->S; s++) nmax = std::max(nmax, h->body_offset[s + 1] - h->body_offset[s]);
-  for (int b = 16; b / 2 < nmax && b <= rbs::kMaxBodiesPerScene; b *= 2) cand.push_back(b);
-  const bool was_persistent = h->persistent;
+  // body-count buckets present in the batch (scenes stepped out of global
+  // memory are not in the queues)
+  std::vector<char> in_hbm(h->S, 0);
+  for (int s : h->hbm) in_hbm[s] = 1;
+  uint32_t present = 0;
+  for (int s = 0; s < h->S; s++)
+    if (!in_hbm[s]) present |= 1u << body_bucket(h->body_offset[s + 1] - h->body_offset[s]);
+  const bool was_persistent = h->persistent, was_table = h->wave_by_table;
   const int was_threshold = h->wave_max_bodies, parity0 = h->parity;
+  const uint32_t was_buckets = h->wave_buckets;
   char* scratch = static_cast<char*>(d_scratch);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) hipEventDestroy(e0);
     return fail(SIM_EDEVICE, "event creation failed");
   }
-  int best = -1, rc = SIM_OK;
-  float best_ms = 0.f;
+  int rc = SIM_OK;
   if (copy_state(h, scratch, true) != 0) rc = fail(SIM_EDEVICE, "state save failed");
-  for (size_t k = 0; k < cand.size() && rc == SIM_OK; k++) {
-    rc = build_queues(h, cand[k]);
-    if (rc != SIM_OK) break;
-    if (k > 0 && h->n_wave == 0) continue;  // same routing as no waves
+  // times `steps` steps of one routing (after an untimed step that captures
+  // the graph) and restores the state
+  auto trial = [&](uint32_t mask, float* ms) -> int {
+    int r = build_queues(h, 0, true, mask);
+    if (r != SIM_OK) return r;
     h->persistent = true;
-    // one untimed step captures the graphs' first parity; then the timed ones
-    for (int it = 0; it <= steps && rc == SIM_OK; it++) {
-      if (it == 1 && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(SIM_EDEVICE, "event record failed");
-      if (rc == SIM_OK) rc = sim_step(h, nullptr, dt, iters);
+    for (int it = 0; it <= steps && r == SIM_OK; it++) {
+      if (it == 1 && hipEventRecord(e0, h->stream) != hipSuccess) r = fail(SIM_EDEVICE, "event record failed");
+      if (r == SIM_OK) r = sim_step(h, nullptr, dt, iters);
     }
-    float ms = 0.f;
-    if (rc == SIM_OK && (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-      rc = fail(SIM_EDEVICE, "timing failed");
-    if (rc == SIM_OK && copy_state(h, scratch, false) != 0) rc = fail(SIM_EDEVICE, "state restore failed");
+    if (r == SIM_OK && (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+      r = fail(SIM_EDEVICE, "timing failed");
+    if (r == SIM_OK && copy_state(h, scratch, false) != 0) r = fail(SIM_EDEVICE, "state restore failed");
     h->parity = parity0;
-    if (rc == SIM_OK && (best < 0 || ms < best_ms)) {
-      best = cand[k];
+    return r;
+  };
+  // greedy over the buckets in ascending size: a bucket's scenes go to single
+  // waves if that makes the batch's step faster
+  uint32_t best = 0;
+  float best_ms = 0.f;
+  if (rc == SIM_OK) rc = trial(0u, &best_ms);
+  for (int k = 0; k < kBuckets && rc == SIM_OK; k++) {
+    if (!((present >> k) & 1u)) continue;
+    const uint32_t mask = best | (1u << k);
+    float ms = 0.f;
+    rc = trial(mask, &ms);
+    if (rc == SIM_OK && h->n_wave > 0 && ms < best_ms) {
+      best = mask;
       best_ms = ms;
     }
   }
@@ -962,13 +1059,13 @@ int sim_autotune(sim_handle* h, void* d_scratch, size_t scratch_bytes, int steps
   if (rc == SIM_OK) hipStreamSynchronize(h->stream);
   if (rc != SIM_OK) {
     h->persistent = was_persistent;
-    if (was_persistent) build_queues(h, was_threshold);
+    if (was_persistent) build_queues(h, was_threshold, was_table, was_buckets);
     return rc;
   }
-  rc = build_queues(h, best);
+  rc = build_queues(h, 0, true, best);
   if (rc != SIM_OK) return rc;
   h->persistent = true;
-  if (out_wave_max_bodies) *out_wave_max_bodies = best;
+  if (out_wave_buckets) *out_wave_buckets = best;
   return SIM_OK;
 }
 

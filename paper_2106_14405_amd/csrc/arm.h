@@ -11,6 +11,7 @@ namespace rbs {
 __device__ inline void arm_chain(const float* base, const float* th, const float* len, V3* c, float (*q)[4], V3* o, V3* ax) {
   float q0 = 1.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
   V3 p = v3(base[0], base[1], base[2]);
+#pragma unroll
   for (int k = 0; k < 7; k++) {
     float sn, cs;
     sincosf(0.5f * th[k], &sn, &cs);

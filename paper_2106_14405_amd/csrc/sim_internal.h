@@ -53,8 +53,15 @@ struct StepParams {
   const float* restitution; // [N]
   float* pose;              // [7][N]  x y z qw qx qy qz
   float* vel;               // [6][N]  vx vy vz wx wy wz
-  int arm;
-  float* theta;             // [S][7]
+  int32_t* rest;            // [N] steps each body has ended at rest
+  float sleep_speed;        // sleeping islands when > 0 (m/s, speed and surface speed)
+  int sleep_steps;          // steps at rest before an island may sleep
+  int arm;                  // 0 none, 1 kinematic links, 2 articulated body driven by joint motors
+  float* theta;             // [S][7] joint angles
+  float* arm_state;         // arm 2: [S][21] joint rates, motor targets, motor impulses
+  float* arm_rows;          // arm 2: [S][kMaxColours][kArmRowWords] joint-space rows of the arm's contacts
+  float motor_kp;           // arm 2: motor position gain
+  float motor_max;          // arm 2: largest motor impulse per step (N s)
   const float* arm_base;    // [S][3]
   float link_len[7];
   float arm_radius;
@@ -129,7 +136,7 @@ struct QueueParams {
 // and increments); outputs (arm force partial sums).  Until the setup
 // writes it, lam holds each contact's previous-impulse slot.
 struct LdsLayout {
-  int geo, dyn, dyn2, ckey, lam, perm, fresh, misc, hist, hbase;
+  int geo, dyn, dyn2, ckey, lam, perm, fresh, misc, arm, hist, hbase;
   int scr;
   int pk, pk2, lo, hi, skey, sval, skey2, sval2, nperm, ncnt;
   int colour, deg, lstart, list, rank, cv0, ck1;
@@ -140,9 +147,26 @@ struct LdsLayout {
 constexpr int kMiscWords = 64;
 // word slots of the misc region: counters, flags, per-wave partials (one
 // word per wave of a 256-thread team from M_WAVE and from M_SCAN)
-enum { M_NPAIRS = 0, M_NCONT = 1, M_FLAGS = 2, M_NCOL = 3, M_CHANGED = 5, M_WAVE = 16, M_SCAN = 32 };
+enum { M_NPAIRS = 0, M_NCONT = 1, M_FLAGS = 2, M_NCOL = 3, M_CHANGED = 5, M_NACT = 6, M_WAVE = 16, M_SCAN = 32 };
+// colour of a contact whose dynamic bodies all sleep: sorted after every
+// solved colour and never swept
+constexpr uint32_t kSleepColour = 128;
+// meta-word bit of a sleeping dynamic body (shape in bits 0-7, motion 8-15)
+constexpr uint32_t kAsleepBit = 1u << 16;
 static_assert(M_SCAN + kMaxThreads / 64 <= kMiscWords && M_WAVE + kMaxThreads / 64 <= M_SCAN, "misc slots");
 constexpr int kDynWords = 12;  // words per body in the dyn region (three float4)
+
+// Links of the articulated arm (arm 2): a motion code of the meta word only;
+// they carry no velocity or mass of their own in LDS (the arm holds both).
+constexpr int ARMLINK = 3;
+// LDS words of the articulated arm (arm 2): M^-1 (row-major 7 x 7), the
+// joint-rate changes of the solve, the joint rates at the setup, the motor
+// impulses and targets, joint origins and axes (x y z each)
+enum { ARM_MI = 0, ARM_DQ = 52, ARM_QREF = 60, ARM_LAM = 68, ARM_BIAS = 76, ARM_O = 84, ARM_AX = 105,
+       kArmWords = 128 };
+// global words per colour of the joint-space rows of the arm contact in that
+// colour (g_n, g_t1, g_t2, then M^-1 g of each; 7 words apiece)
+constexpr int kArmRowWords = 48;
 constexpr int kRec = 5;        // float4 per contact in the solver records
 
 // float4 per scene of the solver-record buffer: the records of CM contacts,
@@ -152,7 +176,7 @@ inline __host__ __device__ long rec_stride(long PM, long CM) {
   return kRec * CM > 8 * PM ? kRec * CM : 8 * PM;
 }
 
-inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int waves, int solver, int warm) {
+inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int waves, int solver, int warm, int arm) {
   LdsLayout L;
   int o = 0;
   auto take = [&](int words) { int r = o; o += (words + 3) & ~3; return r; };
@@ -166,6 +190,7 @@ inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int wave
   L.perm = take(CM);
   L.fresh = (warm == WARM_LEARNED) ? take((CM + 31) / 32) : -1;
   L.misc = take(kMiscWords);
+  L.arm = arm == 2 ? take(kArmWords) : -1;
   L.hist = take(256 * waves);
   L.hbase = take(256);
   L.scr = o;

@@ -46,7 +46,7 @@ struct Team {
 // larger workgroup the wave's own memory fences (its LDS operations
 // complete in issue order; the fence also waits for its global stores).
 template <class TM>
-__device__ __forceinline__ void team_sync(const TM& tm) {
+__device__ __forceinline__ void team_sync(const TM tm) {
   if constexpr (TM::wave) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -91,7 +91,7 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 // In-place exclusive prefix sum of a[0..n) in LDS; every thread takes a
 // contiguous chunk; returns the total.  misc supplies per-wave slots.
 template <class TM>
-__device__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* misc, const TM& tm) {
+__device__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* misc, const TM tm) {
   const int tid = tm.tid, T = tm.T, W = T >> 6, w = tid >> 6, lane = tid & 63;
   const int chunk = (n + T - 1) / T;
   const int i0 = tid * chunk, i1 = min(n, i0 + chunk);
@@ -122,7 +122,7 @@ __device__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* misc, con
 // sorted data ended in (k1, v1), 0 if in (k0, v0).
 template <class TM>
 __device__ int lds_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int n, int shift0, int passes,
-                              uint32_t* hist, uint32_t* base, uint32_t* misc, const TM& tm) {
+                              uint32_t* hist, uint32_t* base, uint32_t* misc, const TM tm) {
   const int T = tm.T, tid = tm.tid, W = T >> 6, w = tid >> 6;
   int swapped = 0;
   for (int ps = 0; ps < passes; ps++) {
@@ -260,7 +260,7 @@ __device__ __forceinline__ void rank_count(const uint32_t* k0, int n, const uint
 
 template <bool kUnique, class TM>
 __device__ void lds_rank_sort(const uint32_t* k0, const uint32_t* v0, uint32_t* k1, uint32_t* v1, int n,
-                              const TM& tm) {
+                              const TM tm) {
   const int T = tm.T, tid = tm.tid;
   uint32_t mk[8], mi[8], rk[8];
 #pragma unroll
@@ -307,7 +307,7 @@ __device__ __forceinline__ float wave_max(float v) {
 
 // Block-wide maximum of non-negative floats (one value per thread).
 template <class TM>
-__device__ __forceinline__ float block_max(float v, uint32_t* misc, const TM& tm) {
+__device__ __forceinline__ float block_max(float v, uint32_t* misc, const TM tm) {
   const int tid = tm.tid, W = tm.T >> 6;
   v = wave_max(v);
   if (W == 1) return v;
@@ -367,6 +367,8 @@ __device__ __forceinline__ uint32_t body_meta(const LdsLayout& L, Smem S, int i)
   return __float_as_uint(S.f[L.geo + 12 * i + 3]);
 }
 __device__ __forceinline__ bool is_dyn_meta(uint32_t meta) { return ((meta >> 8) & 255u) == DYNAMIC; }
+// a dynamic body that is not asleep: the bodies the solver moves
+__device__ __forceinline__ bool is_awake_meta(uint32_t meta) { return is_dyn_meta(meta) && !(meta & kAsleepBit); }
 
 // Dynamic state of a body in registers.
 struct Dyn {
@@ -408,8 +410,8 @@ __device__ __forceinline__ void proj_disk(float& l1, float& l2, float lim) {
 
 // Solver record of one contact, 5 float4 in global memory, colour-major
 // order:
-//  0 (n, m_n)  1 (r_a, m_t1)  2 (r_b, m_t2)  3 (k_1n, k_2n, bias, mu)
-//  4 (key, Jacobi scale, tangent coefficient, 0)
+//  0 (n, m_n)  1 (r_a, m_t1)  2 (r_b, m_t2)  3 (k_1n, k_2n, bias - u_n, mu)
+//  4 (key, Jacobi scale, tangent coefficient, u_t1)
 // n the normal (the tangents t1, t2 follow from it and the coefficient
 // exactly as in the setup), r_a, r_b the contact point relative to the bodies' centres,
 // m_d = 1 / k_d the effective mass of row d, and k_dn the change of row d's
@@ -419,6 +421,16 @@ __device__ __forceinline__ void proj_disk(float& l1, float& l2, float lim) {
 // w_b x r_b) and an impulse P changes w by I^-1 (r x P), with the world
 // inverse inertia I^-1 read from LDS.  80 bytes instead of the 208 of
 // explicit rows keep a sweep's records in L2.
+//
+// During the solve a dynamic body's LDS slot holds its velocity change
+// since the setup, not its velocity: a row's velocity is u_d + d . (point
+// velocity of the changes), with u_d the row's velocity from the dynamic
+// bodies' velocities at the setup (u_n folded into the normal row's bias,
+// u_t1 in the record, u_t2 in the fourth word of the contact's impulse).
+// A sweep's impulse steps are small against a fast body's velocity: added
+// to the velocity itself they would be rounded away in float32 while the
+// impulses still took them, and the two would drift apart over hundreds of
+// sweeps.  Kinematic bodies keep their (unchanging) velocity in the slot.
 static_assert(kRec == 5, "record layout below");
 
 struct Rec {
@@ -445,13 +457,13 @@ __device__ __forceinline__ int rec_b(const Rec& R) {
 }
 
 __device__ __forceinline__ void store_rec(float4* rec, int i, V3 n, V3 ra, V3 rb, const float* m, float k1n, float k2n,
-                                          float bias, float mu, uint32_t key, float jsc) {
+                                          float bias, float mu, uint32_t key, float jsc, float u1) {
   float4* o = rec + kRec * i;
   o[0] = f4(n, m[0]);
   o[1] = f4(ra, m[1]);
   o[2] = f4(rb, m[2]);
   o[3] = make_float4(k1n, k2n, bias, mu);
-  o[4] = make_float4(__uint_as_float(key), jsc, tangent_coef(n), 0.f);
+  o[4] = make_float4(__uint_as_float(key), jsc, tangent_coef(n), u1);
 }
 
 // A body as the solver sees it in LDS: velocities, inverse mass (dynamic
@@ -503,7 +515,7 @@ __device__ __forceinline__ void apply_impulse(Vel& A, Vel& B, V3 ra, V3 rb, V3 P
 // compiler fence (its LDS operations complete in issue order), which keeps
 // prefetched global loads in flight; wider teams use a barrier.
 template <class TM>
-__device__ __forceinline__ void colour_sync(const TM& tm) {
+__device__ __forceinline__ void colour_sync(const TM tm) {
   if (tm.T == 64) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -513,11 +525,46 @@ __device__ __forceinline__ void colour_sync(const TM& tm) {
   }
 }
 
+// The articulated arm (arm 2) as the solver sees it: the joint-rate changes
+// in LDS and this scene's joint-space rows of the arm contacts in global
+// memory, one slot per colour (every contact on the arm takes its own
+// colour, so a colour batch moves the joint rates from one lane at most).
+// A contact's record holds its arm side in word (4, y): +1 when body a is
+// an arm link, -1 when body b is, 0 when neither (the Jacobi scale's word:
+// the Jacobi solver is not used with this arm).
+struct ArmCtx {
+  bool on;
+  float* dq;           // LDS [7] joint-rate changes since the setup
+  const float* rows;   // global [kMaxColours][kArmRowWords]
+};
+
+// Row velocities g . dq of the arm contact in colour c (n, t1, t2).
+__device__ __forceinline__ void arm_row_vel(const ArmCtx& A, int c, float u[3]) {
+  const float* g = A.rows + (long)c * kArmRowWords;
+  u[0] = 0.f; u[1] = 0.f; u[2] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 7; i++) {
+    const float d = A.dq[i];
+    u[0] += g[i] * d;
+    u[1] += g[7 + i] * d;
+    u[2] += g[14 + i] * d;
+  }
+}
+
+// Impulses (dn, d1, d2) of the arm contact in colour c on the arm side sg:
+// dq += sg (dn M^-1 g_n + d1 M^-1 g_t1 + d2 M^-1 g_t2).
+__device__ __forceinline__ void arm_row_apply(const ArmCtx& A, int c, float sg, float dn, float d1, float d2) {
+  const float* w = A.rows + (long)c * kArmRowWords + 21;
+#pragma unroll
+  for (int i = 0; i < 7; i++) A.dq[i] += sg * (dn * w[i] + d1 * w[7 + i] + d2 * w[14 + i]);
+}
+
 // One Gauss-Seidel update at colour-major position i: the normal row, then
 // both friction rows from the velocities after the normal impulse (through
 // the couplings k_1n, k_2n), then the contact's total impulse.  Returns the
 // residual max |dlambda| * k.
-__device__ __forceinline__ float pgs_update(const LdsLayout& L, Smem S, const Rec& R, int i) {
+__device__ __forceinline__ float pgs_update(const LdsLayout& L, Smem S, const Rec& R, int i, const ArmCtx& arm,
+                                           int c) {
   const int a = rec_a(R), b = rec_b(R);
   const float4 lam = ld4(S.f + L.lam, i);
   Vel A = load_vel(L, S, a);
@@ -528,13 +575,23 @@ __device__ __forceinline__ float pgs_update(const LdsLayout& L, Smem S, const Re
   V3 t1, t2;
   tangents_coef(n, R.r[4].z, t1, t2);
   const V3 dv = point_vel(A.v, A.w, B.v, B.w, ra, rb);
-  const float ln = fmaxf(0.f, lam.x + mn * (bias - dot(n, dv)));
+  float un = dot(n, dv), u1 = dot(t1, dv), u2 = dot(t2, dv);
+  const float asg = arm.on ? R.r[4].y : 0.f;  // arm side of the contact (0: none)
+  if (asg != 0.f) {
+    float ua[3];
+    arm_row_vel(arm, c, ua);
+    un += asg * ua[0];
+    u1 += asg * ua[1];
+    u2 += asg * ua[2];
+  }
+  const float ln = fmaxf(0.f, lam.x + mn * (bias - un));
   const float dn = ln - lam.x;
-  float l1 = lam.y - m1 * (dot(t1, dv) + k1n * dn);
-  float l2 = lam.z - m2 * (dot(t2, dv) + k2n * dn);
+  float l1 = lam.y - m1 * ((u1 + R.r[4].w) + k1n * dn);
+  float l2 = lam.z - m2 * ((u2 + lam.w) + k2n * dn);
   proj_disk(l1, l2, mu * ln);
   const float d1 = l1 - lam.y, d2 = l2 - lam.z;
   apply_impulse(A, B, ra, rb, n * dn + t1 * d1 + t2 * d2);
+  if (asg != 0.f) arm_row_apply(arm, c, asg, dn, d1, d2);
   store_vel_dyn(L, S, a, A);
   store_vel_dyn(L, S, b, B);
   st4(S.f + L.lam, i, make_float4(ln, l1, l2, lam.w));
@@ -553,9 +610,12 @@ __device__ __forceinline__ float pair_swap(float x) {
 // lanes hold the same row velocities (the addition commutes exactly), take
 // the same impulse step and apply it to their own body only.  Halves the
 // dependent work of one update; used for colours of at most 32 contacts.
-__device__ __forceinline__ float pgs_update_pair(const LdsLayout& L, Smem S, const Rec& R, int i, int side) {
+__device__ __forceinline__ float pgs_update_pair(const LdsLayout& L, Smem S, const Rec& R, int i, int side,
+                                                const ArmCtx& arm, int c) {
   const int me = side ? rec_b(R) : rec_a(R);
   const float sg = side ? -1.f : 1.f;
+  // the lane of the arm link's side also holds the arm's part
+  const bool arm_lane = arm.on && R.r[4].y == sg;
   const float4 lam = ld4(S.f + L.lam, i);
   Vel M = load_vel(L, S, me);
   const V3 n = xyz(R.r[0]), r = side ? xyz(R.r[2]) : xyz(R.r[1]);
@@ -564,8 +624,16 @@ __device__ __forceinline__ float pgs_update_pair(const LdsLayout& L, Smem S, con
   V3 t1, t2;
   tangents_coef(n, R.r[4].z, t1, t2);
   const V3 pv = M.v + cross(M.w, r);
-  const float cn = sg * dot(n, pv), c1 = sg * dot(t1, pv), c2 = sg * dot(t2, pv);
-  const float un = cn + pair_swap(cn), u1 = c1 + pair_swap(c1), u2 = c2 + pair_swap(c2);
+  float cn = sg * dot(n, pv), c1 = sg * dot(t1, pv), c2 = sg * dot(t2, pv);
+  if (arm_lane) {
+    float ua[3];
+    arm_row_vel(arm, c, ua);
+    cn += sg * ua[0];
+    c1 += sg * ua[1];
+    c2 += sg * ua[2];
+  }
+  const float un = cn + pair_swap(cn);
+  const float u1 = (c1 + pair_swap(c1)) + R.r[4].w, u2 = (c2 + pair_swap(c2)) + lam.w;
   const float ln = fmaxf(0.f, lam.x + mn * (bias - un));
   const float dn = ln - lam.x;
   float l1 = lam.y - m1 * (u1 + k1n * dn);
@@ -576,6 +644,7 @@ __device__ __forceinline__ float pgs_update_pair(const LdsLayout& L, Smem S, con
   M.v = M.v + P * M.im;
   M.w = M.w + Imul(M.I, cross(r, P));
   store_vel_dyn(L, S, me, M);
+  if (arm_lane) arm_row_apply(arm, c, sg, dn, d1, d2);
   if (!side) st4(S.f + L.lam, i, make_float4(ln, l1, l2, lam.w));
   return fmaxf(fmaxf(fabsf(dn) * frcp(mn), fabsf(d1) * frcp(m1)), fabsf(d2) * frcp(m2));
 }
@@ -605,16 +674,17 @@ __device__ __forceinline__ float start_objective(const LdsLayout& L, Smem S, con
   tangents_coef(n, R.r[4].z, t1, t2);
   const V3 dv0 = point_vel(va0, wa0, vb0, wb0, ra, rb), dv1 = point_vel(A1.v, A1.w, B1.v, B1.w, ra, rb);
   float f = lam.x * (0.5f * (dot(n, dv0) + dot(n, dv1)) - bias);
-  f += lam.y * 0.5f * (dot(t1, dv0) + dot(t1, dv1));
-  f += lam.z * 0.5f * (dot(t2, dv0) + dot(t2, dv1));
+  // (velocity changes since the setup: the friction rows add their setup velocity)
+  f += lam.y * (0.5f * (dot(t1, dv0) + dot(t1, dv1)) + R.r[4].w);
+  f += lam.z * (0.5f * (dot(t2, dv0) + dot(t2, dv1)) + lam.w);
   return f;
 }
 
 // Applies the current impulses of every contact, colour-major (warm start);
 // with `select` >= 0 only the contacts whose fresh bit equals it.
 template <class TM>
-__device__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int ncol, const uint32_t* cstart,
-                          const TM& tm, int select = -1) {
+__device__ __forceinline__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int ncol, const uint32_t* cstart,
+                          const TM tm, const ArmCtx& arm, int select = -1) {
   for (int c = 0; c < ncol; c++) {
     for (int i = (int)cstart[c] + tm.tid; i < (int)cstart[c + 1]; i += tm.T) {
       if (select >= 0 && (int)((S.u[L.fresh + (i >> 5)] >> (i & 31)) & 1u) != select) continue;
@@ -629,9 +699,49 @@ __device__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int nco
       apply_impulse(A, B, xyz(R.r[1]), xyz(R.r[2]), n * lam.x + t1 * lam.y + t2 * lam.z);
       store_vel_dyn(L, S, a, A);
       store_vel_dyn(L, S, b, B);
+      if (arm.on && R.r[4].y != 0.f) arm_row_apply(arm, c, R.r[4].y, lam.x, lam.y, lam.z);
     }
     colour_sync(tm);
   }
+}
+
+// ---- the articulated arm (arm 2) -----------------------------------------
+// The arm is one articulated body in reduced coordinates (an articulated
+// robot driven by joint motors under PD position control): its joint angles
+// and rates are the state, link poses follow the angles by the forward
+// kinematics and link velocities the rates through the link Jacobians, so
+// the joints hold exactly.  M(q) = sum over links j of Jv^T m_j Jv + Jw^T
+// I_j Jw (column i of link j's Jacobians: a_i x (c_j - o_i) and a_i, i <=
+// j); velocity-product terms are left out, like the free bodies' gyroscopic
+// term.  Gravity adds dt M^-1 tau_g to the rates.  A contact row d at p on
+// link j acts on the rates through g_i = d . (a_i x (p - o_i)), i <= j.
+// Motor k is the row on rate k with target Kp (target_k - theta_k) / dt
+// (the error wrapped into [-pi, pi]), effective mass 1 / (M^-1)_kk and its
+// impulse bounded by motor_max; the motors are swept after the contacts.
+// The solve works on the rates' changes since the setup (dq), like the free
+// bodies' velocities, so the motor rows' targets are less the setup rates.
+
+// One Gauss-Seidel pass over the 7 motor rows by wave 0 (lane i holds rate
+// change i); returns the pass's max |dlambda| (M^-1)_kk on every lane.
+template <class TM>
+__device__ __forceinline__ float arm_motor_sweep(const LdsLayout& L, Smem S, const TM tm, float lim) {
+  float* arm = S.f + L.arm;
+  const int lane = tm.tid & 63;
+  float dq = lane < 7 ? arm[ARM_DQ + lane] : 0.f;
+  float r = 0.f;
+#pragma unroll
+  for (int k = 0; k < 7; k++) {
+    const float u = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dq), k));
+    const float kk = arm[ARM_MI + 8 * k];
+    const float l0 = arm[ARM_LAM + k];
+    const float l = fminf(fmaxf(l0 + (arm[ARM_BIAS + k] - u) / kk, -lim), lim);
+    const float dl = l - l0;
+    if (lane == 0) arm[ARM_LAM + k] = l;
+    if (lane < 7) dq += dl * arm[ARM_MI + 7 * lane + k];
+    r = fmaxf(r, fabsf(dl) * kk);
+  }
+  if (lane < 7) arm[ARM_DQ + lane] = dq;
+  return r;
 }
 
 // Sweeps of projected Gauss-Seidel, colour batch after colour batch; the
@@ -640,11 +750,32 @@ __device__ void apply_all(const LdsLayout& L, Smem S, const float4* rec, int nco
 // kPairs: small colours by lane pairs (off where the network's registers
 // leave no room for the second update's code).
 template <bool kPairs, class TM>
-__device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int ncol, const uint32_t* cstart, int iters,
-                          float tol, uint32_t* misc, int* sweeps_out, float* res_out, const TM& tm) {
+__device__ __forceinline__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int ncol, const uint32_t* cstart, int iters,
+                          float tol, uint32_t* misc, int* sweeps_out, float* res_out, const TM tm,
+                          const ArmCtx& arm, float motor_max) {
   const int tid = tm.tid, T = tm.T;
   int sweeps = 0;
   float res = 0.f;
+  // the arm's motor rows after the contacts of every sweep (wave 0)
+  auto motors = [&]() __attribute__((always_inline)) -> float {
+    float rm = 0.f;
+    if (tid < 64) rm = arm_motor_sweep(L, S, tm, motor_max);
+    colour_sync(tm);
+    return rm;
+  };
+  if (ncol == 0 && arm.on) {  // motor rows only
+    for (int it = 0; it < iters; it++) {
+      const float r = motors();
+      sweeps++;
+      if (tol > 0.f || it == iters - 1) {
+        res = block_max(r, misc, tm);
+        if (tol > 0.f && res <= tol) break;
+      }
+    }
+    *sweeps_out = sweeps;
+    *res_out = res;
+    return;
+  }
   if (ncol == 0) {
     // no rows: every sweep has residual 0, so a tolerance stops after the
     // first one and a fixed count runs all of them (as empty sweeps)
@@ -691,10 +822,10 @@ __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int nco
       const bool hnext = inext < cst(cn + 1);
       nxt = load_rec(rec, min(inext, last));
       if (kPairs && pair) {
-        if (has) r = fmaxf(r, pgs_update_pair(L, S, cur, i, tid & 1));
+        if (has) r = fmaxf(r, pgs_update_pair(L, S, cur, i, tid & 1, arm, c));
       } else {
-        if (has) r = fmaxf(r, pgs_update(L, S, cur, i));
-        for (int i2 = i + T; i2 < e; i2 += T) r = fmaxf(r, pgs_update(L, S, load_rec(rec, i2), i2));
+        if (has) r = fmaxf(r, pgs_update(L, S, cur, i, arm, c));
+        for (int i2 = i + T; i2 < e; i2 += T) r = fmaxf(r, pgs_update(L, S, load_rec(rec, i2), i2, arm, c));
       }
       colour_sync(tm);
       has = hnext;
@@ -713,6 +844,7 @@ __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int nco
         batch(c, ra, rb);
         ra = rb;
       }
+      if (arm.on) r = fmaxf(r, motors());
       sweeps++;
       if (tol > 0.f || it == iters - 1) {
         res = block_max(r, misc, tm);
@@ -730,9 +862,9 @@ __device__ void solve_pgs(const LdsLayout& L, Smem S, const float4* rec, int nco
 // scaled by 1/max(n_a, n_b) contacts per dynamic body (from the record),
 // applied colour-major.
 template <class TM>
-__device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int nb, int nc, int ncol,
+__device__ __forceinline__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int nb, int nc, int ncol,
                              const uint32_t* cstart, int iters, float tol, uint32_t* misc, int* sweeps_out,
-                             float* res_out, const TM& tm) {
+                             float* res_out, const TM tm) {
   const int tid = tm.tid, T = tm.T;
   float* snap = S.f + L.snap;
   int sweeps = 0;
@@ -761,8 +893,8 @@ __device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int 
       tangents_coef(n, R.r[4].z, t1, t2);
       const V3 dv = point_vel(va, wa, vb, wb, ra, rb);
       float ln = fmaxf(0.f, lam.x + sc * mn * (bias - dot(n, dv)));
-      float l1 = lam.y - sc * m1 * dot(t1, dv);
-      float l2 = lam.z - sc * m2 * dot(t2, dv);
+      float l1 = lam.y - sc * m1 * (dot(t1, dv) + R.r[4].w);
+      float l2 = lam.z - sc * m2 * (dot(t2, dv) + lam.w);
       proj_disk(l1, l2, mu * ln);
       float dn = ln - lam.x, d1 = l1 - lam.y, d2 = l2 - lam.z;
       st4(S.f + L.dl, i, make_float4(dn, d1, d2, 0.f));
@@ -798,11 +930,12 @@ __device__ void solve_jacobi(const LdsLayout& L, Smem S, const float4* rec, int 
 
 // Arm link poses (and, if thd, link velocities) into the LDS records of
 // bodies b0..b0+6.
-__device__ void arm_fk(const StepParams& P, const LdsLayout& L, Smem S, int b0, const float* base, const float* th,
-                       const float* thd) {
+__device__ __forceinline__ void arm_fk(const StepParams& P, const LdsLayout& L, Smem S, int b0, const float* base,
+                                       const float* th, const float* thd) {
   V3 c[7], o[7], ax[7];
   float q[7][4];
   arm_chain(base, th, P.link_len, c, q, o, ax);
+#pragma unroll
   for (int k = 0; k < 7; k++) {
     int bi = b0 + k;
     float meta = S.f[L.geo + 12 * bi + 3];
@@ -810,8 +943,10 @@ __device__ void arm_fk(const StepParams& P, const LdsLayout& L, Smem S, int b0, 
     st4(S.f + L.geo, 3 * bi + 1, make_float4(q[k][0], q[k][1], q[k][2], q[k][3]));
   }
   if (thd) {
+#pragma unroll
     for (int k = 0; k < 7; k++) {
       V3 wv = v3(0.f, 0.f, 0.f), vv = v3(0.f, 0.f, 0.f);
+#pragma unroll
       for (int j = 0; j <= k; j++) {
         wv = wv + ax[j] * thd[j];
         vv = vv + cross(ax[j], c[k] - o[j]) * thd[j];
@@ -824,13 +959,257 @@ __device__ void arm_fk(const StepParams& P, const LdsLayout& L, Smem S, int b0, 
   }
 }
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Setup of the arm by wave 0: joint origins and axes, M^-1 (M from the link
+// Jacobians, then Cholesky), the rates after gravity (the setup rates), the
+// motor targets moved by dt times the commanded rates, the motor rows'
+// targets and warm start; the rate changes start at zero.  Link poses at
+// the step's angles are in LDS; masses and principal inverse inertias of
+// the links in global memory.
+__device__ __forceinline__ void arm_setup(const StepParams& P, const LdsLayout& L, Smem S, int s, long g0, int l0, float dt, V3 g,
+                          int lane) {
+  float* arm = S.f + L.arm;
+  if (lane == 0) {
+    V3 c[7], o[7], ax[7];
+    float q[7][4];
+    arm_chain(P.arm_base + 3 * s, P.theta + 7 * s, P.link_len, c, q, o, ax);
+#pragma unroll
+    for (int k = 0; k < 7; k++) {
+      arm[ARM_O + 3 * k] = o[k].x; arm[ARM_O + 3 * k + 1] = o[k].y; arm[ARM_O + 3 * k + 2] = o[k].z;
+      arm[ARM_AX + 3 * k] = ax[k].x; arm[ARM_AX + 3 * k + 1] = ax[k].y; arm[ARM_AX + 3 * k + 2] = ax[k].z;
+    }
+  }
+  wave_sync();
+  auto o_of = [&](int k) { return v3(arm[ARM_O + 3 * k], arm[ARM_O + 3 * k + 1], arm[ARM_O + 3 * k + 2]); };
+  auto ax_of = [&](int k) { return v3(arm[ARM_AX + 3 * k], arm[ARM_AX + 3 * k + 1], arm[ARM_AX + 3 * k + 2]); };
+  // M, one entry per lane (row-major): links j >= max(i, k) contribute
+  // m_j (a_i x (c_j - o_i)) . (a_k x (c_j - o_k)) + a_i . I_j a_k
+  if (lane < 49) {
+    const int i = lane / 7, k = lane - 7 * (lane / 7);
+    const V3 oi = o_of(i), ai = ax_of(i), ok = o_of(k), ak = ax_of(k);
+    float m = 0.f;
+    for (int j = i > k ? i : k; j < 7; j++) {
+      const long gj = g0 + l0 + j;
+      const V3 cj = xyz(ld4(S.f + L.geo, 3 * (l0 + j)));
+      const float4 qj = ld4(S.f + L.geo, 3 * (l0 + j) + 1);
+      const M3 R = quat_R(qj.x, qj.y, qj.z, qj.w);
+      const V3 bi = RTv(R, ai), bk = RTv(R, ak);
+      const long N = P.n_bodies;
+      m += (1.0f / P.inv_mass[gj]) * dot(cross(ai, cj - oi), cross(ak, cj - ok)) +
+           bi.x * bk.x / P.inv_inertia[gj] + bi.y * bk.y / P.inv_inertia[N + gj] +
+           bi.z * bk.z / P.inv_inertia[2 * N + gj];
+    }
+    arm[ARM_MI + lane] = m;
+  }
+  wave_sync();
+  if (lane == 0) {  // Cholesky factor and inverse, in registers (indices fixed by unrolling)
+    float Lc[7][7];
+#pragma unroll
+    for (int i = 0; i < 7; i++) {
+#pragma unroll
+      for (int k = 0; k <= i; k++) {
+        float sum = arm[ARM_MI + 7 * i + k];
+#pragma unroll
+        for (int t = 0; t < k; t++) sum -= Lc[i][t] * Lc[k][t];
+        Lc[i][k] = i == k ? sqrtf(sum) : sum / Lc[k][k];
+      }
+    }
+#pragma unroll
+    for (int col = 0; col < 7; col++) {
+      float y[7], x[7];
+#pragma unroll
+      for (int i = 0; i < 7; i++) {
+        float sum = i == col ? 1.f : 0.f;
+#pragma unroll
+        for (int t = 0; t < i; t++) sum -= Lc[i][t] * y[t];
+        y[i] = sum / Lc[i][i];
+      }
+#pragma unroll
+      for (int i = 6; i >= 0; i--) {
+        float sum = y[i];
+#pragma unroll
+        for (int t = i + 1; t < 7; t++) sum -= Lc[t][i] * x[t];
+        x[i] = sum / Lc[i][i];
+      }
+#pragma unroll
+      for (int i = 0; i < 7; i++) arm[ARM_MI + 7 * i + col] = x[i];
+    }
+  }
+  wave_sync();
+  // gravity moments about the joint axes, then the setup rates
+  if (lane < 7) {
+    const V3 oi = o_of(lane), ai = ax_of(lane);
+    V3 t = v3(0.f, 0.f, 0.f);
+    for (int j = lane; j < 7; j++) {
+      const V3 cj = xyz(ld4(S.f + L.geo, 3 * (l0 + j)));
+      t = t + cross(cj - oi, g * (1.0f / P.inv_mass[g0 + l0 + j]));
+    }
+    arm[ARM_BIAS + lane] = dot(ai, t);
+  }
+  wave_sync();
+  float* st = P.arm_state + 21 * s;
+  float qref = 0.f;
+  if (lane < 7) {
+    float a = 0.f;
+#pragma unroll
+    for (int k = 0; k < 7; k++) a += arm[ARM_MI + 7 * lane + k] * arm[ARM_BIAS + k];
+    qref = st[lane] + dt * a;
+  }
+  wave_sync();
+  if (lane < 7) {
+    arm[ARM_QREF + lane] = qref;
+    arm[ARM_DQ + lane] = 0.f;
+    const float tgt = st[7 + lane] + dt * (P.actions ? P.actions[7 * s + lane] : 0.f);
+    st[7 + lane] = tgt;
+    float err = tgt - P.theta[7 * s + lane];
+    err -= 6.28318530717958647692f * rintf(err * 0.15915494309189533577f);
+    arm[ARM_BIAS + lane] = P.motor_kp * err / dt - qref;
+    arm[ARM_LAM + lane] = P.warm == WARM_COLD ? 0.f : fminf(fmaxf(st[14 + lane], -P.motor_max), P.motor_max);
+  }
+  wave_sync();
+}
+
+// Motor warm start (wave 0): dq += sum_k lambda_k M^-1 e_k.
+__device__ __forceinline__ void arm_motor_warm(const LdsLayout& L, Smem S, int lane) {
+  float* arm = S.f + L.arm;
+  if (lane < 7) {
+    float a = 0.f;
+#pragma unroll
+    for (int k = 0; k < 7; k++) a += arm[ARM_MI + 7 * lane + k] * arm[ARM_LAM + k];
+    arm[ARM_DQ + lane] += a;
+  }
+  wave_sync();
+}
+
+// Joint-space rows of a contact on arm link j (directions n, t1, t2 at
+// point p, arm side sg): g and M^-1 g to the colour's slot in global
+// memory; returns g . M^-1 g per row (k_add), the normal-friction couplings
+// g_t . M^-1 g_n (c_add) and the rows' velocities sg g . qref (u_add).
+__device__ __forceinline__ void arm_contact_rows(const LdsLayout& L, Smem S, float* slot, int j, V3 p, const V3* dirs, float sg,
+                                 float* k_add, float* c_add, float* u_add) {
+  const float* arm = S.f + L.arm;
+  float w0[7];
+#pragma unroll
+  for (int r = 0; r < 3; r++) {
+    float gr[7];
+#pragma unroll
+    for (int i = 0; i < 7; i++) {
+      const V3 oi = v3(arm[ARM_O + 3 * i], arm[ARM_O + 3 * i + 1], arm[ARM_O + 3 * i + 2]);
+      const V3 ai = v3(arm[ARM_AX + 3 * i], arm[ARM_AX + 3 * i + 1], arm[ARM_AX + 3 * i + 2]);
+      gr[i] = i <= j ? dot(dirs[r], cross(ai, p - oi)) : 0.f;
+      slot[7 * r + i] = gr[i];
+    }
+    float kk = 0.f, uu = 0.f, cc = 0.f;
+#pragma unroll
+    for (int i = 0; i < 7; i++) {
+      float w = 0.f;
+#pragma unroll
+      for (int k = 0; k < 7; k++) w += arm[ARM_MI + 7 * i + k] * gr[k];
+      slot[21 + 7 * r + i] = w;
+      kk += gr[i] * w;
+      uu += gr[i] * arm[ARM_QREF + i];
+      if (r == 0) w0[i] = w;
+      else cc += gr[i] * w0[i];
+    }
+    k_add[r] = kk;
+    u_add[r] = sg * uu;
+    if (r > 0) c_add[r - 1] = cc;
+  }
+}
+
 // One step of scene s by team tm, its working set in the LDS at S laid
 // out by L.
 // kLearned: the learned warm start (P.warm == WARM_LEARNED) is compiled in;
 // the other modes use an instantiation without the network's registers.
+// Sleeping islands (localized physics): islands are the sets of dynamic
+// bodies joined by this step's contacts between two dynamic bodies, found by
+// minimum-label propagation with hooking and pointer jumping (a body's label
+// ends as the least index in its island, whatever order the updates take; a
+// label never exceeds its body's index, so every chain of labels ends).  An
+// island sleeps when every body in it has ended sleep_steps steps at rest and
+// none of them touches a kinematic body; a sleeping body gets the asleep bit
+// in its meta word and zero velocity, and counts as not dynamic for the
+// colouring, the solve and the integration.  Uses the colouring's per-body
+// scratch (deg, lstart), which is free until the colouring starts.
+template <class TM>
+__device__ __forceinline__ void sleep_islands(const StepParams& P, const LdsLayout& L, Smem S, long b0, int nb, int nc,
+                              uint32_t* misc, const TM tm) {
+  const int tid = tm.tid, T = tm.T;
+  uint32_t* lab = S.u + L.deg;
+  uint32_t* wake = S.u + L.lstart;
+  const uint32_t* ckeys = S.u + L.ckey;
+  for (int i = tid; i < nb; i += T) {
+    lab[i] = (uint32_t)i;
+    wake[i] = 0u;
+  }
+  team_sync(tm);
+  for (int round = 0; round <= nb; round++) {
+    if (tid == 0) misc[M_CHANGED] = 0u;
+    team_sync(tm);
+    bool changed = false;
+    for (int q = tid; q < nc; q += T) {
+      const uint32_t key = ckeys[q];
+      const int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
+      if (b == (int)kGroundKey || !is_dyn_meta(body_meta(L, S, a)) || !is_dyn_meta(body_meta(L, S, b))) continue;
+      const uint32_t la = lab[a], lb = lab[b];
+      if (la != lb) {
+        const uint32_t m = la < lb ? la : lb;
+        atomicMin(&lab[a], m);
+        atomicMin(&lab[b], m);
+        atomicMin(&lab[la], m);
+        atomicMin(&lab[lb], m);
+        changed = true;
+      }
+    }
+    if (changed) misc[M_CHANGED] = 1u;
+    team_sync(tm);
+    for (int i = tid; i < nb; i += T) {
+      uint32_t x = lab[i];
+      while (lab[x] != x) x = lab[x];
+      lab[i] = x;
+    }
+    team_sync(tm);
+    if (misc[M_CHANGED] == 0u) break;
+    team_sync(tm);
+  }
+  for (int i = tid; i < nb; i += T)
+    if (is_dyn_meta(body_meta(L, S, i)) && P.rest[b0 + i] < P.sleep_steps) wake[lab[i]] = 1u;
+  for (int q = tid; q < nc; q += T) {
+    const uint32_t key = ckeys[q];
+    const int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
+    if (b == (int)kGroundKey) continue;
+    const uint32_t ma = body_meta(L, S, a), mb = body_meta(L, S, b);
+    // the arm (kinematic or articulated) wakes what it touches
+    const uint32_t ka = (ma >> 8) & 255u, kb = (mb >> 8) & 255u;
+    if ((ka == KINEMATIC || ka == ARMLINK) && is_dyn_meta(mb)) wake[lab[b]] = 1u;
+    if ((kb == KINEMATIC || kb == ARMLINK) && is_dyn_meta(ma)) wake[lab[a]] = 1u;
+  }
+  team_sync(tm);
+  for (int i = tid; i < nb; i += T) {
+    const uint32_t meta = body_meta(L, S, i);
+    if (!is_dyn_meta(meta) || wake[lab[i]]) continue;
+    S.f[L.geo + 12 * i + 3] = __uint_as_float(meta | kAsleepBit);
+    const float4 v = ld4(S.f + L.dyn, 3 * i), w = ld4(S.f + L.dyn, 3 * i + 1);
+    st4(S.f + L.dyn, 3 * i, make_float4(0.f, 0.f, 0.f, v.w));
+    st4(S.f + L.dyn, 3 * i + 1, make_float4(0.f, 0.f, 0.f, w.w));
+  }
+  team_sync(tm);
+}
+
+// A dynamic body's linear velocity at the setup: the state's, plus gravity
+// over the step (read again after the solve, which kept only the change).
+__device__ __forceinline__ V3 setup_lin_vel(const StepParams& P, long gi, long N, V3 g, float dt) {
+  return v3(P.vel[gi], P.vel[N + gi], P.vel[2 * N + gi]) + g * dt;
+}
+
 template <bool kLearned, class TM>
 __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout& L, Smem S, const int s,
-                                           const TM& tm) {
+                                           const TM tm) {
   const int tid = tm.tid, T = tm.T;
   const int b0 = P.body_offset[s];
   const int nb = P.body_offset[s + 1] - b0;
@@ -851,9 +1230,14 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
 
   // ---- load bodies; a2: gravity, world inverse inertia -----------------
   const V3 g = v3(P.gx, P.gy, P.gz);
+  // the articulated arm (not compiled into the learned kernels)
+  bool arm2 = false;
+  if constexpr (!kLearned) arm2 = P.arm == 2;
+  const int arm0 = arm2 ? nb - 7 : nb;  // its first link
   for (int i = tid; i < nb; i += T) {
     const long gi = b0 + i;
     int shape = P.shape[gi], motion = P.motion[gi];
+    if (arm2 && i >= arm0) motion = ARMLINK;  // moved by the arm's joint rates
     uint32_t meta = (uint32_t)shape | ((uint32_t)motion << 8);
     V3 x = v3(P.pose[gi], P.pose[N + gi], P.pose[2 * N + gi]);
     float qw = P.pose[3 * N + gi], qx = P.pose[4 * N + gi], qy = P.pose[5 * N + gi], qz = P.pose[6 * N + gi];
@@ -867,7 +1251,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     if (motion == DYNAMIC) {
       M3 R = quat_R(qw, qx, qy, qz);
       im = P.inv_mass[gi];
-      v = v + g * dt;
+      v = setup_lin_vel(P, gi, N, g, dt);
       float i0 = P.inv_inertia[gi], i1 = P.inv_inertia[N + gi], i2 = P.inv_inertia[2 * N + gi];
       // R diag(i) R^T
       I[0] = R.m[0][0] * R.m[0][0] * i0 + R.m[0][1] * R.m[0][1] * i1 + R.m[0][2] * R.m[0][2] * i2;
@@ -876,7 +1260,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       I[3] = R.m[0][0] * R.m[1][0] * i0 + R.m[0][1] * R.m[1][1] * i1 + R.m[0][2] * R.m[1][2] * i2;
       I[4] = R.m[0][0] * R.m[2][0] * i0 + R.m[0][1] * R.m[2][1] * i1 + R.m[0][2] * R.m[2][2] * i2;
       I[5] = R.m[1][0] * R.m[2][0] * i0 + R.m[1][1] * R.m[2][1] * i1 + R.m[1][2] * R.m[2][2] * i2;
-    } else if (motion == STATIC) {
+    } else if (motion == STATIC || motion == ARMLINK) {
       v = v3(0.f, 0.f, 0.f);
       w = v3(0.f, 0.f, 0.f);
     }
@@ -895,8 +1279,15 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   if (P.arm) {
 #pragma unroll
     for (int k = 0; k < 7; k++) thd[k] = P.actions ? P.actions[7 * s + k] : 0.f;
-    if (tid == 0) arm_fk(P, L, S, nb - 7, P.arm_base + 3 * s, P.theta + 7 * s, thd);
+    if (tid == 0) {  // (two calls: a selected array pointer would put the array in scratch)
+      if (arm2) arm_fk(P, L, S, nb - 7, P.arm_base + 3 * s, P.theta + 7 * s, nullptr);
+      else arm_fk(P, L, S, nb - 7, P.arm_base + 3 * s, P.theta + 7 * s, thd);
+    }
     team_sync(tm);
+    if (arm2) {
+      if (tid < 64) arm_setup(P, L, S, s, b0, arm0, dt, g, tid);
+      team_sync(tm);
+    }
   }
 
   // ---- a3: AABBs and sort keys ------------------------------------------
@@ -922,7 +1313,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       hi = v3(fmaxf(e0.x, e1.x) + r, fmaxf(e0.y, e1.y) + r, fmaxf(e0.z, e1.z) + r);
     }
     uint32_t meta = body_meta(L, S, i);
-    st4(S.f + L.lo, i, f4(lo, is_dyn_meta(meta) ? 1.f : 0.f));
+    st4(S.f + L.lo, i, f4(lo, is_dyn_meta(meta) ? 1.f : (((meta >> 8) & 255u) == ARMLINK ? 2.f : 0.f)));
     st4(S.f + L.hi, i, f4(hi, 0.f));
     S.u[L.skey + i] = orderable(lo.x);
     S.u[L.sval + i] = (uint32_t)i;
@@ -986,7 +1377,8 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
         }
         const int j = (int)order[q++];
         const float4 loj = ld4(S.f + L.lo, j);
-        if (loi.w == 0.f && loj.w == 0.f) continue;  // neither body is dynamic
+        if (loi.w == 0.f && loj.w == 0.f) continue;  // neither body moves
+        if (loi.w == 2.f && loj.w == 2.f) continue;  // two links of the arm: joined, not in contact
         const float4 hij = ld4(S.f + L.hi, j);
         if (loj.y <= hii.y && loi.y <= hij.y && loj.z <= hii.z && loi.z <= hij.z) {
           int a = i < j ? i : j, bb = i < j ? j : i;
@@ -995,7 +1387,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
         }
       }
     }
-    // ground pairs of dynamic bodies reaching z <= 0
+    // ground pairs of dynamic bodies and arm links reaching z <= 0
     for (int i = tid; i < nb; i += T) {
       const float4 loi = ld4(S.f + L.lo, i);
       if (loi.w != 0.f && loi.z <= 0.f) {
@@ -1175,6 +1567,11 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   TRACE(6);
   const int nc_all = (int)misc[M_NCONT];
   const int nc = nc_all < CMs ? nc_all : CMs;
+  // sleeping islands (not compiled into the learned kernels, whose registers
+  // are at their limit: the library refuses sleeping with the learned start)
+  if constexpr (!kLearned) {
+    if (P.sleep_speed > 0.f) sleep_islands(P, L, S, b0, nb, nc, misc, tm);
+  }
 
   // ---- a9: colouring -----------------------------------------------------
   uint32_t* deg = S.u + L.deg;
@@ -1219,14 +1616,19 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     }
     team_sync(tm);
   }
-  // per-body lists of contacts (dynamic bodies only), canonical order
+  // per-body lists of contacts (awake dynamic bodies only, and the
+  // articulated arm as one body: its links share the list of its first
+  // link, since every contact on the arm moves the same joint rates),
+  // canonical order
+  auto cbody = [&](int i) { return i >= arm0 ? arm0 : i; };
+  auto conflicts = [&](int i) { return i >= arm0 || is_awake_meta(body_meta(L, S, i)); };
   for (int i = tid; i <= nb; i += T) deg[i] = 0u;
   team_sync(tm);
   for (int q = tid; q < nc; q += T) {
     uint32_t key = ckeys[q];
     int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
-    if (is_dyn_meta(body_meta(L, S, a))) atomicAdd(&deg[a], 1u);
-    if (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) atomicAdd(&deg[b], 1u);
+    if (conflicts(a)) atomicAdd(&deg[cbody(a)], 1u);
+    if (b != (int)kGroundKey && conflicts(b)) atomicAdd(&deg[cbody(b)], 1u);
   }
   team_sync(tm);
   for (int i = tid; i <= nb; i += T) lstart[i] = i < nb ? deg[i] : 0u;
@@ -1239,8 +1641,8 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   for (int q = tid; q < nc; q += T) {
     uint32_t key = ckeys[q];
     int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
-    if (is_dyn_meta(body_meta(L, S, a))) list[lstart[a] + atomicAdd(&deg[a], 1u)] = (uint32_t)q;
-    if (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) list[lstart[b] + atomicAdd(&deg[b], 1u)] = (uint32_t)q;
+    if (conflicts(a)) list[lstart[cbody(a)] + atomicAdd(&deg[cbody(a)], 1u)] = (uint32_t)q;
+    if (b != (int)kGroundKey && conflicts(b)) list[lstart[cbody(b)] + atomicAdd(&deg[cbody(b)], 1u)] = (uint32_t)q;
     rank[q] = 0u;
   }
   team_sync(tm);
@@ -1260,7 +1662,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     uint32_t r = 0u;
     for (uint32_t y = s0; y < e0; y++) r += list[y] < v ? 1u : 0u;
     // both bodies of a contact write its rank word: combine atomically
-    atomicOr(&rank[v], (int)(ckeys[v] >> 20) == lo ? r : r << 16);
+    atomicOr(&rank[v], cbody((int)(ckeys[v] >> 20)) == lo ? r : r << 16);
   }
   team_sync(tm);
   TRACE(7);
@@ -1277,13 +1679,13 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     const uint32_t key = ckeys[q];
     const int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
     const uint32_t rk = rank[q];
-    if (is_dyn_meta(body_meta(L, S, a))) list[lstart[a] + (rk & 0xFFFFu)] = colour[q];
-    if (b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b))) list[lstart[b] + (rk >> 16)] = colour[q];
+    if (conflicts(a)) list[lstart[cbody(a)] + (rk & 0xFFFFu)] = colour[q];
+    if (b != (int)kGroundKey && conflicts(b)) list[lstart[cbody(b)] + (rk >> 16)] = colour[q];
   }
   team_sync(tm);
   for (int c0 = 0; c0 < nc; c0 += T) {
     const int q = c0 + tid;
-    const bool valid = q < nc;
+    bool valid = q < nc;
     int la = 0, lb = 0;
     bool da = false, db = false;
     uint32_t sa = 0u, sb = 0u;
@@ -1291,12 +1693,18 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       const uint32_t key = ckeys[q];
       const int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
       const uint32_t rk = rank[q];
-      da = is_dyn_meta(body_meta(L, S, a));
-      db = b != (int)kGroundKey && is_dyn_meta(body_meta(L, S, b));
+      da = conflicts(a);
+      db = b != (int)kGroundKey && conflicts(b);
       la = da ? (int)(rk & 0xFFFFu) : 0;
       lb = db ? (int)(rk >> 16) : 0;
-      sa = da ? lstart[a] : 0u;
-      sb = db ? lstart[b] : 0u;
+      sa = da ? lstart[cbody(a)] : 0u;
+      sb = db ? lstart[cbody(b)] : 0u;
+      if constexpr (!kLearned) {  // (nothing sleeps in the learned kernels)
+        if (!da && !db) {  // every dynamic body of the contact sleeps: not solved
+          colour[q] = kSleepColour;
+          valid = false;
+        }
+      }
     }
     for (int round = 0; round <= T + 1; round++) {
       if (tid == 0) misc[M_CHANGED] = 0u;
@@ -1377,11 +1785,17 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   for (int i = tid; i < nc; i += T) {
     uint32_t c = scol[i];
     if (i == 0 || scol[i - 1] != c) cstart[c] = (uint32_t)i;
-    if (i == nc - 1) misc[M_NCOL] = c + 1;
+    // the last solved contact: colour count and solved-contact count
+    if (c < kSleepColour && (i == nc - 1 || scol[i + 1] >= kSleepColour)) {
+      misc[M_NCOL] = c + 1;
+      misc[M_NACT] = (uint32_t)(i + 1);
+    }
   }
   team_sync(tm);
   const int ncol = nc > 0 ? (int)misc[M_NCOL] : 0;
-  if (tid == 0) cstart[ncol] = (uint32_t)nc;
+  // contacts solved (the rest sleep), colour-major first
+  const int nact = kLearned ? nc : (nc > 0 ? (int)misc[M_NACT] : 0);
+  if (tid == 0) cstart[ncol] = (uint32_t)nact;
   team_sync(tm);
   TRACE(9);
 
@@ -1460,12 +1874,20 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     Row rw[3];
     V3 dirs[3] = {n, t1, t2};
     float k3[3];
+    // a contact on the articulated arm: its joint-space rows (to the colour's slot)
+    float asg = 0.f, ka[3] = {0.f, 0.f, 0.f}, kc[2] = {0.f, 0.f}, ua[3] = {0.f, 0.f, 0.f};
+    if (arm2) {
+      asg = a >= arm0 ? 1.f : (b >= arm0 ? -1.f : 0.f);
+      if (asg != 0.f && live)
+        arm_contact_rows(L, S, P.arm_rows + ((long)s * kMaxColours + colour[q]) * kArmRowWords,
+                         (asg > 0.f ? a : b) - arm0, p, dirs, asg, ka, kc, ua);
+    }
 #pragma unroll
     for (int r = 0; r < 3; r++) {
       rw[r].d = dirs[r];
       rw[r].ca = cross(c.ra, dirs[r]);
       rw[r].ia = Imul(A.I, rw[r].ca);
-      float k = A.im + dot(rw[r].ca, rw[r].ia);
+      float k = A.im + dot(rw[r].ca, rw[r].ia) + ka[r];
       if (b >= 0) {
         rw[r].cb = cross(c.rb, dirs[r]);
         rw[r].ib = Imul(B.I, rw[r].cb);
@@ -1477,8 +1899,13 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       k3[r] = k;
       rw[r].m = 1.0f / k;
     }
-    V3 vr = (A.v + cross(A.w, c.ra)) - (B.v + cross(B.w, c.rb));
+    const V3 pa = A.v + cross(A.w, c.ra), pb = B.v + cross(B.w, c.rb);
+    V3 vr = pa - pb;
+    if (asg != 0.f) vr = vr + n * ua[0] + t1 * ua[1] + t2 * ua[2];  // the arm link's point velocity
     float u0 = dot(n, vr);
+    // the rows' velocities from the dynamic bodies' velocities at the setup
+    // (the solve tracks velocity changes from here; kinematic bodies' stay)
+    const V3 vf = (A.im > 0.f ? pa : v3(0.f, 0.f, 0.f)) - (B.im > 0.f ? pb : v3(0.f, 0.f, 0.f));
     float bias = phi > 0.f ? -phi / dt : P.baumgarte / dt * fmaxf(0.f, -phi - P.slop);
     if (e > 0.f && u0 < -P.rest_thresh) bias = fmaxf(bias, -e * u0);
     // previous impulse (normal, and the friction impulse re-projected on the
@@ -1533,7 +1960,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
         }
       }
     }
-    if (P.warm == WARM_PREV) {
+    if (P.warm == WARM_PREV || i >= nact) {  // classic warm start, or a sleeping contact
       l0 = lp0; l1 = lp1; l2 = lp2;
     }
     // projection of the initial impulse
@@ -1546,68 +1973,85 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     if (live) {
       // normal-friction couplings: change of row d's velocity per unit normal impulse
       const float ims = A.im + B.im;
-      const float k1n = dot(t1, n) * ims + dot(rw[1].ca, rw[0].ia) + dot(rw[1].cb, rw[0].ib);
-      const float k2n = dot(t2, n) * ims + dot(rw[2].ca, rw[0].ia) + dot(rw[2].cb, rw[0].ib);
+      const float k1n = dot(t1, n) * ims + dot(rw[1].ca, rw[0].ia) + dot(rw[1].cb, rw[0].ib) + kc[0];
+      const float k2n = dot(t2, n) * ims + dot(rw[2].ca, rw[0].ia) + dot(rw[2].cb, rw[0].ib) + kc[1];
       const float m3[3] = {rw[0].m, rw[1].m, rw[2].m};
-      store_rec(rec, i, n, c.ra, c.rb, m3, k1n, k2n, bias, mu, key, jsc);
-      st4(S.f + L.lam, i, make_float4(l0, l1, l2, phi));
-      if (kLearned && hit < 0) atomicOr(S.u + L.fresh + (i >> 5), 1u << (i & 31));
+      // with the arm, the Jacobi scale's word holds the arm side (Jacobi is not used then)
+      store_rec(rec, i, n, c.ra, c.rb, m3, k1n, k2n, bias - (dot(n, vf) + ua[0]), mu, key, arm2 ? asg : jsc,
+                dot(t1, vf) + ua[1]);
+      st4(S.f + L.lam, i, make_float4(l0, l1, l2, dot(t2, vf) + ua[2]));
+      if (kLearned && hit < 0 && i < nact) atomicOr(S.u + L.fresh + (i >> 5), 1u << (i & 31));
+    }
+  }
+  team_sync(tm);
+  // the solve works on the dynamic bodies' velocity changes from here
+  for (int i = tid; i < nb; i += T) {
+    const float4 v = ld4(S.f + L.dyn, 3 * i), w = ld4(S.f + L.dyn, 3 * i + 1);
+    if (v.w > 0.f) {
+      st4(S.f + L.dyn, 3 * i, make_float4(0.f, 0.f, 0.f, v.w));
+      st4(S.f + L.dyn, 3 * i + 1, make_float4(0.f, 0.f, 0.f, w.w));
     }
   }
   team_sync(tm);
   TRACE(10);
 
   // ---- a8/a11: warm start and sweeps ------------------------------------
+  const ArmCtx armc{arm2, arm2 ? S.f + L.arm + ARM_DQ : nullptr,
+                    arm2 ? P.arm_rows + (long)s * kMaxColours * kArmRowWords : nullptr};
   // Learned start: persisting contacts' previous impulses are applied first,
   // then the network's impulses of the new contacts.  The plain solver
   // judges the network's part before any sweep: if it raises the solver's
   // objective it is dropped (the new contacts start from zero, the classic
   // warm start) and the step is flagged.
   if (kLearned) {
-    apply_all(L, S, rec, ncol, cstart, tm, 0);
+    apply_all(L, S, rec, ncol, cstart, tm, ArmCtx{false, nullptr, nullptr}, 0);
     team_sync(tm);
     for (int i = tid; i < nb; i += T) {
       st4(S.f + L.vsave, 2 * i, ld4(S.f + L.dyn, 3 * i));
       st4(S.f + L.vsave, 2 * i + 1, ld4(S.f + L.dyn, 3 * i + 1));
     }
     team_sync(tm);
-    apply_all(L, S, rec, ncol, cstart, tm, 1);
+    apply_all(L, S, rec, ncol, cstart, tm, ArmCtx{false, nullptr, nullptr}, 1);
     team_sync(tm);
     float* fval = S.f + L.fval;
-    for (int i = tid; i < nc; i += T) fval[i] = start_objective(L, S, rec, i);
+    for (int i = tid; i < nact; i += T) fval[i] = start_objective(L, S, rec, i);
     team_sync(tm);
     // fixed-shape tree sum: same result for any block size
     int width = 1;
-    while (width < nc) width <<= 1;
+    while (width < nact) width <<= 1;
     for (int half = width >> 1; half > 0; half >>= 1) {
       for (int i = tid; i < half; i += T)
-        if (i + half < nc) fval[i] += fval[i + half];
+        if (i + half < nact) fval[i] += fval[i + half];
       team_sync(tm);
     }
-    if (nc > 0 && fval[0] > 0.f) {  // uniform across the workgroup
+    if (nact > 0 && fval[0] > 0.f) {  // uniform across the workgroup
       if (tid == 0) misc[M_FLAGS] |= FLAG_FELLBACK;
       for (int i = tid; i < nb; i += T) {
         st4(S.f + L.dyn, 3 * i, ld4(S.f + L.vsave, 2 * i));
         st4(S.f + L.dyn, 3 * i + 1, ld4(S.f + L.vsave, 2 * i + 1));
       }
-      for (int i = tid; i < nc; i += T) {
+      for (int i = tid; i < nact; i += T) {
         if (!((S.u[L.fresh + (i >> 5)] >> (i & 31)) & 1u)) continue;
-        float phi = S.f[L.lam + 4 * i + 3];
-        st4(S.f + L.lam, i, make_float4(0.f, 0.f, 0.f, phi));
+        const float u2 = S.f[L.lam + 4 * i + 3];
+        st4(S.f + L.lam, i, make_float4(0.f, 0.f, 0.f, u2));
       }
     }
     team_sync(tm);
   } else if (P.warm == WARM_PREV) {
-    apply_all(L, S, rec, ncol, cstart, tm);
+    apply_all(L, S, rec, ncol, cstart, tm, armc);
+  }
+  if (arm2) {  // motor warm start after the contacts'
+    if (tid < 64) arm_motor_warm(L, S, tid);
+    team_sync(tm);
   }
   TRACE(11);
   int sweeps = 0;
   float res = 0.f;
   const uint64_t clk0 = P.trace ? clock64() : 0;
   if (P.solver == SOLVER_JACOBI)
-    solve_jacobi(L, S, rec, nb, nc, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res, tm);
+    solve_jacobi(L, S, rec, nb, nact, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res, tm);
   else
-    solve_pgs<!kLearned>(L, S, rec, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res, tm);
+    solve_pgs<!kLearned>(L, S, rec, ncol, cstart, P.iters, P.tol, misc, &sweeps, &res, tm, armc, P.motor_max);
   team_sync(tm);
   // a step counts as solved only once its residual reached the tolerance
   if (P.tol > 0.f && res > P.tol && tid == 0) misc[M_FLAGS] |= FLAG_NOT_CONVERGED;
@@ -1619,10 +2063,19 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   for (int i = tid; i < nb; i += T) {
     const long gi = b0 + i;
     uint32_t meta = body_meta(L, S, i);
-    if (is_dyn_meta(meta)) {
+    // asleep: pose kept, velocity zero, count kept (sleeping is not compiled
+    // into the learned kernels)
+    bool asleep = false;
+    if constexpr (!kLearned) asleep = is_dyn_meta(meta) && !is_awake_meta(meta);
+    if (asleep) {
+      for (int k = 0; k < 6; k++) P.vel[k * N + gi] = 0.f;
+    } else if (is_dyn_meta(meta)) {
       V3 x = xyz(ld4(S.f + L.geo, 3 * i));
       float4 qq = ld4(S.f + L.geo, 3 * i + 1);
       V3 v = xyz(ld4(S.f + L.dyn, 3 * i)), w = xyz(ld4(S.f + L.dyn, 3 * i + 1));
+      // the solve left the velocity change since the setup in the slot
+      v = setup_lin_vel(P, gi, N, g, dt) + v;
+      w = v3(P.vel[3 * N + gi], P.vel[4 * N + gi], P.vel[5 * N + gi]) + w;
       x = x + v * dt;
       float qw = qq.x, qx = qq.y, qy = qq.z, qz = qq.w;
       // q + dt/2 (0, w) (x) q
@@ -1638,6 +2091,14 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       P.pose[3 * N + gi] = qw; P.pose[4 * N + gi] = qx; P.pose[5 * N + gi] = qy; P.pose[6 * N + gi] = qz;
       P.vel[gi] = v.x; P.vel[N + gi] = v.y; P.vel[2 * N + gi] = v.z;
       P.vel[3 * N + gi] = w.x; P.vel[4 * N + gi] = w.y; P.vel[5 * N + gi] = w.z;
+      if (!kLearned && P.sleep_speed > 0.f) {  // at rest: speed and surface speed |w| r at most sleep_speed
+        const float4 g2 = ld4(S.f + L.geo, 3 * i + 2);
+        const uint32_t sh = meta & 255u;
+        const float rb = sh == SPHERE ? g2.x : (sh == BOX ? sqrtf(g2.x * g2.x + g2.y * g2.y + g2.z * g2.z) : g2.x + g2.y);
+        const bool at_rest = sqrtf(len2(v)) <= P.sleep_speed && sqrtf(len2(w)) * rb <= P.sleep_speed;
+        const int32_t r0 = P.rest[gi];
+        P.rest[gi] = at_rest ? (r0 < (1 << 30) ? r0 + 1 : r0) : 0;
+      }
       bool fin = isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z) &&
                  isfinite(w.x) && isfinite(w.y) && isfinite(w.z);
       if (!fin) atomicOr(&misc[M_FLAGS], (uint32_t)FLAG_NONFINITE);
@@ -1645,13 +2106,31 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   }
   team_sync(tm);  // every read of the arm links' LDS records is done
   if (P.arm && tid == 0) {
-    float th[7];
-    for (int k = 0; k < 7; k++) {
-      th[k] = P.theta[7 * s + k] + dt * thd[k];
-      P.theta[7 * s + k] = th[k];
+    float th[7], qd[7];
+    if (arm2) {  // the angles advance by the joint rates; links follow, moving at those rates
+      float* st = P.arm_state + 21 * s;
+      const float* arm = S.f + L.arm;
+#pragma unroll
+      for (int k = 0; k < 7; k++) {
+        qd[k] = arm[ARM_QREF + k] + arm[ARM_DQ + k];
+        th[k] = P.theta[7 * s + k] + dt * qd[k];
+        P.theta[7 * s + k] = th[k];
+        st[k] = qd[k];
+        st[14 + k] = arm[ARM_LAM + k];
+        if (!isfinite(qd[k])) atomicOr(&misc[M_FLAGS], (uint32_t)FLAG_NONFINITE);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 7; k++) {
+        th[k] = P.theta[7 * s + k] + dt * thd[k];
+        P.theta[7 * s + k] = th[k];
+        qd[k] = 0.f;
+      }
     }
-    // link velocities stay those of this step; poses move to theta_{t+1}
-    arm_fk(P, L, S, nb - 7, P.arm_base + 3 * s, th, nullptr);
+    // kinematic arm: link velocities stay those of this step; poses move to theta_{t+1}
+    if (arm2) arm_fk(P, L, S, nb - 7, P.arm_base + 3 * s, th, qd);
+    else arm_fk(P, L, S, nb - 7, P.arm_base + 3 * s, th, nullptr);
+#pragma unroll
     for (int k = 0; k < 7; k++) {
       int i = nb - 7 + k;
       long gi = b0 + i;
@@ -1666,7 +2145,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   TRACE(13);
 
   // ---- a13: cache, export, arm force, stats ------------------------------
-  const int arm0 = P.arm ? nb - 7 : nb;
+  const int arml = P.arm ? nb - 7 : nb;
   float* force = S.f + L.force;
   for (int i = tid; i < nc; i += T) {
     const int q = (int)perm[i];
@@ -1685,16 +2164,16 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     P.cur_lam[P.scene_cm + o] = F.x;
     P.cur_lam[2 * P.scene_cm + o] = F.y;
     P.cur_lam[3 * P.scene_cm + o] = F.z;
-    bool arm_c = a >= arm0 || (b != (int)kGroundKey && b >= arm0);
+    bool arm_c = a >= arml || (b != (int)kGroundKey && b >= arml);
     force[q] = arm_c ? sqrtf(len2(n * lam.x + F)) / dt : 0.f;
     if (P.export_on) {
       const long sc = P.scene_cm;
       V3 pt = xyz(raw[2 * q + 1]);
       P.x_normal[o] = n.x; P.x_normal[sc + o] = n.y; P.x_normal[2 * sc + o] = n.z;
       P.x_point[o] = pt.x; P.x_point[sc + o] = pt.y; P.x_point[2 * sc + o] = pt.z;
-      P.x_phi[o] = lam.w;
+      P.x_phi[o] = raw[2 * q].w;
       P.x_lambda[o] = lam.x; P.x_lambda[sc + o] = lam.y; P.x_lambda[2 * sc + o] = lam.z;
-      P.x_colour[o] = (int32_t)colour[q];
+      P.x_colour[o] = colour[q] == kSleepColour ? -1 : (int32_t)colour[q];
     }
   }
   team_sync(tm);
@@ -1762,7 +2241,7 @@ __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams
     const int s = Q.team[k];
     const int nb = P.body_offset[s + 1] - P.body_offset[s];
     const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), (int)blockDim.x >> 6, P.solver,
-                                   P.warm);
+                                   P.warm, P.arm);
     scene_step<kLearned>(P, L, Smem{lds, reinterpret_cast<uint32_t*>(lds)}, s, Team<false>{tid, (int)blockDim.x});
     __syncthreads();
   }
@@ -1775,7 +2254,7 @@ __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams
     if (k >= Q.n_wave) break;
     const int s = Q.wave[k];
     const int nb = P.body_offset[s + 1] - P.body_offset[s];
-    const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), 1, P.solver, P.warm);
+    const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), 1, P.solver, P.warm, P.arm);
     scene_step<kLearned>(P, L, Smem{mine, reinterpret_cast<uint32_t*>(mine)}, s, Team<true>{lane, 64});
   }
 }
@@ -1803,12 +2282,14 @@ __global__ void arm_pose_kernel(int S_, const int32_t* off, float* pose, long N,
 
 // Masked reset from a pool of K states: one workgroup per flagged scene
 // copies pool entry index[s] (pose [K][7][N], velocity [K][6][N], joint
-// angles [K][S][7]) into the scene and empties its contact cache; an entry
-// outside [0, K) leaves the scene as it is and flags it.
-__global__ void reset_kernel(const int32_t* off, const uint8_t* mask, float* pose, float* vel, long N, int S_,
-                             int K, const int32_t* index, const float* pool_pose, const float* pool_vel, float* theta,
-                             const float* pool_theta, int32_t* cache_count_a, int32_t* cache_count_b,
-                             int32_t* flags) {
+// angles [K][S][7]) into the scene and empties its contact cache; the
+// articulated arm's state (arm_state, may be null) restarts at rest with its
+// motor targets at the new angles; an entry outside [0, K) leaves the scene
+// as it is and flags it.
+__global__ void reset_kernel(const int32_t* off, const uint8_t* mask, float* pose, float* vel, int32_t* rest, long N,
+                             int S_, int K, const int32_t* index, const float* pool_pose, const float* pool_vel,
+                             float* theta, const float* pool_theta, int32_t* cache_count_a, int32_t* cache_count_b,
+                             int32_t* flags, float* arm_state) {
   const int s = blockIdx.x;
   if (!mask[s]) return;
   const int k = index ? index[s] : 0;
@@ -1822,9 +2303,17 @@ __global__ void reset_kernel(const int32_t* off, const uint8_t* mask, float* pos
   for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
     for (int c = 0; c < 7; c++) pose[c * N + i] = pp[c * N + i];
     for (int c = 0; c < 6; c++) vel[c * N + i] = pv[c * N + i];
+    rest[i] = 0;
   }
-  if (threadIdx.x < 7 && theta && pool_theta)
-    theta[7 * s + threadIdx.x] = pool_theta[(size_t)k * 7 * S_ + 7 * s + threadIdx.x];
+  if (threadIdx.x < 7 && theta && pool_theta) {
+    const float th = pool_theta[(size_t)k * 7 * S_ + 7 * s + threadIdx.x];
+    theta[7 * s + threadIdx.x] = th;
+    if (arm_state) {
+      arm_state[21 * s + threadIdx.x] = 0.f;
+      arm_state[21 * s + 7 + threadIdx.x] = th;
+      arm_state[21 * s + 14 + threadIdx.x] = 0.f;
+    }
+  }
   if (threadIdx.x == 0) {
     cache_count_a[s] = 0;
     cache_count_b[s] = 0;
@@ -1890,7 +2379,7 @@ extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, i
                                 const float* pool_pose, const float* pool_vel, const float* pool_theta,
                                 int32_t* count_a, int32_t* count_b, hipStream_t stream) {
   hipLaunchKernelGGL(rbs::reset_kernel, dim3(P->num_scenes), dim3(128), 0, stream, P->body_offset, mask, P->pose,
-                     P->vel, P->n_bodies, P->num_scenes, K, index, pool_pose, pool_vel, P->theta, pool_theta, count_a,
-                     count_b, P->st_flags);
+                     P->vel, P->rest, P->n_bodies, P->num_scenes, K, index, pool_pose, pool_vel, P->theta, pool_theta, count_a,
+                     count_b, P->st_flags, P->arm == 2 ? P->arm_state : nullptr);
   return (int)hipGetLastError();
 }

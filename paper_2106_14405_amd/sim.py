@@ -114,7 +114,10 @@ class Sim:
         S, N, CM, PM = self.S, self.N, self.max_contacts, self.max_pairs
         self.pose = self._view(sv.pose, torch.float32, (7, N))
         self.vel = self._view(sv.vel, torch.float32, (6, N))
+        self.rest = self._view(sv.rest, torch.int32, (N,))
         self.theta = self._view(sv.theta, torch.float32, (S, 7)) if self.batch.arm else None
+        # articulated arm: [S, 3, 7] joint rates, motor targets, last motor impulses
+        self.arm_state = self._view(sv.arm_state, torch.float32, (S, 3, 7)) if int(self.batch.arm) == 2 else None
         st = L.StatsView()
         L.check(lib.sim_stats(self.h, C.byref(st)), "sim_stats")
         self.stats = dict(
@@ -179,6 +182,14 @@ class Sim:
                 "sim_query_arm")
         return hit, phi
 
+    def set_motors(self, kp: float = 0.3, max_impulse: float = 10.0):
+        """Articulated arm: motor position gain and largest motor impulse per step (N m s)."""
+        L.check(L.load().sim_set_motors(self.h, float(kp), float(max_impulse)), "sim_set_motors")
+
+    def set_sleep(self, speed: float = 0.0, steps: int = 0):
+        """Sleeping islands on (speed m/s > 0, steps >= 1) or off (speed 0)."""
+        L.check(L.load().sim_set_sleep(self.h, float(speed), int(steps)), "sim_set_sleep")
+
     def set_trace(self, on: bool = True):
         """Per-scene phase timestamps ([S, 16] int64 device tensor) written by every later step."""
         if on:
@@ -208,13 +219,18 @@ class Sim:
         """Persistent launch over two size-ordered scene queues, replayed from a HIP graph."""
         L.check(L.load().sim_set_persistent(self.h, int(bool(on)), int(wave_max_bodies)), "sim_set_persistent")
 
+    def set_persistent_table(self, wave_buckets: int):
+        """Persistent launch routed by a body-count bucket table (bit k: bucket k to single waves)."""
+        L.check(L.load().sim_set_persistent_table(self.h, int(wave_buckets)), "sim_set_persistent_table")
+
     def autotune(self, steps: int = 5, dt: float = 1.0 / 120.0, iters: int = 10) -> int:
-        """Times the persistent launch's queue split and keeps the fastest; state is unchanged."""
+        """Times the persistent launch's routing, bucket by bucket, and keeps the
+        fastest table (returned as its bit mask); state is unchanged."""
         lib = L.load()
         need = int(lib.sim_autotune_scratch_bytes(self.h))
         scratch = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
         ptr = (scratch.data_ptr() + 255) // 256 * 256
-        out = C.c_int(0)
+        out = C.c_uint32(0)
         L.check(lib.sim_autotune(self.h, C.c_void_p(ptr), need, int(steps), float(dt), int(iters), C.byref(out)),
                 "sim_autotune")
         return out.value

@@ -44,8 +44,8 @@ static void disjoint(const std::vector<Region>& rs, long total, int NB, int PM, 
   }
 }
 
-static void check_layout(int NB, int PM, int CM, int W, int solver, int warm) {
-  const LdsLayout L = lds_layout(NB, PM, CM, W, solver, warm);
+static void check_layout(int NB, int PM, int CM, int W, int solver, int warm, int arm) {
+  const LdsLayout L = lds_layout(NB, PM, CM, W, solver, warm, arm);
   const long T = L.total;
   // resident for the whole step (the two slots in front of dyn and dyn2: ground and sink)
   std::vector<Region> res = {{"geo", L.geo, L.geo + 12L * NB},
@@ -59,7 +59,12 @@ static void check_layout(int NB, int PM, int CM, int W, int solver, int warm) {
                              {"hbase", L.hbase, L.hbase + 256},
                              {"scratch", L.scr, T}};
   if (warm == WARM_LEARNED) res.push_back({"fresh", L.fresh, L.fresh + (CM + 31) / 32});
+  if (arm == 2) res.push_back({"arm", L.arm, L.arm + kArmWords});
   disjoint(res, T, NB, PM, CM, W);
+  // the arm's words: M^-1, rates, impulses, targets, origins and axes inside the region
+  CHECK(ARM_MI + 49 <= ARM_DQ && ARM_DQ + 7 <= ARM_QREF && ARM_QREF + 7 <= ARM_LAM && ARM_LAM + 7 <= ARM_BIAS &&
+            ARM_BIAS + 7 <= ARM_O && ARM_O + 21 <= ARM_AX && ARM_AX + 21 <= kArmWords,
+        "arm words");
   // misc slots: per-wave words and scan words fit
   CHECK(M_SCAN + W <= kMiscWords && M_WAVE + W <= M_SCAN, "misc slots");
   // colour starts (kMaxColours + 1) live in hbase; class bases 16, per-wave class counts 16 W in hist
@@ -147,10 +152,11 @@ int main() {
         CHECK((long)kRec * (CM - 1) + kRec - 1 < rs, "record index inside the record block");
         for (int W = 1; W <= 4; W++)
           for (int solver = 0; solver < 2; solver++)
-            for (int warm = 0; warm < 3; warm++) {
-              check_layout(NB, PM, CM, W, solver, warm);
-              checked++;
-            }
+            for (int warm = 0; warm < 3; warm++)
+              for (int arm = 0; arm <= 2; arm += 2) {
+                check_layout(NB, PM, CM, W, solver, warm, arm);
+                checked++;
+              }
       }
   }
   std::printf("layouts checked: %ld, failures: %d\n", checked, failures);

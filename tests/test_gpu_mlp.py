@@ -225,7 +225,9 @@ def test_learned_step_parity(torch_cuda, seed, garbage):
     sim.step(None, DT, 500)
     r = ora.step(iters=500, tol=1e-6, warm=O.LEARNED, max_pairs=sim.max_pairs, max_contacts=sim.max_contacts)
     g = gpu_results(sim)
-    rep = compare(b, g, r, ora)
+    # tolerance 1e-6 m/s is the float32 residual's rounding floor: stop
+    # decisions within a factor 2 of it are ties (as for the features below)
+    rep = compare(b, g, r, ora, tol_band=1.0)
     assert rep["scenes"] - rep["flagged"] >= 2 and rep["contacts"] >= 50
     fell_g = g["stats"]["flags"] & O.F_FELLBACK
     fell_o = r["flags"] & O.F_FELLBACK
