@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--launch", default=None, choices=["plain", "persistent"],
                     help="uneven workload: persistent (default) or one workgroup per scene")
     ap.add_argument("--pool", type=int, default=4, help="uneven workload: fresh states per scene in the reset pool")
+    ap.add_argument("--arm-eval", type=int, default=1,
+                    help="clutter: also time the same scenes with the articulated arm (PD joint motors)")
     ap.add_argument("--learned-eval", type=int, default=1)
     ap.add_argument("--learned-scenes", type=int, default=2048)
     ap.add_argument("--learned-steps", type=int, default=240)
@@ -258,6 +260,43 @@ def learned_vs_plain(n_scenes, steps):
     return res
 
 
+def articulated_arm(batch, acts, a, max_contacts, max_pairs, cap, dev):
+    """The clutter scenes with the articulated arm (PD joint motors, the
+    same per-step action rates as motor-target rates): settled like the
+    headline, then the same window timed with the classic warm start at the
+    same tolerance and cap."""
+    import torch
+    from paper_2106_14405_amd import _lib as L
+    from paper_2106_14405_amd.sim import Sim
+    sim = Sim(batch, max_contacts=max_contacts, max_pairs=max_pairs, warm=L.PREV, tol=0.0, threads=a.threads,
+              device=dev)
+    K, W, T0 = a.steps, a.warmup, a.settle
+    for t in range(T0):
+        sim.step(acts[t], DT, 20)
+    sim.set_solver(L.PGS, L.PREV, a.tol)
+    for t in range(W):
+        sim.step(acts[T0 + t], DT, cap)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(sim.stream)
+    for t in range(K):
+        sim.step(acts[T0 + W + t], DT, cap)
+    ev1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    # statistics of the last timed step (a replay of the window would double the run)
+    r = dict(ms_per_step=ms / K, env_steps_per_s=batch.n_scenes * K / (ms / 1e3),
+             workload="clutter scenes with the articulated arm (dynamic links of 2.0-0.5 kg, Kp 0.3, 10 N s)",
+             last_step_sweeps_mean=float(sim.stats["sweeps"].float().mean().item()),
+             last_step_frac_at_tol=float((sim.stats["residual"] <= a.tol).float().mean().item()),
+             last_step_arm_force_mean_N=float(sim.stats["arm_force"].mean().item()),
+             joint_rate_max=float(sim.arm_state[:, 0].abs().max().item()))
+    sim.close()
+    del sim
+    torch.cuda.synchronize()
+    return r
+
+
 def summarise(sweeps, resid, flags, contacts, tol):
     """Statistics over scene-steps [K, S] (scene-steps with contacts for sweeps)."""
     from paper_2106_14405_amd import _lib as L
@@ -319,6 +358,7 @@ def main():
         modes.append(a.headline)
     # every host-side input is generated before the GPU is touched
     batch = batch_fn(n_scenes)
+    batch_arm = S.batch_clutter(n_scenes, seed0=10000, arm=2) if a.workload == "clutter" and a.arm_eval else None
     pool = S.reset_pool(batch, a.pool, seed=40000, kind="drop") if a.workload == "uneven" else None
     cpu_batch = None
     if a.cpu_baseline and a.workload != "uneven":
@@ -420,6 +460,9 @@ def main():
     sim.close()
     del sim
     torch.cuda.synchronize()
+    if batch_arm is not None:
+        results["prev_articulated_arm"] = articulated_arm(batch_arm, acts, a, max_contacts, max_pairs, cap, dev)
+        progress(f"prev_articulated_arm: {results['prev_articulated_arm']['ms_per_step']:.3f} ms per step")
 
     head = results[a.headline]
     motion = batch.motion

@@ -1207,7 +1207,7 @@ __device__ __forceinline__ V3 setup_lin_vel(const StepParams& P, long gi, long N
   return v3(P.vel[gi], P.vel[N + gi], P.vel[2 * N + gi]) + g * dt;
 }
 
-template <bool kLearned, class TM>
+template <bool kLearned, bool kArm, class TM>
 __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout& L, Smem S, const int s,
                                            const TM tm) {
   const int tid = tm.tid, T = tm.T;
@@ -1230,9 +1230,8 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
 
   // ---- load bodies; a2: gravity, world inverse inertia -----------------
   const V3 g = v3(P.gx, P.gy, P.gz);
-  // the articulated arm (not compiled into the learned kernels)
-  bool arm2 = false;
-  if constexpr (!kLearned) arm2 = P.arm == 2;
+  // the articulated arm (its own kernels: compiled out of the others)
+  constexpr bool arm2 = kArm && !kLearned;
   const int arm0 = arm2 ? nb - 7 : nb;  // its first link
   for (int i = tid; i < nb; i += T) {
     const long gi = b0 + i;
@@ -1620,8 +1619,8 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   // articulated arm as one body: its links share the list of its first
   // link, since every contact on the arm moves the same joint rates),
   // canonical order
-  auto cbody = [&](int i) { return i >= arm0 ? arm0 : i; };
-  auto conflicts = [&](int i) { return i >= arm0 || is_awake_meta(body_meta(L, S, i)); };
+  auto cbody = [&](int i) { return (arm2 && i >= arm0) ? arm0 : i; };
+  auto conflicts = [&](int i) { return (arm2 && i >= arm0) || is_awake_meta(body_meta(L, S, i)); };
   for (int i = tid; i <= nb; i += T) deg[i] = 0u;
   team_sync(tm);
   for (int q = tid; q < nc; q += T) {
@@ -2198,13 +2197,13 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   TRACE(14);
 }
 
-template <bool kLearned>
+template <bool kLearned, bool kArm>
 __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
   extern __shared__ float4 smem_f4[];
   Smem S{reinterpret_cast<float*>(smem_f4), reinterpret_cast<uint32_t*>(smem_f4)};
   const Team<false> tm{(int)threadIdx.x, (int)blockDim.x};
   const int s = P.scene_list ? P.scene_list[blockIdx.x] : (int)blockIdx.x;
-  scene_step<kLearned>(P, L, S, s, tm);
+  scene_step<kLearned, kArm>(P, L, S, s, tm);
 }
 
 // Scenes whose working set exceeds a workgroup's LDS: the same step with the
@@ -2212,12 +2211,12 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
 // P.glist, L2 and HBM resident) instead of LDS; one workgroup per scene.
 // The team barriers are workgroup-scope fences, which order global memory
 // as they order LDS, so the step computes exactly what it computes in LDS.
-template <bool kLearned>
+template <bool kLearned, bool kArm>
 __global__ __launch_bounds__(256) void step_kernel_hbm(StepParams P, LdsLayout L) {
   const int k = (int)blockIdx.x;
   float* ws = P.gscr + (size_t)k * (size_t)P.gwords;
   const Team<false> tm{(int)threadIdx.x, (int)blockDim.x};
-  scene_step<kLearned>(P, L, Smem{ws, reinterpret_cast<uint32_t*>(ws)}, P.glist[k], tm);
+  scene_step<kLearned, kArm>(P, L, Smem{ws, reinterpret_cast<uint32_t*>(ws)}, P.glist[k], tm);
 }
 
 // Persistent launch over scenes of uneven size: every workgroup first takes
@@ -2226,7 +2225,7 @@ __global__ __launch_bounds__(256) void step_kernel_hbm(StepParams P, LdsLayout L
 // steps each alone in its quarter of the LDS.  Queues are in descending
 // body count, so the largest scenes start first; a workgroup leaves once
 // both queues are drained.
-template <bool kLearned>
+template <bool kLearned, bool kArm>
 __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams Q) {
   extern __shared__ float4 smem_f4[];
   __shared__ int next_scene;
@@ -2242,7 +2241,7 @@ __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams
     const int nb = P.body_offset[s + 1] - P.body_offset[s];
     const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), (int)blockDim.x >> 6, P.solver,
                                    P.warm, P.arm);
-    scene_step<kLearned>(P, L, Smem{lds, reinterpret_cast<uint32_t*>(lds)}, s, Team<false>{tid, (int)blockDim.x});
+    scene_step<kLearned, kArm>(P, L, Smem{lds, reinterpret_cast<uint32_t*>(lds)}, s, Team<false>{tid, (int)blockDim.x});
     __syncthreads();
   }
   const int w = tid >> 6, lane = tid & 63;
@@ -2255,7 +2254,7 @@ __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams
     const int s = Q.wave[k];
     const int nb = P.body_offset[s + 1] - P.body_offset[s];
     const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), 1, P.solver, P.warm, P.arm);
-    scene_step<kLearned>(P, L, Smem{mine, reinterpret_cast<uint32_t*>(mine)}, s, Team<true>{lane, 64});
+    scene_step<kLearned, kArm>(P, L, Smem{mine, reinterpret_cast<uint32_t*>(mine)}, s, Team<true>{lane, 64});
   }
 }
 
@@ -2326,28 +2325,33 @@ extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L
                                hipStream_t stream) {
   size_t bytes = (size_t)L->total * 4u;
   if (P->warm == rbs::WARM_LEARNED)
-    hipLaunchKernelGGL(rbs::step_kernel<true>, dim3(grid), dim3(threads), bytes, stream, *P, *L);
+    hipLaunchKernelGGL((rbs::step_kernel<true, false>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
+  else if (P->arm == 2)
+    hipLaunchKernelGGL((rbs::step_kernel<false, true>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
   else
-    hipLaunchKernelGGL(rbs::step_kernel<false>, dim3(grid), dim3(threads), bytes, stream, *P, *L);
+    hipLaunchKernelGGL((rbs::step_kernel<false, false>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
   return (int)hipGetLastError();
 }
 
 extern "C" int rbs_launch_step_hbm(const rbs::StepParams* P, const rbs::LdsLayout* L, int n, hipStream_t stream) {
   if (n <= 0) return 0;
   if (P->warm == rbs::WARM_LEARNED)
-    hipLaunchKernelGGL(rbs::step_kernel_hbm<true>, dim3(n), dim3(256), 0, stream, *P, *L);
+    hipLaunchKernelGGL((rbs::step_kernel_hbm<true, false>), dim3(n), dim3(256), 0, stream, *P, *L);
+  else if (P->arm == 2)
+    hipLaunchKernelGGL((rbs::step_kernel_hbm<false, true>), dim3(n), dim3(256), 0, stream, *P, *L);
   else
-    hipLaunchKernelGGL(rbs::step_kernel_hbm<false>, dim3(n), dim3(256), 0, stream, *P, *L);
+    hipLaunchKernelGGL((rbs::step_kernel_hbm<false, false>), dim3(n), dim3(256), 0, stream, *P, *L);
   return (int)hipGetLastError();
 }
 
 // Dynamic LDS limits: the whole budget for the per-scene kernels; the
 // persistent kernel keeps 256 bytes for its static words.
 extern "C" int rbs_set_step_lds_limit(int bytes) {
-  const void* k[4] = {(const void*)rbs::step_kernel<false>, (const void*)rbs::step_kernel<true>,
-                      (const void*)rbs::step_persistent<false>, (const void*)rbs::step_persistent<true>};
-  for (int i = 0; i < 4; i++) {
-    int e = (int)hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, i < 2 ? bytes : bytes - 256);
+  const void* k[6] = {(const void*)rbs::step_kernel<false, false>, (const void*)rbs::step_kernel<true, false>,
+                      (const void*)rbs::step_kernel<false, true>, (const void*)rbs::step_persistent<false, false>,
+                      (const void*)rbs::step_persistent<true, false>, (const void*)rbs::step_persistent<false, true>};
+  for (int i = 0; i < 6; i++) {
+    int e = (int)hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, i < 3 ? bytes : bytes - 256);
     if (e) {
       (void)hipGetLastError();  // leave no sticky error behind
       return e;
@@ -2362,9 +2366,11 @@ extern "C" int rbs_launch_persistent(const rbs::StepParams* P, const rbs::QueueP
   hipLaunchKernelGGL(rbs::queue_reset_kernel, dim3(1), dim3(64), 0, stream, Q->head);
   const size_t bytes = (size_t)Q->lds_words * 4u;
   if (P->warm == rbs::WARM_LEARNED)
-    hipLaunchKernelGGL(rbs::step_persistent<true>, dim3(grid), dim3(256), bytes, stream, *P, *Q);
+    hipLaunchKernelGGL((rbs::step_persistent<true, false>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
+  else if (P->arm == 2)
+    hipLaunchKernelGGL((rbs::step_persistent<false, true>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
   else
-    hipLaunchKernelGGL(rbs::step_persistent<false>, dim3(grid), dim3(256), bytes, stream, *P, *Q);
+    hipLaunchKernelGGL((rbs::step_persistent<false, false>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
   return (int)hipGetLastError();
 }
 
