@@ -50,7 +50,9 @@ class Model(C.Structure):
                 ("arm_base", _P(_d)), ("link_len", _d * 7), ("arm_radius", _d),
                 ("gravity", _d * 3), ("margin", _d), ("baumgarte", _d), ("slop", _d),
                 ("rest_thresh", _d), ("ground_friction", _d), ("ground_restitution", _d),
-                ("sleep_speed", _d), ("sleep_steps", C.c_int), ("motor_kp", _d), ("motor_max", _d)]
+                ("sleep_speed", _d), ("sleep_steps", C.c_int), ("motor_kp", _d), ("motor_max", _d),
+                ("joint", _P(C.c_uint8)), ("joint_axis", _P(_d)), ("joint_anchor", _P(_d)),
+                ("joint_limits", _P(_d)), ("joint_parent", _P(C.c_int32))]
 
 
 class Cache(C.Structure):
@@ -83,7 +85,8 @@ def lib():
     if _lib is None:
         path = build()
         L = C.CDLL(path)
-        L.ora_step.argtypes = [_P(Model), _P(_d), _P(_d), _P(_d), _P(C.c_int32), _P(_d), _P(Cache), _P(_d), _d, C.c_int,
+        L.ora_step.argtypes = [_P(Model), _P(_d), _P(_d), _P(_d), _P(C.c_int32), _P(_d), _P(_d), _P(Cache), _P(_d), _d,
+                               C.c_int,
                                _d, C.c_int, C.c_int, _P(Mlp), _P(Out), C.c_int, C.c_int]
         L.ora_step.restype = C.c_int
         L.ora_arm_pose.argtypes = [_P(Model), _P(_d), _P(_d)]
@@ -138,6 +141,15 @@ class OracleSim:
         self.arm_state = np.zeros((self.S, 3, 7))
         self.arm_state[:, 1] = self.theta.reshape(self.S, 7)
         self.arm_state = self.arm_state.reshape(-1)
+        # articulated container parts: per body the joint coordinate and its rate
+        self.joint_state = np.zeros(2 * int(self.off[-1]))
+        self.has_parts = getattr(b, "joint", None) is not None
+        if self.has_parts:
+            self.joint = np.ascontiguousarray(b.joint, np.uint8)
+            self.joint_axis = np.ascontiguousarray(b.joint_axis, np.float64).reshape(-1)
+            self.joint_anchor = np.ascontiguousarray(b.joint_anchor, np.float64).reshape(-1)
+            self.joint_limits = np.ascontiguousarray(b.joint_limits, np.float64).reshape(-1)
+            self.joint_parent = np.ascontiguousarray(b.joint_parent, np.int32)
         self.m = Model()
         self.m.n_scenes = self.S
         self.m.body_offset = _ptr(self.off, C.c_int32)
@@ -157,6 +169,12 @@ class OracleSim:
         for k in ("margin", "baumgarte", "slop", "rest_thresh", "ground_friction",
                   "ground_restitution", "motor_kp", "motor_max"):
             setattr(self.m, k, c[k])
+        if self.has_parts:
+            self.m.joint = _ptr(self.joint, C.c_uint8)
+            self.m.joint_axis = _ptr(self.joint_axis, _d)
+            self.m.joint_anchor = _ptr(self.joint_anchor, _d)
+            self.m.joint_limits = _ptr(self.joint_limits, _d)
+            self.m.joint_parent = _ptr(self.joint_parent, C.c_int32)
         self.cache_cap = cache_cap
         self.c_count = np.zeros(self.S, np.int32)
         self.c_key = np.zeros(self.S * cache_cap, np.uint32)
@@ -171,6 +189,16 @@ class OracleSim:
         """Dynamic arm: motor position gain and largest impulse per step (N s)."""
         self.m.motor_kp = float(kp)
         self.m.motor_max = float(max_impulse)
+
+    @property
+    def q(self):
+        """Container parts: joint coordinates [N] (a view; 0 for other bodies)."""
+        return self.joint_state.reshape(-1, 2)[:, 0]
+
+    @property
+    def q_rate(self):
+        """Container parts: joint rates [N] (a view)."""
+        return self.joint_state.reshape(-1, 2)[:, 1]
 
     @property
     def qd(self):
@@ -193,10 +221,12 @@ class OracleSim:
         self.m.sleep_steps = int(steps)
 
     # ---------------------------------------------------------------- state
-    def set_state(self, pose, vel, theta=None, cache=None, rest=None, arm_state=None):
+    def set_state(self, pose, vel, theta=None, cache=None, rest=None, arm_state=None, joint_state=None):
         """Overwrite the state with (float32) arrays, widened exactly."""
         self.pose[:] = np.asarray(pose, np.float64).reshape(-1)
         self.vel[:] = np.asarray(vel, np.float64).reshape(-1)
+        if joint_state is not None:
+            self.joint_state[:] = np.asarray(joint_state, np.float64).reshape(-1)
         if arm_state is not None:
             self.arm_state[:] = np.asarray(arm_state, np.float64).reshape(-1)
         if rest is not None:
@@ -284,6 +314,7 @@ class OracleSim:
         mlp = C.byref(self.mlp) if warm == LEARNED else None
         rc = lib().ora_step(C.byref(self.m), _ptr(self.pose, _d), _ptr(self.vel, _d),
                             _ptr(self.theta, _d), _ptr(self.rest, C.c_int32), _ptr(self.arm_state, _d),
+                            _ptr(self.joint_state, _d),
                             C.byref(self.cache) if use_cache else None,
                             _ptr(act, _d) if act is not None else None, dt, int(iters), float(tol),
                             int(warm), int(solver), mlp, C.byref(out) if out is not None else None,

@@ -88,6 +88,13 @@ typedef struct {
     double mu, e;
     V lo, hi;           /* fattened AABB */
     int ncon;           /* contacts touching this body (Jacobi) */
+    /* articulated container part: 1 revolute about the line through jo along
+     * ja, 2 prismatic along ja; qd its joint rate, jM its mass about the
+     * joint (moment of inertia about the hinge line, or the mass); v and w
+     * always equal the motion qd gives the body */
+    int joint;
+    V ja, jo;
+    double jM, qd;
 } Body;
 
 /* Principal moments of a solid body of uniform density. */
@@ -865,12 +872,15 @@ static int movable(const Body *b) { return b->motion == ORA_DYNAMIC || b->motion
 /* Brute-force pair set: every i < j with at least one dynamic body whose
  * closed AABBs overlap on x, y and z, then (i, ground) for dynamic i whose
  * AABB reaches z <= 0; lexicographic order. */
-static int brute_pairs(const Body *B, int n, int arm0, uint32_t *keys, int cap, int *amb, uint8_t *tied) {
+static int brute_pairs(const Body *B, int n, int arm0, const int32_t *parent, uint32_t *keys, int cap, int *amb,
+                       uint8_t *tied) {
     int np = 0;
     for (int i = 0; i < n; i++) {
         for (int j = i + 1; j < n; j++) {
             if (!movable(&B[i]) && !movable(&B[j])) continue;
             if (i >= arm0) continue;     /* two links of the dynamic arm: joined, not in contact */
+            /* a part and the base it is joined to */
+            if (parent && ((B[i].joint && parent[i] == j) || (B[j].joint && parent[j] == i))) continue;
             double sl = INFINITY;
             for (int a = 0; a < 3; a++) {
                 double s1 = comp(B[i].hi, a) - comp(B[j].lo, a);
@@ -936,6 +946,54 @@ static void load_bodies(const ora_model *m, const double *pose, const double *ve
     }
 }
 
+/* ------------------------------------------------------ container parts
+ * Articulated furniture (Sec. 3: doors and drawers that turn about an axis
+ * or slide): a part is one rigid body with one degree of freedom relative
+ * to the world, a revolute joint about a fixed hinge line or a prismatic
+ * one along a fixed axis, its coordinate q held within limits.  Its state is
+ * q and the rate qd; the body's velocity is the one qd gives it (w = qd a,
+ * v = w x (c - o) for a hinge; v = qd a for a slide).  An impulse P at p
+ * changes qd by (a . ((p - o) x P)) / I_o (hinge; I_o its moment of inertia
+ * about the hinge line) or (a . P) / m (slide). */
+static void part_sync(Body *b) {   /* v, w from qd */
+    if (b->joint == 1) {
+        b->w = scl(b->ja, b->qd);
+        b->v = cross(b->w, sub(b->x, b->jo));
+    } else {
+        b->v = scl(b->ja, b->qd);
+        b->w = mk(0, 0, 0);
+    }
+}
+
+/* Generalised impulse of an impulse P at point p on a part. */
+static double part_gen(const Body *b, V p, V P) {
+    return b->joint == 1 ? dot(b->ja, cross(sub(p, b->jo), P)) : dot(b->ja, P);
+}
+
+static void load_parts(const ora_model *m, const double *joint_state, int s, Body *B) {
+    int b0 = m->body_offset[s], n = m->body_offset[s + 1] - b0;
+    for (int k = 0; k < n; k++) {
+        Body *b = &B[k];
+        int g = b0 + k;
+        b->joint = m->joint && b->motion == ORA_DYNAMIC ? m->joint[g] : 0;
+        if (!b->joint) continue;
+        b->ja = mk(m->joint_axis[3 * g], m->joint_axis[3 * g + 1], m->joint_axis[3 * g + 2]);
+        b->jo = mk(m->joint_anchor[3 * g], m->joint_anchor[3 * g + 1], m->joint_anchor[3 * g + 2]);
+        double mass = m->mass[g];
+        if (b->joint == 1) {
+            double Ip[3];
+            body_inertia(b->shape, b->prm, mass, Ip);
+            V al = mk(dot(col(&b->R, 0), b->ja), dot(col(&b->R, 1), b->ja), dot(col(&b->R, 2), b->ja));
+            V d = cross(b->ja, sub(b->x, b->jo));
+            b->jM = al.x * al.x * Ip[0] + al.y * al.y * Ip[1] + al.z * al.z * Ip[2] + mass * len2(d);
+        } else {
+            b->jM = mass;
+        }
+        b->qd = joint_state[2 * g + 1];
+        part_sync(b);
+    }
+}
+
 /* ---------------------------------------------------------------- solver */
 typedef struct {
     int a, b;               /* local body indices, b = -1 for the ground */
@@ -976,11 +1034,23 @@ static V Mv(const M3 *M, V a) { return Rv(M, a); }
 
 static double row_k(const Body *B, const Con *c, V d) {
     double k = 0;
-    V ca = cross(c->ra, d);
-    k += B[c->a].im + dot(ca, Mv(&B[c->a].Iw, ca));
+    const Body *A = &B[c->a];
+    if (A->joint) {   /* a part: the row's generalised direction over its joint mass */
+        double gq = part_gen(A, c->p, d);
+        k += gq * gq / A->jM;
+    } else {
+        V ca = cross(c->ra, d);
+        k += A->im + dot(ca, Mv(&A->Iw, ca));
+    }
     if (c->b >= 0) {
-        V cb = cross(c->rb, d);
-        k += B[c->b].im + dot(cb, Mv(&B[c->b].Iw, cb));
+        const Body *Bb = &B[c->b];
+        if (Bb->joint) {
+            double gq = part_gen(Bb, c->p, d);
+            k += gq * gq / Bb->jM;
+        } else {
+            V cb = cross(c->rb, d);
+            k += Bb->im + dot(cb, Mv(&Bb->Iw, cb));
+        }
     }
     return k;
 }
@@ -988,17 +1058,48 @@ static double row_k(const Body *B, const Con *c, V d) {
 /* Apply the impulse P (from B onto A; -P onto B) at the contact. */
 static void apply(Body *B, const Con *c, V P) {
     Body *A = &B[c->a];
-    if (A->motion == ORA_DYNAMIC) {
+    if (A->joint) {
+        A->qd += part_gen(A, c->p, P) / A->jM;
+        part_sync(A);
+    } else if (A->motion == ORA_DYNAMIC) {
         A->v = add(A->v, scl(P, A->im));
         A->w = add(A->w, Mv(&A->Iw, cross(c->ra, P)));
     }
     if (c->b >= 0) {
         Body *Bb = &B[c->b];
-        if (Bb->motion == ORA_DYNAMIC) {
+        if (Bb->joint) {
+            Bb->qd -= part_gen(Bb, c->p, P) / Bb->jM;
+            part_sync(Bb);
+        } else if (Bb->motion == ORA_DYNAMIC) {
             Bb->v = sub(Bb->v, scl(P, Bb->im));
             Bb->w = sub(Bb->w, Mv(&Bb->Iw, cross(c->rb, P)));
         }
     }
+}
+
+/* Joint limits of the parts: per part a lower and an upper row on the rate
+ * (direction +1, -1), with the contacts' speculative rule: a gap g > 0 to
+ * the limit lets the rate close it within the step (target -g/dt), a
+ * violation is pushed back at baumgarte/dt of it; impulses >= 0, started
+ * from zero every step.  One Gauss-Seidel pass over the parts in body order;
+ * returns max |dlambda| * (1/M). */
+typedef struct { int body; double q, bias[2], lam[2]; } Limit;
+
+static double limit_sweep(Body *B, Limit *Lm, int nl) {
+    double R = 0;
+    for (int k = 0; k < nl; k++) {
+        Body *b = &B[Lm[k].body];
+        for (int r = 0; r < 2; r++) {
+            double sgn = r == 0 ? 1.0 : -1.0;
+            double l = fmax(0.0, Lm[k].lam[r] + b->jM * (Lm[k].bias[r] - sgn * b->qd));
+            double dl = l - Lm[k].lam[r];
+            Lm[k].lam[r] = l;
+            b->qd += sgn * dl / b->jM;
+            part_sync(b);
+            R = fmax(R, fabs(dl) / b->jM);
+        }
+    }
+    return R;
 }
 
 static V vrel(const Body *B, const Con *c) {
@@ -1312,14 +1413,15 @@ static int finite3(V a) { return isfinite(a.x) && isfinite(a.y) && isfinite(a.z)
  * *gap receives the smallest |R - tol| / tol over the sweeps whose residual
  * was tested against the tolerance (infinity when none was): how close the
  * stopping decision came to going the other way. */
-static int solve(Body *B, int nb, Arm *A, Con *C, const int *order, int nc, int iters, double tol,
-                 int solver, double *res, double *gap) {
+static int solve(Body *B, int nb, Arm *A, Limit *Lm, int nl, Con *C, const int *order, int nc, int iters,
+                 double tol, int solver, double *res, double *gap) {
     int sw = 0;
     double R = 0;
     *gap = INFINITY;
     for (int it = 0; it < iters; it++) {
         R = solver == ORA_JACOBI ? jacobi_sweep(B, nb, C, order, nc) : pgs_sweep(B, A, C, order, nc);
         if (A) R = fmax(R, motor_sweep(A));
+        if (nl) R = fmax(R, limit_sweep(B, Lm, nl));
         sw++;
         if (tol > 0) *gap = fmin(*gap, fabs(R - tol) / tol);
         if (tol > 0 && R <= tol) break;
@@ -1377,7 +1479,7 @@ static int uf_find(int *par, int x) {
 }
 
 static void step_scene(const ora_model *m, double *pose, double *vel, double *theta, int32_t *rest,
-                       double *arm_state, ora_cache *cache, const double *actions, double dt, int iters,
+                       double *arm_state, double *joint_state, ora_cache *cache, const double *actions, double dt, int iters,
                        double tol, int warm, int solver, const ora_mlp *mlp, ora_out *out, int s) {
     int b0 = m->body_offset[s], nb = m->body_offset[s + 1] - b0;
     int flags = 0, amb = 0;
@@ -1415,6 +1517,8 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
     }
     Body *B = malloc(sizeof(Body) * (nb ? nb : 1));
     load_bodies(m, pose, vel, s, B);
+    for (int i = 0; i < nb; i++) B[i].joint = 0;
+    if (m->joint) load_parts(m, joint_state, s, B);
     Arm AR;
     if (m->arm == 2) {
         AR.l0 = nb - 7;
@@ -1435,8 +1539,14 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
     }
 
     /* 2. velocity integration (no gyroscopic term; the arm: dt M^-1 tau_g) */
-    for (int i = 0; i < nb; i++)
-        if (B[i].motion == ORA_DYNAMIC) B[i].v = add(B[i].v, scl(g, dt));
+    for (int i = 0; i < nb; i++) {
+        if (B[i].joint) {   /* a part: the gravity moment (force) about its joint over its joint mass */
+            B[i].qd += dt * part_gen(&B[i], B[i].x, scl(g, m->mass[b0 + i])) / B[i].jM;
+            part_sync(&B[i]);
+        } else if (B[i].motion == ORA_DYNAMIC) {
+            B[i].v = add(B[i].v, scl(g, dt));
+        }
+    }
     if (m->arm == 2) {
         double tg[7];
         for (int i = 0; i < 7; i++) {
@@ -1453,7 +1563,7 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
     uint32_t *pk = malloc(sizeof(uint32_t) * maxp);
     uint8_t *tied = calloc((size_t)(nb ? nb : 1), 1);
     const int arm0 = m->arm == 2 ? nb - 7 : nb;   /* first link of the dynamic arm */
-    int np = brute_pairs(B, nb, arm0, pk, maxp, &amb, tied);
+    int np = brute_pairs(B, nb, arm0, m->joint_parent ? m->joint_parent + b0 : NULL, pk, maxp, &amb, tied);
 
     /* 5. narrowphase in canonical pair order; 6. contact list */
     int capc = 4 * np + 1;
@@ -1508,7 +1618,7 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
             if (ra != rb) par[ra < rb ? rb : ra] = ra < rb ? ra : rb;
         }
         for (int i = 0; i < nb; i++)
-            if (B[i].motion == ORA_DYNAMIC && rest[b0 + i] < m->sleep_steps) wake[uf_find(par, i)] = 1;
+            if (B[i].motion == ORA_DYNAMIC && (rest[b0 + i] < m->sleep_steps || B[i].joint)) wake[uf_find(par, i)] = 1;
         for (int q = 0; q < nc; q++) {
             int a = C[q].a, b = C[q].b;
             if (b < 0) continue;
@@ -1684,8 +1794,23 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
             for (int i = 0; i < 7; i++) AR.qd[i] += AR.lam[k] * AR.Mi[i][k];
         }
     }
+    /* joint limits of the parts (the gap to each limit at the step's q) */
+    Limit *Lm = malloc(sizeof(Limit) * (nb ? nb : 1));
+    int nl = 0;
+    for (int i = 0; i < nb; i++) {
+        if (!B[i].joint) continue;
+        Limit *l = &Lm[nl++];
+        int gi = b0 + i;
+        l->body = i;
+        l->q = joint_state[2 * gi];
+        double gaps[2] = {l->q - m->joint_limits[2 * gi], m->joint_limits[2 * gi + 1] - l->q};
+        for (int r = 0; r < 2; r++) {
+            l->bias[r] = gaps[r] > 0 ? -gaps[r] / dt : m->baumgarte / dt * (-gaps[r]);
+            l->lam[r] = 0;
+        }
+    }
     double R = 0, gap = INFINITY;
-    int sweeps = solve(B, nb, AP, C, order, nact, iters, tol, solver, &R, &gap);
+    int sweeps = solve(B, nb, AP, Lm, nl, C, order, nact, iters, tol, solver, &R, &gap);
     /* a step counts as solved only once its residual reached the tolerance */
     if (tol > 0 && R > tol) flags |= ORA_F_NOT_CONVERGED;
     free(vsave);
@@ -1708,13 +1833,34 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
             int at_rest = sp <= m->sleep_speed && sw <= m->sleep_speed;
             rest[gi0] = at_rest ? (rest[gi0] < (1 << 30) ? rest[gi0] + 1 : rest[gi0]) : 0;
         }
-        b->x = add(b->x, scl(b->v, dt));
-        double wq[4] = {0, b->w.x, b->w.y, b->w.z}, dq[4];
-        quat_mul(wq, b->q, dq);
-        double q2[4], L = 0;
-        for (int k = 0; k < 4; k++) { q2[k] = b->q[k] + 0.5 * dt * dq[k]; L += q2[k] * q2[k]; }
-        L = sqrt(L);
-        for (int k = 0; k < 4; k++) b->q[k] = q2[k] / L;
+        if (b->joint) {
+            /* a part moves exactly along its joint: q += dt qd; a hinge turns
+             * the body about its line by dt qd, a slide shifts it by dt qd a */
+            double dq = dt * b->qd;
+            joint_state[2 * gi0] += dq;
+            joint_state[2 * gi0 + 1] = b->qd;
+            if (b->joint == 1) {
+                double c = cos(dq), sn = sin(dq);
+                V r = sub(b->x, b->jo), a = b->ja;
+                V rr = add(add(scl(r, c), scl(cross(a, r), sn)), scl(a, dot(a, r) * (1.0 - c)));
+                b->x = add(b->jo, rr);
+                double hq[4] = {cos(0.5 * dq), a.x * sin(0.5 * dq), a.y * sin(0.5 * dq), a.z * sin(0.5 * dq)}, q2[4];
+                quat_mul(hq, b->q, q2);
+                double L = sqrt(q2[0] * q2[0] + q2[1] * q2[1] + q2[2] * q2[2] + q2[3] * q2[3]);
+                for (int k = 0; k < 4; k++) b->q[k] = q2[k] / L;
+            } else {
+                b->x = add(b->x, scl(b->ja, dq));
+            }
+            part_sync(b);   /* velocity at the new pose */
+        } else {
+            b->x = add(b->x, scl(b->v, dt));
+            double wq[4] = {0, b->w.x, b->w.y, b->w.z}, dq[4];
+            quat_mul(wq, b->q, dq);
+            double q2[4], L = 0;
+            for (int k = 0; k < 4; k++) { q2[k] = b->q[k] + 0.5 * dt * dq[k]; L += q2[k] * q2[k]; }
+            L = sqrt(L);
+            for (int k = 0; k < 4; k++) b->q[k] = q2[k] / L;
+        }
         int gi = b0 + i;
         pose[7 * gi] = b->x.x; pose[7 * gi + 1] = b->x.y; pose[7 * gi + 2] = b->x.z;
         for (int k = 0; k < 4; k++) pose[7 * gi + 3 + k] = b->q[k];
@@ -1805,22 +1951,27 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
     free(asleep);
     free(tied);
     free(order);
+    free(Lm);
     free(C);
     free(pk);
     free(B);
 }
 
 int ora_step(const ora_model *m, double *pose, double *vel, double *theta, int32_t *rest,
-             double *arm_state, ora_cache *cache, const double *actions, double dt, int iters,
+             double *arm_state, double *joint_state, ora_cache *cache, const double *actions, double dt, int iters,
              double tol, int warm, int solver, const ora_mlp *mlp,
              ora_out *out, int s0, int s1) {
     if (!m || !pose || !vel || dt <= 0 || iters < 0 || s0 < 0 || s1 > m->n_scenes || s0 > s1) return -1;
     if (m->arm && !theta) return -1;
     if (m->arm < 0 || m->arm > 2) return -1;
     if (m->arm == 2 && (!arm_state || solver != ORA_PGS || warm == ORA_LEARNED)) return -1;
+    if (m->joint && (!joint_state || !m->joint_axis || !m->joint_anchor || !m->joint_limits || !m->joint_parent ||
+                     solver != ORA_PGS || warm == ORA_LEARNED))
+        return -1;
     if (warm == ORA_LEARNED && !mlp) return -1;
     for (int s = s0; s < s1; s++)
-        step_scene(m, pose, vel, theta, rest, arm_state, cache, actions, dt, iters, tol, warm, solver, mlp, out, s);
+        step_scene(m, pose, vel, theta, rest, arm_state, joint_state, cache, actions, dt, iters, tol, warm, solver, mlp,
+                   out, s);
     return 0;
 }
 
@@ -1831,7 +1982,9 @@ int ora_pairs(const ora_model *m, const double *pose, int s, uint32_t *keys, int
     load_bodies(m, pose, vel, s, B);
     for (int i = 0; i < nb; i++) body_aabb(&B[i], m->margin);
     int amb = 0;
-    int n = brute_pairs(B, nb, m->arm == 2 ? nb - 7 : nb, keys, cap, &amb, NULL);
+    for (int i = 0; i < nb; i++) B[i].joint = m->joint && B[i].motion == ORA_DYNAMIC ? m->joint[m->body_offset[s] + i] : 0;
+    int n = brute_pairs(B, nb, m->arm == 2 ? nb - 7 : nb, m->joint_parent ? m->joint_parent + m->body_offset[s] : NULL,
+                        keys, cap, &amb, NULL);
     free(vel);
     free(B);
     return n;

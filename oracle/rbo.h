@@ -64,6 +64,17 @@ typedef struct ora_model {
     double motor_kp;              /* arm 2: position gain of the joint motors (fraction of the
                                      angle error closed per step) */
     double motor_max;             /* arm 2: largest motor impulse per step (N s) */
+    /* Articulated container parts (doors, drawers): a dynamic body with
+     * joint[i] = 1 turns about the world line through joint_anchor[i] along
+     * joint_axis[i] (revolute, q in rad), with 2 it slides along joint_axis[i]
+     * (prismatic, q in m); q = 0 at its initial pose, held within
+     * joint_limits[i] = (lo, hi); it does not collide with joint_parent[i]
+     * (local index of its static base, -1 for none).  NULL: no parts. */
+    const uint8_t *joint;         /* [N] 0 none, 1 revolute, 2 prismatic */
+    const double *joint_axis;     /* [N*3] unit, world */
+    const double *joint_anchor;   /* [N*3] world point on the hinge line */
+    const double *joint_limits;   /* [N*2] */
+    const int32_t *joint_parent;  /* [N] */
 } ora_model;
 
 typedef struct ora_cache {        /* previous step's contacts, sorted by key */
@@ -109,13 +120,15 @@ typedef struct ora_out {          /* optional per-scene outputs (any pointer may
  * updated.  arm_state [S*21] (arm 2 only, PGS without the learned start;
  * may be NULL otherwise): per scene the joint rates (rad/s), the motor
  * targets (rad) and the motor impulses of the last step (N m s, the warm
- * start), 7 each, read and overwritten.  cache may be NULL (then treated as
+ * start), 7 each, read and overwritten.  joint_state [N*2] (with parts;
+ * may be NULL otherwise): per body the joint coordinate q and its rate,
+ * read and overwritten.  cache may be NULL (then treated as
  * empty and not written).  actions [S*7] joint velocities (rad/s; arm 2:
  * velocities of the motor targets) or NULL.
  * iters: sweep cap.  tol > 0 stops a scene's sweeps once residual <= tol.
  * Returns 0, or -1 on a bad argument. */
 int ora_step(const ora_model *m, double *pose, double *vel, double *theta, int32_t *rest,
-             double *arm_state, ora_cache *cache, const double *actions, double dt, int iters,
+             double *arm_state, double *joint_state, ora_cache *cache, const double *actions, double dt, int iters,
              double tol, int warm, int solver, const ora_mlp *mlp,
              ora_out *out, int s0, int s1);
 

@@ -146,6 +146,9 @@ class Scene:
     arm: bool = False
     arm_base: tuple = ARM_BASE
     arm_theta0: np.ndarray | None = None
+    # articulated container parts: body index -> (joint 1 revolute / 2
+    # prismatic, unit axis, anchor point, (lo, hi) limits, parent body index)
+    joints: dict = field(default_factory=dict)
 
     def add(self, shape, motion, param, mass, mu, e, pos, quat):
         self.shape.append(shape)
@@ -336,6 +339,16 @@ class Batch:
     arm: int                  # 0 none, 1 (True) kinematic, 2 dynamic with joint motors
     arm_base: np.ndarray      # float32 [S,3]
     arm_theta: np.ndarray     # float32 [S,7]
+    # articulated container parts (None: the batch has none): per body the
+    # joint kind (0 none, 1 revolute, 2 prismatic), unit axis and anchor
+    # (world, at the initial pose, where the joint coordinate is 0), limits
+    # (lo, hi) of the coordinate, and the local index of the static body it
+    # is joined to (-1: none)
+    joint: np.ndarray | None = None          # uint8 [N]
+    joint_axis: np.ndarray | None = None     # float32 [N,3]
+    joint_anchor: np.ndarray | None = None   # float32 [N,3]
+    joint_limits: np.ndarray | None = None   # float32 [N,2]
+    joint_parent: np.ndarray | None = None   # int32 [N]
 
     @property
     def n_scenes(self):
@@ -363,6 +376,23 @@ def pack(scenes: list[Scene]) -> Batch:
     q = pose[:, 3:7]
     pose[:, 3:7] = q / np.linalg.norm(q, axis=1, keepdims=True)
     S = len(scenes)
+    joint = axis = anchor = limits = parent = None
+    if any(sc.joints for sc in scenes):
+        N = int(off[-1])
+        joint = np.zeros(N, np.uint8)
+        axis = np.zeros((N, 3), np.float32)
+        anchor = np.zeros((N, 3), np.float32)
+        limits = np.zeros((N, 2), np.float32)
+        parent = np.full(N, -1, np.int32)
+        for si, sc in enumerate(scenes):
+            for bi, (kind, ax, an, lim, par) in sc.joints.items():
+                g = int(off[si]) + bi
+                a = np.asarray(ax, np.float64)
+                joint[g] = kind
+                axis[g] = a / np.linalg.norm(a)
+                anchor[g] = an
+                limits[g] = lim
+                parent[g] = par
     return Batch(
         body_offset=off,
         shape=cat("shape", np.uint8).reshape(-1),
@@ -377,6 +407,7 @@ def pack(scenes: list[Scene]) -> Batch:
         arm_base=np.tile(np.asarray(ARM_BASE, np.float32), (S, 1)),
         arm_theta=(np.stack([s.arm_theta0 for s in scenes]).astype(np.float32) if arm
                    else np.zeros((S, ARM_LINKS), np.float32)),
+        joint=joint, joint_axis=axis, joint_anchor=anchor, joint_limits=limits, joint_parent=parent,
     )
 
 
