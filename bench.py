@@ -159,15 +159,22 @@ def cpu_baseline(batch, settle, timed_steps, cap, tol, warm, arm):
     bounds = [(k * n // nth, (k + 1) * n // nth) for k in range(nth)]
 
     def run(t0, t1, iters, tl, wm):
+        errors = []
+
         def work(s0, s1):
-            for t in range(t0, t1):
-                o.step(actions=acts[t], iters=iters, tol=tl, warm=wm, outputs=False, scenes=(s0, s1))
+            try:
+                for t in range(t0, t1):
+                    o.step(actions=acts[t], iters=iters, tol=tl, warm=wm, outputs=False, scenes=(s0, s1))
+            except Exception as e:   # re-raised below: a failed chunk must not be timed as done
+                errors.append(e)
         th = [threading.Thread(target=work, args=b) for b in bounds]
         start = time.perf_counter()
         for x in th:
             x.start()
         for x in th:
             x.join()
+        if errors:
+            raise RuntimeError(f"oracle baseline failed in {len(errors)} of {len(th)} threads") from errors[0]
         return time.perf_counter() - start
 
     run(0, settle, 20, 0.0, O.PREV)

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 4
+#define SIM_ABI_VERSION 5
 
 enum { SIM_OK = 0, SIM_EINVAL = -1, SIM_EDEVICE = -2, SIM_EWORKSPACE = -3, SIM_EABI = -4, SIM_ECAPACITY = -5 };
 enum { SIM_SPHERE = 0, SIM_BOX = 1, SIM_CAPSULE = 2 };
@@ -103,6 +103,24 @@ typedef struct sim_batch_desc {
                                     (HBM, through the caches); > 0: also every scene of at least
                                     this many bodies uses global memory.  Results do not depend
                                     on where the working set lives. */
+    /* Articulated container parts (Sec. 3: doors and drawers of the
+     * furniture turn about an axis or slide): NULL h_joint for none.  A part
+     * is a dynamic body with one degree of freedom relative to the world,
+     * its coordinate q (0 at the initial pose) and rate qd the state
+     * (sim_state_view.joint_state): revolute (1) about the line through the
+     * anchor along the axis, q in rad, or prismatic (2) along the axis, q in
+     * m; q is held within [lower, upper] by limit rows solved after the
+     * contacts in every sweep; gravity and contacts act on it through the
+     * joint.  A part never collides with the body it is joined to (its
+     * parent: the cabinet that carries the door).  At most 16 parts per
+     * scene; not arm links.  Needs the PGS solver without the learned warm
+     * start.  Parts start at rest (q = 0, qd = 0; h_vel is not read for them)
+     * and never sleep. */
+    const uint8_t *h_joint;        /* [N] 0 none, 1 revolute, 2 prismatic (only dynamic bodies) */
+    const float *h_joint_axis;     /* [N*3] unit axis (world, at the initial pose) */
+    const float *h_joint_anchor;   /* [N*3] a point of the hinge line (world, m; read for revolute) */
+    const float *h_joint_limits;   /* [N*2] lower <= upper limit of q */
+    const int32_t *h_joint_parent; /* [N] local index (within the scene) of the parent body, or -1 */
 } sim_batch_desc;
 
 typedef struct sim_handle sim_handle;
@@ -119,6 +137,9 @@ typedef struct sim_state_view {
     float *arm_state;     /* articulated arm only (else NULL): [S][21] per scene the joint rates
                              (rad/s), the motor targets (rad) and the last step's motor impulses
                              (N m s, the motors' warm start), 7 each */
+    float *joint_state;   /* container parts only (else NULL): [2][N] joint coordinate q and
+                             rate qd of every part (0 for the other bodies); a caller that
+                             writes q must move the part's pose to match */
     int cache_cap;        /* per-scene contact capacity (= max_contacts) */
     int32_t *cache_count; /* [S] contacts stored for the next step's warm start */
     uint32_t *cache_key;  /* [S][cache_cap] sorted contact keys */
@@ -220,8 +241,9 @@ int sim_set_export(sim_handle *h, int on);
 
 /* Change the solver settings used by later steps: SIM_PGS or SIM_JACOBI,
  * SIM_COLD / SIM_PREV / SIM_LEARNED start, residual tolerance (m/s; 0 =
- * fixed sweeps).  SIM_EINVAL on a bad value, SIM_ECAPACITY if a scene no
- * longer fits the persistent launch's LDS (settings unchanged). */
+ * fixed sweeps).  SIM_EINVAL on a bad value or on Jacobi or the learned
+ * start with an articulated arm or container parts, SIM_ECAPACITY if a scene
+ * no longer fits the persistent launch's LDS (settings unchanged). */
 int sim_set_solver(sim_handle *h, int solver, int warm_start, float tolerance);
 
 /* Sleeping islands for later steps (localized physics, Sec. 4.1: the robot
@@ -375,13 +397,14 @@ int sim_mlp_gather(sim_handle *h, float *d_x, float *d_t, long cap, float target
  * stats flags (visible until the next step).  Static and kinematic bodies
  * are copied like the others.  Asynchronous on the handle's stream;
  * SIM_EINVAL on NULL mask, pool, pose or vel, size < 1, or a missing theta
- * for an arm batch. */
+ * for an arm batch or joint_state for a batch with container parts. */
 typedef struct sim_reset_pool {
     int size;                 /* K */
     const float *pose;        /* [K][7][N] */
     const float *vel;         /* [K][6][N] */
     const float *theta;       /* [K][S][7] or NULL when the batch has no arm */
     const int32_t *index;     /* [S] pool entry per scene, or NULL (entry 0) */
+    const float *joint_state; /* [K][2][N] container parts' q and qd, or NULL when the batch has none */
 } sim_reset_pool;
 
 int sim_reset(sim_handle *h, const uint8_t *d_mask, const sim_reset_pool *pool);

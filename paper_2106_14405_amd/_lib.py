@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbsim.so")
 
-SIM_ABI_VERSION = 4
+SIM_ABI_VERSION = 5
 SIM_OK, SIM_EINVAL, SIM_EDEVICE, SIM_EWORKSPACE, SIM_EABI, SIM_ECAPACITY = 0, -1, -2, -3, -4, -5
 SPHERE, BOX, CAPSULE = 0, 1, 2
 DYNAMIC, STATIC, KINEMATIC = 0, 1, 2
@@ -36,12 +36,14 @@ class BatchDesc(C.Structure):
         ("max_pairs", C.c_int), ("max_contacts", C.c_int),
         ("solver", C.c_int), ("warm_start", C.c_int), ("tolerance", _f), ("threads", C.c_int),
         ("stream", C.c_void_p), ("hbm_min_bodies", C.c_int),
+        ("h_joint", _P(C.c_uint8)), ("h_joint_axis", _P(_f)), ("h_joint_anchor", _P(_f)),
+        ("h_joint_limits", _P(_f)), ("h_joint_parent", _P(C.c_int32)),
     ]
 
 
 class StateView(C.Structure):
     _fields_ = [("n_bodies", C.c_long), ("pose", C.c_void_p), ("vel", C.c_void_p), ("rest", C.c_void_p),
-                ("theta", C.c_void_p), ("arm_state", C.c_void_p),
+                ("theta", C.c_void_p), ("arm_state", C.c_void_p), ("joint_state", C.c_void_p),
                 ("cache_cap", C.c_int), ("cache_count", C.c_void_p), ("cache_key", C.c_void_p),
                 ("cache_lam", C.c_void_p)]
 
@@ -60,7 +62,7 @@ class StatsView(C.Structure):
 
 class ResetPool(C.Structure):
     _fields_ = [("size", C.c_int), ("pose", C.c_void_p), ("vel", C.c_void_p), ("theta", C.c_void_p),
-                ("index", C.c_void_p)]
+                ("index", C.c_void_p), ("joint_state", C.c_void_p)]
 
 
 class MlpWeights(C.Structure):

@@ -45,7 +45,7 @@ extern "C" int rbs_launch_query(int n_scenes, int max_bodies, long n_bodies, con
 extern "C" int rbs_launch_arm_pose(const rbs::StepParams* P, const uint8_t* mask, hipStream_t stream);
 extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, int K, const int32_t* index,
                                 const float* pool_pose, const float* pool_vel, const float* pool_theta,
-                                int32_t* count_a, int32_t* count_b, hipStream_t stream);
+                                const float* pool_joint, int32_t* count_a, int32_t* count_b, hipStream_t stream);
 
 namespace {
 
@@ -60,6 +60,7 @@ struct Layout {
   size_t off_body_offset, off_shape, off_motion, off_prm, off_inv_mass, off_inv_inertia, off_friction,
       off_restitution, off_pose, off_vel, off_rest, off_theta, off_arm_state, off_arm_base, off_scene_list;
   size_t off_arm_rows;
+  size_t off_joint, off_joint_axis, off_joint_anchor, off_joint_limits, off_joint_parent, off_joint_state;
   size_t off_ckey[2], off_clam[2], off_ccount[2], off_ccol[2];
   size_t off_x_pair, off_x_npairs, off_x_normal, off_x_point, off_x_phi, off_x_lambda, off_x_colour, off_x_feat;
   size_t off_raw, off_crec;
@@ -73,7 +74,10 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255u) & ~size_t(255u); }
 
-Layout make_layout(long S, long N, long PM, long CM, long n_hbm, long hbm_words, int arm) {
+// art: the arm mode plus rbs::kArtParts when the batch has container parts
+Layout make_layout(long S, long N, long PM, long CM, long n_hbm, long hbm_words, int art) {
+  const int arm = art & 3;
+  const bool parts = (art & rbs::kArtParts) != 0;
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
@@ -91,6 +95,13 @@ Layout make_layout(long S, long N, long PM, long CM, long n_hbm, long hbm_words,
   L.off_theta = take(4 * 7 * S);
   L.off_arm_state = take(arm == 2 ? 4 * 21 * S : 0);  // articulated arm: joint rates, motor targets, impulses
   L.off_arm_base = take(4 * 3 * S);
+  // container parts: joint kinds, axes, anchors, limits, parents; q and qd
+  L.off_joint = take(parts ? N : 0);
+  L.off_joint_axis = take(parts ? 4 * 3 * N : 0);
+  L.off_joint_anchor = take(parts ? 4 * 3 * N : 0);
+  L.off_joint_limits = take(parts ? 4 * 2 * N : 0);
+  L.off_joint_parent = take(parts ? 4 * N : 0);
+  L.off_joint_state = take(parts ? 4 * 2 * N : 0);
   L.off_scene_list = take(4 * S);
   for (int k = 0; k < 2; k++) {
     L.off_ckey[k] = take(4 * S * CM);
@@ -137,6 +148,8 @@ struct sim_handle {
   float last_dt;    // dt of the last step (0 before the first)
   int last_export;  // export was on during the last step
   int arm;                 // 0 none, 1 kinematic, 2 articulated with joint motors
+  bool parts;              // articulated container parts
+  int art;                 // arm | (rbs::kArtParts if parts): the layouts' articulation code
   float motor_kp, motor_max;
   float link_len[7];
   float arm_radius;
@@ -213,6 +226,15 @@ rbs::StepParams params(sim_handle* h) {
   P.theta = at<float>(h, L.off_theta);
   P.arm_state = h->arm == 2 ? at<float>(h, L.off_arm_state) : nullptr;
   P.arm_rows = h->arm == 2 ? at<float>(h, L.off_arm_rows) : nullptr;
+  if (h->parts) {
+    P.joint = at<uint8_t>(h, L.off_joint);
+    P.joint_axis = at<float>(h, L.off_joint_axis);
+    P.joint_anchor = at<float>(h, L.off_joint_anchor);
+    P.joint_limits = at<float>(h, L.off_joint_limits);
+    P.joint_parent = at<int32_t>(h, L.off_joint_parent);
+    P.joint_state = at<float>(h, L.off_joint_state);
+  }
+  P.art = h->art;
   P.motor_kp = h->motor_kp;
   P.motor_max = h->motor_max;
   P.arm_base = at<float>(h, L.off_arm_base);
@@ -313,6 +335,36 @@ int validate(const sim_batch_desc* d, Caps* caps) {
                                               : "the last 7 bodies of an arm scene must be kinematic capsules");
       }
   }
+  if (d->h_joint) {
+    if (!d->h_joint_axis || !d->h_joint_anchor || !d->h_joint_limits || !d->h_joint_parent)
+      return fail(SIM_EINVAL, "container parts need axis, anchor, limit and parent arrays");
+    if (d->solver != SIM_PGS || d->warm_start == SIM_LEARNED)
+      return fail(SIM_EINVAL, "container parts need the PGS solver without the learned warm start");
+    for (int s = 0; s < d->num_scenes; s++) {
+      const int b0 = d->h_body_offset[s], nb = d->h_body_offset[s + 1] - b0;
+      int np = 0;
+      for (int k = 0; k < nb; k++) {
+        const long i = b0 + k;
+        const int kind = d->h_joint[i];
+        if (kind == 0) continue;
+        if (kind > 2) return fail(SIM_EINVAL, "joint kind must be 0, 1 or 2");
+        if (d->h_motion[i] != SIM_DYNAMIC) return fail(SIM_EINVAL, "a container part must be a dynamic body");
+        if (d->arm && k >= nb - 7) return fail(SIM_EINVAL, "an arm link cannot be a container part");
+        const float* a = d->h_joint_axis + 3 * i;
+        const float* o = d->h_joint_anchor + 3 * i;
+        const float* lim = d->h_joint_limits + 2 * i;
+        const double n2 = (double)a[0] * a[0] + (double)a[1] * a[1] + (double)a[2] * a[2];
+        if (!(std::fabs(n2 - 1.0) <= 1e-4)) return fail(SIM_EINVAL, "a joint axis must be a unit vector");
+        if (!std::isfinite(o[0]) || !std::isfinite(o[1]) || !std::isfinite(o[2]))
+          return fail(SIM_EINVAL, "joint anchors must be finite");
+        if (!std::isfinite(lim[0]) || !std::isfinite(lim[1]) || !(lim[0] <= lim[1]))
+          return fail(SIM_EINVAL, "joint limits must be finite with lower <= upper");
+        const int par = d->h_joint_parent[i];
+        if (par < -1 || par >= nb || par == k) return fail(SIM_EINVAL, "bad joint parent index");
+        if (++np > rbs::kMaxParts) return fail(SIM_ECAPACITY, "a scene exceeds 16 container parts");
+      }
+    }
+  }
   if (d->max_pairs < 1 || d->max_contacts < 1) return fail(SIM_EINVAL, "capacities must be >= 1");
   if (d->max_pairs > (1 << 20) || d->max_contacts > (1 << 20)) return fail(SIM_EINVAL, "capacity too large");
   // the narrowphase stages 4 contacts per pair in a contact record slot set
@@ -328,6 +380,9 @@ int validate(const sim_batch_desc* d, Caps* caps) {
   caps->ok = true;
   return SIM_OK;
 }
+
+// articulation code of a descriptor (the layouts' last argument)
+int desc_art(const sim_batch_desc* d) { return d->arm | (d->h_joint ? rbs::kArtParts : 0); }
 
 int lds_bytes(int NB, int PM, int CM, int T, int solver, int warm, int arm) {
   rbs::LdsLayout L = rbs::lds_layout(NB, PM, CM, T / 64, solver, warm, arm);
@@ -411,8 +466,8 @@ int build_queues(sim_handle* h, int wave_max_bodies, bool by_table = false, uint
     if (in_hbm[s]) continue;
     const int nb = h->body_offset[s + 1] - h->body_offset[s];
     const int pm = rbs::scene_cap(nb, h->PM), cm = rbs::scene_cap(nb, h->CM);
-    const int need_wave = rbs::lds_layout(nb, pm, cm, 1, h->solver, h->warm, h->arm).total;
-    const int need_team = rbs::lds_layout(nb, pm, cm, 4, h->solver, h->warm, h->arm).total;
+    const int need_wave = rbs::lds_layout(nb, pm, cm, 1, h->solver, h->warm, h->art).total;
+    const int need_team = rbs::lds_layout(nb, pm, cm, 4, h->solver, h->warm, h->art).total;
     const bool to_wave = by_table ? ((buckets >> body_bucket(nb)) & 1u) != 0u : nb <= wave_max_bodies;
     if (to_wave && need_wave <= lds_words / 4)
       wave.push_back(s);
@@ -465,7 +520,7 @@ rbs::QueueParams queue_params(sim_handle* h) {
 rbs::LdsLayout hbm_layout(const sim_handle* h) {
   int nb = 0;
   for (int s : h->hbm) nb = std::max(nb, h->body_offset[s + 1] - h->body_offset[s]);
-  return rbs::lds_layout(nb, rbs::scene_cap(nb, h->PM), rbs::scene_cap(nb, h->CM), 4, h->solver, h->warm, h->arm);
+  return rbs::lds_layout(nb, rbs::scene_cap(nb, h->PM), rbs::scene_cap(nb, h->CM), 4, h->solver, h->warm, h->art);
 }
 
 // One step through a graph of (queue reset, persistent kernel) captured once
@@ -536,6 +591,7 @@ std::vector<StateSpan> state_spans(const sim_handle* h) {
   std::vector<StateSpan> v = {{L.off_pose, 4 * 7 * N}, {L.off_vel, 4 * 6 * N}, {L.off_rest, 4 * N},
                               {L.off_theta, 4 * 7 * S}};
   if (h->arm == 2) v.push_back({L.off_arm_state, 4 * 21 * S});
+  if (h->parts) v.push_back({L.off_joint_state, 4 * 2 * N});
   for (int k = 0; k < 2; k++) {
     v.push_back({L.off_ckey[k], 4 * S * CM});
     v.push_back({L.off_clam[k], 4 * 4 * S * CM});
@@ -570,8 +626,8 @@ size_t sim_workspace_bytes(const sim_batch_desc* d) {
   Caps c;
   if (validate(d, &c) != SIM_OK) return 0;
   const HbmSplit sp = hbm_split(d->h_body_offset, d->num_scenes, d->max_pairs, d->max_contacts, device_lds_limit(),
-                                d->hbm_min_bodies, d->arm);
-  return make_layout(d->num_scenes, c.N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words, d->arm)
+                                d->hbm_min_bodies, desc_art(d));
+  return make_layout(d->num_scenes, c.N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words, desc_art(d))
       .total;
 }
 
@@ -584,8 +640,9 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   const int S = d->num_scenes;
   const long N = c.N;
   const int limit = device_lds_limit();
-  HbmSplit sp = hbm_split(d->h_body_offset, S, d->max_pairs, d->max_contacts, limit, d->hbm_min_bodies, d->arm);
-  Layout lay = make_layout(S, N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words, d->arm);
+  const int art = desc_art(d);
+  HbmSplit sp = hbm_split(d->h_body_offset, S, d->max_pairs, d->max_contacts, limit, d->hbm_min_bodies, art);
+  Layout lay = make_layout(S, N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words, art);
   if (!d_workspace || workspace_bytes < lay.total) return fail(SIM_EWORKSPACE, "workspace too small");
   if (((uintptr_t)d_workspace & 255u) != 0) return fail(SIM_EWORKSPACE, "workspace must be 256-byte aligned");
   const int T = d->threads ? d->threads : 64;
@@ -593,7 +650,7 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   // (the split above sends every larger one to global memory)
   const int nbl = sp.nb_lds;
   int need = nbl ? lds_bytes(nbl, rbs::scene_cap(nbl, d->max_pairs), rbs::scene_cap(nbl, d->max_contacts), T,
-                             rbs::SOLVER_JACOBI, rbs::WARM_LEARNED, d->arm)
+                             rbs::SOLVER_JACOBI, rbs::WARM_LEARNED, art)
                  : 0;
   if (need > limit)
     return fail(SIM_ECAPACITY, "per-scene working set (" + std::to_string(need) + " B) exceeds LDS (" +
@@ -615,6 +672,8 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   h->last_dt = 0.f;
   h->last_export = 0;
   h->arm = d->arm;
+  h->parts = d->h_joint != nullptr;
+  h->art = art;
   h->motor_kp = 0.3f;      // position gain of the joint motors (Sec. 5)
   h->motor_max = 10.0f;    // largest motor impulse per step, N s (Sec. 5)
   for (int k = 0; k < 7; k++) h->link_len[k] = d->link_len[k];
@@ -712,6 +771,24 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
       for (int k = 0; k < 7; k++) arm_state[21 * s2 + 7 + k] = theta[7 * s2 + k];
     if (e == hipSuccess) e = up(lay.off_arm_state, arm_state.data(), 4 * 21 * S);
   }
+  std::vector<float> jax, jan, jlim;
+  if (d->h_joint) {  // planes [3][N], [3][N], [2][N]; q and qd start at 0 (the workspace is cleared)
+    jax.assign(3 * (size_t)N, 0.f);
+    jan.assign(3 * (size_t)N, 0.f);
+    jlim.assign(2 * (size_t)N, 0.f);
+    for (long i = 0; i < N; i++) {
+      for (int k = 0; k < 3; k++) {
+        jax[k * N + i] = d->h_joint_axis[3 * i + k];
+        jan[k * N + i] = d->h_joint_anchor[3 * i + k];
+      }
+      for (int k = 0; k < 2; k++) jlim[k * N + i] = d->h_joint_limits[2 * i + k];
+    }
+    if (e == hipSuccess) e = up(lay.off_joint, d->h_joint, N);
+    if (e == hipSuccess) e = up(lay.off_joint_axis, jax.data(), 4 * 3 * N);
+    if (e == hipSuccess) e = up(lay.off_joint_anchor, jan.data(), 4 * 3 * N);
+    if (e == hipSuccess) e = up(lay.off_joint_limits, jlim.data(), 4 * 2 * N);
+    if (e == hipSuccess) e = up(lay.off_joint_parent, d->h_joint_parent, 4 * N);
+  }
   if (e == hipSuccess) e = up(lay.off_arm_base, base.data(), 4 * 3 * S);
   if (e == hipSuccess) e = up(lay.off_scene_list, order.data(), 4 * S);
   if (e == hipSuccess) e = up(lay.off_glist, glist.data(), 4 * S);
@@ -758,7 +835,7 @@ int sim_step(sim_handle* h, const float* d_actions, float dt, int iters) {
     rc = 0;
     if (nl > 0) {
       rbs::LdsLayout L = rbs::lds_layout(nbl, rbs::scene_cap(nbl, h->PM), rbs::scene_cap(nbl, h->CM),
-                                         h->threads / 64, h->solver, h->warm, h->arm);
+                                         h->threads / 64, h->solver, h->warm, h->art);
       if (L.total * 4 > h->lds_limit) return fail(SIM_ECAPACITY, "working set exceeds LDS");
       rc = rbs_launch_step(&P, &L, h->threads, nl, h->stream);
     }
@@ -822,6 +899,7 @@ int sim_state(const sim_handle* hc, sim_state_view* out) {
   out->rest = at<int32_t>(h, L.off_rest);
   out->theta = h->arm ? at<float>(h, L.off_theta) : nullptr;
   out->arm_state = h->arm == 2 ? at<float>(h, L.off_arm_state) : nullptr;
+  out->joint_state = h->parts ? at<float>(h, L.off_joint_state) : nullptr;
   out->cache_cap = h->CM;
   out->cache_count = at<int32_t>(h, L.off_ccount[h->parity]);
   out->cache_key = at<uint32_t>(h, L.off_ckey[h->parity]);
@@ -868,6 +946,8 @@ int sim_set_solver(sim_handle* h, int solver, int warm_start, float tolerance) {
     return fail(SIM_EINVAL, "the learned warm start is not available with sleeping islands");
   if (h->arm == 2 && (solver != SIM_PGS || warm_start == SIM_LEARNED))
     return fail(SIM_EINVAL, "the articulated arm needs the PGS solver without the learned warm start");
+  if (h->parts && (solver != SIM_PGS || warm_start == SIM_LEARNED))
+    return fail(SIM_EINVAL, "container parts need the PGS solver without the learned warm start");
   const int old_solver = h->solver, old_warm = h->warm;
   h->solver = solver;
   h->warm = warm_start;
@@ -907,9 +987,11 @@ int sim_reset(sim_handle* h, const uint8_t* d_mask, const sim_reset_pool* pool) 
   if (!d_mask || !pool || !pool->pose || !pool->vel) return fail(SIM_EINVAL, "mask, pool, pose and vel are required");
   if (pool->size < 1) return fail(SIM_EINVAL, "pool size must be >= 1");
   if (h->arm && !pool->theta) return fail(SIM_EINVAL, "arm scenes need theta");
+  if (h->parts && !pool->joint_state) return fail(SIM_EINVAL, "container parts need joint_state");
   rbs::StepParams P = params(h);
   int rc = rbs_launch_reset(&P, d_mask, pool->size, pool->index, pool->pose, pool->vel, h->arm ? pool->theta : nullptr,
-                            at<int32_t>(h, h->lay.off_ccount[0]), at<int32_t>(h, h->lay.off_ccount[1]), h->stream);
+                            h->parts ? pool->joint_state : nullptr, at<int32_t>(h, h->lay.off_ccount[0]),
+                            at<int32_t>(h, h->lay.off_ccount[1]), h->stream);
   if (rc == 0 && h->arm) rc = rbs_launch_arm_pose(&P, d_mask, h->stream);
   if (rc != 0) return fail(SIM_EDEVICE, "reset launch failed");
   return SIM_OK;

@@ -62,6 +62,16 @@ struct StepParams {
   float* arm_rows;          // arm 2: [S][kMaxColours][kArmRowWords] joint-space rows of the arm's contacts
   float motor_kp;           // arm 2: motor position gain
   float motor_max;          // arm 2: largest motor impulse per step (N s)
+  // articulated container parts (null: none): per body the joint kind (0
+  // none, 1 revolute, 2 prismatic), unit axis and anchor (world), limits of
+  // the coordinate, local index of the static base it is joined to (-1 none)
+  const uint8_t* joint;     // [N]
+  const float* joint_axis;  // [3][N]
+  const float* joint_anchor;// [3][N]
+  const float* joint_limits;// [2][N]
+  const int32_t* joint_parent;  // [N]
+  float* joint_state;       // [2][N] joint coordinate and its rate
+  int art;                  // articulation code of the layouts: arm | (kArtParts when joint is set)
   const float* arm_base;    // [S][3]
   float link_len[7];
   float arm_radius;
@@ -136,7 +146,7 @@ struct QueueParams {
 // and increments); outputs (arm force partial sums).  Until the setup
 // writes it, lam holds each contact's previous-impulse slot.
 struct LdsLayout {
-  int geo, dyn, dyn2, ckey, lam, perm, fresh, misc, arm, hist, hbase;
+  int geo, dyn, dyn2, ckey, lam, perm, fresh, misc, arm, parts, hist, hbase;
   int scr;
   int pk, pk2, lo, hi, skey, sval, skey2, sval2, nperm, ncnt;
   int colour, deg, lstart, list, rank, cv0, ck1;
@@ -167,6 +177,20 @@ enum { ARM_MI = 0, ARM_DQ = 52, ARM_QREF = 60, ARM_LAM = 68, ARM_BIAS = 76, ARM_
 // global words per colour of the joint-space rows of the arm contact in that
 // colour (g_n, g_t1, g_t2, then M^-1 g of each; 7 words apiece)
 constexpr int kArmRowWords = 48;
+// Articulated container parts in LDS (the limit rows): per part 16 words:
+// body, kind (1 revolute, 2 prismatic), mass about the joint M, the two
+// limit targets, the two limit impulses, 1 / M, axis x y z; at most
+// kMaxParts parts per scene.  In the dyn region a part's inverse-mass word
+// is a flag (-1 prismatic, -2 revolute), its inverse inertia the projector
+// a a^T / M, and a revolute part's velocity is taken about its hinge point
+// (linear part zero, w = qd a); dyn2's fourth word holds its part slot.
+constexpr int kMaxParts = 16;
+enum { PART_BODY = 0, PART_KIND = 1, PART_M = 2, PART_BIAS = 3, PART_LAM = 5, PART_IM = 7, PART_AX = 8,
+       kPartStride = 16, kPartWords = 4 + kMaxParts * kPartStride };  // word 0 of the region: the part count
+constexpr float kPrismaticFlag = -1.f, kRevoluteFlag = -2.f;
+// articulation code of a batch for the layouts: the arm mode (0, 1, 2) plus
+// kArtParts when it has container parts
+constexpr int kArtParts = 8;
 constexpr int kRec = 5;        // float4 per contact in the solver records
 
 // float4 per scene of the solver-record buffer: the records of CM contacts,
@@ -190,7 +214,8 @@ inline __host__ __device__ LdsLayout lds_layout(int NB, int PM, int CM, int wave
   L.perm = take(CM);
   L.fresh = (warm == WARM_LEARNED) ? take((CM + 31) / 32) : -1;
   L.misc = take(kMiscWords);
-  L.arm = arm == 2 ? take(kArmWords) : -1;
+  L.arm = (arm & 3) == 2 ? take(kArmWords) : -1;
+  L.parts = (arm & kArtParts) ? take(kPartWords) : -1;
   L.hist = take(256 * waves);
   L.hbase = take(256);
   L.scr = o;

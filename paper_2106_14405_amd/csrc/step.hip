@@ -495,7 +495,7 @@ __device__ __forceinline__ void store_vel(const LdsLayout& L, Smem S, int i, con
 // Writes back a body of a contact update: dynamic bodies to their slot, the
 // others (ground, static, kinematic) to the sink slot, without a branch.
 __device__ __forceinline__ void store_vel_dyn(const LdsLayout& L, Smem S, int i, const Vel& b) {
-  store_vel(L, S, b.im > 0.f ? i : -2, b);
+  store_vel(L, S, b.im != 0.f ? i : -2, b);  // (negative: a container part's flag)
 }
 
 // Relative velocity of the contact point: (v_a + w_a x r_a) - (v_b + w_b x r_b).
@@ -503,12 +503,29 @@ __device__ __forceinline__ V3 point_vel(V3 va, V3 wa, V3 vb, V3 wb, V3 ra, V3 rb
   return (va + cross(wa, ra)) - (vb + cross(wb, rb));
 }
 
+// Impulse P at r on one body.  With container parts (parts true): a
+// prismatic part's velocity changes by its projector a a^T / m times P, a
+// revolute part's (about its hinge point) by a a^T / I_o times r x P.
+__device__ __forceinline__ void apply_body(Vel& A, V3 r, V3 P, bool parts) {
+  if (parts && A.im == kPrismaticFlag) {
+    A.v = A.v + Imul(A.I, P);
+  } else {
+    A.v = A.v + P * (parts ? fmaxf(A.im, 0.f) : A.im);
+    A.w = A.w + Imul(A.I, cross(r, P));
+  }
+}
+
 // Impulse P at the contact point on body a and -P on body b.
-__device__ __forceinline__ void apply_impulse(Vel& A, Vel& B, V3 ra, V3 rb, V3 P) {
-  A.v = A.v + P * A.im;
-  A.w = A.w + Imul(A.I, cross(ra, P));
-  B.v = B.v - P * B.im;
-  B.w = B.w - Imul(B.I, cross(rb, P));
+__device__ __forceinline__ void apply_impulse(Vel& A, Vel& B, V3 ra, V3 rb, V3 P, bool parts = false) {
+  if (!parts) {
+    A.v = A.v + P * A.im;
+    A.w = A.w + Imul(A.I, cross(ra, P));
+    B.v = B.v - P * B.im;
+    B.w = B.w - Imul(B.I, cross(rb, P));
+  } else {
+    apply_body(A, ra, P, true);
+    apply_body(B, rb, -P, true);
+  }
 }
 
 // Synchronisation between colour batches: a single-wave team needs only a
@@ -536,6 +553,7 @@ struct ArmCtx {
   bool on;
   float* dq;           // LDS [7] joint-rate changes since the setup
   const float* rows;   // global [kMaxColours][kArmRowWords]
+  bool parts;          // the scene has container parts (flagged bodies, limit rows)
 };
 
 // Row velocities g . dq of the arm contact in colour c (n, t1, t2).
@@ -590,7 +608,7 @@ __device__ __forceinline__ float pgs_update(const LdsLayout& L, Smem S, const Re
   float l2 = lam.z - m2 * ((u2 + lam.w) + k2n * dn);
   proj_disk(l1, l2, mu * ln);
   const float d1 = l1 - lam.y, d2 = l2 - lam.z;
-  apply_impulse(A, B, ra, rb, n * dn + t1 * d1 + t2 * d2);
+  apply_impulse(A, B, ra, rb, n * dn + t1 * d1 + t2 * d2, arm.parts);
   if (asg != 0.f) arm_row_apply(arm, c, asg, dn, d1, d2);
   store_vel_dyn(L, S, a, A);
   store_vel_dyn(L, S, b, B);
@@ -641,8 +659,12 @@ __device__ __forceinline__ float pgs_update_pair(const LdsLayout& L, Smem S, con
   proj_disk(l1, l2, mu * ln);
   const float d1 = l1 - lam.y, d2 = l2 - lam.z;
   const V3 P = (n * dn + t1 * d1 + t2 * d2) * sg;
-  M.v = M.v + P * M.im;
-  M.w = M.w + Imul(M.I, cross(r, P));
+  if (arm.parts) {
+    apply_body(M, r, P, true);
+  } else {
+    M.v = M.v + P * M.im;
+    M.w = M.w + Imul(M.I, cross(r, P));
+  }
   store_vel_dyn(L, S, me, M);
   if (arm_lane) arm_row_apply(arm, c, sg, dn, d1, d2);
   if (!side) st4(S.f + L.lam, i, make_float4(ln, l1, l2, lam.w));
@@ -696,7 +718,7 @@ __device__ __forceinline__ void apply_all(const LdsLayout& L, Smem S, const floa
       const V3 n = xyz(R.r[0]);
       V3 t1, t2;
       tangents_coef(n, R.r[4].z, t1, t2);
-      apply_impulse(A, B, xyz(R.r[1]), xyz(R.r[2]), n * lam.x + t1 * lam.y + t2 * lam.z);
+      apply_impulse(A, B, xyz(R.r[1]), xyz(R.r[2]), n * lam.x + t1 * lam.y + t2 * lam.z, arm.parts);
       store_vel_dyn(L, S, a, A);
       store_vel_dyn(L, S, b, B);
       if (arm.on && R.r[4].y != 0.f) arm_row_apply(arm, c, R.r[4].y, lam.x, lam.y, lam.z);
@@ -744,6 +766,116 @@ __device__ __forceinline__ float arm_motor_sweep(const LdsLayout& L, Smem S, con
   return r;
 }
 
+// ---- articulated container parts -----------------------------------------
+// A door or drawer (a part) is one rigid body with one degree of freedom
+// relative to the world: a revolute joint about a fixed hinge line (anchor
+// o, unit axis a) or a prismatic one along a; its coordinate q and rate qd
+// are the state, q held within limits.  The body moves with the rate (w =
+// qd a, v = w x (c - o) for a hinge; v = qd a for a slide), and an impulse P
+// at p changes qd by (a . ((p - o) x P)) / M or (a . P) / M, M the mass
+// about the joint (the moment of inertia about the hinge line, or the
+// mass).  In the solver's LDS slots a part is a body whose inverse inertia
+// is the projector a a^T / M: a hinge's velocity is taken about its hinge
+// point (its rows' lever arms run from o), a slide's linear velocity
+// changes by a a^T P / M and its angular stays zero.  Parts keep their whole
+// velocity in the slot during the solve (their setup velocity is not
+// folded into the rows), like the kinematic bodies.
+
+// Parts of the scene: slots in body order (wave 0, a ballot per 64
+// bodies), rate plus gravity over the step (its moment about the hinge, or
+// its force along the slide, over M), slot velocities and projector, and the
+// two limit rows (q - lower >= 0, upper - q >= 0) with the contacts'
+// speculative target: a gap g > 0 may close within the step (-g / dt), a
+// violation is pushed back at baumgarte / dt of it.
+__device__ __forceinline__ void part_setup(const StepParams& P, const LdsLayout& L, Smem S, int b0, int nb, float dt,
+                                           V3 g, int lane) {
+  const long N = P.n_bodies;
+  float* pt = S.f + L.parts;
+  int np = 0;
+  for (int i0 = 0; i0 < nb; i0 += 64) {
+    const int i = i0 + lane;
+    const long gi = b0 + i;
+    const int kind = (i < nb && is_dyn_meta(body_meta(L, S, i))) ? (int)P.joint[gi] : 0;
+    const u64 m = __ballot(kind != 0);
+    const int slot = np + (int)lanes_below(m);
+    np += __popcll(m);
+    if (kind == 0 || slot >= kMaxParts) continue;
+    const V3 a = v3(P.joint_axis[gi], P.joint_axis[N + gi], P.joint_axis[2 * N + gi]);
+    const V3 o = v3(P.joint_anchor[gi], P.joint_anchor[N + gi], P.joint_anchor[2 * N + gi]);
+    const float mass = 1.0f / P.inv_mass[gi];
+    const Geom G = load_geom(L, S, i);
+    const bool rev = kind == 1;
+    float M = mass, gq = dot(a, g * mass);
+    if (rev) {
+      // principal moments about the body axes, the axis in body coordinates
+      const V3 al = v3(dot(col(G.R, 0), a), dot(col(G.R, 1), a), dot(col(G.R, 2), a));
+      const V3 d = cross(a, G.x - o);
+      M = al.x * al.x / P.inv_inertia[gi] + al.y * al.y / P.inv_inertia[N + gi] +
+          al.z * al.z / P.inv_inertia[2 * N + gi] + mass * len2(d);
+      gq = dot(a, cross(G.x - o, g * mass));
+    }
+    const float qd = P.joint_state[N + gi] + dt * gq / M;
+    const float iM = 1.0f / M;
+    const V3 u = a * qd;
+    const float mu = S.f[L.dyn + kDynWords * i + 7];
+    st4(S.f + L.dyn, 3 * i, rev ? make_float4(0.f, 0.f, 0.f, kRevoluteFlag) : f4(u, kPrismaticFlag));
+    st4(S.f + L.dyn, 3 * i + 1, rev ? f4(u, mu) : make_float4(0.f, 0.f, 0.f, mu));
+    st4(S.f + L.dyn, 3 * i + 2, make_float4(a.x * a.x * iM, a.y * a.y * iM, a.z * a.z * iM, a.x * a.y * iM));
+    const float e = S.f[L.dyn2 + 4 * i + 2];
+    st4(S.f + L.dyn2, i, make_float4(a.x * a.z * iM, a.y * a.z * iM, e, (float)slot));
+    const float q = P.joint_state[gi];
+    const float gap[2] = {q - P.joint_limits[gi], P.joint_limits[N + gi] - q};
+    float* E = pt + 4 + slot * kPartStride;
+    E[PART_BODY] = __uint_as_float((uint32_t)i);
+    E[PART_KIND] = (float)kind;
+    E[PART_M] = M;
+    E[PART_IM] = iM;
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      E[PART_BIAS + r] = gap[r] > 0.f ? -gap[r] / dt : P.baumgarte / dt * (-gap[r]);
+      E[PART_LAM + r] = 0.f;
+    }
+    E[PART_AX] = a.x;
+    E[PART_AX + 1] = a.y;
+    E[PART_AX + 2] = a.z;
+  }
+  if (lane == 0) S.u[L.parts] = (uint32_t)(np < kMaxParts ? np : kMaxParts);
+}
+
+// One Gauss-Seidel pass over the parts' limit rows by wave 0, a lane per
+// part (the rows of different parts touch different bodies): the lower
+// row (+1 on the rate), then the upper (-1), impulses >= 0.  Returns the
+// pass's max |dlambda| / M of the lane's part (0 on the other lanes).
+__device__ __forceinline__ float part_limit_sweep(const LdsLayout& L, Smem S, int lane) {
+  float r = 0.f;
+  const int np = (int)S.u[L.parts];
+  if (lane < np) {
+    float* E = S.f + L.parts + 4 + lane * kPartStride;
+    const int i = (int)__float_as_uint(E[PART_BODY]);
+    const float M = E[PART_M], iM = E[PART_IM];
+    const V3 a = v3(E[PART_AX], E[PART_AX + 1], E[PART_AX + 2]);
+    // the slot that carries the rate: angular for a hinge, linear for a slide
+    float* u = S.f + L.dyn + kDynWords * i + (E[PART_KIND] == 1.f ? 4 : 0);
+    V3 w = v3(u[0], u[1], u[2]);
+    float qd = dot(a, w);
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const float sg = k == 0 ? 1.f : -1.f;
+      const float l0 = E[PART_LAM + k];
+      const float l = fmaxf(0.f, l0 + M * (E[PART_BIAS + k] - sg * qd));
+      const float dl = l - l0;
+      E[PART_LAM + k] = l;
+      qd += sg * dl * iM;
+      w = w + a * (sg * dl * iM);
+      r = fmaxf(r, fabsf(dl) * iM);
+    }
+    u[0] = w.x;
+    u[1] = w.y;
+    u[2] = w.z;
+  }
+  return r;
+}
+
 // Sweeps of projected Gauss-Seidel, colour batch after colour batch; the
 // record of a lane's next batch is loaded while the current one is solved.
 // Stops after `iters` sweeps or once a sweep's residual is <= tol (tol > 0).
@@ -756,14 +888,18 @@ __device__ __forceinline__ void solve_pgs(const LdsLayout& L, Smem S, const floa
   const int tid = tm.tid, T = tm.T;
   int sweeps = 0;
   float res = 0.f;
-  // the arm's motor rows after the contacts of every sweep (wave 0)
+  // the arm's motor rows, then the parts' limit rows, after the contacts of
+  // every sweep (wave 0)
   auto motors = [&]() __attribute__((always_inline)) -> float {
     float rm = 0.f;
-    if (tid < 64) rm = arm_motor_sweep(L, S, tm, motor_max);
+    if (tid < 64) {
+      if (arm.on) rm = arm_motor_sweep(L, S, tm, motor_max);
+      if (arm.parts) rm = fmaxf(rm, part_limit_sweep(L, S, tid));
+    }
     colour_sync(tm);
     return rm;
   };
-  if (ncol == 0 && arm.on) {  // motor rows only
+  if (ncol == 0 && (arm.on || arm.parts)) {  // motor and limit rows only
     for (int it = 0; it < iters; it++) {
       const float r = motors();
       sweeps++;
@@ -844,7 +980,7 @@ __device__ __forceinline__ void solve_pgs(const LdsLayout& L, Smem S, const floa
         batch(c, ra, rb);
         ra = rb;
       }
-      if (arm.on) r = fmaxf(r, motors());
+      if (arm.on || arm.parts) r = fmaxf(r, motors());
       sweeps++;
       if (tol > 0.f || it == iters - 1) {
         res = block_max(r, misc, tm);
@@ -1134,11 +1270,13 @@ __device__ __forceinline__ void arm_contact_rows(const LdsLayout& L, Smem S, flo
 // island sleeps when every body in it has ended sleep_steps steps at rest and
 // none of them touches a kinematic body; a sleeping body gets the asleep bit
 // in its meta word and zero velocity, and counts as not dynamic for the
-// colouring, the solve and the integration.  Uses the colouring's per-body
-// scratch (deg, lstart), which is free until the colouring starts.
+// colouring, the solve and the integration.  A container part (parts
+// true: flagged in its inverse-mass word) never sleeps and keeps its island
+// awake.  Uses the colouring's per-body scratch (deg, lstart), which is free
+// until the colouring starts.
 template <class TM>
 __device__ __forceinline__ void sleep_islands(const StepParams& P, const LdsLayout& L, Smem S, long b0, int nb, int nc,
-                              uint32_t* misc, const TM tm) {
+                              uint32_t* misc, const TM tm, bool parts) {
   const int tid = tm.tid, T = tm.T;
   uint32_t* lab = S.u + L.deg;
   uint32_t* wake = S.u + L.lstart;
@@ -1178,7 +1316,9 @@ __device__ __forceinline__ void sleep_islands(const StepParams& P, const LdsLayo
     team_sync(tm);
   }
   for (int i = tid; i < nb; i += T)
-    if (is_dyn_meta(body_meta(L, S, i)) && P.rest[b0 + i] < P.sleep_steps) wake[lab[i]] = 1u;
+    if (is_dyn_meta(body_meta(L, S, i)) &&
+        (P.rest[b0 + i] < P.sleep_steps || (parts && S.f[L.dyn + kDynWords * i + 3] < 0.f)))
+      wake[lab[i]] = 1u;
   for (int q = tid; q < nc; q += T) {
     const uint32_t key = ckeys[q];
     const int a = (int)(key >> 20), b = (int)((key >> 8) & 0xFFFu);
@@ -1207,7 +1347,7 @@ __device__ __forceinline__ V3 setup_lin_vel(const StepParams& P, long gi, long N
   return v3(P.vel[gi], P.vel[N + gi], P.vel[2 * N + gi]) + g * dt;
 }
 
-template <bool kLearned, bool kArm, class TM>
+template <bool kLearned, bool kArt, class TM>
 __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout& L, Smem S, const int s,
                                            const TM tm) {
   const int tid = tm.tid, T = tm.T;
@@ -1230,8 +1370,10 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
 
   // ---- load bodies; a2: gravity, world inverse inertia -----------------
   const V3 g = v3(P.gx, P.gy, P.gz);
-  // the articulated arm (its own kernels: compiled out of the others)
-  constexpr bool arm2 = kArm && !kLearned;
+  // the articulated arm and the container parts (their own kernels:
+  // compiled out of the others)
+  const bool arm2 = kArt && !kLearned && P.arm == 2;
+  const bool parts = kArt && !kLearned && P.joint != nullptr;
   const int arm0 = arm2 ? nb - 7 : nb;  // its first link
   for (int i = tid; i < nb; i += T) {
     const long gi = b0 + i;
@@ -1272,6 +1414,10 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   if (tid < kDynWords) S.f[L.dyn - kDynWords + tid] = 0.f;
   if (tid < 4) S.f[L.dyn2 - 4 + tid] = 0.f;
   team_sync(tm);
+  if (parts) {  // the parts' rates, projectors and limit rows
+    if (tid < 64) part_setup(P, L, S, b0, nb, dt, g, tid);
+    team_sync(tm);
+  }
   TRACE(1);
   // ---- a1: arm at theta_t, link velocities from the actions -------------
   float thd[7];
@@ -1313,7 +1459,10 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     }
     uint32_t meta = body_meta(L, S, i);
     st4(S.f + L.lo, i, f4(lo, is_dyn_meta(meta) ? 1.f : (((meta >> 8) & 255u) == ARMLINK ? 2.f : 0.f)));
-    st4(S.f + L.hi, i, f4(hi, 0.f));
+    // a part: 1 + the local index of the base it is joined to (never a pair)
+    float base = 0.f;
+    if (parts && S.f[L.dyn + kDynWords * i + 3] < 0.f) base = (float)(P.joint_parent[b0 + i] + 1);
+    st4(S.f + L.hi, i, f4(hi, base));
     S.u[L.skey + i] = orderable(lo.x);
     S.u[L.sval + i] = (uint32_t)i;
   }
@@ -1380,6 +1529,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
         if (loi.w == 2.f && loj.w == 2.f) continue;  // two links of the arm: joined, not in contact
         const float4 hij = ld4(S.f + L.hi, j);
         if (loj.y <= hii.y && loi.y <= hij.y && loj.z <= hii.z && loi.z <= hij.z) {
+          if (parts && (hii.w == (float)(j + 1) || hij.w == (float)(i + 1))) continue;  // a part and its base
           int a = i < j ? i : j, bb = i < j ? j : i;
           uint32_t slot = atomicAdd(&misc[M_NPAIRS], 1u);
           if ((int)slot < PMs) pk[slot] = ((uint32_t)a << 11) | (uint32_t)bb;
@@ -1569,7 +1719,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   // sleeping islands (not compiled into the learned kernels, whose registers
   // are at their limit: the library refuses sleeping with the learned start)
   if constexpr (!kLearned) {
-    if (P.sleep_speed > 0.f) sleep_islands(P, L, S, b0, nb, nc, misc, tm);
+    if (P.sleep_speed > 0.f) sleep_islands(P, L, S, b0, nb, nc, misc, tm, parts);
   }
 
   // ---- a9: colouring -----------------------------------------------------
@@ -1881,16 +2031,30 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
         arm_contact_rows(L, S, P.arm_rows + ((long)s * kMaxColours + colour[q]) * kArmRowWords,
                          (asg > 0.f ? a : b) - arm0, p, dirs, asg, ka, kc, ua);
     }
+    // a container part: a hinge's lever arm runs from its hinge point; a
+    // slide's rows act through its linear projector (d . (a a^T / M) d)
+    bool slideA = false, slideB = false;
+    float imA = A.im, imB = B.im;
+    if (parts) {
+      if (A.im == kRevoluteFlag) c.ra = p - v3(P.joint_anchor[b0 + a], P.joint_anchor[N + b0 + a],
+                                                P.joint_anchor[2 * N + b0 + a]);
+      if (b >= 0 && B.im == kRevoluteFlag)
+        c.rb = p - v3(P.joint_anchor[b0 + b], P.joint_anchor[N + b0 + b], P.joint_anchor[2 * N + b0 + b]);
+      slideA = A.im == kPrismaticFlag;
+      slideB = B.im == kPrismaticFlag;
+      imA = fmaxf(A.im, 0.f);
+      imB = fmaxf(B.im, 0.f);
+    }
 #pragma unroll
     for (int r = 0; r < 3; r++) {
       rw[r].d = dirs[r];
-      rw[r].ca = cross(c.ra, dirs[r]);
+      rw[r].ca = slideA ? dirs[r] : cross(c.ra, dirs[r]);
       rw[r].ia = Imul(A.I, rw[r].ca);
-      float k = A.im + dot(rw[r].ca, rw[r].ia) + ka[r];
+      float k = imA + dot(rw[r].ca, rw[r].ia) + ka[r];
       if (b >= 0) {
-        rw[r].cb = cross(c.rb, dirs[r]);
+        rw[r].cb = slideB ? dirs[r] : cross(c.rb, dirs[r]);
         rw[r].ib = Imul(B.I, rw[r].cb);
-        k += B.im + dot(rw[r].cb, rw[r].ib);
+        k += imB + dot(rw[r].cb, rw[r].ib);
       } else {
         rw[r].cb = v3(0.f, 0.f, 0.f);
         rw[r].ib = v3(0.f, 0.f, 0.f);
@@ -1903,7 +2067,8 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     if (asg != 0.f) vr = vr + n * ua[0] + t1 * ua[1] + t2 * ua[2];  // the arm link's point velocity
     float u0 = dot(n, vr);
     // the rows' velocities from the dynamic bodies' velocities at the setup
-    // (the solve tracks velocity changes from here; kinematic bodies' stay)
+    // (the solve tracks velocity changes from here; kinematic bodies' and
+    // container parts' velocities stay whole)
     const V3 vf = (A.im > 0.f ? pa : v3(0.f, 0.f, 0.f)) - (B.im > 0.f ? pb : v3(0.f, 0.f, 0.f));
     float bias = phi > 0.f ? -phi / dt : P.baumgarte / dt * fmaxf(0.f, -phi - P.slop);
     if (e > 0.f && u0 < -P.rest_thresh) bias = fmaxf(bias, -e * u0);
@@ -1971,7 +2136,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     float jsc = 1.0f / (float)(na > nbb ? na : nbb);
     if (live) {
       // normal-friction couplings: change of row d's velocity per unit normal impulse
-      const float ims = A.im + B.im;
+      const float ims = imA + imB;
       const float k1n = dot(t1, n) * ims + dot(rw[1].ca, rw[0].ia) + dot(rw[1].cb, rw[0].ib) + kc[0];
       const float k2n = dot(t2, n) * ims + dot(rw[2].ca, rw[0].ia) + dot(rw[2].cb, rw[0].ib) + kc[1];
       const float m3[3] = {rw[0].m, rw[1].m, rw[2].m};
@@ -1996,21 +2161,21 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
 
   // ---- a8/a11: warm start and sweeps ------------------------------------
   const ArmCtx armc{arm2, arm2 ? S.f + L.arm + ARM_DQ : nullptr,
-                    arm2 ? P.arm_rows + (long)s * kMaxColours * kArmRowWords : nullptr};
+                    arm2 ? P.arm_rows + (long)s * kMaxColours * kArmRowWords : nullptr, parts};
   // Learned start: persisting contacts' previous impulses are applied first,
   // then the network's impulses of the new contacts.  The plain solver
   // judges the network's part before any sweep: if it raises the solver's
   // objective it is dropped (the new contacts start from zero, the classic
   // warm start) and the step is flagged.
   if (kLearned) {
-    apply_all(L, S, rec, ncol, cstart, tm, ArmCtx{false, nullptr, nullptr}, 0);
+    apply_all(L, S, rec, ncol, cstart, tm, ArmCtx{false, nullptr, nullptr, false}, 0);
     team_sync(tm);
     for (int i = tid; i < nb; i += T) {
       st4(S.f + L.vsave, 2 * i, ld4(S.f + L.dyn, 3 * i));
       st4(S.f + L.vsave, 2 * i + 1, ld4(S.f + L.dyn, 3 * i + 1));
     }
     team_sync(tm);
-    apply_all(L, S, rec, ncol, cstart, tm, ArmCtx{false, nullptr, nullptr}, 1);
+    apply_all(L, S, rec, ncol, cstart, tm, ArmCtx{false, nullptr, nullptr, false}, 1);
     team_sync(tm);
     float* fval = S.f + L.fval;
     for (int i = tid; i < nact; i += T) fval[i] = start_objective(L, S, rec, i);
@@ -2071,21 +2236,63 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     } else if (is_dyn_meta(meta)) {
       V3 x = xyz(ld4(S.f + L.geo, 3 * i));
       float4 qq = ld4(S.f + L.geo, 3 * i + 1);
-      V3 v = xyz(ld4(S.f + L.dyn, 3 * i)), w = xyz(ld4(S.f + L.dyn, 3 * i + 1));
-      // the solve left the velocity change since the setup in the slot
-      v = setup_lin_vel(P, gi, N, g, dt) + v;
-      w = v3(P.vel[3 * N + gi], P.vel[4 * N + gi], P.vel[5 * N + gi]) + w;
-      x = x + v * dt;
+      const float4 d0 = ld4(S.f + L.dyn, 3 * i);
+      V3 v = xyz(d0), w = xyz(ld4(S.f + L.dyn, 3 * i + 1));
       float qw = qq.x, qx = qq.y, qy = qq.z, qz = qq.w;
-      // q + dt/2 (0, w) (x) q
-      float dw = -(w.x * qx + w.y * qy + w.z * qz);
-      float dx = qw * w.x + (w.y * qz - w.z * qy);
-      float dy = qw * w.y + (w.z * qx - w.x * qz);
-      float dz = qw * w.z + (w.x * qy - w.y * qx);
-      float h = 0.5f * dt;
-      qw += h * dw; qx += h * dx; qy += h * dy; qz += h * dz;
-      float inv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-      qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+      V3 vr, wr;  // the velocity that decides rest (at the step's pose)
+      if (parts && d0.w < 0.f) {
+        // a container part moves exactly along its joint: q += dt qd; a
+        // hinge turns the body about its line by dt qd, a slide shifts it
+        // by dt qd a; the velocity out is the rate's at the new pose
+        const bool rev = d0.w == kRevoluteFlag;
+        const V3 a = v3(P.joint_axis[gi], P.joint_axis[N + gi], P.joint_axis[2 * N + gi]);
+        const V3 o = v3(P.joint_anchor[gi], P.joint_anchor[N + gi], P.joint_anchor[2 * N + gi]);
+        const float qd = dot(a, rev ? w : v);
+        const float dq = dt * qd;
+        P.joint_state[gi] += dq;
+        P.joint_state[N + gi] = qd;
+        if (rev) {
+          wr = a * qd;
+          vr = cross(wr, x - o);
+          float sn, cs, sh, ch;
+          sincosf(dq, &sn, &cs);
+          sincosf(0.5f * dq, &sh, &ch);
+          const V3 r = x - o;
+          x = o + (r * cs + cross(a, r) * sn + a * (dot(a, r) * (1.f - cs)));
+          // (cos dq/2, a sin dq/2) (x) q
+          const V3 hv = a * sh;
+          const float nw = ch * qw - (hv.x * qx + hv.y * qy + hv.z * qz);
+          const float nx = ch * qx + hv.x * qw + (hv.y * qz - hv.z * qy);
+          const float ny = ch * qy + hv.y * qw + (hv.z * qx - hv.x * qz);
+          const float nz = ch * qz + hv.z * qw + (hv.x * qy - hv.y * qx);
+          const float inv = 1.0f / sqrtf(nw * nw + nx * nx + ny * ny + nz * nz);
+          qw = nw * inv; qx = nx * inv; qy = ny * inv; qz = nz * inv;
+          w = wr;
+          v = cross(wr, x - o);
+        } else {
+          vr = a * qd;
+          wr = v3(0.f, 0.f, 0.f);
+          x = x + a * dq;
+          v = vr;
+          w = wr;
+        }
+      } else {
+        // the solve left the velocity change since the setup in the slot
+        v = setup_lin_vel(P, gi, N, g, dt) + v;
+        w = v3(P.vel[3 * N + gi], P.vel[4 * N + gi], P.vel[5 * N + gi]) + w;
+        vr = v;
+        wr = w;
+        x = x + v * dt;
+        // q + dt/2 (0, w) (x) q
+        float dw = -(w.x * qx + w.y * qy + w.z * qz);
+        float dx = qw * w.x + (w.y * qz - w.z * qy);
+        float dy = qw * w.y + (w.z * qx - w.x * qz);
+        float dz = qw * w.z + (w.x * qy - w.y * qx);
+        float h = 0.5f * dt;
+        qw += h * dw; qx += h * dx; qy += h * dy; qz += h * dz;
+        float inv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+        qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+      }
       P.pose[gi] = x.x; P.pose[N + gi] = x.y; P.pose[2 * N + gi] = x.z;
       P.pose[3 * N + gi] = qw; P.pose[4 * N + gi] = qx; P.pose[5 * N + gi] = qy; P.pose[6 * N + gi] = qz;
       P.vel[gi] = v.x; P.vel[N + gi] = v.y; P.vel[2 * N + gi] = v.z;
@@ -2094,7 +2301,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
         const float4 g2 = ld4(S.f + L.geo, 3 * i + 2);
         const uint32_t sh = meta & 255u;
         const float rb = sh == SPHERE ? g2.x : (sh == BOX ? sqrtf(g2.x * g2.x + g2.y * g2.y + g2.z * g2.z) : g2.x + g2.y);
-        const bool at_rest = sqrtf(len2(v)) <= P.sleep_speed && sqrtf(len2(w)) * rb <= P.sleep_speed;
+        const bool at_rest = sqrtf(len2(vr)) <= P.sleep_speed && sqrtf(len2(wr)) * rb <= P.sleep_speed;
         const int32_t r0 = P.rest[gi];
         P.rest[gi] = at_rest ? (r0 < (1 << 30) ? r0 + 1 : r0) : 0;
       }
@@ -2197,13 +2404,13 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   TRACE(14);
 }
 
-template <bool kLearned, bool kArm>
+template <bool kLearned, bool kArt>
 __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
   extern __shared__ float4 smem_f4[];
   Smem S{reinterpret_cast<float*>(smem_f4), reinterpret_cast<uint32_t*>(smem_f4)};
   const Team<false> tm{(int)threadIdx.x, (int)blockDim.x};
   const int s = P.scene_list ? P.scene_list[blockIdx.x] : (int)blockIdx.x;
-  scene_step<kLearned, kArm>(P, L, S, s, tm);
+  scene_step<kLearned, kArt>(P, L, S, s, tm);
 }
 
 // Scenes whose working set exceeds a workgroup's LDS: the same step with the
@@ -2211,12 +2418,12 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
 // P.glist, L2 and HBM resident) instead of LDS; one workgroup per scene.
 // The team barriers are workgroup-scope fences, which order global memory
 // as they order LDS, so the step computes exactly what it computes in LDS.
-template <bool kLearned, bool kArm>
+template <bool kLearned, bool kArt>
 __global__ __launch_bounds__(256) void step_kernel_hbm(StepParams P, LdsLayout L) {
   const int k = (int)blockIdx.x;
   float* ws = P.gscr + (size_t)k * (size_t)P.gwords;
   const Team<false> tm{(int)threadIdx.x, (int)blockDim.x};
-  scene_step<kLearned, kArm>(P, L, Smem{ws, reinterpret_cast<uint32_t*>(ws)}, P.glist[k], tm);
+  scene_step<kLearned, kArt>(P, L, Smem{ws, reinterpret_cast<uint32_t*>(ws)}, P.glist[k], tm);
 }
 
 // Persistent launch over scenes of uneven size: every workgroup first takes
@@ -2225,7 +2432,7 @@ __global__ __launch_bounds__(256) void step_kernel_hbm(StepParams P, LdsLayout L
 // steps each alone in its quarter of the LDS.  Queues are in descending
 // body count, so the largest scenes start first; a workgroup leaves once
 // both queues are drained.
-template <bool kLearned, bool kArm>
+template <bool kLearned, bool kArt>
 __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams Q) {
   extern __shared__ float4 smem_f4[];
   __shared__ int next_scene;
@@ -2240,8 +2447,8 @@ __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams
     const int s = Q.team[k];
     const int nb = P.body_offset[s + 1] - P.body_offset[s];
     const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), (int)blockDim.x >> 6, P.solver,
-                                   P.warm, P.arm);
-    scene_step<kLearned, kArm>(P, L, Smem{lds, reinterpret_cast<uint32_t*>(lds)}, s, Team<false>{tid, (int)blockDim.x});
+                                   P.warm, P.art);
+    scene_step<kLearned, kArt>(P, L, Smem{lds, reinterpret_cast<uint32_t*>(lds)}, s, Team<false>{tid, (int)blockDim.x});
     __syncthreads();
   }
   const int w = tid >> 6, lane = tid & 63;
@@ -2253,8 +2460,8 @@ __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams
     if (k >= Q.n_wave) break;
     const int s = Q.wave[k];
     const int nb = P.body_offset[s + 1] - P.body_offset[s];
-    const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), 1, P.solver, P.warm, P.arm);
-    scene_step<kLearned, kArm>(P, L, Smem{mine, reinterpret_cast<uint32_t*>(mine)}, s, Team<true>{lane, 64});
+    const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), 1, P.solver, P.warm, P.art);
+    scene_step<kLearned, kArt>(P, L, Smem{mine, reinterpret_cast<uint32_t*>(mine)}, s, Team<true>{lane, 64});
   }
 }
 
@@ -2281,14 +2488,14 @@ __global__ void arm_pose_kernel(int S_, const int32_t* off, float* pose, long N,
 
 // Masked reset from a pool of K states: one workgroup per flagged scene
 // copies pool entry index[s] (pose [K][7][N], velocity [K][6][N], joint
-// angles [K][S][7]) into the scene and empties its contact cache; the
-// articulated arm's state (arm_state, may be null) restarts at rest with its
-// motor targets at the new angles; an entry outside [0, K) leaves the scene
-// as it is and flags it.
+// angles [K][S][7], container parts' q and qd [K][2][N]) into the scene and
+// empties its contact cache; the articulated arm's state (arm_state, may be
+// null) restarts at rest with its motor targets at the new angles; an entry
+// outside [0, K) leaves the scene as it is and flags it.
 __global__ void reset_kernel(const int32_t* off, const uint8_t* mask, float* pose, float* vel, int32_t* rest, long N,
                              int S_, int K, const int32_t* index, const float* pool_pose, const float* pool_vel,
-                             float* theta, const float* pool_theta, int32_t* cache_count_a, int32_t* cache_count_b,
-                             int32_t* flags, float* arm_state) {
+                             float* theta, const float* pool_theta, float* joint_state, const float* pool_joint,
+                             int32_t* cache_count_a, int32_t* cache_count_b, int32_t* flags, float* arm_state) {
   const int s = blockIdx.x;
   if (!mask[s]) return;
   const int k = index ? index[s] : 0;
@@ -2303,6 +2510,8 @@ __global__ void reset_kernel(const int32_t* off, const uint8_t* mask, float* pos
     for (int c = 0; c < 7; c++) pose[c * N + i] = pp[c * N + i];
     for (int c = 0; c < 6; c++) vel[c * N + i] = pv[c * N + i];
     rest[i] = 0;
+    if (joint_state && pool_joint)
+      for (int c = 0; c < 2; c++) joint_state[c * N + i] = pool_joint[(size_t)k * 2 * N + c * N + i];
   }
   if (threadIdx.x < 7 && theta && pool_theta) {
     const float th = pool_theta[(size_t)k * 7 * S_ + 7 * s + threadIdx.x];
@@ -2326,7 +2535,7 @@ extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L
   size_t bytes = (size_t)L->total * 4u;
   if (P->warm == rbs::WARM_LEARNED)
     hipLaunchKernelGGL((rbs::step_kernel<true, false>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
-  else if (P->arm == 2)
+  else if (P->arm == 2 || P->joint)
     hipLaunchKernelGGL((rbs::step_kernel<false, true>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
   else
     hipLaunchKernelGGL((rbs::step_kernel<false, false>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
@@ -2337,7 +2546,7 @@ extern "C" int rbs_launch_step_hbm(const rbs::StepParams* P, const rbs::LdsLayou
   if (n <= 0) return 0;
   if (P->warm == rbs::WARM_LEARNED)
     hipLaunchKernelGGL((rbs::step_kernel_hbm<true, false>), dim3(n), dim3(256), 0, stream, *P, *L);
-  else if (P->arm == 2)
+  else if (P->arm == 2 || P->joint)
     hipLaunchKernelGGL((rbs::step_kernel_hbm<false, true>), dim3(n), dim3(256), 0, stream, *P, *L);
   else
     hipLaunchKernelGGL((rbs::step_kernel_hbm<false, false>), dim3(n), dim3(256), 0, stream, *P, *L);
@@ -2367,7 +2576,7 @@ extern "C" int rbs_launch_persistent(const rbs::StepParams* P, const rbs::QueueP
   const size_t bytes = (size_t)Q->lds_words * 4u;
   if (P->warm == rbs::WARM_LEARNED)
     hipLaunchKernelGGL((rbs::step_persistent<true, false>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
-  else if (P->arm == 2)
+  else if (P->arm == 2 || P->joint)
     hipLaunchKernelGGL((rbs::step_persistent<false, true>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
   else
     hipLaunchKernelGGL((rbs::step_persistent<false, false>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
@@ -2383,9 +2592,10 @@ extern "C" int rbs_launch_arm_pose(const rbs::StepParams* P, const uint8_t* mask
 
 extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, int K, const int32_t* index,
                                 const float* pool_pose, const float* pool_vel, const float* pool_theta,
-                                int32_t* count_a, int32_t* count_b, hipStream_t stream) {
+                                const float* pool_joint, int32_t* count_a, int32_t* count_b, hipStream_t stream) {
   hipLaunchKernelGGL(rbs::reset_kernel, dim3(P->num_scenes), dim3(128), 0, stream, P->body_offset, mask, P->pose,
-                     P->vel, P->rest, P->n_bodies, P->num_scenes, K, index, pool_pose, pool_vel, P->theta, pool_theta, count_a,
-                     count_b, P->st_flags, P->arm == 2 ? P->arm_state : nullptr);
+                     P->vel, P->rest, P->n_bodies, P->num_scenes, K, index, pool_pose, pool_vel, P->theta, pool_theta,
+                     P->joint_state, pool_joint, count_a, count_b, P->st_flags,
+                     P->arm == 2 ? P->arm_state : nullptr);
   return (int)hipGetLastError();
 }

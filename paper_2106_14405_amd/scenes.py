@@ -232,9 +232,82 @@ def drop_scene(seed: int, n_spheres: int = 32, n_boxes: int = 32, size=(0.05, 0.
     return sc
 
 
+def _yaw_boxes_overlap(c1, h1, yaw1, c2, h2, yaw2) -> bool:
+    """Whether two boxes turned about z only overlap: their z intervals and
+    their footprints (separating axes: the four edge normals)."""
+    if abs(c1[2] - c2[2]) >= h1[2] + h2[2]:
+        return False
+    d = np.asarray(c2[:2], np.float64) - np.asarray(c1[:2], np.float64)
+    u1 = [np.array([math.cos(yaw1), math.sin(yaw1)]), np.array([-math.sin(yaw1), math.cos(yaw1)])]
+    u2 = [np.array([math.cos(yaw2), math.sin(yaw2)]), np.array([-math.sin(yaw2), math.cos(yaw2)])]
+    for ax in u1 + u2:
+        r1 = h1[0] * abs(u1[0] @ ax) + h1[1] * abs(u1[1] @ ax)
+        r2 = h2[0] * abs(u2[0] @ ax) + h2[1] * abs(u2[1] @ ax)
+        if abs(d @ ax) >= r1 + r2:
+            return False
+    return True
+
+
+def _plan_cabinet(st: _Stream, taken: list, ring=(0.75, 1.2)) -> dict:
+    """A cabinet facing the arm base (Sec. 3: furniture with articulated
+    doors and drawers): a static carcass of half-extents U[0.2, 0.3] x
+    U[0.25, 0.4] x U[0.35, 0.5] m on the floor, its front face U[ring] m
+    from the base (horizontally), clear of the cabinets in `taken`
+    (footprints with the door's swing and the drawer's travel in front);
+    the door 2-5 kg, the drawer 1-3 kg.  Placed before the static boxes,
+    which then keep clear of it."""
+    cx, cy, cz = st.uniform(0.2, 0.3), st.uniform(0.25, 0.4), st.uniform(0.35, 0.5)
+    mu_c = st.uniform(0.3, 0.8)
+    m_door, m_drawer = st.uniform(2.0, 5.0), st.uniform(1.0, 3.0)
+    base = np.array(ARM_BASE[:2])
+    hc = np.array([cx, cy, cz])
+    hf = np.array([cy, cy + 0.05, cz])        # in front: the door's swing and the drawer's travel
+    for _ in range(4000):
+        ang, front = st.uniform(0.0, 2.0 * math.pi), st.uniform(*ring)
+        f = np.array([math.cos(ang), math.sin(ang)])          # from the base outwards
+        c2 = base + f * (front + cx)
+        C = np.array([c2[0], c2[1], cz])
+        F = np.array([c2[0] - f[0] * (cx + cy), c2[1] - f[1] * (cx + cy), cz])
+        if not any(_yaw_boxes_overlap(b, h, ang, c, ho, yo) for (b, h) in ((C, hc), (F, hf))
+                   for (c, ho, yo) in taken):
+            break
+    else:
+        raise RuntimeError("could not place a cabinet")
+    taken += [(C, hc, ang), (F, hf, ang)]
+    return dict(C=C, h=hc, yaw=ang + math.pi, mu=mu_c, m_door=m_door, m_drawer=m_drawer)
+
+
+def _add_cabinet(sc: Scene, cab: dict, statics: list) -> None:
+    """The cabinet's bodies: the carcass; a door over the upper half of the
+    front on a vertical hinge at one side edge, opening outwards (q in
+    [0, 1.9] rad); a drawer in the lower half, its front 2 cm proud of the
+    carcass, sliding out along the front normal (q in [0, 1.2 hx] m).  Both
+    parts are joined to the carcass (no contacts with it)."""
+    C, (cx, cy, cz), yaw, mu_c = cab["C"], cab["h"], cab["yaw"], cab["mu"]
+    fn = np.array([math.cos(yaw), math.sin(yaw), 0.0])         # local +x: the front normal, towards the base
+    sd = np.array([-math.sin(yaw), math.cos(yaw), 0.0])
+    q = _yaw_quat(yaw)
+    ic = sc.n
+    sc.add(BOX, STATIC, [cx, cy, cz], 0.0, mu_c, 0.0, C, q)
+    statics.append((C, np.array([cx, cy, cz]), yaw))
+    # door: half-extents (0.015, cy - 0.005, cz / 2 - 0.005) over the upper half,
+    # hinge at the +side edge (turning by +q about z swings it outwards)
+    hd = np.array([0.015, cy - 0.005, 0.5 * cz - 0.005])
+    pd = C + fn * (cx + hd[0] + 0.002) + np.array([0.0, 0.0, 0.5 * cz])
+    sc.add(BOX, DYNAMIC, hd, cab["m_door"], mu_c, 0.0, pd, q)
+    sc.joints[sc.n - 1] = (1, (0.0, 0.0, 1.0), pd + sd * cy, (0.0, 1.9), ic)
+    statics.append((pd, hd, yaw))
+    # drawer: in the lower half, its front 2 cm proud of the carcass
+    hw = np.array([0.8 * cx, 0.85 * cy, 0.3 * cz])
+    pw = C + fn * (cx + 0.02 - hw[0]) - np.array([0.0, 0.0, 0.5 * cz])
+    sc.add(BOX, DYNAMIC, hw, cab["m_drawer"], mu_c, 0.0, pw, q)
+    sc.joints[sc.n - 1] = (2, tuple(fn), pw, (0.0, 1.2 * cx), ic)
+    statics.append((pw, hw, yaw))
+
+
 def clutter_scene(seed: int, n_static: int = 20, n_each: int = 36, size=(0.03, 0.30),
                   cap_radius=(0.03, 0.15), mass=(0.05, 3.0), friction=(0.3, 0.8),
-                  arm: int = True, n_dynamic: int | None = None) -> Scene:
+                  arm: int = True, n_dynamic: int | None = None, cabinets: int = 0) -> Scene:
     """Rearrangement clutter: static boxes on a 4 m x 4 m floor (a quarter of
     them floating shelves), dynamic spheres/boxes/capsules dropped above, and
     a 7-link capsule arm based at (0, 0, 0.8) m: kinematic (arm True or 1) or
@@ -242,10 +315,18 @@ def clutter_scene(seed: int, n_static: int = 20, n_each: int = 36, size=(0.03, 0
     same scene otherwise.  With n_dynamic
     given, that many dynamic bodies (a third of each shape, the remainder to
     spheres then boxes) dropped from a region scaled by (n_dynamic/108)^(1/3)
-    (x, y within +-2 m times the scale, z from 0.2 m up to 4 m times it)."""
+    (x, y within +-2 m times the scale, z from 0.2 m up to 4 m times it).
+    cabinets > 0 adds that many cabinets with a door and a drawer each
+    (_plan_cabinet, _add_cabinet: drawn from a stream of their own and
+    placed first; the static boxes keep clear of them; their bodies follow
+    the static boxes)."""
     st = _Stream(stream_key(seed, 2) if n_dynamic is None else stream_key(seed, 6, n_dynamic))
     sc = Scene()
     statics = []
+    cabs, taken = [], []
+    if cabinets:  # placed first, from a stream of their own
+        stc = _Stream(stream_key(seed, 9, cabinets))
+        cabs = [_plan_cabinet(stc, taken) for _ in range(cabinets)]
     for i in range(n_static):
         hx, hy = st.uniform(0.15, 1.0), st.uniform(0.15, 1.0)
         shelf = st.take(1)[0] < 0.25
@@ -259,13 +340,16 @@ def clutter_scene(seed: int, n_static: int = 20, n_each: int = 36, size=(0.03, 0
         rad = math.hypot(hx, hy)
         for _ in range(4000):
             x, y = st.uniform(-2.0, 2.0), st.uniform(-2.0, 2.0)
-            if math.hypot(x, y) - rad >= 0.8:
+            if math.hypot(x, y) - rad >= 0.8 and not any(
+                    _yaw_boxes_overlap((x, y, z), (hx, hy, hz), yaw, c, h, y2) for (c, h, y2) in taken):
                 break
         else:
             raise RuntimeError("could not place static box")
         c = np.array([x, y, z])
         statics.append((c, np.array([hx, hy, hz]), yaw))
         sc.add(BOX, STATIC, [hx, hy, hz], 0.0, st.uniform(*friction), 0.0, c, _yaw_quat(yaw))
+    for cab in cabs:
+        _add_cabinet(sc, cab, statics)
     reach = sum(ARM_LINK_LENGTH) + ARM_RADIUS
     keepout = (np.array(ARM_BASE), reach) if arm else None
     if n_dynamic is None:

@@ -56,6 +56,14 @@ class Sim:
             arm_base=np.ascontiguousarray(batch.arm_base, np.float32).reshape(-1),
             arm_theta=np.ascontiguousarray(batch.arm_theta, np.float32).reshape(-1),
         )
+        self.has_parts = getattr(batch, "joint", None) is not None
+        if self.has_parts:
+            h2 = self._host
+            h2["joint"] = np.ascontiguousarray(batch.joint, np.uint8)
+            h2["joint_axis"] = np.ascontiguousarray(batch.joint_axis, np.float32).reshape(-1)
+            h2["joint_anchor"] = np.ascontiguousarray(batch.joint_anchor, np.float32).reshape(-1)
+            h2["joint_limits"] = np.ascontiguousarray(batch.joint_limits, np.float32).reshape(-1)
+            h2["joint_parent"] = np.ascontiguousarray(batch.joint_parent, np.int32)
         h = self._host
         d = L.BatchDesc()
         d.abi_version = L.SIM_ABI_VERSION
@@ -83,6 +91,12 @@ class Sim:
         d.max_pairs, d.max_contacts = self.max_pairs, self.max_contacts
         d.solver, d.warm_start, d.tolerance, d.threads = int(solver), int(warm), float(tol), int(threads)
         d.hbm_min_bodies = int(hbm_min_bodies)
+        if self.has_parts:
+            d.h_joint = _np_ptr(h["joint"], C.c_uint8)
+            d.h_joint_axis = _np_ptr(h["joint_axis"], C.c_float)
+            d.h_joint_anchor = _np_ptr(h["joint_anchor"], C.c_float)
+            d.h_joint_limits = _np_ptr(h["joint_limits"], C.c_float)
+            d.h_joint_parent = _np_ptr(h["joint_parent"], C.c_int32)
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             d.stream = C.c_void_p(self.stream.cuda_stream)
@@ -118,6 +132,8 @@ class Sim:
         self.theta = self._view(sv.theta, torch.float32, (S, 7)) if self.batch.arm else None
         # articulated arm: [S, 3, 7] joint rates, motor targets, last motor impulses
         self.arm_state = self._view(sv.arm_state, torch.float32, (S, 3, 7)) if int(self.batch.arm) == 2 else None
+        # container parts: [2, N] joint coordinates q and rates qd (0 for other bodies)
+        self.joint_state = self._view(sv.joint_state, torch.float32, (2, N)) if self.has_parts else None
         st = L.StatsView()
         L.check(lib.sim_stats(self.h, C.byref(st)), "sim_stats")
         self.stats = dict(
@@ -249,18 +265,20 @@ class Sim:
         L.check(L.load().sim_load_state(self.h, C.c_void_p(blob.data_ptr())), "sim_load_state")
 
     def reset(self, mask: torch.Tensor, pose: torch.Tensor, vel: torch.Tensor, theta: torch.Tensor | None = None,
-              index: torch.Tensor | None = None):
+              index: torch.Tensor | None = None, joint_state: torch.Tensor | None = None):
         """Masked reset from a pool of K states: pose [K, 7, N], vel [K, 6, N],
-        theta [K, S, 7] (arm batches); a single state may be given without
-        the leading K.  index: int32 [S] pool entry per scene (None: 0)."""
+        theta [K, S, 7] (arm batches), joint_state [K, 2, N] (batches with
+        container parts); a single state may be given without the leading K.
+        index: int32 [S] pool entry per scene (None: 0)."""
         pose = pose.reshape(-1, 7, self.N)
         K = pose.shape[0]
         ts = [mask.to(torch.uint8).contiguous(), pose.contiguous(), vel.reshape(K, 6, self.N).contiguous()]
         th = theta.reshape(K, self.S, 7).contiguous() if theta is not None else None
         ix = index.to(torch.int32).contiguous() if index is not None else None
-        self._reset_keep = ts + [th, ix]
+        js = joint_state.reshape(K, 2, self.N).contiguous() if joint_state is not None else None
+        self._reset_keep = ts + [th, ix, js]
         ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
-        pool = L.ResetPool(K, ptr(ts[1]), ptr(ts[2]), ptr(th), ptr(ix))
+        pool = L.ResetPool(K, ptr(ts[1]), ptr(ts[2]), ptr(th), ptr(ix), ptr(js))
         L.check(L.load().sim_reset(self.h, ptr(ts[0]), C.byref(pool)), "sim_reset")
 
     def close(self):

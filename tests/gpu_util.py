@@ -57,6 +57,14 @@ def arm_snapshot32(ora):
     return ast.reshape(-1, 3, 7)
 
 
+def joint_snapshot32(ora):
+    """Float32 joint state of the container parts [2, N] (q, qd planes, the
+    library's layout), and the oracle reset to exactly it."""
+    js = ora.joint_state.reshape(-1, 2).astype(np.float32)
+    ora.joint_state[:] = js.astype(np.float64).reshape(-1)
+    return np.ascontiguousarray(js.T)
+
+
 def gpu_set_rest(sim, rest):
     """Copy the oracle's per-body rest counters into the simulation."""
     import torch
@@ -100,6 +108,7 @@ def gpu_results(sim):
     out["theta"] = sim.theta.cpu().numpy() if sim.theta is not None else None
     out["rest"] = sim.rest.cpu().numpy().copy()
     out["arm_state"] = sim.arm_state.cpu().numpy().copy() if sim.arm_state is not None else None
+    out["joint_state"] = sim.joint_state.cpu().numpy().copy() if sim.joint_state is not None else None
     return out
 
 
@@ -325,13 +334,32 @@ def compare(batch, g, r, ora, check_values=True, contact_values=False, partial=T
                 dyn = (batch.motion[b0:b1] == S.DYNAMIC) & ~aff
                 if int(batch.arm) == 2:  # links of the articulated arm: the arm as a whole is checked by its rates
                     dyn[-7:] = False
+                rad = np.array([S.bounding_radius(int(batch.shape[i]), batch.param[i]) for i in range(b0, b1)])
+                jk = batch.joint[b0:b1] if getattr(batch, "joint", None) is not None else np.zeros(b1 - b0, np.uint8)
+                part = dyn & (jk > 0)
+                dyn &= jk == 0
                 if dyn.any():
-                    rad = np.array([S.bounding_radius(int(batch.shape[i]), batch.param[i]) for i in range(b0, b1)])
                     eF = np.linalg.norm(Fg - Fo, axis=1)[dyn].max()
                     eT = (np.linalg.norm(Tg - To, axis=1) / rad)[dyn].max()
                     rep["max_res"] = max(rep["max_res"], max(eF, eT) / max(scale, 1e-12))
                     assert max(eF, eT) <= LAM_REL * scale + LAM_ABS, \
                         f"scene {s}: resultant impulse error force {eF:.3e} torque/r {eT:.3e} (scale {scale:.3e})"
+                # a container part: its joint takes every impulse but the
+                # generalised one (moment about the hinge line over the
+                # bounding radius, or force along the slide), which is unique
+                for i in np.nonzero(part)[0]:
+                    ax = batch.joint_axis[b0 + i].astype(np.float64)
+                    if jk[i] == 1:
+                        o = batch.joint_anchor[b0 + i].astype(np.float64)
+                        # moments about the anchor from those about xref: T_o = T_x + (x - o) x F
+                        go = ax @ (To[i] + np.cross(xref[i] - o, Fo[i]))
+                        gg = ax @ (Tg[i] + np.cross(xref[i] - o, Fg[i]))
+                        eG = abs(gg - go) / rad[i]
+                    else:
+                        eG = abs(ax @ (Fg[i] - Fo[i]))
+                    rep["max_res"] = max(rep["max_res"], eG / max(scale, 1e-12))
+                    assert eG <= LAM_REL * scale + LAM_ABS, \
+                        f"scene {s}: generalised impulse error {eG:.3e} on part {i} (scale {scale:.3e})"
         if not check_values or not values:
             continue
         capped = tol_band is not None and bool(int(r["flags"][s]) & O.F_NOT_CONVERGED)

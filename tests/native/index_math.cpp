@@ -59,8 +59,15 @@ static void check_layout(int NB, int PM, int CM, int W, int solver, int warm, in
                              {"hbase", L.hbase, L.hbase + 256},
                              {"scratch", L.scr, T}};
   if (warm == WARM_LEARNED) res.push_back({"fresh", L.fresh, L.fresh + (CM + 31) / 32});
-  if (arm == 2) res.push_back({"arm", L.arm, L.arm + kArmWords});
+  if ((arm & 3) == 2) res.push_back({"arm", L.arm, L.arm + kArmWords});
+  if (arm & kArtParts) res.push_back({"parts", L.parts, L.parts + kPartWords});
+  CHECK(((arm & 3) == 2) == (L.arm >= 0) && ((arm & kArtParts) != 0) == (L.parts >= 0), "arm/parts regions present");
   disjoint(res, T, NB, PM, CM, W);
+  // a part's words inside its 16-word entry; the count word in front of the entries
+  CHECK(PART_BODY < kPartStride && PART_KIND < kPartStride && PART_M < kPartStride && PART_BIAS + 2 <= PART_LAM &&
+            PART_LAM + 2 <= PART_IM && PART_IM < PART_AX && PART_AX + 3 <= kPartStride &&
+            kPartWords >= 4 + kMaxParts * kPartStride && kMaxParts <= 64,
+        "part words");
   // the arm's words: M^-1, rates, impulses, targets, origins and axes inside the region
   CHECK(ARM_MI + 49 <= ARM_DQ && ARM_DQ + 7 <= ARM_QREF && ARM_QREF + 7 <= ARM_LAM && ARM_LAM + 7 <= ARM_BIAS &&
             ARM_BIAS + 7 <= ARM_O && ARM_O + 21 <= ARM_AX && ARM_AX + 21 <= kArmWords,
@@ -153,8 +160,8 @@ int main() {
         for (int W = 1; W <= 4; W++)
           for (int solver = 0; solver < 2; solver++)
             for (int warm = 0; warm < 3; warm++)
-              for (int arm = 0; arm <= 2; arm += 2) {
-                check_layout(NB, PM, CM, W, solver, warm, arm);
+              for (int art : {0, 2, kArtParts, 2 | kArtParts}) {
+                check_layout(NB, PM, CM, W, solver, warm, art);
                 checked++;
               }
       }

@@ -1,0 +1,284 @@
+"""Articulated container parts on the GPU (Sec. 3: cabinet doors on a hinge
+and drawers on a slide, each joined to its static carcass) against the
+oracle: one step from the same float32 state, joint coordinates and rates.
+
+Clutter scenes with two cabinets each; the oracle runs the warm-up with
+the parts started at random rates, so that at the compared step doors and
+drawers rest on their limits, swing or slide, and carry or strike objects
+(and, with the articulated arm, the arm).  Pairs, contacts, colours,
+impulses and body states as in every parity test (`compare`: a part's
+generalised impulse in place of its resultant), plus the parts' q and qd.
+The persistent launch, the global-memory working set and 256-thread teams
+give the same bits as one 64-thread workgroup per scene; modes the parts
+do not support are refused."""
+import numpy as np
+import pytest
+
+from gpu_util import (arm_snapshot32, compare, gpu_results, gpu_set_rest, gpu_sim, joint_snapshot32, report,
+                      snapshot32)
+from helpers import DT, S
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+Q_BAR = 1e-5     # joint coordinate after one step (rad or m): dt * rate
+QD_BAR = 1e-4    # joint rate, relative with a 1 rad/s (m/s) floor
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def sweep_actions(n, t):
+    """Arm joint-rate targets that swing the arm round through the scene
+    (shoulder and elbow down for 110 steps, base yaw 0.8-1 rad/s)."""
+    a = np.zeros((n, 7))
+    a[:, 0] = 0.8 * (1 + 0.25 * np.arange(n) / max(n - 1, 1))
+    a[:, 1] = 1.0 if t < 110 else 0.0
+    a[:, 3] = 0.4 if t < 110 else 0.0
+    return a.astype(np.float32)
+
+
+def kick_parts(b, ora, seed=3):
+    """Random start rates: doors U[-2, 2] rad/s, drawers U[-0.5, 0.5] m/s."""
+    rng = np.random.default_rng(seed)
+    for g in np.nonzero(b.joint)[0]:
+        ora.q_rate[g] = rng.uniform(-2.0, 2.0) if b.joint[g] == 1 else rng.uniform(-0.5, 0.5)
+
+
+def warmup(b, steps, sleep=None):
+    ora = O.OracleSim(b)
+    if sleep:
+        ora.set_sleep(*sleep)
+    kick_parts(b, ora)
+    for t in range(steps):
+        act = sweep_actions(b.n_scenes, t) if int(b.arm) == 2 else (S.arm_actions(1, b.n_scenes, t) if b.arm else None)
+        ora.step(actions=act, iters=20, warm=O.PREV, outputs=False)
+    return ora
+
+
+def step_both(torch, b, ora, warm, iters, tol=0.0, step_index=0, sleep=None, **kw):
+    pose, vel, theta, cache = snapshot32(ora)
+    js = joint_snapshot32(ora)
+    sim = gpu_sim(b, pose, vel, theta, cache, warm=warm, tol=tol, **kw)
+    sim.joint_state.copy_(torch.as_tensor(js))
+    if int(b.arm) == 2:
+        sim.arm_state.copy_(torch.as_tensor(arm_snapshot32(ora)))
+    if sleep:
+        sim.set_sleep(*sleep)
+        gpu_set_rest(sim, ora.rest)
+    if int(b.arm) == 2:
+        act = sweep_actions(b.n_scenes, step_index)
+    else:
+        act = S.arm_actions(1, b.n_scenes, step_index) if b.arm else None
+    sim.step(torch.as_tensor(act, device=sim.device) if act is not None else None, DT, iters)
+    r = ora.step(actions=act, iters=iters, tol=tol, warm=warm, max_pairs=sim.max_pairs, max_contacts=sim.max_contacts)
+    return sim, gpu_results(sim), r
+
+
+def part_contacts(b, r):
+    n = 0
+    for s in range(b.n_scenes):
+        b0, b1 = int(b.body_offset[s]), int(b.body_offset[s + 1])
+        isp = b.joint[b0:b1] > 0
+        k = r["c_key"][s, :int(r["n_contacts"][s])]
+        a, bb = k >> 20, (k >> 8) & 0xFFF
+        n += int(np.sum(isp[a] | ((bb != 0xFFF) & isp[np.minimum(bb, b1 - b0 - 1)])))
+    return n
+
+
+def check_joints(b, g, r, ora, tol_mode=False):
+    """q and qd of every part whose scene's sweep counts agree and that no
+    tie touched; returns how many parts of the batch rest on a limit."""
+    jo = ora.joint_state.reshape(-1, 2)
+    jg = g["joint_state"]
+    worst_q = worst_qd = 0.0
+    # parts resting on a limit after the step (oracle), over the whole batch
+    parts = np.nonzero(b.joint)[0]
+    lim = b.joint_limits[parts]
+    at_limit = int(np.sum(np.minimum(np.abs(jo[parts, 0] - lim[:, 0]), np.abs(jo[parts, 0] - lim[:, 1])) < 1e-6))
+    for s in range(b.n_scenes):
+        if int(g["stats"]["sweeps"][s]) != int(r["sweeps"][s]) or r["ambiguous"][s]:
+            continue
+        b0, b1 = int(b.body_offset[s]), int(b.body_offset[s + 1])
+        for i in np.nonzero(b.joint[b0:b1])[0]:
+            gi = b0 + i
+            eq = abs(float(jg[0, gi]) - jo[gi, 0])
+            eqd = abs(float(jg[1, gi]) - jo[gi, 1]) / max(abs(jo[gi, 1]), 1.0)
+            worst_q, worst_qd = max(worst_q, eq), max(worst_qd, eqd)
+            assert eq <= Q_BAR, f"scene {s} part {i}: joint coordinate error {eq:.3e}"
+            assert eqd <= (1e-3 if tol_mode else QD_BAR), f"scene {s} part {i}: joint rate error {eqd:.3e}"
+    print(f"[parts] max err q {worst_q:.1e} qd {worst_qd:.1e}; parts at a limit {at_limit}", flush=True)
+    return at_limit
+
+
+@pytest.mark.parametrize("warm,tol,iters", [(O.PREV, 0.0, 20), (O.COLD, 0.0, 20), (O.PREV, 1e-4, 1000)])
+def test_cabinet_parity(torch_cuda, warm, tol, iters):
+    """Clutter with two cabinets a scene and the kinematic arm, 100 oracle steps after the kick."""
+    b = S.batch_clutter(8, seed0=10000, arm=True, cabinets=2)
+    ora = warmup(b, 100)
+    sim, g, r = step_both(torch_cuda, b, ora, warm, iters, tol=tol, step_index=100)
+    rep = compare(b, g, r, ora, contact_values=True, tol_band=0.02 if tol > 0 else None)
+    report(f"cabinets, warm={warm} tol={tol:g}", rep)
+    npc = part_contacts(b, r)
+    print(f"contacts on parts: {npc}", flush=True)
+    assert npc >= 10 and rep["contacts_solved"] >= 500
+    assert check_joints(b, g, r, ora, tol_mode=tol > 0) >= 8
+
+
+def test_cabinets_with_articulated_arm_parity(torch_cuda):
+    """The articulated arm swept through clutter with cabinets (arm contacts,
+    part contacts and limit rows in one solve)."""
+    b = S.batch_clutter(8, seed0=10000, arm=2, cabinets=2)
+    ora = warmup(b, 100)
+    sim, g, r = step_both(torch_cuda, b, ora, O.PREV, 20, step_index=100)
+    rep = compare(b, g, r, ora, contact_values=True)
+    report("cabinets, articulated arm", rep)
+    assert part_contacts(b, r) >= 10
+    check_joints(b, g, r, ora)
+    ast_g, ast_o = g["arm_state"], ora.arm_state.reshape(-1, 3, 7)
+    ok = [s for s in range(b.n_scenes) if int(g["stats"]["sweeps"][s]) == int(r["sweeps"][s])
+          and not r["tied"][int(b.body_offset[s + 1]) - 7:int(b.body_offset[s + 1])].any()]
+    eqd = np.abs(ast_g[ok, 0] - ast_o[ok, 0]) / np.maximum(np.abs(ast_o[ok, 0]), 1.0)
+    assert eqd.max() <= 1e-4, eqd.max()
+
+
+def test_cabinet_sleeping_parity(torch_cuda):
+    """Sleeping on: parts never sleep and keep their islands awake; rest counters equal."""
+    sleep = (0.02, 30)
+    b = S.batch_clutter(8, seed0=10100, arm=True, cabinets=2)
+    ora = warmup(b, 150, sleep=sleep)
+    sim, g, r = step_both(torch_cuda, b, ora, O.PREV, 20, step_index=150, sleep=sleep)
+    rep = compare(b, g, r, ora, contact_values=True, check_rest=True)
+    report("cabinets, sleeping", rep)
+    check_joints(b, g, r, ora)
+    cols = g["colour"]
+    for s in range(b.n_scenes):
+        b0 = int(b.body_offset[s])
+        k = g["key"][s, :int(g["count"][s])].astype(np.int64)
+        a = k >> 20
+        isp = b.joint[b0:int(b.body_offset[s + 1])] > 0
+        assert np.all(cols[s, :len(k)][isp[a]] >= 0), "a contact of a part was left asleep"
+
+
+def state(sim):
+    import torch
+    torch.cuda.synchronize()
+    cnt, key, lam = sim.cache()
+    out = dict(pose=sim.pose.cpu().numpy().copy(), vel=sim.vel.cpu().numpy().copy(),
+               joint=sim.joint_state.cpu().numpy().copy(), count=cnt.cpu().numpy().copy(),
+               key=key.cpu().numpy().copy(), lam=lam.cpu().numpy().copy(),
+               **{k: v.cpu().numpy().copy() for k, v in sim.stats.items()})
+    if sim.arm_state is not None:
+        out["arm"] = sim.arm_state.cpu().numpy().copy()
+    return out
+
+
+@pytest.mark.parametrize("variant", ["persistent", "hbm", "threads"])
+def test_parts_launches_bit_identical(torch_cuda, variant):
+    """60 steps of clutter with cabinets and the articulated arm: every launch
+    gives the same bits as one 64-thread workgroup per scene in LDS."""
+    torch = torch_cuda
+    from paper_2106_14405_amd.sim import Sim
+    b = S.batch_clutter(12, seed0=10300, arm=2, cabinets=2)
+    rng = np.random.default_rng(5)
+    js = np.zeros((2, b.n_bodies), np.float32)
+    for g in np.nonzero(b.joint)[0]:
+        js[1, g] = rng.uniform(-2.0, 2.0) if b.joint[g] == 1 else rng.uniform(-0.5, 0.5)
+    sims = []
+    for alt in (False, True):
+        kw = dict(max_pairs=2048, max_contacts=2048, warm=O.PREV, tol=1e-4, threads=64)
+        if alt and variant == "hbm":
+            kw["hbm_min_bodies"] = 1
+        if alt and variant == "threads":
+            kw["threads"] = 256
+        sm = Sim(b, **kw)
+        sm.joint_state.copy_(torch.as_tensor(js))
+        if alt and variant == "persistent":
+            sm.set_persistent(True, 64)
+        sims.append(sm)
+    for t in range(60):
+        act = torch.as_tensor(sweep_actions(b.n_scenes, t + 40), device="cuda:0", dtype=torch.float32)
+        for sm in sims:
+            sm.step(act, DT, 200)
+        if t % 20 == 19:
+            x, y = state(sims[0]), state(sims[1])
+            for k in x:
+                assert np.array_equal(x[k], y[k]), f"step {t}: {k} differs"
+    assert np.abs(state(sims[0])["joint"][1]).max() > 0.05   # the parts did move
+
+
+def test_parts_reset_from_pool(torch_cuda):
+    """A masked reset restores the pool entry's joint state with its poses."""
+    torch = torch_cuda
+    from paper_2106_14405_amd import _lib as L
+    from paper_2106_14405_amd.sim import Sim
+    b = S.batch_clutter(4, seed0=10400, arm=True, cabinets=2)
+    sim = Sim(b, warm=O.PREV)
+    pose0, vel0 = sim.pose.clone(), sim.vel.clone()
+    th0 = sim.theta.clone()
+    js0 = torch.zeros_like(sim.joint_state)
+    js0[1, torch.as_tensor(np.nonzero(b.joint)[0], device=sim.device)] = 0.7
+    sim.joint_state.copy_(js0)
+    for t in range(20):
+        sim.step(None, DT, 20)
+    torch.cuda.synchronize()
+    moved = sim.joint_state.cpu().numpy()
+    assert np.abs(moved[0]).max() > 0.05
+    mask = torch.as_tensor([1, 0, 1, 0], dtype=torch.uint8, device=sim.device)
+    with pytest.raises(L.SimError):
+        sim.reset(mask, pose0, vel0, th0)               # the pool must hold the joint state
+    js_pool = torch.zeros_like(sim.joint_state)
+    sim.reset(mask, pose0, vel0, th0, joint_state=js_pool)
+    torch.cuda.synchronize()
+    after = sim.joint_state.cpu().numpy()
+    off = b.body_offset
+    for s in range(4):
+        sl = slice(int(off[s]), int(off[s + 1]))
+        if s in (0, 2):
+            assert np.all(after[:, sl] == 0.0)
+            assert torch.equal(sim.pose[:, sl], pose0[:, sl])
+        else:
+            assert np.array_equal(after[:, sl], moved[:, sl])
+
+
+def test_parts_refusals(torch_cuda):
+    from paper_2106_14405_amd import _lib as L
+    from paper_2106_14405_amd.sim import Sim
+    b = S.batch_clutter(2, seed0=10000, arm=True, cabinets=2)
+    with pytest.raises(L.SimError):
+        Sim(b, solver=L.JACOBI)
+    with pytest.raises(L.SimError):
+        Sim(b, warm=O.LEARNED)
+    sim = Sim(b, warm=O.PREV)
+    with pytest.raises(L.SimError, match="container parts"):
+        sim.set_solver(L.JACOBI, L.PREV, 0.0)
+
+    def bad(match=None, **change):
+        bb = S.Batch(**{**b.__dict__})
+        for k, fn in change.items():
+            v = getattr(bb, k).copy()
+            fn(v)
+            setattr(bb, k, v)
+        with pytest.raises(L.SimError, match=match):
+            Sim(bb, warm=O.PREV)
+    p0 = int(np.nonzero(b.joint)[0][0])
+    bad(joint=lambda v: v.__setitem__(p0, 3))                       # unknown kind
+    bad(joint=lambda v: v.__setitem__(0, 1))                        # a static body as a part
+    bad(joint_axis=lambda v: v.__setitem__(p0, (1.0, 1.0, 0.0)))    # not a unit axis
+    bad(joint_limits=lambda v: v.__setitem__(p0, (0.5, -0.5)))      # lower above upper
+    bad(joint_parent=lambda v: v.__setitem__(p0, 9999))             # outside the scene
+    # 17 parts in one scene
+    n0 = int(b.body_offset[1])
+    dyn = [i for i in range(n0 - 7) if b.motion[i] == S.DYNAMIC and b.joint[i] == 0][:13]
+
+    def many(v):
+        v[dyn] = 2
+
+    def axes(v):
+        v[dyn] = (1.0, 0.0, 0.0)
+    bad(match="16 container parts", joint=many, joint_axis=axes)
