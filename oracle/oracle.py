@@ -52,7 +52,9 @@ class Model(C.Structure):
                 ("rest_thresh", _d), ("ground_friction", _d), ("ground_restitution", _d),
                 ("sleep_speed", _d), ("sleep_steps", C.c_int), ("motor_kp", _d), ("motor_max", _d),
                 ("joint", _P(C.c_uint8)), ("joint_axis", _P(_d)), ("joint_anchor", _P(_d)),
-                ("joint_limits", _P(_d)), ("joint_parent", _P(C.c_int32))]
+                ("joint_limits", _P(_d)), ("joint_parent", _P(C.c_int32)),
+                ("n_hulls", C.c_int), ("hull_index", _P(C.c_int32)), ("hull_vert", _P(_d)),
+                ("hull_face", _P(C.c_int32))]
 
 
 class Cache(C.Structure):
@@ -93,6 +95,11 @@ def lib():
         L.ora_collide.argtypes = [C.c_int, _P(_d), _P(_d), C.c_int, _P(_d), _P(_d), C.c_int, _d,
                                   _P(C.c_int), _P(_d), _P(_d), _P(_d), _P(C.c_int)]
         L.ora_collide.restype = C.c_int
+        L.ora_collide_hulls.argtypes = [_P(Model), C.c_int, _P(_d), _P(_d), C.c_int, _P(_d), _P(_d), C.c_int, _d,
+                                        _P(C.c_int), _P(_d), _P(_d), _P(_d), _P(C.c_int)]
+        L.ora_collide_hulls.restype = C.c_int
+        L.ora_hull_mass.argtypes = [_P(Model), C.c_int, _d, _P(_d), _P(_d), _P(_d)]
+        L.ora_hull_mass.restype = C.c_int
         L.ora_pairs.argtypes = [_P(Model), _P(_d), C.c_int, _P(C.c_uint32), C.c_int]
         L.ora_pairs.restype = C.c_int
         L.ora_arm_query.argtypes = [_P(Model), _P(_d), _P(_d), C.c_int, _d, _P(C.c_uint8), _P(_d),
@@ -175,6 +182,9 @@ class OracleSim:
             self.m.joint_anchor = _ptr(self.joint_anchor, _d)
             self.m.joint_limits = _ptr(self.joint_limits, _d)
             self.m.joint_parent = _ptr(self.joint_parent, C.c_int32)
+        self.has_hulls = getattr(b, "hull_index", None) is not None
+        if self.has_hulls:
+            self._hulls = set_hulls(self.m, b.hull_index, b.hull_vert, b.hull_face)
         self.cache_cap = cache_cap
         self.c_count = np.zeros(self.S, np.int32)
         self.c_key = np.zeros(self.S * cache_cap, np.uint32)
@@ -335,9 +345,52 @@ class OracleSim:
         return res
 
 
-def collide(shape_a, param_a, pose_a, shape_b=None, param_b=None, pose_b=None, margin=0.02):
+def set_hulls(m, hull_index, hull_vert, hull_face):
+    """Point the model's hull fields at float64 / int32 copies of a hull
+    library; returns the arrays (keep them alive with the model)."""
+    keep = (np.ascontiguousarray(hull_index, np.int32).reshape(-1),
+            np.ascontiguousarray(hull_vert, np.float64).reshape(-1),
+            np.ascontiguousarray(hull_face, np.int32).reshape(-1))
+    m.n_hulls = len(keep[0]) // 4
+    m.hull_index = _ptr(keep[0], C.c_int32)
+    m.hull_vert = _ptr(keep[1], _d)
+    m.hull_face = _ptr(keep[2], C.c_int32)
+    return keep
+
+
+def hull_library(hulls):
+    """(index [H,4], vertices [V,3], faces [F,8]) of a list of (vertices, face loops)."""
+    idx, vs, fs = [], [], []
+    nv = nf = 0
+    for V, F in hulls:
+        idx.append((nv, len(V), nf, len(F)))
+        vs.append(np.asarray(V, np.float64))
+        for f in F:
+            row = np.full(8, -1, np.int32)
+            row[:len(f)] = f
+            fs.append(row)
+        nv += len(V)
+        nf += len(F)
+    return np.asarray(idx, np.int32), np.concatenate(vs), np.asarray(fs, np.int32)
+
+
+def hull_mass(hulls, h, mass):
+    """(inertia [3,3] about the body origin, centre of mass [3], volume) of hull h."""
+    m = Model()
+    keep = set_hulls(m, *hull_library(hulls))
+    I = np.zeros(9)
+    c = np.zeros(3)
+    v = C.c_double(0.0)
+    if lib().ora_hull_mass(C.byref(m), int(h), float(mass), _ptr(I, _d), _ptr(c, _d), C.byref(v)) != 0:
+        raise ValueError("unusable hull")
+    del keep
+    return I.reshape(3, 3), c, v.value
+
+
+def collide(shape_a, param_a, pose_a, shape_b=None, param_b=None, pose_b=None, margin=0.02, hulls=None):
     """Contacts of one pair (b = ground when shape_b is None).  Returns a list
-    of (feature, normal[3], point[3], phi) and the ambiguity count."""
+    of (feature, normal[3], point[3], phi) and the ambiguity count.  hulls:
+    a list of (vertices, face loops) that HULL shapes index by param[0]."""
     L = lib()
     pa = np.ascontiguousarray(param_a, np.float64)
     xa = np.ascontiguousarray(pose_a, np.float64)
@@ -349,9 +402,14 @@ def collide(shape_a, param_a, pose_a, shape_b=None, param_b=None, pose_b=None, m
     p = np.zeros(12)
     ph = np.zeros(4)
     amb = C.c_int(0)
-    k = L.ora_collide(int(shape_a), _ptr(pa, _d), _ptr(xa, _d), int(shape_b or 0), _ptr(pb, _d),
-                      _ptr(xb, _d), int(ground), float(margin), f.ctypes.data_as(_P(C.c_int)),
-                      _ptr(n, _d), _ptr(p, _d), _ptr(ph, _d), C.byref(amb))
+    m = Model()
+    keep = set_hulls(m, *hull_library(hulls)) if hulls else None
+    k = L.ora_collide_hulls(C.byref(m), int(shape_a), _ptr(pa, _d), _ptr(xa, _d), int(shape_b or 0), _ptr(pb, _d),
+                            _ptr(xb, _d), int(ground), float(margin), f.ctypes.data_as(_P(C.c_int)),
+                            _ptr(n, _d), _ptr(p, _d), _ptr(ph, _d), C.byref(amb))
+    del keep
+    if k < 0:
+        raise ValueError("oracle rejected the pair")
     return [(int(f[i]), n[3 * i:3 * i + 3].copy(), p[3 * i:3 * i + 3].copy(), float(ph[i]))
             for i in range(k)], amb.value
 

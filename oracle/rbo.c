@@ -95,6 +95,8 @@ typedef struct {
     int joint;
     V ja, jo;
     double jM, qd;
+    const struct HullS *hull;   /* shape ORA_HULL: its hull (prm: its bounding box half-extents) */
+    double Ib[3][3];    /* inertia tensor in the body frame (dynamic bodies) */
 } Body;
 
 /* Principal moments of a solid body of uniform density. */
@@ -123,7 +125,7 @@ static void body_aabb(Body *b, double margin) {
         double e = b->prm[0] + margin;
         b->lo = sub(b->x, mk(e, e, e));
         b->hi = add(b->x, mk(e, e, e));
-    } else if (b->shape == ORA_BOX) {
+    } else if (b->shape == ORA_BOX || b->shape == ORA_HULL) {   /* a hull: its bounding box */
         V e;
         e.x = fabs(b->R.m[0][0]) * b->prm[0] + fabs(b->R.m[0][1]) * b->prm[1] + fabs(b->R.m[0][2]) * b->prm[2] + margin;
         e.y = fabs(b->R.m[1][0]) * b->prm[0] + fabs(b->R.m[1][1]) * b->prm[1] + fabs(b->R.m[1][2]) * b->prm[2] + margin;
@@ -144,7 +146,25 @@ static void body_aabb(Body *b, double margin) {
  * argument to the FIRST; phi is the signed separation along n (negative =
  * penetration); p is the midpoint of the two surface witness points; f is a
  * feature id.  A contact is kept iff phi <= margin. */
-typedef struct { int shape; V x; M3 R; double prm[3]; } Geom;
+/* A convex hull (shape ORA_HULL) in its body frame: vertices, face planes
+ * (outward unit normal n and offset d: n . x = d on the face), faces as
+ * vertex loops counter-clockwise seen from outside, and the undirected
+ * edges; the half-extents of its local bounding box and its largest
+ * vertex distance from the origin. */
+#define HULL_MAXV 32
+#define HULL_MAXF 32
+#define HULL_MAXE 64
+#define HULL_MAXL 8
+typedef struct HullS {
+    int nv, nf, ne;
+    V v[HULL_MAXV];
+    V fn[HULL_MAXF];
+    double fd[HULL_MAXF];
+    int nl[HULL_MAXF], loop[HULL_MAXF][HULL_MAXL];
+    int ea[HULL_MAXE], eb[HULL_MAXE];
+    double h[3], rad;
+} Hull;
+typedef struct { int shape; V x; M3 R; double prm[3]; const Hull *hull; } Geom;
 typedef struct { int f; V n, p; double phi; } PC;
 
 static int keep(double phi, double margin, int *amb) {
@@ -711,10 +731,734 @@ static int box_box(const Geom *A, const Geom *B, double margin, PC *out, int *am
     return ns;
 }
 
+
+/* ------------------------------------------------------------ convex hulls
+ * Convex collision proxies (Sec. 3: objects and furniture collide as convex
+ * hulls of their parts; Sec. 4.3: simplified collision geometry).  From the
+ * library's vertices and face loops: a face's plane is Newell's normal of
+ * its loop (Newell 1972, as in Sutherland, Sproull and Schumacker 1974)
+ * through the mean of its vertices; the edges are the loops' consecutive
+ * vertex pairs, each once, in order of first appearance (faces in order,
+ * each loop from its first vertex).  A box is the hull of its 8 corners
+ * (corner k at (+-hx, +-hy, +-hz), + where bit 0, 1, 2 of k is set) with
+ * faces -x, +x, -y, +y, -z, +z, loops {0 4 6 2} {1 3 7 5} {0 1 5 4}
+ * {2 6 7 3} {0 2 3 1} {4 5 7 6}. */
+static int hull_finish(Hull *H) {
+    H->ne = 0;
+    H->h[0] = H->h[1] = H->h[2] = 0.0;
+    H->rad = 0.0;
+    for (int k = 0; k < H->nv; k++) {
+        H->h[0] = fmax(H->h[0], fabs(H->v[k].x));
+        H->h[1] = fmax(H->h[1], fabs(H->v[k].y));
+        H->h[2] = fmax(H->h[2], fabs(H->v[k].z));
+        H->rad = fmax(H->rad, sqrt(len2(H->v[k])));
+    }
+    for (int f = 0; f < H->nf; f++) {
+        const int n = H->nl[f];
+        if (n < 3) return -1;
+        V nn = mk(0, 0, 0), c = mk(0, 0, 0);
+        for (int k = 0; k < n; k++) {
+            V a = H->v[H->loop[f][k]], b = H->v[H->loop[f][(k + 1) % n]];
+            nn.x += (a.y - b.y) * (a.z + b.z);
+            nn.y += (a.z - b.z) * (a.x + b.x);
+            nn.z += (a.x - b.x) * (a.y + b.y);
+            c = add(c, a);
+        }
+        double L = sqrt(len2(nn));
+        if (!(L > 0)) return -1;
+        H->fn[f] = scl(nn, 1.0 / L);
+        H->fd[f] = dot(H->fn[f], scl(c, 1.0 / n));
+        for (int k = 0; k < n; k++) {
+            int a = H->loop[f][k], b = H->loop[f][(k + 1) % n];
+            int lo = a < b ? a : b, hi = a < b ? b : a, seen = 0;
+            for (int e = 0; e < H->ne; e++) if (H->ea[e] == lo && H->eb[e] == hi) seen = 1;
+            if (!seen) {
+                if (H->ne >= HULL_MAXE) return -1;
+                H->ea[H->ne] = lo;
+                H->eb[H->ne] = hi;
+                H->ne++;
+            }
+        }
+    }
+    return 0;
+}
+
+static int hull_from_lib(const ora_model *m, int h, Hull *H) {
+    if (!m || h < 0 || h >= m->n_hulls) return -1;
+    const int32_t *ix = m->hull_index + 4 * h;
+    int v0 = ix[0], nv = ix[1], f0 = ix[2], nf = ix[3];
+    if (nv < 4 || nv > HULL_MAXV || nf < 4 || nf > HULL_MAXF) return -1;
+    H->nv = nv;
+    H->nf = nf;
+    for (int k = 0; k < nv; k++)
+        H->v[k] = mk(m->hull_vert[3 * (v0 + k)], m->hull_vert[3 * (v0 + k) + 1], m->hull_vert[3 * (v0 + k) + 2]);
+    for (int f = 0; f < nf; f++) {
+        int n = 0;
+        for (int k = 0; k < HULL_MAXL; k++) {
+            int vi = m->hull_face[HULL_MAXL * (f0 + f) + k];
+            if (vi < 0) break;
+            if (vi >= nv) return -1;
+            H->loop[f][n++] = vi;
+        }
+        H->nl[f] = n;
+    }
+    return hull_finish(H);
+}
+
+static void hull_box(const double *hb, Hull *H) {
+    static const int loops[6][4] = {{0, 4, 6, 2}, {1, 3, 7, 5}, {0, 1, 5, 4}, {2, 6, 7, 3}, {0, 2, 3, 1}, {4, 5, 7, 6}};
+    H->nv = 8;
+    H->nf = 6;
+    for (int k = 0; k < 8; k++)
+        H->v[k] = mk((k & 1) ? hb[0] : -hb[0], (k & 2) ? hb[1] : -hb[1], (k & 4) ? hb[2] : -hb[2]);
+    for (int f = 0; f < 6; f++) {
+        H->nl[f] = 4;
+        for (int k = 0; k < 4; k++) H->loop[f][k] = loops[f][k];
+    }
+    hull_finish(H);
+}
+
+/* Every hull of the library (NULL when there are none or one is unusable). */
+static Hull *hulls_of(const ora_model *m) {
+    if (!m || m->n_hulls <= 0 || !m->hull_index || !m->hull_vert || !m->hull_face) return NULL;
+    Hull *HL = malloc(sizeof(Hull) * m->n_hulls);
+    for (int h = 0; h < m->n_hulls; h++)
+        if (hull_from_lib(m, h, &HL[h]) != 0) { free(HL); return NULL; }
+    return HL;
+}
+
+/* Mass properties of a solid hull of uniform density: the solid is the
+ * union of the tetrahedra (origin, a, b, c) over a fan triangulation of
+ * every face loop (signed volumes, so any interior origin works); a
+ * tetrahedron (0, a, b, c) of volume v has second moment
+ * v/20 (a a^T + b b^T + c c^T + s s^T), s = a + b + c, and centroid s/4. */
+static int hull_mass_props(const Hull *H, double mass, double I[3][3], V *com, double *vol) {
+    double C[3][3] = {{0}};
+    double V0 = 0;
+    V cm = mk(0, 0, 0);
+    for (int f = 0; f < H->nf; f++)
+        for (int k = 1; k + 1 < H->nl[f]; k++) {
+            V a = H->v[H->loop[f][0]], b = H->v[H->loop[f][k]], c = H->v[H->loop[f][k + 1]];
+            double v = dot(a, cross(b, c)) / 6.0;
+            V sm = add(add(a, b), c);
+            V P[4] = {a, b, c, sm};
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    double t = 0;
+                    for (int q = 0; q < 4; q++) t += comp(P[q], i) * comp(P[q], j);
+                    C[i][j] += v / 20.0 * t;
+                }
+            V0 += v;
+            cm = add(cm, scl(sm, v / 4.0));
+        }
+    if (!(V0 > 0)) return -1;
+    double rho = mass / V0, tr = (C[0][0] + C[1][1] + C[2][2]) * rho;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) I[i][j] = (i == j ? tr : 0.0) - rho * C[i][j];
+    *com = scl(cm, 1.0 / V0);
+    *vol = V0;
+    return 0;
+}
+
+int ora_hull_mass(const ora_model *m, int h, double mass, double *I, double *com, double *volume) {
+    Hull H;
+    if (hull_from_lib(m, h, &H) != 0) return -1;
+    double T[3][3];
+    V c;
+    if (hull_mass_props(&H, mass, T, &c, volume) != 0) return -1;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) I[3 * i + j] = T[i][j];
+    com[0] = c.x; com[1] = c.y; com[2] = c.z;
+    return 0;
+}
+
+/* Whether p (in the face's plane) lies inside face f's loop (strictly or on
+ * an edge: the side of every loop edge's in-plane outward normal). */
+static int inside_loop(const Hull *H, int f, V p) {
+    const int n = H->nl[f];
+    for (int k = 0; k < n; k++) {
+        V a = H->v[H->loop[f][k]], b = H->v[H->loop[f][(k + 1) % n]];
+        if (dot(cross(sub(b, a), H->fn[f]), sub(p, a)) > 0) return 0;
+    }
+    return 1;
+}
+
+/* Closest point of the hull to p, for p outside it: the projections onto
+ * faces that p lies above and that fall inside their loops, and the closest
+ * point of every edge; the nearest wins (ties: faces first, lower index).
+ * Returns the distance; *q the point, *face the face (-1 for an edge). */
+static double hull_closest(const Hull *H, V p, V *q, int *face) {
+    double best = INFINITY;
+    *face = -1;
+    for (int f = 0; f < H->nf; f++) {
+        double s = dot(H->fn[f], p) - H->fd[f];
+        if (s <= 0) continue;
+        V pr = sub(p, scl(H->fn[f], s));
+        if (inside_loop(H, f, pr) && s < best) { best = s; *q = pr; *face = f; }
+    }
+    for (int e = 0; e < H->ne; e++) {
+        V a = H->v[H->ea[e]], d = sub(H->v[H->eb[e]], a);
+        double t = clampd(dot(sub(p, a), d) / len2(d), 0.0, 1.0);
+        V c = add(a, scl(d, t));
+        double L = sqrt(len2(sub(p, c)));
+        if (L < best) { best = L; *q = c; *face = -1; }
+    }
+    return best;
+}
+
+/* Choice among scores v[idx[0..n)] (candidates in index order) with a
+ * tolerance: the first candidate whose score is within tol of the largest
+ * (so scores equal up to rounding, as on a symmetric face, go to the lower
+ * index); a score within band of the cut is ambiguous.  Skips used[].  Returns the
+ * candidate, -1 if none. */
+static int argmax_tol(const double *v, const int *idx, int n, const int *used, double tol, double band, int *amb) {
+    double vmax = -INFINITY;
+    for (int k = 0; k < n; k++) if (!used[idx[k]]) vmax = fmax(vmax, v[idx[k]]);
+    int best = -1;
+    for (int k = 0; k < n; k++) {
+        int q = idx[k];
+        if (used[q]) continue;
+        if (fabs(v[q] - (vmax - tol)) < band) (*amb)++;
+        if (best < 0 && v[q] >= vmax - tol) best = q;
+    }
+    return best;
+}
+
+/* At most 4 of n candidate points p[idx[k]] (in index order; n > 4): the
+ * first, the farthest from it, the one spanning the largest triangle with
+ * those, the one adding most to the three triangles' areas; each by
+ * argmax_tol with CLIP_ON (areas scaled by the first edge's length, the
+ * last by the triangle's perimeter). */
+static void reduce4(const V *p, const int *idx, int n, int first, int *used, int *amb) {
+    double sc[96];
+    used[first] = 1;
+    for (int k = 0; k < n; k++) sc[idx[k]] = sqrt(len2(sub(p[idx[k]], p[first])));
+    int i2 = argmax_tol(sc, idx, n, used, CLIP_ON, BAND, amb);
+    used[i2] = 1;
+    V e12 = sub(p[i2], p[first]);
+    double l12 = sqrt(len2(e12));
+    for (int k = 0; k < n; k++) sc[idx[k]] = sqrt(len2(cross(e12, sub(p[idx[k]], p[first]))));
+    int i3 = argmax_tol(sc, idx, n, used, CLIP_ON * l12, BAND * l12, amb);
+    used[i3] = 1;
+    V e23 = sub(p[i3], p[i2]), e31 = sub(p[first], p[i3]);
+    double per = l12 + sqrt(len2(e23)) + sqrt(len2(e31));
+    for (int k = 0; k < n; k++) {
+        int q = idx[k];
+        sc[q] = sqrt(len2(cross(e12, sub(p[q], p[first])))) + sqrt(len2(cross(e23, sub(p[q], p[i2])))) +
+                sqrt(len2(cross(e31, sub(p[q], p[i3]))));
+    }
+    int i4 = argmax_tol(sc, idx, n, used, CLIP_ON * per, BAND * per, amb);
+    used[i4] = 1;
+}
+
+/* Hull (first) on the ground plane: vertices with depth <= margin; above
+ * 4, reduce4 from the first vertex within CLIP_ON of the deepest (a flat
+ * face resting on the ground keeps a spread of its corners); reported in
+ * vertex order, the feature the vertex index. */
+static int hull_ground(const Geom *A, double margin, PC *out, int *amb) {
+    const Hull *H = A->hull;
+    V w[HULL_MAXV];
+    double z[HULL_MAXV];
+    int id[HULL_MAXV], m = 0;
+    for (int k = 0; k < H->nv; k++) {
+        w[k] = add(A->x, Rv(&A->R, H->v[k]));
+        z[k] = w[k].z;
+        if (keep(z[k], margin, amb)) id[m++] = k;
+    }
+    if (m > 4) {
+        double nz[HULL_MAXV];
+        int used[96] = {0};
+        for (int k = 0; k < H->nv; k++) nz[k] = -z[k];
+        int first = argmax_tol(nz, id, m, used, CLIP_ON, BAND, amb);
+        reduce4(w, id, m, first, used, amb);
+        m = 0;
+        for (int k = 0; k < H->nv; k++) if (used[k]) id[m++] = k;
+    }
+    for (int k = 0; k < m; k++) {
+        PC c;
+        c.n = mk(0, 0, 1);
+        c.phi = z[id[k]];
+        c.p = mk(w[id[k]].x, w[id[k]].y, 0.5 * w[id[k]].z);
+        c.f = id[k];
+        out[k] = c;
+    }
+    return m;
+}
+
+/* Sphere (first) against a hull (second), in the hull frame: a centre
+ * outside leaves along the line to the hull's closest point; a centre
+ * inside through the face of least penetration (ties: lower face). */
+static int sphere_hull(const Geom *S, const Geom *G, double margin, PC *out, int *amb) {
+    const Hull *H = G->hull;
+    double r = S->prm[0];
+    V l = RTv(&G->R, sub(S->x, G->x));
+    double smax = -INFINITY, sf[HULL_MAXF];
+    int fm = 0;
+    for (int f = 0; f < H->nf; f++) {
+        sf[f] = dot(H->fn[f], l) - H->fd[f];
+        if (sf[f] > smax) { smax = sf[f]; fm = f; }
+    }
+    if (fabs(smax) < BAND) (*amb)++;
+    V nl, q;
+    double phi;
+    if (smax <= 0) {
+        for (int f = 0; f < H->nf; f++) if (f != fm && fabs(sf[f] - smax) < BAND) (*amb)++;
+        nl = H->fn[fm];
+        q = sub(l, scl(nl, smax));
+        phi = smax - r;
+    } else {
+        int face;
+        double dist = hull_closest(H, l, &q, &face);
+        if (dist < BAND) (*amb)++;
+        nl = scl(sub(l, q), 1.0 / dist);
+        phi = dist - r;
+    }
+    PC c;
+    c.n = Rv(&G->R, nl);
+    V wb = add(G->x, Rv(&G->R, q));
+    V wa = sub(S->x, scl(c.n, r));
+    c.p = scl(add(wa, wb), 0.5);
+    c.phi = phi;
+    c.f = 0;
+    if (!keep(phi, margin, amb)) return 0;
+    out[0] = c;
+    return 1;
+}
+
+/* The core segment p0 + t d clipped to face f's prism (the in-plane
+ * outward normals of its loop edges); ok iff t0 <= t1. */
+static int clip_prism(const Hull *H, int f, V p0, V d, double *t0, double *t1) {
+    double a = 0.0, b = 1.0;
+    const int n = H->nl[f];
+    for (int k = 0; k < n; k++) {
+        V va = H->v[H->loop[f][k]], vb = H->v[H->loop[f][(k + 1) % n]];
+        V mm = cross(sub(vb, va), H->fn[f]);
+        double g0 = dot(mm, sub(p0, va)), gd = dot(mm, d);
+        if (gd == 0.0) {
+            if (g0 > 0) return 0;
+            continue;
+        }
+        double t = -g0 / gd;
+        if (gd > 0) b = fmin(b, t);
+        else a = fmax(a, t);
+    }
+    *t0 = a;
+    *t1 = b;
+    return a <= b;
+}
+
+/* One contact of the core point l against face f (hull frame). */
+static PC hull_face_contact(const Hull *H, int f, V l, double r, int ft) {
+    PC c;
+    c.n = H->fn[f];
+    double s = dot(c.n, l) - H->fd[f];
+    c.phi = s - r;
+    V q = sub(l, scl(c.n, s));
+    c.p = scl(add(q, sub(l, scl(c.n, r))), 0.5);
+    c.f = ft;
+    return c;
+}
+
+/* Face region of a core point l outside the hull: the face whose plane it
+ * is above and whose loop holds its projection (-1: edge or vertex region). */
+static int face_region(const Hull *H, V l) {
+    int best = -1;
+    double bs = 0;
+    for (int f = 0; f < H->nf; f++) {
+        double s = dot(H->fn[f], l) - H->fd[f];
+        if (s > 0 && inside_loop(H, f, sub(l, scl(H->fn[f], s))) && (best < 0 || s > bs)) { best = f; bs = s; }
+    }
+    return best;
+}
+
+/* Capsule (first) against a hull (second), in the hull frame, after
+ * capsule_box:
+ * 1. Core separated from the hull (the segment clipped to every face's
+ *    half-space (Cyrus and Beck 1978) is empty): closest points among the
+ *    ends against the hull and the core against every edge (Ericson 2005,
+ *    5.1.9, clamped); nearest wins (ties: the order tried).
+ * 2. Closest core point in a face's region with the core within ~1 mrad
+ *    of parallel to that face: two contacts at the ends of the core clipped
+ *    to the face's prism (f 0, 1); otherwise one at the closest points (f 2).
+ * 3. Core touching the hull: leave through the face whose plane the deeper
+ *    core end lies least below (ties: lower face); contacts at the ends of
+ *    the core clipped to that face's prism (f 0, 1), else at the deeper end
+ *    (f 3). */
+static int capsule_hull(const Geom *C, const Geom *G, double margin, PC *out, int *amb) {
+    const Hull *H = G->hull;
+    double r = C->prm[0];
+    V P0, D;
+    capsule_seg(C, &P0, &D);
+    V p0 = RTv(&G->R, sub(P0, G->x));
+    V d = RTv(&G->R, D);
+    double dl = sqrt(len2(d));
+    double tin = 0.0, tout = 1.0;
+    for (int f = 0; f < H->nf; f++) {
+        double dn = dot(H->fn[f], d), s0 = dot(H->fn[f], p0) - H->fd[f];
+        if (dn == 0.0) {
+            if (fabs(s0) < BAND) (*amb)++;
+            if (s0 > 0) tout = -1.0;
+            continue;
+        }
+        double t = -s0 / dn;
+        if (dn < 0) tin = fmax(tin, t);
+        else tout = fmin(tout, t);
+    }
+    int meets = tin <= tout;
+    if (fabs(tout - tin) * dl < BAND) (*amb)++;
+    PC loc[2];
+    int n = 0;
+    if (!meets) {
+        /* candidates: (distance, core parameter, hull point) */
+        double cd[2 + HULL_MAXE], ct[2 + HULL_MAXE];
+        V cq[2 + HULL_MAXE];
+        int nc = 0;
+        for (int e2 = 0; e2 < 2; e2++) {
+            int face;
+            V q;
+            cd[nc] = hull_closest(H, add(p0, scl(d, (double)e2)), &q, &face);
+            ct[nc] = (double)e2;
+            cq[nc] = q;
+            nc++;
+        }
+        for (int e = 0; e < H->ne; e++) {
+            V a = H->v[H->ea[e]], u = sub(H->v[H->eb[e]], a);
+            /* closest points of p0 + t d and a + s u, t, s in [0, 1] */
+            V w = sub(p0, a);
+            double A2 = len2(d), B2 = dot(d, u), C2 = len2(u), D2 = dot(d, w), E2 = dot(u, w);
+            double den = A2 * C2 - B2 * B2, t = 0.0, sv;
+            if (den > 1e-18 * A2 * C2) t = clampd((B2 * E2 - C2 * D2) / den, 0.0, 1.0);
+            sv = (B2 * t + E2) / C2;
+            if (sv < 0.0) { sv = 0.0; t = clampd(-D2 / A2, 0.0, 1.0); }
+            else if (sv > 1.0) { sv = 1.0; t = clampd((B2 - D2) / A2, 0.0, 1.0); }
+            V pc = add(p0, scl(d, t)), qc = add(a, scl(u, sv));
+            cd[nc] = sqrt(len2(sub(pc, qc)));
+            ct[nc] = t;
+            cq[nc] = qc;
+            nc++;
+        }
+        int bi = 0;
+        for (int i = 1; i < nc; i++) if (cd[i] < cd[bi]) bi = i;
+        double dist = cd[bi], t = ct[bi];
+        V l = add(p0, scl(d, t)), q = cq[bi];
+        if (dist < BAND) (*amb)++;
+        int fr = face_region(H, l);
+        int facecase = fr >= 0 && fabs(dot(d, H->fn[fr])) <= SIN_PAR * dl;
+        if (fr >= 0) {
+            double thr = SIN_PAR * dl;
+            if (fabs(fabs(dot(d, H->fn[fr])) - thr) < 1e-2 * thr) (*amb)++;
+        }
+        /* a plateau of the distance at another place decides differently */
+        for (int i = 0; i < nc; i++) {
+            if (i == bi || fabs(cd[i] - dist) >= BAND || fabs(ct[i] - t) * dl <= BAND) continue;
+            V li = add(p0, scl(d, ct[i]));
+            int fi = face_region(H, li);
+            int fci = fi >= 0 && fabs(dot(d, H->fn[fi])) <= SIN_PAR * dl;
+            if (!facecase || !fci || fi != fr) { (*amb)++; break; }
+        }
+        int done = 0;
+        if (facecase) {
+            double t0, t1;
+            if (clip_prism(H, fr, p0, d, &t0, &t1)) {
+                if (fabs(t1 - t0) * dl < BAND) (*amb)++;
+                loc[n++] = hull_face_contact(H, fr, add(p0, scl(d, t0)), r, 0);
+                if (t1 > t0) loc[n++] = hull_face_contact(H, fr, add(p0, scl(d, t1)), r, 1);
+                done = 1;
+            }
+        }
+        if (!done) {
+            PC c;
+            c.n = scl(sub(l, q), 1.0 / dist);
+            c.phi = dist - r;
+            c.p = scl(add(q, sub(l, scl(c.n, r))), 0.5);
+            c.f = 2;
+            loc[n++] = c;
+        }
+    } else {
+        double best = INFINITY, second = INFINITY;
+        int bf = 0;
+        V p1 = add(p0, d);
+        for (int f = 0; f < H->nf; f++) {
+            double ex = H->fd[f] - fmin(dot(H->fn[f], p0), dot(H->fn[f], p1));
+            if (ex < best) { second = best; best = ex; bf = f; }
+            else if (ex < second) second = ex;
+        }
+        if (second - best < BAND) (*amb)++;
+        double t0, t1;
+        int ok = clip_prism(H, bf, p0, d, &t0, &t1);
+        if (ok && fabs(t1 - t0) * dl < BAND) (*amb)++;
+        if (ok) {
+            loc[n++] = hull_face_contact(H, bf, add(p0, scl(d, t0)), r, 0);
+            if (t1 > t0) loc[n++] = hull_face_contact(H, bf, add(p0, scl(d, t1)), r, 1);
+        } else {
+            double e0 = dot(H->fn[bf], p0), e1 = dot(H->fn[bf], p1);
+            if (fabs(e0 - e1) < BAND) (*amb)++;
+            loc[n++] = hull_face_contact(H, bf, e0 <= e1 ? p0 : p1, r, 3);
+        }
+    }
+    int m = 0;
+    for (int k = 0; k < n; k++) {
+        if (!keep(loc[k].phi, margin, amb)) continue;
+        PC c = loc[k];
+        c.n = Rv(&G->R, loc[k].n);
+        c.p = add(G->x, Rv(&G->R, loc[k].p));
+        out[m++] = c;
+    }
+    return m;
+}
+
+/* Hull against hull (a box enters as the hull of its corners): separating
+ * axes (Gottschalk et al. 1996) over both hulls' face normals and the
+ * cross products of every edge pair, a separation being the gap between
+ * the two vertex sets' projections; the first hull's face wins near ties,
+ * edges only when clearly better (the thresholds of box_box, the largest
+ * half-extent of the two local bounding boxes for the boxes').
+ * Edge contact: closest points of the supporting edges (f 0xFF).
+ * Face contact: the incident face is the other hull's face most opposed to
+ * the reference face; the contact points are the vertices of the two
+ * faces' overlap seen along the reference normal (the polygon that
+ * clipping the incident face by the reference face's side planes leaves,
+ * Sutherland and Hodgman 1974), taken point by point with an index each:
+ * incident vertices inside every side plane (id k), incident edges crossing
+ * a side plane inside the others (id 8 + 8 k + j), reference corners inside
+ * the incident face (id 72 + j; the point on the incident face's plane
+ * along the reference normal); three-state sides as in box_box.  Kept
+ * points (depth <= margin) above 4 are reduced by reduce4 from the
+ * smallest id; the feature is (reference is the second hull) | id << 1,
+ * points in id order. */
+static int hull_hull(const Geom *A, const Geom *B, double margin, PC *out, int *amb) {
+    Hull ba, bb;
+    const Hull *HA = A->hull, *HB = B->hull;
+    if (A->shape == ORA_BOX) { hull_box(A->prm, &ba); HA = &ba; }
+    if (B->shape == ORA_BOX) { hull_box(B->prm, &bb); HB = &bb; }
+    V VA[HULL_MAXV], VB[HULL_MAXV], NA[HULL_MAXF], NB[HULL_MAXF];
+    double DA[HULL_MAXF], DB[HULL_MAXF];
+    for (int k = 0; k < HA->nv; k++) VA[k] = add(A->x, Rv(&A->R, HA->v[k]));
+    for (int k = 0; k < HB->nv; k++) VB[k] = add(B->x, Rv(&B->R, HB->v[k]));
+    for (int f = 0; f < HA->nf; f++) { NA[f] = Rv(&A->R, HA->fn[f]); DA[f] = dot(NA[f], A->x) + HA->fd[f]; }
+    for (int f = 0; f < HB->nf; f++) { NB[f] = Rv(&B->R, HB->fn[f]); DB[f] = dot(NB[f], B->x) + HB->fd[f]; }
+    double sA[HULL_MAXF], sB[HULL_MAXF];
+    int fa = 0, fb = 0;
+    for (int f = 0; f < HA->nf; f++) {
+        double s = INFINITY;
+        for (int k = 0; k < HB->nv; k++) s = fmin(s, dot(NA[f], VB[k]) - DA[f]);
+        sA[f] = s;
+        if (s > sA[fa]) fa = f;
+    }
+    for (int f = 0; f < HB->nf; f++) {
+        double s = INFINITY;
+        for (int k = 0; k < HA->nv; k++) s = fmin(s, dot(NB[f], VA[k]) - DB[f]);
+        sB[f] = s;
+        if (s > sB[fb]) fb = f;
+    }
+    double se = -INFINITY, sge = 1.0;
+    int ei = -1, ej = -1;
+    V ue = mk(0, 0, 1);
+    for (int i = 0; i < HA->ne; i++) {
+        V da = sub(VA[HA->eb[i]], VA[HA->ea[i]]);
+        da = scl(da, 1.0 / sqrt(len2(da)));
+        for (int j = 0; j < HB->ne; j++) {
+            V db = sub(VB[HB->eb[j]], VB[HB->ea[j]]);
+            db = scl(db, 1.0 / sqrt(len2(db)));
+            V c = cross(da, db);
+            double L2 = len2(c);
+            if (fabs(L2 - 1e-12) < 1e-13) (*amb)++;
+            if (L2 < 1e-12) continue;
+            V u = scl(c, 1.0 / sqrt(L2));
+            double a0 = INFINITY, a1 = -INFINITY, b0 = INFINITY, b1 = -INFINITY;
+            for (int k = 0; k < HA->nv; k++) { double x = dot(u, VA[k]); a0 = fmin(a0, x); a1 = fmax(a1, x); }
+            for (int k = 0; k < HB->nv; k++) { double x = dot(u, VB[k]); b0 = fmin(b0, x); b1 = fmax(b1, x); }
+            double s1 = a0 - b1, s2 = b0 - a1, s = fmax(s1, s2);
+            if (s > se) { se = s; ei = i; ej = j; ue = u; sge = s1 >= s2 ? 1.0 : -1.0; }
+        }
+    }
+    double smax = fmax(fmax(sA[fa], sB[fb]), se);
+    if (fabs(smax - margin) < BAND) (*amb)++;
+    if (smax > margin) return 0;
+    double hmax = 0;
+    for (int i = 0; i < 3; i++) hmax = fmax(hmax, fmax(HA->h[i], HB->h[i]));
+    int refB = 0;
+    double sface = sA[fa];
+    double thr = 0.95 * sA[fa] + 0.01 * hmax;
+    if (fabs(sB[fb] - thr) < BAND) (*amb)++;
+    if (sB[fb] > thr) { refB = 1; sface = sB[fb]; }
+    int edge = 0;
+    if (ei >= 0) {
+        double thr2 = 0.95 * sface + 0.01 * hmax;
+        if (fabs(se - thr2) < BAND) (*amb)++;
+        edge = se > thr2;
+    }
+    if (edge) {
+        /* near ties with another axis direction */
+        for (int i = 0; i < HA->ne; i++) {
+            V da = sub(VA[HA->eb[i]], VA[HA->ea[i]]);
+            da = scl(da, 1.0 / sqrt(len2(da)));
+            for (int j = 0; j < HB->ne; j++) {
+                V db = sub(VB[HB->eb[j]], VB[HB->ea[j]]);
+                db = scl(db, 1.0 / sqrt(len2(db)));
+                V c = cross(da, db);
+                double L2 = len2(c);
+                if (L2 < 1e-12) continue;
+                V u = scl(c, 1.0 / sqrt(L2));
+                if (len2(cross(u, ue)) < 1e-10) continue;
+                double a0 = INFINITY, a1 = -INFINITY, b0 = INFINITY, b1 = -INFINITY;
+                for (int k = 0; k < HA->nv; k++) { double x = dot(u, VA[k]); a0 = fmin(a0, x); a1 = fmax(a1, x); }
+                for (int k = 0; k < HB->nv; k++) { double x = dot(u, VB[k]); b0 = fmin(b0, x); b1 = fmax(b1, x); }
+                if (fabs(fmax(a0 - b1, b0 - a1) - se) < BAND) { (*amb)++; i = HA->ne; break; }
+            }
+        }
+        V N = scl(ue, sge);   /* from B to A */
+        /* supporting edges: A's edge along edge ei lowest along N, B's along ej highest */
+        V dai = sub(VA[HA->eb[ei]], VA[HA->ea[ei]]), dbj = sub(VB[HB->eb[ej]], VB[HB->ea[ej]]);
+        dai = scl(dai, 1.0 / sqrt(len2(dai)));
+        dbj = scl(dbj, 1.0 / sqrt(len2(dbj)));
+        int ia = -1, jb = -1;
+        double va = 0, vb = 0;
+        for (int k = 0; k < HA->ne; k++) {
+            V dk = sub(VA[HA->eb[k]], VA[HA->ea[k]]);
+            if (len2(cross(dk, dai)) > 1e-10 * len2(dk)) continue;
+            double x = dot(N, scl(add(VA[HA->ea[k]], VA[HA->eb[k]]), 0.5));
+            if (ia < 0 || x < va) { ia = k; va = x; }
+        }
+        for (int k = 0; k < HA->ne; k++) {
+            V dk = sub(VA[HA->eb[k]], VA[HA->ea[k]]);
+            if (k == ia || len2(cross(dk, dai)) > 1e-10 * len2(dk)) continue;
+            if (fabs(dot(N, scl(add(VA[HA->ea[k]], VA[HA->eb[k]]), 0.5)) - va) < BAND) (*amb)++;
+        }
+        for (int k = 0; k < HB->ne; k++) {
+            V dk = sub(VB[HB->eb[k]], VB[HB->ea[k]]);
+            if (len2(cross(dk, dbj)) > 1e-10 * len2(dk)) continue;
+            double x = dot(N, scl(add(VB[HB->ea[k]], VB[HB->eb[k]]), 0.5));
+            if (jb < 0 || x > vb) { jb = k; vb = x; }
+        }
+        for (int k = 0; k < HB->ne; k++) {
+            V dk = sub(VB[HB->eb[k]], VB[HB->ea[k]]);
+            if (k == jb || len2(cross(dk, dbj)) > 1e-10 * len2(dk)) continue;
+            if (fabs(dot(N, scl(add(VB[HB->ea[k]], VB[HB->eb[k]]), 0.5)) - vb) < BAND) (*amb)++;
+        }
+        V a0 = VA[HA->ea[ia]], a1 = VA[HA->eb[ia]], b0 = VB[HB->ea[jb]], b1 = VB[HB->eb[jb]];
+        V pa = scl(add(a0, a1), 0.5), pb = scl(add(b0, b1), 0.5);
+        V ai = sub(a1, a0), bj = sub(b1, b0);
+        double la = 0.5 * sqrt(len2(ai)), lb = 0.5 * sqrt(len2(bj));
+        ai = scl(ai, 0.5 / la);
+        bj = scl(bj, 0.5 / lb);
+        V w = sub(pa, pb);
+        double bbd = dot(ai, bj), dd = dot(ai, w), ee = dot(bj, w);
+        double den = 1.0 - bbd * bbd;
+        double ta = (bbd * ee - dd) / den;
+        double tb = ee + ta * bbd;
+        ta = clampd(ta, -la, la);
+        tb = clampd(tb, -lb, lb);
+        V PA = add(pa, scl(ai, ta)), PB = add(pb, scl(bj, tb));
+        PC c;
+        c.n = N;
+        c.phi = dot(sub(PA, PB), N);
+        c.p = scl(add(PA, PB), 0.5);
+        c.f = 0xFF;
+        if (!keep(c.phi, margin, amb)) return 0;
+        out[0] = c;
+        return 1;
+    }
+    /* near ties inside the face group used */
+    if (!refB) { for (int f = 0; f < HA->nf; f++) if (f != fa && fabs(sA[f] - sA[fa]) < BAND) (*amb)++; }
+    else { for (int f = 0; f < HB->nf; f++) if (f != fb && fabs(sB[f] - sB[fb]) < BAND) (*amb)++; }
+    const Hull *HR = refB ? HB : HA, *HI = refB ? HA : HB;
+    const V *VR = refB ? VB : VA, *VI = refB ? VA : VB;
+    const V *NI = refB ? NA : NB;
+    const double *DI = refB ? DA : DB;
+    int rf = refB ? fb : fa;
+    V nout = refB ? NB[fb] : NA[fa];
+    double Dref = refB ? DB[fb] : DA[fa];
+    V N = refB ? nout : scl(nout, -1.0);
+    /* incident face: most opposed to nout (ties: lower face) */
+    int inf = 0;
+    for (int f = 1; f < HI->nf; f++) if (dot(NI[f], nout) < dot(NI[inf], nout)) inf = f;
+    for (int f = 0; f < HI->nf; f++)
+        if (f != inf && fabs(dot(NI[f], nout) - dot(NI[inf], nout)) < BAND_DIM) (*amb)++;
+    const int nR = HR->nl[rf], nI = HI->nl[inf];
+    V R[HULL_MAXL], X[HULL_MAXL], mR[HULL_MAXL], mI[HULL_MAXL];
+    for (int j = 0; j < nR; j++) R[j] = VR[HR->loop[rf][j]];
+    for (int k = 0; k < nI; k++) X[k] = VI[HI->loop[inf][k]];
+    for (int j = 0; j < nR; j++) {
+        V m = cross(sub(R[(j + 1) % nR], R[j]), nout);
+        mR[j] = scl(m, 1.0 / sqrt(len2(m)));
+    }
+    V ninc = NI[inf];
+    for (int k = 0; k < nI; k++) {
+        V m = cross(sub(X[(k + 1) % nI], X[k]), ninc);
+        mI[k] = scl(m, 1.0 / sqrt(len2(m)));
+    }
+    /* candidate points in id order */
+    V cp[96];
+    double cph[96];
+    int cid[96], nk = 0;
+#define SIDE(dv) ((dv) < -CLIP_ON ? -1 : ((dv) > CLIP_ON ? 1 : 0))
+    for (int k = 0; k < nI; k++) {
+        int in = 1;
+        for (int j = 0; j < nR; j++) {
+            double dv = dot(mR[j], sub(X[k], R[j]));
+            if (fabs(fabs(dv) - CLIP_ON) < BAND) (*amb)++;
+            if (dv > CLIP_ON) in = 0;
+        }
+        if (in) { cp[nk] = X[k]; cid[nk] = k; nk++; }
+    }
+    for (int k = 0; k < nI; k++)
+        for (int j = 0; j < nR; j++) {
+            V x0 = X[k], x1 = X[(k + 1) % nI];
+            double d0 = dot(mR[j], sub(x0, R[j])), d1 = dot(mR[j], sub(x1, R[j]));
+            if (SIDE(d0) * SIDE(d1) >= 0) continue;
+            V y = add(x0, scl(sub(x1, x0), d0 / (d0 - d1)));
+            int in = 1;
+            for (int i = 0; i < nR; i++) {
+                if (i == j) continue;
+                double dv = dot(mR[i], sub(y, R[i]));
+                if (fabs(fabs(dv) - CLIP_ON) < BAND) (*amb)++;
+                if (dv > CLIP_ON) in = 0;
+            }
+            if (in) { cp[nk] = y; cid[nk] = 8 + 8 * k + j; nk++; }
+        }
+    double Dinc = DI[inf];
+    for (int j = 0; j < nR; j++) {
+        double t = (Dinc - dot(ninc, R[j])) / dot(ninc, nout);
+        V z = add(R[j], scl(nout, t));
+        int in = 1;
+        for (int k = 0; k < nI; k++) {
+            double dv = dot(mI[k], sub(z, X[k]));
+            if (fabs(fabs(dv) - CLIP_ON) < BAND) (*amb)++;
+            if (!(dv < -CLIP_ON)) in = 0;
+        }
+        if (in) { cp[nk] = z; cid[nk] = 72 + j; nk++; }
+    }
+#undef SIDE
+    int idx[96], nkeep = 0;
+    for (int k = 0; k < nk; k++) {
+        cph[k] = dot(nout, cp[k]) - Dref;
+        if (keep(cph[k], margin, amb)) idx[nkeep++] = k;
+    }
+    int used[96] = {0};
+    if (nkeep <= 4) {
+        for (int k = 0; k < nkeep; k++) used[idx[k]] = 1;
+    } else {
+        reduce4(cp, idx, nkeep, idx[0], used, amb);   /* from the smallest id */
+    }
+    int m = 0;
+    for (int k = 0; k < nk; k++) {
+        if (!used[k]) continue;
+        PC c;
+        c.n = N;
+        c.phi = cph[k];
+        c.p = sub(cp[k], scl(nout, 0.5 * cph[k]));
+        c.f = refB | (cid[k] << 1);
+        out[m++] = c;
+    }
+    return m;
+}
+
 /* Ground plane z = 0 (second) against a body (first). */
 static int ground_contacts(const Geom *A, double margin, PC *out, int *amb) {
     int n = 0;
     V up = mk(0, 0, 1);
+    if (A->shape == ORA_HULL) return hull_ground(A, margin, out, amb);
     if (A->shape == ORA_SPHERE) {
         PC c;
         c.n = up;
@@ -777,6 +1521,16 @@ static int ground_contacts(const Geom *A, double margin, PC *out, int *amb) {
 /* Contacts of the pair (A, B) with the normal from B to A. */
 static int collide(const Geom *A, const Geom *B, double margin, PC *out, int *amb) {
     int ta = A->shape, tb = B->shape, n = 0, flip = 0;
+    if (ta == ORA_HULL || tb == ORA_HULL) {
+        if (ta == ORA_SPHERE) n = sphere_hull(A, B, margin, out, amb);
+        else if (tb == ORA_SPHERE) { n = sphere_hull(B, A, margin, out, amb); flip = 1; }
+        else if (ta == ORA_CAPSULE) n = capsule_hull(A, B, margin, out, amb);
+        else if (tb == ORA_CAPSULE) { n = capsule_hull(B, A, margin, out, amb); flip = 1; }
+        else n = hull_hull(A, B, margin, out, amb);
+        if (flip)
+            for (int k = 0; k < n; k++) out[k].n = scl(out[k].n, -1.0);
+        return n;
+    }
     if (ta == ORA_SPHERE && tb == ORA_SPHERE) {
         PC c = sphere_sphere(A->x, A->prm[0], B->x, B->prm[0], 0);
         if (keep(c.phi, margin, amb)) out[n++] = c;
@@ -793,12 +1547,17 @@ static int collide(const Geom *A, const Geom *B, double margin, PC *out, int *am
     return n;
 }
 
-static Geom geom_of(int shape, const double *prm, const double *pose) {
+static Geom geom_of(int shape, const double *prm, const double *pose, const Hull *HL) {
     Geom g;
     g.shape = shape;
     g.x = mk(pose[0], pose[1], pose[2]);
     g.R = quat_R(pose + 3);
     for (int i = 0; i < 3; i++) g.prm[i] = prm[i];
+    g.hull = NULL;
+    if (shape == ORA_HULL) {
+        g.hull = &HL[(int)prm[0]];
+        for (int i = 0; i < 3; i++) g.prm[i] = g.hull->h[i];
+    }
     return g;
 }
 
@@ -806,14 +1565,30 @@ int ora_collide(int shape_a, const double *param_a, const double *pose_a,
                 int shape_b, const double *param_b, const double *pose_b,
                 int ground, double margin, int *feature, double *normal,
                 double *point, double *phi, int *ambiguous) {
-    Geom A = geom_of(shape_a, param_a, pose_a);
+    if (shape_a == ORA_HULL || (!ground && shape_b == ORA_HULL)) return -1;
+    return ora_collide_hulls(NULL, shape_a, param_a, pose_a, shape_b, param_b, pose_b, ground, margin, feature,
+                             normal, point, phi, ambiguous);
+}
+
+int ora_collide_hulls(const ora_model *m, int shape_a, const double *param_a, const double *pose_a,
+                      int shape_b, const double *param_b, const double *pose_b,
+                      int ground, double margin, int *feature, double *normal,
+                      double *point, double *phi, int *ambiguous) {
+    Hull *HL = hulls_of(m);
+    if ((shape_a == ORA_HULL && (!HL || !(param_a[0] >= 0 && param_a[0] < m->n_hulls))) ||
+        (!ground && shape_b == ORA_HULL && (!HL || !(param_b[0] >= 0 && param_b[0] < m->n_hulls)))) {
+        free(HL);
+        return -1;
+    }
+    Geom A = geom_of(shape_a, param_a, pose_a, HL);
     PC c[4];
     int amb = 0, n;
     if (ground) n = ground_contacts(&A, margin, c, &amb);
     else {
-        Geom B = geom_of(shape_b, param_b, pose_b);
+        Geom B = geom_of(shape_b, param_b, pose_b, HL);
         n = collide(&A, &B, margin, c, &amb);
     }
+    free(HL);
     for (int k = 0; k < n; k++) {
         feature[k] = c[k].f;
         normal[3 * k] = c[k].n.x; normal[3 * k + 1] = c[k].n.y; normal[3 * k + 2] = c[k].n.z;
@@ -911,7 +1686,36 @@ static int brute_pairs(const Body *B, int n, int arm0, const int32_t *parent, ui
 }
 
 /* ---------------------------------------------------------------- scene setup */
-static void load_bodies(const ora_model *m, const double *pose, const double *vel, int s, Body *B) {
+/* Inertia tensor of a dynamic body in its frame: the principal moments of
+ * body_inertia, or a hull's solid (hull_mass_props). */
+static void body_tensor(const Body *b, double mass, double T[3][3]) {
+    if (b->shape == ORA_HULL) {
+        V c;
+        double v;
+        hull_mass_props(b->hull, mass, T, &c, &v);
+        return;
+    }
+    double I[3];
+    body_inertia(b->shape, b->prm, mass, I);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) T[i][j] = i == j ? I[i] : 0.0;
+}
+
+static void inv3(const double A[3][3], double Ai[3][3]) {
+    double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                 A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    Ai[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det;
+    Ai[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+    Ai[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+    Ai[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det;
+    Ai[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+    Ai[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+    Ai[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
+    Ai[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+    Ai[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+}
+
+static void load_bodies(const ora_model *m, const double *pose, const double *vel, int s, Body *B, const Hull *HL) {
     int b0 = m->body_offset[s], n = m->body_offset[s + 1] - b0;
     for (int k = 0; k < n; k++) {
         int g = b0 + k;
@@ -922,6 +1726,11 @@ static void load_bodies(const ora_model *m, const double *pose, const double *ve
         for (int i = 0; i < 4; i++) b->q[i] = pose[7 * g + 3 + i];
         b->R = quat_R(b->q);
         for (int i = 0; i < 3; i++) b->prm[i] = m->param[3 * g + i];
+        b->hull = NULL;
+        if (b->shape == ORA_HULL) {
+            b->hull = &HL[(int)m->param[3 * g]];
+            for (int i = 0; i < 3; i++) b->prm[i] = b->hull->h[i];
+        }
         b->v = mk(vel[6 * g], vel[6 * g + 1], vel[6 * g + 2]);
         b->w = mk(vel[6 * g + 3], vel[6 * g + 4], vel[6 * g + 5]);
         b->mu = m->friction[g];
@@ -930,13 +1739,16 @@ static void load_bodies(const ora_model *m, const double *pose, const double *ve
         b->im = 0;
         b->ncon = 0;
         if (b->motion == ORA_DYNAMIC) {
-            double I[3];
-            body_inertia(b->shape, b->prm, m->mass[g], I);
+            double Ii[3][3];
+            body_tensor(b, m->mass[g], b->Ib);
+            inv3(b->Ib, Ii);
             b->im = 1.0 / m->mass[g];
+            /* world inverse inertia R I^-1 R^T */
             for (int i = 0; i < 3; i++)
                 for (int j = 0; j < 3; j++) {
                     double sum = 0;
-                    for (int k2 = 0; k2 < 3; k2++) sum += b->R.m[i][k2] * b->R.m[j][k2] / I[k2];
+                    for (int k2 = 0; k2 < 3; k2++)
+                        for (int k3 = 0; k3 < 3; k3++) sum += b->R.m[i][k2] * Ii[k2][k3] * b->R.m[j][k3];
                     b->Iw.m[i][j] = sum;
                 }
         } else if (b->motion == ORA_STATIC) {
@@ -981,11 +1793,13 @@ static void load_parts(const ora_model *m, const double *joint_state, int s, Bod
         b->jo = mk(m->joint_anchor[3 * g], m->joint_anchor[3 * g + 1], m->joint_anchor[3 * g + 2]);
         double mass = m->mass[g];
         if (b->joint == 1) {
-            double Ip[3];
-            body_inertia(b->shape, b->prm, mass, Ip);
+            /* a^T I a about the centre (the axis in the body frame) plus the parallel-axis term */
             V al = mk(dot(col(&b->R, 0), b->ja), dot(col(&b->R, 1), b->ja), dot(col(&b->R, 2), b->ja));
             V d = cross(b->ja, sub(b->x, b->jo));
-            b->jM = al.x * al.x * Ip[0] + al.y * al.y * Ip[1] + al.z * al.z * Ip[2] + mass * len2(d);
+            double Ia = 0;
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) Ia += comp(al, i) * b->Ib[i][j] * comp(al, j);
+            b->jM = Ia + mass * len2(d);
         } else {
             b->jM = mass;
         }
@@ -1469,7 +2283,8 @@ static void warm_apply(Body *B, Arm *A, Con *C, const int *order, int nc, int se
  * angular speed into the largest surface speed. */
 static double bound_radius(const Body *b) {
     if (b->shape == ORA_SPHERE) return b->prm[0];
-    if (b->shape == ORA_BOX) return sqrt(b->prm[0] * b->prm[0] + b->prm[1] * b->prm[1] + b->prm[2] * b->prm[2]);
+    if (b->shape == ORA_BOX || b->shape == ORA_HULL)   /* a hull: its bounding box's half-diagonal */
+        return sqrt(b->prm[0] * b->prm[0] + b->prm[1] * b->prm[1] + b->prm[2] * b->prm[2]);
     return b->prm[0] + b->prm[1];
 }
 
@@ -1516,7 +2331,8 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         for (int k = 0; k < 7; k++) memcpy(pose + 7 * (b0 + nb - 7 + k), lp[k], 7 * sizeof(double));
     }
     Body *B = malloc(sizeof(Body) * (nb ? nb : 1));
-    load_bodies(m, pose, vel, s, B);
+    Hull *HL = hulls_of(m);
+    load_bodies(m, pose, vel, s, B, HL);
     for (int i = 0; i < nb; i++) B[i].joint = 0;
     if (m->joint) load_parts(m, joint_state, s, B);
     Arm AR;
@@ -1573,13 +2389,13 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
         int a = pk[q] >> 16, b = pk[q] & 0xFFFF;
         int ground = b == PAIR_GROUND;
         Geom GA, GB;
-        GA.shape = B[a].shape; GA.x = B[a].x; GA.R = B[a].R;
+        GA.shape = B[a].shape; GA.x = B[a].x; GA.R = B[a].R; GA.hull = B[a].hull;
         memcpy(GA.prm, B[a].prm, sizeof GA.prm);
         PC pc[4];
         int k, amb0 = amb;
         if (ground) k = ground_contacts(&GA, margin, pc, &amb);
         else {
-            GB.shape = B[b].shape; GB.x = B[b].x; GB.R = B[b].R;
+            GB.shape = B[b].shape; GB.x = B[b].x; GB.R = B[b].R; GB.hull = B[b].hull;
             memcpy(GB.prm, B[b].prm, sizeof GB.prm);
             k = collide(&GA, &GB, margin, pc, &amb);
         }
@@ -1955,6 +2771,7 @@ static void step_scene(const ora_model *m, double *pose, double *vel, double *th
     free(C);
     free(pk);
     free(B);
+    free(HL);
 }
 
 int ora_step(const ora_model *m, double *pose, double *vel, double *theta, int32_t *rest,
@@ -1969,6 +2786,14 @@ int ora_step(const ora_model *m, double *pose, double *vel, double *theta, int32
                      solver != ORA_PGS || warm == ORA_LEARNED))
         return -1;
     if (warm == ORA_LEARNED && !mlp) return -1;
+    /* hull bodies need a usable library entry */
+    Hull *HL = hulls_of(m);
+    for (int i = m->body_offset[s0]; i < m->body_offset[s1]; i++)
+        if (m->shape[i] == ORA_HULL && (!HL || !(m->param[3 * i] >= 0 && m->param[3 * i] < m->n_hulls))) {
+            free(HL);
+            return -1;
+        }
+    free(HL);
     for (int s = s0; s < s1; s++)
         step_scene(m, pose, vel, theta, rest, arm_state, joint_state, cache, actions, dt, iters, tol, warm, solver, mlp,
                    out, s);
@@ -1979,7 +2804,8 @@ int ora_pairs(const ora_model *m, const double *pose, int s, uint32_t *keys, int
     int b0 = m->body_offset[s], nb = m->body_offset[s + 1] - b0;
     Body *B = malloc(sizeof(Body) * (nb ? nb : 1));
     double *vel = calloc((size_t)6 * m->body_offset[m->n_scenes], sizeof(double));
-    load_bodies(m, pose, vel, s, B);
+    Hull *HL = hulls_of(m);
+    load_bodies(m, pose, vel, s, B, HL);
     for (int i = 0; i < nb; i++) body_aabb(&B[i], m->margin);
     int amb = 0;
     for (int i = 0; i < nb; i++) B[i].joint = m->joint && B[i].motion == ORA_DYNAMIC ? m->joint[m->body_offset[s] + i] : 0;
@@ -1987,6 +2813,7 @@ int ora_pairs(const ora_model *m, const double *pose, int s, uint32_t *keys, int
                         keys, cap, &amb, NULL);
     free(vel);
     free(B);
+    free(HL);
     return n;
 }
 
@@ -2010,9 +2837,10 @@ int ora_arm_query(const ora_model *m, const double *pose, const double *theta_q,
     if (!m || !m->arm || !pose || M < 0 || !(clearance >= 0) || s0 < 0 || s1 > m->n_scenes || s0 > s1) return -1;
     if (M > 0 && (!theta_q || !hit)) return -1;
     const double reach = clearance + 2.0 * BAND;
+    Hull *HL = hulls_of(m);
     for (int s = s0; s < s1; s++) {
         int b0 = m->body_offset[s], nb = m->body_offset[s + 1] - b0;
-        if (nb < 7) return -1;
+        if (nb < 7) { free(HL); return -1; }
         int nobs = nb - 7;
         for (int j = 0; j < M; j++) {
             const size_t q = (size_t)s * (size_t)M + (size_t)j;
@@ -2021,14 +2849,14 @@ int ora_arm_query(const ora_model *m, const double *pose, const double *theta_q,
             arm_fk(m, m->arm_base + 3 * s, theta_q + 7 * q, lp, o, ax);
             double best = INFINITY;
             for (int k = 0; k < 7; k++) {
-                Geom L = geom_of(ORA_CAPSULE, m->param + 3 * (size_t)(b0 + nobs + k), lp[k]);
+                Geom L = geom_of(ORA_CAPSULE, m->param + 3 * (size_t)(b0 + nobs + k), lp[k], NULL);
                 PC c[4];
                 int amb = 0;
                 int n = ground_contacts(&L, reach, c, &amb);
                 for (int i = 0; i < n; i++) best = fmin(best, c[i].phi);
                 for (int b = 0; b < nobs; b++) {
                     int g = b0 + b;
-                    Geom O = geom_of(m->shape[g], m->param + 3 * (size_t)g, pose + 7 * (size_t)g);
+                    Geom O = geom_of(m->shape[g], m->param + 3 * (size_t)g, pose + 7 * (size_t)g, HL);
                     n = collide(&L, &O, reach, c, &amb);
                     for (int i = 0; i < n; i++) best = fmin(best, c[i].phi);
                 }
@@ -2038,5 +2866,6 @@ int ora_arm_query(const ora_model *m, const double *pose, const double *theta_q,
             if (ambiguous) ambiguous[q] = fabs(best - clearance) < BAND;
         }
     }
+    free(HL);
     return 0;
 }

@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-enum { ORA_SPHERE = 0, ORA_BOX = 1, ORA_CAPSULE = 2 };
+enum { ORA_SPHERE = 0, ORA_BOX = 1, ORA_CAPSULE = 2, ORA_HULL = 3 };
 enum { ORA_DYNAMIC = 0, ORA_STATIC = 1, ORA_KINEMATIC = 2 };
 enum { ORA_COLD = 0, ORA_PREV = 1, ORA_LEARNED = 2 };
 enum { ORA_PGS = 0, ORA_JACOBI = 1 };
@@ -75,6 +75,16 @@ typedef struct ora_model {
     const double *joint_anchor;   /* [N*3] world point on the hinge line */
     const double *joint_limits;   /* [N*2] */
     const int32_t *joint_parent;  /* [N] */
+    /* Convex hulls (shape ORA_HULL; convex collision proxies, Sec. 3 and
+     * Sec. 4.3): param[3*i] of a hull body is the index of its hull in this
+     * library.  A hull's vertices are in the body frame (origin at the
+     * centre of mass of the solid, axes along its principal axes); its faces
+     * are vertex loops counter-clockwise seen from outside, at most 8
+     * vertices, -1 after the last; at most 32 vertices and 32 faces. */
+    int n_hulls;
+    const int32_t *hull_index;    /* [H*4]: first vertex, vertex count, first face, face count */
+    const double *hull_vert;      /* [V*3] */
+    const int32_t *hull_face;     /* [F*8] */
 } ora_model;
 
 typedef struct ora_cache {        /* previous step's contacts, sorted by key */
@@ -143,6 +153,18 @@ int ora_collide(int shape_a, const double *param_a, const double *pose_a,
                 int shape_b, const double *param_b, const double *pose_b,
                 int ground, double margin, int *feature, double *normal,
                 double *point, double *phi, int *ambiguous);
+
+/* ora_collide with a hull library (the model's hull fields; other fields
+ * unused): shapes may be ORA_HULL, param[0] the hull index. */
+int ora_collide_hulls(const ora_model *m, int shape_a, const double *param_a, const double *pose_a,
+                      int shape_b, const double *param_b, const double *pose_b,
+                      int ground, double margin, int *feature, double *normal,
+                      double *point, double *phi, int *ambiguous);
+
+/* Mass properties of hull h of the library for mass m: writes the inertia
+ * tensor about the body origin (row-major 3x3), the centre of mass and the
+ * volume.  Returns 0, or -1 for a bad index or an unusable hull. */
+int ora_hull_mass(const ora_model *m, int h, double mass, double *I, double *com, double *volume);
 
 /* Brute-force pair set of scene s at the given poses. Returns the count. */
 int ora_pairs(const ora_model *m, const double *pose, int s, uint32_t *keys, int cap);

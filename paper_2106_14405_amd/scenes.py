@@ -30,7 +30,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-SPHERE, BOX, CAPSULE = 0, 1, 2
+SPHERE, BOX, CAPSULE, HULL = 0, 1, 2, 3
 DYNAMIC, STATIC, KINEMATIC = 0, 1, 2
 
 ARM_LINKS = 7
@@ -123,11 +123,98 @@ def _yaw_quat(yaw: float) -> np.ndarray:
     return np.array([math.cos(0.5 * yaw), 0.0, 0.0, math.sin(0.5 * yaw)])
 
 
+# ---- convex hulls (collision proxies of objects: Sec. 3, Sec. 4.3) -------
+# Three families of convex polyhedra, each built in its principal frame by
+# symmetry (mirror-symmetric about z = 0 and either mirror-symmetric about
+# x = 0 and y = 0 or a regular polygon in the xy-plane): the centre of mass
+# is the origin and the coordinate axes are principal axes.  A hull is
+# (vertices [V, 3], face loops [F] of vertex indices, counter-clockwise
+# seen from outside).
+
+def _loop_ccw(V, idx, n):
+    """Vertex indices idx of a planar face, ordered counter-clockwise seen
+    from outside (outward direction n)."""
+    P = V[idx]
+    c = P.mean(axis=0)
+    t1 = P[0] - c
+    t1 = t1 - n * (t1 @ n)
+    t1 = t1 / np.linalg.norm(t1)
+    t2 = np.cross(n, t1)
+    ang = np.arctan2((P - c) @ t2, (P - c) @ t1)
+    return [int(idx[i]) for i in np.argsort(ang, kind="stable")]
+
+
+def hull_prism(n: int, r: float, h: float):
+    """Regular n-gonal prism: circumradius r, half-height h."""
+    th = 2.0 * math.pi * np.arange(n) / n
+    ring = np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+    V = np.concatenate([np.c_[ring, np.full(n, -h)], np.c_[ring, np.full(n, h)]])
+    F = [list(range(n, 2 * n)), list(range(n - 1, -1, -1))]
+    F += [[k, (k + 1) % n, n + (k + 1) % n, n + k] for k in range(n)]
+    return V, F
+
+
+def hull_bipyramid(n: int, r: float, h: float):
+    """Regular n-gonal bipyramid: equator circumradius r, apexes at +-h."""
+    th = 2.0 * math.pi * np.arange(n) / n
+    V = np.concatenate([np.c_[r * np.cos(th), r * np.sin(th), np.zeros(n)], [[0.0, 0.0, h], [0.0, 0.0, -h]]])
+    F = [[k, (k + 1) % n, n] for k in range(n)] + [[(k + 1) % n, k, n + 1] for k in range(n)]
+    return V, F
+
+
+def hull_chamfered_box(hx: float, hy: float, hz: float, t: float):
+    """Box of half-extents (hx, hy, hz) with its 8 corners cut off t along
+    each edge: 24 vertices, 6 octagons and 8 triangles."""
+    h = np.array([hx, hy, hz])
+    V, corner = [], {}
+    for sx in (-1, 1):
+        for sy in (-1, 1):
+            for sz in (-1, 1):
+                sg = np.array([sx, sy, sz], float)
+                ids = []
+                for ax in range(3):
+                    p = sg * h
+                    p[ax] -= sg[ax] * t
+                    ids.append(len(V))
+                    V.append(p)
+                corner[(sx, sy, sz)] = ids
+    V = np.array(V)
+    F = []
+    for ax in range(3):
+        for sg in (-1, 1):
+            nrm = np.zeros(3)
+            nrm[ax] = sg
+            idx = np.array([i for i in range(len(V)) if abs(V[i, ax] - sg * h[ax]) < 1e-12])
+            F.append(_loop_ccw(V, idx, nrm))
+    for key, ids in corner.items():
+        F.append(_loop_ccw(V, np.array(ids), np.array(key, float) / math.sqrt(3.0)))
+    return V, F
+
+
+def random_hull(st: "_Stream", size=(0.05, 0.15)):
+    """A hull of a random family and size: prisms and bipyramids of 3 to 8
+    sides (circumradius and half-height U[size]), chamfered boxes
+    (half-extents U[size], cut U[0.2, 0.45] of the smallest)."""
+    fam = int(st.take(1)[0] * 3.0)
+    if fam == 0:
+        return hull_prism(3 + int(st.take(1)[0] * 6.0), st.uniform(*size), st.uniform(*size))
+    if fam == 1:
+        return hull_bipyramid(3 + int(st.take(1)[0] * 6.0), st.uniform(*size), st.uniform(*size))
+    h = st.uniform(size[0], size[1], 3)
+    return hull_chamfered_box(h[0], h[1], h[2], st.uniform(0.2, 0.45) * float(np.min(h)))
+
+
+def hull_radius(V) -> float:
+    """Largest vertex distance from the origin."""
+    return float(np.max(np.linalg.norm(np.asarray(V, float), axis=1)))
+
+
 def bounding_radius(shape: int, param) -> float:
-    """Radius of a sphere about the centre that encloses the shape."""
+    """Radius of a sphere about the centre that encloses the shape (a hull:
+    its bounding box's half-diagonal, given as param)."""
     if shape == SPHERE:
         return float(param[0])
-    if shape == BOX:
+    if shape in (BOX, HULL):
         return float(math.sqrt(param[0] ** 2 + param[1] ** 2 + param[2] ** 2))
     return float(param[0] + param[1])
 
@@ -149,6 +236,13 @@ class Scene:
     # articulated container parts: body index -> (joint 1 revolute / 2
     # prismatic, unit axis, anchor point, (lo, hi) limits, parent body index)
     joints: dict = field(default_factory=dict)
+    # convex hulls of the scene's HULL bodies ((vertices, face loops)); a
+    # HULL body's param[0] is its index here
+    hulls: list = field(default_factory=list)
+
+    def add_hull(self, verts, faces, motion, mass, mu, e, pos, quat):
+        self.hulls.append((np.asarray(verts, np.float64), [list(f) for f in faces]))
+        self.add(HULL, motion, [float(len(self.hulls) - 1), 0.0, 0.0], mass, mu, e, pos, quat)
 
     def add(self, shape, motion, param, mass, mu, e, pos, quat):
         self.shape.append(shape)
@@ -204,14 +298,18 @@ def _place(st, R, lo, hi, placed, statics=(), keepout=None, tries=4000):
 
 
 def drop_scene(seed: int, n_spheres: int = 32, n_boxes: int = 32, size=(0.05, 0.15),
-               mass=(0.1, 2.0), friction=0.5, edge: float | None = None) -> Scene:
-    """Spheres and boxes dropped from uniform positions in a cube onto the
-    ground: x, y in [-L/2, L/2], z in [0.2, 0.2 + L], L = 2 m * (n/64)^(1/3)
-    unless given; uniform orientation; zero velocity; restitution 0."""
+               mass=(0.1, 2.0), friction=0.5, edge: float | None = None, n_capsules: int = 0,
+               n_hulls: int = 0) -> Scene:
+    """Spheres and boxes (and capsules: radius U[0.03, 0.1], half-length
+    U[size]; and convex hulls: random_hull) dropped from uniform positions
+    in a cube onto the ground: x, y in [-L/2, L/2], z in [0.2, 0.2 + L],
+    L = 2 m * (n/64)^(1/3) unless given; uniform orientation; zero
+    velocity; restitution 0.  Hull shapes come from a stream of their own."""
     st = _Stream(stream_key(seed, 1))
-    n = n_spheres + n_boxes
+    sth = _Stream(stream_key(seed, 10))
+    n = n_spheres + n_boxes + n_capsules + n_hulls
     L = edge if edge is not None else 2.0 * (n / 64.0) ** (1.0 / 3.0)
-    kinds = np.array([SPHERE] * n_spheres + [BOX] * n_boxes)
+    kinds = np.array([SPHERE] * n_spheres + [BOX] * n_boxes + [CAPSULE] * n_capsules + [HULL] * n_hulls)
     order = np.argsort(st.take(n), kind="stable")
     kinds = kinds[order]
     sc = Scene()
@@ -219,16 +317,24 @@ def drop_scene(seed: int, n_spheres: int = 32, n_boxes: int = 32, size=(0.05, 0.
     lo = np.array([-0.5 * L, -0.5 * L, 0.2])
     hi = np.array([0.5 * L, 0.5 * L, 0.2 + L])
     for k in kinds:
+        hv = None
         if k == SPHERE:
             param = [st.uniform(*size), 0.0, 0.0]
-        else:
+        elif k == BOX:
             param = list(st.uniform(size[0], size[1], 3))
+        elif k == CAPSULE:
+            param = [st.uniform(0.03, 0.1), st.uniform(*size), 0.0]
+        else:
+            hv, hf = random_hull(sth, size)
         m = st.uniform(*mass)
-        R = bounding_radius(int(k), param)
+        R = hull_radius(hv) if hv is not None else bounding_radius(int(k), param)
         p = _place(st, R, lo, hi, placed)
         placed.append((p, R))
         q = _random_quat(st)
-        sc.add(int(k), DYNAMIC, param, m, friction, 0.0, p, q)
+        if hv is not None:
+            sc.add_hull(hv, hf, DYNAMIC, m, friction, 0.0, p, q)
+        else:
+            sc.add(int(k), DYNAMIC, param, m, friction, 0.0, p, q)
     return sc
 
 
@@ -433,6 +539,11 @@ class Batch:
     joint_anchor: np.ndarray | None = None   # float32 [N,3]
     joint_limits: np.ndarray | None = None   # float32 [N,2]
     joint_parent: np.ndarray | None = None   # int32 [N]
+    # convex hulls (None: none): per hull (first vertex, vertex count, first
+    # face, face count); vertices in the body frame; face loops padded with -1
+    hull_index: np.ndarray | None = None     # int32 [H,4]
+    hull_vert: np.ndarray | None = None      # float32 [V,3]
+    hull_face: np.ndarray | None = None      # int32 [F,8]
 
     @property
     def n_scenes(self):
@@ -477,11 +588,33 @@ def pack(scenes: list[Scene]) -> Batch:
                 anchor[g] = an
                 limits[g] = lim
                 parent[g] = par
+    hull_index = hull_vert = hull_face = None
+    param_all = cat("param", np.float64)
+    if any(sc.hulls for sc in scenes):
+        hi_, hv_, hf_ = [], [], []
+        nv = nf = 0
+        for si, sc in enumerate(scenes):
+            base = len(hi_)
+            for (V, F) in sc.hulls:
+                hi_.append((nv, len(V), nf, len(F)))
+                hv_.append(np.asarray(V, np.float64))
+                for f in F:
+                    row = np.full(8, -1, np.int32)
+                    row[:len(f)] = f
+                    hf_.append(row)
+                nv += len(V)
+                nf += len(F)
+            for bi in range(sc.n):
+                if sc.shape[bi] == HULL:
+                    param_all[int(off[si]) + bi, 0] += base
+        hull_index = np.asarray(hi_, np.int32).reshape(-1, 4)
+        hull_vert = np.concatenate(hv_).astype(np.float32)
+        hull_face = np.asarray(hf_, np.int32).reshape(-1, 8)
     return Batch(
         body_offset=off,
         shape=cat("shape", np.uint8).reshape(-1),
         motion=cat("motion", np.uint8).reshape(-1),
-        param=cat("param", np.float64).astype(np.float32),
+        param=param_all.astype(np.float32),
         mass=cat("mass", np.float64).reshape(-1).astype(np.float32),
         friction=cat("friction", np.float64).reshape(-1).astype(np.float32),
         restitution=cat("restitution", np.float64).reshape(-1).astype(np.float32),
@@ -492,6 +625,7 @@ def pack(scenes: list[Scene]) -> Batch:
         arm_theta=(np.stack([s.arm_theta0 for s in scenes]).astype(np.float32) if arm
                    else np.zeros((S, ARM_LINKS), np.float32)),
         joint=joint, joint_axis=axis, joint_anchor=anchor, joint_limits=limits, joint_parent=parent,
+        hull_index=hull_index, hull_vert=hull_vert, hull_face=hull_face,
     )
 
 
