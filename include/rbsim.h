@@ -40,10 +40,10 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 5
+#define SIM_ABI_VERSION 6
 
 enum { SIM_OK = 0, SIM_EINVAL = -1, SIM_EDEVICE = -2, SIM_EWORKSPACE = -3, SIM_EABI = -4, SIM_ECAPACITY = -5 };
-enum { SIM_SPHERE = 0, SIM_BOX = 1, SIM_CAPSULE = 2 };
+enum { SIM_SPHERE = 0, SIM_BOX = 1, SIM_CAPSULE = 2, SIM_HULL = 3 };
 enum { SIM_DYNAMIC = 0, SIM_STATIC = 1, SIM_KINEMATIC = 2 };
 enum { SIM_COLD = 0, SIM_PREV = 1, SIM_LEARNED = 2 };
 enum { SIM_PGS = 0, SIM_JACOBI = 1 };
@@ -59,7 +59,8 @@ typedef struct sim_batch_desc {
     const int32_t *h_body_offset;/* [S+1], non-decreasing, body_offset[0] = 0 */
     const uint8_t *h_shape;      /* [N] SIM_SPHERE / SIM_BOX / SIM_CAPSULE */
     const uint8_t *h_motion;     /* [N] SIM_DYNAMIC / SIM_STATIC / SIM_KINEMATIC */
-    const float *h_param;        /* [N*3] sphere (r,-,-); box half-extents; capsule (r, half-length, -), m */
+    const float *h_param;        /* [N*3] sphere (r,-,-); box half-extents; capsule (r, half-length, -), m;
+                                    hull (index in the hull library, -, -) */
     const float *h_mass;         /* [N] kg, > 0 for dynamic bodies */
     const float *h_friction;     /* [N] */
     const float *h_restitution;  /* [N] */
@@ -121,6 +122,21 @@ typedef struct sim_batch_desc {
     const float *h_joint_anchor;   /* [N*3] a point of the hinge line (world, m; read for revolute) */
     const float *h_joint_limits;   /* [N*2] lower <= upper limit of q */
     const int32_t *h_joint_parent; /* [N] local index (within the scene) of the parent body, or -1 */
+    /* Convex hulls (shape SIM_HULL; convex collision proxies, Sec. 3 and
+     * Sec. 4.3): a library of convex polyhedra that hull bodies index.  A
+     * hull's vertices are in its body frame, which must have its origin at
+     * the centre of mass of the solid (uniform density) and its axes along
+     * the principal axes of inertia (checked: SIM_EINVAL otherwise); faces
+     * are vertex loops counter-clockwise seen from outside, 3 to 8 vertices,
+     * -1 after the last; every vertex on or inside every face plane; at
+     * most 32 vertices and 32 faces a hull.  Contacts with hulls: against
+     * the ground (vertices), spheres (closest point), capsules and boxes
+     * and other hulls (separating axes and face clipping).  Batches with
+     * hulls step without the learned warm start and have no arm queries. */
+    int n_hulls;                   /* H (0: none) */
+    const int32_t *h_hull_index;   /* [H*4]: first vertex, vertex count, first face, face count */
+    const float *h_hull_vert;      /* [V*3] m */
+    const int32_t *h_hull_face;    /* [F*8] */
 } sim_batch_desc;
 
 typedef struct sim_handle sim_handle;
@@ -216,7 +232,7 @@ int sim_step(sim_handle *h, const float *d_actions, float dt, int iters);
  * d_min_phi (device float32 [S][M], or NULL) gets the least separation of
  * those contacts, +INF when none is within the clearance.  The scenes'
  * state is read, not changed; no solver runs.  SIM_EINVAL for a batch
- * without the arm, M < 0, a bad clearance or NULL/misaligned arrays
+ * without the arm or with convex hulls, M < 0, a bad clearance or NULL/misaligned arrays
  * (nothing launched); M = 0 does nothing.  Asynchronous on the handle's
  * stream, after any step enqueued before it. */
 int sim_query_arm(sim_handle *h, const float *d_theta, int M, float clearance, uint8_t *d_hit, float *d_min_phi);

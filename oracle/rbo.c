@@ -162,6 +162,7 @@ typedef struct HullS {
     double fd[HULL_MAXF];
     int nl[HULL_MAXF], loop[HULL_MAXF][HULL_MAXL];
     int ea[HULL_MAXE], eb[HULL_MAXE];
+    int ef[HULL_MAXE][2];   /* the two faces that share the edge (first, second appearance) */
     double h[3], rad;
 } Hull;
 typedef struct { int shape; V x; M3 R; double prm[3]; const Hull *hull; } Geom;
@@ -768,18 +769,26 @@ static int hull_finish(Hull *H) {
         if (!(L > 0)) return -1;
         H->fn[f] = scl(nn, 1.0 / L);
         H->fd[f] = dot(H->fn[f], scl(c, 1.0 / n));
+    }
+    for (int f = 0; f < H->nf; f++) {
+        const int n = H->nl[f];
         for (int k = 0; k < n; k++) {
             int a = H->loop[f][k], b = H->loop[f][(k + 1) % n];
-            int lo = a < b ? a : b, hi = a < b ? b : a, seen = 0;
-            for (int e = 0; e < H->ne; e++) if (H->ea[e] == lo && H->eb[e] == hi) seen = 1;
-            if (!seen) {
+            int lo = a < b ? a : b, hi = a < b ? b : a, seen = -1;
+            for (int e = 0; e < H->ne; e++) if (H->ea[e] == lo && H->eb[e] == hi) seen = e;
+            if (seen < 0) {
                 if (H->ne >= HULL_MAXE) return -1;
                 H->ea[H->ne] = lo;
                 H->eb[H->ne] = hi;
+                H->ef[H->ne][0] = f;
+                H->ef[H->ne][1] = -1;
                 H->ne++;
+            } else {
+                H->ef[seen][1] = f;
             }
         }
     }
+    for (int e = 0; e < H->ne; e++) if (H->ef[e][1] < 0) return -1;   /* not a closed surface */
     return 0;
 }
 
@@ -1213,7 +1222,9 @@ static int capsule_hull(const Geom *C, const Geom *G, double margin, PC *out, in
  * the two vertex sets' projections; the first hull's face wins near ties,
  * edges only when clearly better (the thresholds of box_box, the largest
  * half-extent of the two local bounding boxes for the boxes').
- * Edge contact: closest points of the supporting edges (f 0xFF).
+ * Edge axes from the pairs of edges that build faces of the Minkowski
+ * difference (Gregorius 2013); edge contact: closest points of the two
+ * edges (f 0xFF).
  * Face contact: the incident face is the other hull's face most opposed to
  * the reference face; the contact points are the vertices of the two
  * faces' overlap seen along the reference normal (the polygon that
@@ -1251,25 +1262,31 @@ static int hull_hull(const Geom *A, const Geom *B, double margin, PC *out, int *
         sB[f] = s;
         if (s > sB[fb]) fb = f;
     }
-    double se = -INFINITY, sge = 1.0;
+    /* edge axes: only pairs whose edges build a face of the Minkowski
+     * difference (their arcs on the Gauss map cross: Gregorius 2013); the
+     * axis u = e_A x e_B points away from A's centre and the separation is
+     * u . (b - a), a and b the edges' first vertices */
+    double se = -INFINITY;
     int ei = -1, ej = -1;
     V ue = mk(0, 0, 1);
     for (int i = 0; i < HA->ne; i++) {
+        V a = NA[HA->ef[i][0]], b = NA[HA->ef[i][1]], bxa = cross(b, a);
         V da = sub(VA[HA->eb[i]], VA[HA->ea[i]]);
-        da = scl(da, 1.0 / sqrt(len2(da)));
         for (int j = 0; j < HB->ne; j++) {
+            V c = scl(NB[HB->ef[j][0]], -1.0), d = scl(NB[HB->ef[j][1]], -1.0), dxc = cross(d, c);
+            double cba = dot(c, bxa), dba = dot(d, bxa), adc = dot(a, dxc), bdc = dot(b, dxc);
+            /* (arcs that only touch give an axis equal to a face normal, whose
+             * separation the face axes already hold: no tie to flag) */
+            if (!(cba * dba < 0 && adc * bdc < 0 && cba * bdc > 0)) continue;
             V db = sub(VB[HB->eb[j]], VB[HB->ea[j]]);
-            db = scl(db, 1.0 / sqrt(len2(db)));
-            V c = cross(da, db);
-            double L2 = len2(c);
-            if (fabs(L2 - 1e-12) < 1e-13) (*amb)++;
-            if (L2 < 1e-12) continue;
-            V u = scl(c, 1.0 / sqrt(L2));
-            double a0 = INFINITY, a1 = -INFINITY, b0 = INFINITY, b1 = -INFINITY;
-            for (int k = 0; k < HA->nv; k++) { double x = dot(u, VA[k]); a0 = fmin(a0, x); a1 = fmax(a1, x); }
-            for (int k = 0; k < HB->nv; k++) { double x = dot(u, VB[k]); b0 = fmin(b0, x); b1 = fmax(b1, x); }
-            double s1 = a0 - b1, s2 = b0 - a1, s = fmax(s1, s2);
-            if (s > se) { se = s; ei = i; ej = j; ue = u; sge = s1 >= s2 ? 1.0 : -1.0; }
+            V u = cross(da, db);
+            double L2 = len2(u), ref = len2(da) * len2(db);
+            if (fabs(L2 - 1e-12 * ref) < 1e-13 * ref) (*amb)++;
+            if (L2 < 1e-12 * ref) continue;
+            u = scl(u, 1.0 / sqrt(L2));
+            if (dot(u, sub(VA[HA->ea[i]], A->x)) < 0) u = scl(u, -1.0);
+            double sv = dot(u, sub(VB[HB->ea[j]], VA[HA->ea[i]]));
+            if (sv > se) { se = sv; ei = i; ej = j; ue = u; }
         }
     }
     double smax = fmax(fmax(sA[fa], sB[fb]), se);
@@ -1289,53 +1306,26 @@ static int hull_hull(const Geom *A, const Geom *B, double margin, PC *out, int *
         edge = se > thr2;
     }
     if (edge) {
-        /* near ties with another axis direction */
+        /* near ties with another Minkowski pair of another axis direction */
         for (int i = 0; i < HA->ne; i++) {
+            V a = NA[HA->ef[i][0]], b = NA[HA->ef[i][1]], bxa = cross(b, a);
             V da = sub(VA[HA->eb[i]], VA[HA->ea[i]]);
-            da = scl(da, 1.0 / sqrt(len2(da)));
             for (int j = 0; j < HB->ne; j++) {
+                V c = scl(NB[HB->ef[j][0]], -1.0), d = scl(NB[HB->ef[j][1]], -1.0), dxc = cross(d, c);
+                double cba = dot(c, bxa), dba = dot(d, bxa), adc = dot(a, dxc), bdc = dot(b, dxc);
+                if (!(cba * dba < 0 && adc * bdc < 0 && cba * bdc > 0)) continue;
                 V db = sub(VB[HB->eb[j]], VB[HB->ea[j]]);
-                db = scl(db, 1.0 / sqrt(len2(db)));
-                V c = cross(da, db);
-                double L2 = len2(c);
-                if (L2 < 1e-12) continue;
-                V u = scl(c, 1.0 / sqrt(L2));
+                V u = cross(da, db);
+                double L2 = len2(u), ref = len2(da) * len2(db);
+                if (L2 < 1e-12 * ref) continue;
+                u = scl(u, 1.0 / sqrt(L2));
                 if (len2(cross(u, ue)) < 1e-10) continue;
-                double a0 = INFINITY, a1 = -INFINITY, b0 = INFINITY, b1 = -INFINITY;
-                for (int k = 0; k < HA->nv; k++) { double x = dot(u, VA[k]); a0 = fmin(a0, x); a1 = fmax(a1, x); }
-                for (int k = 0; k < HB->nv; k++) { double x = dot(u, VB[k]); b0 = fmin(b0, x); b1 = fmax(b1, x); }
-                if (fabs(fmax(a0 - b1, b0 - a1) - se) < BAND) { (*amb)++; i = HA->ne; break; }
+                if (dot(u, sub(VA[HA->ea[i]], A->x)) < 0) u = scl(u, -1.0);
+                if (fabs(dot(u, sub(VB[HB->ea[j]], VA[HA->ea[i]])) - se) < BAND) (*amb)++;
             }
         }
-        V N = scl(ue, sge);   /* from B to A */
-        /* supporting edges: A's edge along edge ei lowest along N, B's along ej highest */
-        V dai = sub(VA[HA->eb[ei]], VA[HA->ea[ei]]), dbj = sub(VB[HB->eb[ej]], VB[HB->ea[ej]]);
-        dai = scl(dai, 1.0 / sqrt(len2(dai)));
-        dbj = scl(dbj, 1.0 / sqrt(len2(dbj)));
-        int ia = -1, jb = -1;
-        double va = 0, vb = 0;
-        for (int k = 0; k < HA->ne; k++) {
-            V dk = sub(VA[HA->eb[k]], VA[HA->ea[k]]);
-            if (len2(cross(dk, dai)) > 1e-10 * len2(dk)) continue;
-            double x = dot(N, scl(add(VA[HA->ea[k]], VA[HA->eb[k]]), 0.5));
-            if (ia < 0 || x < va) { ia = k; va = x; }
-        }
-        for (int k = 0; k < HA->ne; k++) {
-            V dk = sub(VA[HA->eb[k]], VA[HA->ea[k]]);
-            if (k == ia || len2(cross(dk, dai)) > 1e-10 * len2(dk)) continue;
-            if (fabs(dot(N, scl(add(VA[HA->ea[k]], VA[HA->eb[k]]), 0.5)) - va) < BAND) (*amb)++;
-        }
-        for (int k = 0; k < HB->ne; k++) {
-            V dk = sub(VB[HB->eb[k]], VB[HB->ea[k]]);
-            if (len2(cross(dk, dbj)) > 1e-10 * len2(dk)) continue;
-            double x = dot(N, scl(add(VB[HB->ea[k]], VB[HB->eb[k]]), 0.5));
-            if (jb < 0 || x > vb) { jb = k; vb = x; }
-        }
-        for (int k = 0; k < HB->ne; k++) {
-            V dk = sub(VB[HB->eb[k]], VB[HB->ea[k]]);
-            if (k == jb || len2(cross(dk, dbj)) > 1e-10 * len2(dk)) continue;
-            if (fabs(dot(N, scl(add(VB[HB->ea[k]], VB[HB->eb[k]]), 0.5)) - vb) < BAND) (*amb)++;
-        }
+        V N = scl(ue, -1.0);   /* from B to A */
+        int ia = ei, jb = ej;
         V a0 = VA[HA->ea[ia]], a1 = VA[HA->eb[ia]], b0 = VB[HB->ea[jb]], b1 = VB[HB->eb[jb]];
         V pa = scl(add(a0, a1), 0.5), pb = scl(add(b0, b1), 0.5);
         V ai = sub(a1, a0), bj = sub(b1, b0);

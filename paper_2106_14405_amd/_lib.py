@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbsim.so")
 
-SIM_ABI_VERSION = 5
+SIM_ABI_VERSION = 6
 SIM_OK, SIM_EINVAL, SIM_EDEVICE, SIM_EWORKSPACE, SIM_EABI, SIM_ECAPACITY = 0, -1, -2, -3, -4, -5
 SPHERE, BOX, CAPSULE = 0, 1, 2
 DYNAMIC, STATIC, KINEMATIC = 0, 1, 2
@@ -38,6 +38,8 @@ class BatchDesc(C.Structure):
         ("stream", C.c_void_p), ("hbm_min_bodies", C.c_int),
         ("h_joint", _P(C.c_uint8)), ("h_joint_axis", _P(_f)), ("h_joint_anchor", _P(_f)),
         ("h_joint_limits", _P(_f)), ("h_joint_parent", _P(C.c_int32)),
+        ("n_hulls", C.c_int), ("h_hull_index", _P(C.c_int32)), ("h_hull_vert", _P(_f)),
+        ("h_hull_face", _P(C.c_int32)),
     ]
 
 

@@ -61,6 +61,7 @@ struct Layout {
       off_restitution, off_pose, off_vel, off_rest, off_theta, off_arm_state, off_arm_base, off_scene_list;
   size_t off_arm_rows;
   size_t off_joint, off_joint_axis, off_joint_anchor, off_joint_limits, off_joint_parent, off_joint_state;
+  size_t off_hull_info, off_hull_vert, off_hull_plane, off_hull_loop, off_hull_edge, off_hull_ext;
   size_t off_ckey[2], off_clam[2], off_ccount[2], off_ccol[2];
   size_t off_x_pair, off_x_npairs, off_x_normal, off_x_point, off_x_phi, off_x_lambda, off_x_colour, off_x_feat;
   size_t off_raw, off_crec;
@@ -75,7 +76,12 @@ struct Layout {
 size_t align256(size_t x) { return (x + 255u) & ~size_t(255u); }
 
 // art: the arm mode plus rbs::kArtParts when the batch has container parts
-Layout make_layout(long S, long N, long PM, long CM, long n_hbm, long hbm_words, int art) {
+// Sizes of the hull library's device tables (hulls, vertices, faces, edges).
+struct HullSizes {
+  long H = 0, V = 0, F = 0, E = 0;
+};
+
+Layout make_layout(long S, long N, long PM, long CM, long n_hbm, long hbm_words, int art, HullSizes hs = HullSizes()) {
   const int arm = art & 3;
   const bool parts = (art & rbs::kArtParts) != 0;
   Layout L;
@@ -102,6 +108,14 @@ Layout make_layout(long S, long N, long PM, long CM, long n_hbm, long hbm_words,
   L.off_joint_limits = take(parts ? 4 * 2 * N : 0);
   L.off_joint_parent = take(parts ? 4 * N : 0);
   L.off_joint_state = take(parts ? 4 * 2 * N : 0);
+  // convex hulls: per hull 8 ints and a float4; float4 vertices and planes;
+  // 8-byte loops, 4-byte edges
+  L.off_hull_info = take(4 * 8 * hs.H);
+  L.off_hull_vert = take(16 * hs.V);
+  L.off_hull_plane = take(16 * hs.F);
+  L.off_hull_loop = take(8 * hs.F);
+  L.off_hull_edge = take(4 * hs.E);
+  L.off_hull_ext = take(16 * hs.H);
   L.off_scene_list = take(4 * S);
   for (int k = 0; k < 2; k++) {
     L.off_ckey[k] = take(4 * S * CM);
@@ -149,6 +163,7 @@ struct sim_handle {
   int last_export;  // export was on during the last step
   int arm;                 // 0 none, 1 kinematic, 2 articulated with joint motors
   bool parts;              // articulated container parts
+  long n_hulls = 0;        // convex hulls in the library
   int art;                 // arm | (rbs::kArtParts if parts): the layouts' articulation code
   float motor_kp, motor_max;
   float link_len[7];
@@ -235,6 +250,14 @@ rbs::StepParams params(sim_handle* h) {
     P.joint_state = at<float>(h, L.off_joint_state);
   }
   P.art = h->art;
+  if (h->n_hulls > 0) {
+    P.hull_info = at<int32_t>(h, L.off_hull_info);
+    P.hull_vert = at<float4>(h, L.off_hull_vert);
+    P.hull_plane = at<float4>(h, L.off_hull_plane);
+    P.hull_loop = at<uint8_t>(h, L.off_hull_loop);
+    P.hull_edge = at<uint8_t>(h, L.off_hull_edge);
+    P.hull_ext = at<float4>(h, L.off_hull_ext);
+  }
   P.motor_kp = h->motor_kp;
   P.motor_max = h->motor_max;
   P.arm_base = at<float>(h, L.off_arm_base);
@@ -287,6 +310,114 @@ rbs::StepParams params(sim_handle* h) {
   return P;
 }
 
+// A hull of the library, prepared in double precision: face planes
+// (Newell's normal of the loop through its mean vertex), edges (each
+// undirected vertex pair once, in order of first appearance over the
+// loops, with the faces of its first and second appearance), the local
+// bounding box, and the solid's volume, centre of mass and inertia for a
+// unit mass (tetrahedra from the origin over a fan of every loop: a
+// tetrahedron (0, a, b, c) of volume v has second moment v/20 (a a^T +
+// b b^T + c c^T + s s^T), s = a + b + c, and centroid s / 4).
+struct HullPrep {
+  int nv = 0, nf = 0;
+  std::vector<double> v;          // [nv][3]
+  std::vector<int> loop;          // [nf][8], -1 after the last
+  std::vector<double> plane;      // [nf][4]
+  std::vector<int> edge;          // [ne][4]: a, b, face 0, face 1
+  double ext[3] = {0, 0, 0};
+  double vol = 0, com[3] = {0, 0, 0}, I[3][3] = {{0}};
+};
+
+// Returns an empty string, or what makes the hull unusable.
+std::string prepare_hull(const sim_batch_desc* d, int h, HullPrep& P) {
+  const int32_t* ix = d->h_hull_index + 4 * h;
+  const int v0 = ix[0], nv = ix[1], f0 = ix[2], nf = ix[3];
+  if (v0 < 0 || f0 < 0 || nv < 4 || nv > 32 || nf < 4 || nf > 32) return "hull sizes out of range";
+  P.nv = nv;
+  P.nf = nf;
+  P.v.assign(d->h_hull_vert + 3L * v0, d->h_hull_vert + 3L * (v0 + nv));
+  for (double x : P.v)
+    if (!std::isfinite(x)) return "hull vertices must be finite";
+  P.loop.assign(d->h_hull_face + 8L * f0, d->h_hull_face + 8L * (f0 + nf));
+  P.plane.assign(4L * nf, 0.0);
+  auto V = [&](int k, int c) { return P.v[3 * k + c]; };
+  for (int f = 0; f < nf; f++) {
+    int n = 0;
+    while (n < 8 && P.loop[8 * f + n] >= 0) n++;
+    for (int k = n; k < 8; k++)
+      if (P.loop[8 * f + k] >= 0) return "a face loop continues after -1";
+    if (n < 3) return "a face needs at least 3 vertices";
+    double nn[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+    for (int k = 0; k < n; k++) {
+      const int a = P.loop[8 * f + k], b = P.loop[8 * f + (k + 1) % n];
+      if (a >= nv || b >= nv) return "a face loop index is out of range";
+      nn[0] += (V(a, 1) - V(b, 1)) * (V(a, 2) + V(b, 2));
+      nn[1] += (V(a, 2) - V(b, 2)) * (V(a, 0) + V(b, 0));
+      nn[2] += (V(a, 0) - V(b, 0)) * (V(a, 1) + V(b, 1));
+      for (int q = 0; q < 3; q++) c[q] += V(a, q);
+    }
+    const double L = std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    if (!(L > 0)) return "a degenerate face";
+    for (int q = 0; q < 3; q++) P.plane[4 * f + q] = nn[q] / L;
+    P.plane[4 * f + 3] = (P.plane[4 * f] * c[0] + P.plane[4 * f + 1] * c[1] + P.plane[4 * f + 2] * c[2]) / n;
+    for (int k = 0; k < n; k++) {
+      const int a = P.loop[8 * f + k], b = P.loop[8 * f + (k + 1) % n];
+      const int lo = std::min(a, b), hi = std::max(a, b);
+      int seen = -1;
+      for (size_t e = 0; e < P.edge.size() / 4; e++)
+        if (P.edge[4 * e] == lo && P.edge[4 * e + 1] == hi) seen = (int)e;
+      if (seen < 0) P.edge.insert(P.edge.end(), {lo, hi, f, -1});
+      else if (P.edge[4 * seen + 3] < 0) P.edge[4 * seen + 3] = f;
+      else return "an edge is shared by more than two faces";
+    }
+  }
+  if (P.edge.size() / 4 > 64) return "more than 64 edges";
+  for (size_t e = 0; e < P.edge.size() / 4; e++)
+    if (P.edge[4 * e + 3] < 0) return "the faces do not close the surface";
+  // convex: every vertex on or inside every face plane
+  double ext = 0;
+  for (int k = 0; k < nv; k++)
+    for (int q = 0; q < 3; q++) {
+      P.ext[q] = std::max(P.ext[q], std::fabs(V(k, q)));
+      ext = std::max(ext, std::fabs(V(k, q)));
+    }
+  for (int f = 0; f < nf; f++)
+    for (int k = 0; k < nv; k++) {
+      const double s = P.plane[4 * f] * V(k, 0) + P.plane[4 * f + 1] * V(k, 1) + P.plane[4 * f + 2] * V(k, 2) -
+                       P.plane[4 * f + 3];
+      if (s > 1e-5 * ext) return "the hull is not convex (or a loop is clockwise)";
+    }
+  double C[3][3] = {{0}}, cm[3] = {0, 0, 0};
+  for (int f = 0; f < nf; f++) {
+    int n = 0;
+    while (n < 8 && P.loop[8 * f + n] >= 0) n++;
+    for (int k = 1; k + 1 < n; k++) {
+      const int ia = P.loop[8 * f], ib = P.loop[8 * f + k], ic = P.loop[8 * f + k + 1];
+      const double a[3] = {V(ia, 0), V(ia, 1), V(ia, 2)}, b[3] = {V(ib, 0), V(ib, 1), V(ib, 2)},
+                   c[3] = {V(ic, 0), V(ic, 1), V(ic, 2)};
+      const double vt = (a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+                         a[2] * (b[0] * c[1] - b[1] * c[0])) / 6.0;
+      const double sm[3] = {a[0] + b[0] + c[0], a[1] + b[1] + c[1], a[2] + b[2] + c[2]};
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+          C[i][j] += vt / 20.0 * (a[i] * a[j] + b[i] * b[j] + c[i] * c[j] + sm[i] * sm[j]);
+      for (int i = 0; i < 3; i++) cm[i] += vt * sm[i] / 4.0;
+      P.vol += vt;
+    }
+  }
+  if (!(P.vol > 0)) return "the hull has no volume";
+  for (int i = 0; i < 3; i++) P.com[i] = cm[i] / P.vol;
+  const double tr = (C[0][0] + C[1][1] + C[2][2]) / P.vol;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) P.I[i][j] = (i == j ? tr : 0.0) - C[i][j] / P.vol;
+  const double Imax = std::max(P.I[0][0], std::max(P.I[1][1], P.I[2][2]));
+  for (int i = 0; i < 3; i++)
+    if (std::fabs(P.com[i]) > 1e-6 * ext) return "the hull's origin is not its centre of mass";
+  if (std::fabs(P.I[0][1]) > 1e-6 * Imax || std::fabs(P.I[0][2]) > 1e-6 * Imax || std::fabs(P.I[1][2]) > 1e-6 * Imax)
+    return "the hull's axes are not its principal axes";
+  return "";
+}
+
 struct Caps {
   int NB;
   long N;
@@ -311,13 +442,18 @@ int validate(const sim_batch_desc* d, Caps* caps) {
   }
   long N = d->h_body_offset[d->num_scenes];
   for (long i = 0; i < N; i++) {
-    if (d->h_shape[i] > SIM_CAPSULE) return fail(SIM_EINVAL, "bad shape type");
+    if (d->h_shape[i] > SIM_HULL) return fail(SIM_EINVAL, "bad shape type");
     if (d->h_motion[i] > SIM_KINEMATIC) return fail(SIM_EINVAL, "bad motion type");
     const float* p = d->h_param + 3 * i;
     int sh = d->h_shape[i];
-    int need = sh == SIM_SPHERE ? 1 : (sh == SIM_BOX ? 3 : 2);
-    for (int k = 0; k < need; k++)
-      if (!(p[k] > 0.f) || !std::isfinite(p[k])) return fail(SIM_EINVAL, "shape parameters must be positive");
+    if (sh == SIM_HULL) {
+      if (!(p[0] >= 0.f && p[0] < (float)d->n_hulls) || p[0] != std::floor(p[0]))
+        return fail(SIM_EINVAL, "a hull body needs the index of a hull in the library");
+    } else {
+      int need = sh == SIM_SPHERE ? 1 : (sh == SIM_BOX ? 3 : 2);
+      for (int k = 0; k < need; k++)
+        if (!(p[k] > 0.f) || !std::isfinite(p[k])) return fail(SIM_EINVAL, "shape parameters must be positive");
+    }
     if (d->h_motion[i] == SIM_DYNAMIC && !(d->h_mass[i] > 0.f && std::isfinite(d->h_mass[i])))
       return fail(SIM_EINVAL, "dynamic bodies need a positive mass");
   }
@@ -365,6 +501,17 @@ int validate(const sim_batch_desc* d, Caps* caps) {
       }
     }
   }
+  if (d->n_hulls < 0) return fail(SIM_EINVAL, "n_hulls must be >= 0");
+  if (d->n_hulls > 0) {
+    if (!d->h_hull_index || !d->h_hull_vert || !d->h_hull_face)
+      return fail(SIM_EINVAL, "a hull library needs index, vertex and face arrays");
+    if (d->warm_start == SIM_LEARNED) return fail(SIM_EINVAL, "convex hulls are not available with the learned warm start");
+    for (int h = 0; h < d->n_hulls; h++) {
+      HullPrep hp;
+      const std::string why = prepare_hull(d, h, hp);
+      if (!why.empty()) return fail(SIM_EINVAL, "hull " + std::to_string(h) + ": " + why);
+    }
+  }
   if (d->max_pairs < 1 || d->max_contacts < 1) return fail(SIM_EINVAL, "capacities must be >= 1");
   if (d->max_pairs > (1 << 20) || d->max_contacts > (1 << 20)) return fail(SIM_EINVAL, "capacity too large");
   // the narrowphase stages 4 contacts per pair in a contact record slot set
@@ -383,6 +530,20 @@ int validate(const sim_batch_desc* d, Caps* caps) {
 
 // articulation code of a descriptor (the layouts' last argument)
 int desc_art(const sim_batch_desc* d) { return d->arm | (d->h_joint ? rbs::kArtParts : 0); }
+
+// device table sizes of a validated descriptor's hull library
+HullSizes hull_sizes(const sim_batch_desc* d) {
+  HullSizes hs;
+  hs.H = d->n_hulls;
+  for (int h = 0; h < d->n_hulls; h++) {
+    HullPrep hp;
+    prepare_hull(d, h, hp);
+    hs.V += hp.nv;
+    hs.F += hp.nf;
+    hs.E += (long)hp.edge.size() / 4;
+  }
+  return hs;
+}
 
 int lds_bytes(int NB, int PM, int CM, int T, int solver, int warm, int arm) {
   rbs::LdsLayout L = rbs::lds_layout(NB, PM, CM, T / 64, solver, warm, arm);
@@ -627,7 +788,8 @@ size_t sim_workspace_bytes(const sim_batch_desc* d) {
   if (validate(d, &c) != SIM_OK) return 0;
   const HbmSplit sp = hbm_split(d->h_body_offset, d->num_scenes, d->max_pairs, d->max_contacts, device_lds_limit(),
                                 d->hbm_min_bodies, desc_art(d));
-  return make_layout(d->num_scenes, c.N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words, desc_art(d))
+  return make_layout(d->num_scenes, c.N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words, desc_art(d),
+                     hull_sizes(d))
       .total;
 }
 
@@ -642,7 +804,8 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   const int limit = device_lds_limit();
   const int art = desc_art(d);
   HbmSplit sp = hbm_split(d->h_body_offset, S, d->max_pairs, d->max_contacts, limit, d->hbm_min_bodies, art);
-  Layout lay = make_layout(S, N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words, art);
+  const HullSizes hs = hull_sizes(d);
+  Layout lay = make_layout(S, N, d->max_pairs, d->max_contacts, (long)sp.scenes.size(), sp.words, art, hs);
   if (!d_workspace || workspace_bytes < lay.total) return fail(SIM_EWORKSPACE, "workspace too small");
   if (((uintptr_t)d_workspace & 255u) != 0) return fail(SIM_EWORKSPACE, "workspace must be 256-byte aligned");
   const int T = d->threads ? d->threads : 64;
@@ -673,6 +836,7 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   h->last_export = 0;
   h->arm = d->arm;
   h->parts = d->h_joint != nullptr;
+  h->n_hulls = d->n_hulls;
   h->art = art;
   h->motor_kp = 0.3f;      // position gain of the joint motors (Sec. 5)
   h->motor_max = 10.0f;    // largest motor impulse per step, N s (Sec. 5)
@@ -697,6 +861,9 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
   h->hbm_words = sp.words;
   h->nb_lds = nbl;
 
+  // the hull library, prepared once
+  std::vector<HullPrep> preps(d->n_hulls > 0 ? d->n_hulls : 0);
+  for (int hh = 0; hh < d->n_hulls; hh++) prepare_hull(d, hh, preps[hh]);
   // host staging: structure-of-arrays planes
   std::vector<float> prm(3 * N), inv_mass(N), inv_I(3 * N), pose(7 * N), vel(6 * N);
   for (long i = 0; i < N; i++) {
@@ -707,7 +874,10 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
       double m = d->h_mass[i];
       const float* p = d->h_param + 3 * i;
       double I[3];
-      if (d->h_shape[i] == SIM_SPHERE) {
+      if (d->h_shape[i] == SIM_HULL) {  // principal moments of the solid hull (its frame is principal)
+        const HullPrep& hp = preps[(int)p[0]];
+        for (int k = 0; k < 3; k++) I[k] = m * hp.I[k][k];
+      } else if (d->h_shape[i] == SIM_SPHERE) {
         I[0] = I[1] = I[2] = 0.4 * m * (double)p[0] * p[0];
       } else if (d->h_shape[i] == SIM_BOX) {
         double x2 = (double)p[0] * p[0], y2 = (double)p[1] * p[1], z2 = (double)p[2] * p[2];
@@ -789,6 +959,37 @@ int sim_create(const sim_batch_desc* d, void* d_workspace, size_t workspace_byte
     if (e == hipSuccess) e = up(lay.off_joint_limits, jlim.data(), 4 * 2 * N);
     if (e == hipSuccess) e = up(lay.off_joint_parent, d->h_joint_parent, 4 * N);
   }
+  if (d->n_hulls > 0) {  // the hull library's device tables
+    std::vector<int32_t> info(8L * hs.H, 0);
+    std::vector<float> hv(4 * hs.V, 0.f), hp4(4 * hs.F, 0.f), hext(4 * hs.H, 0.f);
+    std::vector<uint8_t> hloop(8 * hs.F, 255u), hedge(4 * hs.E, 0u);
+    long v0 = 0, f0 = 0, e0 = 0;
+    for (int hh = 0; hh < d->n_hulls; hh++) {
+      const HullPrep& q = preps[hh];
+      const long ne = (long)q.edge.size() / 4;
+      const int32_t row[8] = {(int32_t)v0, q.nv, (int32_t)f0, q.nf, (int32_t)e0, (int32_t)ne, 0, 0};
+      for (int k = 0; k < 8; k++) info[8 * hh + k] = row[k];
+      for (int k = 0; k < q.nv; k++)
+        for (int c = 0; c < 3; c++) hv[4 * (v0 + k) + c] = (float)q.v[3 * k + c];
+      for (int f = 0; f < q.nf; f++) {
+        for (int c = 0; c < 4; c++) hp4[4 * (f0 + f) + c] = (float)q.plane[4 * f + c];
+        for (int k = 0; k < 8; k++)
+          if (q.loop[8 * f + k] >= 0) hloop[8 * (f0 + f) + k] = (uint8_t)q.loop[8 * f + k];
+      }
+      for (long k = 0; k < ne; k++)
+        for (int c = 0; c < 4; c++) hedge[4 * (e0 + k) + c] = (uint8_t)q.edge[4 * k + c];
+      for (int c = 0; c < 3; c++) hext[4 * hh + c] = (float)q.ext[c];
+      v0 += q.nv;
+      f0 += q.nf;
+      e0 += ne;
+    }
+    if (e == hipSuccess) e = up(lay.off_hull_info, info.data(), 4 * info.size());
+    if (e == hipSuccess) e = up(lay.off_hull_vert, hv.data(), 4 * hv.size());
+    if (e == hipSuccess) e = up(lay.off_hull_plane, hp4.data(), 4 * hp4.size());
+    if (e == hipSuccess) e = up(lay.off_hull_loop, hloop.data(), hloop.size());
+    if (e == hipSuccess) e = up(lay.off_hull_edge, hedge.data(), hedge.size());
+    if (e == hipSuccess) e = up(lay.off_hull_ext, hext.data(), 4 * hext.size());
+  }
   if (e == hipSuccess) e = up(lay.off_arm_base, base.data(), 4 * 3 * S);
   if (e == hipSuccess) e = up(lay.off_scene_list, order.data(), 4 * S);
   if (e == hipSuccess) e = up(lay.off_glist, glist.data(), 4 * S);
@@ -854,6 +1055,7 @@ int sim_step(sim_handle* h, const float* d_actions, float dt, int iters) {
 int sim_query_arm(sim_handle* h, const float* d_theta, int M, float clearance, uint8_t* d_hit, float* d_min_phi) {
   if (!h) return fail(SIM_EINVAL, "handle is NULL");
   if (!h->arm) return fail(SIM_EINVAL, "the batch has no arm");
+  if (h->n_hulls > 0) return fail(SIM_EINVAL, "arm queries do not support convex hulls");
   if (M < 0) return fail(SIM_EINVAL, "M must be >= 0");
   if (!(clearance >= 0.f) || !std::isfinite(clearance)) return fail(SIM_EINVAL, "clearance must be finite and >= 0");
   if (M == 0) return SIM_OK;
@@ -948,6 +1150,8 @@ int sim_set_solver(sim_handle* h, int solver, int warm_start, float tolerance) {
     return fail(SIM_EINVAL, "the articulated arm needs the PGS solver without the learned warm start");
   if (h->parts && (solver != SIM_PGS || warm_start == SIM_LEARNED))
     return fail(SIM_EINVAL, "container parts need the PGS solver without the learned warm start");
+  if (h->n_hulls > 0 && warm_start == SIM_LEARNED)
+    return fail(SIM_EINVAL, "convex hulls are not available with the learned warm start");
   const int old_solver = h->solver, old_warm = h->warm;
   h->solver = solver;
   h->warm = warm_start;

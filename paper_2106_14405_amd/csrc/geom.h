@@ -13,7 +13,7 @@
 
 namespace rbs {
 
-enum { SPHERE = 0, BOX = 1, CAPSULE = 2 };
+enum { SPHERE = 0, BOX = 1, CAPSULE = 2, HULL = 3 };
 enum { DYNAMIC = 0, STATIC = 1, KINEMATIC = 2 };
 
 constexpr float kSinParallel = 1e-3f;   // segment within ~1 mrad of a face plane
@@ -85,7 +85,8 @@ struct Geom {
   int shape;
   V3 x;
   M3 R;
-  float p[3];
+  float p[3];   // a hull: the half-extents of its local bounding box
+  int hull;     // a hull: its index in the hull library
 };
 struct PC {
   V3 n, p;

@@ -72,6 +72,14 @@ struct StepParams {
   const int32_t* joint_parent;  // [N]
   float* joint_state;       // [2][N] joint coordinate and its rate
   int art;                  // articulation code of the layouts: arm | (kArtParts when joint is set)
+  // convex hulls (null hull_info: none): the hull library (HullLib's
+  // arrays) and each hull's local bounding-box half-extents
+  const int32_t* hull_info; // [H][8]
+  const float4* hull_vert;  // [V]
+  const float4* hull_plane; // [F]
+  const uint8_t* hull_loop; // [F][8]
+  const uint8_t* hull_edge; // [E][4]
+  const float4* hull_ext;   // [H]
   const float* arm_base;    // [S][3]
   float link_len[7];
   float arm_radius;

@@ -27,6 +27,7 @@
 
 #include "arm.h"
 #include "geom.h"
+#include "hull.h"
 #include "mlp_mfma.h"
 #include "sim_internal.h"
 
@@ -360,6 +361,7 @@ __device__ __forceinline__ Geom load_geom(const LdsLayout& L, Smem S, int i) {
   g.p[0] = g2.x;
   g.p[1] = g2.y;
   g.p[2] = g2.z;
+  g.hull = (int)g2.w;
   return g;
 }
 
@@ -1384,7 +1386,12 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
     float qw = P.pose[3 * N + gi], qx = P.pose[4 * N + gi], qy = P.pose[5 * N + gi], qz = P.pose[6 * N + gi];
     st4(S.f + L.geo, 3 * i, f4(x, __uint_as_float(meta)));
     st4(S.f + L.geo, 3 * i + 1, make_float4(qw, qx, qy, qz));
-    st4(S.f + L.geo, 3 * i + 2, make_float4(P.prm[gi], P.prm[N + gi], P.prm[2 * N + gi], 0.f));
+    if (shape == HULL) {  // its bounding box's half-extents, its index in the library
+      const int h = (int)P.prm[gi];
+      st4(S.f + L.geo, 3 * i + 2, make_float4(P.hull_ext[h].x, P.hull_ext[h].y, P.hull_ext[h].z, (float)h));
+    } else {
+      st4(S.f + L.geo, 3 * i + 2, make_float4(P.prm[gi], P.prm[N + gi], P.prm[2 * N + gi], 0.f));
+    }
     V3 v = v3(P.vel[gi], P.vel[N + gi], P.vel[2 * N + gi]);
     V3 w = v3(P.vel[3 * N + gi], P.vel[4 * N + gi], P.vel[5 * N + gi]);
     float im = 0.f;
@@ -1443,7 +1450,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       float e = G.p[0] + P.margin;
       lo = G.x - v3(e, e, e);
       hi = G.x + v3(e, e, e);
-    } else if (G.shape == BOX) {
+    } else if (G.shape == BOX || G.shape == HULL) {  // a hull: its bounding box
       V3 e;
       e.x = fabsf(G.R.m[0][0]) * G.p[0] + fabsf(G.R.m[0][1]) * G.p[1] + fabsf(G.R.m[0][2]) * G.p[2] + P.margin;
       e.y = fabsf(G.R.m[1][0]) * G.p[0] + fabsf(G.R.m[1][1]) * G.p[1] + fabsf(G.R.m[1][2]) * G.p[2] + P.margin;
@@ -1587,9 +1594,11 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       const uint32_t k = pairs[p];
       const int a = (int)(k >> 11), bb = (int)(k & 2047u);
       const uint32_t sa = body_meta(L, S, a) & 255u;
-      if (bb == 2047) return 9u + sa;
+      if (bb == 2047) return 10u + sa;
       const uint32_t sb = body_meta(L, S, bb) & 255u;
-      return sa < sb ? 3u * sa + sb : 3u * sb + sa;
+      // the 10 unordered shape pairs of 4 shapes: lo * 4 + hi - lo (lo + 1) / 2
+      const uint32_t lo = sa < sb ? sa : sb, hi = sa < sb ? sb : sa;
+      return lo * 4u + hi - (lo * (lo + 1u)) / 2u;
     };
     for (int i = tid; i < 16 + 16 * W; i += T) {
       if (i < 16) cbase[i] = 0u;
@@ -1646,11 +1655,23 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       Out4 o;
       o.n = 0;
       Geom A = load_geom(L, S, a);
-      if (bb == 2047) {
-        ground_contacts(A, P.margin, o);
+      if constexpr (kArt) {  // convex hulls: only in the extended kernels
+        const HullLib HL{P.hull_info, P.hull_vert, P.hull_plane, P.hull_loop, P.hull_edge};
+        if (bb == 2047) {
+          if (A.shape == HULL) hull_ground(A, HL, P.margin, o);
+          else ground_contacts(A, P.margin, o);
+        } else {
+          Geom B = load_geom(L, S, bb);
+          if (A.shape == HULL || B.shape == HULL) collide_hull(A, B, HL, P.margin, o);
+          else collide(A, B, P.margin, o);
+        }
       } else {
-        Geom B = load_geom(L, S, bb);
-        collide(A, B, P.margin, o);
+        if (bb == 2047) {
+          ground_contacts(A, P.margin, o);
+        } else {
+          Geom B = load_geom(L, S, bb);
+          collide(A, B, P.margin, o);
+        }
       }
       ncnt[p] = (uint8_t)o.n;
 #pragma unroll
@@ -2300,7 +2321,8 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       if (!kLearned && P.sleep_speed > 0.f) {  // at rest: speed and surface speed |w| r at most sleep_speed
         const float4 g2 = ld4(S.f + L.geo, 3 * i + 2);
         const uint32_t sh = meta & 255u;
-        const float rb = sh == SPHERE ? g2.x : (sh == BOX ? sqrtf(g2.x * g2.x + g2.y * g2.y + g2.z * g2.z) : g2.x + g2.y);
+        const float rb = sh == SPHERE ? g2.x
+                         : ((sh == BOX || sh == HULL) ? sqrtf(g2.x * g2.x + g2.y * g2.y + g2.z * g2.z) : g2.x + g2.y);
         const bool at_rest = sqrtf(len2(vr)) <= P.sleep_speed && sqrtf(len2(wr)) * rb <= P.sleep_speed;
         const int32_t r0 = P.rest[gi];
         P.rest[gi] = at_rest ? (r0 < (1 << 30) ? r0 + 1 : r0) : 0;
@@ -2535,7 +2557,7 @@ extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L
   size_t bytes = (size_t)L->total * 4u;
   if (P->warm == rbs::WARM_LEARNED)
     hipLaunchKernelGGL((rbs::step_kernel<true, false>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
-  else if (P->arm == 2 || P->joint)
+  else if (P->arm == 2 || P->joint || P->hull_info)
     hipLaunchKernelGGL((rbs::step_kernel<false, true>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
   else
     hipLaunchKernelGGL((rbs::step_kernel<false, false>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
@@ -2546,7 +2568,7 @@ extern "C" int rbs_launch_step_hbm(const rbs::StepParams* P, const rbs::LdsLayou
   if (n <= 0) return 0;
   if (P->warm == rbs::WARM_LEARNED)
     hipLaunchKernelGGL((rbs::step_kernel_hbm<true, false>), dim3(n), dim3(256), 0, stream, *P, *L);
-  else if (P->arm == 2 || P->joint)
+  else if (P->arm == 2 || P->joint || P->hull_info)
     hipLaunchKernelGGL((rbs::step_kernel_hbm<false, true>), dim3(n), dim3(256), 0, stream, *P, *L);
   else
     hipLaunchKernelGGL((rbs::step_kernel_hbm<false, false>), dim3(n), dim3(256), 0, stream, *P, *L);
@@ -2576,7 +2598,7 @@ extern "C" int rbs_launch_persistent(const rbs::StepParams* P, const rbs::QueueP
   const size_t bytes = (size_t)Q->lds_words * 4u;
   if (P->warm == rbs::WARM_LEARNED)
     hipLaunchKernelGGL((rbs::step_persistent<true, false>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
-  else if (P->arm == 2 || P->joint)
+  else if (P->arm == 2 || P->joint || P->hull_info)
     hipLaunchKernelGGL((rbs::step_persistent<false, true>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
   else
     hipLaunchKernelGGL((rbs::step_persistent<false, false>), dim3(grid), dim3(256), bytes, stream, *P, *Q);

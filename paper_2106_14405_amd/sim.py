@@ -64,6 +64,11 @@ class Sim:
             h2["joint_anchor"] = np.ascontiguousarray(batch.joint_anchor, np.float32).reshape(-1)
             h2["joint_limits"] = np.ascontiguousarray(batch.joint_limits, np.float32).reshape(-1)
             h2["joint_parent"] = np.ascontiguousarray(batch.joint_parent, np.int32)
+        self.has_hulls = getattr(batch, "hull_index", None) is not None
+        if self.has_hulls:
+            self._host["hull_index"] = np.ascontiguousarray(batch.hull_index, np.int32).reshape(-1)
+            self._host["hull_vert"] = np.ascontiguousarray(batch.hull_vert, np.float32).reshape(-1)
+            self._host["hull_face"] = np.ascontiguousarray(batch.hull_face, np.int32).reshape(-1)
         h = self._host
         d = L.BatchDesc()
         d.abi_version = L.SIM_ABI_VERSION
@@ -91,6 +96,11 @@ class Sim:
         d.max_pairs, d.max_contacts = self.max_pairs, self.max_contacts
         d.solver, d.warm_start, d.tolerance, d.threads = int(solver), int(warm), float(tol), int(threads)
         d.hbm_min_bodies = int(hbm_min_bodies)
+        if self.has_hulls:
+            d.n_hulls = int(len(h["hull_index"]) // 4)
+            d.h_hull_index = _np_ptr(h["hull_index"], C.c_int32)
+            d.h_hull_vert = _np_ptr(h["hull_vert"], C.c_float)
+            d.h_hull_face = _np_ptr(h["hull_face"], C.c_int32)
         if self.has_parts:
             d.h_joint = _np_ptr(h["joint"], C.c_uint8)
             d.h_joint_axis = _np_ptr(h["joint_axis"], C.c_float)

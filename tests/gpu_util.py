@@ -112,6 +112,20 @@ def gpu_results(sim):
     return out
 
 
+def body_radii(batch, b0, b1):
+    """Bounding radii of bodies [b0, b1): a hull's is its bounding box's
+    half-diagonal (from its library vertices), the others' from their params."""
+    out = []
+    for i in range(b0, b1):
+        if int(batch.shape[i]) == S.HULL:
+            v0, nv = batch.hull_index[int(batch.param[i, 0])][:2]
+            ext = np.abs(batch.hull_vert[v0:v0 + nv]).max(axis=0)
+            out.append(float(np.linalg.norm(ext)))
+        else:
+            out.append(S.bounding_radius(int(batch.shape[i]), batch.param[i]))
+    return np.array(out)
+
+
 def _find(par, x):
     while par[x] != x:
         par[x] = par[par[x]]
@@ -334,7 +348,7 @@ def compare(batch, g, r, ora, check_values=True, contact_values=False, partial=T
                 dyn = (batch.motion[b0:b1] == S.DYNAMIC) & ~aff
                 if int(batch.arm) == 2:  # links of the articulated arm: the arm as a whole is checked by its rates
                     dyn[-7:] = False
-                rad = np.array([S.bounding_radius(int(batch.shape[i]), batch.param[i]) for i in range(b0, b1)])
+                rad = body_radii(batch, b0, b1)
                 jk = batch.joint[b0:b1] if getattr(batch, "joint", None) is not None else np.zeros(b1 - b0, np.uint8)
                 part = dyn & (jk > 0)
                 dyn &= jk == 0
@@ -372,7 +386,7 @@ def compare(batch, g, r, ora, check_values=True, contact_values=False, partial=T
         # velocities as vectors: the error relative to the oracle's speed
         # (floor 1 m/s); an angular velocity by the surface speed |w| r it
         # gives the body (r its bounding radius), with the same floor
-        rad = np.array([S.bounding_radius(int(batch.shape[i]), batch.param[i]) for i in range(b0, b1)])[keep]
+        rad = body_radii(batch, b0, b1)[keep]
         nv = np.linalg.norm
         ev = np.max(nv(vg[:, :3] - vo[:, :3], axis=1) / np.maximum(nv(vo[:, :3], axis=1), V_FLOOR), initial=0.0)
         ew = np.max(nv(vg[:, 3:] - vo[:, 3:], axis=1) * rad / np.maximum(nv(vo[:, 3:], axis=1) * rad, V_FLOOR),

@@ -1,0 +1,135 @@
+"""Convex hulls on the GPU (Sec. 3 and Sec. 4.3: objects collide as convex
+hulls) against the oracle: one step from the same float32 state.
+
+Drop scenes of prisms, bipyramids and chamfered boxes among spheres, boxes
+and capsules, settled in the oracle, so that hulls rest on the ground, on
+each other and on the other shapes: every pair class with a hull occurs.
+Pairs, contact keys (features included), colours, contact geometry and
+impulses, and body states as in every parity test (`compare`).  The
+persistent launch, the global-memory working set and 256-thread teams give
+the same bits as one 64-thread workgroup per scene; modes and libraries
+the step does not support are refused."""
+import numpy as np
+import pytest
+
+from gpu_util import compare, gpu_results, gpu_sim, oracle_warmup, report, snapshot32
+from helpers import DT, S
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def hull_batch(n, seed0=500):
+    return S.pack([S.drop_scene(seed0 + s, n_spheres=8, n_boxes=8, n_capsules=8, n_hulls=24) for s in range(n)])
+
+
+def pair_classes(b, r):
+    """Counts of contacts by the shapes of their bodies (with a hull)."""
+    out = {}
+    names = {S.SPHERE: "sphere", S.BOX: "box", S.CAPSULE: "capsule", S.HULL: "hull"}
+    for s in range(b.n_scenes):
+        b0 = int(b.body_offset[s])
+        k = r["c_key"][s, :int(r["n_contacts"][s])]
+        for key in k:
+            a, bb = int(key) >> 20, (int(key) >> 8) & 0xFFF
+            sa = int(b.shape[b0 + a])
+            sb = "ground" if bb == 0xFFF else names[int(b.shape[b0 + bb])]
+            if S.HULL not in (sa, -1 if bb == 0xFFF else int(b.shape[b0 + bb])):
+                continue
+            name = "-".join(sorted([names[sa], sb]))
+            out[name] = out.get(name, 0) + 1
+    return out
+
+
+@pytest.mark.parametrize("warm,tol,iters,steps", [(O.PREV, 0.0, 20, 120), (O.COLD, 0.0, 20, 60),
+                                                  (O.PREV, 1e-4, 1000, 200)])
+def test_hull_drop_parity(torch_cuda, warm, tol, iters, steps):
+    b = hull_batch(8)
+    ora = oracle_warmup(b, steps, iters=20, warm=O.PREV)
+    pose, vel, theta, cache = snapshot32(ora)
+    sim = gpu_sim(b, pose, vel, theta, cache, warm=warm, tol=tol)
+    sim.step(None, DT, iters)
+    r = ora.step(iters=iters, tol=tol, warm=warm, max_pairs=sim.max_pairs, max_contacts=sim.max_contacts)
+    g = gpu_results(sim)
+    rep = compare(b, g, r, ora, contact_values=True, tol_band=0.02 if tol > 0 else None)
+    report(f"hull drop, step {steps}, warm={warm} tol={tol:g}", rep)
+    cls = pair_classes(b, r)
+    print(f"contacts with a hull by class: {cls}", flush=True)
+    for name in ("ground-hull", "hull-hull", "box-hull", "hull-sphere", "capsule-hull"):
+        assert cls.get(name, 0) >= 3, (name, cls)
+    assert rep["contacts_solved"] >= 300
+
+
+def state(sim):
+    import torch
+    torch.cuda.synchronize()
+    cnt, key, lam = sim.cache()
+    return dict(pose=sim.pose.cpu().numpy().copy(), vel=sim.vel.cpu().numpy().copy(),
+                count=cnt.cpu().numpy().copy(), key=key.cpu().numpy().copy(), lam=lam.cpu().numpy().copy(),
+                **{k: v.cpu().numpy().copy() for k, v in sim.stats.items()})
+
+
+@pytest.mark.parametrize("variant", ["persistent", "hbm", "threads"])
+def test_hull_launches_bit_identical(torch_cuda, variant):
+    """80 steps of a hull drop: every launch gives the same bits as one
+    64-thread workgroup per scene in LDS."""
+    from paper_2106_14405_amd.sim import Sim
+    b = hull_batch(12, seed0=700)
+    sims = []
+    for alt in (False, True):
+        kw = dict(warm=O.PREV, tol=1e-4, threads=64)
+        if alt and variant == "hbm":
+            kw["hbm_min_bodies"] = 1
+        if alt and variant == "threads":
+            kw["threads"] = 256
+        sm = Sim(b, **kw)
+        if alt and variant == "persistent":
+            sm.set_persistent(True, 64)
+        sims.append(sm)
+    for t in range(80):
+        for sm in sims:
+            sm.step(None, DT, 200)
+        if t % 20 == 19:
+            x, y = state(sims[0]), state(sims[1])
+            for k in x:
+                assert np.array_equal(x[k], y[k]), f"step {t}: {k} differs"
+
+
+def test_hull_refusals(torch_cuda):
+    from paper_2106_14405_amd import _lib as L
+    from paper_2106_14405_amd.sim import Sim
+    b = hull_batch(2)
+    with pytest.raises(L.SimError):
+        Sim(b, warm=O.LEARNED)
+    sim = Sim(b, warm=O.PREV)
+    with pytest.raises(L.SimError, match="hulls"):
+        sim.set_solver(L.PGS, L.LEARNED, 0.0)
+
+    def bad(match, fn):
+        bb = S.Batch(**{**b.__dict__})
+        bb.hull_vert = b.hull_vert.copy()
+        bb.hull_face = b.hull_face.copy()
+        bb.param = b.param.copy()
+        fn(bb)
+        with pytest.raises(L.SimError, match=match):
+            Sim(bb, warm=O.PREV)
+    v0, nv, f0, nf = b.hull_index[0]
+    bad("centre of mass", lambda bb: bb.hull_vert.__setitem__(slice(v0, v0 + nv), b.hull_vert[v0:v0 + nv] + 0.01))
+    bad("close the surface", lambda bb: bb.hull_face.__setitem__(f0, np.r_[b.hull_face[f0][:3][::-1], b.hull_face[f0][3:]]))
+
+    def dent(bb):   # one vertex pulled in towards the centre: a face through it bends inwards
+        bb.hull_vert[v0] = 0.5 * b.hull_vert[v0]
+    bad("convex|centre of mass", dent)
+    hb = np.nonzero(b.shape == S.HULL)[0][0]
+    bad("index", lambda bb: bb.param.__setitem__((hb, 0), 1e6))
+    # arm queries are not available with hulls
+    ba = S.pack([S.clutter_scene(1, arm=True)])
+    assert ba.hull_index is None
