@@ -81,7 +81,8 @@ def parse():
                     help="uneven workload: persistent (default) or one workgroup per scene")
     ap.add_argument("--pool", type=int, default=4, help="uneven workload: fresh states per scene in the reset pool")
     ap.add_argument("--arm-eval", type=int, default=1,
-                    help="clutter: also time the same scenes with the articulated arm (PD joint motors)")
+                    help="clutter: also time variants of the workload: the articulated arm (PD joint "
+                         "motors), cabinets with doors and drawers, convex hulls")
     ap.add_argument("--learned-eval", type=int, default=1)
     ap.add_argument("--learned-scenes", type=int, default=2048)
     ap.add_argument("--learned-steps", type=int, default=240)
@@ -267,41 +268,54 @@ def learned_vs_plain(n_scenes, steps):
     return res
 
 
-def articulated_arm(batch, acts, a, max_contacts, max_pairs, cap, dev):
-    """The clutter scenes with the articulated arm (PD joint motors, the
-    same per-step action rates as motor-target rates): settled like the
-    headline, then the same window timed with the classic warm start at the
-    same tolerance and cap."""
+def extra_mode(batch, acts, a, max_contacts, max_pairs, cap, dev, workload):
+    """A variant of the clutter workload (the articulated arm with the same
+    per-step action rates as motor-target rates; cabinets with doors and
+    drawers; convex hulls): settled like the headline, then the same window
+    timed with the classic warm start at the same tolerance and cap."""
     import torch
     from paper_2106_14405_amd import _lib as L
     from paper_2106_14405_amd.sim import Sim
     sim = Sim(batch, max_contacts=max_contacts, max_pairs=max_pairs, warm=L.PREV, tol=0.0, threads=a.threads,
               device=dev)
     K, W, T0 = a.steps, a.warmup, a.settle
+    act = (lambda t: acts[t]) if batch.arm else (lambda t: None)
     for t in range(T0):
-        sim.step(acts[t], DT, 20)
+        sim.step(act(t), DT, 20)
     sim.set_solver(L.PGS, L.PREV, a.tol)
     for t in range(W):
-        sim.step(acts[T0 + t], DT, cap)
+        sim.step(act(T0 + t), DT, cap)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(sim.stream)
     for t in range(K):
-        sim.step(acts[T0 + W + t], DT, cap)
+        sim.step(act(T0 + W + t), DT, cap)
     ev1.record(sim.stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     # statistics of the last timed step (a replay of the window would double the run)
-    r = dict(ms_per_step=ms / K, env_steps_per_s=batch.n_scenes * K / (ms / 1e3),
-             workload="clutter scenes with the articulated arm (dynamic links of 2.0-0.5 kg, Kp 0.3, 10 N s)",
+    r = dict(ms_per_step=ms / K, env_steps_per_s=batch.n_scenes * K / (ms / 1e3), workload=workload,
+             bodies_per_scene=float(batch.n_bodies / batch.n_scenes),
              last_step_sweeps_mean=float(sim.stats["sweeps"].float().mean().item()),
              last_step_frac_at_tol=float((sim.stats["residual"] <= a.tol).float().mean().item()),
-             last_step_arm_force_mean_N=float(sim.stats["arm_force"].mean().item()),
-             joint_rate_max=float(sim.arm_state[:, 0].abs().max().item()))
+             last_step_contacts_mean=float(sim.stats["contacts"].float().mean().item()))
+    if sim.arm_state is not None:
+        r["last_step_arm_force_mean_N"] = float(sim.stats["arm_force"].mean().item())
+        r["joint_rate_max"] = float(sim.arm_state[:, 0].abs().max().item())
+    if sim.joint_state is not None:
+        js = sim.joint_state.cpu().numpy()
+        parts = batch.joint > 0
+        r["parts_per_scene"] = float(parts.sum() / batch.n_scenes)
+        r["parts_moved_frac"] = float(np.mean(np.abs(js[0, parts]) > 1e-3))
     sim.close()
     del sim
     torch.cuda.synchronize()
     return r
+
+
+def _hull_scene(seed):
+    from paper_2106_14405_amd import scenes as S
+    return S.drop_scene(seed, n_spheres=27, n_boxes=27, n_capsules=27, n_hulls=27, size=(0.03, 0.3), edge=4.0)
 
 
 def summarise(sweeps, resid, flags, contacts, tol):
@@ -365,7 +379,15 @@ def main():
         modes.append(a.headline)
     # every host-side input is generated before the GPU is touched
     batch = batch_fn(n_scenes)
-    batch_arm = S.batch_clutter(n_scenes, seed0=10000, arm=2) if a.workload == "clutter" and a.arm_eval else None
+    extra = []   # (name, batch, description): variants of the clutter workload
+    if a.workload == "clutter" and a.arm_eval:
+        extra.append(("prev_articulated_arm", S.batch_clutter(n_scenes, seed0=10000, arm=2),
+                      "clutter scenes with the articulated arm (dynamic links of 2.0-0.5 kg, Kp 0.3, 10 N s)"))
+        extra.append(("prev_cabinets", S.batch_clutter(n_scenes, seed0=10000, arm=2, cabinets=2),
+                      "the articulated-arm clutter with 2 cabinets a scene (a hinged door and a drawer each)"))
+        extra.append(("prev_hulls", S.pack(S._map(_hull_scene, [10000 + s for s in range(n_scenes)], None)),
+                      "drop scenes of 27 spheres, 27 boxes, 27 capsules and 27 convex hulls (prisms, bipyramids, "
+                      "chamfered boxes), sizes 0.03-0.3 m, dropped in a 4 m cube"))
     pool = S.reset_pool(batch, a.pool, seed=40000, kind="drop") if a.workload == "uneven" else None
     cpu_batch = None
     if a.cpu_baseline and a.workload != "uneven":
@@ -467,9 +489,9 @@ def main():
     sim.close()
     del sim
     torch.cuda.synchronize()
-    if batch_arm is not None:
-        results["prev_articulated_arm"] = articulated_arm(batch_arm, acts, a, max_contacts, max_pairs, cap, dev)
-        progress(f"prev_articulated_arm: {results['prev_articulated_arm']['ms_per_step']:.3f} ms per step")
+    for name, xb, desc in extra:
+        results[name] = extra_mode(xb, acts, a, max_contacts, max_pairs, cap, dev, desc)
+        progress(f"{name}: {results[name]['ms_per_step']:.3f} ms per step")
 
     head = results[a.headline]
     motion = batch.motion

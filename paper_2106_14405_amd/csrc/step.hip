@@ -1349,9 +1349,13 @@ __device__ __forceinline__ V3 setup_lin_vel(const StepParams& P, long gi, long N
   return v3(P.vel[gi], P.vel[N + gi], P.vel[2 * N + gi]) + g * dt;
 }
 
-template <bool kLearned, bool kArt, class TM>
+// kExt: 0 the plain step; 1 with the articulated arm and container parts;
+// 2 also with convex hulls (their narrowphase's registers and stack stay
+// out of the other variants).
+template <bool kLearned, int kExt, class TM>
 __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout& L, Smem S, const int s,
                                            const TM tm) {
+  constexpr bool kArt = kExt >= 1;
   const int tid = tm.tid, T = tm.T;
   const int b0 = P.body_offset[s];
   const int nb = P.body_offset[s + 1] - b0;
@@ -1655,7 +1659,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       Out4 o;
       o.n = 0;
       Geom A = load_geom(L, S, a);
-      if constexpr (kArt) {  // convex hulls: only in the extended kernels
+      if constexpr (kExt == 2) {  // convex hulls: only in their own kernels
         const HullLib HL{P.hull_info, P.hull_vert, P.hull_plane, P.hull_loop, P.hull_edge};
         if (bb == 2047) {
           if (A.shape == HULL) hull_ground(A, HL, P.margin, o);
@@ -2426,13 +2430,13 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   TRACE(14);
 }
 
-template <bool kLearned, bool kArt>
+template <bool kLearned, int kExt>
 __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
   extern __shared__ float4 smem_f4[];
   Smem S{reinterpret_cast<float*>(smem_f4), reinterpret_cast<uint32_t*>(smem_f4)};
   const Team<false> tm{(int)threadIdx.x, (int)blockDim.x};
   const int s = P.scene_list ? P.scene_list[blockIdx.x] : (int)blockIdx.x;
-  scene_step<kLearned, kArt>(P, L, S, s, tm);
+  scene_step<kLearned, kExt>(P, L, S, s, tm);
 }
 
 // Scenes whose working set exceeds a workgroup's LDS: the same step with the
@@ -2440,12 +2444,12 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams P, LdsLayout L) {
 // P.glist, L2 and HBM resident) instead of LDS; one workgroup per scene.
 // The team barriers are workgroup-scope fences, which order global memory
 // as they order LDS, so the step computes exactly what it computes in LDS.
-template <bool kLearned, bool kArt>
+template <bool kLearned, int kExt>
 __global__ __launch_bounds__(256) void step_kernel_hbm(StepParams P, LdsLayout L) {
   const int k = (int)blockIdx.x;
   float* ws = P.gscr + (size_t)k * (size_t)P.gwords;
   const Team<false> tm{(int)threadIdx.x, (int)blockDim.x};
-  scene_step<kLearned, kArt>(P, L, Smem{ws, reinterpret_cast<uint32_t*>(ws)}, P.glist[k], tm);
+  scene_step<kLearned, kExt>(P, L, Smem{ws, reinterpret_cast<uint32_t*>(ws)}, P.glist[k], tm);
 }
 
 // Persistent launch over scenes of uneven size: every workgroup first takes
@@ -2454,7 +2458,7 @@ __global__ __launch_bounds__(256) void step_kernel_hbm(StepParams P, LdsLayout L
 // steps each alone in its quarter of the LDS.  Queues are in descending
 // body count, so the largest scenes start first; a workgroup leaves once
 // both queues are drained.
-template <bool kLearned, bool kArt>
+template <bool kLearned, int kExt>
 __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams Q) {
   extern __shared__ float4 smem_f4[];
   __shared__ int next_scene;
@@ -2470,7 +2474,7 @@ __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams
     const int nb = P.body_offset[s + 1] - P.body_offset[s];
     const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), (int)blockDim.x >> 6, P.solver,
                                    P.warm, P.art);
-    scene_step<kLearned, kArt>(P, L, Smem{lds, reinterpret_cast<uint32_t*>(lds)}, s, Team<false>{tid, (int)blockDim.x});
+    scene_step<kLearned, kExt>(P, L, Smem{lds, reinterpret_cast<uint32_t*>(lds)}, s, Team<false>{tid, (int)blockDim.x});
     __syncthreads();
   }
   const int w = tid >> 6, lane = tid & 63;
@@ -2483,7 +2487,7 @@ __global__ __launch_bounds__(256) void step_persistent(StepParams P, QueueParams
     const int s = Q.wave[k];
     const int nb = P.body_offset[s + 1] - P.body_offset[s];
     const LdsLayout L = lds_layout(nb, scene_cap(nb, P.PM), scene_cap(nb, P.CM), 1, P.solver, P.warm, P.art);
-    scene_step<kLearned, kArt>(P, L, Smem{mine, reinterpret_cast<uint32_t*>(mine)}, s, Team<true>{lane, 64});
+    scene_step<kLearned, kExt>(P, L, Smem{mine, reinterpret_cast<uint32_t*>(mine)}, s, Team<true>{lane, 64});
   }
 }
 
@@ -2556,33 +2560,38 @@ extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L
                                hipStream_t stream) {
   size_t bytes = (size_t)L->total * 4u;
   if (P->warm == rbs::WARM_LEARNED)
-    hipLaunchKernelGGL((rbs::step_kernel<true, false>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
-  else if (P->arm == 2 || P->joint || P->hull_info)
-    hipLaunchKernelGGL((rbs::step_kernel<false, true>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
+    hipLaunchKernelGGL((rbs::step_kernel<true, 0>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
+  else if (P->hull_info)
+    hipLaunchKernelGGL((rbs::step_kernel<false, 2>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
+  else if (P->arm == 2 || P->joint)
+    hipLaunchKernelGGL((rbs::step_kernel<false, 1>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
   else
-    hipLaunchKernelGGL((rbs::step_kernel<false, false>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
+    hipLaunchKernelGGL((rbs::step_kernel<false, 0>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
   return (int)hipGetLastError();
 }
 
 extern "C" int rbs_launch_step_hbm(const rbs::StepParams* P, const rbs::LdsLayout* L, int n, hipStream_t stream) {
   if (n <= 0) return 0;
   if (P->warm == rbs::WARM_LEARNED)
-    hipLaunchKernelGGL((rbs::step_kernel_hbm<true, false>), dim3(n), dim3(256), 0, stream, *P, *L);
-  else if (P->arm == 2 || P->joint || P->hull_info)
-    hipLaunchKernelGGL((rbs::step_kernel_hbm<false, true>), dim3(n), dim3(256), 0, stream, *P, *L);
+    hipLaunchKernelGGL((rbs::step_kernel_hbm<true, 0>), dim3(n), dim3(256), 0, stream, *P, *L);
+  else if (P->hull_info)
+    hipLaunchKernelGGL((rbs::step_kernel_hbm<false, 2>), dim3(n), dim3(256), 0, stream, *P, *L);
+  else if (P->arm == 2 || P->joint)
+    hipLaunchKernelGGL((rbs::step_kernel_hbm<false, 1>), dim3(n), dim3(256), 0, stream, *P, *L);
   else
-    hipLaunchKernelGGL((rbs::step_kernel_hbm<false, false>), dim3(n), dim3(256), 0, stream, *P, *L);
+    hipLaunchKernelGGL((rbs::step_kernel_hbm<false, 0>), dim3(n), dim3(256), 0, stream, *P, *L);
   return (int)hipGetLastError();
 }
 
 // Dynamic LDS limits: the whole budget for the per-scene kernels; the
 // persistent kernel keeps 256 bytes for its static words.
 extern "C" int rbs_set_step_lds_limit(int bytes) {
-  const void* k[6] = {(const void*)rbs::step_kernel<false, false>, (const void*)rbs::step_kernel<true, false>,
-                      (const void*)rbs::step_kernel<false, true>, (const void*)rbs::step_persistent<false, false>,
-                      (const void*)rbs::step_persistent<true, false>, (const void*)rbs::step_persistent<false, true>};
-  for (int i = 0; i < 6; i++) {
-    int e = (int)hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, i < 3 ? bytes : bytes - 256);
+  const void* k[8] = {(const void*)rbs::step_kernel<false, 0>,     (const void*)rbs::step_kernel<true, 0>,
+                      (const void*)rbs::step_kernel<false, 1>,     (const void*)rbs::step_kernel<false, 2>,
+                      (const void*)rbs::step_persistent<false, 0>, (const void*)rbs::step_persistent<true, 0>,
+                      (const void*)rbs::step_persistent<false, 1>, (const void*)rbs::step_persistent<false, 2>};
+  for (int i = 0; i < 8; i++) {
+    int e = (int)hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, i < 4 ? bytes : bytes - 256);
     if (e) {
       (void)hipGetLastError();  // leave no sticky error behind
       return e;
@@ -2597,11 +2606,13 @@ extern "C" int rbs_launch_persistent(const rbs::StepParams* P, const rbs::QueueP
   hipLaunchKernelGGL(rbs::queue_reset_kernel, dim3(1), dim3(64), 0, stream, Q->head);
   const size_t bytes = (size_t)Q->lds_words * 4u;
   if (P->warm == rbs::WARM_LEARNED)
-    hipLaunchKernelGGL((rbs::step_persistent<true, false>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
-  else if (P->arm == 2 || P->joint || P->hull_info)
-    hipLaunchKernelGGL((rbs::step_persistent<false, true>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
+    hipLaunchKernelGGL((rbs::step_persistent<true, 0>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
+  else if (P->hull_info)
+    hipLaunchKernelGGL((rbs::step_persistent<false, 2>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
+  else if (P->arm == 2 || P->joint)
+    hipLaunchKernelGGL((rbs::step_persistent<false, 1>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
   else
-    hipLaunchKernelGGL((rbs::step_persistent<false, false>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
+    hipLaunchKernelGGL((rbs::step_persistent<false, 0>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
   return (int)hipGetLastError();
 }
 
