@@ -109,7 +109,7 @@ def probe_copy(mib):
 
 def kernel_hash():
     h = hashlib.sha256()
-    for f in ("step.hip", "arm.h", "geom.h", "sim_internal.h", "mlp_mfma.h", "mlp.hip"):
+    for f in ("step.hip", "arm.h", "geom.h", "hull.h", "sim_internal.h", "mlp_mfma.h", "mlp.hip"):
         p = os.path.join(ROOT, "paper_2106_14405_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
