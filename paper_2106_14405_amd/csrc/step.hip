@@ -1349,9 +1349,9 @@ __device__ __forceinline__ V3 setup_lin_vel(const StepParams& P, long gi, long N
   return v3(P.vel[gi], P.vel[N + gi], P.vel[2 * N + gi]) + g * dt;
 }
 
-// kExt: 0 the plain step; 1 with the articulated arm and container parts;
-// 2 also with convex hulls (their narrowphase's registers and stack stay
-// out of the other variants).
+// kExt: 0 the plain step; 1 with the articulated arm; 2 also with
+// container parts; 3 also with convex hulls (each level's code, registers
+// and stack stay out of the lower levels' kernels).
 template <bool kLearned, int kExt, class TM>
 __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout& L, Smem S, const int s,
                                            const TM tm) {
@@ -1379,7 +1379,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
   // the articulated arm and the container parts (their own kernels:
   // compiled out of the others)
   const bool arm2 = kArt && !kLearned && P.arm == 2;
-  const bool parts = kArt && !kLearned && P.joint != nullptr;
+  const bool parts = kExt >= 2 && !kLearned && P.joint != nullptr;
   const int arm0 = arm2 ? nb - 7 : nb;  // its first link
   for (int i = tid; i < nb; i += T) {
     const long gi = b0 + i;
@@ -1659,7 +1659,7 @@ __device__ __forceinline__ void scene_step(const StepParams& P, const LdsLayout&
       Out4 o;
       o.n = 0;
       Geom A = load_geom(L, S, a);
-      if constexpr (kExt == 2) {  // convex hulls: only in their own kernels
+      if constexpr (kExt == 3) {  // convex hulls: only in their own kernels
         const HullLib HL{P.hull_info, P.hull_vert, P.hull_plane, P.hull_loop, P.hull_edge};
         if (bb == 2047) {
           if (A.shape == HULL) hull_ground(A, HL, P.margin, o);
@@ -2562,8 +2562,10 @@ extern "C" int rbs_launch_step(const rbs::StepParams* P, const rbs::LdsLayout* L
   if (P->warm == rbs::WARM_LEARNED)
     hipLaunchKernelGGL((rbs::step_kernel<true, 0>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
   else if (P->hull_info)
+    hipLaunchKernelGGL((rbs::step_kernel<false, 3>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
+  else if (P->joint)
     hipLaunchKernelGGL((rbs::step_kernel<false, 2>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
-  else if (P->arm == 2 || P->joint)
+  else if (P->arm == 2)
     hipLaunchKernelGGL((rbs::step_kernel<false, 1>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
   else
     hipLaunchKernelGGL((rbs::step_kernel<false, 0>), dim3(grid), dim3(threads), bytes, stream, *P, *L);
@@ -2575,8 +2577,10 @@ extern "C" int rbs_launch_step_hbm(const rbs::StepParams* P, const rbs::LdsLayou
   if (P->warm == rbs::WARM_LEARNED)
     hipLaunchKernelGGL((rbs::step_kernel_hbm<true, 0>), dim3(n), dim3(256), 0, stream, *P, *L);
   else if (P->hull_info)
+    hipLaunchKernelGGL((rbs::step_kernel_hbm<false, 3>), dim3(n), dim3(256), 0, stream, *P, *L);
+  else if (P->joint)
     hipLaunchKernelGGL((rbs::step_kernel_hbm<false, 2>), dim3(n), dim3(256), 0, stream, *P, *L);
-  else if (P->arm == 2 || P->joint)
+  else if (P->arm == 2)
     hipLaunchKernelGGL((rbs::step_kernel_hbm<false, 1>), dim3(n), dim3(256), 0, stream, *P, *L);
   else
     hipLaunchKernelGGL((rbs::step_kernel_hbm<false, 0>), dim3(n), dim3(256), 0, stream, *P, *L);
@@ -2586,12 +2590,13 @@ extern "C" int rbs_launch_step_hbm(const rbs::StepParams* P, const rbs::LdsLayou
 // Dynamic LDS limits: the whole budget for the per-scene kernels; the
 // persistent kernel keeps 256 bytes for its static words.
 extern "C" int rbs_set_step_lds_limit(int bytes) {
-  const void* k[8] = {(const void*)rbs::step_kernel<false, 0>,     (const void*)rbs::step_kernel<true, 0>,
-                      (const void*)rbs::step_kernel<false, 1>,     (const void*)rbs::step_kernel<false, 2>,
-                      (const void*)rbs::step_persistent<false, 0>, (const void*)rbs::step_persistent<true, 0>,
-                      (const void*)rbs::step_persistent<false, 1>, (const void*)rbs::step_persistent<false, 2>};
-  for (int i = 0; i < 8; i++) {
-    int e = (int)hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, i < 4 ? bytes : bytes - 256);
+  const void* k[10] = {(const void*)rbs::step_kernel<false, 0>,     (const void*)rbs::step_kernel<true, 0>,
+                       (const void*)rbs::step_kernel<false, 1>,     (const void*)rbs::step_kernel<false, 2>,
+                       (const void*)rbs::step_kernel<false, 3>,     (const void*)rbs::step_persistent<false, 0>,
+                       (const void*)rbs::step_persistent<true, 0>,  (const void*)rbs::step_persistent<false, 1>,
+                       (const void*)rbs::step_persistent<false, 2>, (const void*)rbs::step_persistent<false, 3>};
+  for (int i = 0; i < 10; i++) {
+    int e = (int)hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, i < 5 ? bytes : bytes - 256);
     if (e) {
       (void)hipGetLastError();  // leave no sticky error behind
       return e;
@@ -2608,8 +2613,10 @@ extern "C" int rbs_launch_persistent(const rbs::StepParams* P, const rbs::QueueP
   if (P->warm == rbs::WARM_LEARNED)
     hipLaunchKernelGGL((rbs::step_persistent<true, 0>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
   else if (P->hull_info)
+    hipLaunchKernelGGL((rbs::step_persistent<false, 3>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
+  else if (P->joint)
     hipLaunchKernelGGL((rbs::step_persistent<false, 2>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
-  else if (P->arm == 2 || P->joint)
+  else if (P->arm == 2)
     hipLaunchKernelGGL((rbs::step_persistent<false, 1>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
   else
     hipLaunchKernelGGL((rbs::step_persistent<false, 0>), dim3(grid), dim3(256), bytes, stream, *P, *Q);
