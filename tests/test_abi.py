@@ -168,3 +168,93 @@ def test_no_cpu_fallback_when_library_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         L.load()
+
+
+def _with_hulls(d, keep, b):
+    P = lambda a, t: a.ctypes.data_as(C.POINTER(t))
+    keep["hi"] = np.ascontiguousarray(b.hull_index, np.int32).reshape(-1).copy()
+    keep["hv"] = np.ascontiguousarray(b.hull_vert, np.float32).reshape(-1).copy()
+    keep["hf"] = np.ascontiguousarray(b.hull_face, np.int32).reshape(-1).copy()
+    d.n_hulls = len(keep["hi"]) // 4
+    d.h_hull_index = P(keep["hi"], C.c_int32)
+    d.h_hull_vert = P(keep["hv"], C.c_float)
+    d.h_hull_face = P(keep["hf"], C.c_int32)
+
+
+def test_hull_library_validated():
+    """The host's checks of a hull library (convexity, closed surface,
+    principal frame about the centre of mass, index range, no learned
+    start), without a GPU: sim_workspace_bytes validates first."""
+    from paper_2106_14405_amd import _lib as L
+    lib = L.load()
+    b = S.pack([S.drop_scene(3, n_spheres=2, n_boxes=2, n_hulls=4)])
+    d, keep = _desc(b)
+    _with_hulls(d, keep, b)
+    assert lib.sim_workspace_bytes(C.byref(d)) > 0, lib.sim_last_error()
+    v0, nv, f0, nf = b.hull_index[0]
+    cases = [("not convex", lambda: keep["hv"].__setitem__(slice(3 * v0, 3 * v0 + 3), 0.4 * keep["hv"][3 * v0:3 * v0 + 3])),
+             ("centre of mass", lambda: keep["hv"].__setitem__(slice(3 * v0, 3 * (v0 + nv)), keep["hv"][3 * v0:3 * (v0 + nv)] + 0.01)),
+             ("close the surface", lambda: keep["hf"].__setitem__(slice(8 * f0, 8 * f0 + 3), keep["hf"][8 * f0:8 * f0 + 3][::-1].copy())),
+             ("index of a hull", lambda: keep["param"].__setitem__(3 * int(np.nonzero(b.shape == S.HULL)[0][0]), 99.0))]
+    for why, spoil in cases:
+        d, keep = _desc(b)
+        keep["param"] = keep["param"].copy()
+        d.h_param = keep["param"].ctypes.data_as(C.POINTER(C.c_float))
+        _with_hulls(d, keep, b)
+        spoil()
+        assert lib.sim_workspace_bytes(C.byref(d)) == 0, why
+        msg = lib.sim_last_error().decode()
+        assert why in msg or (why == "not convex" and "centre of mass" in msg), (why, msg)
+    d, keep = _desc(b, warm_start=L.LEARNED)
+    _with_hulls(d, keep, b)
+    assert lib.sim_workspace_bytes(C.byref(d)) == 0
+    assert b"learned" in lib.sim_last_error()
+
+
+def test_container_parts_validated():
+    """The host's checks of container parts without a GPU: kinds, dynamic
+    bodies only, unit axes, ordered limits, parent range, 16 a scene, PGS
+    without the learned start."""
+    from paper_2106_14405_amd import _lib as L
+    lib = L.load()
+    b = S.batch_clutter(1, seed0=10000, arm=True, cabinets=2)
+    P = lambda a, t: a.ctypes.data_as(C.POINTER(t))
+
+    def desc(spoil=None, **kw):
+        d, keep = _desc(b, **kw)
+        keep["j"] = np.ascontiguousarray(b.joint, np.uint8).copy()
+        keep["ja"] = np.ascontiguousarray(b.joint_axis, np.float32).reshape(-1).copy()
+        keep["jo"] = np.ascontiguousarray(b.joint_anchor, np.float32).reshape(-1).copy()
+        keep["jl"] = np.ascontiguousarray(b.joint_limits, np.float32).reshape(-1).copy()
+        keep["jp"] = np.ascontiguousarray(b.joint_parent, np.int32).copy()
+        if spoil:
+            spoil(keep)
+        d.h_joint = P(keep["j"], C.c_uint8)
+        d.h_joint_axis = P(keep["ja"], C.c_float)
+        d.h_joint_anchor = P(keep["jo"], C.c_float)
+        d.h_joint_limits = P(keep["jl"], C.c_float)
+        d.h_joint_parent = P(keep["jp"], C.c_int32)
+        return d, keep
+    d, keep = desc()
+    assert lib.sim_workspace_bytes(C.byref(d)) > 0, lib.sim_last_error()
+    p0 = int(np.nonzero(b.joint)[0][0])
+    dyn = [i for i in range(len(b.joint) - 7) if b.motion[i] == S.DYNAMIC and b.joint[i] == 0][:13]
+
+    def many(k):
+        k["j"][dyn] = 2
+        for i in dyn:
+            k["ja"][3 * i:3 * i + 3] = (1.0, 0.0, 0.0)
+    cases = [("joint kind", lambda k: k["j"].__setitem__(p0, 3)),
+             ("dynamic body", lambda k: k["j"].__setitem__(0, 1)),
+             ("unit vector", lambda k: k["ja"].__setitem__(slice(3 * p0, 3 * p0 + 3), (1.0, 1.0, 0.0))),
+             ("lower <= upper", lambda k: k["jl"].__setitem__(slice(2 * p0, 2 * p0 + 2), (0.5, -0.5))),
+             ("parent", lambda k: k["jp"].__setitem__(p0, 9999)),
+             ("16 container parts", many)]
+    for why, spoil in cases:
+        d, keep = desc(spoil)
+        assert lib.sim_workspace_bytes(C.byref(d)) == 0, why
+        assert why in lib.sim_last_error().decode(), (why, lib.sim_last_error())
+    for kw in (dict(solver=L.JACOBI), dict(warm_start=L.LEARNED)):
+        d, keep = desc(**kw)
+        assert lib.sim_workspace_bytes(C.byref(d)) == 0
+        assert b"container parts" in lib.sim_last_error()
