@@ -339,7 +339,7 @@ def main():
         probe_copy(a.probe_copy_mib)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     from paper_2106_14405_amd import scenes as S
     if a.workload == "clutter":
