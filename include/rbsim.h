@@ -131,8 +131,9 @@ typedef struct sim_batch_desc {
      * -1 after the last; every vertex on or inside every face plane; at
      * most 32 vertices and 32 faces a hull.  Contacts with hulls: against
      * the ground (vertices), spheres (closest point), capsules and boxes
-     * and other hulls (separating axes and face clipping).  Batches with
-     * hulls step without the learned warm start and have no arm queries. */
+     * and other hulls (separating axes and face clipping); arm queries
+     * test the links against hulls too.  Batches with hulls step without
+     * the learned warm start. */
     int n_hulls;                   /* H (0: none) */
     const int32_t *h_hull_index;   /* [H*4]: first vertex, vertex count, first face, face count */
     const float *h_hull_vert;      /* [V*3] m */
@@ -232,7 +233,7 @@ int sim_step(sim_handle *h, const float *d_actions, float dt, int iters);
  * d_min_phi (device float32 [S][M], or NULL) gets the least separation of
  * those contacts, +INF when none is within the clearance.  The scenes'
  * state is read, not changed; no solver runs.  SIM_EINVAL for a batch
- * without the arm or with convex hulls, M < 0, a bad clearance or NULL/misaligned arrays
+ * without the arm, M < 0, a bad clearance or NULL/misaligned arrays
  * (nothing launched); M = 0 does nothing.  Asynchronous on the handle's
  * stream, after any step enqueued before it. */
 int sim_query_arm(sim_handle *h, const float *d_theta, int M, float clearance, uint8_t *d_hit, float *d_min_phi);

@@ -41,7 +41,9 @@ extern "C" int rbs_gather(const int32_t* count, const int32_t* flags, int S, int
 extern "C" int rbs_launch_query(int n_scenes, int max_bodies, long n_bodies, const int32_t* body_offset,
                                 const uint8_t* shape, const float* prm, const float* pose, const float* arm_base,
                                 const float* link_len, const float* theta, int M, float clearance, uint8_t* hit,
-                                float* min_phi, hipStream_t stream);
+                                float* min_phi, const int32_t* hull_info, const float4* hull_vert,
+                                const float4* hull_plane, const uint8_t* hull_loop, const uint8_t* hull_edge,
+                                const float4* hull_ext, hipStream_t stream);
 extern "C" int rbs_launch_arm_pose(const rbs::StepParams* P, const uint8_t* mask, hipStream_t stream);
 extern "C" int rbs_launch_reset(const rbs::StepParams* P, const uint8_t* mask, int K, const int32_t* index,
                                 const float* pool_pose, const float* pool_vel, const float* pool_theta,
@@ -1055,7 +1057,6 @@ int sim_step(sim_handle* h, const float* d_actions, float dt, int iters) {
 int sim_query_arm(sim_handle* h, const float* d_theta, int M, float clearance, uint8_t* d_hit, float* d_min_phi) {
   if (!h) return fail(SIM_EINVAL, "handle is NULL");
   if (!h->arm) return fail(SIM_EINVAL, "the batch has no arm");
-  if (h->n_hulls > 0) return fail(SIM_EINVAL, "arm queries do not support convex hulls");
   if (M < 0) return fail(SIM_EINVAL, "M must be >= 0");
   if (!(clearance >= 0.f) || !std::isfinite(clearance)) return fail(SIM_EINVAL, "clearance must be finite and >= 0");
   if (M == 0) return SIM_OK;
@@ -1065,7 +1066,8 @@ int sim_query_arm(sim_handle* h, const float* d_theta, int M, float clearance, u
   for (int s = 0; s < h->S; s++) nb_max = std::max(nb_max, h->body_offset[s + 1] - h->body_offset[s]);
   const rbs::StepParams P = params(h);
   const int rc = rbs_launch_query(h->S, nb_max, h->N, P.body_offset, P.shape, P.prm, P.pose, P.arm_base,
-                                  h->link_len, d_theta, M, clearance, d_hit, d_min_phi, h->stream);
+                                  h->link_len, d_theta, M, clearance, d_hit, d_min_phi, P.hull_info, P.hull_vert,
+                                  P.hull_plane, P.hull_loop, P.hull_edge, P.hull_ext, h->stream);
   if (rc == -2) return fail(SIM_EINVAL, "too many scenes x configuration blocks for one launch");
   if (rc != 0) return fail(SIM_EDEVICE, std::string("query launch failed: ") + hipGetErrorString((hipError_t)rc));
   return SIM_OK;

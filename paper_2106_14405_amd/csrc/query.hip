@@ -28,6 +28,7 @@
 
 #include "arm.h"
 #include "geom.h"
+#include "hull.h"
 
 namespace rbs {
 
@@ -46,6 +47,8 @@ struct QueryParams {
   float clearance;
   uint8_t* hit;              // [S][M]
   float* min_phi;            // [S][M] or null
+  HullLib hl;                // convex hulls (hl.info null: none)
+  const float4* hull_ext;    // [H] their local bounding-box half-extents
 };
 
 constexpr int kQueryWaves = 4;
@@ -76,6 +79,14 @@ __device__ __forceinline__ Geom body_geom(const QueryParams& Q, long g) {
   G.p[0] = Q.prm[g];
   G.p[1] = Q.prm[N + g];
   G.p[2] = Q.prm[2 * N + g];
+  G.hull = -1;
+  if (G.shape == HULL) {  // a hull: its index in the library, its bounding box's half-extents
+    G.hull = (int)G.p[0];
+    const float4 e = Q.hull_ext[G.hull];
+    G.p[0] = e.x;
+    G.p[1] = e.y;
+    G.p[2] = e.z;
+  }
   return G;
 }
 
@@ -83,7 +94,7 @@ __device__ __forceinline__ Geom body_geom(const QueryParams& Q, long g) {
 __device__ __forceinline__ void shape_box(const Geom& G, float w, V3& lo, V3& hi) {
   V3 e;
   V3 c = G.x;
-  if (G.shape == BOX) {
+  if (G.shape == BOX || G.shape == HULL) {  // a hull: its bounding box
     e.x = fabsf(G.R.m[0][0]) * G.p[0] + fabsf(G.R.m[0][1]) * G.p[1] + fabsf(G.R.m[0][2]) * G.p[2];
     e.y = fabsf(G.R.m[1][0]) * G.p[0] + fabsf(G.R.m[1][1]) * G.p[1] + fabsf(G.R.m[1][2]) * G.p[2];
     e.z = fabsf(G.R.m[2][0]) * G.p[0] + fabsf(G.R.m[2][1]) * G.p[1] + fabsf(G.R.m[2][2]) * G.p[2];
@@ -198,10 +209,12 @@ __global__ __launch_bounds__(256) void query_kernel(QueryParams Q) {
         Lg.p[0] = w[7];
         Lg.p[1] = w[8];
         Lg.p[2] = 0.f;
+        Lg.hull = -1;
         const Geom Og = body_geom(Q, b0 + oi);
         Out4 out;
         out.n = 0;
-        collide(Lg, Og, clear, out);
+        if (Og.shape == HULL) collide_hull(Lg, Og, Q.hl, clear, out);
+        else collide(Lg, Og, clear, out);
         for (int t = 0; t < out.n; t++) best = fminf(best, out.get(t).phi);
       }
       wave_sync();  // the queue is rewritten by the next chunk
@@ -228,7 +241,9 @@ extern "C" size_t rbs_query_lds_bytes(int max_obstacles) {
 extern "C" int rbs_launch_query(int n_scenes, int max_bodies, long n_bodies, const int32_t* body_offset,
                                 const uint8_t* shape, const float* prm, const float* pose, const float* arm_base,
                                 const float* link_len, const float* theta, int M, float clearance, uint8_t* hit,
-                                float* min_phi, hipStream_t stream) {
+                                float* min_phi, const int32_t* hull_info, const float4* hull_vert,
+                                const float4* hull_plane, const uint8_t* hull_loop, const uint8_t* hull_edge,
+                                const float4* hull_ext, hipStream_t stream) {
   if (M <= 0 || n_scenes <= 0) return 0;
   QueryParams Q;
   Q.n_bodies = n_bodies;
@@ -245,6 +260,8 @@ extern "C" int rbs_launch_query(int n_scenes, int max_bodies, long n_bodies, con
   Q.clearance = clearance;
   Q.hit = hit;
   Q.min_phi = min_phi;
+  Q.hl = HullLib{hull_info, hull_vert, hull_plane, hull_loop, hull_edge};
+  Q.hull_ext = hull_ext;
   const size_t grid = (size_t)n_scenes * (size_t)Q.cfg_blocks;
   if (grid > 0x7FFFFFFFu) return -2;
   const size_t lds = rbs_query_lds_bytes(Q.max_obstacles);

@@ -103,6 +103,29 @@ def test_hull_launches_bit_identical(torch_cuda, variant):
                 assert np.array_equal(x[k], y[k]), f"step {t}: {k} differs"
 
 
+def hull_arm_scene(seed):
+    """Hulls among spheres, boxes and capsules dropped round the arm base
+    (x, y within 0.8 m, z 0.2 to 1.8 m), and the kinematic arm."""
+    sc = S.drop_scene(seed, n_spheres=4, n_boxes=4, n_capsules=4, n_hulls=16, edge=1.6)
+    for L in S.ARM_LINK_LENGTH:
+        sc.add(S.CAPSULE, S.KINEMATIC, [S.ARM_RADIUS, 0.5 * L, 0.0], 0.0, 0.5, 0.0, S.ARM_BASE, (1.0, 0.0, 0.0, 0.0))
+    sc.arm = True
+    sc.arm_theta0 = np.zeros(7)
+    return sc
+
+
+@pytest.mark.parametrize("clearance", [0.0, 0.05])
+def test_hull_query_parity(torch_cuda, clearance):
+    """Arm collision queries (motion planning) against scenes with hulls:
+    hit flags bit-exact outside the tie band, separations within 1e-5 m."""
+    from test_gpu_query import compare as qcompare, run_both
+    b = S.pack([hull_arm_scene(900 + k) for k in range(8)])
+    ora = oracle_warmup(b, 40, iters=20)
+    for hg, pg, ho, po, ao, c in run_both(torch_cuda, b, ora, 96, [clearance]):
+        frac = qcompare(hg, pg, ho, po, ao, c, f"hull scenes, clearance {c}")
+        assert 0.05 < frac < 0.95
+
+
 def test_hull_refusals(torch_cuda):
     from paper_2106_14405_amd import _lib as L
     from paper_2106_14405_amd.sim import Sim
@@ -130,6 +153,3 @@ def test_hull_refusals(torch_cuda):
     bad("convex|centre of mass", dent)
     hb = np.nonzero(b.shape == S.HULL)[0][0]
     bad("index", lambda bb: bb.param.__setitem__((hb, 0), 1e6))
-    # arm queries are not available with hulls
-    ba = S.pack([S.clutter_scene(1, arm=True)])
-    assert ba.hull_index is None
