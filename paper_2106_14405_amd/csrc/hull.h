@@ -453,12 +453,15 @@ __device__ inline void hull_hull(const Geom& GA, const Geom& GB, const HullLib& 
   const Poly A = make_poly(GA, HL), B = make_poly(GB, HL);
   float sfa = -INFINITY, sfb = -INFINITY;
   int fa = 0, fb = 0;
+  // a face axis that already separates the hulls by more than the margin
+  // ends the pair (no contact whatever the other axes give)
   for (int f = 0; f < A.nf; f++) {
     V3 n;
     float d;
     A.plane(f, n, d);
     float s = INFINITY;
     for (int k = 0; k < B.nv; k++) s = fminf(s, dot(n, B.vert(k)) - d);
+    if (s > margin) return;
     if (s > sfa) { sfa = s; fa = f; }
   }
   for (int f = 0; f < B.nf; f++) {
@@ -467,6 +470,7 @@ __device__ inline void hull_hull(const Geom& GA, const Geom& GB, const HullLib& 
     B.plane(f, n, d);
     float s = INFINITY;
     for (int k = 0; k < A.nv; k++) s = fminf(s, dot(n, A.vert(k)) - d);
+    if (s > margin) return;
     if (s > sfb) { sfb = s; fb = f; }
   }
   float se = -INFINITY;
