@@ -258,3 +258,16 @@ def test_container_parts_validated():
         d, keep = desc(**kw)
         assert lib.sim_workspace_bytes(C.byref(d)) == 0
         assert b"container parts" in lib.sim_last_error()
+
+
+def test_generated_hulls_pass_the_library_checks():
+    """Every hull the scene generator draws (prisms, bipyramids, cut boxes of
+    every size) is convex, closed and in its principal frame about its
+    centre of mass, as the library requires."""
+    lib = __import__("paper_2106_14405_amd._lib", fromlist=["load"]).load()
+    b = S.pack([S.drop_scene(50 + k, n_spheres=1, n_boxes=1, n_hulls=25, size=(0.03, 0.3), edge=4.0)
+                for k in range(8)])
+    assert len(b.hull_index) == 200
+    d, keep = _desc(b)
+    _with_hulls(d, keep, b)
+    assert lib.sim_workspace_bytes(C.byref(d)) > 0, lib.sim_last_error()
