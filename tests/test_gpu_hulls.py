@@ -153,3 +153,61 @@ def test_hull_refusals(torch_cuda):
     bad("convex|centre of mass", dent)
     hb = np.nonzero(b.shape == S.HULL)[0][0]
     bad("index", lambda bb: bb.param.__setitem__((hb, 0), 1e6))
+
+
+def hull_part_scene(seed):
+    """A chamfered-box door on a vertical hinge beside a static post and a
+    prism drawer on a slide, with hulls, spheres and boxes dropped on and
+    around them (the kernel level with parts and hulls together)."""
+    rng = np.random.default_rng(seed)
+    sc = S.Scene()
+    sc.add(S.BOX, S.STATIC, [0.05, 0.05, 0.5], 0.0, 0.6, 0.0, [0.0, -0.05, 0.5], (1.0, 0.0, 0.0, 0.0))
+    Vd, Fd = S.hull_chamfered_box(0.3, 0.02, 0.4, 0.015)
+    sc.add_hull(Vd, Fd, S.DYNAMIC, 3.0, 0.6, 0.0, [0.3, 0.03, 0.5], (1.0, 0.0, 0.0, 0.0))
+    sc.joints[1] = (1, (0.0, 0.0, 1.0), (0.0, 0.03, 0.5), (-1.5, 1.5), 0)
+    Vw, Fw = S.hull_prism(6, 0.2, 0.05)
+    sc.add_hull(Vw, Fw, S.DYNAMIC, 2.0, 0.6, 0.0, [-0.6, 0.6, 0.3], (1.0, 0.0, 0.0, 0.0))
+    sc.joints[2] = (2, (1.0, 0.0, 0.0), (-0.6, 0.6, 0.3), (-0.3, 0.3), -1)
+    for k in range(12):
+        p = [rng.uniform(-0.8, 0.8), rng.uniform(-0.3, 0.9), rng.uniform(0.9, 2.0)]
+        q = rng.normal(size=4)
+        q /= np.linalg.norm(q)
+        if k % 3 == 0:
+            sc.add(S.SPHERE, S.DYNAMIC, [rng.uniform(0.04, 0.08), 0, 0], 0.5, 0.5, 0.0, p, q)
+        elif k % 3 == 1:
+            V, F = S.random_hull(S._Stream(S.stream_key(seed, 11, k)), (0.04, 0.08))
+            sc.add_hull(V, F, S.DYNAMIC, 0.6, 0.5, 0.0, p, q)
+        else:
+            sc.add(S.BOX, S.DYNAMIC, list(rng.uniform(0.03, 0.07, 3)), 0.7, 0.5, 0.0, p, q)
+    return sc
+
+
+def test_hull_parts_parity(torch_cuda):
+    """Container parts that are hulls, struck by falling hulls and other
+    shapes: one step against the oracle after 120 steps with the parts
+    started at 1 rad/s and 0.3 m/s."""
+    from gpu_util import joint_snapshot32
+    torch = torch_cuda
+    b = S.pack([hull_part_scene(70 + k) for k in range(8)])
+    ora = O.OracleSim(b)
+    for g in np.nonzero(b.joint)[0]:
+        ora.q_rate[g] = 1.0 if b.joint[g] == 1 else 0.3
+    for t in range(120):
+        ora.step(iters=20, warm=O.PREV, outputs=False)
+    pose, vel, theta, cache = snapshot32(ora)
+    js = joint_snapshot32(ora)
+    sim = gpu_sim(b, pose, vel, theta, cache, warm=O.PREV)
+    sim.joint_state.copy_(torch.as_tensor(js))
+    sim.step(None, DT, 20)
+    r = ora.step(iters=20, warm=O.PREV, max_pairs=sim.max_pairs, max_contacts=sim.max_contacts)
+    g = gpu_results(sim)
+    rep = compare(b, g, r, ora, contact_values=True)
+    report("hull parts", rep)
+    jo = ora.joint_state.reshape(-1, 2)
+    for gi in np.nonzero(b.joint)[0]:
+        s = int(np.searchsorted(b.body_offset, gi, side="right") - 1)
+        if r["ambiguous"][s]:
+            continue
+        assert abs(float(g["joint_state"][0, gi]) - jo[gi, 0]) <= 1e-5
+        assert abs(float(g["joint_state"][1, gi]) - jo[gi, 1]) <= 1e-4 * max(abs(jo[gi, 1]), 1.0)
+    assert rep["contacts_solved"] >= 100
