@@ -282,3 +282,29 @@ def test_parts_refusals(torch_cuda):
     def axes(v):
         v[dyn] = (1.0, 0.0, 0.0)
     bad(match="16 container parts", joint=many, joint_axis=axes)
+
+
+def test_parts_checkpoint_roundtrip(torch_cuda):
+    """A saved state holds the parts' joint state: restoring it and
+    stepping again repeats the same bits."""
+    torch = torch_cuda
+    from paper_2106_14405_amd.sim import Sim
+    b = S.batch_clutter(4, seed0=10500, arm=2, cabinets=2)
+    sim = Sim(b, warm=O.PREV, tol=1e-4)
+    js = torch.zeros_like(sim.joint_state)
+    js[1, torch.as_tensor(np.nonzero(b.joint)[0], device=sim.device)] = 0.8
+    sim.joint_state.copy_(js)
+    acts = [torch.as_tensor(sweep_actions(b.n_scenes, t), device=sim.device) for t in range(40)]
+    for t in range(20):
+        sim.step(acts[t], DT, 100)
+    blob = sim.save_state()
+    for t in range(20, 40):
+        sim.step(acts[t], DT, 100)
+    first = state(sim)
+    sim.load_state(blob)
+    for t in range(20, 40):
+        sim.step(acts[t], DT, 100)
+    again = state(sim)
+    for k in first:
+        assert np.array_equal(first[k], again[k]), k
+    assert np.abs(first["joint"][0]).max() > 0.01
