@@ -211,3 +211,26 @@ def test_hull_parts_parity(torch_cuda):
         assert abs(float(g["joint_state"][0, gi]) - jo[gi, 0]) <= 1e-5
         assert abs(float(g["joint_state"][1, gi]) - jo[gi, 1]) <= 1e-4 * max(abs(jo[gi, 1]), 1.0)
     assert rep["contacts_solved"] >= 100
+
+
+def test_hull_sleeping_parity(torch_cuda):
+    """Sleeping on (0.02 m/s, 30 steps): hulls at rest fall asleep by their
+    bounding box's radius; one step against the oracle, rest counters equal."""
+    from gpu_util import gpu_set_rest
+    sleep = (0.02, 30)
+    b = hull_batch(8, seed0=560)
+    ora = O.OracleSim(b)
+    ora.set_sleep(*sleep)
+    for t in range(200):
+        ora.step(iters=20, warm=O.PREV, outputs=False)
+    pose, vel, theta, cache = snapshot32(ora)
+    sim = gpu_sim(b, pose, vel, theta, cache, warm=O.PREV)
+    sim.set_sleep(*sleep)
+    gpu_set_rest(sim, ora.rest)
+    sim.step(None, DT, 20)
+    r = ora.step(iters=20, warm=O.PREV, max_pairs=sim.max_pairs, max_contacts=sim.max_contacts)
+    g = gpu_results(sim)
+    rep = compare(b, g, r, ora, contact_values=True, check_rest=True)
+    report("hull drop, sleeping", rep)
+    hull_rows = b.shape == S.HULL
+    assert np.sum(ora.rest[hull_rows] >= sleep[1]) >= 20   # hulls asleep
