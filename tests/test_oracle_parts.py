@@ -175,3 +175,26 @@ def test_parts_refuse_jacobi_and_learned():
     ora = O.OracleSim(bt)
     with pytest.raises(ValueError):
         ora.step(iters=10, solver=O.JACOBI)
+
+
+def test_parts_keep_their_islands_awake():
+    """Sleeping on: a box resting on a closed drawer never sleeps (the part
+    keeps its island awake), a box on the floor far away does."""
+    drawer = dict(param=[0.25, 0.3, 0.1], mass=3.0, pos=[0.0, 0.0, 0.5])
+    on_drawer = dict(param=[0.05, 0.05, 0.05], mass=0.5, pos=[0.0, 0.0, 0.6 + 0.05 - 0.001])
+    far = dict(param=[0.05, 0.05, 0.05], mass=0.5, pos=[1.5, 1.5, 0.049])
+    bt = part_batch([drawer, on_drawer, far], {0: (2, (1.0, 0.0, 0.0), (0.0, 0.0, 0.5), (-0.2, 0.2), -1)})
+    ora = O.OracleSim(bt)
+    ora.set_sleep(0.02, 30)
+    for t in range(150):
+        ora.step(iters=100, tol=1e-9, warm=O.PREV, outputs=False)
+    assert ora.rest[1] >= 30 and ora.rest[2] >= 30      # both at rest long enough
+    r = ora.step(iters=100, tol=1e-9, warm=O.PREV)
+    n = int(r["n_contacts"][0])
+    col = r["c_colour"][0, :n]
+    keys = r["c_key"][0, :n]
+    a, b = keys >> 20, (keys >> 8) & 0xFFF
+    far_c, top_c = (a == 2) | (b == 2), (a == 1) | (b == 1)
+    assert far_c.any() and top_c.any()
+    assert np.all(col[far_c] == -1), "the far box should sleep"
+    assert np.all(col[top_c] >= 0), "the box on the drawer must stay awake"
