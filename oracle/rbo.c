@@ -1087,8 +1087,11 @@ static int face_region(const Hull *H, V l) {
  *    ends against the hull and the core against every edge (Ericson 2005,
  *    5.1.9, clamped); nearest wins (ties: the order tried).
  * 2. Closest core point in a face's region with the core within ~1 mrad
- *    of parallel to that face: two contacts at the ends of the core clipped
- *    to the face's prism (f 0, 1); otherwise one at the closest points (f 2).
+ *    of parallel to that face, or the core that parallel to a face whose
+ *    plane lies at the closest distance (within CLIP_ON) and whose prism it
+ *    crosses (a plateau of the distance over the face): two contacts at the
+ *    ends of the core clipped to the face's prism (f 0, 1); otherwise one at
+ *    the closest points (f 2).
  * 3. Core touching the hull: leave through the face whose plane the deeper
  *    core end lies least below (ties: lower face); contacts at the ends of
  *    the core clipped to that face's prism (f 0, 1), else at the deeper end
@@ -1157,8 +1160,27 @@ static int capsule_hull(const Geom *C, const Geom *G, double margin, PC *out, in
             double thr = SIN_PAR * dl;
             if (fabs(fabs(dot(d, H->fn[fr])) - thr) < 1e-2 * thr) (*amb)++;
         }
+        /* a core level with a face at the distance found lies on that face's
+         * plateau, which may end on the face's boundary (where the region of
+         * the closest point is ill-defined): the first such face whose prism
+         * the core crosses */
+        int plateau = 0;
+        if (!facecase) {
+            for (int f = 0; f < H->nf && !facecase; f++) {
+                double thr = SIN_PAR * dl, dn = fabs(dot(d, H->fn[f]));
+                if (dn > thr) continue;
+                double gap = fabs(dot(H->fn[f], l) - H->fd[f] - dist);
+                if (fabs(gap - CLIP_ON) < BAND) (*amb)++;
+                double t0, t1;
+                if (gap <= CLIP_ON && clip_prism(H, f, p0, d, &t0, &t1)) {
+                    if (fabs(dn - thr) < 1e-2 * thr) (*amb)++;
+                    fr = f;
+                    facecase = plateau = 1;
+                }
+            }
+        }
         /* a plateau of the distance at another place decides differently */
-        for (int i = 0; i < nc; i++) {
+        for (int i = 0; i < nc && !plateau; i++) {
             if (i == bi || fabs(cd[i] - dist) >= BAND || fabs(ct[i] - t) * dl <= BAND) continue;
             V li = add(p0, scl(d, ct[i]));
             int fi = face_region(H, li);

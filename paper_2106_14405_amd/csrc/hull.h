@@ -332,8 +332,10 @@ __device__ inline int face_region(const Poly& P, V3 l, V3& nr, float& dr) {
 
 // Capsule (first) against a hull (second), after capsule_box: separated
 // core -> closest points among the ends and the core against every edge;
-// in a face region within ~1 mrad of parallel -> the core clipped to that
-// face's prism (f 0, 1), else one contact (f 2); touching core -> the face
+// in a face region within ~1 mrad of parallel, or that parallel to a face
+// whose plane lies at the closest distance (within CLIP_ON) and whose
+// prism it crosses -> the core clipped to that face's prism (f 0, 1), else
+// one contact (f 2); touching core -> the face
 // whose plane the deeper end lies least below, clipped (f 0, 1) or the
 // deeper end (f 3).
 __device__ inline void capsule_hull(const Geom& C, const Geom& G, const HullLib& HL, float margin, Out4& out) {
@@ -390,9 +392,24 @@ __device__ inline void capsule_hull(const Geom& C, const Geom& G, const HullLib&
     const V3 l = p0 + d * t;
     V3 nr;
     float dr;
-    const int fr = face_region(P, l, nr, dr);
+    int fr = face_region(P, l, nr, dr);
+    bool facecase = fr >= 0 && fabsf(dot(d, nr)) <= kSinParallel * dl;
+    // a core level with a face at the distance found: that face's plateau
+    for (int f = 0; f < P.nf && !facecase; f++) {
+      V3 n;
+      float dd;
+      P.plane(f, n, dd);
+      if (fabsf(dot(d, n)) > kSinParallel * dl) continue;
+      float t0, t1;
+      if (fabsf(dot(n, l) - dd - dist) <= kClipOn && clip_prism(P, f, n, p0, d, t0, t1)) {
+        fr = f;
+        nr = n;
+        dr = dd;
+        facecase = true;
+      }
+    }
     bool done = false;
-    if (fr >= 0 && fabsf(dot(d, nr)) <= kSinParallel * dl) {
+    if (facecase) {
       float t0, t1;
       if (clip_prism(P, fr, nr, p0, d, t0, t1)) {
         loc0 = poly_face_contact(nr, dr, p0 + d * t0, r, 0);

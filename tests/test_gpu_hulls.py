@@ -234,3 +234,40 @@ def test_hull_sleeping_parity(torch_cuda):
     report("hull drop, sleeping", rep)
     hull_rows = b.shape == S.HULL
     assert np.sum(ora.rest[hull_rows] >= sleep[1]) >= 20   # hulls asleep
+
+
+def level_capsule_scene(k):
+    """A capsule lying level, a few mm above the top face of a static
+    hexagonal prism, short enough to lie inside the face or long enough to
+    hang over its edges, at a yaw of its own."""
+    sc = S.Scene()
+    V, F = S.hull_prism(6, 0.2, 0.05)
+    sc.add_hull(V, F, S.STATIC, 0.0, 0.6, 0.0, [0.0, 0.0, 0.5], (1.0, 0.0, 0.0, 0.0))
+    r, hl = 0.03, (0.05, 0.12, 0.3, 0.45)[k % 4]
+    gap = (0.002, 0.004)[k // 4 % 2]
+    yaw = 0.37 * k
+    qz = np.array([np.cos(yaw / 2), 0.0, 0.0, np.sin(yaw / 2)])
+    qy = np.array([np.cos(np.pi / 4), 0.0, np.sin(np.pi / 4), 0.0])
+    w1, v1, w2, v2 = qz[0], qz[1:], qy[0], qy[1:]
+    q = np.r_[w1 * w2 - v1 @ v2, w1 * v2 + w2 * v1 + np.cross(v1, v2)]
+    sc.add(S.CAPSULE, S.DYNAMIC, [r, hl, 0.0], 0.5, 0.5, 0.0, [0.01 * k, 0.02, 0.5 + 0.05 + r + gap], q)
+    return sc
+
+
+def test_capsule_level_on_a_hull_face_parity(torch_cuda):
+    """A capsule level with a hull's face touches it at the two ends of its
+    core clipped to the face (features 0 and 1), also where it hangs over
+    the face's edges: one step against the oracle from rest."""
+    b = S.pack([level_capsule_scene(k) for k in range(16)])
+    ora = O.OracleSim(b)
+    pose, vel, theta, cache = snapshot32(ora)
+    sim = gpu_sim(b, pose, vel, theta, cache, warm=O.COLD)
+    sim.step(None, DT, 20)
+    r = ora.step(iters=20, warm=O.COLD, max_pairs=sim.max_pairs, max_contacts=sim.max_contacts)
+    g = gpu_results(sim)
+    rep = compare(b, g, r, ora, contact_values=True)
+    report("capsule level on a hull face", rep)
+    for s in range(b.n_scenes):
+        assert not r["ambiguous"][s]
+        for key, n in ((g["key"], g["count"]), (r["c_key"], r["n_contacts"])):
+            assert sorted(int(k) & 0xFF for k in key[s, :int(n[s])]) == [0, 1], s

@@ -296,3 +296,40 @@ def test_hull_rests_on_the_ground():
     np.testing.assert_allclose(r["c_lambda"][0, :n, 0].sum(), float(b.mass[0]) * G * DT, rtol=1e-6)
     assert np.abs(ora.vel.reshape(-1, 6)[0]).max() < 1e-6
     np.testing.assert_allclose(ora.pose.reshape(-1, 7)[0, 2], 0.05, atol=1e-3)
+
+
+def test_capsule_flat_on_a_hull_face():
+    """A capsule lying level on a hexagonal prism's top face, lifted by a
+    gap g: two contacts at its core's ends, phi = g, normal up; a long
+    capsule hanging over the face's edges is clipped to the face."""
+    V, F = S.hull_prism(6, 0.2, 0.05)
+    hull_pose = np.r_[0.0, 0.0, 0.5, 1, 0, 0, 0]
+    r = 0.03
+    for hl, g in ((0.05, 0.004), (0.3, 0.0)):
+        # core along x (capsule axis z turned onto x)
+        cpose = np.r_[0.0, 0.02, 0.5 + 0.05 + r + g, math.cos(math.pi / 4), 0, math.sin(math.pi / 4), 0]
+        cs, amb = O.collide(S.CAPSULE, [r, hl, 0], cpose, S.HULL, [0, 0, 0], hull_pose, margin=0.02, hulls=[(V, F)])
+        assert amb == 0 and len(cs) == 2
+        xs = sorted(c[2][0] for c in cs)
+        for f, n, p, ph in cs:
+            np.testing.assert_allclose(ph, g, atol=1e-12)
+            np.testing.assert_allclose(n, [0, 0, 1], atol=1e-12)
+        # the core's ends, or where the top hexagon's edges cut the core (x = +-r_in sqrt(1 - (y/r_in)^2)...)
+        if hl < 0.1:
+            np.testing.assert_allclose(xs, [-hl, hl], atol=1e-12)
+        else:
+            # the hexagon (circumradius 0.2, a vertex on +x): its boundary at y = 0.02
+            assert all(abs(x) < 0.2 for x in xs) and xs[0] < -0.15 and xs[1] > 0.15
+
+
+def test_sphere_inside_a_hull_leaves_by_the_nearest_face():
+    """A sphere centre inside a chamfered box nearest its +x face: the
+    normal is that face's and phi is minus (depth + radius)."""
+    V, F = S.hull_chamfered_box(0.2, 0.15, 0.1, 0.02)
+    pose = np.r_[0.0, 0.0, 0.5, 1, 0, 0, 0]
+    c = np.array([0.17, 0.0, 0.5])
+    cs, amb = O.collide(S.SPHERE, [0.05, 0, 0], np.r_[c, 1, 0, 0, 0], S.HULL, [0, 0, 0], pose, margin=0.02, hulls=[(V, F)])
+    assert amb == 0 and len(cs) == 1
+    f, n, p, ph = cs[0]
+    np.testing.assert_allclose(n, [1, 0, 0], atol=1e-12)
+    np.testing.assert_allclose(ph, -(0.2 - 0.17) - 0.05, atol=1e-12)
