@@ -333,3 +333,39 @@ def test_sphere_inside_a_hull_leaves_by_the_nearest_face():
     f, n, p, ph = cs[0]
     np.testing.assert_allclose(n, [1, 0, 0], atol=1e-12)
     np.testing.assert_allclose(ph, -(0.2 - 0.17) - 0.05, atol=1e-12)
+
+
+def test_capsule_level_on_a_turned_hull():
+    """The same level capsule on the prism turned about its axis and about
+    a tilted axis carried along: in the hull's frame the result is that of
+    the upright case (contact count, phi, normal along the face's normal,
+    contact points midway between the face and the capsule, over the face)."""
+    V, F = S.hull_prism(6, 0.2, 0.05)
+    r, g = 0.03, 0.004
+
+    def qmul(a, b):
+        return np.r_[a[0] * b[0] - a[1:] @ b[1:], a[0] * b[1:] + b[0] * a[1:] + np.cross(a[1:], b[1:])]
+
+    def rot(q, v):
+        return qmul(qmul(q, np.r_[0.0, v]), q * np.r_[1, -1, -1, -1])[1:]
+
+    for k, (ax, ang) in enumerate((((0, 0, 1), 0.7), ((1, 2, 0.5), 0.4), ((-0.3, 1, 0.2), 2.1))):
+        ax = np.asarray(ax, float) / np.linalg.norm(ax)
+        qh = np.r_[math.cos(ang / 2), math.sin(ang / 2) * ax]
+        ch = np.array([0.1, -0.2, 0.6])
+        for hl in (0.05, 0.3):
+            # capsule core along local x at local height top + r + g, yawed by 0.3 k in the face
+            qc_local = qmul(np.r_[math.cos(0.15 * k), 0, 0, math.sin(0.15 * k)],
+                            np.r_[math.cos(math.pi / 4), 0, math.sin(math.pi / 4), 0])
+            pc = ch + rot(qh, np.array([0.0, 0.02, 0.05 + r + g]))
+            cs, amb = O.collide(S.CAPSULE, [r, hl, 0], np.r_[pc, qmul(qh, qc_local)], S.HULL, [0, 0, 0],
+                                np.r_[ch, qh], margin=0.02, hulls=[(V, F)])
+            assert amb == 0 and len(cs) == 2, (k, hl, cs)
+            up = rot(qh, np.array([0.0, 0.0, 1.0]))
+            for f, n, p, ph in cs:
+                assert f in (0, 1)
+                np.testing.assert_allclose(ph, g, atol=1e-9)
+                np.testing.assert_allclose(n, up, atol=1e-9)
+                loc = rot(qh * np.r_[1, -1, -1, -1], np.asarray(p) - ch)
+                np.testing.assert_allclose(loc[2], 0.05 + g / 2, atol=1e-9)   # midway between the surfaces
+                assert math.hypot(loc[0], loc[1]) <= 0.2 + 1e-9
