@@ -236,30 +236,48 @@ def test_hull_sleeping_parity(torch_cuda):
     assert np.sum(ora.rest[hull_rows] >= sleep[1]) >= 20   # hulls asleep
 
 
+def _qmul(a, b):
+    return np.r_[a[0] * b[0] - a[1:] @ b[1:], a[0] * b[1:] + b[0] * a[1:] + np.cross(a[1:], b[1:])]
+
+
 def level_capsule_scene(k):
     """A capsule lying level, a few mm above the top face of a static
     hexagonal prism, short enough to lie inside the face or long enough to
-    hang over its edges, at a yaw of its own."""
+    hang over its edges, at a yaw of its own; from k = 8 on the prism is
+    turned about a tilted axis and the capsule with it."""
     sc = S.Scene()
     V, F = S.hull_prism(6, 0.2, 0.05)
-    sc.add_hull(V, F, S.STATIC, 0.0, 0.6, 0.0, [0.0, 0.0, 0.5], (1.0, 0.0, 0.0, 0.0))
+    ang = 0.0 if k < 8 else 0.25 * (k - 7)
+    ax = np.array([1.0, 0.5 * (k % 3), 0.3])
+    qh = np.r_[np.cos(ang / 2), np.sin(ang / 2) * ax / np.linalg.norm(ax)]
+    ch = np.array([0.0, 0.0, 0.5])
+    sc.add_hull(V, F, S.STATIC, 0.0, 0.6, 0.0, list(ch), tuple(qh))
     r, hl = 0.03, (0.05, 0.12, 0.3, 0.45)[k % 4]
     gap = (0.002, 0.004)[k // 4 % 2]
     yaw = 0.37 * k
-    qz = np.array([np.cos(yaw / 2), 0.0, 0.0, np.sin(yaw / 2)])
-    qy = np.array([np.cos(np.pi / 4), 0.0, np.sin(np.pi / 4), 0.0])
-    w1, v1, w2, v2 = qz[0], qz[1:], qy[0], qy[1:]
-    q = np.r_[w1 * w2 - v1 @ v2, w1 * v2 + w2 * v1 + np.cross(v1, v2)]
-    sc.add(S.CAPSULE, S.DYNAMIC, [r, hl, 0.0], 0.5, 0.5, 0.0, [0.01 * k, 0.02, 0.5 + 0.05 + r + gap], q)
+    qc = _qmul(np.array([np.cos(yaw / 2), 0.0, 0.0, np.sin(yaw / 2)]),
+               np.array([np.cos(np.pi / 4), 0.0, np.sin(np.pi / 4), 0.0]))
+    loc = np.array([0.01 * (k % 8), 0.02, 0.05 + r + gap])
+    pc = ch + _qmul(_qmul(qh, np.r_[0.0, loc]), qh * np.r_[1, -1, -1, -1])[1:]
+    sc.add(S.CAPSULE, S.DYNAMIC, [r, hl, 0.0], 0.5, 0.5, 0.0, list(pc), _qmul(qh, qc))
     return sc
 
 
 def test_capsule_level_on_a_hull_face_parity(torch_cuda):
     """A capsule level with a hull's face touches it at the two ends of its
     core clipped to the face (features 0 and 1), also where it hangs over
-    the face's edges: one step against the oracle from rest."""
+    the face's edges: one step against the oracle, the capsule approaching
+    the face."""
     b = S.pack([level_capsule_scene(k) for k in range(16)])
+    assert b.n_scenes == 16
     ora = O.OracleSim(b)
+    # each capsule approaches its face at 0.6 m/s, so that the patch is solved
+    pose, vel = ora.pose.reshape(-1, 7), ora.vel.reshape(-1, 6)
+    for s in range(b.n_scenes):
+        h, c = int(b.body_offset[s]), int(b.body_offset[s]) + 1
+        q = pose[h, 3:7]
+        up = _qmul(_qmul(q, np.r_[0.0, 0.0, 0.0, 1.0]), q * np.r_[1, -1, -1, -1])[1:]
+        vel[c, :3] = -0.6 * up
     pose, vel, theta, cache = snapshot32(ora)
     sim = gpu_sim(b, pose, vel, theta, cache, warm=O.COLD)
     sim.step(None, DT, 20)
@@ -267,6 +285,7 @@ def test_capsule_level_on_a_hull_face_parity(torch_cuda):
     g = gpu_results(sim)
     rep = compare(b, g, r, ora, contact_values=True)
     report("capsule level on a hull face", rep)
+    assert (r["c_lambda"][:, :2, 0] > 0).all()
     for s in range(b.n_scenes):
         assert not r["ambiguous"][s]
         for key, n in ((g["key"], g["count"]), (r["c_key"], r["n_contacts"])):
